@@ -1,0 +1,172 @@
+"""Poisson system of the same discretisation, and its solvers (oracle; test
+infrastructure only).
+
+Sec. 2.2 discretises Delta P = f cell by cell (eq. (7)): the Laplacian of
+cell i is (1/mu_i) sum_f grad(P)_f . n_f |sigma_f| with the diamond face
+gradient (eq. (laplace)); vertex values come from the least-squares
+interpolation.  Readings:
+
+* rows are assembled without the 1/mu_i factor and with the sign flipped,
+  K = -A_lin, b = -mu * f + (ghost constants moved to the right), so the
+  diagonal is positive and the solution is unchanged;
+* a Dirichlet face uses the diamond with its ghost (u_g = 2 g - u_L); a
+  zero-flux / Neumann face carries its prescribed flux (0 or value*|S_f|);
+* convergence is the unpreconditioned true residual
+  ||b - K x||_2 <= tol ||b||_2 with tol = 1e-10 (the paper's table caption
+  prints the tolerance garbled as "10e^-10").
+
+K is not symmetric on general tetrahedra (diamond cross terms and the
+least-squares vertex coupling); ``symmetry_report`` measures how far, and the
+CG below is the plain textbook Jacobi-preconditioned CG regardless.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .geometry import Geometry, ZERO_FLUX, NEUMANN, DIRICHLET, ghost_coefficients
+from .fv import extend_with_ghosts, node_values, diamond_flux
+
+
+def _face_kinds(geo: Geometry, kinds, values):
+    interior = geo.fghost < 0
+    tag = np.maximum(geo.ftag, 0)
+    kind = np.where(interior, DIRICHLET, np.asarray(kinds)[tag])
+    val = np.where(interior, 0.0, np.asarray(values, np.float64)[tag])
+    return kind, val
+
+
+def apply_laplacian(geo: Geometry, P, kinds, values):
+    """Matrix-free (A P)_i = sum_f s_if F_f(P), affine in P (ghost constants
+    included): F_f = S_f . grad(P)_f (eq. (laplace)) or the prescribed flux."""
+    gs, gt = ghost_coefficients(geo, kinds, values)
+    P_ext = extend_with_ghosts(geo, P, gs, gt)
+    Pn = node_values(geo, P_ext)
+    F = diamond_flux(geo, P_ext, Pn)
+    kind, val = _face_kinds(geo, kinds, values)
+    area = np.linalg.norm(geo.fS, axis=1)
+    F = np.where(kind == NEUMANN, val * area, F)
+    F = np.where(kind == ZERO_FLUX, 0.0, F)
+    return np.sum(geo.csign * F[geo.cfaces], axis=1)
+
+
+def assemble(geo: Geometry, kinds, values):
+    """K (CSR) and the constant vector c such that K P = -mu*f + c.
+
+    Every face flux is a linear combination of vertex values and of P_R, P_L;
+    every vertex value is a combination of cell values and ghost values; every
+    ghost value is s*P_owner + t.  The coefficients are expanded and summed
+    into (row, column) entries; the t-parts go to c."""
+    gs, gt = ghost_coefficients(geo, kinds, values)
+    kind, val = _face_kinds(geo, kinds, values)
+    nc = geo.nc
+    active = kind == DIRICHLET                 # faces whose flux depends on P
+    # flux coefficients of each face on its "inputs"
+    # vertex part: weight w_v on vertex v, for v in A, B, C
+    fv_face, fv_vert, fv_w = [], [], []
+    for col, w in ((0, geo.kAC), (1, geo.kBC), (2, -(geo.kAC + geo.kBC))):
+        fv_face.append(np.arange(geo.nf))
+        fv_vert.append(geo.fabc[:, col])
+        fv_w.append(w)
+    fv_face = np.concatenate(fv_face)
+    fv_vert = np.concatenate(fv_vert)
+    fv_w = np.concatenate(fv_w)
+    keep = active[fv_face]
+    fv_face, fv_vert, fv_w = fv_face[keep], fv_vert[keep], fv_w[keep]
+    # expand vertex -> (entity, alpha)
+    deg = np.diff(geo.nptr)[fv_vert]
+    face_e = np.repeat(fv_face, deg)
+    w_e = np.repeat(fv_w, deg)
+    base = np.repeat(geo.nptr[fv_vert], deg)
+    offs = np.arange(deg.sum()) - np.repeat(np.cumsum(deg) - deg, deg)
+    ent = geo.nidx[base + offs]
+    coef = w_e * geo.nalpha[base + offs]
+    # two-point part: +kRL on R, -kRL on L
+    af = np.nonzero(active)[0]
+    face_e = np.concatenate([face_e, af, af])
+    ent = np.concatenate([ent, geo.fR[af], geo.fL[af]])
+    coef = np.concatenate([coef, geo.kRL[af], -geo.kRL[af]])
+    # ghost entities -> owner column with factor s, constant t
+    is_g = ent >= nc
+    g = np.where(is_g, ent - nc, 0)
+    col = np.where(is_g, geo.gowner[g], ent)
+    lin = np.where(is_g, gs[g], 1.0) * coef
+    const = np.where(is_g, gt[g], 0.0) * coef
+    # F_f = sum lin * P_col + sum const  (+ prescribed flux on Neumann faces)
+    Fc = np.bincount(face_e, weights=const, minlength=geo.nf)
+    area = np.linalg.norm(geo.fS, axis=1)
+    Fc = Fc + np.where(kind == NEUMANN, val * area, 0.0)
+    # scatter face rows into cell rows with sign: row L (+1), row R (-1)
+    rows, cols, vals = [geo.fL[face_e]], [col], [lin]
+    interior_e = geo.fghost[face_e] < 0
+    rows.append(geo.fR[face_e][interior_e])
+    cols.append(col[interior_e])
+    vals.append(-lin[interior_e])
+    rows, cols, vals = map(np.concatenate, (rows, cols, vals))
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(nc, nc)).tocsr()
+    A.sum_duplicates()
+    c_face = np.sum(geo.csign * Fc[geo.cfaces], axis=1)
+    K = (-A).tocsr()
+    K.sort_indices()
+    return K, c_face
+
+
+def rhs(geo: Geometry, f, c):
+    """b = -mu * f + c."""
+    return -geo.vol * np.asarray(f, np.float64) + c
+
+
+def jacobi_cg(K, b, x0=None, tol=1e-10, maxit=20000, history=None):
+    """Textbook preconditioned CG with the Jacobi preconditioner
+    z = D^{-1} r.  Stops when ||r||_2 <= tol ||b||_2 (recurrence residual),
+    then confirms with the true residual; returns (x, iterations, true_rel)."""
+    b = np.asarray(b, np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, np.float64)
+    dinv = 1.0 / K.diagonal()
+    bnorm = np.linalg.norm(b)
+    r = b - K @ x
+    it = 0
+    while True:
+        if np.linalg.norm(r) <= tol * bnorm or it >= maxit:
+            true_rel = np.linalg.norm(b - K @ x) / bnorm
+            if true_rel <= tol or it >= maxit:
+                return x, it, true_rel
+            r = b - K @ x                       # drift: restart from true r
+        z = dinv * r
+        p = z.copy()
+        rz = r @ z
+        while it < maxit:
+            q = K @ p
+            alpha = rz / (p @ q)
+            x = x + alpha * p
+            r = r - alpha * q
+            it += 1
+            if history is not None:
+                history.append(x.copy())
+            if np.linalg.norm(r) <= tol * bnorm:
+                break
+            z = dinv * r
+            rz_new = r @ z
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+
+
+def direct_solve(K, b):
+    """Sparse LU solve (SuperLU), the pin for x* = K^{-1} b."""
+    return spla.spsolve(K.tocsc(), b)
+
+
+def true_relative_residual(K, b, x):
+    return float(np.linalg.norm(b - K @ x) / np.linalg.norm(b))
+
+
+def symmetry_report(K):
+    """||K - K^T||_F / ||K + K^T||_F, min diagonal, and the smallest
+    eigenvalue of the symmetric part (sparse Lanczos)."""
+    Kt = K.T.tocsr()
+    asym = spla.norm(K - Kt) / spla.norm(K + Kt)
+    Ssym = ((K + Kt) * 0.5).tocsc()
+    lam = spla.eigsh(Ssym, k=1, sigma=0, which="LM", return_eigenvectors=False)
+    return dict(asym=float(asym), min_diag=float(K.diagonal().min()),
+                lambda_min_sym=float(lam[0]))
