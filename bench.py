@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the finite-volume hot path on one MI355X.
+
+One step = one 3-stage Runge-Kutta finite-volume step of the convection-
+diffusion problem followed by one Poisson solve (Jacobi-CG to 1e-10 relative
+true residual, warm-started from the previous solution, right-hand side =
+the transported scalar), on a synthetic jittered-tetrahedron unit cube:
+
+  cube120 (default): 120^3 hexes x 6 tets = 10,368,000 cells, seed 2
+  cube20:             20^3 hexes x 6 tets =     48,000 cells, seed 1
+
+Fields: Gaussian pulse (sigma 0.1, centre 0.5,0.5,0.5), velocity
+(sin pi y, sin pi z, sin pi x), diffusivity 1e-3, zero-flux walls for the
+scalar, Dirichlet 0 for the potential, dt from CFL 0.4.
+
+Prints one JSON line.  `value` is FV cell-updates per second (cells x RK3
+steps / FV time); the Poisson solve time per step is reported beside it.
+Per-kernel durations come from HIP events the library records around its
+own launches on the launch stream during the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FV cell-updates/s + Poisson solve ms @1e-10 rel; plain vs mixed/learned"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "cube120": dict(n=120, seed=2),
+    "cube20": dict(n=20, seed=1),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(info):
+    """Bytes each kernel must move once per launch (every stored array read or
+    written once; gathered neighbour values counted once per array)."""
+    nc, nf, nb, nv = info.nc, info.nf, info.nb, info.nv
+    offdiag = info.matrix_nnz - nc
+    return {
+        # stencil idx 4/entry; per cell: M^-1 48, centre 24, u 8, c2f 16, c2n 16,
+        # grad 24 + psi 8 written; face centroids 24/face; ghost centre+u 32
+        "grad_limiter": info.stencil_entries * 4 + nc * (48 + 24 + 8 + 16 + 16 + 24 + 8)
+        + nf * 24 + nb * 32,
+        # idx 4 + alpha 8 per entry, u gathered once, u_node written
+        "node_interp": info.node_entries * 12 + (nc + nb) * 8 + nv * 8,
+        # per face: L,R,A,B,C 20 + kAC,kBC,kRL,phi 32 + centroid 24 + F 8;
+        # per cell gathered once: u, grad, psi, centre 64; vertex values 8
+        "face_flux": nf * 84 + nc * 64 + nv * 8,
+        # per cell: c2f 16, F gathered 16, vol 8, src 8, u^n 8, u 8 written
+        "update": nc * (16 + 16 + 8 + 8 + 8 + 8),
+        # off-diagonal val 8 + col 4; per row diag 8, p 8, q 8 written
+        "cg_spmv": offdiag * 12 + nc * 24,
+        # x,p,r,q,dinv read 40; x,r,z written 24
+        "cg_axpy": nc * 64,
+        # z,p read, p written
+        "cg_dir": nc * 24,
+    }
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle on the host (single thread), on the 48,000-cell cube of
+    the same recipe: RK3 steps for about `seconds_target` seconds."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import synth
+    from oracle import fv, poisson
+    from oracle.geometry import build_geometry, ZERO_FLUX, DIRICHLET
+    with threadpool_limits(limits=1):
+        m = synth.jittered_cube(20, 1)
+        geo = build_geometry(m.xyz, m.tets, m.btris, m.btags)
+        pf = synth.problem_fields(m)
+        kinds = [ZERO_FLUX] * 6
+        phi = fv.face_velocity_flux(geo, pf.vel)
+        dt = fv.cfl_dt(geo, phi, pf.diffusivity, pf.cfl, kinds)
+        u = pf.u0
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds_target or steps == 0:
+            u = fv.rk3_step(geo, u, dt, phi, pf.diffusivity, kinds, [0.0] * 6)
+            steps += 1
+        t_fv = time.perf_counter() - t0
+        K, c = poisson.assemble(geo, [DIRICHLET] * 6, [0.0] * 6)
+        t1 = time.perf_counter()
+        _, its, _ = poisson.jacobi_cg(K, poisson.rhs(geo, u, c), tol=1e-10)
+        t_solve = time.perf_counter() - t1
+    return {"value": geo.nc * steps / t_fv, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"48,000-cell cube of the same recipe (n=20, seed 1), {steps} RK3 steps "
+                      f"in {t_fv:.1f} s; one cold Jacobi-CG solve to 1e-10: {its} iterations, "
+                      f"{t_solve * 1e3:.0f} ms",
+            "poisson_solve_ms": t_solve * 1e3}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cube120")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the method's "
+                          "multi-GPU decomposition is not built (see DESIGN.md)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_2203_00925_amd import binding as B
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(3)
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[args.workload]
+    t = time.perf_counter()
+    mesh = synth.jittered_cube(wl["n"], wl["seed"])
+    pf = synth.problem_fields(mesh)
+    log(f"mesh n={wl['n']} cells={mesh.nc} generated in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    M = B.Mesh.from_cube(mesh)
+    info = M.info
+    log(f"preprocessed in {time.perf_counter() - t:.1f}s; workspace {info.ws_bytes / 1e9:.2f} GB")
+    st = B.State(M, diffusivity=pf.diffusivity)
+    st.set_bcs(B.VAR_SCALAR, [B.ZERO_FLUX] * 6)
+    st.set_bcs(B.VAR_POTENTIAL, [B.DIRICHLET] * 6)
+    st.set_field(B.FIELD_VEL, torch.from_numpy(np.ascontiguousarray(pf.vel.T.ravel())))
+    st.set_field(B.FIELD_U, torch.from_numpy(pf.u0))
+    del mesh
+    st.poisson_assemble()
+    dt = st.cfl_dt(pf.cfl)
+    total0 = st.conservation()
+    log(f"state ready; dt={dt:.6g}")
+
+    stream = torch.cuda.current_stream()
+
+    def one_step(evs=None):
+        if evs is not None:
+            evs[0].record(stream)
+        st.step(1, dt)
+        if evs is not None:
+            evs[1].record(stream)
+        info_s = st.poisson_solve(None, tol=1e-10)
+        if evs is not None:
+            evs[2].record(stream)
+        return info_s
+
+    for w in range(args.warmup):
+        s = one_step()
+        log(f"warmup {w}: solve {s['iterations']} it, {s['ms']:.1f} ms")
+    torch.cuda.synchronize()
+    st.kernel_timing(True)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    solves = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        solves.append(one_step(events[k]))
+        log(f"step {k}: solve {solves[-1]['iterations']} it, rel {solves[-1]['rel_residual']:.2e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kstats = st.kernel_stats()
+    st.kernel_timing(False)
+    fv_ms = [e[0].elapsed_time(e[1]) for e in events]
+    solve_ms = [e[1].elapsed_time(e[2]) for e in events]
+    total1 = st.conservation()
+
+    fv_total_s = sum(fv_ms) / 1e3
+    value = info.nc * args.steps / fv_total_s
+    nbytes = algorithmic_bytes(info)
+
+    def roof(name):
+        ms, n = kstats[name]
+        avg_s = ms / max(n, 1) / 1e3
+        gbs = nbytes[name] / avg_s / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"k_{name}",
+                "avg_us": round(avg_s * 1e6, 2), "launches": n,
+                "bytes_per_launch": nbytes[name]}
+
+    iters = [s["iterations"] for s in solves]
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: jittered 6-tet cube n={wl['n']} seed {wl['seed']}, "
+                               f"{info.nc} cells; RK3 step (CFL 0.4, D=1e-3, zero-flux) + "
+                               "warm-started Jacobi-CG Poisson solve to 1e-10",
+                   "cells": info.nc, "faces": info.nf, "matrix_nnz": info.matrix_nnz,
+                   "parallelism": "single GPU"},
+        "fv_ms_per_step": sum(fv_ms) / args.steps,
+        "poisson_solve_ms": sum(solve_ms) / args.steps,
+        "poisson_iterations": iters,
+        "poisson_rel_residual": max(s["rel_residual"] for s in solves),
+        "conservation_rel_drift": abs(total1 - total0) / abs(total0),
+        "roofline": roof("cg_spmv"),
+        "roofline_fv": {k: roof(k) for k in ("grad_limiter", "node_interp", "face_flux", "update")},
+        "roofline_cg": {k: roof(k) for k in ("cg_axpy", "cg_dir")},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

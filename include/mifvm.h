@@ -1,0 +1,230 @@
+/*
+ * mifvm.h - C ABI of the MI355X finite-volume library.
+ *
+ * The library implements the data-parallel hot path of the cell-centred
+ * finite-volume method of Kissami & Ratnani (arXiv 2203.00925, "Manapy"):
+ * one explicit time step of the convection-diffusion equation (Sec. 2.1,
+ * eqs. (1)-(4), (15), (diamond), (6)) on an unstructured tetrahedral mesh,
+ * and the assembly and solve of the Poisson system the same discretisation
+ * gives (Sec. 2.2, eqs. (7), (laplace)).  The calls mirror the paper's
+ * problem statement (annex example): load a mesh, declare a variable with
+ * boundary conditions, step, assemble, solve.
+ *
+ * Conventions, common to every call:
+ *  - status: 0 = OK, > 0 = non-fatal outcome, < 0 = error; no exception or
+ *    abort crosses the ABI.  mifvm_last_error() returns a thread-local text
+ *    for the last failing call on this thread (valid until the next call).
+ *  - "d_" pointers are device pointers (HIP device memory on the current
+ *    device); every other pointer is host memory.  Host arrays are copied
+ *    during the call and may be freed afterwards.
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream).  Device
+ *    work is enqueued on that stream only; calls that return a host scalar
+ *    synchronise the stream, all others are asynchronous.
+ *  - field arrays at the ABI are in the caller's ("user") cell order, the
+ *    order of the tets array given to mifvm_mesh_preprocess; the library
+ *    renumbers internally.
+ *  - handles are owned by the library and freed with the matching
+ *    *_destroy; a handle may be used by one thread at a time.
+ *  - the device workspace is owned by the caller; it must be at least
+ *    mifvm_mesh_info.ws_bytes bytes, 256-byte aligned, and outlive the
+ *    state that uses it.
+ */
+#ifndef MIFVM_H
+#define MIFVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum mifvm_status {
+    MIFVM_OK = 0,
+    MIFVM_NOT_CONVERGED = 1,   /* solve hit maxit; info is filled          */
+    MIFVM_E_ARG = -1,          /* invalid argument (null, range, size)      */
+    MIFVM_E_MESH = -2,         /* degenerate/inverted cell, non-manifold or
+                                  untagged boundary face                    */
+    MIFVM_E_HIP = -3,          /* a HIP runtime call failed                 */
+    MIFVM_E_WORKSPACE = -4,    /* workspace too small or misaligned         */
+    MIFVM_E_STATE = -5         /* call out of order (e.g. solve before
+                                  assemble)                                 */
+};
+
+/* boundary-condition kinds, per boundary tag (the per-name dictionary of the
+ * paper's annex).  Ghost value u_g = s*u_owner + t:
+ *   ZERO_FLUX  no flux of any kind crosses the face; ghost (1, 0)
+ *   NEUMANN    du/dn = value: diffusive flux D*value*|S|, convective upwind
+ *              with the ghost value on inflow; ghost (1, value*|x_g - x_L|)
+ *   DIRICHLET  u = value on the face: diamond flux with the ghost as the
+ *              right cell, convective upwind; ghost (-1, 2*value)          */
+enum mifvm_bc_kind { MIFVM_ZERO_FLUX = 0, MIFVM_NEUMANN = 1, MIFVM_DIRICHLET = 2 };
+
+/* variables with their own boundary conditions */
+enum mifvm_var { MIFVM_VAR_SCALAR = 0, MIFVM_VAR_POTENTIAL = 1 };
+
+/* per-cell fields (all float64, user cell order) */
+enum mifvm_field {
+    MIFVM_FIELD_U = 0,        /* transported scalar u                        */
+    MIFVM_FIELD_VEL = 1,      /* velocity, 3*Nc values laid out [x..., y..., z...] */
+    MIFVM_FIELD_SOURCE = 2,   /* source S_i of eq. (1)                        */
+    MIFVM_FIELD_P = 3         /* Poisson unknown (last solution)              */
+};
+
+enum mifvm_renumber { MIFVM_RENUMBER_NONE = 0, MIFVM_RENUMBER_MORTON = 1 };
+
+#define MIFVM_MAX_TAGS 32
+
+typedef struct mifvm_mesh mifvm_mesh;     /* host-side preprocessed mesh     */
+typedef struct mifvm_state mifvm_state;   /* device-resident mesh + fields   */
+
+typedef struct {
+    int32_t renumber;          /* enum mifvm_renumber                         */
+} mifvm_mesh_opts;
+
+typedef struct {
+    int64_t nc;                /* cells                                       */
+    int64_t nv;                /* vertices                                    */
+    int64_t nf;                /* faces (interior first, then boundary)       */
+    int64_t nf_interior;
+    int64_t nb;                /* boundary faces = ghost cells                */
+    int64_t stencil_entries;   /* node-neighbour entries (unpadded)           */
+    int64_t stencil_padded;    /* stored entries after 64-row slicing         */
+    int64_t node_entries;      /* vertex->cell/ghost entries (unpadded)       */
+    int64_t matrix_nnz;        /* Poisson entries incl. diagonal (pattern)    */
+    int64_t matrix_padded;     /* stored off-diagonal entries after slicing   */
+    int32_t stencil_max;       /* longest node-neighbour list                 */
+    int32_t node_max;          /* longest vertex list                         */
+    int32_t row_max;           /* longest off-diagonal matrix row             */
+    int32_t pad_;
+    size_t ws_bytes;           /* device workspace needed by a state          */
+} mifvm_mesh_info;
+
+typedef struct {
+    double diffusivity;        /* D of eq. (1)                                */
+} mifvm_params;
+
+typedef struct {
+    double tol;                /* relative true residual ||b-Kx||/||b||       */
+    int32_t maxit;
+    int32_t chunk;             /* iterations enqueued between host checks    */
+} mifvm_solve_opts;
+
+typedef struct {
+    int32_t iterations;
+    int32_t restarts;          /* times the true residual reopened the loop   */
+    double rel_residual;       /* final true relative residual (FP64)        */
+    double ms;                 /* wall time of the solve call                */
+} mifvm_solve_info;
+
+/* ---- errors --------------------------------------------------------------- */
+const char* mifvm_last_error(void);
+const char* mifvm_version(void);
+
+/* ---- load mesh (readmesh + Domain of the paper's annex) --------------------
+ * xyz: float64 [nv][3]; tets: int32 [nc][4] (any orientation); btris: int32
+ * [nb][3] boundary triangles with tags btags[nb] in [0, MIFVM_MAX_TAGS).
+ * Computes, on the host: orientation, volumes, centres of gravity, faces
+ * (interior ones have L = the owner with the smaller user index), face
+ * vectors S (L -> R), face centroids, ghost cells (owner centre mirrored
+ * across the face), the node-neighbour stencil of Algorithm 1 with the
+ * inverse of its normal matrix, the vertex lists of Algorithm 2 with their
+ * least-squares weights, the diamond coefficients of eq. (diamond), the
+ * cell->face table and the sparsity pattern of the Poisson matrix; then
+ * renumbers cells by a Morton curve of their centres.
+ * Errors: E_ARG (null/negative sizes, index out of range), E_MESH (cell
+ * volume <= 1e-14 * mean volume, a face shared by more than two cells, a
+ * boundary face without a tag or a tag on an interior face).              */
+int mifvm_mesh_preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
+                          const int32_t* btris, const int32_t* btags, int64_t nb,
+                          const mifvm_mesh_opts* opts, mifvm_mesh** out);
+int mifvm_mesh_get_info(const mifvm_mesh* mesh, mifvm_mesh_info* out);
+void mifvm_mesh_destroy(mifvm_mesh* mesh);
+
+/* Copy one preprocessed host array out (for inspection and tests; no GPU).
+ * what (all internal numbering unless stated):
+ *   0 CELL_PERM   int32 [nc]  internal cell -> user cell
+ *   1 VERT_PERM   int32 [nv]  internal vertex -> user vertex
+ *   2 VOLUME      f64   [nc]
+ *   3 CENTRE      f64   [3][nc+nb]  cells then ghosts, SoA
+ *   4 FACE_LR     int32 [2][nf]     L, R (R >= nc: ghost R-nc)
+ *   5 FACE_ABC    int32 [3][nf]     diamond vertex labels (internal vertices)
+ *   6 FACE_COEF   f64   [3][nf]     kAC, kBC, kRL
+ *   7 FACE_S      f64   [3][nf]     face vector
+ *   8 STENCIL_PTR int64 [nc+1]      CSR over internal cells
+ *   9 STENCIL_IDX int32 [stencil_entries]  cell or nc+ghost, ascending
+ *  10 NODE_PTR    int64 [nv+1]
+ *  11 NODE_IDX    int32 [node_entries]
+ *  12 NODE_ALPHA  f64   [node_entries]
+ *  13 GHOST_OWNER int32 [nb]
+ *  14 GHOST_TAG   int32 [nb]
+ *  15 MINV        f64   [6][nc]     xx, xy, xz, yy, yz, zz of M_i^{-1}
+ * bytes must equal the array's size exactly (E_ARG otherwise).            */
+int mifvm_mesh_export(const mifvm_mesh* mesh, int32_t what, void* dst, size_t bytes);
+
+/* ---- variable + boundary conditions (Variable(domain, BC, values)) ------- */
+int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params,
+                       void* d_ws, size_t ws_bytes, void* stream, mifvm_state** out);
+void mifvm_state_destroy(mifvm_state* st);
+/* kind/value for one boundary tag of one variable; takes effect at the next
+ * step (SCALAR) or assemble (POTENTIAL).  Default: ZERO_FLUX, 0.           */
+int mifvm_set_bc(mifvm_state* st, int32_t var, int32_t tag, int32_t kind, double value);
+int mifvm_set_diffusivity(mifvm_state* st, double diffusivity);
+/* d_src: float64 in user cell order (3*nc for VEL).  Setting VEL recomputes
+ * the face velocity fluxes phi_f = 1/2 (V_L + V_R) . S_f.                  */
+int mifvm_set_field(mifvm_state* st, int32_t field, const double* d_src, void* stream);
+int mifvm_get_field(const mifvm_state* st, int32_t field, double* d_dst, void* stream);
+
+/* ---- step (eq. (4) with the Runge-Kutta scheme of eq. (6)) ---------------
+ * dt = cfl * min_i mu_i / sum_{faces of i not ZERO_FLUX} (|phi_f| + D kRL_f).
+ * Synchronises.                                                            */
+int mifvm_cfl_dt(mifvm_state* st, double cfl, double* dt_out, void* stream);
+/* n_steps explicit 3-stage steps u^(k) = u^n + a_k dt Res(u^(k-1)),
+ * a = (1/2, 1/2, 1).  Asynchronous.                                        */
+int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream);
+/* One evaluation of Res(U) and its parts, for inspection; any output may be
+ * NULL.  d_res, d_psi [nc], d_grad [3][nc] in user cell order; d_unode [nv]
+ * in user vertex order; d_flux [nf] in internal face order (FACE_LR gives
+ * each face's cells).                                                      */
+int mifvm_residual(mifvm_state* st, double* d_res, double* d_grad, double* d_psi,
+                   double* d_unode, double* d_flux, void* stream);
+/* sum_i mu_i u_i in FP64, deterministic order.  Synchronises.              */
+int mifvm_conservation(mifvm_state* st, double* total_out, void* stream);
+
+/* ---- Poisson (LinearSystem.assembly() / .solve()) ------------------------
+ * Assemble K and the ghost-constant vector c of K P = -mu*f + c, from the
+ * POTENTIAL boundary conditions (rows without the 1/mu_i factor, sign
+ * flipped so that the diagonal is positive).  Asynchronous.                */
+int mifvm_poisson_assemble(mifvm_state* st, void* stream);
+/* d_y = K d_x, both user order.                                            */
+int mifvm_poisson_apply(mifvm_state* st, const double* d_x, double* d_y, void* stream);
+/* d_b = -mu * d_f + c (user order; d_f NULL = the current U).              */
+int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* stream);
+/* Jacobi-preconditioned CG on K x = b with b from d_f (NULL = current U);
+ * starts from the stored P (zero after create, the last solution after a
+ * solve: warm start) and stores the result back in P.  Converged when the
+ * recomputed FP64 true residual ||b - K x||_2 <= tol ||b||_2.  opts NULL =
+ * tol 1e-10, maxit 20000, chunk 32.  Returns NOT_CONVERGED at maxit.
+ * Synchronises (once per chunk).                                           */
+int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_opts* opts,
+                        mifvm_solve_info* info, void* stream);
+
+/* ---- per-kernel timing (HIP events on the launch stream) -----------------
+ * enable != 0 starts recording an event pair around every kernel launch of
+ * this state and clears the totals; enable == 0 stops.  Kernel ids: */
+enum mifvm_kernel {
+    MIFVM_K_GHOST_FILL = 0, MIFVM_K_GRAD_LIMITER = 1, MIFVM_K_NODE_INTERP = 2,
+    MIFVM_K_FACE_FLUX = 3, MIFVM_K_UPDATE = 4, MIFVM_K_CG_SETUP = 5, MIFVM_K_CG_SPMV = 6,
+    MIFVM_K_CG_AXPY = 7, MIFVM_K_CG_DIR = 8, MIFVM_K_RHS = 9, MIFVM_K_ASSEMBLE = 10,
+    MIFVM_K_COUNT = 11
+};
+int mifvm_kernel_timing(mifvm_state* st, int32_t enable);
+/* Total milliseconds and number of timed launches of one kernel since the
+ * last enable.  Synchronises the stream.                                    */
+int mifvm_kernel_stats(mifvm_state* st, int32_t kernel, double* total_ms, int64_t* launches,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MIFVM_H */

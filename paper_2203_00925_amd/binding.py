@@ -1,0 +1,297 @@
+"""Thin Python binding of libmifvm (ctypes over the C ABI in include/mifvm.h).
+
+Argument marshalling only: host arrays are passed as NumPy buffers, device
+buffers as torch CUDA (HIP) tensors' data pointers, streams as the raw
+hipStream_t of a torch stream.  Every computation runs in the library.  If
+the library has not been built, importing this module raises - there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libmifvm.so")
+
+OK, NOT_CONVERGED = 0, 1
+ZERO_FLUX, NEUMANN, DIRICHLET = 0, 1, 2
+VAR_SCALAR, VAR_POTENTIAL = 0, 1
+FIELD_U, FIELD_VEL, FIELD_SOURCE, FIELD_P = 0, 1, 2, 3
+RENUMBER_NONE, RENUMBER_MORTON = 0, 1
+KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
+           "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble")
+
+EXPORTS = {  # id: (name, dtype, shape-fn(info))
+    0: ("cell_perm", np.int32, lambda i: (i.nc,)),
+    1: ("vert_perm", np.int32, lambda i: (i.nv,)),
+    2: ("volume", np.float64, lambda i: (i.nc,)),
+    3: ("centre", np.float64, lambda i: (3, i.nc + i.nb)),
+    4: ("face_lr", np.int32, lambda i: (2, i.nf)),
+    5: ("face_abc", np.int32, lambda i: (3, i.nf)),
+    6: ("face_coef", np.float64, lambda i: (3, i.nf)),
+    7: ("face_s", np.float64, lambda i: (3, i.nf)),
+    8: ("stencil_ptr", np.int64, lambda i: (i.nc + 1,)),
+    9: ("stencil_idx", np.int32, lambda i: (i.stencil_entries,)),
+    10: ("node_ptr", np.int64, lambda i: (i.nv + 1,)),
+    11: ("node_idx", np.int32, lambda i: (i.node_entries,)),
+    12: ("node_alpha", np.float64, lambda i: (i.node_entries,)),
+    13: ("ghost_owner", np.int32, lambda i: (i.nb,)),
+    14: ("ghost_tag", np.int32, lambda i: (i.nb,)),
+    15: ("minv", np.float64, lambda i: (6, i.nc)),
+}
+EXPORT_IDS = {v[0]: k for k, v in EXPORTS.items()}
+
+
+class MifvmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mifvm error {code}: {msg}")
+        self.code = code
+
+
+class _MeshOpts(C.Structure):
+    _fields_ = [("renumber", C.c_int32)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("nc", C.c_int64), ("nv", C.c_int64), ("nf", C.c_int64),
+                ("nf_interior", C.c_int64), ("nb", C.c_int64),
+                ("stencil_entries", C.c_int64), ("stencil_padded", C.c_int64),
+                ("node_entries", C.c_int64), ("matrix_nnz", C.c_int64),
+                ("matrix_padded", C.c_int64), ("stencil_max", C.c_int32),
+                ("node_max", C.c_int32), ("row_max", C.c_int32), ("pad_", C.c_int32),
+                ("ws_bytes", C.c_size_t)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("diffusivity", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("chunk", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32),
+                ("rel_residual", C.c_double), ("ms", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                          "`python -m paper_2203_00925_amd.build` (no fallback exists)")
+    lib = C.CDLL(_LIB_PATH)
+    P, I32, I64, D, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    sig = {
+        "mifvm_last_error": (C.c_char_p, []),
+        "mifvm_version": (C.c_char_p, []),
+        "mifvm_mesh_preprocess": (C.c_int, [P, I64, P, I64, P, P, I64, P, C.POINTER(P)]),
+        "mifvm_mesh_get_info": (C.c_int, [P, C.POINTER(MeshInfo)]),
+        "mifvm_mesh_destroy": (None, [P]),
+        "mifvm_mesh_export": (C.c_int, [P, I32, P, SZ]),
+        "mifvm_state_create": (C.c_int, [P, C.POINTER(_Params), P, SZ, P, C.POINTER(P)]),
+        "mifvm_state_destroy": (None, [P]),
+        "mifvm_set_bc": (C.c_int, [P, I32, I32, I32, D]),
+        "mifvm_set_diffusivity": (C.c_int, [P, D]),
+        "mifvm_set_field": (C.c_int, [P, I32, P, P]),
+        "mifvm_get_field": (C.c_int, [P, I32, P, P]),
+        "mifvm_cfl_dt": (C.c_int, [P, D, C.POINTER(D), P]),
+        "mifvm_step": (C.c_int, [P, I32, D, P]),
+        "mifvm_residual": (C.c_int, [P, P, P, P, P, P, P]),
+        "mifvm_conservation": (C.c_int, [P, C.POINTER(D), P]),
+        "mifvm_poisson_assemble": (C.c_int, [P, P]),
+        "mifvm_poisson_apply": (C.c_int, [P, P, P, P]),
+        "mifvm_poisson_rhs": (C.c_int, [P, P, P, P]),
+        "mifvm_poisson_solve": (C.c_int, [P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), P]),
+        "mifvm_kernel_timing": (C.c_int, [P, I32]),
+        "mifvm_kernel_stats": (C.c_int, [P, I32, C.POINTER(D), C.POINTER(I64), P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc, allow=(OK,)):
+    if rc not in allow:
+        raise MifvmError(rc, _lib.mifvm_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    """Device pointer of a torch tensor (or None)."""
+    return None if a is None else C.c_void_p(a.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Mesh:
+    """Host-side preprocessed mesh (mifvm_mesh_preprocess)."""
+
+    def __init__(self, xyz, tets, btris, btags, renumber=RENUMBER_MORTON):
+        xyz = np.ascontiguousarray(xyz, np.float64)
+        tets = np.ascontiguousarray(tets, np.int32)
+        btris = np.ascontiguousarray(btris, np.int32)
+        btags = np.ascontiguousarray(btags, np.int32)
+        h = C.c_void_p()
+        opts = _MeshOpts(renumber)
+        _check(_lib.mifvm_mesh_preprocess(
+            xyz.ctypes.data, len(xyz), tets.ctypes.data, len(tets),
+            btris.ctypes.data, btags.ctypes.data, len(btags), C.byref(opts), C.byref(h)))
+        self._h = h
+        self.info = MeshInfo()
+        _check(_lib.mifvm_mesh_get_info(h, C.byref(self.info)))
+
+    @classmethod
+    def from_cube(cls, m, renumber=RENUMBER_MORTON):
+        return cls(m.xyz, m.tets, m.btris, m.btags, renumber)
+
+    def export(self, name):
+        what = EXPORT_IDS[name]
+        _, dt, shape = EXPORTS[what]
+        out = np.empty(shape(self.info), dt)
+        _check(_lib.mifvm_mesh_export(self._h, what, out.ctypes.data, out.nbytes))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.mifvm_mesh_destroy(h)
+            self._h = None
+
+
+class State:
+    """Device-resident mesh and fields (mifvm_state_create); the workspace is
+    a torch uint8 tensor on the current device."""
+
+    def __init__(self, mesh: Mesh, diffusivity=0.0, device="cuda", stream=None):
+        import torch
+        self.mesh = mesh
+        nbytes = int(mesh.info.ws_bytes)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self._off = (-base) % 256
+        h = C.c_void_p()
+        params = _Params(float(diffusivity))
+        _check(_lib.mifvm_state_create(mesh._h, C.byref(params), C.c_void_p(base + self._off),
+                                       nbytes, _stream(stream), C.byref(h)))
+        self._h = h
+        self.device = device
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.mifvm_state_destroy(h)
+            self._h = None
+
+    # -- boundary conditions and fields --------------------------------------
+    def set_bc(self, var, tag, kind, value=0.0):
+        _check(_lib.mifvm_set_bc(self._h, var, tag, kind, float(value)))
+
+    def set_bcs(self, var, kinds, values=None):
+        values = values if values is not None else [0.0] * len(kinds)
+        for t, (k, v) in enumerate(zip(kinds, values)):
+            self.set_bc(var, t, k, v)
+
+    def set_diffusivity(self, D):
+        _check(_lib.mifvm_set_diffusivity(self._h, float(D)))
+
+    def set_field(self, field, t, stream=None):
+        import torch
+        t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        _check(_lib.mifvm_set_field(self._h, field, _ptr(t), _stream(stream)))
+        (stream or torch.cuda.current_stream()).synchronize()   # t may be a temporary
+
+    def get_field(self, field, stream=None):
+        import torch
+        n = self.mesh.info.nc * (3 if field == FIELD_VEL else 1)
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        _check(_lib.mifvm_get_field(self._h, field, _ptr(out), _stream(stream)))
+        return out
+
+    # -- step ------------------------------------------------------------------
+    def cfl_dt(self, cfl, stream=None):
+        dt = C.c_double()
+        _check(_lib.mifvm_cfl_dt(self._h, float(cfl), C.byref(dt), _stream(stream)))
+        return dt.value
+
+    def step(self, n_steps, dt, stream=None):
+        _check(_lib.mifvm_step(self._h, int(n_steps), float(dt), _stream(stream)))
+
+    def residual(self, stream=None):
+        import torch
+        i = self.mesh.info
+        kw = dict(dtype=torch.float64, device=self.device)
+        res = torch.empty(i.nc, **kw)
+        grad = torch.empty(3 * i.nc, **kw)
+        psi = torch.empty(i.nc, **kw)
+        un = torch.empty(i.nv, **kw)
+        flux = torch.empty(i.nf, **kw)
+        _check(_lib.mifvm_residual(self._h, _ptr(res), _ptr(grad), _ptr(psi), _ptr(un),
+                                   _ptr(flux), _stream(stream)))
+        return dict(res=res, grad=grad.view(3, i.nc), psi=psi, u_node=un, flux=flux)
+
+    def conservation(self, stream=None):
+        t = C.c_double()
+        _check(_lib.mifvm_conservation(self._h, C.byref(t), _stream(stream)))
+        return t.value
+
+    # -- Poisson -----------------------------------------------------------------
+    def poisson_assemble(self, stream=None):
+        _check(_lib.mifvm_poisson_assemble(self._h, _stream(stream)))
+
+    def poisson_apply(self, x, stream=None):
+        import torch
+        x = x.to(device=self.device, dtype=torch.float64).contiguous()
+        y = torch.empty_like(x)
+        _check(_lib.mifvm_poisson_apply(self._h, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def poisson_rhs(self, f=None, stream=None):
+        import torch
+        y = torch.empty(self.mesh.info.nc, dtype=torch.float64, device=self.device)
+        if f is not None:
+            f = f.to(device=self.device, dtype=torch.float64).contiguous()
+        _check(_lib.mifvm_poisson_rhs(self._h, _ptr(f), _ptr(y), _stream(stream)))
+        return y
+
+    def poisson_solve(self, f=None, tol=1e-10, maxit=20000, chunk=32, stream=None,
+                      allow_not_converged=False):
+        import torch
+        if f is not None:
+            f = f.to(device=self.device, dtype=torch.float64).contiguous()
+        opts = SolveOpts(float(tol), int(maxit), int(chunk))
+        info = SolveInfo()
+        allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        rc = _check(_lib.mifvm_poisson_solve(self._h, _ptr(f), C.byref(opts), C.byref(info),
+                                             _stream(stream)), allow)
+        return dict(status=rc, iterations=info.iterations, restarts=info.restarts,
+                    rel_residual=info.rel_residual, ms=info.ms)
+
+    # -- per-kernel timing ----------------------------------------------------------
+    def kernel_timing(self, enable=True):
+        _check(_lib.mifvm_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_stats(self, stream=None):
+        """{kernel: (total_ms, launches)} since timing was enabled (synchronises)."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms, n = C.c_double(), C.c_int64()
+            _check(_lib.mifvm_kernel_stats(self._h, k, C.byref(ms), C.byref(n), _stream(stream)))
+            out[name] = (ms.value, n.value)
+        return out

@@ -1,0 +1,574 @@
+// C ABI of the library (declared in include/mifvm.h): argument checking,
+// workspace layout, and the host-side sequencing of the kernels (stages of
+// eq. (6), chunks of CG iterations).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/mifvm.h"
+#include "mesh.h"
+#include "state.h"
+
+struct mifvm_mesh {
+    mifvm::Mesh m;
+};
+struct mifvm_state {
+    mifvm::State s;
+};
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+int hip_fail(hipError_t e, const char* where) {
+    return fail(MIFVM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(call)                                          \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);     \
+    } while (0)
+
+inline hipStream_t S(void* p) { return reinterpret_cast<hipStream_t>(p); }
+
+template <class T>
+T* carve(char* base, size_t& off, size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+}
+
+template <class T>
+hipError_t up(T* dst, const std::vector<T>& src, hipStream_t s) {
+    if (src.empty()) return hipSuccess;
+    return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+int reduce_blocks(int64_t n) {
+    int64_t b = (n + mifvm::kBlock - 1) / mifvm::kBlock;
+    return int(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+}
+
+// Launch `fn` on `s`; with timing on, bracket it with an event pair.
+template <class F>
+hipError_t timed(mifvm::KernelTimer& t, int kid, hipStream_t s, F fn) {
+    if (!t.on) return fn();
+    while (t.pool.size() < t.used + 2) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        t.pool.push_back(e);
+    }
+    const size_t at = t.used;
+    t.used += 2;
+    hipError_t err = hipEventRecord(t.pool[at], s);
+    if (err != hipSuccess) return err;
+    err = fn();
+    if (err != hipSuccess) return err;
+    err = hipEventRecord(t.pool[at + 1], s);
+    if (err != hipSuccess) return err;
+    t.pending.emplace_back(kid, at);
+    return hipSuccess;
+}
+
+// After the stream has been synchronised: fold pending pairs into totals.
+hipError_t timer_flush(mifvm::KernelTimer& t) {
+    for (auto& pr : t.pending) {
+        float ms = 0.f;
+        hipError_t err = hipEventElapsedTime(&ms, t.pool[pr.second], t.pool[pr.second + 1]);
+        if (err != hipSuccess) return err;
+        t.total_ms[pr.first] += ms;
+        t.count[pr.first] += 1;
+    }
+    t.pending.clear();
+    t.used = 0;
+    return hipSuccess;
+}
+}  // namespace
+
+namespace mifvm {
+
+size_t layout(const Mesh& m, char* base, Dev& d) {
+    size_t off = 0;
+    const int64_t nc = m.nc, nv = m.nv, nf = m.nf, nb = m.nb, NX = nc + nb;
+    d.nc = nc; d.nv = nv; d.nf = nf; d.nfi = m.nfi; d.nb = nb;
+    d.ns = m.stencil.nslices; d.nvs = m.node.nslices;
+    d.vol = carve<double>(base, off, nc);
+    d.xc = carve<double>(base, off, 3 * NX);
+    d.minv = carve<double>(base, off, 6 * nc);
+    d.c2f = carve<int32_t>(base, off, 4 * nc);
+    d.c2n = carve<int32_t>(base, off, 4 * nc);
+    d.s_off = carve<int64_t>(base, off, m.stencil.off.size());
+    d.s_w = carve<int32_t>(base, off, m.stencil.width.size());
+    d.s_idx = carve<int32_t>(base, off, m.stencil.idx.size());
+    d.fL = carve<int32_t>(base, off, nf);
+    d.fR = carve<int32_t>(base, off, nf);
+    d.fA = carve<int32_t>(base, off, nf);
+    d.fB = carve<int32_t>(base, off, nf);
+    d.fC = carve<int32_t>(base, off, nf);
+    d.kAC = carve<double>(base, off, nf);
+    d.kBC = carve<double>(base, off, nf);
+    d.kRL = carve<double>(base, off, nf);
+    d.fx = carve<double>(base, off, 3 * nf);
+    d.S = carve<double>(base, off, 3 * nf);
+    d.area = carve<double>(base, off, nf);
+    d.gowner = carve<int32_t>(base, off, nb);
+    d.gtag = carve<int32_t>(base, off, nb);
+    d.gdist = carve<double>(base, off, nb);
+    d.n_off = carve<int64_t>(base, off, m.node.off.size());
+    d.n_w = carve<int32_t>(base, off, m.node.width.size());
+    d.n_idx = carve<int32_t>(base, off, m.node.idx.size());
+    d.n_alpha = carve<double>(base, off, m.node.val.size());
+    d.k_off = carve<int64_t>(base, off, m.kmat.off.size());
+    d.k_w = carve<int32_t>(base, off, m.kmat.width.size());
+    d.k_col = carve<int32_t>(base, off, m.kmat.idx.size());
+    d.k_len = carve<int32_t>(base, off, nc);
+    d.k_val = carve<double>(base, off, m.kmat.idx.size());
+    d.k_diag = carve<double>(base, off, nc);
+    d.k_dinv = carve<double>(base, off, nc);
+    d.k_c = carve<double>(base, off, nc);
+    d.cell_perm = carve<int32_t>(base, off, nc);
+    d.vert_perm = carve<int32_t>(base, off, nv);
+    d.u = carve<double>(base, off, NX);
+    d.un = carve<double>(base, off, nc);
+    d.src = carve<double>(base, off, nc);
+    d.vel = carve<double>(base, off, 3 * nc);
+    d.phi = carve<double>(base, off, nf);
+    d.grad = carve<double>(base, off, 3 * nc);
+    d.psi = carve<double>(base, off, nc);
+    d.unode = carve<double>(base, off, nv);
+    d.flux = carve<double>(base, off, nf);
+    d.x = carve<double>(base, off, nc);
+    d.r = carve<double>(base, off, nc);
+    d.z = carve<double>(base, off, nc);
+    d.p = carve<double>(base, off, nc);
+    d.q = carve<double>(base, off, nc);
+    d.b = carve<double>(base, off, nc);
+    d.tmp = carve<double>(base, off, 3 * NX);
+    const int64_t nblk = (nc + kBlock - 1) / kBlock;
+    d.partial = carve<double>(base, off, 4 * (nblk + 1024));
+    d.scal = carve<double>(base, off, SC_COUNT_);
+    d.counter = carve<uint32_t>(base, off, 64);
+    return (off + 255) & ~size_t(255);
+}
+
+}  // namespace mifvm
+
+using namespace mifvm;
+
+extern "C" {
+
+const char* mifvm_last_error(void) { return g_err.c_str(); }
+const char* mifvm_version(void) { return "mifvm 0.1 (gfx950, fp64)"; }
+
+int mifvm_mesh_preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
+                          const int32_t* btris, const int32_t* btags, int64_t nb,
+                          const mifvm_mesh_opts* opts, mifvm_mesh** out) {
+    if (!out) return fail(MIFVM_E_ARG, "out is null");
+    *out = nullptr;
+    auto* h = new (std::nothrow) mifvm_mesh();
+    if (!h) return fail(MIFVM_E_ARG, "out of host memory");
+    std::string err;
+    int rc;
+    try {
+        rc = preprocess(xyz, nv, tets, nc, btris, btags, nb, opts ? opts->renumber : 1, h->m, err);
+    } catch (const std::bad_alloc&) {
+        rc = MIFVM_E_ARG;
+        err = "out of host memory";
+    }
+    if (rc != 0) {
+        delete h;
+        return fail(rc, err);
+    }
+    *out = h;
+    return MIFVM_OK;
+}
+
+int mifvm_mesh_get_info(const mifvm_mesh* mesh, mifvm_mesh_info* out) {
+    if (!mesh || !out) return fail(MIFVM_E_ARG, "null argument");
+    const Mesh& m = mesh->m;
+    std::memset(out, 0, sizeof(*out));
+    out->nc = m.nc; out->nv = m.nv; out->nf = m.nf; out->nf_interior = m.nfi; out->nb = m.nb;
+    out->stencil_entries = (int64_t)m.sidx.size();
+    out->stencil_padded = (int64_t)m.stencil.idx.size();
+    out->node_entries = (int64_t)m.nidx.size();
+    out->matrix_nnz = m.matrix_nnz;
+    out->matrix_padded = (int64_t)m.kmat.idx.size();
+    out->stencil_max = m.stencil_max;
+    out->node_max = m.node_max;
+    out->row_max = m.row_max;
+    Dev d{};
+    out->ws_bytes = layout(m, nullptr, d);
+    return MIFVM_OK;
+}
+
+void mifvm_mesh_destroy(mifvm_mesh* mesh) { delete mesh; }
+
+int mifvm_mesh_export(const mifvm_mesh* mesh, int32_t what, void* dst, size_t bytes) {
+    if (!mesh || !dst) return fail(MIFVM_E_ARG, "null argument");
+    const Mesh& m = mesh->m;
+    const void* src = nullptr;
+    size_t n = 0;
+    std::vector<int32_t> tmp32;
+    std::vector<double> tmp64;
+    switch (what) {
+        case 0: src = m.cell_perm.data(); n = m.cell_perm.size() * 4; break;
+        case 1: src = m.vert_perm.data(); n = m.vert_perm.size() * 4; break;
+        case 2: src = m.vol.data(); n = m.vol.size() * 8; break;
+        case 3: src = m.xc.data(); n = m.xc.size() * 8; break;
+        case 4:
+            tmp32 = m.fL; tmp32.insert(tmp32.end(), m.fR.begin(), m.fR.end());
+            src = tmp32.data(); n = tmp32.size() * 4; break;
+        case 5:
+            tmp32 = m.fA; tmp32.insert(tmp32.end(), m.fB.begin(), m.fB.end());
+            tmp32.insert(tmp32.end(), m.fC.begin(), m.fC.end());
+            src = tmp32.data(); n = tmp32.size() * 4; break;
+        case 6:
+            tmp64 = m.kAC; tmp64.insert(tmp64.end(), m.kBC.begin(), m.kBC.end());
+            tmp64.insert(tmp64.end(), m.kRL.begin(), m.kRL.end());
+            src = tmp64.data(); n = tmp64.size() * 8; break;
+        case 7: src = m.S.data(); n = m.S.size() * 8; break;
+        case 8: src = m.sptr.data(); n = m.sptr.size() * 8; break;
+        case 9: src = m.sidx.data(); n = m.sidx.size() * 4; break;
+        case 10: src = m.nptr.data(); n = m.nptr.size() * 8; break;
+        case 11: src = m.nidx.data(); n = m.nidx.size() * 4; break;
+        case 12: src = m.nalpha.data(); n = m.nalpha.size() * 8; break;
+        case 13: src = m.gowner.data(); n = m.gowner.size() * 4; break;
+        case 14: src = m.gtag.data(); n = m.gtag.size() * 4; break;
+        case 15: src = m.minv.data(); n = m.minv.size() * 8; break;
+        default: return fail(MIFVM_E_ARG, "unknown export id");
+    }
+    if (bytes != n) return fail(MIFVM_E_ARG, "size mismatch: expected " + std::to_string(n) + " bytes");
+    if (n) std::memcpy(dst, src, n);
+    return MIFVM_OK;
+}
+
+int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void* d_ws, size_t ws_bytes,
+                       void* stream, mifvm_state** out) {
+    if (!mesh || !out || !d_ws) return fail(MIFVM_E_ARG, "null argument");
+    *out = nullptr;
+    if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(MIFVM_E_WORKSPACE, "workspace not 256-byte aligned");
+    const Mesh& m = mesh->m;
+    Dev probe{};
+    const size_t need = layout(m, nullptr, probe);
+    if (ws_bytes < need) return fail(MIFVM_E_WORKSPACE, "workspace too small: need " + std::to_string(need));
+    auto* h = new (std::nothrow) mifvm_state();
+    if (!h) return fail(MIFVM_E_ARG, "out of host memory");
+    State& st = h->s;
+    st.mesh = &m;
+    layout(m, static_cast<char*>(d_ws), st.d);
+    st.diffusivity = params ? params->diffusivity : 0.0;
+    for (int v = 0; v < 2; ++v)
+        for (int t = 0; t < kMaxTags; ++t) {
+            st.bc[v].kind[t] = kZeroFlux;
+            st.bc[v].value[t] = 0.0;
+        }
+    st.nblk_cells = reduce_blocks(m.nc);
+    hipStream_t s = S(stream);
+    const Dev& d = st.d;
+    auto cleanup = [&](int rc) {
+        delete h;
+        return rc;
+    };
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&st.h_scal), SC_COUNT_ * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipHostMalloc"));
+#define UP(dst, vec)                                            \
+    do {                                                        \
+        hipError_t e2 = up(dst, vec, s);                        \
+        if (e2 != hipSuccess) return cleanup(hip_fail(e2, "upload " #vec)); \
+    } while (0)
+    UP(d.vol, m.vol); UP(d.xc, m.xc); UP(d.minv, m.minv); UP(d.c2f, m.c2f); UP(d.c2n, m.c2n);
+    UP(d.s_off, m.stencil.off); UP(d.s_w, m.stencil.width); UP(d.s_idx, m.stencil.idx);
+    UP(d.fL, m.fL); UP(d.fR, m.fR); UP(d.fA, m.fA); UP(d.fB, m.fB); UP(d.fC, m.fC);
+    UP(d.kAC, m.kAC); UP(d.kBC, m.kBC); UP(d.kRL, m.kRL); UP(d.fx, m.fx); UP(d.S, m.S); UP(d.area, m.area);
+    UP(d.gowner, m.gowner); UP(d.gtag, m.gtag); UP(d.gdist, m.gdist);
+    UP(d.n_off, m.node.off); UP(d.n_w, m.node.width); UP(d.n_idx, m.node.idx); UP(d.n_alpha, m.node.val);
+    UP(d.k_off, m.kmat.off); UP(d.k_w, m.kmat.width); UP(d.k_col, m.kmat.idx); UP(d.k_len, m.klen);
+    UP(d.cell_perm, m.cell_perm); UP(d.vert_perm, m.vert_perm);
+#undef UP
+    const int64_t NX = m.nc + m.nb;
+    e = hipMemsetAsync(d.u, 0, NX * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.src, 0, m.nc * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.vel, 0, 3 * m.nc * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.phi, 0, m.nf * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.x, 0, m.nc * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.scal, 0, SC_COUNT_ * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 64 * sizeof(uint32_t), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // host vectors are not pinned
+    if (e != hipSuccess) return cleanup(hip_fail(e, "state init"));
+    *out = h;
+    return MIFVM_OK;
+}
+
+void mifvm_state_destroy(mifvm_state* st) {
+    if (!st) return;
+    if (st->s.h_scal) (void)hipHostFree(st->s.h_scal);
+    for (hipEvent_t e : st->s.timer.pool) (void)hipEventDestroy(e);
+    delete st;
+}
+
+int mifvm_kernel_timing(mifvm_state* st, int32_t enable) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    KernelTimer& t = st->s.timer;
+    if (!t.pending.empty()) return fail(MIFVM_E_STATE, "timed launches not yet collected (call mifvm_kernel_stats)");
+    t.on = enable != 0;
+    if (t.on)
+        for (int k = 0; k < kNumKernels; ++k) {
+            t.total_ms[k] = 0.0;
+            t.count[k] = 0;
+        }
+    return MIFVM_OK;
+}
+
+int mifvm_kernel_stats(mifvm_state* st, int32_t kernel, double* total_ms, int64_t* launches, void* stream) {
+    if (!st || !total_ms || !launches) return fail(MIFVM_E_ARG, "null argument");
+    if (kernel < 0 || kernel >= kNumKernels) return fail(MIFVM_E_ARG, "unknown kernel id");
+    KernelTimer& t = st->s.timer;
+    HIPCHK(hipStreamSynchronize(S(stream)));
+    HIPCHK(timer_flush(t));
+    *total_ms = t.total_ms[kernel];
+    *launches = t.count[kernel];
+    return MIFVM_OK;
+}
+
+int mifvm_set_bc(mifvm_state* st, int32_t var, int32_t tag, int32_t kind, double value) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    if (var < 0 || var > 1) return fail(MIFVM_E_ARG, "unknown variable");
+    if (tag < 0 || tag >= kMaxTags) return fail(MIFVM_E_ARG, "tag out of range");
+    if (kind < 0 || kind > 2) return fail(MIFVM_E_ARG, "unknown boundary-condition kind");
+    if (!std::isfinite(value)) return fail(MIFVM_E_ARG, "non-finite boundary value");
+    st->s.bc[var].kind[tag] = kind;
+    st->s.bc[var].value[tag] = value;
+    if (var == MIFVM_VAR_POTENTIAL) st->s.assembled = false;
+    return MIFVM_OK;
+}
+
+int mifvm_set_diffusivity(mifvm_state* st, double D) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    if (!(D >= 0) || !std::isfinite(D)) return fail(MIFVM_E_ARG, "diffusivity must be finite and >= 0");
+    st->s.diffusivity = D;
+    return MIFVM_OK;
+}
+
+int mifvm_set_field(mifvm_state* st, int32_t field, const double* d_src, void* stream) {
+    if (!st || !d_src) return fail(MIFVM_E_ARG, "null argument");
+    State& s = st->s;
+    const Dev& d = s.d;
+    hipStream_t hs = S(stream);
+    switch (field) {
+        case MIFVM_FIELD_U:
+            HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.u, hs));
+            HIPCHK(launch_ghost_fill(d, d.u, s.bc[0], hs));
+            break;
+        case MIFVM_FIELD_VEL:
+            HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 3, d_src, d.vel, hs));
+            HIPCHK(launch_face_phi(d, hs));
+            s.vel_set = true;
+            break;
+        case MIFVM_FIELD_SOURCE:
+            HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.src, hs));
+            break;
+        case MIFVM_FIELD_P:
+            HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.x, hs));
+            break;
+        default:
+            return fail(MIFVM_E_ARG, "unknown field");
+    }
+    return MIFVM_OK;
+}
+
+int mifvm_get_field(const mifvm_state* st, int32_t field, double* d_dst, void* stream) {
+    if (!st || !d_dst) return fail(MIFVM_E_ARG, "null argument");
+    const Dev& d = st->s.d;
+    hipStream_t hs = S(stream);
+    switch (field) {
+        case MIFVM_FIELD_U: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.u, d_dst, hs)); break;
+        case MIFVM_FIELD_VEL: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 3, d.vel, d_dst, hs)); break;
+        case MIFVM_FIELD_SOURCE: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.src, d_dst, hs)); break;
+        case MIFVM_FIELD_P: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.x, d_dst, hs)); break;
+        default: return fail(MIFVM_E_ARG, "unknown field");
+    }
+    return MIFVM_OK;
+}
+
+int mifvm_cfl_dt(mifvm_state* st, double cfl, double* dt_out, void* stream) {
+    if (!st || !dt_out) return fail(MIFVM_E_ARG, "null argument");
+    if (!(cfl > 0)) return fail(MIFVM_E_ARG, "cfl must be > 0");
+    State& s = st->s;
+    hipStream_t hs = S(stream);
+    HIPCHK(launch_cfl(s.d, s.bc[0], s.diffusivity, s.nblk_cells, hs));
+    HIPCHK(hipMemcpyAsync(s.h_scal, s.d.scal, SC_COUNT_ * sizeof(double), hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipStreamSynchronize(hs));
+    const double m = s.h_scal[SC_DT_INV];
+    if (!std::isfinite(m)) return fail(MIFVM_E_STATE, "no active face: time step unbounded");
+    *dt_out = cfl * m;
+    return MIFVM_OK;
+}
+
+namespace {
+// ghost fill, gradient + limiter, vertex values, face fluxes
+int residual_parts(State& s, hipStream_t hs) {
+    const Dev& d = s.d;
+    KernelTimer& t = s.timer;
+    HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, d.u, s.bc[0], hs); }));
+    HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, hs); }));
+    HIPCHK(timed(t, MIFVM_K_NODE_INTERP, hs, [&] { return launch_node_interp(d, hs); }));
+    HIPCHK(timed(t, MIFVM_K_FACE_FLUX, hs, [&] { return launch_face_flux(d, s.bc[0], s.diffusivity, hs); }));
+    return MIFVM_OK;
+}
+}  // namespace
+
+int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    if (n_steps < 0 || !(dt >= 0) || !std::isfinite(dt)) return fail(MIFVM_E_ARG, "bad n_steps or dt");
+    State& s = st->s;
+    hipStream_t hs = S(stream);
+    static const double alpha[3] = {0.5, 0.5, 1.0};
+    for (int n = 0; n < n_steps; ++n)
+        for (int k = 0; k < 3; ++k) {
+            int rc = residual_parts(s, hs);
+            if (rc) return rc;
+            HIPCHK(timed(s.timer, MIFVM_K_UPDATE, hs, [&] { return launch_update(s.d, alpha[k] * dt, k == 0, hs); }));
+        }
+    if (n_steps > 0)
+        HIPCHK(timed(s.timer, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(s.d, s.d.u, s.bc[0], hs); }));
+    return MIFVM_OK;
+}
+
+int mifvm_residual(mifvm_state* st, double* d_res, double* d_grad, double* d_psi, double* d_unode,
+                   double* d_flux, void* stream) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    State& s = st->s;
+    const Dev& d = s.d;
+    hipStream_t hs = S(stream);
+    int rc = residual_parts(s, hs);
+    if (rc) return rc;
+    if (d_res) {
+        HIPCHK(launch_residual_out(d, d.tmp, hs));
+        HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.tmp, d_res, hs));
+    }
+    if (d_grad) HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 3, d.grad, d_grad, hs));
+    if (d_psi) HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.psi, d_psi, hs));
+    if (d_unode) HIPCHK(launch_to_user(d.vert_perm, d.nv, d.nv, d.nv, 1, d.unode, d_unode, hs));
+    if (d_flux) HIPCHK(hipMemcpyAsync(d_flux, d.flux, d.nf * sizeof(double), hipMemcpyDeviceToDevice, hs));
+    return MIFVM_OK;
+}
+
+int mifvm_conservation(mifvm_state* st, double* total_out, void* stream) {
+    if (!st || !total_out) return fail(MIFVM_E_ARG, "null argument");
+    State& s = st->s;
+    hipStream_t hs = S(stream);
+    HIPCHK(launch_conservation(s.d, s.nblk_cells, hs));
+    HIPCHK(hipMemcpyAsync(s.h_scal, s.d.scal, SC_COUNT_ * sizeof(double), hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipStreamSynchronize(hs));
+    *total_out = s.h_scal[SC_CONS];
+    return MIFVM_OK;
+}
+
+int mifvm_poisson_assemble(mifvm_state* st, void* stream) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    State& s = st->s;
+    hipStream_t hs = S(stream);
+    HIPCHK(timed(s.timer, MIFVM_K_ASSEMBLE, hs, [&] { return launch_assemble(s.d, s.bc[1], s.mesh->row_max, hs); }));
+    s.assembled = true;
+    return MIFVM_OK;
+}
+
+int mifvm_poisson_apply(mifvm_state* st, const double* d_x, double* d_y, void* stream) {
+    if (!st || !d_x || !d_y) return fail(MIFVM_E_ARG, "null argument");
+    State& s = st->s;
+    if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
+    const Dev& d = s.d;
+    hipStream_t hs = S(stream);
+    HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_x, d.tmp, hs));
+    HIPCHK(launch_spmv_plain(d, d.tmp, d.tmp + d.nc, hs));
+    HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.tmp + d.nc, d_y, hs));
+    return MIFVM_OK;
+}
+
+namespace {
+int rhs_internal(State& s, const double* d_f, hipStream_t hs) {
+    const Dev& d = s.d;
+    if (d_f) HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_f, d.tmp, hs));
+    const double* f = d_f ? d.tmp : d.u;
+    HIPCHK(timed(s.timer, MIFVM_K_RHS, hs, [&] { return launch_rhs(d, f, hs); }));
+    return MIFVM_OK;
+}
+}  // namespace
+
+int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* stream) {
+    if (!st || !d_b) return fail(MIFVM_E_ARG, "null argument");
+    State& s = st->s;
+    if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
+    hipStream_t hs = S(stream);
+    int rc = rhs_internal(s, d_f, hs);
+    if (rc) return rc;
+    HIPCHK(launch_to_user(s.d.cell_perm, s.d.nc, s.d.nc, s.d.nc, 1, s.d.b, d_b, hs));
+    return MIFVM_OK;
+}
+
+int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_opts* opts,
+                        mifvm_solve_info* info, void* stream) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    State& s = st->s;
+    if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
+    const double tol = opts ? opts->tol : 1e-10;
+    const int maxit = opts ? opts->maxit : 20000;
+    const int chunk = opts && opts->chunk > 0 ? opts->chunk : 32;
+    if (!(tol > 0) || maxit < 0) return fail(MIFVM_E_ARG, "bad tol or maxit");
+    const Dev& d = s.d;
+    hipStream_t hs = S(stream);
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = rhs_internal(s, d_f, hs);
+    if (rc) return rc;
+    KernelTimer& tm = s.timer;
+    auto pull = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(s.h_scal, d.scal, SC_COUNT_ * sizeof(double), hipMemcpyDeviceToHost, hs));
+        HIPCHK(hipStreamSynchronize(hs));
+        HIPCHK(timer_flush(tm));
+        return MIFVM_OK;
+    };
+    HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, 0, tol, maxit, hs); }));
+    if ((rc = pull())) return rc;
+    int restarts = 0;
+    if (s.h_scal[SC_BB] == 0.0) {       // b = 0: the solution is 0
+        HIPCHK(hipMemsetAsync(d.x, 0, d.nc * sizeof(double), hs));
+        HIPCHK(hipStreamSynchronize(hs));
+    } else {
+        for (;;) {
+            while (s.h_scal[SC_DONE] == 0.0) {
+                for (int c = 0; c < chunk; ++c) {
+                    HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
+                    HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
+                    HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
+                }
+                if ((rc = pull())) return rc;
+            }
+            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_true_residual(d, 0, hs); }));  // r = b - K x
+            if ((rc = pull())) return rc;
+            if (s.h_scal[SC_DONE] != 0.0) break;      // converged on the true residual, or maxit
+            ++restarts;
+        }
+    }
+    const double bb = s.h_scal[SC_BB];
+    const double rel = bb > 0 ? std::sqrt(s.h_scal[SC_TRUE_RR] / bb) : 0.0;
+    const int iters = int(s.h_scal[SC_IT]);
+    if (info) {
+        info->iterations = iters;
+        info->restarts = restarts;
+        info->rel_residual = rel;
+        info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!(rel <= tol)) return MIFVM_NOT_CONVERGED;
+    return MIFVM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,462 @@
+// Host preprocessing of an unstructured tetrahedral mesh for the
+// cell-centred finite-volume kernels (the "readmesh + Domain" stage of the
+// paper's annex, redesigned for one GPU holding the whole mesh).
+//
+// Geometry follows Sec. 2.1: data at cell centres of gravity, fluxes on
+// faces with normal n_ij |sigma_ij|, ghost cells behind boundary faces, the
+// node-neighbour stencil of Algorithm 1, the least-squares vertex weights of
+// Algorithm 2, and the diamond cell of eq. (diamond) with a triangular base.
+// Where the paper is silent this code takes the same readings as the rest
+// of the library: ghost centre = owner centre mirrored across the face
+// plane; an interior face's L cell is the owner with the smaller user index;
+// vertex weights are the unweighted least-squares linear fit evaluated at
+// the vertex; the gradient solves the 3x3 normal equations.
+#include "mesh.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <numeric>
+
+namespace mifvm {
+namespace {
+
+struct V3 {
+    double x, y, z;
+};
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 scale(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+inline V3 cross(V3 a, V3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+uint64_t spread21(uint64_t v) {
+    v &= 0x1fffffULL;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+struct FaceRec {
+    int32_t a, b, c;   // sorted user vertex ids
+    int32_t owner;     // user cell id
+};
+
+// Solve the 4x4 system A w = rhs by Gaussian elimination with partial
+// pivoting; returns false when singular.
+bool solve4(double A[4][4], double rhs[4], double w[4]) {
+    for (int col = 0; col < 4; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 4; ++r)
+            if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+        if (A[piv][col] == 0.0) return false;
+        if (piv != col) {
+            for (int k = 0; k < 4; ++k) std::swap(A[col][k], A[piv][k]);
+            std::swap(rhs[col], rhs[piv]);
+        }
+        for (int r = col + 1; r < 4; ++r) {
+            double m = A[r][col] / A[col][col];
+            for (int k = col; k < 4; ++k) A[r][k] -= m * A[col][k];
+            rhs[r] -= m * rhs[col];
+        }
+    }
+    for (int r = 3; r >= 0; --r) {
+        double s = rhs[r];
+        for (int k = r + 1; k < 4; ++k) s -= A[r][k] * w[k];
+        w[r] = s / A[r][r];
+    }
+    return true;
+}
+
+template <class PadIdx>
+void pack_sell(const std::vector<int64_t>& ptr, const std::vector<int32_t>& idx,
+               const std::vector<double>* val, const std::vector<int32_t>* len_override,
+               int64_t nrows, PadIdx pad_idx, Sell64& out) {
+    out.nslices = (nrows + 63) / 64;
+    out.off.assign(out.nslices + 1, 0);
+    out.width.assign(out.nslices, 0);
+    auto rowlen = [&](int64_t r) -> int64_t {
+        return len_override ? (*len_override)[r] : ptr[r + 1] - ptr[r];
+    };
+    for (int64_t s = 0; s < out.nslices; ++s) {
+        int64_t w = 0;
+        for (int64_t r = s * 64; r < std::min(nrows, s * 64 + 64); ++r) w = std::max(w, rowlen(r));
+        out.width[s] = (int32_t)w;
+        out.off[s + 1] = out.off[s] + w * 64;
+    }
+    out.idx.assign(out.off[out.nslices], 0);
+    if (val) out.val.assign(out.off[out.nslices], 0.0);
+    for (int64_t s = 0; s < out.nslices; ++s) {
+        for (int lane = 0; lane < 64; ++lane) {
+            int64_t r = s * 64 + lane;
+            int64_t L = r < nrows ? rowlen(r) : 0;
+            int32_t pad = r < nrows ? pad_idx(r) : 0;
+            for (int64_t k = 0; k < out.width[s]; ++k) {
+                int64_t at = out.off[s] + k * 64 + lane;
+                if (k < L) {
+                    out.idx[at] = idx[ptr[r] + k];
+                    if (val) out.val[at] = (*val)[ptr[r] + k];
+                } else {
+                    out.idx[at] = pad;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
+               const int32_t* btris, const int32_t* btags, int64_t nb_in,
+               int renumber, Mesh& M, std::string& err) {
+    const int E_ARG = -1, E_MESH = -2;
+    if (!xyz || !tets || nv <= 0 || nc <= 0 || nb_in < 0 || (nb_in > 0 && (!btris || !btags))) {
+        err = "null pointer or non-positive size";
+        return E_ARG;
+    }
+    if (nc > (int64_t(1) << 30) || nv > (int64_t(1) << 30)) {
+        err = "mesh too large for 32-bit indices";
+        return E_ARG;
+    }
+    for (int64_t i = 0; i < 4 * nc; ++i)
+        if (tets[i] < 0 || tets[i] >= nv) { err = "tet vertex index out of range"; return E_ARG; }
+    for (int64_t i = 0; i < 3 * nb_in; ++i)
+        if (btris[i] < 0 || btris[i] >= nv) { err = "boundary vertex index out of range"; return E_ARG; }
+    for (int64_t i = 0; i < nb_in; ++i)
+        if (btags[i] < 0 || btags[i] >= 32) { err = "boundary tag out of [0, 32)"; return E_ARG; }
+
+    auto P = [&](int64_t v) { return V3{xyz[3 * v], xyz[3 * v + 1], xyz[3 * v + 2]}; };
+
+    // -- 1. orientation, volume, centre of gravity (user order) --------------
+    std::vector<std::array<int32_t, 4>> T(nc);
+    std::vector<double> vol_u(nc);
+    std::vector<V3> cen_u(nc);
+    double vsum = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+        std::array<int32_t, 4> t = {tets[4 * c], tets[4 * c + 1], tets[4 * c + 2], tets[4 * c + 3]};
+        V3 p0 = P(t[0]), p1 = P(t[1]), p2 = P(t[2]), p3 = P(t[3]);
+        double det = dot(sub(p1, p0), cross(sub(p2, p0), sub(p3, p0)));
+        if (det < 0) std::swap(t[2], t[3]);
+        T[c] = t;
+        vol_u[c] = std::fabs(det) / 6.0;
+        vsum += vol_u[c];
+        V3 q0 = P(t[0]), q1 = P(t[1]), q2 = P(t[2]), q3 = P(t[3]);
+        cen_u[c] = scale(add(add(add(q0, q1), q2), q3), 0.25);
+    }
+    double vmean = vsum / double(nc);
+    for (int64_t c = 0; c < nc; ++c)
+        if (!(vol_u[c] > 1e-14 * vmean)) { err = "degenerate tetrahedron"; return E_MESH; }
+
+    // -- 2. cell renumbering --------------------------------------------------
+    std::vector<int32_t> new2old(nc), old2new(nc);
+    std::iota(new2old.begin(), new2old.end(), 0);
+    if (renumber == 1) {
+        V3 lo = cen_u[0], hi = cen_u[0];
+        for (auto& p : cen_u) {
+            lo = {std::min(lo.x, p.x), std::min(lo.y, p.y), std::min(lo.z, p.z)};
+            hi = {std::max(hi.x, p.x), std::max(hi.y, p.y), std::max(hi.z, p.z)};
+        }
+        double ext = std::max({hi.x - lo.x, hi.y - lo.y, hi.z - lo.z, 1e-300});
+        double q = double((1 << 21) - 1) / ext;
+        std::vector<uint64_t> key(nc);
+        for (int64_t c = 0; c < nc; ++c) {
+            auto cx = uint64_t((cen_u[c].x - lo.x) * q), cy = uint64_t((cen_u[c].y - lo.y) * q),
+                 cz = uint64_t((cen_u[c].z - lo.z) * q);
+            key[c] = spread21(cx) | (spread21(cy) << 1) | (spread21(cz) << 2);
+        }
+        std::stable_sort(new2old.begin(), new2old.end(),
+                         [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    } else if (renumber != 0) {
+        err = "unknown renumbering";
+        return E_ARG;
+    }
+    for (int64_t i = 0; i < nc; ++i) old2new[new2old[i]] = (int32_t)i;
+
+    // -- 3. faces: sorted vertex triples, grouped (counting sort on a) -------
+    static const int opp[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    std::vector<FaceRec> rec(4 * nc);
+    std::vector<int64_t> bucket(nv + 1, 0);
+    {
+        std::vector<FaceRec> tmp(4 * nc);
+        for (int64_t c = 0; c < nc; ++c)
+            for (int k = 0; k < 4; ++k) {
+                int32_t v[3] = {T[c][opp[k][0]], T[c][opp[k][1]], T[c][opp[k][2]]};
+                std::sort(v, v + 3);
+                tmp[4 * c + k] = {v[0], v[1], v[2], (int32_t)c};
+                bucket[v[0] + 1]++;
+            }
+        for (int64_t v = 0; v < nv; ++v) bucket[v + 1] += bucket[v];
+        std::vector<int64_t> pos(bucket.begin(), bucket.end() - 1);
+        for (auto& r : tmp) rec[pos[r.a]++] = r;
+        for (int64_t v = 0; v < nv; ++v)
+            std::sort(rec.begin() + bucket[v], rec.begin() + bucket[v + 1],
+                      [](const FaceRec& x, const FaceRec& y) {
+                          if (x.b != y.b) return x.b < y.b;
+                          if (x.c != y.c) return x.c < y.c;
+                          return x.owner < y.owner;
+                      });
+    }
+    struct UFace {
+        int32_t a, b, c;
+        int32_t L, R;   // user cells; R = -1 on the boundary
+        int32_t tag;
+    };
+    std::vector<UFace> uf;
+    uf.reserve(2 * nc + nb_in);
+    for (size_t i = 0; i < rec.size();) {
+        size_t j = i + 1;
+        while (j < rec.size() && rec[j].a == rec[i].a && rec[j].b == rec[i].b && rec[j].c == rec[i].c) ++j;
+        if (j - i > 2) { err = "face shared by more than two cells"; return E_MESH; }
+        uf.push_back({rec[i].a, rec[i].b, rec[i].c, rec[i].owner, j - i == 2 ? rec[i + 1].owner : -1, -1});
+        i = j;
+    }
+    rec.clear();
+    rec.shrink_to_fit();
+
+    // -- 4. boundary tags ------------------------------------------------------
+    auto less3 = [](const UFace& x, int32_t a, int32_t b, int32_t c) {
+        if (x.a != a) return x.a < a;
+        if (x.b != b) return x.b < b;
+        return x.c < c;
+    };
+    for (int64_t i = 0; i < nb_in; ++i) {
+        int32_t v[3] = {btris[3 * i], btris[3 * i + 1], btris[3 * i + 2]};
+        std::sort(v, v + 3);
+        auto it = std::lower_bound(uf.begin(), uf.end(), 0,
+                                   [&](const UFace& x, int) { return less3(x, v[0], v[1], v[2]); });
+        if (it == uf.end() || it->a != v[0] || it->b != v[1] || it->c != v[2] || it->R >= 0) {
+            err = "tagged triangle is not a boundary face";
+            return E_MESH;
+        }
+        if (it->tag >= 0) { err = "boundary face tagged twice"; return E_MESH; }
+        it->tag = btags[i];
+    }
+    int64_t nb = 0, nfi = 0;
+    for (auto& f : uf) {
+        if (f.R < 0) {
+            if (f.tag < 0) { err = "untagged boundary face"; return E_MESH; }
+            ++nb;
+        } else {
+            ++nfi;
+        }
+    }
+    const int64_t nf = nfi + nb;
+
+    // -- 5. face orientation: S = 1/2 (B-A)x(C-A) points from L outwards ----
+    for (auto& f : uf) {
+        V3 A = P(f.a), B = P(f.b), C = P(f.c);
+        V3 S = scale(cross(sub(B, A), sub(C, A)), 0.5);
+        V3 xf = scale(add(add(A, B), C), 1.0 / 3.0);
+        if (dot(S, sub(xf, cen_u[f.L])) < 0) std::swap(f.b, f.c);
+    }
+
+    // -- 6. internal face order ------------------------------------------------
+    std::vector<int64_t> ford(uf.size());
+    std::iota(ford.begin(), ford.end(), 0);
+    auto fkey = [&](int64_t i) {
+        const UFace& f = uf[i];
+        int64_t l = old2new[f.L];
+        if (f.R < 0) return std::array<int64_t, 3>{1, l, i};
+        int64_t r = old2new[f.R];
+        return std::array<int64_t, 3>{0, std::min(l, r) * (nc + 1) + std::max(l, r), i};
+    };
+    std::sort(ford.begin(), ford.end(), [&](int64_t x, int64_t y) { return fkey(x) < fkey(y); });
+
+    // -- 7. vertex renumbering: by the first internal cell touching it ---------
+    std::vector<int64_t> vmin(nv, INT64_MAX);
+    for (int64_t c = 0; c < nc; ++c)
+        for (int k = 0; k < 4; ++k) vmin[T[c][k]] = std::min<int64_t>(vmin[T[c][k]], old2new[c]);
+    for (int64_t v = 0; v < nv; ++v)
+        if (vmin[v] == INT64_MAX) { err = "vertex not used by any cell"; return E_MESH; }
+    std::vector<int32_t> vnew2old(nv), vold2new(nv);
+    std::iota(vnew2old.begin(), vnew2old.end(), 0);
+    std::stable_sort(vnew2old.begin(), vnew2old.end(), [&](int32_t a, int32_t b) { return vmin[a] < vmin[b]; });
+    for (int64_t v = 0; v < nv; ++v) vold2new[vnew2old[v]] = (int32_t)v;
+
+    // -- 8. fill internal arrays ------------------------------------------------
+    M = Mesh();
+    M.nc = nc; M.nv = nv; M.nf = nf; M.nfi = nfi; M.nb = nb;
+    M.cell_perm = new2old;
+    M.vert_perm = vnew2old;
+    M.vol.resize(nc);
+    M.xc.assign(3 * (nc + nb), 0.0);
+    const int64_t NX = nc + nb;
+    for (int64_t i = 0; i < nc; ++i) {
+        int32_t o = new2old[i];
+        M.vol[i] = vol_u[o];
+        M.xc[i] = cen_u[o].x; M.xc[NX + i] = cen_u[o].y; M.xc[2 * NX + i] = cen_u[o].z;
+    }
+    M.fL.resize(nf); M.fR.resize(nf); M.fA.resize(nf); M.fB.resize(nf); M.fC.resize(nf);
+    M.kAC.resize(nf); M.kBC.resize(nf); M.kRL.resize(nf); M.area.resize(nf);
+    M.fx.resize(3 * nf); M.S.resize(3 * nf);
+    M.gowner.resize(nb); M.gtag.resize(nb); M.gdist.resize(nb);
+    for (int64_t f = 0; f < nf; ++f) {
+        const UFace& u = uf[ford[f]];
+        V3 A = P(u.a), B = P(u.b), C = P(u.c);
+        V3 S = scale(cross(sub(B, A), sub(C, A)), 0.5);
+        V3 xf = scale(add(add(A, B), C), 1.0 / 3.0);
+        int32_t L = old2new[u.L];
+        V3 xL = cen_u[u.L];
+        V3 xR;
+        int32_t R;
+        if (u.R >= 0) {
+            R = old2new[u.R];
+            xR = cen_u[u.R];
+        } else {
+            int64_t g = f - nfi;
+            R = (int32_t)(nc + g);
+            double a = std::sqrt(dot(S, S));
+            V3 nh = scale(S, 1.0 / a);
+            xR = add(xL, scale(nh, 2.0 * dot(sub(xf, xL), nh)));
+            M.gowner[g] = L;
+            M.gtag[g] = u.tag;
+            V3 d = sub(xR, xL);
+            M.gdist[g] = std::sqrt(dot(d, d));
+            M.xc[nc + g] = xR.x; M.xc[NX + nc + g] = xR.y; M.xc[2 * NX + nc + g] = xR.z;
+        }
+        // diamond (eq. (diamond) with D = C): dual basis of {A-C, B-C, R-L}
+        V3 cvec = sub(xR, xL);
+        double muD = dot(S, cvec) / 3.0;
+        if (!(muD > 0)) { err = "non-positive diamond volume"; return E_MESH; }
+        V3 N1 = scale(cross(sub(B, C), cvec), 0.5);
+        V3 N2 = scale(cross(cvec, sub(A, C)), 0.5);
+        M.kAC[f] = dot(N1, S) / (3.0 * muD);
+        M.kBC[f] = dot(N2, S) / (3.0 * muD);
+        M.kRL[f] = dot(S, S) / (3.0 * muD);
+        M.fL[f] = L; M.fR[f] = R;
+        M.fA[f] = vold2new[u.a]; M.fB[f] = vold2new[u.b]; M.fC[f] = vold2new[u.c];
+        M.fx[f] = xf.x; M.fx[nf + f] = xf.y; M.fx[2 * nf + f] = xf.z;
+        M.S[f] = S.x; M.S[nf + f] = S.y; M.S[2 * nf + f] = S.z;
+        M.area[f] = std::sqrt(dot(S, S));
+    }
+    uf.clear();
+    uf.shrink_to_fit();
+
+    // -- 9. cell -> faces ---------------------------------------------------------
+    M.c2f.assign(4 * nc, -1);
+    M.c2n.assign(4 * nc, -1);
+    std::vector<int8_t> cnt(nc, 0);
+    auto put = [&](int32_t cell, int32_t code, int32_t nbr) -> bool {
+        if (cnt[cell] >= 4) return false;
+        M.c2f[cnt[cell] * nc + cell] = code;
+        M.c2n[cnt[cell] * nc + cell] = nbr;
+        cnt[cell]++;
+        return true;
+    };
+    for (int64_t f = 0; f < nf; ++f) {
+        if (!put(M.fL[f], (int32_t)f, M.fR[f])) { err = "cell with more than 4 faces"; return E_MESH; }
+        if (f < nfi && !put(M.fR[f], ~(int32_t)f, M.fL[f])) { err = "cell with more than 4 faces"; return E_MESH; }
+    }
+    for (int64_t c = 0; c < nc; ++c)
+        if (cnt[c] != 4) { err = "cell without 4 faces"; return E_MESH; }
+
+    // -- 10. vertex -> cells and ghosts ------------------------------------------
+    {
+        std::vector<int64_t> deg(nv + 1, 0);
+        for (int64_t c = 0; c < nc; ++c)
+            for (int k = 0; k < 4; ++k) deg[vold2new[T[c][k]] + 1]++;
+        for (int64_t g = 0; g < nb; ++g) {
+            int64_t f = nfi + g;
+            deg[M.fA[f] + 1]++; deg[M.fB[f] + 1]++; deg[M.fC[f] + 1]++;
+        }
+        for (int64_t v = 0; v < nv; ++v) deg[v + 1] += deg[v];
+        M.nptr = deg;
+        M.nidx.assign(M.nptr[nv], 0);
+        std::vector<int64_t> pos(M.nptr.begin(), M.nptr.end() - 1);
+        for (int64_t i = 0; i < nc; ++i) {   // internal order -> ascending per vertex
+            const auto& t = T[new2old[i]];
+            for (int k = 0; k < 4; ++k) M.nidx[pos[vold2new[t[k]]]++] = (int32_t)i;
+        }
+        for (int64_t g = 0; g < nb; ++g) {
+            int64_t f = nfi + g;
+            for (int32_t v : {M.fA[f], M.fB[f], M.fC[f]}) M.nidx[pos[v]++] = (int32_t)(nc + g);
+        }
+    }
+    M.node_max = 0;
+    for (int64_t v = 0; v < nv; ++v) M.node_max = std::max<int32_t>(M.node_max, int32_t(M.nptr[v + 1] - M.nptr[v]));
+
+    // -- 11. least-squares vertex weights (Algorithm 2) -------------------------
+    M.nalpha.assign(M.nidx.size(), 0.0);
+    for (int64_t v = 0; v < nv; ++v) {
+        V3 xv = P(vnew2old[v]);
+        double A[4][4] = {{0}};
+        for (int64_t e = M.nptr[v]; e < M.nptr[v + 1]; ++e) {
+            int32_t id = M.nidx[e];
+            double r[4] = {1.0, M.xc[id] - xv.x, M.xc[NX + id] - xv.y, M.xc[2 * NX + id] - xv.z};
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) A[i][j] += r[i] * r[j];
+        }
+        double rhs[4] = {1, 0, 0, 0}, w[4];
+        if (!solve4(A, rhs, w)) { err = "singular vertex least-squares system"; return E_MESH; }
+        for (int64_t e = M.nptr[v]; e < M.nptr[v + 1]; ++e) {
+            int32_t id = M.nidx[e];
+            M.nalpha[e] = w[0] + w[1] * (M.xc[id] - xv.x) + w[2] * (M.xc[NX + id] - xv.y) +
+                          w[3] * (M.xc[2 * NX + id] - xv.z);
+        }
+    }
+
+    // -- 12. node-neighbour stencil (Algorithm 1): merge of 4 sorted lists ----
+    M.sptr.assign(nc + 1, 0);
+    M.sidx.clear();
+    M.sidx.reserve(size_t(nc) * 72);
+    M.minv.assign(6 * nc, 0.0);
+    M.klen.assign(nc, 0);
+    M.stencil_max = 0;
+    M.row_max = 0;
+    for (int64_t i = 0; i < nc; ++i) {
+        const auto& t = T[new2old[i]];
+        int64_t h[4], e[4];
+        for (int k = 0; k < 4; ++k) {
+            int32_t v = vold2new[t[k]];
+            h[k] = M.nptr[v];
+            e[k] = M.nptr[v + 1];
+        }
+        int64_t last = -1;
+        double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
+        int32_t klen = 0;
+        for (;;) {
+            int64_t best = INT64_MAX;
+            for (int k = 0; k < 4; ++k)
+                if (h[k] < e[k]) best = std::min<int64_t>(best, M.nidx[h[k]]);
+            if (best == INT64_MAX) break;
+            for (int k = 0; k < 4; ++k)
+                if (h[k] < e[k] && M.nidx[h[k]] == best) ++h[k];
+            if (best == last || best == i) continue;
+            last = best;
+            M.sidx.push_back((int32_t)best);
+            if (best < nc) ++klen;
+            double dx = M.xc[best] - M.xc[i], dy = M.xc[NX + best] - M.xc[NX + i],
+                   dz = M.xc[2 * NX + best] - M.xc[2 * NX + i];
+            m00 += dx * dx; m01 += dx * dy; m02 += dx * dz;
+            m11 += dy * dy; m12 += dy * dz; m22 += dz * dz;
+        }
+        M.sptr[i + 1] = (int64_t)M.sidx.size();
+        M.klen[i] = klen;
+        M.stencil_max = std::max<int32_t>(M.stencil_max, int32_t(M.sptr[i + 1] - M.sptr[i]));
+        M.row_max = std::max(M.row_max, klen);
+        // inverse of the symmetric normal matrix by cofactors
+        double c00 = m11 * m22 - m12 * m12, c01 = m02 * m12 - m01 * m22, c02 = m01 * m12 - m02 * m11;
+        double c11 = m00 * m22 - m02 * m02, c12 = m01 * m02 - m00 * m12, c22 = m00 * m11 - m01 * m01;
+        double det = m00 * c00 + m01 * c01 + m02 * c02;
+        if (!(det > 0)) { err = "singular gradient normal matrix"; return E_MESH; }
+        double id = 1.0 / det;
+        M.minv[0 * nc + i] = c00 * id; M.minv[1 * nc + i] = c01 * id; M.minv[2 * nc + i] = c02 * id;
+        M.minv[3 * nc + i] = c11 * id; M.minv[4 * nc + i] = c12 * id; M.minv[5 * nc + i] = c22 * id;
+    }
+    M.matrix_nnz = 0;
+    for (int64_t i = 0; i < nc; ++i) M.matrix_nnz += M.klen[i] + 1;
+
+    // -- 13. 64-row slicing ------------------------------------------------------
+    pack_sell(M.sptr, M.sidx, nullptr, nullptr, nc, [](int64_t r) { return (int32_t)r; }, M.stencil);
+    pack_sell(M.nptr, M.nidx, &M.nalpha, nullptr, nv,
+              [&](int64_t r) { return M.nidx[M.nptr[r]]; }, M.node);
+    pack_sell(M.sptr, M.sidx, nullptr, &M.klen, nc, [](int64_t r) { return (int32_t)r; }, M.kmat);
+    return 0;
+}
+
+}  // namespace mifvm

@@ -1,0 +1,56 @@
+// Host-side preprocessed mesh: every array the device kernels read, in the
+// library's internal numbering (cells on a Morton curve of their centres).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mifvm {
+
+// Rows packed in slices of 64 (one wavefront): slice s stores entry k of row
+// 64*s + lane at off[s] + k*64 + lane, for k < width[s].  Short rows are
+// padded with entries that contribute exactly zero (documented per use).
+struct Sell64 {
+    int64_t nslices = 0;
+    std::vector<int64_t> off;      // nslices + 1
+    std::vector<int32_t> width;    // nslices
+    std::vector<int32_t> idx;      // off[nslices]
+    std::vector<double> val;       // off[nslices] (empty when unused)
+};
+
+struct Mesh {
+    int64_t nc = 0, nv = 0, nf = 0, nfi = 0, nb = 0;
+    std::vector<int32_t> cell_perm;   // internal cell -> user cell
+    std::vector<int32_t> vert_perm;   // internal vertex -> user vertex
+    std::vector<double> vol;          // nc
+    std::vector<double> xc;           // 3 x (nc+nb), SoA
+    std::vector<double> minv;         // 6 x nc: xx xy xz yy yz zz
+    // faces: interior [0,nfi), boundary [nfi,nf); boundary face nfi+g <-> ghost g
+    std::vector<int32_t> fL, fR;      // R = nc+g on the boundary
+    std::vector<int32_t> fA, fB, fC;  // internal vertex ids
+    std::vector<double> kAC, kBC, kRL;
+    std::vector<double> fx;           // 3 x nf face centroid
+    std::vector<double> S;            // 3 x nf face vector
+    std::vector<double> area;         // nf
+    // ghosts
+    std::vector<int32_t> gowner, gtag;
+    std::vector<double> gdist;
+    // cell -> faces (f if the cell is L, ~f if R) and cell across each face
+    std::vector<int32_t> c2f, c2n;    // 4 x nc
+    // CSR forms (for export/tests) and packed forms (for the device)
+    std::vector<int64_t> sptr; std::vector<int32_t> sidx;
+    std::vector<int64_t> nptr; std::vector<int32_t> nidx; std::vector<double> nalpha;
+    int32_t stencil_max = 0, node_max = 0, row_max = 0;
+    int64_t matrix_nnz = 0;
+    Sell64 stencil;                   // node-neighbour stencil, pad = the row itself
+    Sell64 node;                      // vertex lists + weights, pad = first entry, weight 0
+    Sell64 kmat;                      // Poisson off-diagonal pattern, pad = the row itself
+    std::vector<int32_t> klen;        // off-diagonal entries per row (sorted prefix)
+};
+
+// Returns 0 or a negative mifvm status; err receives a message.
+int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
+               const int32_t* btris, const int32_t* btags, int64_t nb,
+               int renumber, Mesh& out, std::string& err);
+
+}  // namespace mifvm

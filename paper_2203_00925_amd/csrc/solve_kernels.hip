@@ -1,0 +1,269 @@
+// Poisson system of the discretisation (Sec. 2.2, eqs. (7), (laplace)):
+// on-device assembly into 64-row slices, the sparse product, and the
+// Jacobi-preconditioned conjugate-gradient iteration with every scalar kept
+// in device memory (alpha, beta and the convergence test are computed by the
+// last block of the kernel that produces their partial sums; later kernels
+// of an enqueued chunk return at once when the solve has finished).
+#include "reduce.h"
+#include "state.h"
+
+namespace mifvm {
+
+__device__ inline int64_t gtid_s() { return int64_t(blockIdx.x) * blockDim.x + threadIdx.x; }
+inline int grid_rows(int64_t n) { return int((n + kBlock - 1) / kBlock); }
+
+// Row i of K = -(sum_f s_if dF_f/dP), c_i = sum_f s_if (constant part of F_f),
+// where F_f = kAC (P_A - P_C) + kBC (P_B - P_C) + kRL (P_R - P_L) on interior
+// and Dirichlet faces, P_v = sum alpha_{v,e} P_e over the vertex list, and a
+// ghost value is s_g P_owner + t_g.  Neumann / zero-flux faces carry a fixed
+// flux that only enters c.  One thread per row, 64-thread blocks, the row's
+// accumulators in LDS ([entry][lane] so lanes hit distinct banks); each row
+// is summed by one thread in a fixed order (deterministic, no atomics).
+__global__ __launch_bounds__(64) void k_assemble(Dev d, BcTable bc) {
+    extern __shared__ double acc[];                       // [row_max][64]
+    const int lane = threadIdx.x;
+    const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+    const int64_t nc = d.nc;
+    if (i >= nc) return;
+    const int64_t s = i >> 6;
+    const int32_t* __restrict__ cols = d.k_col + d.k_off[s] + (i & 63);
+    const int len = d.k_len[i];
+    const int w = d.k_w[s];
+    for (int k = 0; k < len; ++k) acc[k * 64 + lane] = 0.0;
+    double diag = 0.0, cconst = 0.0;
+
+    auto add = [&](int e, double coef) {
+        if (e >= nc) {                                   // ghost -> owner
+            const int g = e - int(nc);
+            const int t = d.gtag[g];
+            const int kind = bc.kind[t];
+            const double val = bc.value[t];
+            const double sg = kind == kDirichlet ? -1.0 : 1.0;
+            const double tg = kind == kDirichlet ? 2.0 * val : (kind == kNeumann ? val * d.gdist[g] : 0.0);
+            cconst += tg * coef;
+            coef = sg * coef;
+            e = d.gowner[g];
+        }
+        if (e == i) {
+            diag += coef;
+            return;
+        }
+        int lo = 0, hi = len - 1;                        // sorted prefix of the row
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cols[int64_t(mid) * 64] < e) lo = mid + 1;
+            else hi = mid;
+        }
+        acc[lo * 64 + lane] += coef;
+    };
+
+    for (int k = 0; k < 4; ++k) {
+        const int code = d.c2f[k * nc + i];
+        const double sgn = code >= 0 ? 1.0 : -1.0;
+        const int f = code >= 0 ? code : ~code;
+        if (f >= d.nfi) {
+            const int t = d.gtag[f - d.nfi];
+            const int kind = bc.kind[t];
+            if (kind != kDirichlet) {
+                if (kind == kNeumann) cconst += sgn * (bc.value[t] * d.area[f]);
+                continue;
+            }
+        }
+        const double kac = d.kAC[f], kbc = d.kBC[f], krl = d.kRL[f];
+        const int verts[3] = {d.fA[f], d.fB[f], d.fC[f]};
+        const double wts[3] = {kac, kbc, -(kac + kbc)};
+        for (int a = 0; a < 3; ++a) {
+            const int v = verts[a];
+            const int64_t vs = v >> 6;
+            const int64_t base = d.n_off[vs] + (v & 63);
+            const int vw = d.n_w[vs];
+            const double wv = sgn * wts[a];
+            for (int kk = 0; kk < vw; ++kk) {
+                const int64_t at = base + int64_t(kk) * 64;
+                const double al = d.n_alpha[at];
+                if (al != 0.0) add(d.n_idx[at], wv * al);
+            }
+        }
+        add(d.fR[f], sgn * krl);
+        add(d.fL[f], -sgn * krl);
+    }
+    double* __restrict__ vals = d.k_val + d.k_off[s] + (i & 63);
+    for (int k = 0; k < w; ++k) vals[int64_t(k) * 64] = k < len ? -acc[k * 64 + lane] : 0.0;
+    d.k_diag[i] = -diag;
+    d.k_dinv[i] = 1.0 / (-diag);
+    d.k_c[i] = cconst;
+}
+
+__device__ inline double spmv_row(const Dev& d, const double* __restrict__ x, int64_t i) {
+    const int64_t s = i >> 6;
+    const int64_t base = d.k_off[s] + (i & 63);
+    const int w = d.k_w[s];
+    double y = d.k_diag[i] * x[i];
+    for (int k = 0; k < w; ++k) {
+        const int64_t at = base + int64_t(k) * 64;
+        y += d.k_val[at] * x[d.k_col[at]];
+    }
+    return y;
+}
+
+__global__ __launch_bounds__(kBlock) void k_spmv(Dev d, const double* __restrict__ x, double* y) {
+    const int64_t i = gtid_s();
+    if (i >= d.nc) return;
+    y[i] = spmv_row(d, x, i);
+}
+
+// b = -mu f + c
+__global__ __launch_bounds__(kBlock) void k_rhs(Dev d, const double* __restrict__ f) {
+    const int64_t i = gtid_s();
+    if (i >= d.nc) return;
+    d.b[i] = -d.vol[i] * f[i] + d.k_c[i];
+}
+
+// r = b - K x; z = D^-1 r; p = z; rz, rr, bb.  Opens (or reopens) the loop.
+__global__ __launch_bounds__(kBlock) void k_cg_setup(Dev d, double tol, int maxit, int reset_it) {
+    __shared__ double lds[4];
+    const int64_t i = gtid_s();
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    if (i < d.nc) {
+        const double bi = d.b[i];
+        const double ri = bi - spmv_row(d, d.x, i);
+        const double zi = d.k_dinv[i] * ri;
+        d.r[i] = ri;
+        d.z[i] = zi;
+        d.p[i] = zi;
+        rz = ri * zi;
+        rr = ri * ri;
+        bb = bi * bi;
+    }
+    const double v[3] = {block_sum256(rz, lds), block_sum256(rr, lds), block_sum256(bb, lds)};
+    if (publish_partials<3>(v, d.partial, d.counter)) {
+        const double trz = sum_partials(d.partial, 0, lds);
+        const double trr = sum_partials(d.partial, 1, lds);
+        const double tbb = sum_partials(d.partial, 2, lds);
+        if (threadIdx.x == 0) {
+            double* sc = d.scal;
+            sc[SC_RZ] = trz;
+            sc[SC_RR] = trr;
+            sc[SC_TRUE_RR] = trr;
+            sc[SC_BB] = tbb;
+            if (reset_it) {           // fresh solve; a reopen keeps tol, maxit, count
+                sc[SC_TOL2BB] = tol * tol * tbb;
+                sc[SC_MAXIT] = double(maxit);
+                sc[SC_IT] = 0.0;
+            }
+            sc[SC_DONE] = trr <= sc[SC_TOL2BB] ? 1.0 : (sc[SC_IT] >= sc[SC_MAXIT] ? 2.0 : 0.0);
+            *d.counter = 0u;
+        }
+    }
+}
+
+// q = K p; alpha = rz / (p . q)
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(Dev d) {
+    __shared__ double lds[4];
+    if (d.scal[SC_DONE] != 0.0) return;
+    const int64_t i = gtid_s();
+    double pq = 0.0;
+    if (i < d.nc) {
+        const double qi = spmv_row(d, d.p, i);
+        d.q[i] = qi;
+        pq = d.p[i] * qi;
+    }
+    const double v[1] = {block_sum256(pq, lds)};
+    if (publish_partials<1>(v, d.partial, d.counter)) {
+        const double t = sum_partials(d.partial, 0, lds);
+        if (threadIdx.x == 0) {
+            d.scal[SC_PQ] = t;
+            d.scal[SC_ALPHA] = d.scal[SC_RZ] / t;
+            *d.counter = 0u;
+        }
+    }
+}
+
+// x += alpha p; r -= alpha q; z = D^-1 r; beta = rz_new / rz; convergence test
+__global__ __launch_bounds__(kBlock) void k_cg_axpy(Dev d) {
+    __shared__ double lds[4];
+    if (d.scal[SC_DONE] != 0.0) return;
+    const double alpha = d.scal[SC_ALPHA];
+    const int64_t i = gtid_s();
+    double rz = 0.0, rr = 0.0;
+    if (i < d.nc) {
+        d.x[i] = d.x[i] + alpha * d.p[i];
+        const double ri = d.r[i] - alpha * d.q[i];
+        const double zi = d.k_dinv[i] * ri;
+        d.r[i] = ri;
+        d.z[i] = zi;
+        rz = ri * zi;
+        rr = ri * ri;
+    }
+    const double v[2] = {block_sum256(rz, lds), block_sum256(rr, lds)};
+    if (publish_partials<2>(v, d.partial, d.counter)) {
+        const double trz = sum_partials(d.partial, 0, lds);
+        const double trr = sum_partials(d.partial, 1, lds);
+        if (threadIdx.x == 0) {
+            double* sc = d.scal;
+            sc[SC_BETA] = trz / sc[SC_RZ];
+            sc[SC_RZ] = trz;
+            sc[SC_RR] = trr;
+            sc[SC_IT] = sc[SC_IT] + 1.0;
+            if (trr <= sc[SC_TOL2BB]) sc[SC_DONE] = 1.0;
+            else if (sc[SC_IT] >= sc[SC_MAXIT]) sc[SC_DONE] = 2.0;
+            *d.counter = 0u;
+        }
+    }
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(kBlock) void k_cg_dir(Dev d) {
+    if (d.scal[SC_DONE] != 0.0) return;
+    const double beta = d.scal[SC_BETA];
+    const int64_t i = gtid_s();
+    if (i >= d.nc) return;
+    d.p[i] = d.z[i] + beta * d.p[i];
+}
+
+// ---- launchers ---------------------------------------------------------------
+hipError_t launch_assemble(const Dev& d, const BcTable& bc, int row_max, hipStream_t s) {
+    const size_t lds = size_t(row_max > 0 ? row_max : 1) * 64 * sizeof(double);
+    hipLaunchKernelGGL(k_assemble, dim3(unsigned((d.nc + 63) / 64)), dim3(64), lds, s, d, bc);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_plain(const Dev& d, const double* x, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_spmv, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs(const Dev& d, const double* f, hipStream_t s) {
+    hipLaunchKernelGGL(k_rhs, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_setup(const Dev& d, int nblk, double tol, int maxit, hipStream_t s) {
+    (void)nblk;
+    hipLaunchKernelGGL(k_cg_setup, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d, tol, maxit, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_true_residual(const Dev& d, int nblk, hipStream_t s) {
+    (void)nblk;
+    // reopen without resetting the iteration count; tol/maxit are reused
+    hipLaunchKernelGGL(k_cg_setup, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d, -1.0, -1, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_spmv(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_spmv, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_axpy(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_axpy, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_dir(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_dir, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+}  // namespace mifvm

@@ -1,0 +1,115 @@
+// Device-resident state: the preprocessed mesh and every field, carved out
+// of one caller-owned workspace.  Shared by the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "mesh.h"
+
+namespace mifvm {
+
+constexpr int kMaxTags = 32;
+constexpr int kBlock = 256;               // threads per block (4 wavefronts)
+constexpr int kZeroFlux = 0, kNeumann = 1, kDirichlet = 2;
+
+struct BcTable {                          // per-tag boundary conditions
+    int32_t kind[kMaxTags];
+    double value[kMaxTags];
+};
+
+// Pointers into the workspace.  Layout: SoA, float64 unless noted, every
+// array 256-byte aligned.
+struct Dev {
+    int64_t nc, nv, nf, nfi, nb;
+    int64_t ns, nvs;                      // 64-row slices of cells / vertices
+    // cells
+    double *vol, *xc;                     // xc: 3 x (nc+nb)
+    double* minv;                         // 6 x nc
+    int32_t *c2f, *c2n;                   // 4 x nc
+    int64_t* s_off; int32_t* s_w; int32_t* s_idx;
+    // faces
+    int32_t *fL, *fR, *fA, *fB, *fC;
+    double *kAC, *kBC, *kRL, *fx, *S, *area;   // fx, S: 3 x nf
+    // ghosts
+    int32_t *gowner, *gtag; double* gdist;
+    // vertices
+    int64_t* n_off; int32_t* n_w; int32_t* n_idx; double* n_alpha;
+    // Poisson pattern and values
+    int64_t* k_off; int32_t* k_w; int32_t* k_col; int32_t* k_len;
+    double *k_val, *k_diag, *k_dinv, *k_c;
+    // renumbering
+    int32_t *cell_perm, *vert_perm;       // internal -> user
+    // fields
+    double *u, *un, *src, *vel, *phi;     // u: nc+nb (ghosts behind), vel 3 x nc
+    double *grad, *psi, *unode, *flux;    // grad 3 x nc
+    // solver vectors (P lives in x)
+    double *x, *r, *z, *p, *q, *b;
+    double* tmp;                          // nc+nb scratch (permutation, residual)
+    double* partial;                      // reduction partials (2 per block)
+    double* scal;                         // solver scalars (see solve_kernels)
+    uint32_t* counter;                    // last-block counters (self-resetting)
+};
+
+constexpr int kNumKernels = 11;
+
+// Event pairs around kernel launches, resolved into totals at sync points.
+struct KernelTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> pending;   // kernel id, index of start event
+    double total_ms[kNumKernels] = {};
+    int64_t count[kNumKernels] = {};
+};
+
+struct State {
+    const Mesh* mesh = nullptr;           // host copy kept for sizes
+    Dev d{};
+    BcTable bc[2]{};                      // SCALAR, POTENTIAL
+    double diffusivity = 0.0;
+    bool assembled = false;
+    bool vel_set = false;
+    double* h_scal = nullptr;             // pinned host mirror of scalars
+    int nblk_cells = 0;                   // grid for per-cell reductions
+    KernelTimer timer;
+};
+
+// workspace layout; returns total bytes (and fills d when base != nullptr)
+size_t layout(const Mesh& m, char* base, Dev& d);
+
+// launchers (fv_kernels.hip)
+hipError_t launch_ghost_fill(const Dev& d, double* u, const BcTable& bc, hipStream_t s);
+hipError_t launch_grad_limiter(const Dev& d, hipStream_t s);
+hipError_t launch_node_interp(const Dev& d, hipStream_t s);
+hipError_t launch_face_flux(const Dev& d, const BcTable& bc, double D, hipStream_t s);
+hipError_t launch_update(const Dev& d, double a_dt, bool first_stage, hipStream_t s);
+hipError_t launch_residual_out(const Dev& d, double* res_internal, hipStream_t s);
+hipError_t launch_face_phi(const Dev& d, hipStream_t s);
+hipError_t launch_to_internal(const int32_t* perm, int64_t n, int64_t stride_in, int64_t stride_out,
+                              int comps, const double* src, double* dst, hipStream_t s);
+hipError_t launch_to_user(const int32_t* perm, int64_t n, int64_t stride_in, int64_t stride_out,
+                          int comps, const double* src, double* dst, hipStream_t s);
+hipError_t launch_cfl(const Dev& d, const BcTable& bc, double D, int nblk, hipStream_t s);
+hipError_t launch_conservation(const Dev& d, int nblk, hipStream_t s);
+
+// launchers (solve_kernels.hip)
+hipError_t launch_assemble(const Dev& d, const BcTable& bc, int row_max, hipStream_t s);
+hipError_t launch_spmv_plain(const Dev& d, const double* x, double* y, hipStream_t s);
+hipError_t launch_rhs(const Dev& d, const double* f_internal, hipStream_t s);
+hipError_t launch_cg_setup(const Dev& d, int nblk, double tol, int maxit, hipStream_t s);
+hipError_t launch_cg_spmv(const Dev& d, hipStream_t s);
+hipError_t launch_cg_axpy(const Dev& d, hipStream_t s);
+hipError_t launch_cg_dir(const Dev& d, hipStream_t s);
+hipError_t launch_true_residual(const Dev& d, int nblk, hipStream_t s);
+
+// scalar slots in Dev::scal
+enum Scal {
+    SC_RZ = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_BB, SC_TOL2BB, SC_DONE, SC_IT, SC_MAXIT,
+    SC_TRUE_RR, SC_CONS, SC_DT_INV, SC_COUNT_ = 16
+};
+
+}  // namespace mifvm
