@@ -153,7 +153,7 @@ def main():
         st.step(1, dt)
         if evs is not None:
             evs[1].record(stream)
-        info_s = st.poisson_solve(None, tol=1e-10)
+        info_s = st.poisson_solve(None, tol=1e-10, restart=500)
         if evs is not None:
             evs[2].record(stream)
         return info_s

@@ -106,13 +106,22 @@ typedef struct {
 
 typedef struct {
     double tol;                /* relative true residual ||b-Kx||/||b||       */
-    int32_t maxit;
+    int32_t maxit;             /* iteration limit                             */
     int32_t chunk;             /* iterations enqueued between host checks    */
+    int32_t restart;           /* restart from the true residual every this
+                                  many iterations (0 = only when the
+                                  recurrence residual claims convergence)    */
+    int32_t history_cap;       /* capacity of history (0 = none)              */
+    double* history;           /* host, optional: recurrence ||r||/||b|| at
+                                  every host check                           */
 } mifvm_solve_opts;
 
 typedef struct {
     int32_t iterations;
-    int32_t restarts;          /* times the true residual reopened the loop   */
+    int32_t restarts;          /* times the loop was reopened from the true
+                                  residual without having converged           */
+    int32_t history_len;       /* entries written to opts->history            */
+    int32_t pad_;
     double rel_residual;       /* final true relative residual (FP64)        */
     double ms;                 /* wall time of the solve call                */
 } mifvm_solve_info;
@@ -204,7 +213,9 @@ int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* str
  * starts from the stored P (zero after create, the last solution after a
  * solve: warm start) and stores the result back in P.  Converged when the
  * recomputed FP64 true residual ||b - K x||_2 <= tol ||b||_2.  opts NULL =
- * tol 1e-10, maxit 20000, chunk 32.  Returns NOT_CONVERGED at maxit.
+ * tol 1e-10, maxit 20000, chunk 32, restart 500.  A restart
+ * recomputes r = b - K x and sets p = D^-1 r.  Returns NOT_CONVERGED at
+ * maxit.
  * Synchronises (once per chunk).                                           */
 int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_opts* opts,
                         mifvm_solve_info* info, void* stream);

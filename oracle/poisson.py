@@ -117,34 +117,40 @@ def rhs(geo: Geometry, f, c):
     return -geo.vol * np.asarray(f, np.float64) + c
 
 
-def jacobi_cg(K, b, x0=None, tol=1e-10, maxit=20000, history=None):
-    """Textbook preconditioned CG with the Jacobi preconditioner
-    z = D^{-1} r.  Stops when ||r||_2 <= tol ||b||_2 (recurrence residual),
-    then confirms with the true residual; returns (x, iterations, true_rel)."""
+def jacobi_cg(K, b, x0=None, tol=1e-10, maxit=20000, restart=0, history=None):
+    """Textbook preconditioned CG with the Jacobi preconditioner z = D^{-1} r.
+
+    The loop is opened from the true residual r = b - K x; it is left when the
+    recurrence residual satisfies ||r||_2 <= tol ||b||_2, when maxit
+    iterations have been done, or - if restart > 0 - after `restart`
+    iterations since the last opening.  It is then reopened from the true
+    residual (a restart, p = D^{-1} r) unless that already meets the
+    tolerance or the limit.  Returns (x, iterations, true relative residual).
+    """
     b = np.asarray(b, np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, np.float64)
     dinv = 1.0 / K.diagonal()
     bnorm = np.linalg.norm(b)
-    r = b - K @ x
     it = 0
     while True:
+        r = b - K @ x
         if np.linalg.norm(r) <= tol * bnorm or it >= maxit:
-            true_rel = np.linalg.norm(b - K @ x) / bnorm
-            if true_rel <= tol or it >= maxit:
-                return x, it, true_rel
-            r = b - K @ x                       # drift: restart from true r
+            return x, it, float(np.linalg.norm(r) / bnorm)
         z = dinv * r
         p = z.copy()
         rz = r @ z
-        while it < maxit:
+        since = 0
+        while True:
             q = K @ p
             alpha = rz / (p @ q)
             x = x + alpha * p
             r = r - alpha * q
             it += 1
+            since += 1
             if history is not None:
                 history.append(x.copy())
-            if np.linalg.norm(r) <= tol * bnorm:
+            if (np.linalg.norm(r) <= tol * bnorm or it >= maxit
+                    or (restart > 0 and since >= restart)):
                 break
             z = dinv * r
             rz_new = r @ z

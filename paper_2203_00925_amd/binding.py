@@ -70,11 +70,14 @@ class _Params(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("chunk", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("chunk", C.c_int32),
+                ("restart", C.c_int32), ("history_cap", C.c_int32),
+                ("history", C.POINTER(C.c_double))]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32),
+                ("history_len", C.c_int32), ("pad_", C.c_int32),
                 ("rel_residual", C.c_double), ("ms", C.c_double)]
 
 
@@ -170,7 +173,7 @@ class Mesh:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.mifvm_mesh_destroy(h)
             self._h = None
 
@@ -195,7 +198,7 @@ class State:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.mifvm_state_destroy(h)
             self._h = None
 
@@ -270,18 +273,20 @@ class State:
         _check(_lib.mifvm_poisson_rhs(self._h, _ptr(f), _ptr(y), _stream(stream)))
         return y
 
-    def poisson_solve(self, f=None, tol=1e-10, maxit=20000, chunk=32, stream=None,
-                      allow_not_converged=False):
+    def poisson_solve(self, f=None, tol=1e-10, maxit=20000, chunk=32, restart=500,
+                      history=0, stream=None, allow_not_converged=False):
         import torch
         if f is not None:
             f = f.to(device=self.device, dtype=torch.float64).contiguous()
-        opts = SolveOpts(float(tol), int(maxit), int(chunk))
+        hist = (C.c_double * max(int(history), 1))()
+        opts = SolveOpts(float(tol), int(maxit), int(chunk), int(restart), int(history), hist)
         info = SolveInfo()
         allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
         rc = _check(_lib.mifvm_poisson_solve(self._h, _ptr(f), C.byref(opts), C.byref(info),
                                              _stream(stream)), allow)
         return dict(status=rc, iterations=info.iterations, restarts=info.restarts,
-                    rel_residual=info.rel_residual, ms=info.ms)
+                    rel_residual=info.rel_residual, ms=info.ms,
+                    history=list(hist[:info.history_len]))
 
     # -- per-kernel timing ----------------------------------------------------------
     def kernel_timing(self, enable=True):

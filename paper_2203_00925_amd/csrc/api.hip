@@ -135,6 +135,15 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.k_diag = carve<double>(base, off, nc);
     d.k_dinv = carve<double>(base, off, nc);
     d.k_c = carve<double>(base, off, nc);
+    d.tile_rows = m.tile_rows;
+    d.halo_max = m.halo_max;
+    d.ntiles = (int64_t)m.h_self.size();
+    d.h_off = carve<int64_t>(base, off, m.h_off.size());
+    d.h_idx = carve<int32_t>(base, off, m.h_idx.size());
+    d.h_self = carve<int32_t>(base, off, m.h_self.size());
+    d.s_lidx = carve<uint16_t>(base, off, m.s_lidx.size());
+    d.k_lidx = carve<uint16_t>(base, off, m.k_lidx.size());
+    d.c2n_l = carve<uint16_t>(base, off, m.c2n_l.size());
     d.cell_perm = carve<int32_t>(base, off, nc);
     d.vert_perm = carve<int32_t>(base, off, nv);
     d.u = carve<double>(base, off, NX);
@@ -156,7 +165,6 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     const int64_t nblk = (nc + kBlock - 1) / kBlock;
     d.partial = carve<double>(base, off, 4 * (nblk + 1024));
     d.scal = carve<double>(base, off, SC_COUNT_);
-    d.counter = carve<uint32_t>(base, off, 64);
     return (off + 255) & ~size_t(255);
 }
 
@@ -293,6 +301,8 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     UP(d.n_off, m.node.off); UP(d.n_w, m.node.width); UP(d.n_idx, m.node.idx); UP(d.n_alpha, m.node.val);
     UP(d.k_off, m.kmat.off); UP(d.k_w, m.kmat.width); UP(d.k_col, m.kmat.idx); UP(d.k_len, m.klen);
     UP(d.cell_perm, m.cell_perm); UP(d.vert_perm, m.vert_perm);
+    UP(d.h_off, m.h_off); UP(d.h_idx, m.h_idx); UP(d.h_self, m.h_self);
+    UP(d.s_lidx, m.s_lidx); UP(d.k_lidx, m.k_lidx); UP(d.c2n_l, m.c2n_l);
 #undef UP
     const int64_t NX = m.nc + m.nb;
     e = hipMemsetAsync(d.u, 0, NX * sizeof(double), s);
@@ -301,7 +311,6 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     if (e == hipSuccess) e = hipMemsetAsync(d.phi, 0, m.nf * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.x, 0, m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.scal, 0, SC_COUNT_ * sizeof(double), s);
-    if (e == hipSuccess) e = hipMemsetAsync(d.counter, 0, 64 * sizeof(uint32_t), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // host vectors are not pinned
     if (e != hipSuccess) return cleanup(hip_fail(e, "state init"));
     *out = h;
@@ -523,20 +532,26 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
     const double tol = opts ? opts->tol : 1e-10;
     const int maxit = opts ? opts->maxit : 20000;
     const int chunk = opts && opts->chunk > 0 ? opts->chunk : 32;
-    if (!(tol > 0) || maxit < 0) return fail(MIFVM_E_ARG, "bad tol or maxit");
+    const int restart = opts ? opts->restart : 500;
+    double* hist = opts ? opts->history : nullptr;
+    const int hist_cap = opts && opts->history ? opts->history_cap : 0;
+    if (!(tol > 0) || maxit < 0 || restart < 0 || hist_cap < 0) return fail(MIFVM_E_ARG, "bad tol, maxit, restart or history");
     const Dev& d = s.d;
     hipStream_t hs = S(stream);
     auto t0 = std::chrono::steady_clock::now();
     int rc = rhs_internal(s, d_f, hs);
     if (rc) return rc;
     KernelTimer& tm = s.timer;
+    int nhist = 0;
     auto pull = [&]() -> int {
         HIPCHK(hipMemcpyAsync(s.h_scal, d.scal, SC_COUNT_ * sizeof(double), hipMemcpyDeviceToHost, hs));
         HIPCHK(hipStreamSynchronize(hs));
         HIPCHK(timer_flush(tm));
+        const double bb = s.h_scal[SC_BB];
+        if (nhist < hist_cap) hist[nhist++] = bb > 0 ? std::sqrt(s.h_scal[SC_RR] / bb) : 0.0;
         return MIFVM_OK;
     };
-    HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, 0, tol, maxit, hs); }));
+    HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, true, hs); }));
     if ((rc = pull())) return rc;
     int restarts = 0;
     if (s.h_scal[SC_BB] == 0.0) {       // b = 0: the solution is 0
@@ -552,7 +567,9 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
                 }
                 if ((rc = pull())) return rc;
             }
-            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_true_residual(d, 0, hs); }));  // r = b - K x
+            // recurrence converged, limit reached or restart due: recompute the
+            // true residual r = b - K x (FP64) and reopen from it
+            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, false, hs); }));
             if ((rc = pull())) return rc;
             if (s.h_scal[SC_DONE] != 0.0) break;      // converged on the true residual, or maxit
             ++restarts;
@@ -564,6 +581,7 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
     if (info) {
         info->iterations = iters;
         info->restarts = restarts;
+        info->history_len = nhist;
         info->rel_residual = rel;
         info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }

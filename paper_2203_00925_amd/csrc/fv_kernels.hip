@@ -43,25 +43,42 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(int64_t nc, int64_t nb,
     u[nc + g] = ug;
 }
 
+// One block per tile of d.tile_rows cells.  The tile's halo (every cell and
+// ghost its stencils reference) is staged in LDS as (x, y, z, u) records, so
+// the ~70 neighbour reads per cell are LDS reads addressed by 16-bit local
+// indices; global memory sees one gather per halo entity and the streamed
+// local index list.
 __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d) {
-    const int64_t i = gtid();
-    if (i >= d.nc) return;
+    extern __shared__ double4 sm[];                  // [halo] x, y, z, u
     const int64_t nc = d.nc, NX = d.nc + d.nb, nf = d.nf;
+    const int64_t t = blockIdx.x;
+    const int T = blockDim.x;
+    const int64_t h0 = d.h_off[t];
+    const int hn = int(d.h_off[t + 1] - h0);
     const double* __restrict__ X = d.xc;
     const double* __restrict__ Y = d.xc + NX;
     const double* __restrict__ Z = d.xc + 2 * NX;
     const double* __restrict__ u = d.u;
-    const double xi = X[i], yi = Y[i], zi = Z[i], ui = u[i];
+    for (int h = threadIdx.x; h < hn; h += T) {
+        const int e = d.h_idx[h0 + h];
+        sm[h] = make_double4(X[e], Y[e], Z[e], u[e]);
+    }
+    __syncthreads();
+    const int64_t i = t * T + threadIdx.x;
+    if (i >= nc) return;
+    const double4 me = sm[d.h_self[t] + threadIdx.x];
+    const double xi = me.x, yi = me.y, zi = me.z, ui = me.w;
     const int64_t s = i >> 6;
-    const int32_t* __restrict__ idx = d.s_idx + d.s_off[s] + (i & 63);
+    const uint16_t* __restrict__ idx = d.s_lidx + d.s_off[s] + (i & 63);
     const int w = d.s_w[s];
     double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll 4
     for (int k = 0; k < w; ++k) {
-        const int j = idx[int64_t(k) * 64];
-        const double du = u[j] - ui;
-        jx += (X[j] - xi) * du;
-        jy += (Y[j] - yi) * du;
-        jz += (Z[j] - zi) * du;
+        const double4 o = sm[idx[int64_t(k) * 64]];
+        const double du = o.w - ui;
+        jx += (o.x - xi) * du;
+        jy += (o.y - yi) * du;
+        jz += (o.z - zi) * du;
     }
     const double* __restrict__ m = d.minv;
     const double m0 = m[i], m1 = m[nc + i], m2 = m[2 * nc + i];
@@ -77,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d) {
     double umax = ui, umin = ui;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double v = u[d.c2n[k * nc + i]];
+        const double v = sm[d.c2n_l[k * nc + i]].w;
         umax = fmax(umax, v);
         umin = fmin(umin, v);
     }
@@ -215,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_to_user(const int32_t* __restrict__ 
     for (int c = 0; c < comps; ++c) dst[c * sout + o] = src[c * sin + i];
 }
 
-// dt bound: min_i mu_i / sum_{active faces} (|phi_f| + D kRL_f) -> scal[SC_DT_INV]
+// dt bound: min_i mu_i / sum_{active faces} (|phi_f| + D kRL_f), per block
 __global__ __launch_bounds__(kBlock) void k_cfl(Dev d, BcTable bc, double D) {
     __shared__ double lds[4];
     const int64_t nc = d.nc;
@@ -230,30 +247,23 @@ __global__ __launch_bounds__(kBlock) void k_cfl(Dev d, BcTable bc, double D) {
         }
         best = fmin(best, d.vol[i] / rate);
     }
-    const double b = block_min256(best, lds);
-    const double vals[1] = {b};
-    if (publish_partials<1>(vals, d.partial, d.counter)) {
-        const double m = min_partials(d.partial, 0, lds);
-        if (threadIdx.x == 0) {
-            d.scal[SC_DT_INV] = m;
-            *d.counter = 0u;
-        }
-    }
+    best = block_min256(best, lds);
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = best;
 }
 
 __global__ __launch_bounds__(kBlock) void k_conservation(Dev d) {
     __shared__ double lds[4];
     double s = 0.0;
     for (int64_t i = gtid(); i < d.nc; i += int64_t(gridDim.x) * blockDim.x) s += d.vol[i] * d.u[i];
-    const double b = block_sum256(s, lds);
-    const double vals[1] = {b};
-    if (publish_partials<1>(vals, d.partial, d.counter)) {
-        const double t = sum_partials(d.partial, 0, lds);
-        if (threadIdx.x == 0) {
-            d.scal[SC_CONS] = t;
-            *d.counter = 0u;
-        }
-    }
+    s = block_sum256(s, lds);
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = s;
+}
+
+// one block: reduce n partials into scal[slot] (op 0 = sum, 1 = min)
+__global__ __launch_bounds__(1024) void k_finalize(Dev d, int64_t n, int slot, int op) {
+    __shared__ double lds[16];
+    const double v = op == 0 ? reduce_partials_sum(d.partial, n, lds) : reduce_partials_min(d.partial, n, lds);
+    if (threadIdx.x == 0) d.scal[slot] = v;
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -265,7 +275,8 @@ hipError_t launch_ghost_fill(const Dev& d, double* u, const BcTable& bc, hipStre
 }
 
 hipError_t launch_grad_limiter(const Dev& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_grad_limiter, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_grad_limiter, dim3(unsigned(d.ntiles)), dim3(d.tile_rows),
+                       size_t(d.halo_max) * sizeof(double4), s, d);
     return hipGetLastError();
 }
 
@@ -310,11 +321,13 @@ hipError_t launch_to_user(const int32_t* perm, int64_t n, int64_t sin, int64_t s
 
 hipError_t launch_cfl(const Dev& d, const BcTable& bc, double D, int nblk, hipStream_t s) {
     hipLaunchKernelGGL(k_cfl, dim3(nblk), dim3(kBlock), 0, s, d, bc, D);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, d, int64_t(nblk), int(SC_DT_INV), 1);
     return hipGetLastError();
 }
 
 hipError_t launch_conservation(const Dev& d, int nblk, hipStream_t s) {
     hipLaunchKernelGGL(k_conservation, dim3(nblk), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, d, int64_t(nblk), int(SC_CONS), 0);
     return hipGetLastError();
 }
 

@@ -15,7 +15,10 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 namespace mifvm {
@@ -131,6 +134,16 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
         if (btags[i] < 0 || btags[i] >= 32) { err = "boundary tag out of [0, 32)"; return E_ARG; }
 
     auto P = [&](int64_t v) { return V3{xyz[3 * v], xyz[3 * v + 1], xyz[3 * v + 2]}; };
+    // MIFVM_PREPROCESS_TIMING=1 prints the time of each stage to stderr
+    const bool timing = std::getenv("MIFVM_PREPROCESS_TIMING") != nullptr;
+    auto tprev = std::chrono::steady_clock::now();
+    auto mark = [&](const char* what) {
+        if (!timing) return;
+        auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[mifvm preprocess] %-28s %8.3f s\n", what,
+                     std::chrono::duration<double>(now - tprev).count());
+        tprev = now;
+    };
 
     // -- 1. orientation, volume, centre of gravity (user order) --------------
     std::vector<std::array<int32_t, 4>> T(nc);
@@ -152,6 +165,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     for (int64_t c = 0; c < nc; ++c)
         if (!(vol_u[c] > 1e-14 * vmean)) { err = "degenerate tetrahedron"; return E_MESH; }
 
+    mark("orientation+volumes");
     // -- 2. cell renumbering --------------------------------------------------
     std::vector<int32_t> new2old(nc), old2new(nc);
     std::iota(new2old.begin(), new2old.end(), 0);
@@ -177,6 +191,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     }
     for (int64_t i = 0; i < nc; ++i) old2new[new2old[i]] = (int32_t)i;
 
+    mark("renumbering");
     // -- 3. faces: sorted vertex triples, grouped (counting sort on a) -------
     static const int opp[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
     std::vector<FaceRec> rec(4 * nc);
@@ -218,6 +233,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     rec.clear();
     rec.shrink_to_fit();
 
+    mark("faces");
     // -- 4. boundary tags ------------------------------------------------------
     auto less3 = [](const UFace& x, int32_t a, int32_t b, int32_t c) {
         if (x.a != a) return x.a < a;
@@ -255,6 +271,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
         if (dot(S, sub(xf, cen_u[f.L])) < 0) std::swap(f.b, f.c);
     }
 
+    mark("tags+orientation");
     // -- 6. internal face order ------------------------------------------------
     std::vector<int64_t> ford(uf.size());
     std::iota(ford.begin(), ford.end(), 0);
@@ -267,6 +284,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     };
     std::sort(ford.begin(), ford.end(), [&](int64_t x, int64_t y) { return fkey(x) < fkey(y); });
 
+    mark("face order");
     // -- 7. vertex renumbering: by the first internal cell touching it ---------
     std::vector<int64_t> vmin(nv, INT64_MAX);
     for (int64_t c = 0; c < nc; ++c)
@@ -337,6 +355,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     uf.clear();
     uf.shrink_to_fit();
 
+    mark("face geometry");
     // -- 9. cell -> faces ---------------------------------------------------------
     M.c2f.assign(4 * nc, -1);
     M.c2n.assign(4 * nc, -1);
@@ -355,6 +374,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     for (int64_t c = 0; c < nc; ++c)
         if (cnt[c] != 4) { err = "cell without 4 faces"; return E_MESH; }
 
+    mark("cell->face");
     // -- 10. vertex -> cells and ghosts ------------------------------------------
     {
         std::vector<int64_t> deg(nv + 1, 0);
@@ -380,6 +400,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     M.node_max = 0;
     for (int64_t v = 0; v < nv; ++v) M.node_max = std::max<int32_t>(M.node_max, int32_t(M.nptr[v + 1] - M.nptr[v]));
 
+    mark("vertex lists");
     // -- 11. least-squares vertex weights (Algorithm 2) -------------------------
     M.nalpha.assign(M.nidx.size(), 0.0);
     for (int64_t v = 0; v < nv; ++v) {
@@ -400,6 +421,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
         }
     }
 
+    mark("vertex weights");
     // -- 12. node-neighbour stencil (Algorithm 1): merge of 4 sorted lists ----
     M.sptr.assign(nc + 1, 0);
     M.sidx.clear();
@@ -451,11 +473,102 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     M.matrix_nnz = 0;
     for (int64_t i = 0; i < nc; ++i) M.matrix_nnz += M.klen[i] + 1;
 
+    mark("stencil+gradient matrix");
     // -- 13. 64-row slicing ------------------------------------------------------
     pack_sell(M.sptr, M.sidx, nullptr, nullptr, nc, [](int64_t r) { return (int32_t)r; }, M.stencil);
     pack_sell(M.nptr, M.nidx, &M.nalpha, nullptr, nv,
               [&](int64_t r) { return M.nidx[M.nptr[r]]; }, M.node);
     pack_sell(M.sptr, M.sidx, nullptr, &M.klen, nc, [](int64_t r) { return (int32_t)r; }, M.kmat);
+
+    mark("slicing");
+    // -- 14. tiles and their halos -------------------------------------------------
+    const int64_t kHaloCap = 2048;            // 64 KB of LDS at 32 bytes per entity
+    std::vector<int64_t> seen(nc + nb, -1);      // last tile that collected the entity
+    for (int32_t T = 256; T >= 64; T /= 2) {
+        M.tile_rows = T;
+        const int64_t nt = (nc + T - 1) / T;
+        M.h_off.assign(nt + 1, 0);
+        M.h_idx.clear();
+        M.h_idx.reserve(size_t(nc) * 6);
+        M.h_self.assign(nt, 0);
+        M.halo_max = 0;
+        std::fill(seen.begin(), seen.end(), -1);
+        std::vector<int32_t> buf;
+        for (int64_t t = 0; t < nt; ++t) {
+            const int64_t t0 = t * T, t1 = std::min(nc, t0 + T);
+            buf.clear();
+            for (int64_t i = t0; i < t1; ++i) {
+                seen[i] = t;
+                buf.push_back((int32_t)i);
+            }
+            for (int64_t e = M.sptr[t0]; e < M.sptr[t1]; ++e) {
+                const int32_t v = M.sidx[e];
+                if (seen[v] != t) {
+                    seen[v] = t;
+                    buf.push_back(v);
+                }
+            }
+            std::sort(buf.begin(), buf.end());
+            M.h_self[t] = int32_t(std::lower_bound(buf.begin(), buf.end(), (int32_t)t0) - buf.begin());
+            M.h_idx.insert(M.h_idx.end(), buf.begin(), buf.end());
+            M.h_off[t + 1] = (int64_t)M.h_idx.size();
+            M.halo_max = std::max<int32_t>(M.halo_max, (int32_t)buf.size());
+        }
+        if (M.halo_max <= kHaloCap || T == 64) break;
+    }
+    if (M.halo_max > kHaloCap) { err = "stencil neighbourhood too large for the LDS tile"; return E_MESH; }
+    mark("tile halos");
+    // global -> local through a dense map filled for one tile at a time
+    M.s_lidx.assign(M.stencil.idx.size(), 0);
+    M.k_lidx.assign(M.kmat.idx.size(), 0);
+    M.c2n_l.assign(4 * nc, 0);
+    {
+        std::vector<int32_t> g2l(nc + nb, -1);
+        const int64_t T = M.tile_rows;
+        const int64_t nt = (int64_t)M.h_self.size();
+        for (int64_t t = 0; t < nt; ++t) {
+            for (int64_t h = M.h_off[t]; h < M.h_off[t + 1]; ++h) g2l[M.h_idx[h]] = int32_t(h - M.h_off[t]);
+            const int64_t t0 = t * T, t1 = std::min(nc, t0 + T);
+            for (int64_t r = t0; r < t1; ++r) {
+                const int64_t sl = r >> 6;
+                const int lane = int(r & 63);
+                for (int64_t k = 0; k < M.stencil.width[sl]; ++k) {
+                    const int64_t at = M.stencil.off[sl] + k * 64 + lane;
+                    M.s_lidx[at] = (uint16_t)g2l[M.stencil.idx[at]];
+                }
+                for (int64_t k = 0; k < M.kmat.width[sl]; ++k) {
+                    const int64_t at = M.kmat.off[sl] + k * 64 + lane;
+                    M.k_lidx[at] = (uint16_t)g2l[M.kmat.idx[at]];
+                }
+                for (int k = 0; k < 4; ++k) M.c2n_l[k * nc + r] = (uint16_t)g2l[M.c2n[k * nc + r]];
+            }
+            for (int64_t h = M.h_off[t]; h < M.h_off[t + 1]; ++h) g2l[M.h_idx[h]] = -1;
+        }
+    }
+    mark("local indices");
+    // every local index must name the same entity as the global one
+    auto verify = [&](const Sell64& sl, const std::vector<uint16_t>& loc) -> bool {
+        for (int64_t s_ = 0; s_ < sl.nslices; ++s_)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int64_t r = s_ * 64 + lane;
+                if (r >= nc) continue;
+                const int64_t t = r / M.tile_rows;
+                for (int64_t k = 0; k < sl.width[s_]; ++k) {
+                    const int64_t at = sl.off[s_] + k * 64 + lane;
+                    if (int64_t(loc[at]) >= M.h_off[t + 1] - M.h_off[t] || M.h_idx[M.h_off[t] + loc[at]] != sl.idx[at])
+                        return false;
+                }
+            }
+        return true;
+    };
+    bool ok = verify(M.stencil, M.s_lidx) && verify(M.kmat, M.k_lidx);
+    for (int64_t i = 0; ok && i < nc; ++i) {
+        const int64_t t = i / M.tile_rows;
+        ok = M.h_idx[M.h_off[t] + M.h_self[t] + (i - t * M.tile_rows)] == i;
+        for (int k = 0; ok && k < 4; ++k) ok = M.h_idx[M.h_off[t] + M.c2n_l[k * nc + i]] == M.c2n[k * nc + i];
+    }
+    if (!ok) { err = "internal error: tile-local index mismatch"; return E_MESH; }
+    mark("verification");
     return 0;
 }
 

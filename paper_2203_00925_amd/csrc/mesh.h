@@ -46,6 +46,19 @@ struct Mesh {
     Sell64 node;                      // vertex lists + weights, pad = first entry, weight 0
     Sell64 kmat;                      // Poisson off-diagonal pattern, pad = the row itself
     std::vector<int32_t> klen;        // off-diagonal entries per row (sorted prefix)
+    // Tiles of `tile_rows` consecutive cells (a multiple of 64).  Each tile's
+    // halo is the sorted set of cells and ghosts its stencils reference
+    // (its own cells included, contiguous); kernels stage the halo's data in
+    // LDS and address it with 16-bit local indices laid out like the
+    // corresponding 64-row slices.
+    int32_t tile_rows = 256;
+    int32_t halo_max = 0;
+    std::vector<int64_t> h_off;       // ntiles + 1
+    std::vector<int32_t> h_idx;       // halo entities
+    std::vector<int32_t> h_self;      // ntiles: local index of the tile's first cell
+    std::vector<uint16_t> s_lidx;     // like stencil.idx, local
+    std::vector<uint16_t> k_lidx;     // like kmat.idx, local
+    std::vector<uint16_t> c2n_l;      // 4 x nc local index of the face neighbour
 };
 
 // Returns 0 or a negative mifvm status; err receives a message.

@@ -2,9 +2,11 @@
 //
 // A block reduces with a butterfly over the 64 lanes of each wavefront (every
 // lane ends with the bitwise-identical total, since a+b == b+a) and then sums
-// the 4 wavefront totals in a fixed order.  A grid reduction writes one
-// partial per block; the last block to finish (device-scope counter) sums the
-// partials in index order, so the result does not depend on block timing.
+// the wavefront totals in a fixed order.  A grid reduction writes one partial
+// per block with a plain store; a separate one-block kernel sums the partials
+// in index order.  No device-scope fence is executed per block: on a
+// multi-XCD part such a fence writes back the XCD's L2, which costs more than
+// the extra kernel launch.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -32,6 +34,56 @@ __device__ inline double block_sum256(double v, double* lds) {
     return ((lds[0] + lds[1]) + lds[2]) + lds[3];
 }
 
+// blockDim.x in {64, 128, 256}; lds needs 4 doubles.  Result valid in all threads.
+__device__ inline double block_sum_upto256(double v, double* lds) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = lds[0];
+    for (int k = 1; k < nw; ++k) s += lds[k];
+    return s;
+}
+
+// blockDim.x == 1024 assumed; lds needs 16 doubles.  Result valid in all threads.
+__device__ inline double block_sum1024(double v, double* lds) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += lds[k];
+    return s;
+}
+
+__device__ inline double block_min1024(double v, double* lds) {
+    v = wave_min(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double s = lds[0];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) s = fmin(s, lds[k]);
+    return s;
+}
+
+// In a one-block kernel of 1024 threads: fixed-order sum of n partials.
+__device__ inline double reduce_partials_sum(const double* partial, int64_t n, double* lds) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) s += partial[i];
+    return block_sum1024(s, lds);
+}
+
+__device__ inline double reduce_partials_min(const double* partial, int64_t n, double* lds) {
+    double s = __builtin_huge_val();
+    for (int64_t i = threadIdx.x; i < n; i += 1024) s = fmin(s, partial[i]);
+    return block_min1024(s, lds);
+}
+
 __device__ inline double block_min256(double v, double* lds) {
     v = wave_min(v);
     const int w = threadIdx.x >> 6;
@@ -39,39 +91,6 @@ __device__ inline double block_min256(double v, double* lds) {
     if ((threadIdx.x & 63) == 0) lds[w] = v;
     __syncthreads();
     return fmin(fmin(lds[0], lds[1]), fmin(lds[2], lds[3]));
-}
-
-// Publish this block's partial(s) and report whether it is the last block.
-// partial[k * nblocks + blockIdx.x] = vals[k] for k < K.
-template <int K>
-__device__ inline bool publish_partials(const double (&vals)[K], double* partial,
-                                        unsigned int* counter) {
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) partial[k * gridDim.x + blockIdx.x] = vals[k];
-        __threadfence();
-        unsigned int t = atomicAdd(counter, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
-// In the last block: fixed-order sum of partial[k*nblocks ...].
-__device__ inline double sum_partials(const double* partial, int k, double* lds) {
-    double s = 0.0;
-    for (unsigned int i = threadIdx.x; i < gridDim.x; i += blockDim.x)
-        s += __builtin_nontemporal_load(&partial[k * gridDim.x + i]);
-    return block_sum256(s, lds);
-}
-
-__device__ inline double min_partials(const double* partial, int k, double* lds) {
-    double s = __builtin_huge_val();
-    for (unsigned int i = threadIdx.x; i < gridDim.x; i += blockDim.x)
-        s = fmin(s, __builtin_nontemporal_load(&partial[k * gridDim.x + i]));
-    return block_min256(s, lds);
 }
 
 }  // namespace mifvm

@@ -119,8 +119,12 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Dev d, const double* __restrict_
     d.b[i] = -d.vol[i] * f[i] + d.k_c[i];
 }
 
-// r = b - K x; z = D^-1 r; p = z; rz, rr, bb.  Opens (or reopens) the loop.
-__global__ __launch_bounds__(kBlock) void k_cg_setup(Dev d, double tol, int maxit, int reset_it) {
+// Each CG kernel returns at once when the solve has finished (SC_DONE != 0),
+// so a chunk of enqueued iterations past convergence costs only launches.
+__device__ inline bool cg_done(const Dev& d) { return d.scal[SC_DONE] != 0.0; }
+
+// r = b - K x; z = D^-1 r; p = z; partial rz, rr, bb.  (Re)opens the loop.
+__global__ __launch_bounds__(kBlock) void k_cg_setup(Dev d) {
     __shared__ double lds[4];
     const int64_t i = gtid_s();
     double rz = 0.0, rr = 0.0, bb = 0.0;
@@ -135,54 +139,95 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(Dev d, double tol, int maxi
         rr = ri * ri;
         bb = bi * bi;
     }
-    const double v[3] = {block_sum256(rz, lds), block_sum256(rr, lds), block_sum256(bb, lds)};
-    if (publish_partials<3>(v, d.partial, d.counter)) {
-        const double trz = sum_partials(d.partial, 0, lds);
-        const double trr = sum_partials(d.partial, 1, lds);
-        const double tbb = sum_partials(d.partial, 2, lds);
-        if (threadIdx.x == 0) {
-            double* sc = d.scal;
-            sc[SC_RZ] = trz;
-            sc[SC_RR] = trr;
-            sc[SC_TRUE_RR] = trr;
-            sc[SC_BB] = tbb;
-            if (reset_it) {           // fresh solve; a reopen keeps tol, maxit, count
-                sc[SC_TOL2BB] = tol * tol * tbb;
-                sc[SC_MAXIT] = double(maxit);
-                sc[SC_IT] = 0.0;
-            }
-            sc[SC_DONE] = trr <= sc[SC_TOL2BB] ? 1.0 : (sc[SC_IT] >= sc[SC_MAXIT] ? 2.0 : 0.0);
-            *d.counter = 0u;
-        }
+    rz = block_sum256(rz, lds);
+    rr = block_sum256(rr, lds);
+    bb = block_sum256(bb, lds);
+    if (threadIdx.x == 0) {
+        d.partial[blockIdx.x] = rz;
+        d.partial[gridDim.x + blockIdx.x] = rr;
+        d.partial[2 * gridDim.x + blockIdx.x] = bb;
     }
 }
 
-// q = K p; alpha = rz / (p . q)
+// fresh != 0: a new solve (sets tolerance, limits, count); otherwise a reopen
+// after a true-residual check or a restart keeps them.
+__global__ __launch_bounds__(1024) void k_cg_setup_fin(Dev d, int64_t nparts, double tol, int maxit,
+                                                       int restart, int fresh) {
+    __shared__ double lds[16];
+    const double trz = reduce_partials_sum(d.partial, nparts, lds);
+    const double trr = reduce_partials_sum(d.partial + nparts, nparts, lds);
+    const double tbb = reduce_partials_sum(d.partial + 2 * nparts, nparts, lds);
+    if (threadIdx.x == 0) {
+        double* sc = d.scal;
+        sc[SC_RZ] = trz;
+        sc[SC_RR] = trr;
+        sc[SC_TRUE_RR] = trr;
+        sc[SC_BB] = tbb;
+        if (fresh) {
+            sc[SC_TOL2BB] = tol * tol * tbb;
+            sc[SC_MAXIT] = double(maxit);
+            sc[SC_RESTART] = double(restart);
+            sc[SC_IT] = 0.0;
+        }
+        sc[SC_SINCE] = 0.0;
+        sc[SC_DONE] = trr <= sc[SC_TOL2BB] ? 1.0 : (sc[SC_IT] >= sc[SC_MAXIT] ? 2.0 : 0.0);
+    }
+}
+
+// q = K p; partial p . q.  One block per cell tile: the tile's halo of p is
+// staged in LDS (ghost halo entries are not unknowns and read as 0) and the
+// rows address it with 16-bit local indices; the same entries in the same
+// order as spmv_row, so the result is bitwise the same.
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(Dev d) {
+    extern __shared__ double sp[];                   // [halo] p
     __shared__ double lds[4];
-    if (d.scal[SC_DONE] != 0.0) return;
-    const int64_t i = gtid_s();
-    double pq = 0.0;
-    if (i < d.nc) {
-        const double qi = spmv_row(d, d.p, i);
-        d.q[i] = qi;
-        pq = d.p[i] * qi;
+    if (cg_done(d)) return;
+    const int64_t nc = d.nc;
+    const int64_t t = blockIdx.x;
+    const int T = blockDim.x;
+    const int64_t h0 = d.h_off[t];
+    const int hn = int(d.h_off[t + 1] - h0);
+    const double* __restrict__ p = d.p;
+    for (int h = threadIdx.x; h < hn; h += T) {
+        const int e = d.h_idx[h0 + h];
+        sp[h] = e < nc ? p[e] : 0.0;
     }
-    const double v[1] = {block_sum256(pq, lds)};
-    if (publish_partials<1>(v, d.partial, d.counter)) {
-        const double t = sum_partials(d.partial, 0, lds);
-        if (threadIdx.x == 0) {
-            d.scal[SC_PQ] = t;
-            d.scal[SC_ALPHA] = d.scal[SC_RZ] / t;
-            *d.counter = 0u;
+    __syncthreads();
+    const int64_t i = t * T + threadIdx.x;
+    double pq = 0.0;
+    if (i < nc) {
+        const double pi = sp[d.h_self[t] + threadIdx.x];
+        const int64_t s = i >> 6;
+        const int64_t base = d.k_off[s] + (i & 63);
+        const int w = d.k_w[s];
+        double y = d.k_diag[i] * pi;
+#pragma unroll 4
+        for (int k = 0; k < w; ++k) {
+            const int64_t at = base + int64_t(k) * 64;
+            y += d.k_val[at] * sp[d.k_lidx[at]];
         }
+        d.q[i] = y;
+        pq = pi * y;
+    }
+    pq = block_sum_upto256(pq, lds);
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = pq;
+}
+
+// alpha = rz / (p . q)
+__global__ __launch_bounds__(1024) void k_cg_alpha(Dev d, int64_t nparts) {
+    __shared__ double lds[16];
+    if (cg_done(d)) return;
+    const double pq = reduce_partials_sum(d.partial, nparts, lds);
+    if (threadIdx.x == 0) {
+        d.scal[SC_PQ] = pq;
+        d.scal[SC_ALPHA] = d.scal[SC_RZ] / pq;
     }
 }
 
-// x += alpha p; r -= alpha q; z = D^-1 r; beta = rz_new / rz; convergence test
+// x += alpha p; r -= alpha q; z = D^-1 r; partial rz, rr
 __global__ __launch_bounds__(kBlock) void k_cg_axpy(Dev d) {
     __shared__ double lds[4];
-    if (d.scal[SC_DONE] != 0.0) return;
+    if (cg_done(d)) return;
     const double alpha = d.scal[SC_ALPHA];
     const int64_t i = gtid_s();
     double rz = 0.0, rr = 0.0;
@@ -195,26 +240,37 @@ __global__ __launch_bounds__(kBlock) void k_cg_axpy(Dev d) {
         rz = ri * zi;
         rr = ri * ri;
     }
-    const double v[2] = {block_sum256(rz, lds), block_sum256(rr, lds)};
-    if (publish_partials<2>(v, d.partial, d.counter)) {
-        const double trz = sum_partials(d.partial, 0, lds);
-        const double trr = sum_partials(d.partial, 1, lds);
-        if (threadIdx.x == 0) {
-            double* sc = d.scal;
-            sc[SC_BETA] = trz / sc[SC_RZ];
-            sc[SC_RZ] = trz;
-            sc[SC_RR] = trr;
-            sc[SC_IT] = sc[SC_IT] + 1.0;
-            if (trr <= sc[SC_TOL2BB]) sc[SC_DONE] = 1.0;
-            else if (sc[SC_IT] >= sc[SC_MAXIT]) sc[SC_DONE] = 2.0;
-            *d.counter = 0u;
-        }
+    rz = block_sum256(rz, lds);
+    rr = block_sum256(rr, lds);
+    if (threadIdx.x == 0) {
+        d.partial[blockIdx.x] = rz;
+        d.partial[gridDim.x + blockIdx.x] = rr;
+    }
+}
+
+// beta = rz_new / rz; count; convergence (1), iteration limit (2) or a
+// scheduled restart (3) ends the enqueued chunk.
+__global__ __launch_bounds__(1024) void k_cg_beta(Dev d, int64_t nparts) {
+    __shared__ double lds[16];
+    if (cg_done(d)) return;
+    const double trz = reduce_partials_sum(d.partial, nparts, lds);
+    const double trr = reduce_partials_sum(d.partial + nparts, nparts, lds);
+    if (threadIdx.x == 0) {
+        double* sc = d.scal;
+        sc[SC_BETA] = trz / sc[SC_RZ];
+        sc[SC_RZ] = trz;
+        sc[SC_RR] = trr;
+        sc[SC_IT] = sc[SC_IT] + 1.0;
+        sc[SC_SINCE] = sc[SC_SINCE] + 1.0;
+        if (trr <= sc[SC_TOL2BB]) sc[SC_DONE] = 1.0;
+        else if (sc[SC_IT] >= sc[SC_MAXIT]) sc[SC_DONE] = 2.0;
+        else if (sc[SC_RESTART] > 0.0 && sc[SC_SINCE] >= sc[SC_RESTART]) sc[SC_DONE] = 3.0;
     }
 }
 
 // p = z + beta p
 __global__ __launch_bounds__(kBlock) void k_cg_dir(Dev d) {
-    if (d.scal[SC_DONE] != 0.0) return;
+    if (cg_done(d)) return;
     const double beta = d.scal[SC_BETA];
     const int64_t i = gtid_s();
     if (i >= d.nc) return;
@@ -238,26 +294,25 @@ hipError_t launch_rhs(const Dev& d, const double* f, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_cg_setup(const Dev& d, int nblk, double tol, int maxit, hipStream_t s) {
-    (void)nblk;
-    hipLaunchKernelGGL(k_cg_setup, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d, tol, maxit, 1);
-    return hipGetLastError();
-}
-
-hipError_t launch_true_residual(const Dev& d, int nblk, hipStream_t s) {
-    (void)nblk;
-    // reopen without resetting the iteration count; tol/maxit are reused
-    hipLaunchKernelGGL(k_cg_setup, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d, -1.0, -1, 0);
+hipError_t launch_cg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s) {
+    const int nb = grid_rows(d.nc);
+    hipLaunchKernelGGL(k_cg_setup, dim3(nb), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_cg_setup_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb), tol, maxit, restart,
+                       fresh ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_spmv(const Dev& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_spmv, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_cg_spmv, dim3(unsigned(d.ntiles)), dim3(d.tile_rows),
+                       size_t(d.halo_max) * sizeof(double), s, d);
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, d, d.ntiles);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_axpy(const Dev& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_axpy, dim3(grid_rows(d.nc)), dim3(kBlock), 0, s, d);
+    const int nb = grid_rows(d.nc);
+    hipLaunchKernelGGL(k_cg_axpy, dim3(nb), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, d, int64_t(nb));
     return hipGetLastError();
 }
 

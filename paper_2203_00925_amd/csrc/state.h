@@ -41,6 +41,11 @@ struct Dev {
     // Poisson pattern and values
     int64_t* k_off; int32_t* k_w; int32_t* k_col; int32_t* k_len;
     double *k_val, *k_diag, *k_dinv, *k_c;
+    // LDS tiles: tile_rows consecutive cells and their halo
+    int32_t tile_rows, halo_max;
+    int64_t ntiles;
+    int64_t* h_off; int32_t* h_idx; int32_t* h_self;
+    uint16_t *s_lidx, *k_lidx, *c2n_l;
     // renumbering
     int32_t *cell_perm, *vert_perm;       // internal -> user
     // fields
@@ -49,9 +54,8 @@ struct Dev {
     // solver vectors (P lives in x)
     double *x, *r, *z, *p, *q, *b;
     double* tmp;                          // nc+nb scratch (permutation, residual)
-    double* partial;                      // reduction partials (2 per block)
+    double* partial;                      // reduction partials ([k][block], k < 4)
     double* scal;                         // solver scalars (see solve_kernels)
-    uint32_t* counter;                    // last-block counters (self-resetting)
 };
 
 constexpr int kNumKernels = 11;
@@ -100,16 +104,15 @@ hipError_t launch_conservation(const Dev& d, int nblk, hipStream_t s);
 hipError_t launch_assemble(const Dev& d, const BcTable& bc, int row_max, hipStream_t s);
 hipError_t launch_spmv_plain(const Dev& d, const double* x, double* y, hipStream_t s);
 hipError_t launch_rhs(const Dev& d, const double* f_internal, hipStream_t s);
-hipError_t launch_cg_setup(const Dev& d, int nblk, double tol, int maxit, hipStream_t s);
+hipError_t launch_cg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s);
 hipError_t launch_cg_spmv(const Dev& d, hipStream_t s);
 hipError_t launch_cg_axpy(const Dev& d, hipStream_t s);
 hipError_t launch_cg_dir(const Dev& d, hipStream_t s);
-hipError_t launch_true_residual(const Dev& d, int nblk, hipStream_t s);
 
 // scalar slots in Dev::scal
 enum Scal {
     SC_RZ = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_BB, SC_TOL2BB, SC_DONE, SC_IT, SC_MAXIT,
-    SC_TRUE_RR, SC_CONS, SC_DT_INV, SC_COUNT_ = 16
+    SC_TRUE_RR, SC_CONS, SC_DT_INV, SC_RESTART, SC_SINCE, SC_COUNT_ = 16
 };
 
 }  // namespace mifvm
