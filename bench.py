@@ -30,6 +30,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FV cell-updates/s + Poisson solve ms @1e-10 rel; plain vs mixed/learned"
+
+# HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE + WRITE_SIZE on the
+# cube120 workload, scaled by a known-size copy (profiles/all_kernels_cube120_
+# hbm_traffic.md).  Valid only for the kernel sources they were taken on: the
+# bench reports them when the sources still hash to `src`, else null.
+MEASURED_TRAFFIC = {
+    "cube120": {"src": "7c50cf207300467d",
+                "bytes": {"k_grad_limiter": 7057313400, "k_face_flux": 3292082502,
+                          "k_update": 923862782, "k_cg_spmv": 8384813319,
+                          "k_cg_axpy": 666175430, "k_cg_dir": 248850625}},
+}
+
+
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2203_00925_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "cube120": dict(n=120, seed=2),
@@ -42,24 +64,28 @@ def log(msg):
 
 
 def algorithmic_bytes(info):
-    """Bytes each kernel must move once per launch (every stored array read or
-    written once; gathered neighbour values counted once per array)."""
+    """Bytes each kernel must move per launch: every stored array it reads or
+    writes counted once (gathered neighbour data counted once per array, not
+    once per reference; padding of the 64-row slices not counted)."""
     nc, nf, nb, nv = info.nc, info.nf, info.nb, info.nv
     offdiag = info.matrix_nnz - nc
+    halo = info.halo_entries
     return {
-        # stencil idx 4/entry; per cell: M^-1 48, centre 24, u 8, c2f 16, c2n 16,
-        # grad 24 + psi 8 written; face centroids 24/face; ghost centre+u 32
-        "grad_limiter": info.stencil_entries * 4 + nc * (48 + 24 + 8 + 16 + 16 + 24 + 8)
-        + nf * 24 + nb * 32,
-        # idx 4 + alpha 8 per entry, u gathered once, u_node written
-        "node_interp": info.node_entries * 12 + (nc + nb) * 8 + nv * 8,
+        # 16-bit local stencil index per entry; tile halo list 4/entity;
+        # x, y, z, u of cells and ghosts 32; per cell M^-1 48, c2f 16,
+        # local face neighbours 8, grad + psi written 32; face centroids 24/face;
+        # vertex values: weight 8 + 16-bit local index 2 per entry, value written 8
+        "grad_limiter": info.stencil_entries * 2 + halo * 4 + (nc + nb) * 32
+        + nc * (48 + 16 + 8 + 32) + nf * 24 + info.node_entries * 10 + nv * 8,
         # per face: L,R,A,B,C 20 + kAC,kBC,kRL,phi 32 + centroid 24 + F 8;
-        # per cell gathered once: u, grad, psi, centre 64; vertex values 8
+        # per cell (gathered): u, grad, psi, centre 64; vertex values 8
         "face_flux": nf * 84 + nc * 64 + nv * 8,
-        # per cell: c2f 16, F gathered 16, vol 8, src 8, u^n 8, u 8 written
+        # per cell: c2f 16, F 16 (each face read by its 2 cells), vol 8,
+        # src 8, u^n 8, u written 8
         "update": nc * (16 + 16 + 8 + 8 + 8 + 8),
-        # off-diagonal val 8 + col 4; per row diag 8, p 8, q 8 written
-        "cg_spmv": offdiag * 12 + nc * 24,
+        # value 8 + 16-bit local index 2 per off-diagonal entry; tile halo
+        # list 4/entity; p 8, diagonal 8, q written 8 per row
+        "cg_spmv": offdiag * 10 + halo * 4 + nc * 24,
         # x,p,r,q,dinv read 40; x,r,z written 24
         "cg_axpy": nc * 64,
         # z,p read, p written
@@ -109,6 +135,9 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cube120")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy-gb", type=float, default=0.0,
+                    help="first run one device-to-device copy of this many GB (a kernel of "
+                         "known traffic, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the method's "
@@ -125,6 +154,14 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(3)
     torch.cuda.set_device(0)
+    if args.calibrate_copy_gb > 0:
+        n = int(args.calibrate_copy_gb * 1e9 / 8)
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {n * 8} bytes read, {n * 8} bytes written")
+        del a, b
     wl = WORKLOADS[args.workload]
     t = time.perf_counter()
     mesh = synth.jittered_cube(wl["n"], wl["seed"])
@@ -182,14 +219,19 @@ def main():
     value = info.nc * args.steps / fv_total_s
     nbytes = algorithmic_bytes(info)
 
+    measured = MEASURED_TRAFFIC.get(args.workload)
+    traffic_ok = measured is not None and measured["src"] == kernel_source_hash()
+
     def roof(name):
         ms, n = kstats[name]
         avg_s = ms / max(n, 1) / 1e3
         gbs = nbytes[name] / avg_s / 1e9
+        traffic = measured["bytes"].get(f"k_{name}") if traffic_ok else None
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"k_{name}",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": f"k_{name}",
                 "avg_us": round(avg_s * 1e6, 2), "launches": n,
-                "bytes_per_launch": nbytes[name]}
+                "bytes_per_launch": nbytes[name],
+                "traffic_GBps": round(traffic / avg_s / 1e9, 1) if traffic else None}
 
     iters = [s["iterations"] for s in solves]
     result = {
@@ -216,7 +258,7 @@ def main():
         "poisson_rel_residual": max(s["rel_residual"] for s in solves),
         "conservation_rel_drift": abs(total1 - total0) / abs(total0),
         "roofline": roof("cg_spmv"),
-        "roofline_fv": {k: roof(k) for k in ("grad_limiter", "node_interp", "face_flux", "update")},
+        "roofline_fv": {k: roof(k) for k in ("grad_limiter", "face_flux", "update")},
         "roofline_cg": {k: roof(k) for k in ("cg_axpy", "cg_dir")},
     }
     if not args.no_cpu_baseline:

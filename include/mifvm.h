@@ -96,7 +96,10 @@ typedef struct {
     int32_t stencil_max;       /* longest node-neighbour list                 */
     int32_t node_max;          /* longest vertex list                         */
     int32_t row_max;           /* longest off-diagonal matrix row             */
+    int32_t tile_rows;         /* cells per LDS tile (256, 128 or 64)         */
+    int32_t halo_max;          /* largest tile halo (cells + ghosts)          */
     int32_t pad_;
+    int64_t halo_entries;      /* sum of tile halo sizes                      */
     size_t ws_bytes;           /* device workspace needed by a state          */
 } mifvm_mesh_info;
 
@@ -224,7 +227,8 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
  * enable != 0 starts recording an event pair around every kernel launch of
  * this state and clears the totals; enable == 0 stops.  Kernel ids: */
 enum mifvm_kernel {
-    MIFVM_K_GHOST_FILL = 0, MIFVM_K_GRAD_LIMITER = 1, MIFVM_K_NODE_INTERP = 2,
+    MIFVM_K_GHOST_FILL = 0, MIFVM_K_GRAD_LIMITER = 1 /* incl. vertex values */,
+    MIFVM_K_NODE_INTERP = 2 /* reserved: computed inside GRAD_LIMITER, never launched */,
     MIFVM_K_FACE_FLUX = 3, MIFVM_K_UPDATE = 4, MIFVM_K_CG_SETUP = 5, MIFVM_K_CG_SPMV = 6,
     MIFVM_K_CG_AXPY = 7, MIFVM_K_CG_DIR = 8, MIFVM_K_RHS = 9, MIFVM_K_ASSEMBLE = 10,
     MIFVM_K_COUNT = 11

@@ -144,6 +144,8 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.s_lidx = carve<uint16_t>(base, off, m.s_lidx.size());
     d.k_lidx = carve<uint16_t>(base, off, m.k_lidx.size());
     d.c2n_l = carve<uint16_t>(base, off, m.c2n_l.size());
+    d.n_lidx = carve<uint16_t>(base, off, m.n_lidx.size());
+    d.v_off = carve<int64_t>(base, off, m.v_off.size());
     d.cell_perm = carve<int32_t>(base, off, nc);
     d.vert_perm = carve<int32_t>(base, off, nv);
     d.u = carve<double>(base, off, NX);
@@ -213,6 +215,9 @@ int mifvm_mesh_get_info(const mifvm_mesh* mesh, mifvm_mesh_info* out) {
     out->stencil_max = m.stencil_max;
     out->node_max = m.node_max;
     out->row_max = m.row_max;
+    out->tile_rows = m.tile_rows;
+    out->halo_max = m.halo_max;
+    out->halo_entries = (int64_t)m.h_idx.size();
     Dev d{};
     out->ws_bytes = layout(m, nullptr, d);
     return MIFVM_OK;
@@ -303,6 +308,7 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     UP(d.cell_perm, m.cell_perm); UP(d.vert_perm, m.vert_perm);
     UP(d.h_off, m.h_off); UP(d.h_idx, m.h_idx); UP(d.h_self, m.h_self);
     UP(d.s_lidx, m.s_lidx); UP(d.k_lidx, m.k_lidx); UP(d.c2n_l, m.c2n_l);
+    UP(d.n_lidx, m.n_lidx); UP(d.v_off, m.v_off);
 #undef UP
     const int64_t NX = m.nc + m.nb;
     e = hipMemsetAsync(d.u, 0, NX * sizeof(double), s);
@@ -423,13 +429,12 @@ int mifvm_cfl_dt(mifvm_state* st, double cfl, double* dt_out, void* stream) {
 }
 
 namespace {
-// ghost fill, gradient + limiter, vertex values, face fluxes
+// ghost fill, gradient + limiter + vertex values, face fluxes
 int residual_parts(State& s, hipStream_t hs) {
     const Dev& d = s.d;
     KernelTimer& t = s.timer;
     HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, d.u, s.bc[0], hs); }));
     HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, hs); }));
-    HIPCHK(timed(t, MIFVM_K_NODE_INTERP, hs, [&] { return launch_node_interp(d, hs); }));
     HIPCHK(timed(t, MIFVM_K_FACE_FLUX, hs, [&] { return launch_face_flux(d, s.bc[0], s.diffusivity, hs); }));
     return MIFVM_OK;
 }

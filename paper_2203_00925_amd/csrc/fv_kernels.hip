@@ -1,12 +1,13 @@
 // Kernels of the explicit finite-volume residual (eq. (4) of the paper) and
 // its Runge-Kutta update (eq. (6)), for CDNA4 wave64.
 //
-// One residual evaluation is four gather kernels, each owner-computes and
+// One residual evaluation is three gather kernels, each owner-computes and
 // free of atomics:
 //   k_grad_limiter  per cell: least-squares gradient over the node-neighbour
 //                   stencil (Algorithm 1), then the Barth-Jespersen limiter
 //                   over the 4 face neighbours;
-//   k_node_interp   per vertex: least-squares interpolation (Algorithm 2);
+//                   the same kernel computes the vertex values of the
+//                   least-squares interpolation (Algorithm 2);
 //   k_face_flux     per face: MUSCL upwind convective flux (eq. (15)) minus
 //                   the diamond diffusive flux (eq. (diamond)), written once;
 //   k_update        per cell: gathers its 4 face fluxes with their signs.
@@ -47,7 +48,9 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(int64_t nc, int64_t nb,
 // ghost its stencils reference) is staged in LDS as (x, y, z, u) records, so
 // the ~70 neighbour reads per cell are LDS reads addressed by 16-bit local
 // indices; global memory sees one gather per halo entity and the streamed
-// local index list.
+// local index list.  The same halo holds the cell/ghost list of every vertex
+// owned by the tile, so the vertex values of Algorithm 2 are computed here
+// too (u_v = sum alpha u_c, entries in the same order as the vertex list).
 __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d) {
     extern __shared__ double4 sm[];                  // [halo] x, y, z, u
     const int64_t nc = d.nc, NX = d.nc + d.nb, nf = d.nf;
@@ -64,6 +67,16 @@ __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d) {
         sm[h] = make_double4(X[e], Y[e], Z[e], u[e]);
     }
     __syncthreads();
+    for (int64_t v = d.v_off[t] + threadIdx.x; v < d.v_off[t + 1]; v += T) {
+        const int64_t vb = d.n_off[v >> 6] + (v & 63);
+        const int vw = d.n_w[v >> 6];
+        double acc = 0.0;
+        for (int k = 0; k < vw; ++k) {
+            const int64_t at = vb + int64_t(k) * 64;
+            acc += d.n_alpha[at] * sm[d.n_lidx[at]].w;
+        }
+        d.unode[v] = acc;
+    }
     const int64_t i = t * T + threadIdx.x;
     if (i >= nc) return;
     const double4 me = sm[d.h_self[t] + threadIdx.x];
@@ -110,21 +123,6 @@ __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d) {
         psi = fmin(psi, ph);
     }
     d.psi[i] = psi;
-}
-
-__global__ __launch_bounds__(kBlock) void k_node_interp(Dev d) {
-    const int64_t v = gtid();
-    if (v >= d.nv) return;
-    const int64_t s = v >> 6;
-    const int64_t base = d.n_off[s] + (v & 63);
-    const int w = d.n_w[s];
-    const double* __restrict__ u = d.u;
-    double acc = 0.0;
-    for (int k = 0; k < w; ++k) {
-        const int64_t at = base + int64_t(k) * 64;
-        acc += d.n_alpha[at] * u[d.n_idx[at]];
-    }
-    d.unode[v] = acc;
 }
 
 __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, BcTable bc, double D) {
@@ -277,11 +275,6 @@ hipError_t launch_ghost_fill(const Dev& d, double* u, const BcTable& bc, hipStre
 hipError_t launch_grad_limiter(const Dev& d, hipStream_t s) {
     hipLaunchKernelGGL(k_grad_limiter, dim3(unsigned(d.ntiles)), dim3(d.tile_rows),
                        size_t(d.halo_max) * sizeof(double4), s, d);
-    return hipGetLastError();
-}
-
-hipError_t launch_node_interp(const Dev& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_node_interp, dim3(grid_for(d.nv)), dim3(kBlock), 0, s, d);
     return hipGetLastError();
 }
 

@@ -518,7 +518,15 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     }
     if (M.halo_max > kHaloCap) { err = "stencil neighbourhood too large for the LDS tile"; return E_MESH; }
     mark("tile halos");
+    // vertices of each tile (vertices are ordered by their lowest cell)
+    {
+        const int64_t nt = (int64_t)M.h_self.size();
+        M.v_off.assign(nt + 1, 0);
+        for (int64_t v = 0; v < nv; ++v) M.v_off[vmin[vnew2old[v]] / M.tile_rows + 1]++;
+        for (int64_t t = 0; t < nt; ++t) M.v_off[t + 1] += M.v_off[t];
+    }
     // global -> local through a dense map filled for one tile at a time
+    M.n_lidx.assign(M.node.idx.size(), 0);
     M.s_lidx.assign(M.stencil.idx.size(), 0);
     M.k_lidx.assign(M.kmat.idx.size(), 0);
     M.c2n_l.assign(4 * nc, 0);
@@ -541,6 +549,16 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
                     M.k_lidx[at] = (uint16_t)g2l[M.kmat.idx[at]];
                 }
                 for (int k = 0; k < 4; ++k) M.c2n_l[k * nc + r] = (uint16_t)g2l[M.c2n[k * nc + r]];
+            }
+            for (int64_t v = M.v_off[t]; v < M.v_off[t + 1]; ++v) {
+                const int64_t sl = v >> 6;
+                const int lane = int(v & 63);
+                for (int64_t k = 0; k < M.node.width[sl]; ++k) {
+                    const int64_t at = M.node.off[sl] + k * 64 + lane;
+                    const int32_t l = g2l[M.node.idx[at]];
+                    if (l < 0) { err = "internal error: vertex list outside its tile halo"; return E_MESH; }
+                    M.n_lidx[at] = (uint16_t)l;
+                }
             }
             for (int64_t h = M.h_off[t]; h < M.h_off[t + 1]; ++h) g2l[M.h_idx[h]] = -1;
         }

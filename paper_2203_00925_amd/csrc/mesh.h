@@ -59,6 +59,11 @@ struct Mesh {
     std::vector<uint16_t> s_lidx;     // like stencil.idx, local
     std::vector<uint16_t> k_lidx;     // like kmat.idx, local
     std::vector<uint16_t> c2n_l;      // 4 x nc local index of the face neighbour
+    // vertices are numbered by their lowest cell, so the vertices of tile t
+    // (those whose lowest cell lies in it) are [v_off[t], v_off[t+1]); their
+    // cell/ghost lists lie inside the tile's halo
+    std::vector<int64_t> v_off;       // ntiles + 1
+    std::vector<uint16_t> n_lidx;     // like node.idx, local to the owning tile
 };
 
 // Returns 0 or a negative mifvm status; err receives a message.

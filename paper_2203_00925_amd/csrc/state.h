@@ -45,7 +45,8 @@ struct Dev {
     int32_t tile_rows, halo_max;
     int64_t ntiles;
     int64_t* h_off; int32_t* h_idx; int32_t* h_self;
-    uint16_t *s_lidx, *k_lidx, *c2n_l;
+    uint16_t *s_lidx, *k_lidx, *c2n_l, *n_lidx;
+    int64_t* v_off;
     // renumbering
     int32_t *cell_perm, *vert_perm;       // internal -> user
     // fields
@@ -88,7 +89,6 @@ size_t layout(const Mesh& m, char* base, Dev& d);
 // launchers (fv_kernels.hip)
 hipError_t launch_ghost_fill(const Dev& d, double* u, const BcTable& bc, hipStream_t s);
 hipError_t launch_grad_limiter(const Dev& d, hipStream_t s);
-hipError_t launch_node_interp(const Dev& d, hipStream_t s);
 hipError_t launch_face_flux(const Dev& d, const BcTable& bc, double D, hipStream_t s);
 hipError_t launch_update(const Dev& d, double a_dt, bool first_stage, hipStream_t s);
 hipError_t launch_residual_out(const Dev& d, double* res_internal, hipStream_t s);
