@@ -105,7 +105,15 @@ typedef struct {
 
 typedef struct {
     double diffusivity;        /* D of eq. (1)                                */
+    int32_t precision;         /* enum mifvm_precision                        */
+    int32_t pad_;
 } mifvm_params;
+
+/* FP64: the step in FP64.  FP32: the reduced-precision form - state,
+ * gradients, limiter, vertex values, fluxes and the geometry they read in
+ * FP32 (positions relative to a nearby cell); the CFL bound and the
+ * conservation sum stay FP64.  Fields cross the ABI as FP64 either way.    */
+enum mifvm_precision { MIFVM_FP64 = 0, MIFVM_FP32 = 1 };
 
 typedef struct {
     double tol;                /* relative true residual ||b-Kx||/||b||       */
@@ -117,14 +125,24 @@ typedef struct {
     int32_t history_cap;       /* capacity of history (0 = none)              */
     double* history;           /* host, optional: recurrence ||r||/||b|| at
                                   every host check                           */
+    int32_t method;            /* enum mifvm_solve_method                     */
+    int32_t pad_;
+    double inner_tol;          /* IR_FP32: relative reduction asked of each
+                                  FP32 inner solve (0 = 1e-4)                */
 } mifvm_solve_opts;
+
+/* PLAIN: FP64 Jacobi-CG.  IR_FP32: iterative refinement - the FP64 true
+ * residual r = b - K x, an FP32 Jacobi-CG solve of K d = r on an FP32 copy of
+ * K (dot products accumulated in FP64), x += d in FP64 - repeated until the
+ * FP64 true residual meets tol.                                            */
+enum mifvm_solve_method { MIFVM_SOLVE_PLAIN = 0, MIFVM_SOLVE_IR_FP32 = 1 };
 
 typedef struct {
     int32_t iterations;
     int32_t restarts;          /* times the loop was reopened from the true
                                   residual without having converged           */
     int32_t history_len;       /* entries written to opts->history            */
-    int32_t pad_;
+    int32_t outer;             /* IR_FP32: refinement steps                   */
     double rel_residual;       /* final true relative residual (FP64)        */
     double ms;                 /* wall time of the solve call                */
 } mifvm_solve_info;
@@ -217,8 +235,9 @@ int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* str
  * solve: warm start) and stores the result back in P.  Converged when the
  * recomputed FP64 true residual ||b - K x||_2 <= tol ||b||_2.  opts NULL =
  * tol 1e-10, maxit 20000, chunk 32, restart 500.  A restart
- * recomputes r = b - K x and sets p = D^-1 r.  Returns NOT_CONVERGED at
- * maxit.
+ * recomputes r = b - K x and sets p = D^-1 r.  With method IR_FP32,
+ * `iterations` counts FP32 inner iterations and every outer step restarts
+ * the inner CG.  Returns NOT_CONVERGED at maxit.
  * Synchronises (once per chunk).                                           */
 int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_opts* opts,
                         mifvm_solve_info* info, void* stream);

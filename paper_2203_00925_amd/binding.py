@@ -21,6 +21,8 @@ ZERO_FLUX, NEUMANN, DIRICHLET = 0, 1, 2
 VAR_SCALAR, VAR_POTENTIAL = 0, 1
 FIELD_U, FIELD_VEL, FIELD_SOURCE, FIELD_P = 0, 1, 2, 3
 RENUMBER_NONE, RENUMBER_MORTON = 0, 1
+SOLVE_PLAIN, SOLVE_IR_FP32 = 0, 1
+FP64, FP32 = 0, 1
 KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
            "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble")
 
@@ -67,18 +69,19 @@ class MeshInfo(C.Structure):
 
 
 class _Params(C.Structure):
-    _fields_ = [("diffusivity", C.c_double)]
+    _fields_ = [("diffusivity", C.c_double), ("precision", C.c_int32), ("pad_", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("chunk", C.c_int32),
                 ("restart", C.c_int32), ("history_cap", C.c_int32),
-                ("history", C.POINTER(C.c_double))]
+                ("history", C.POINTER(C.c_double)), ("method", C.c_int32),
+                ("pad_", C.c_int32), ("inner_tol", C.c_double)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32),
-                ("history_len", C.c_int32), ("pad_", C.c_int32),
+                ("history_len", C.c_int32), ("outer", C.c_int32),
                 ("rel_residual", C.c_double), ("ms", C.c_double)]
 
 
@@ -183,7 +186,7 @@ class State:
     """Device-resident mesh and fields (mifvm_state_create); the workspace is
     a torch uint8 tensor on the current device."""
 
-    def __init__(self, mesh: Mesh, diffusivity=0.0, device="cuda", stream=None):
+    def __init__(self, mesh: Mesh, diffusivity=0.0, device="cuda", stream=None, precision=FP64):
         import torch
         self.mesh = mesh
         nbytes = int(mesh.info.ws_bytes)
@@ -191,7 +194,7 @@ class State:
         base = self.ws.data_ptr()
         self._off = (-base) % 256
         h = C.c_void_p()
-        params = _Params(float(diffusivity))
+        params = _Params(float(diffusivity), int(precision), 0)
         _check(_lib.mifvm_state_create(mesh._h, C.byref(params), C.c_void_p(base + self._off),
                                        nbytes, _stream(stream), C.byref(h)))
         self._h = h
@@ -275,18 +278,20 @@ class State:
         return y
 
     def poisson_solve(self, f=None, tol=1e-10, maxit=20000, chunk=32, restart=500,
-                      history=0, stream=None, allow_not_converged=False):
+                      history=0, method=SOLVE_PLAIN, inner_tol=1e-4, stream=None,
+                      allow_not_converged=False):
         import torch
         if f is not None:
             f = f.to(device=self.device, dtype=torch.float64).contiguous()
         hist = (C.c_double * max(int(history), 1))()
-        opts = SolveOpts(float(tol), int(maxit), int(chunk), int(restart), int(history), hist)
+        opts = SolveOpts(float(tol), int(maxit), int(chunk), int(restart), int(history), hist,
+                         int(method), 0, float(inner_tol))
         info = SolveInfo()
         allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
         rc = _check(_lib.mifvm_poisson_solve(self._h, _ptr(f), C.byref(opts), C.byref(info),
                                              _stream(stream)), allow)
         return dict(status=rc, iterations=info.iterations, restarts=info.restarts,
-                    rel_residual=info.rel_residual, ms=info.ms,
+                    outer=info.outer, rel_residual=info.rel_residual, ms=info.ms,
                     history=list(hist[:info.history_len]))
 
     # -- per-kernel timing ----------------------------------------------------------

@@ -104,6 +104,8 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.vol = carve<double>(base, off, nc);
     d.xc = carve<double>(base, off, 3 * NX);
     d.minv = carve<double>(base, off, 6 * nc);
+    d.xyz4 = carve<double4>(base, off, NX);
+    d.fx4 = carve<double4>(base, off, nf);
     d.c2f = carve<int32_t>(base, off, 4 * nc);
     d.c2n = carve<int32_t>(base, off, 4 * nc);
     d.s_off = carve<int64_t>(base, off, m.stencil.off.size());
@@ -135,6 +137,14 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.k_diag = carve<double>(base, off, nc);
     d.k_dinv = carve<double>(base, off, nc);
     d.k_c = carve<double>(base, off, nc);
+    d.k_val32 = carve<float>(base, off, m.kmat.idx.size());
+    d.k_diag32 = carve<float>(base, off, nc);
+    d.k_dinv32 = carve<float>(base, off, nc);
+    d.d32 = carve<float>(base, off, nc);
+    d.r32 = carve<float>(base, off, nc);
+    d.z32 = carve<float>(base, off, nc);
+    d.p32 = carve<float>(base, off, nc);
+    d.q32 = carve<float>(base, off, nc);
     d.tile_rows = m.tile_rows;
     d.halo_max = m.halo_max;
     d.ntiles = (int64_t)m.h_self.size();
@@ -163,6 +173,24 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.p = carve<double>(base, off, nc);
     d.q = carve<double>(base, off, nc);
     d.b = carve<double>(base, off, nc);
+    d.u32 = carve<float>(base, off, NX);
+    d.un32 = carve<float>(base, off, nc);
+    d.src32 = carve<float>(base, off, nc);
+    d.phi32 = carve<float>(base, off, nf);
+    d.grad32 = carve<float>(base, off, 3 * nc);
+    d.psi32 = carve<float>(base, off, nc);
+    d.unode32 = carve<float>(base, off, nv);
+    d.flux32 = carve<float>(base, off, nf);
+    d.minv32 = carve<float>(base, off, 6 * nc);
+    d.kAC32 = carve<float>(base, off, nf);
+    d.kBC32 = carve<float>(base, off, nf);
+    d.kRL32 = carve<float>(base, off, nf);
+    d.area32 = carve<float>(base, off, nf);
+    d.vol32 = carve<float>(base, off, nc);
+    d.n_alpha32 = carve<float>(base, off, m.node.val.size());
+    d.fx32 = carve<float>(base, off, 3 * nf);
+    d.xc32 = carve<float>(base, off, 3 * NX);
+    d.gdist32 = carve<float>(base, off, nb);
     d.tmp = carve<double>(base, off, 3 * NX);
     const int64_t nblk = (nc + kBlock - 1) / kBlock;
     d.partial = carve<double>(base, off, 4 * (nblk + 1024));
@@ -279,6 +307,11 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     st.mesh = &m;
     layout(m, static_cast<char*>(d_ws), st.d);
     st.diffusivity = params ? params->diffusivity : 0.0;
+    st.fp32 = params && params->precision == MIFVM_FP32;
+    if (params && params->precision != MIFVM_FP64 && params->precision != MIFVM_FP32) {
+        delete h;
+        return fail(MIFVM_E_ARG, "unknown precision");
+    }
     for (int v = 0; v < 2; ++v)
         for (int t = 0; t < kMaxTags; ++t) {
             st.bc[v].kind[t] = kZeroFlux;
@@ -309,6 +342,20 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     UP(d.h_off, m.h_off); UP(d.h_idx, m.h_idx); UP(d.h_self, m.h_self);
     UP(d.s_lidx, m.s_lidx); UP(d.k_lidx, m.k_lidx); UP(d.c2n_l, m.c2n_l);
     UP(d.n_lidx, m.n_lidx); UP(d.v_off, m.v_off);
+    {   // packed records of the centres and face centroids (gathered by tiles)
+        std::vector<double> rec(4 * (m.nc + m.nb)), frec(4 * m.nf);
+        const int64_t NXh = m.nc + m.nb;
+        for (int64_t e = 0; e < NXh; ++e) {
+            rec[4 * e] = m.xc[e]; rec[4 * e + 1] = m.xc[NXh + e]; rec[4 * e + 2] = m.xc[2 * NXh + e]; rec[4 * e + 3] = 0.0;
+        }
+        for (int64_t f = 0; f < m.nf; ++f) {
+            frec[4 * f] = m.fx[f]; frec[4 * f + 1] = m.fx[m.nf + f]; frec[4 * f + 2] = m.fx[2 * m.nf + f]; frec[4 * f + 3] = 0.0;
+        }
+        hipError_t e1 = hipMemcpyAsync(d.xyz4, rec.data(), rec.size() * 8, hipMemcpyHostToDevice, s);
+        if (e1 == hipSuccess) e1 = hipMemcpyAsync(d.fx4, frec.data(), frec.size() * 8, hipMemcpyHostToDevice, s);
+        if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);      // rec/frec are freed at scope exit
+        if (e1 != hipSuccess) return cleanup(hip_fail(e1, "upload packed records"));
+    }
 #undef UP
     const int64_t NX = m.nc + m.nb;
     e = hipMemsetAsync(d.u, 0, NX * sizeof(double), s);
@@ -317,6 +364,10 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     if (e == hipSuccess) e = hipMemsetAsync(d.phi, 0, m.nf * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.x, 0, m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.scal, 0, SC_COUNT_ * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.u32, 0, NX * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.src32, 0, m.nc * sizeof(float), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.phi32, 0, m.nf * sizeof(float), s);
+    if (e == hipSuccess) e = launch_make_fp32_geometry(d, (int64_t)m.node.val.size(), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // host vectors are not pinned
     if (e != hipSuccess) return cleanup(hip_fail(e, "state init"));
     *out = h;
@@ -381,7 +432,8 @@ int mifvm_set_field(mifvm_state* st, int32_t field, const double* d_src, void* s
     switch (field) {
         case MIFVM_FIELD_U:
             HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.u, hs));
-            HIPCHK(launch_ghost_fill(d, d.u, s.bc[0], hs));
+            if (s.fp32) HIPCHK(launch_cast_to_f32(d.nc, d.u, d.u32, hs));
+            HIPCHK(launch_ghost_fill(d, s.fp32, s.bc[0], hs));
             break;
         case MIFVM_FIELD_VEL:
             HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 3, d_src, d.vel, hs));
@@ -390,6 +442,7 @@ int mifvm_set_field(mifvm_state* st, int32_t field, const double* d_src, void* s
             break;
         case MIFVM_FIELD_SOURCE:
             HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.src, hs));
+            HIPCHK(launch_cast_to_f32(d.nc, d.src, d.src32, hs));
             break;
         case MIFVM_FIELD_P:
             HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.x, hs));
@@ -405,7 +458,14 @@ int mifvm_get_field(const mifvm_state* st, int32_t field, double* d_dst, void* s
     const Dev& d = st->s.d;
     hipStream_t hs = S(stream);
     switch (field) {
-        case MIFVM_FIELD_U: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.u, d_dst, hs)); break;
+        case MIFVM_FIELD_U:
+            if (st->s.fp32) {
+                HIPCHK(launch_cast_to_f64(d.nc, d.u32, d.tmp, hs));
+                HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.tmp, d_dst, hs));
+            } else {
+                HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.u, d_dst, hs));
+            }
+            break;
         case MIFVM_FIELD_VEL: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 3, d.vel, d_dst, hs)); break;
         case MIFVM_FIELD_SOURCE: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.src, d_dst, hs)); break;
         case MIFVM_FIELD_P: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.x, d_dst, hs)); break;
@@ -433,9 +493,10 @@ namespace {
 int residual_parts(State& s, hipStream_t hs) {
     const Dev& d = s.d;
     KernelTimer& t = s.timer;
-    HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, d.u, s.bc[0], hs); }));
-    HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, hs); }));
-    HIPCHK(timed(t, MIFVM_K_FACE_FLUX, hs, [&] { return launch_face_flux(d, s.bc[0], s.diffusivity, hs); }));
+    HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, s.fp32, s.bc[0], hs); }));
+    HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, s.fp32, hs); }));
+    HIPCHK(timed(t, MIFVM_K_FACE_FLUX, hs,
+                 [&] { return launch_face_flux(d, s.fp32, s.bc[0], s.diffusivity, hs); }));
     return MIFVM_OK;
 }
 }  // namespace
@@ -450,10 +511,11 @@ int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream) {
         for (int k = 0; k < 3; ++k) {
             int rc = residual_parts(s, hs);
             if (rc) return rc;
-            HIPCHK(timed(s.timer, MIFVM_K_UPDATE, hs, [&] { return launch_update(s.d, alpha[k] * dt, k == 0, hs); }));
+            HIPCHK(timed(s.timer, MIFVM_K_UPDATE, hs,
+                         [&] { return launch_update(s.d, s.fp32, alpha[k] * dt, k == 0, hs); }));
         }
     if (n_steps > 0)
-        HIPCHK(timed(s.timer, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(s.d, s.d.u, s.bc[0], hs); }));
+        HIPCHK(timed(s.timer, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(s.d, s.fp32, s.bc[0], hs); }));
     return MIFVM_OK;
 }
 
@@ -466,13 +528,25 @@ int mifvm_residual(mifvm_state* st, double* d_res, double* d_grad, double* d_psi
     int rc = residual_parts(s, hs);
     if (rc) return rc;
     if (d_res) {
-        HIPCHK(launch_residual_out(d, d.tmp, hs));
+        HIPCHK(launch_residual_out(d, s.fp32, d.tmp, hs));
         HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.tmp, d_res, hs));
     }
-    if (d_grad) HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 3, d.grad, d_grad, hs));
-    if (d_psi) HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.psi, d_psi, hs));
-    if (d_unode) HIPCHK(launch_to_user(d.vert_perm, d.nv, d.nv, d.nv, 1, d.unode, d_unode, hs));
-    if (d_flux) HIPCHK(hipMemcpyAsync(d_flux, d.flux, d.nf * sizeof(double), hipMemcpyDeviceToDevice, hs));
+    // FP32 parts are widened into the scratch buffer before being reordered
+    auto out = [&](const double* a64, const float* a32, int64_t n, int comps, const int32_t* perm,
+                   double* dst) -> int {
+        const double* src = a64;
+        if (s.fp32) {
+            HIPCHK(launch_cast_to_f64(n * comps, a32, d.tmp, hs));
+            src = d.tmp;
+        }
+        if (perm) HIPCHK(launch_to_user(perm, n, n, n, comps, src, dst, hs));
+        else HIPCHK(hipMemcpyAsync(dst, src, n * comps * sizeof(double), hipMemcpyDeviceToDevice, hs));
+        return MIFVM_OK;
+    };
+    if (d_grad && (rc = out(d.grad, d.grad32, d.nc, 3, d.cell_perm, d_grad))) return rc;
+    if (d_psi && (rc = out(d.psi, d.psi32, d.nc, 1, d.cell_perm, d_psi))) return rc;
+    if (d_unode && (rc = out(d.unode, d.unode32, d.nv, 1, d.vert_perm, d_unode))) return rc;
+    if (d_flux && (rc = out(d.flux, d.flux32, d.nf, 1, nullptr, d_flux))) return rc;
     return MIFVM_OK;
 }
 
@@ -480,7 +554,7 @@ int mifvm_conservation(mifvm_state* st, double* total_out, void* stream) {
     if (!st || !total_out) return fail(MIFVM_E_ARG, "null argument");
     State& s = st->s;
     hipStream_t hs = S(stream);
-    HIPCHK(launch_conservation(s.d, s.nblk_cells, hs));
+    HIPCHK(launch_conservation(s.d, s.fp32, s.nblk_cells, hs));
     HIPCHK(hipMemcpyAsync(s.h_scal, s.d.scal, SC_COUNT_ * sizeof(double), hipMemcpyDeviceToHost, hs));
     HIPCHK(hipStreamSynchronize(hs));
     *total_out = s.h_scal[SC_CONS];
@@ -493,6 +567,7 @@ int mifvm_poisson_assemble(mifvm_state* st, void* stream) {
     hipStream_t hs = S(stream);
     HIPCHK(timed(s.timer, MIFVM_K_ASSEMBLE, hs, [&] { return launch_assemble(s.d, s.bc[1], s.mesh->row_max, hs); }));
     s.assembled = true;
+    s.k32_ready = false;
     return MIFVM_OK;
 }
 
@@ -512,7 +587,8 @@ namespace {
 int rhs_internal(State& s, const double* d_f, hipStream_t hs) {
     const Dev& d = s.d;
     if (d_f) HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_f, d.tmp, hs));
-    const double* f = d_f ? d.tmp : d.u;
+    else if (s.fp32) HIPCHK(launch_cast_to_f64(d.nc, d.u32, d.tmp, hs));   // f = the FP32 state, widened
+    const double* f = (d_f || s.fp32) ? d.tmp : d.u;
     HIPCHK(timed(s.timer, MIFVM_K_RHS, hs, [&] { return launch_rhs(d, f, hs); }));
     return MIFVM_OK;
 }
@@ -538,9 +614,13 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
     const int maxit = opts ? opts->maxit : 20000;
     const int chunk = opts && opts->chunk > 0 ? opts->chunk : 32;
     const int restart = opts ? opts->restart : 500;
+    const int method = opts ? opts->method : MIFVM_SOLVE_PLAIN;
+    const double tol_in = opts && opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
     double* hist = opts ? opts->history : nullptr;
     const int hist_cap = opts && opts->history ? opts->history_cap : 0;
-    if (!(tol > 0) || maxit < 0 || restart < 0 || hist_cap < 0) return fail(MIFVM_E_ARG, "bad tol, maxit, restart or history");
+    if (!(tol > 0) || maxit < 0 || restart < 0 || hist_cap < 0 || !(tol_in < 1))
+        return fail(MIFVM_E_ARG, "bad tol, maxit, restart, inner_tol or history");
+    if (method != MIFVM_SOLVE_PLAIN && method != MIFVM_SOLVE_IR_FP32) return fail(MIFVM_E_ARG, "unknown method");
     const Dev& d = s.d;
     hipStream_t hs = S(stream);
     auto t0 = std::chrono::steady_clock::now();
@@ -556,29 +636,55 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         if (nhist < hist_cap) hist[nhist++] = bb > 0 ? std::sqrt(s.h_scal[SC_RR] / bb) : 0.0;
         return MIFVM_OK;
     };
-    HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, true, hs); }));
-    if ((rc = pull())) return rc;
-    int restarts = 0;
-    if (s.h_scal[SC_BB] == 0.0) {       // b = 0: the solution is 0
-        HIPCHK(hipMemsetAsync(d.x, 0, d.nc * sizeof(double), hs));
-        HIPCHK(hipStreamSynchronize(hs));
+    int restarts = 0, outer = 0;
+    if (method == MIFVM_SOLVE_PLAIN) {
+        HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, true, hs); }));
+        if ((rc = pull())) return rc;
+        if (s.h_scal[SC_BB] != 0.0) {
+            for (;;) {
+                while (s.h_scal[SC_DONE] == 0.0) {
+                    for (int c = 0; c < chunk; ++c) {
+                        HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
+                        HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
+                        HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
+                    }
+                    if ((rc = pull())) return rc;
+                }
+                // recurrence converged, limit reached or restart due: recompute the
+                // true residual r = b - K x (FP64) and reopen from it
+                HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, false, hs); }));
+                if ((rc = pull())) return rc;
+                if (s.h_scal[SC_DONE] != 0.0) break;      // converged on the true residual, or maxit
+                ++restarts;
+            }
+        }
     } else {
+        if (!s.k32_ready) {
+            HIPCHK(launch_cast_matrix(d, (int64_t)s.mesh->kmat.idx.size(), hs));
+            s.k32_ready = true;
+        }
+        bool fresh = true;
         for (;;) {
+            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs,
+                         [&] { return launch_ir_residual(d, tol, tol_in, maxit, restart, fresh, hs); }));
+            fresh = false;
+            if ((rc = pull())) return rc;
+            if (s.h_scal[SC_BB] == 0.0 || s.h_scal[SC_DONE] != 0.0) break;   // converged, or maxit
             while (s.h_scal[SC_DONE] == 0.0) {
                 for (int c = 0; c < chunk; ++c) {
-                    HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
-                    HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
-                    HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
+                    HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg32_spmv(d, hs); }));
+                    HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg32_axpy(d, hs); }));
+                    HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg32_dir(d, hs); }));
                 }
                 if ((rc = pull())) return rc;
             }
-            // recurrence converged, limit reached or restart due: recompute the
-            // true residual r = b - K x (FP64) and reopen from it
-            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, false, hs); }));
-            if ((rc = pull())) return rc;
-            if (s.h_scal[SC_DONE] != 0.0) break;      // converged on the true residual, or maxit
-            ++restarts;
+            HIPCHK(launch_ir_update(d, hs));
+            ++outer;
         }
+    }
+    if (s.h_scal[SC_BB] == 0.0) {       // b = 0: the solution is 0
+        HIPCHK(hipMemsetAsync(d.x, 0, d.nc * sizeof(double), hs));
+        HIPCHK(hipStreamSynchronize(hs));
     }
     const double bb = s.h_scal[SC_BB];
     const double rel = bb > 0 ? std::sqrt(s.h_scal[SC_TRUE_RR] / bb) : 0.0;
@@ -587,6 +693,7 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         info->iterations = iters;
         info->restarts = restarts;
         info->history_len = nhist;
+        info->outer = outer;
         info->rel_residual = rel;
         info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }

@@ -5,18 +5,27 @@
 // free of atomics:
 //   k_grad_limiter  per cell: least-squares gradient over the node-neighbour
 //                   stencil (Algorithm 1), then the Barth-Jespersen limiter
-//                   over the 4 face neighbours;
-//                   the same kernel computes the vertex values of the
-//                   least-squares interpolation (Algorithm 2);
+//                   over the 4 face neighbours; the same kernel computes the
+//                   vertex values of the least-squares interpolation
+//                   (Algorithm 2);
 //   k_face_flux     per face: MUSCL upwind convective flux (eq. (15)) minus
 //                   the diamond diffusive flux (eq. (diamond)), written once;
 //   k_update        per cell: gathers its 4 face fluxes with their signs.
 // Ghost values (behind boundary faces) are materialised after every update
 // by k_ghost_fill, so every gather is a plain indexed load.
 //
+// Every kernel is instantiated for FP64 (the method as stated) and FP32 (the
+// reduced-precision form: state, gradients, fluxes and geometry copies in
+// FP32; in LDS the FP32 form keeps positions relative to the tile's first
+// cell, computed in FP64, so differences of nearby positions keep their
+// digits).  Sums that must stay FP64 (conservation, the CFL bound) read the
+// FP64 geometry.
+//
 // Per-row lists (stencil, vertex lists) are stored in 64-row slices with the
 // entry index as the slow dimension, so the index/weight loads of a
-// wavefront are one contiguous 256/512-byte segment.
+// wavefront are one contiguous 128/256/512-byte segment.
+#include <type_traits>
+
 #include "reduce.h"
 #include "state.h"
 
@@ -26,19 +35,26 @@ __device__ inline int64_t gtid() { return int64_t(blockIdx.x) * blockDim.x + thr
 
 inline int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 
+template <class R> struct Vec4T;
+template <> struct Vec4T<double> { using T = double4; };
+template <> struct Vec4T<float> { using T = float4; };
+
+__device__ inline double4 mk4(double x, double y, double z, double w) { return make_double4(x, y, z, w); }
+__device__ inline float4 mk4(float x, float y, float z, float w) { return make_float4(x, y, z, w); }
+
+template <class R>
 __global__ __launch_bounds__(kBlock) void k_ghost_fill(int64_t nc, int64_t nb,
                                                         const int32_t* __restrict__ gowner,
                                                         const int32_t* __restrict__ gtag,
-                                                        const double* __restrict__ gdist,
-                                                        BcTable bc, double* u) {
+                                                        const R* __restrict__ gdist, BcTable bc, R* u) {
     const int64_t g = gtid();
     if (g >= nb) return;
     const int t = gtag[g];
     const int kind = bc.kind[t];
-    const double val = bc.value[t];
-    const double uo = u[gowner[g]];
-    double ug;
-    if (kind == kDirichlet) ug = 2.0 * val - uo;
+    const R val = R(bc.value[t]);
+    const R uo = u[gowner[g]];
+    R ug;
+    if (kind == kDirichlet) ug = R(2) * val - uo;
     else if (kind == kNeumann) ug = uo + val * gdist[g];
     else ug = uo;
     u[nc + g] = ug;
@@ -51,155 +67,205 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(int64_t nc, int64_t nb,
 // local index list.  The same halo holds the cell/ghost list of every vertex
 // owned by the tile, so the vertex values of Algorithm 2 are computed here
 // too (u_v = sum alpha u_c, entries in the same order as the vertex list).
-__global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d) {
-    extern __shared__ double4 sm[];                  // [halo] x, y, z, u
-    const int64_t nc = d.nc, NX = d.nc + d.nb, nf = d.nf;
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d, FvArrays<R> a) {
+    using V4 = typename Vec4T<R>::T;
+    extern __shared__ __align__(16) unsigned char sm_raw[];
+    V4* sm = reinterpret_cast<V4*>(sm_raw);          // [halo] x, y, z, u
+    constexpr bool rel = std::is_same<R, float>::value;
+    const int64_t nc = d.nc;
     const int64_t t = blockIdx.x;
     const int T = blockDim.x;
     const int64_t h0 = d.h_off[t];
     const int hn = int(d.h_off[t + 1] - h0);
-    const double* __restrict__ X = d.xc;
-    const double* __restrict__ Y = d.xc + NX;
-    const double* __restrict__ Z = d.xc + 2 * NX;
-    const double* __restrict__ u = d.u;
-    for (int h = threadIdx.x; h < hn; h += T) {
-        const int e = d.h_idx[h0 + h];
-        sm[h] = make_double4(X[e], Y[e], Z[e], u[e]);
+    const R* __restrict__ u = a.u;
+    const double4* __restrict__ P = d.xyz4;
+    // positions relative to the tile's first cell in the FP32 form
+    const double4 ref = rel ? P[t * T] : make_double4(0.0, 0.0, 0.0, 0.0);
+    // stage the halo: all index loads of a thread first, then all gathers
+    for (int hb = 0; hb < hn; hb += 8 * T) {
+        int e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int h = hb + j * T + threadIdx.x;
+            e[j] = h < hn ? d.h_idx[h0 + h] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (e[j] >= 0) {
+                const double4 r = P[e[j]];
+                sm[hb + j * T + threadIdx.x] = mk4(R(r.x - ref.x), R(r.y - ref.y), R(r.z - ref.z), u[e[j]]);
+            }
+        }
     }
     __syncthreads();
-    for (int64_t v = d.v_off[t] + threadIdx.x; v < d.v_off[t + 1]; v += T) {
-        const int64_t vb = d.n_off[v >> 6] + (v & 63);
-        const int vw = d.n_w[v >> 6];
-        double acc = 0.0;
-        for (int k = 0; k < vw; ++k) {
-            const int64_t at = vb + int64_t(k) * 64;
-            acc += d.n_alpha[at] * sm[d.n_lidx[at]].w;
+
+    // vertex values (Algorithm 2) of the tile's vertices, spread over the waves
+    {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = T >> 6;
+        for (int64_t v = d.v_off[t] + wave + int64_t(nw) * lane; v < d.v_off[t + 1]; v += int64_t(nw) * 64) {
+            const int64_t vb = d.n_off[v >> 6] + (v & 63);
+            const int vw = d.n_w[v >> 6];
+            R acc = R(0);
+            for (int k0 = 0; k0 < vw; k0 += 8) {
+                uint16_t l[8];
+                R al[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bool in = k0 + j < vw;
+                    const int64_t at = vb + int64_t(k0 + j) * 64;
+                    l[j] = in ? d.n_lidx[at] : 0;
+                    al[j] = in ? a.n_alpha[at] : R(0);
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (k0 + j < vw) acc += al[j] * sm[l[j]].w;
+            }
+            a.unode[v] = acc;
         }
-        d.unode[v] = acc;
     }
+
     const int64_t i = t * T + threadIdx.x;
     if (i >= nc) return;
-    const double4 me = sm[d.h_self[t] + threadIdx.x];
-    const double xi = me.x, yi = me.y, zi = me.z, ui = me.w;
+    const int lself = d.h_self[t] + threadIdx.x;
+    const V4 me = sm[lself];
+    const R xi = me.x, yi = me.y, zi = me.z, ui = me.w;
     const int64_t s = i >> 6;
     const uint16_t* __restrict__ idx = d.s_lidx + d.s_off[s] + (i & 63);
     const int w = d.s_w[s];
-    double jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < w; ++k) {
-        const double4 o = sm[idx[int64_t(k) * 64]];
-        const double du = o.w - ui;
-        jx += (o.x - xi) * du;
-        jy += (o.y - yi) * du;
-        jz += (o.z - zi) * du;
+    R jx = R(0), jy = R(0), jz = R(0);
+    // 16 index loads in flight, then 16 LDS reads; slots past the row length
+    // read the cell itself, which adds exact zeros
+    for (int k0 = 0; k0 < w; k0 += 16) {
+        uint16_t l[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) l[j] = k0 + j < w ? idx[int64_t(k0 + j) * 64] : uint16_t(lself);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const V4 o = sm[l[j]];
+            const R du = o.w - ui;
+            jx += (o.x - xi) * du;
+            jy += (o.y - yi) * du;
+            jz += (o.z - zi) * du;
+        }
     }
-    const double* __restrict__ m = d.minv;
-    const double m0 = m[i], m1 = m[nc + i], m2 = m[2 * nc + i];
-    const double m3 = m[3 * nc + i], m4 = m[4 * nc + i], m5 = m[5 * nc + i];
-    const double gx = m0 * jx + m1 * jy + m2 * jz;
-    const double gy = m1 * jx + m3 * jy + m4 * jz;
-    const double gz = m2 * jx + m4 * jy + m5 * jz;
-    d.grad[i] = gx;
-    d.grad[nc + i] = gy;
-    d.grad[2 * nc + i] = gz;
+    const R* __restrict__ m = a.minv;
+    const R m0 = m[i], m1 = m[nc + i], m2 = m[2 * nc + i];
+    const R m3 = m[3 * nc + i], m4 = m[4 * nc + i], m5 = m[5 * nc + i];
+    const R gx = m0 * jx + m1 * jy + m2 * jz;
+    const R gy = m1 * jx + m3 * jy + m4 * jz;
+    const R gz = m2 * jx + m4 * jy + m5 * jz;
+    a.grad[i] = gx;
+    a.grad[nc + i] = gy;
+    a.grad[2 * nc + i] = gz;
 
     // Barth-Jespersen: bounds over the cell and its face neighbours
-    double umax = ui, umin = ui;
+    int fc[4];
+    uint16_t nl[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double v = sm[d.c2n_l[k * nc + i]].w;
+        const int f = d.c2f[k * nc + i];
+        fc[k] = f < 0 ? ~f : f;
+        nl[k] = d.c2n_l[k * nc + i];
+    }
+    R umax = ui, umin = ui;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const R v = sm[nl[k]].w;
         umax = fmax(umax, v);
         umin = fmin(umin, v);
     }
-    double psi = 1.0;
+    R psi = R(1);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int f = d.c2f[k * nc + i];
-        f = f < 0 ? ~f : f;
-        const double dl = gx * (d.fx[f] - xi) + gy * (d.fx[nf + f] - yi) + gz * (d.fx[2 * nf + f] - zi);
-        double ph = 1.0;
-        if (dl > 0.0) ph = fmin(1.0, (umax - ui) / dl);
-        else if (dl < 0.0) ph = fmin(1.0, (umin - ui) / dl);
+        const double4 xf = d.fx4[fc[k]];
+        const R dl = gx * (R(xf.x - ref.x) - xi) + gy * (R(xf.y - ref.y) - yi) + gz * (R(xf.z - ref.z) - zi);
+        R ph = R(1);
+        if (dl > R(0)) ph = fmin(R(1), (umax - ui) / dl);
+        else if (dl < R(0)) ph = fmin(R(1), (umin - ui) / dl);
         psi = fmin(psi, ph);
     }
-    d.psi[i] = psi;
+    a.psi[i] = psi;
 }
 
-__global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, BcTable bc, double D) {
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTable bc, R D) {
     const int64_t f = gtid();
     if (f >= d.nf) return;
     const int64_t nc = d.nc, NX = d.nc + d.nb, nf = d.nf;
-    const double* __restrict__ u = d.u;
+    const R* __restrict__ u = a.u;
     int kind = kDirichlet;
-    double val = 0.0;
+    R val = R(0);
     if (f >= d.nfi) {
         const int t = d.gtag[f - d.nfi];
         kind = bc.kind[t];
-        val = bc.value[t];
+        val = R(bc.value[t]);
     }
     if (kind == kZeroFlux) {
-        d.flux[f] = 0.0;
+        a.flux[f] = R(0);
         return;
     }
-    const int L = d.fL[f], R = d.fR[f];
-    const double ph = d.phi[f];
-    const int up = ph >= 0.0 ? L : R;
-    double uup = u[up];
+    const int L = d.fL[f], Rc = d.fR[f];
+    const R ph = a.phi[f];
+    const int up = ph >= R(0) ? L : Rc;
+    R uup = u[up];
     if (up < nc) {   // MUSCL reconstruction at the face centroid (ghost side: first order)
-        const double rx = d.fx[f] - d.xc[up];
-        const double ry = d.fx[nf + f] - d.xc[NX + up];
-        const double rz = d.fx[2 * nf + f] - d.xc[2 * NX + up];
-        const double gr = d.grad[up] * rx + d.grad[nc + up] * ry + d.grad[2 * nc + up] * rz;
-        uup = uup + d.psi[up] * gr;
+        const R rx = a.fx[f] - a.xc[up];
+        const R ry = a.fx[nf + f] - a.xc[NX + up];
+        const R rz = a.fx[2 * nf + f] - a.xc[2 * NX + up];
+        const R gr = a.grad[up] * rx + a.grad[nc + up] * ry + a.grad[2 * nc + up] * rz;
+        uup = uup + a.psi[up] * gr;
     }
-    double diff;
+    R diff;
     if (kind == kNeumann) {
-        diff = val * d.area[f];
+        diff = val * a.area[f];
     } else {
-        const double uA = d.unode[d.fA[f]], uB = d.unode[d.fB[f]], uC = d.unode[d.fC[f]];
-        diff = d.kAC[f] * (uA - uC) + d.kBC[f] * (uB - uC) + d.kRL[f] * (u[R] - u[L]);
+        const R uA = a.unode[d.fA[f]], uB = a.unode[d.fB[f]], uC = a.unode[d.fC[f]];
+        diff = a.kAC[f] * (uA - uC) + a.kBC[f] * (uB - uC) + a.kRL[f] * (u[Rc] - u[L]);
     }
-    d.flux[f] = uup * ph - D * diff;
+    a.flux[f] = uup * ph - D * diff;
 }
 
 // u^(k) = u^n + a dt Res(u^(k-1)); the first stage also saves u^n.
-__global__ __launch_bounds__(kBlock) void k_update(Dev d, double a_dt, int first) {
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_update(Dev d, FvArrays<R> a, R a_dt, int first) {
     const int64_t i = gtid();
     if (i >= d.nc) return;
     const int64_t nc = d.nc;
-    double acc = 0.0;
+    R acc = R(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int c = d.c2f[k * nc + i];
-        if (c >= 0) acc += d.flux[c];
-        else acc -= d.flux[~c];
+        if (c >= 0) acc += a.flux[c];
+        else acc -= a.flux[~c];
     }
-    const double res = -acc / d.vol[i] + d.src[i];
-    double base;
+    const R res = -acc / a.vol[i] + a.src[i];
+    R base;
     if (first) {
-        base = d.u[i];
-        d.un[i] = base;
+        base = a.u[i];
+        a.un[i] = base;
     } else {
-        base = d.un[i];
+        base = a.un[i];
     }
-    d.u[i] = base + a_dt * res;
+    a.u[i] = base + a_dt * res;
 }
 
-__global__ __launch_bounds__(kBlock) void k_residual_out(Dev d, double* res) {
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_residual_out(Dev d, FvArrays<R> a, double* res) {
     const int64_t i = gtid();
     if (i >= d.nc) return;
     const int64_t nc = d.nc;
-    double acc = 0.0;
+    R acc = R(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int c = d.c2f[k * nc + i];
-        if (c >= 0) acc += d.flux[c];
-        else acc -= d.flux[~c];
+        if (c >= 0) acc += a.flux[c];
+        else acc -= a.flux[~c];
     }
-    res[i] = -acc / d.vol[i] + d.src[i];
+    res[i] = double(-acc / a.vol[i] + a.src[i]);
 }
 
-// phi_f = 1/2 (V_L + V_R) . S_f  (V_L . S_f on the boundary)
+// phi_f = 1/2 (V_L + V_R) . S_f  (V_L . S_f on the boundary), with an FP32 copy
 __global__ __launch_bounds__(kBlock) void k_face_phi(Dev d) {
     const int64_t f = gtid();
     if (f >= d.nf) return;
@@ -209,7 +275,40 @@ __global__ __launch_bounds__(kBlock) void k_face_phi(Dev d) {
     const double vx = 0.5 * (d.vel[L] + d.vel[R]);
     const double vy = 0.5 * (d.vel[nc + L] + d.vel[nc + R]);
     const double vz = 0.5 * (d.vel[2 * nc + L] + d.vel[2 * nc + R]);
-    d.phi[f] = vx * d.S[f] + vy * d.S[nf + f] + vz * d.S[2 * nf + f];
+    const double ph = vx * d.S[f] + vy * d.S[nf + f] + vz * d.S[2 * nf + f];
+    d.phi[f] = ph;
+    d.phi32[f] = float(ph);
+}
+
+// FP32 copies of the static geometry the FP32 kernels read
+__global__ __launch_bounds__(kBlock) void k_make_fp32_geometry(Dev d, int64_t node_padded) {
+    const int64_t i = gtid();
+    const int64_t nc = d.nc, nf = d.nf, NX = d.nc + d.nb;
+    if (i < nc) {
+        d.vol32[i] = float(d.vol[i]);
+        for (int k = 0; k < 6; ++k) d.minv32[k * nc + i] = float(d.minv[k * nc + i]);
+    }
+    if (i < NX)
+        for (int k = 0; k < 3; ++k) d.xc32[k * NX + i] = float(d.xc[k * NX + i]);
+    if (i < nf) {
+        d.kAC32[i] = float(d.kAC[i]);
+        d.kBC32[i] = float(d.kBC[i]);
+        d.kRL32[i] = float(d.kRL[i]);
+        d.area32[i] = float(d.area[i]);
+        for (int k = 0; k < 3; ++k) d.fx32[k * nf + i] = float(d.fx[k * nf + i]);
+    }
+    if (i < d.nb) d.gdist32[i] = float(d.gdist[i]);
+    if (i < node_padded) d.n_alpha32[i] = float(d.n_alpha[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_to_f32(int64_t n, const double* __restrict__ src, float* dst) {
+    const int64_t i = gtid();
+    if (i < n) dst[i] = float(src[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_to_f64(int64_t n, const float* __restrict__ src, double* dst) {
+    const int64_t i = gtid();
+    if (i < n) dst[i] = double(src[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_to_internal(const int32_t* __restrict__ perm, int64_t n,
@@ -230,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_to_user(const int32_t* __restrict__ 
     for (int c = 0; c < comps; ++c) dst[c * sout + o] = src[c * sin + i];
 }
 
-// dt bound: min_i mu_i / sum_{active faces} (|phi_f| + D kRL_f), per block
+// dt bound: min_i mu_i / sum_{active faces} (|phi_f| + D kRL_f), per block (FP64)
 __global__ __launch_bounds__(kBlock) void k_cfl(Dev d, BcTable bc, double D) {
     __shared__ double lds[4];
     const int64_t nc = d.nc;
@@ -249,10 +348,12 @@ __global__ __launch_bounds__(kBlock) void k_cfl(Dev d, BcTable bc, double D) {
     if (threadIdx.x == 0) d.partial[blockIdx.x] = best;
 }
 
-__global__ __launch_bounds__(kBlock) void k_conservation(Dev d) {
+// sum_i mu_i u_i in FP64 (FP64 volumes, the state widened to FP64)
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_conservation(Dev d, const R* __restrict__ u) {
     __shared__ double lds[4];
     double s = 0.0;
-    for (int64_t i = gtid(); i < d.nc; i += int64_t(gridDim.x) * blockDim.x) s += d.vol[i] * d.u[i];
+    for (int64_t i = gtid(); i < d.nc; i += int64_t(gridDim.x) * blockDim.x) s += d.vol[i] * double(u[i]);
     s = block_sum256(s, lds);
     if (threadIdx.x == 0) d.partial[blockIdx.x] = s;
 }
@@ -265,36 +366,83 @@ __global__ __launch_bounds__(1024) void k_finalize(Dev d, int64_t n, int slot, i
 }
 
 // ---- launchers ---------------------------------------------------------------
-hipError_t launch_ghost_fill(const Dev& d, double* u, const BcTable& bc, hipStream_t s) {
+FvArrays<double> fv64(const Dev& d) {
+    return {d.u, d.un, d.grad, d.psi, d.unode, d.flux, d.phi, d.minv, d.kAC, d.kBC, d.kRL, d.area,
+            d.vol, d.src, d.n_alpha, d.fx, d.xc, d.gdist};
+}
+
+FvArrays<float> fv32(const Dev& d) {
+    return {d.u32, d.un32, d.grad32, d.psi32, d.unode32, d.flux32, d.phi32, d.minv32, d.kAC32, d.kBC32,
+            d.kRL32, d.area32, d.vol32, d.src32, d.n_alpha32, d.fx32, d.xc32, d.gdist32};
+}
+
+template <class R>
+hipError_t launch_ghost_fill_t(const Dev& d, const FvArrays<R>& a, const BcTable& bc, hipStream_t s) {
     if (d.nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ghost_fill, dim3(grid_for(d.nb)), dim3(kBlock), 0, s, d.nc, d.nb, d.gowner,
-                       d.gtag, d.gdist, bc, u);
+    hipLaunchKernelGGL(k_ghost_fill<R>, dim3(grid_for(d.nb)), dim3(kBlock), 0, s, d.nc, d.nb, d.gowner,
+                       d.gtag, a.gdist, bc, a.u);
     return hipGetLastError();
 }
 
-hipError_t launch_grad_limiter(const Dev& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_grad_limiter, dim3(unsigned(d.ntiles)), dim3(d.tile_rows),
-                       size_t(d.halo_max) * sizeof(double4), s, d);
+hipError_t launch_ghost_fill(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s) {
+    return fp32 ? launch_ghost_fill_t(d, fv32(d), bc, s) : launch_ghost_fill_t(d, fv64(d), bc, s);
+}
+
+hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s) {
+    const dim3 g(unsigned(d.ntiles)), b(d.tile_rows);
+    if (fp32)
+        hipLaunchKernelGGL(k_grad_limiter<float>, g, b, size_t(d.halo_max) * sizeof(float4), s, d, fv32(d));
+    else
+        hipLaunchKernelGGL(k_grad_limiter<double>, g, b, size_t(d.halo_max) * sizeof(double4), s, d, fv64(d));
     return hipGetLastError();
 }
 
-hipError_t launch_face_flux(const Dev& d, const BcTable& bc, double D, hipStream_t s) {
-    hipLaunchKernelGGL(k_face_flux, dim3(grid_for(d.nf)), dim3(kBlock), 0, s, d, bc, D);
+hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, double D, hipStream_t s) {
+    if (fp32)
+        hipLaunchKernelGGL(k_face_flux<float>, dim3(grid_for(d.nf)), dim3(kBlock), 0, s, d, fv32(d), bc, float(D));
+    else
+        hipLaunchKernelGGL(k_face_flux<double>, dim3(grid_for(d.nf)), dim3(kBlock), 0, s, d, fv64(d), bc, D);
     return hipGetLastError();
 }
 
-hipError_t launch_update(const Dev& d, double a_dt, bool first_stage, hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, a_dt, first_stage ? 1 : 0);
+hipError_t launch_update(const Dev& d, bool fp32, double a_dt, bool first_stage, hipStream_t s) {
+    if (fp32)
+        hipLaunchKernelGGL(k_update<float>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv32(d), float(a_dt),
+                           first_stage ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_update<double>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv64(d), a_dt,
+                           first_stage ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_residual_out(const Dev& d, double* res, hipStream_t s) {
-    hipLaunchKernelGGL(k_residual_out, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, res);
+hipError_t launch_residual_out(const Dev& d, bool fp32, double* res, hipStream_t s) {
+    if (fp32)
+        hipLaunchKernelGGL(k_residual_out<float>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv32(d), res);
+    else
+        hipLaunchKernelGGL(k_residual_out<double>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv64(d), res);
     return hipGetLastError();
 }
 
 hipError_t launch_face_phi(const Dev& d, hipStream_t s) {
     hipLaunchKernelGGL(k_face_phi, dim3(grid_for(d.nf)), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_fp32_geometry(const Dev& d, int64_t node_padded, hipStream_t s) {
+    int64_t n = d.nc + d.nb;
+    if (d.nf > n) n = d.nf;
+    if (node_padded > n) n = node_padded;
+    hipLaunchKernelGGL(k_make_fp32_geometry, dim3(grid_for(n)), dim3(kBlock), 0, s, d, node_padded);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_to_f32(int64_t n, const double* src, float* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_cast_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_to_f64(int64_t n, const float* src, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_cast_to_f64, dim3(grid_for(n)), dim3(kBlock), 0, s, n, src, dst);
     return hipGetLastError();
 }
 
@@ -318,8 +466,11 @@ hipError_t launch_cfl(const Dev& d, const BcTable& bc, double D, int nblk, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_conservation(const Dev& d, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_conservation, dim3(nblk), dim3(kBlock), 0, s, d);
+hipError_t launch_conservation(const Dev& d, bool fp32, int nblk, hipStream_t s) {
+    if (fp32)
+        hipLaunchKernelGGL(k_conservation<float>, dim3(nblk), dim3(kBlock), 0, s, d, (const float*)d.u32);
+    else
+        hipLaunchKernelGGL(k_conservation<double>, dim3(nblk), dim3(kBlock), 0, s, d, (const double*)d.u);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, d, int64_t(nblk), int(SC_CONS), 0);
     return hipGetLastError();
 }

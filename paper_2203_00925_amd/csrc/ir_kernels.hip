@@ -1,0 +1,220 @@
+// Mixed-precision Poisson solve: iterative refinement whose correction
+// equation K d = r is solved approximately by Jacobi-CG in FP32 (FP32 matrix
+// copy and vectors, FP64 accumulation of every dot product), while the true
+// residual r = b - K x and the update x += d stay in FP64.  The FP64 outer
+// residual also serves as the restart of the inner CG.
+#include "cg_scalars.h"
+#include "reduce.h"
+#include "state.h"
+
+namespace mifvm {
+
+namespace {
+__device__ inline int64_t tid_g() { return int64_t(blockIdx.x) * blockDim.x + threadIdx.x; }
+inline int rows_grid(int64_t n) { return int((n + kBlock - 1) / kBlock); }
+__device__ inline bool ir_done(const Dev& d) { return d.scal[SC_DONE] != 0.0; }
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void k_cast_matrix(Dev d, int64_t padded) {
+    const int64_t i = tid_g();
+    if (i < padded) d.k_val32[i] = float(d.k_val[i]);
+    if (i < d.nc) {
+        d.k_diag32[i] = float(d.k_diag[i]);
+        d.k_dinv32[i] = float(d.k_dinv[i]);
+    }
+}
+
+// Outer step: r = b - K x (FP64, same entries and order as the plain SpMV);
+// inner start d = 0, r32 = r, z32 = D^-1 r32, p32 = z32.  Partials: true
+// rr (FP64), inner rz and rr (FP64 sums of FP32 values), bb.
+__global__ __launch_bounds__(kBlock) void k_ir_residual(Dev d) {
+    __shared__ double lds[4];
+    const int64_t i = tid_g();
+    double rr = 0.0, rz = 0.0, rr32 = 0.0, bb = 0.0;
+    if (i < d.nc) {
+        const int64_t s = i >> 6;
+        const int64_t base = d.k_off[s] + (i & 63);
+        const int w = d.k_w[s];
+        double y = d.k_diag[i] * d.x[i];
+        for (int k = 0; k < w; ++k) {
+            const int64_t at = base + int64_t(k) * 64;
+            y += d.k_val[at] * d.x[d.k_col[at]];
+        }
+        const double bi = d.b[i];
+        const double ri = bi - y;
+        const float r32 = float(ri);
+        const float z32 = d.k_dinv32[i] * r32;
+        d.r32[i] = r32;
+        d.z32[i] = z32;
+        d.p32[i] = z32;
+        d.d32[i] = 0.0f;
+        rr = ri * ri;
+        rz = double(r32) * double(z32);
+        rr32 = double(r32) * double(r32);
+        bb = bi * bi;
+    }
+    rr = block_sum256(rr, lds);
+    rz = block_sum256(rz, lds);
+    rr32 = block_sum256(rr32, lds);
+    bb = block_sum256(bb, lds);
+    if (threadIdx.x == 0) {
+        d.partial[blockIdx.x] = rr;
+        d.partial[gridDim.x + blockIdx.x] = rz;
+        d.partial[2 * gridDim.x + blockIdx.x] = rr32;
+        d.partial[3 * gridDim.x + blockIdx.x] = bb;
+    }
+}
+
+// fresh: a new solve (sets the outer tolerance, limits and count).  The inner
+// solve runs until ||r32|| <= max(tol_in ||r32_0||, tol ||b|| / 2), the
+// iteration limit, or a restart; the outer loop ends when the FP64 true
+// residual meets tol.
+__global__ __launch_bounds__(1024) void k_ir_residual_fin(Dev d, int64_t nparts, double tol, double tol_in,
+                                                          int maxit, int restart, int fresh) {
+    __shared__ double lds[16];
+    const double trr = reduce_partials_sum(d.partial, nparts, lds);
+    const double trz = reduce_partials_sum(d.partial + nparts, nparts, lds);
+    const double trr32 = reduce_partials_sum(d.partial + 2 * nparts, nparts, lds);
+    const double tbb = reduce_partials_sum(d.partial + 3 * nparts, nparts, lds);
+    if (threadIdx.x == 0) {
+        double* sc = d.scal;
+        sc[SC_TRUE_RR] = trr;
+        sc[SC_BB] = tbb;
+        sc[SC_RZ] = trz;
+        sc[SC_RR] = trr32;
+        if (fresh) {
+            sc[SC_TOL2BB_OUT] = tol * tol * tbb;
+            sc[SC_MAXIT] = double(maxit);
+            sc[SC_RESTART] = double(restart);
+            sc[SC_IT] = 0.0;
+        }
+        // inner target: the asked reduction of this step's residual, but no
+        // further than half the outer tolerance (the last step stops early)
+        sc[SC_TOL2BB] = fmax(tol_in * tol_in * trr32, 0.25 * sc[SC_TOL2BB_OUT]);
+        sc[SC_SINCE] = 0.0;
+        sc[SC_DONE] = trr <= sc[SC_TOL2BB_OUT] ? 1.0 : (sc[SC_IT] >= sc[SC_MAXIT] ? 2.0 : 0.0);
+    }
+}
+
+// q32 = K32 p32 with the tile's halo of p32 in LDS; partial p.q in FP64
+__global__ __launch_bounds__(kBlock) void k_cg32_spmv(Dev d) {
+    extern __shared__ float sp32[];
+    __shared__ double lds[4];
+    if (ir_done(d)) return;
+    const int64_t nc = d.nc;
+    const int64_t t = blockIdx.x;
+    const int T = blockDim.x;
+    const int64_t h0 = d.h_off[t];
+    const int hn = int(d.h_off[t + 1] - h0);
+    for (int h = threadIdx.x; h < hn; h += T) {
+        const int e = d.h_idx[h0 + h];
+        sp32[h] = e < nc ? d.p32[e] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t i = t * T + threadIdx.x;
+    double pq = 0.0;
+    if (i < nc) {
+        const float pi = sp32[d.h_self[t] + threadIdx.x];
+        const int64_t s = i >> 6;
+        const int64_t base = d.k_off[s] + (i & 63);
+        const int w = d.k_w[s];
+        float y = d.k_diag32[i] * pi;
+        for (int k0 = 0; k0 < w; k0 += 16) {
+            uint16_t l[16];
+            float v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const bool in = k0 + j < w;
+                const int64_t at = base + int64_t(k0 + j) * 64;
+                l[j] = in ? d.k_lidx[at] : 0;
+                v[j] = in ? d.k_val32[at] : 0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) y += v[j] * sp32[l[j]];
+        }
+        d.q32[i] = y;
+        pq = double(pi) * double(y);
+    }
+    pq = block_sum_upto256(pq, lds);
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = pq;
+}
+
+// d += alpha p; r -= alpha q; z = D^-1 r (FP32); partial rz, rr (FP64)
+__global__ __launch_bounds__(kBlock) void k_cg32_axpy(Dev d) {
+    __shared__ double lds[4];
+    if (ir_done(d)) return;
+    const float alpha = float(d.scal[SC_ALPHA]);
+    const int64_t i = tid_g();
+    double rz = 0.0, rr = 0.0;
+    if (i < d.nc) {
+        d.d32[i] = d.d32[i] + alpha * d.p32[i];
+        const float ri = d.r32[i] - alpha * d.q32[i];
+        const float zi = d.k_dinv32[i] * ri;
+        d.r32[i] = ri;
+        d.z32[i] = zi;
+        rz = double(ri) * double(zi);
+        rr = double(ri) * double(ri);
+    }
+    rz = block_sum256(rz, lds);
+    rr = block_sum256(rr, lds);
+    if (threadIdx.x == 0) {
+        d.partial[blockIdx.x] = rz;
+        d.partial[gridDim.x + blockIdx.x] = rr;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg32_dir(Dev d) {
+    if (ir_done(d)) return;
+    const float beta = float(d.scal[SC_BETA]);
+    const int64_t i = tid_g();
+    if (i >= d.nc) return;
+    d.p32[i] = d.z32[i] + beta * d.p32[i];
+}
+
+// x += d (FP64)
+__global__ __launch_bounds__(kBlock) void k_ir_update(Dev d) {
+    const int64_t i = tid_g();
+    if (i >= d.nc) return;
+    d.x[i] = d.x[i] + double(d.d32[i]);
+}
+
+hipError_t launch_cast_matrix(const Dev& d, int64_t padded, hipStream_t s) {
+    const int64_t n = padded > d.nc ? padded : d.nc;
+    hipLaunchKernelGGL(k_cast_matrix, dim3(rows_grid(n)), dim3(kBlock), 0, s, d, padded);
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_residual(const Dev& d, double tol, double tol_in, int maxit, int restart, bool fresh,
+                              hipStream_t s) {
+    const int nb = rows_grid(d.nc);
+    hipLaunchKernelGGL(k_ir_residual, dim3(nb), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_ir_residual_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb), tol, tol_in, maxit,
+                       restart, fresh ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg32_spmv(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg32_spmv, dim3(unsigned(d.ntiles)), dim3(d.tile_rows),
+                       size_t(d.halo_max) * sizeof(float), s, d);
+    hipLaunchKernelGGL(k_cg_alpha<0>, dim3(1), dim3(1024), 0, s, d, d.ntiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg32_axpy(const Dev& d, hipStream_t s) {
+    const int nb = rows_grid(d.nc);
+    hipLaunchKernelGGL(k_cg32_axpy, dim3(nb), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_cg_beta<0>, dim3(1), dim3(1024), 0, s, d, int64_t(nb));
+    return hipGetLastError();
+}
+
+hipError_t launch_cg32_dir(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg32_dir, dim3(rows_grid(d.nc)), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_update(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_ir_update, dim3(rows_grid(d.nc)), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+}  // namespace mifvm

@@ -74,7 +74,14 @@ __device__ inline double block_min1024(double v, double* lds) {
 // In a one-block kernel of 1024 threads: fixed-order sum of n partials.
 __device__ inline double reduce_partials_sum(const double* partial, int64_t n, double* lds) {
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) s += partial[i];
+    // batches of 8 independent loads, summed in index order
+    for (int64_t b = threadIdx.x; b < n; b += 8 * 1024) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = b + j * 1024 < n ? partial[b + j * 1024] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
     return block_sum1024(s, lds);
 }
 

@@ -4,6 +4,7 @@
 // in device memory (alpha, beta and the convergence test are computed by the
 // last block of the kernel that produces their partial sums; later kernels
 // of an enqueued chunk return at once when the solve has finished).
+#include "cg_scalars.h"
 #include "reduce.h"
 #include "state.h"
 
@@ -213,17 +214,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Dev d) {
     if (threadIdx.x == 0) d.partial[blockIdx.x] = pq;
 }
 
-// alpha = rz / (p . q)
-__global__ __launch_bounds__(1024) void k_cg_alpha(Dev d, int64_t nparts) {
-    __shared__ double lds[16];
-    if (cg_done(d)) return;
-    const double pq = reduce_partials_sum(d.partial, nparts, lds);
-    if (threadIdx.x == 0) {
-        d.scal[SC_PQ] = pq;
-        d.scal[SC_ALPHA] = d.scal[SC_RZ] / pq;
-    }
-}
-
 // x += alpha p; r -= alpha q; z = D^-1 r; partial rz, rr
 __global__ __launch_bounds__(kBlock) void k_cg_axpy(Dev d) {
     __shared__ double lds[4];
@@ -245,26 +235,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_axpy(Dev d) {
     if (threadIdx.x == 0) {
         d.partial[blockIdx.x] = rz;
         d.partial[gridDim.x + blockIdx.x] = rr;
-    }
-}
-
-// beta = rz_new / rz; count; convergence (1), iteration limit (2) or a
-// scheduled restart (3) ends the enqueued chunk.
-__global__ __launch_bounds__(1024) void k_cg_beta(Dev d, int64_t nparts) {
-    __shared__ double lds[16];
-    if (cg_done(d)) return;
-    const double trz = reduce_partials_sum(d.partial, nparts, lds);
-    const double trr = reduce_partials_sum(d.partial + nparts, nparts, lds);
-    if (threadIdx.x == 0) {
-        double* sc = d.scal;
-        sc[SC_BETA] = trz / sc[SC_RZ];
-        sc[SC_RZ] = trz;
-        sc[SC_RR] = trr;
-        sc[SC_IT] = sc[SC_IT] + 1.0;
-        sc[SC_SINCE] = sc[SC_SINCE] + 1.0;
-        if (trr <= sc[SC_TOL2BB]) sc[SC_DONE] = 1.0;
-        else if (sc[SC_IT] >= sc[SC_MAXIT]) sc[SC_DONE] = 2.0;
-        else if (sc[SC_RESTART] > 0.0 && sc[SC_SINCE] >= sc[SC_RESTART]) sc[SC_DONE] = 3.0;
     }
 }
 
@@ -305,14 +275,14 @@ hipError_t launch_cg_setup(const Dev& d, double tol, int maxit, int restart, boo
 hipError_t launch_cg_spmv(const Dev& d, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_spmv, dim3(unsigned(d.ntiles)), dim3(d.tile_rows),
                        size_t(d.halo_max) * sizeof(double), s, d);
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, s, d, d.ntiles);
+    hipLaunchKernelGGL(k_cg_alpha<0>, dim3(1), dim3(1024), 0, s, d, d.ntiles);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_axpy(const Dev& d, hipStream_t s) {
     const int nb = grid_rows(d.nc);
     hipLaunchKernelGGL(k_cg_axpy, dim3(nb), dim3(kBlock), 0, s, d);
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(1024), 0, s, d, int64_t(nb));
+    hipLaunchKernelGGL(k_cg_beta<0>, dim3(1), dim3(1024), 0, s, d, int64_t(nb));
     return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@ struct Dev {
     int64_t ns, nvs;                      // 64-row slices of cells / vertices
     // cells
     double *vol, *xc;                     // xc: 3 x (nc+nb)
+    double4* xyz4;                        // nc+nb centres as (x, y, z, 0) records
+    double4* fx4;                         // nf face centroids as (x, y, z, 0) records
     double* minv;                         // 6 x nc
     int32_t *c2f, *c2n;                   // 4 x nc
     int64_t* s_off; int32_t* s_w; int32_t* s_idx;
@@ -41,6 +43,8 @@ struct Dev {
     // Poisson pattern and values
     int64_t* k_off; int32_t* k_w; int32_t* k_col; int32_t* k_len;
     double *k_val, *k_diag, *k_dinv, *k_c;
+    float *k_val32, *k_diag32, *k_dinv32;  // FP32 copy for the refined solve
+    float *d32, *r32, *z32, *p32, *q32;   // FP32 inner-CG vectors
     // LDS tiles: tile_rows consecutive cells and their halo
     int32_t tile_rows, halo_max;
     int64_t ntiles;
@@ -54,9 +58,19 @@ struct Dev {
     double *grad, *psi, *unode, *flux;    // grad 3 x nc
     // solver vectors (P lives in x)
     double *x, *r, *z, *p, *q, *b;
+    // reduced-precision (FP32) form of the step
+    float *u32, *un32, *src32, *phi32, *grad32, *psi32, *unode32, *flux32;
+    float *minv32, *kAC32, *kBC32, *kRL32, *area32, *vol32, *n_alpha32, *fx32, *xc32, *gdist32;
     double* tmp;                          // nc+nb scratch (permutation, residual)
     double* partial;                      // reduction partials ([k][block], k < 4)
     double* scal;                         // solver scalars (see solve_kernels)
+};
+
+// The arrays one precision of the step reads and writes.
+template <class R>
+struct FvArrays {
+    R *u, *un, *grad, *psi, *unode, *flux;
+    const R *phi, *minv, *kAC, *kBC, *kRL, *area, *vol, *src, *n_alpha, *fx, *xc, *gdist;
 };
 
 constexpr int kNumKernels = 11;
@@ -76,7 +90,9 @@ struct State {
     Dev d{};
     BcTable bc[2]{};                      // SCALAR, POTENTIAL
     double diffusivity = 0.0;
+    bool fp32 = false;                    // reduced-precision form of the step
     bool assembled = false;
+    bool k32_ready = false;               // FP32 copy of K matches K
     bool vel_set = false;
     double* h_scal = nullptr;             // pinned host mirror of scalars
     int nblk_cells = 0;                   // grid for per-cell reductions
@@ -87,18 +103,21 @@ struct State {
 size_t layout(const Mesh& m, char* base, Dev& d);
 
 // launchers (fv_kernels.hip)
-hipError_t launch_ghost_fill(const Dev& d, double* u, const BcTable& bc, hipStream_t s);
-hipError_t launch_grad_limiter(const Dev& d, hipStream_t s);
-hipError_t launch_face_flux(const Dev& d, const BcTable& bc, double D, hipStream_t s);
-hipError_t launch_update(const Dev& d, double a_dt, bool first_stage, hipStream_t s);
-hipError_t launch_residual_out(const Dev& d, double* res_internal, hipStream_t s);
+hipError_t launch_ghost_fill(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
+hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s);
+hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, double D, hipStream_t s);
+hipError_t launch_update(const Dev& d, bool fp32, double a_dt, bool first_stage, hipStream_t s);
+hipError_t launch_residual_out(const Dev& d, bool fp32, double* res_internal, hipStream_t s);
 hipError_t launch_face_phi(const Dev& d, hipStream_t s);
+hipError_t launch_make_fp32_geometry(const Dev& d, int64_t node_padded, hipStream_t s);
+hipError_t launch_cast_to_f32(int64_t n, const double* src, float* dst, hipStream_t s);
+hipError_t launch_cast_to_f64(int64_t n, const float* src, double* dst, hipStream_t s);
 hipError_t launch_to_internal(const int32_t* perm, int64_t n, int64_t stride_in, int64_t stride_out,
                               int comps, const double* src, double* dst, hipStream_t s);
 hipError_t launch_to_user(const int32_t* perm, int64_t n, int64_t stride_in, int64_t stride_out,
                           int comps, const double* src, double* dst, hipStream_t s);
 hipError_t launch_cfl(const Dev& d, const BcTable& bc, double D, int nblk, hipStream_t s);
-hipError_t launch_conservation(const Dev& d, int nblk, hipStream_t s);
+hipError_t launch_conservation(const Dev& d, bool fp32, int nblk, hipStream_t s);
 
 // launchers (solve_kernels.hip)
 hipError_t launch_assemble(const Dev& d, const BcTable& bc, int row_max, hipStream_t s);
@@ -109,10 +128,19 @@ hipError_t launch_cg_spmv(const Dev& d, hipStream_t s);
 hipError_t launch_cg_axpy(const Dev& d, hipStream_t s);
 hipError_t launch_cg_dir(const Dev& d, hipStream_t s);
 
+// launchers (ir_kernels.hip): FP32 inner CG inside FP64 iterative refinement
+hipError_t launch_cast_matrix(const Dev& d, int64_t padded, hipStream_t s);
+hipError_t launch_ir_residual(const Dev& d, double tol, double tol_in, int maxit, int restart, bool fresh,
+                              hipStream_t s);
+hipError_t launch_cg32_spmv(const Dev& d, hipStream_t s);
+hipError_t launch_cg32_axpy(const Dev& d, hipStream_t s);
+hipError_t launch_cg32_dir(const Dev& d, hipStream_t s);
+hipError_t launch_ir_update(const Dev& d, hipStream_t s);
+
 // scalar slots in Dev::scal
 enum Scal {
     SC_RZ = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_BB, SC_TOL2BB, SC_DONE, SC_IT, SC_MAXIT,
-    SC_TRUE_RR, SC_CONS, SC_DT_INV, SC_RESTART, SC_SINCE, SC_COUNT_ = 16
+    SC_TRUE_RR, SC_CONS, SC_DT_INV, SC_RESTART, SC_SINCE, SC_TOL2BB_OUT, SC_COUNT_ = 32
 };
 
 }  // namespace mifvm

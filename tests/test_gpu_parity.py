@@ -219,3 +219,81 @@ def test_error_codes():
     with pytest.raises(B.MifvmError) as e:
         st.step(-1, 1e-3)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("inner_tol", [1e-2, 1e-4])
+def test_refined_fp32_solve_accepted_by_oracle(inner_tol):
+    """Precision form of the solve: FP32 inner CG inside FP64 iterative
+    refinement must reach the same 1e-10 true residual, judged by the
+    oracle's FP64 matrix."""
+    n, seed, kinds, vals = POISSON["config1"]
+    mp = Mapped(n, seed)
+    g = mp.geo
+    st = B.State(mp.lib)
+    st.set_bcs(B.VAR_POTENTIAL, kinds, vals)
+    st.poisson_assemble()
+    f = synth.gaussian_field(mp.m)
+    info = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_IR_FP32, inner_tol=inner_tol)
+    assert info["status"] == B.OK and info["rel_residual"] <= 1e-10 and info["outer"] >= 2
+    K, c = poisson.assemble(g, kinds, vals)
+    b = poisson.rhs(g, f, c)
+    x = host(st.get_field(B.FIELD_P))
+    assert poisson.true_relative_residual(K, b, x) <= 1.01e-10
+    xo, _, _ = poisson.jacobi_cg(K, b, tol=1e-12)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-7
+
+
+def test_refined_fp32_solve_mixed_boundaries():
+    n, seed, kinds, vals = POISSON["ragged_mixed"]
+    mp = Mapped(n, seed)
+    st = B.State(mp.lib)
+    st.set_bcs(B.VAR_POTENTIAL, kinds, vals)
+    st.poisson_assemble()
+    f = synth.gaussian_field(mp.m)
+    info = st.poisson_solve(dev(f), tol=1e-12, method=B.SOLVE_IR_FP32)
+    K, c = poisson.assemble(mp.geo, kinds, vals)
+    x = host(st.get_field(B.FIELD_P))
+    assert info["status"] == B.OK
+    assert poisson.true_relative_residual(K, poisson.rhs(mp.geo, f, c), x) <= 1.01e-12
+
+
+def test_precision_form_config1_reports_error_per_step():
+    """Reduced-precision form on the 48,000-cell benchmark mesh: FP32 fluxes,
+    gradients and state, FP64 conservation sum; then the FP32-refined solve
+    of the potential.  The per-step error of u against the FP64 oracle is
+    printed and bounded: FP32 rounding (6e-8) amplified by the gradient's
+    relative coordinates (~1e-6 per step) over 10 steps gives < 1e-5."""
+    mp = Mapped(20, 1)
+    g = mp.geo
+    pf = synth.problem_fields(mp.m)
+    kinds, vals = [ZERO_FLUX] * 6, [0.0] * 6
+    st = B.State(mp.lib, diffusivity=pf.diffusivity, precision=B.FP32)
+    st.set_bcs(B.VAR_SCALAR, kinds, vals)
+    st.set_bcs(B.VAR_POTENTIAL, [DIRICHLET] * 6)
+    st.set_field(B.FIELD_VEL, dev(pf.vel.T.ravel()))
+    st.set_field(B.FIELD_U, dev(pf.u0))
+    phi = fv.face_velocity_flux(g, pf.vel)
+    dt = fv.cfl_dt(g, phi, pf.diffusivity, 0.4, kinds)
+    assert abs(st.cfl_dt(0.4) - dt) <= 1e-14 * dt
+    u = pf.u0.copy()
+    t0 = fv.conservation_total(g, u)
+    errs = []
+    for k in range(10):
+        st.step(1, dt)
+        u = fv.rk3_step(g, u, dt, phi, pf.diffusivity, kinds, vals)
+        errs.append(rel(host(st.get_field(B.FIELD_U)), u))
+    print("[gpu] fp32 form: per-step rel. error of u:", " ".join(f"{e:.2e}" for e in errs))
+    assert max(errs) < 1e-5 and errs[-1] > 0
+    # conservation: FP32 rounding of the state, summed in FP64
+    assert abs(st.conservation() - t0) <= 1e-6 * abs(t0)
+    st.poisson_assemble()
+    info = st.poisson_solve(None, tol=1e-10, method=B.SOLVE_IR_FP32)
+    assert info["status"] == B.OK
+    K, c = poisson.assemble(g, [DIRICHLET] * 6, [0.0] * 6)
+    u_gpu = host(st.get_field(B.FIELD_U))
+    x = host(st.get_field(B.FIELD_P))
+    assert poisson.true_relative_residual(K, poisson.rhs(g, u_gpu, c), x) <= 1.01e-10
+    xo, _, _ = poisson.jacobi_cg(K, poisson.rhs(g, u, c), tol=1e-12)
+    perr = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"[gpu] fp32 form: potential rel. error vs FP64 oracle {perr:.2e}")
+    assert perr < 1e-4
