@@ -135,6 +135,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cube120")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the reduced-precision (FP32 + refined solve) run")
     ap.add_argument("--calibrate-copy-gb", type=float, default=0.0,
                     help="first run one device-to-device copy of this many GB (a kernel of "
                          "known traffic, to scale hardware byte counters)")
@@ -261,10 +263,66 @@ def main():
         "roofline_fv": {k: roof(k) for k in ("grad_limiter", "face_flux", "update")},
         "roofline_cg": {k: roof(k) for k in ("cg_axpy", "cg_dir")},
     }
+    if not args.no_forms:
+        u64 = st.get_field(B.FIELD_U)
+        p64 = st.get_field(B.FIELD_P)
+        torch.cuda.synchronize()
+        del st
+        torch.cuda.empty_cache()
+        result["forms"] = {"fp32_refined": run_fp32_form(args, M, pf, u64, p64)}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def run_fp32_form(args, M, pf, u64, p64):
+    """The same steps in the reduced-precision form: FP32 step kernels and the
+    FP32-inner, FP64-refined Poisson solve.  Errors are against the FP64 run
+    after the same number of steps (same inputs, same dt)."""
+    import numpy as np
+    import torch
+    from paper_2203_00925_amd import binding as B
+    st = B.State(M, diffusivity=pf.diffusivity, precision=B.FP32)
+    st.set_bcs(B.VAR_SCALAR, [B.ZERO_FLUX] * 6)
+    st.set_bcs(B.VAR_POTENTIAL, [B.DIRICHLET] * 6)
+    st.set_field(B.FIELD_VEL, torch.from_numpy(np.ascontiguousarray(pf.vel.T.ravel())))
+    st.set_field(B.FIELD_U, torch.from_numpy(pf.u0))
+    st.poisson_assemble()
+    dt = st.cfl_dt(pf.cfl)
+    stream = torch.cuda.current_stream()
+    solve_kw = dict(tol=1e-10, restart=500, method=B.SOLVE_IR_FP32, inner_tol=1e-2)
+    for w in range(args.warmup):
+        st.step(1, dt)
+        s = st.poisson_solve(None, **solve_kw)
+        log(f"fp32 form warmup {w}: solve {s['iterations']} it, {s['outer']} outer, {s['ms']:.1f} ms")
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    solves = []
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        st.step(1, dt)
+        ev[k][1].record(stream)
+        solves.append(st.poisson_solve(None, **solve_kw))
+        ev[k][2].record(stream)
+        log(f"fp32 form step {k}: solve {solves[-1]['iterations']} it, {solves[-1]['outer']} outer")
+    torch.cuda.synchronize()
+    fv_ms = sum(e[0].elapsed_time(e[1]) for e in ev)
+    solve_ms = sum(e[1].elapsed_time(e[2]) for e in ev)
+    u = st.get_field(B.FIELD_U)
+    p = st.get_field(B.FIELD_P)
+    torch.cuda.synchronize()
+    uerr = float((u - u64).abs().max() / u64.abs().max())
+    perr = float((p - p64).norm() / p64.norm())
+    del st
+    return {"fv_cell_updates_per_s": M.info.nc * args.steps / (fv_ms / 1e3),
+            "fv_ms_per_step": fv_ms / args.steps,
+            "poisson_solve_ms": solve_ms / args.steps,
+            "poisson_inner_iterations": [s["iterations"] for s in solves],
+            "poisson_outer_steps": [s["outer"] for s in solves],
+            "poisson_rel_residual": max(s["rel_residual"] for s in solves),
+            "u_max_rel_err_vs_fp64": uerr, "P_rel_err_vs_fp64": perr,
+            "dtype": "f32 step; f32 inner CG with f64 residual, dots and refinement"}
 
 
 if __name__ == "__main__":

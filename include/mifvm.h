@@ -80,6 +80,11 @@ typedef struct mifvm_state mifvm_state;   /* device-resident mesh + fields   */
 
 typedef struct {
     int32_t renumber;          /* enum mifvm_renumber                         */
+    int32_t nmeshes;           /* independent meshes in the tets array (>=1)  */
+    const int64_t* mesh_cell_start;  /* nmeshes+1 offsets into tets; mesh m is
+                                  tets[start[m]:start[m+1]]; NULL when
+                                  nmeshes <= 1.  Meshes of a batch share no
+                                  face; each needs >= 256 cells.             */
 } mifvm_mesh_opts;
 
 typedef struct {
@@ -88,6 +93,8 @@ typedef struct {
     int64_t nf;                /* faces (interior first, then boundary)       */
     int64_t nf_interior;
     int64_t nb;                /* boundary faces = ghost cells                */
+    int32_t nmeshes;           /* independent meshes (batch size)             */
+    int32_t pad0_;
     int64_t stencil_entries;   /* node-neighbour entries (unpadded)           */
     int64_t stencil_padded;    /* stored entries after 64-row slicing         */
     int64_t node_entries;      /* vertex->cell/ghost entries (unpadded)       */
@@ -199,18 +206,22 @@ void mifvm_state_destroy(mifvm_state* st);
 /* kind/value for one boundary tag of one variable; takes effect at the next
  * step (SCALAR) or assemble (POTENTIAL).  Default: ZERO_FLUX, 0.           */
 int mifvm_set_bc(mifvm_state* st, int32_t var, int32_t tag, int32_t kind, double value);
-int mifvm_set_diffusivity(mifvm_state* st, double diffusivity);
+int mifvm_set_diffusivity(mifvm_state* st, double diffusivity);          /* every mesh */
+/* one diffusivity per mesh of a batch (n = nmeshes).  Synchronises.        */
+int mifvm_set_mesh_diffusivity(mifvm_state* st, const double* D, int32_t n);
 /* d_src: float64 in user cell order (3*nc for VEL).  Setting VEL recomputes
  * the face velocity fluxes phi_f = 1/2 (V_L + V_R) . S_f.                  */
 int mifvm_set_field(mifvm_state* st, int32_t field, const double* d_src, void* stream);
 int mifvm_get_field(const mifvm_state* st, int32_t field, double* d_dst, void* stream);
 
 /* ---- step (eq. (4) with the Runge-Kutta scheme of eq. (6)) ---------------
- * dt = cfl * min_i mu_i / sum_{faces of i not ZERO_FLUX} (|phi_f| + D kRL_f).
- * Synchronises.                                                            */
+ * Per mesh: dt_m = cfl * min_i mu_i / sum_{faces of i not ZERO_FLUX}
+ * (|phi_f| + D_m kRL_f); returns the smallest and keeps every dt_m for
+ * steps called with dt = 0.  Synchronises.                                 */
 int mifvm_cfl_dt(mifvm_state* st, double cfl, double* dt_out, void* stream);
 /* n_steps explicit 3-stage steps u^(k) = u^n + a_k dt Res(u^(k-1)),
- * a = (1/2, 1/2, 1).  Asynchronous.                                        */
+ * a = (1/2, 1/2, 1); dt > 0 for every mesh, dt = 0 for each mesh's own CFL
+ * step (E_STATE before any mifvm_cfl_dt).  Asynchronous.                   */
 int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream);
 /* One evaluation of Res(U) and its parts, for inspection; any output may be
  * NULL.  d_res, d_psi [nc], d_grad [3][nc] in user cell order; d_unode [nv]
@@ -218,8 +229,13 @@ int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream);
  * each face's cells).                                                      */
 int mifvm_residual(mifvm_state* st, double* d_res, double* d_grad, double* d_psi,
                    double* d_unode, double* d_flux, void* stream);
-/* sum_i mu_i u_i in FP64, deterministic order.  Synchronises.              */
+/* sum_i mu_i u_i in FP64 over all meshes (per mesh, deterministic order,
+ * then the meshes in order).  Synchronises.                                */
 int mifvm_conservation(mifvm_state* st, double* total_out, void* stream);
+/* Per-mesh results of the last call that produced them (n = nmeshes):
+ * what 0 = dt_m of mifvm_cfl_dt, 1 = conservation total, 2 = iterations of
+ * the last solve, 3 = its true relative residual.                          */
+int mifvm_mesh_values(const mifvm_state* st, int32_t what, double* out, int32_t n);
 
 /* ---- Poisson (LinearSystem.assembly() / .solve()) ------------------------
  * Assemble K and the ghost-constant vector c of K P = -mu*f + c, from the
@@ -237,7 +253,9 @@ int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* str
  * tol 1e-10, maxit 20000, chunk 32, restart 500.  A restart
  * recomputes r = b - K x and sets p = D^-1 r.  With method IR_FP32,
  * `iterations` counts FP32 inner iterations and every outer step restarts
- * the inner CG.  Returns NOT_CONVERGED at maxit.
+ * the inner CG.  On a batch every mesh runs its own CG (own scalars and
+ * stopping test); info reports the largest iteration count and residual.
+ * Returns NOT_CONVERGED at maxit.
  * Synchronises (once per chunk).                                           */
 int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_opts* opts,
                         mifvm_solve_info* info, void* stream);

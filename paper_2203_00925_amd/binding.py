@@ -54,12 +54,14 @@ class MifvmError(RuntimeError):
 
 
 class _MeshOpts(C.Structure):
-    _fields_ = [("renumber", C.c_int32)]
+    _fields_ = [("renumber", C.c_int32), ("nmeshes", C.c_int32),
+                ("mesh_cell_start", C.c_void_p)]
 
 
 class MeshInfo(C.Structure):
     _fields_ = [("nc", C.c_int64), ("nv", C.c_int64), ("nf", C.c_int64),
-                ("nf_interior", C.c_int64), ("nb", C.c_int64),
+                ("nf_interior", C.c_int64), ("nb", C.c_int64), ("nmeshes", C.c_int32),
+                ("pad0_", C.c_int32),
                 ("stencil_entries", C.c_int64), ("stencil_padded", C.c_int64),
                 ("node_entries", C.c_int64), ("matrix_nnz", C.c_int64),
                 ("matrix_padded", C.c_int64), ("stencil_max", C.c_int32),
@@ -102,6 +104,8 @@ def _load():
         "mifvm_state_destroy": (None, [P]),
         "mifvm_set_bc": (C.c_int, [P, I32, I32, I32, D]),
         "mifvm_set_diffusivity": (C.c_int, [P, D]),
+        "mifvm_set_mesh_diffusivity": (C.c_int, [P, P, I32]),
+        "mifvm_mesh_values": (C.c_int, [P, I32, P, I32]),
         "mifvm_set_field": (C.c_int, [P, I32, P, P]),
         "mifvm_get_field": (C.c_int, [P, I32, P, P]),
         "mifvm_cfl_dt": (C.c_int, [P, D, C.POINTER(D), P]),
@@ -150,13 +154,18 @@ def _stream(stream):
 class Mesh:
     """Host-side preprocessed mesh (mifvm_mesh_preprocess)."""
 
-    def __init__(self, xyz, tets, btris, btags, renumber=RENUMBER_MORTON):
+    def __init__(self, xyz, tets, btris, btags, renumber=RENUMBER_MORTON, mesh_cell_start=None):
         xyz = np.ascontiguousarray(xyz, np.float64)
         tets = np.ascontiguousarray(tets, np.int32)
         btris = np.ascontiguousarray(btris, np.int32)
         btags = np.ascontiguousarray(btags, np.int32)
         h = C.c_void_p()
-        opts = _MeshOpts(renumber)
+        if mesh_cell_start is not None:
+            starts = np.ascontiguousarray(mesh_cell_start, np.int64)
+            opts = _MeshOpts(renumber, len(starts) - 1, starts.ctypes.data)
+        else:
+            starts = None
+            opts = _MeshOpts(renumber, 1, None)
         _check(_lib.mifvm_mesh_preprocess(
             xyz.ctypes.data, len(xyz), tets.ctypes.data, len(tets),
             btris.ctypes.data, btags.ctypes.data, len(btags), C.byref(opts), C.byref(h)))
@@ -167,6 +176,18 @@ class Mesh:
     @classmethod
     def from_cube(cls, m, renumber=RENUMBER_MORTON):
         return cls(m.xyz, m.tets, m.btris, m.btags, renumber)
+
+    @classmethod
+    def from_batch(cls, meshes, renumber=RENUMBER_MORTON):
+        """Independent meshes as one batch: vertex ids of mesh k are offset by
+        the vertices of meshes 0..k-1; cells stay in mesh order."""
+        voff = np.cumsum([0] + [m.nv for m in meshes])
+        coff = np.cumsum([0] + [m.nc for m in meshes])
+        xyz = np.concatenate([m.xyz for m in meshes])
+        tets = np.concatenate([m.tets + voff[k] for k, m in enumerate(meshes)])
+        btris = np.concatenate([m.btris + voff[k] for k, m in enumerate(meshes)])
+        btags = np.concatenate([m.btags for m in meshes])
+        return cls(xyz, tets, btris, btags, renumber, mesh_cell_start=coff)
 
     def export(self, name):
         what = EXPORT_IDS[name]
@@ -217,6 +238,17 @@ class State:
 
     def set_diffusivity(self, D):
         _check(_lib.mifvm_set_diffusivity(self._h, float(D)))
+
+    def set_mesh_diffusivity(self, Ds):
+        a = np.ascontiguousarray(Ds, np.float64)
+        _check(_lib.mifvm_set_mesh_diffusivity(self._h, a.ctypes.data, len(a)))
+
+    def mesh_values(self, what):
+        """Per-mesh results: 'dt', 'conservation', 'iterations', 'rel_residual'."""
+        ids = {"dt": 0, "conservation": 1, "iterations": 2, "rel_residual": 3}
+        out = np.empty(self.mesh.info.nmeshes, np.float64)
+        _check(_lib.mifvm_mesh_values(self._h, ids[what], out.ctypes.data, len(out)))
+        return out
 
     def set_field(self, field, t, stream=None):
         import torch

@@ -192,9 +192,14 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.xc32 = carve<float>(base, off, 3 * NX);
     d.gdist32 = carve<float>(base, off, nb);
     d.tmp = carve<double>(base, off, 3 * NX);
-    const int64_t nblk = (nc + kBlock - 1) / kBlock;
-    d.partial = carve<double>(base, off, 4 * (nblk + 1024));
-    d.scal = carve<double>(base, off, SC_COUNT_);
+    // per-block partials of up to 4 sums x 2 mesh slots, for blocks of >= 64 rows
+    const int64_t nblk = (nc + 63) / 64;
+    d.partial = carve<double>(base, off, 8 * (nblk + 1024));
+    d.nm = int32_t(m.mesh_start.size() - 1);
+    d.mesh_start = carve<int64_t>(base, off, m.mesh_start.size());
+    d.mesh_D = carve<double>(base, off, d.nm);
+    d.mesh_dt = carve<double>(base, off, d.nm);
+    d.scal = carve<double>(base, off, size_t(d.nm) * SC_COUNT_);
     return (off + 255) & ~size_t(255);
 }
 
@@ -217,7 +222,8 @@ int mifvm_mesh_preprocess(const double* xyz, int64_t nv, const int32_t* tets, in
     std::string err;
     int rc;
     try {
-        rc = preprocess(xyz, nv, tets, nc, btris, btags, nb, opts ? opts->renumber : 1, h->m, err);
+        rc = preprocess(xyz, nv, tets, nc, btris, btags, nb, opts ? opts->renumber : 1,
+                        opts ? opts->mesh_cell_start : nullptr, opts ? opts->nmeshes : 1, h->m, err);
     } catch (const std::bad_alloc&) {
         rc = MIFVM_E_ARG;
         err = "out of host memory";
@@ -235,6 +241,7 @@ int mifvm_mesh_get_info(const mifvm_mesh* mesh, mifvm_mesh_info* out) {
     const Mesh& m = mesh->m;
     std::memset(out, 0, sizeof(*out));
     out->nc = m.nc; out->nv = m.nv; out->nf = m.nf; out->nf_interior = m.nfi; out->nb = m.nb;
+    out->nmeshes = int32_t(m.mesh_start.size() - 1);
     out->stencil_entries = (int64_t)m.sidx.size();
     out->stencil_padded = (int64_t)m.stencil.idx.size();
     out->node_entries = (int64_t)m.nidx.size();
@@ -324,7 +331,8 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
         delete h;
         return rc;
     };
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&st.h_scal), SC_COUNT_ * sizeof(double), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&st.h_scal),
+                                 size_t(st.d.nm) * SC_COUNT_ * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipHostMalloc"));
 #define UP(dst, vec)                                            \
     do {                                                        \
@@ -340,6 +348,14 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     UP(d.k_off, m.kmat.off); UP(d.k_w, m.kmat.width); UP(d.k_col, m.kmat.idx); UP(d.k_len, m.klen);
     UP(d.cell_perm, m.cell_perm); UP(d.vert_perm, m.vert_perm);
     UP(d.h_off, m.h_off); UP(d.h_idx, m.h_idx); UP(d.h_self, m.h_self);
+    UP(d.mesh_start, m.mesh_start);
+    {
+        const std::vector<double> Dm(d.nm, st.diffusivity), zero(d.nm, 0.0);
+        UP(d.mesh_D, Dm);
+        UP(d.mesh_dt, zero);
+        e = hipStreamSynchronize(s);                       // Dm/zero are freed at scope exit
+        if (e != hipSuccess) return cleanup(hip_fail(e, "upload mesh parameters"));
+    }
     UP(d.s_lidx, m.s_lidx); UP(d.k_lidx, m.k_lidx); UP(d.c2n_l, m.c2n_l);
     UP(d.n_lidx, m.n_lidx); UP(d.v_off, m.v_off);
     {   // packed records of the centres and face centroids (gathered by tiles)
@@ -363,7 +379,7 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     if (e == hipSuccess) e = hipMemsetAsync(d.vel, 0, 3 * m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.phi, 0, m.nf * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.x, 0, m.nc * sizeof(double), s);
-    if (e == hipSuccess) e = hipMemsetAsync(d.scal, 0, SC_COUNT_ * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.scal, 0, size_t(d.nm) * SC_COUNT_ * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.u32, 0, NX * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.src32, 0, m.nc * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.phi32, 0, m.nf * sizeof(float), s);
@@ -417,11 +433,28 @@ int mifvm_set_bc(mifvm_state* st, int32_t var, int32_t tag, int32_t kind, double
     return MIFVM_OK;
 }
 
+namespace {
+int upload_mesh_D(State& s, const std::vector<double>& Dm) {
+    HIPCHK(hipDeviceSynchronize());           // order against work on any stream
+    HIPCHK(hipMemcpy(s.d.mesh_D, Dm.data(), Dm.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipDeviceSynchronize());
+    return MIFVM_OK;
+}
+}  // namespace
+
 int mifvm_set_diffusivity(mifvm_state* st, double D) {
     if (!st) return fail(MIFVM_E_ARG, "null state");
     if (!(D >= 0) || !std::isfinite(D)) return fail(MIFVM_E_ARG, "diffusivity must be finite and >= 0");
     st->s.diffusivity = D;
-    return MIFVM_OK;
+    return upload_mesh_D(st->s, std::vector<double>(st->s.d.nm, D));
+}
+
+int mifvm_set_mesh_diffusivity(mifvm_state* st, const double* D, int32_t n) {
+    if (!st || !D) return fail(MIFVM_E_ARG, "null argument");
+    if (n != st->s.d.nm) return fail(MIFVM_E_ARG, "need one diffusivity per mesh");
+    for (int32_t m = 0; m < n; ++m)
+        if (!(D[m] >= 0) || !std::isfinite(D[m])) return fail(MIFVM_E_ARG, "diffusivity must be finite and >= 0");
+    return upload_mesh_D(st->s, std::vector<double>(D, D + n));
 }
 
 int mifvm_set_field(mifvm_state* st, int32_t field, const double* d_src, void* stream) {
@@ -474,17 +507,33 @@ int mifvm_get_field(const mifvm_state* st, int32_t field, double* d_dst, void* s
     return MIFVM_OK;
 }
 
+namespace {
+// copy every mesh's scalars to the pinned host mirror and wait
+int pull_scalars(State& s, hipStream_t hs) {
+    HIPCHK(hipMemcpyAsync(s.h_scal, s.d.scal, size_t(s.d.nm) * SC_COUNT_ * sizeof(double),
+                          hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipStreamSynchronize(hs));
+    return MIFVM_OK;
+}
+inline double hsc(const State& s, int m, int slot) { return s.h_scal[size_t(m) * SC_COUNT_ + slot]; }
+}  // namespace
+
 int mifvm_cfl_dt(mifvm_state* st, double cfl, double* dt_out, void* stream) {
     if (!st || !dt_out) return fail(MIFVM_E_ARG, "null argument");
     if (!(cfl > 0)) return fail(MIFVM_E_ARG, "cfl must be > 0");
     State& s = st->s;
     hipStream_t hs = S(stream);
-    HIPCHK(launch_cfl(s.d, s.bc[0], s.diffusivity, s.nblk_cells, hs));
-    HIPCHK(hipMemcpyAsync(s.h_scal, s.d.scal, SC_COUNT_ * sizeof(double), hipMemcpyDeviceToHost, hs));
-    HIPCHK(hipStreamSynchronize(hs));
-    const double m = s.h_scal[SC_DT_INV];
-    if (!std::isfinite(m)) return fail(MIFVM_E_STATE, "no active face: time step unbounded");
-    *dt_out = cfl * m;
+    HIPCHK(launch_cfl(s.d, *s.mesh, s.bc[0], hs));
+    int rc = pull_scalars(s, hs);
+    if (rc) return rc;
+    double dmin = __builtin_huge_val();
+    for (int m = 0; m < s.d.nm; ++m) {
+        const double v = hsc(s, m, SC_DT_INV);
+        if (!std::isfinite(v)) return fail(MIFVM_E_STATE, "no active face: time step unbounded");
+        dmin = std::fmin(dmin, cfl * v);
+    }
+    s.cfl = cfl;
+    *dt_out = dmin;
     return MIFVM_OK;
 }
 
@@ -495,8 +544,7 @@ int residual_parts(State& s, hipStream_t hs) {
     KernelTimer& t = s.timer;
     HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, s.fp32, s.bc[0], hs); }));
     HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, s.fp32, hs); }));
-    HIPCHK(timed(t, MIFVM_K_FACE_FLUX, hs,
-                 [&] { return launch_face_flux(d, s.fp32, s.bc[0], s.diffusivity, hs); }));
+    HIPCHK(timed(t, MIFVM_K_FACE_FLUX, hs, [&] { return launch_face_flux(d, s.fp32, s.bc[0], hs); }));
     return MIFVM_OK;
 }
 }  // namespace
@@ -506,13 +554,15 @@ int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream) {
     if (n_steps < 0 || !(dt >= 0) || !std::isfinite(dt)) return fail(MIFVM_E_ARG, "bad n_steps or dt");
     State& s = st->s;
     hipStream_t hs = S(stream);
+    if (dt == 0.0 && !(s.cfl > 0)) return fail(MIFVM_E_STATE, "dt = 0 asks for the CFL steps: call mifvm_cfl_dt first");
+    if (n_steps > 0) HIPCHK(launch_set_dt(s.d, dt, s.cfl, hs));
     static const double alpha[3] = {0.5, 0.5, 1.0};
     for (int n = 0; n < n_steps; ++n)
         for (int k = 0; k < 3; ++k) {
             int rc = residual_parts(s, hs);
             if (rc) return rc;
             HIPCHK(timed(s.timer, MIFVM_K_UPDATE, hs,
-                         [&] { return launch_update(s.d, s.fp32, alpha[k] * dt, k == 0, hs); }));
+                         [&] { return launch_update(s.d, s.fp32, alpha[k], k == 0, hs); }));
         }
     if (n_steps > 0)
         HIPCHK(timed(s.timer, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(s.d, s.fp32, s.bc[0], hs); }));
@@ -554,10 +604,12 @@ int mifvm_conservation(mifvm_state* st, double* total_out, void* stream) {
     if (!st || !total_out) return fail(MIFVM_E_ARG, "null argument");
     State& s = st->s;
     hipStream_t hs = S(stream);
-    HIPCHK(launch_conservation(s.d, s.fp32, s.nblk_cells, hs));
-    HIPCHK(hipMemcpyAsync(s.h_scal, s.d.scal, SC_COUNT_ * sizeof(double), hipMemcpyDeviceToHost, hs));
-    HIPCHK(hipStreamSynchronize(hs));
-    *total_out = s.h_scal[SC_CONS];
+    HIPCHK(launch_conservation(s.d, *s.mesh, s.fp32, hs));
+    int rc = pull_scalars(s, hs);
+    if (rc) return rc;
+    double total = 0.0;
+    for (int m = 0; m < s.d.nm; ++m) total += hsc(s, m, SC_CONS);
+    *total_out = total;
     return MIFVM_OK;
 }
 
@@ -622,41 +674,52 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         return fail(MIFVM_E_ARG, "bad tol, maxit, restart, inner_tol or history");
     if (method != MIFVM_SOLVE_PLAIN && method != MIFVM_SOLVE_IR_FP32) return fail(MIFVM_E_ARG, "unknown method");
     const Dev& d = s.d;
+    const int nm = d.nm;
     hipStream_t hs = S(stream);
     auto t0 = std::chrono::steady_clock::now();
     int rc = rhs_internal(s, d_f, hs);
     if (rc) return rc;
     KernelTimer& tm = s.timer;
     int nhist = 0;
+    // every mesh's scalars to the host; the history records the largest
+    // recurrence residual over the meshes
     auto pull = [&]() -> int {
-        HIPCHK(hipMemcpyAsync(s.h_scal, d.scal, SC_COUNT_ * sizeof(double), hipMemcpyDeviceToHost, hs));
-        HIPCHK(hipStreamSynchronize(hs));
+        int r = pull_scalars(s, hs);
+        if (r) return r;
         HIPCHK(timer_flush(tm));
-        const double bb = s.h_scal[SC_BB];
-        if (nhist < hist_cap) hist[nhist++] = bb > 0 ? std::sqrt(s.h_scal[SC_RR] / bb) : 0.0;
+        if (nhist < hist_cap) {
+            double worst = 0.0;
+            for (int m = 0; m < nm; ++m) {
+                const double bb = hsc(s, m, SC_BB);
+                if (bb > 0) worst = std::fmax(worst, std::sqrt(hsc(s, m, SC_RR) / bb));
+            }
+            hist[nhist++] = worst;
+        }
         return MIFVM_OK;
+    };
+    auto any_running = [&]() {
+        for (int m = 0; m < nm; ++m)
+            if (hsc(s, m, SC_DONE) == 0.0) return true;
+        return false;
     };
     int restarts = 0, outer = 0;
     if (method == MIFVM_SOLVE_PLAIN) {
         HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, true, hs); }));
         if ((rc = pull())) return rc;
-        if (s.h_scal[SC_BB] != 0.0) {
-            for (;;) {
-                while (s.h_scal[SC_DONE] == 0.0) {
-                    for (int c = 0; c < chunk; ++c) {
-                        HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
-                        HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
-                        HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
-                    }
-                    if ((rc = pull())) return rc;
+        while (any_running()) {
+            while (any_running()) {
+                for (int c = 0; c < chunk; ++c) {
+                    HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
+                    HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
+                    HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
                 }
-                // recurrence converged, limit reached or restart due: recompute the
-                // true residual r = b - K x (FP64) and reopen from it
-                HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, false, hs); }));
                 if ((rc = pull())) return rc;
-                if (s.h_scal[SC_DONE] != 0.0) break;      // converged on the true residual, or maxit
-                ++restarts;
             }
+            // every mesh's recurrence converged, reached its limit or is due a
+            // restart: recompute the true residual r = b - K x (FP64) and reopen
+            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, false, hs); }));
+            if ((rc = pull())) return rc;
+            if (any_running()) ++restarts;
         }
     } else {
         if (!s.k32_ready) {
@@ -669,8 +732,8 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
                          [&] { return launch_ir_residual(d, tol, tol_in, maxit, restart, fresh, hs); }));
             fresh = false;
             if ((rc = pull())) return rc;
-            if (s.h_scal[SC_BB] == 0.0 || s.h_scal[SC_DONE] != 0.0) break;   // converged, or maxit
-            while (s.h_scal[SC_DONE] == 0.0) {
+            if (!any_running()) break;                   // every mesh converged, or at its limit
+            while (any_running()) {
                 for (int c = 0; c < chunk; ++c) {
                     HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg32_spmv(d, hs); }));
                     HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg32_axpy(d, hs); }));
@@ -682,13 +745,23 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
             ++outer;
         }
     }
-    if (s.h_scal[SC_BB] == 0.0) {       // b = 0: the solution is 0
-        HIPCHK(hipMemsetAsync(d.x, 0, d.nc * sizeof(double), hs));
-        HIPCHK(hipStreamSynchronize(hs));
+    // per-mesh outcome; b = 0 on a mesh: its solution is 0
+    s.last_iters.assign(nm, 0);
+    s.last_rel.assign(nm, 0.0);
+    int iters = 0;
+    double rel = 0.0;
+    for (int m = 0; m < nm; ++m) {
+        const double bb = hsc(s, m, SC_BB);
+        if (bb == 0.0) {
+            const int64_t lo = s.mesh->mesh_start[m], hi = s.mesh->mesh_start[m + 1];
+            HIPCHK(hipMemsetAsync(d.x + lo, 0, (hi - lo) * sizeof(double), hs));
+        }
+        s.last_rel[m] = bb > 0 ? std::sqrt(hsc(s, m, SC_TRUE_RR) / bb) : 0.0;
+        s.last_iters[m] = int(hsc(s, m, SC_IT));
+        iters = std::max(iters, s.last_iters[m]);
+        rel = std::fmax(rel, s.last_rel[m]);
     }
-    const double bb = s.h_scal[SC_BB];
-    const double rel = bb > 0 ? std::sqrt(s.h_scal[SC_TRUE_RR] / bb) : 0.0;
-    const int iters = int(s.h_scal[SC_IT]);
+    HIPCHK(hipStreamSynchronize(hs));
     if (info) {
         info->iterations = iters;
         info->restarts = restarts;
@@ -698,6 +771,22 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     if (!(rel <= tol)) return MIFVM_NOT_CONVERGED;
+    return MIFVM_OK;
+}
+
+int mifvm_mesh_values(const mifvm_state* st, int32_t what, double* out, int32_t n) {
+    if (!st || !out) return fail(MIFVM_E_ARG, "null argument");
+    const State& s = st->s;
+    if (n != s.d.nm) return fail(MIFVM_E_ARG, "need one value per mesh");
+    for (int m = 0; m < n; ++m) {
+        switch (what) {
+            case 0: out[m] = s.cfl * hsc(s, m, SC_DT_INV); break;
+            case 1: out[m] = hsc(s, m, SC_CONS); break;
+            case 2: out[m] = m < int(s.last_iters.size()) ? double(s.last_iters[m]) : 0.0; break;
+            case 3: out[m] = m < int(s.last_rel.size()) ? s.last_rel[m] : 0.0; break;
+            default: return fail(MIFVM_E_ARG, "unknown value id");
+        }
+    }
     return MIFVM_OK;
 }
 

@@ -1,35 +1,38 @@
 // Scalar steps of a CG iteration, shared by the FP64 and FP32-inner solvers:
-// one-block kernels that reduce the per-block partials (in index order) and
-// update the device-resident scalars.  Templates so that every translation
-// unit instantiates its own copy.
+// one 1024-thread block per mesh reduces that mesh's partial sums (in block
+// order) and updates its device-resident scalars.  Templates so that every
+// translation unit instantiates its own copy.
 #pragma once
-#include "reduce.h"
+#include "seg.h"
 #include "state.h"
 
 namespace mifvm {
 
 // alpha = rz / (p . q)
 template <int Unused>
-__global__ __launch_bounds__(1024) void k_cg_alpha(Dev d, int64_t nparts) {
+__global__ __launch_bounds__(1024) void k_cg_alpha(Dev d, int64_t nparts, int64_t rows_per_block) {
     __shared__ double lds[16];
-    if (d.scal[SC_DONE] != 0.0) return;
-    const double pq = reduce_partials_sum(d.partial, nparts, lds);
+    const int m = blockIdx.x;
+    double* sc = msc(d, m);
+    if (sc[SC_DONE] != 0.0) return;
+    const double pq = seg_sum(d, 0, m, nparts, rows_per_block, lds);
     if (threadIdx.x == 0) {
-        d.scal[SC_PQ] = pq;
-        d.scal[SC_ALPHA] = d.scal[SC_RZ] / pq;
+        sc[SC_PQ] = pq;
+        sc[SC_ALPHA] = sc[SC_RZ] / pq;
     }
 }
 
 // beta = rz_new / rz; count; convergence (1), iteration limit (2) or a
-// scheduled restart (3) ends the enqueued chunk.
+// scheduled restart (3) ends this mesh's part of the enqueued chunk.
 template <int Unused>
-__global__ __launch_bounds__(1024) void k_cg_beta(Dev d, int64_t nparts) {
+__global__ __launch_bounds__(1024) void k_cg_beta(Dev d, int64_t nparts, int64_t rows_per_block) {
     __shared__ double lds[16];
-    if (d.scal[SC_DONE] != 0.0) return;
-    const double trz = reduce_partials_sum(d.partial, nparts, lds);
-    const double trr = reduce_partials_sum(d.partial + nparts, nparts, lds);
+    const int m = blockIdx.x;
+    double* sc = msc(d, m);
+    if (sc[SC_DONE] != 0.0) return;
+    const double trz = seg_sum(d, 0, m, nparts, rows_per_block, lds);
+    const double trr = seg_sum(d, 1, m, nparts, rows_per_block, lds);
     if (threadIdx.x == 0) {
-        double* sc = d.scal;
         sc[SC_BETA] = trz / sc[SC_RZ];
         sc[SC_RZ] = trz;
         sc[SC_RR] = trr;

@@ -27,6 +27,7 @@
 #include <type_traits>
 
 #include "reduce.h"
+#include "seg.h"
 #include "state.h"
 
 namespace mifvm {
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d, FvArrays<R> a) {
 }
 
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTable bc, R D) {
+__global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTable bc) {
     const int64_t f = gtid();
     if (f >= d.nf) return;
     const int64_t nc = d.nc, NX = d.nc + d.nb, nf = d.nf;
@@ -206,6 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTa
         return;
     }
     const int L = d.fL[f], Rc = d.fR[f];
+    const R D = R(d.mesh_D[mesh_of(d, L)]);
     const R ph = a.phi[f];
     const int up = ph >= R(0) ? L : Rc;
     R uup = u[up];
@@ -226,11 +228,13 @@ __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTa
     a.flux[f] = uup * ph - D * diff;
 }
 
-// u^(k) = u^n + a dt Res(u^(k-1)); the first stage also saves u^n.
+// u^(k) = u^n + a dt Res(u^(k-1)) with the cell's mesh's dt; the first stage
+// also saves u^n.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_update(Dev d, FvArrays<R> a, R a_dt, int first) {
+__global__ __launch_bounds__(kBlock) void k_update(Dev d, FvArrays<R> a, double alpha, int first) {
     const int64_t i = gtid();
     if (i >= d.nc) return;
+    const R a_dt = R(alpha * d.mesh_dt[mesh_of(d, i)]);
     const int64_t nc = d.nc;
     R acc = R(0);
 #pragma unroll
@@ -329,12 +333,14 @@ __global__ __launch_bounds__(kBlock) void k_to_user(const int32_t* __restrict__ 
     for (int c = 0; c < comps; ++c) dst[c * sout + o] = src[c * sin + i];
 }
 
-// dt bound: min_i mu_i / sum_{active faces} (|phi_f| + D kRL_f), per block (FP64)
-__global__ __launch_bounds__(kBlock) void k_cfl(Dev d, BcTable bc, double D) {
+// dt bound of mesh m: min_i mu_i / sum_{active faces} (|phi_f| + D_m kRL_f),
+// per block (FP64)
+__global__ __launch_bounds__(kBlock) void k_cfl(Dev d, BcTable bc, int m) {
     __shared__ double lds[4];
     const int64_t nc = d.nc;
+    const double D = d.mesh_D[m];
     double best = __builtin_huge_val();
-    for (int64_t i = gtid(); i < nc; i += int64_t(gridDim.x) * blockDim.x) {
+    for (int64_t i = d.mesh_start[m] + gtid(); i < d.mesh_start[m + 1]; i += int64_t(gridDim.x) * blockDim.x) {
         double rate = 0.0;
         for (int k = 0; k < 4; ++k) {
             int f = d.c2f[k * nc + i];
@@ -348,21 +354,29 @@ __global__ __launch_bounds__(kBlock) void k_cfl(Dev d, BcTable bc, double D) {
     if (threadIdx.x == 0) d.partial[blockIdx.x] = best;
 }
 
-// sum_i mu_i u_i in FP64 (FP64 volumes, the state widened to FP64)
+// sum_i mu_i u_i over mesh m in FP64 (FP64 volumes, the state widened to FP64)
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_conservation(Dev d, const R* __restrict__ u) {
+__global__ __launch_bounds__(kBlock) void k_conservation(Dev d, const R* __restrict__ u, int m) {
     __shared__ double lds[4];
     double s = 0.0;
-    for (int64_t i = gtid(); i < d.nc; i += int64_t(gridDim.x) * blockDim.x) s += d.vol[i] * double(u[i]);
+    for (int64_t i = d.mesh_start[m] + gtid(); i < d.mesh_start[m + 1]; i += int64_t(gridDim.x) * blockDim.x)
+        s += d.vol[i] * double(u[i]);
     s = block_sum256(s, lds);
     if (threadIdx.x == 0) d.partial[blockIdx.x] = s;
 }
 
-// one block: reduce n partials into scal[slot] (op 0 = sum, 1 = min)
-__global__ __launch_bounds__(1024) void k_finalize(Dev d, int64_t n, int slot, int op) {
+// one block: reduce n partials into mesh m's scal[slot] (op 0 = sum, 1 = min)
+__global__ __launch_bounds__(1024) void k_finalize(Dev d, int64_t n, int m, int slot, int op) {
     __shared__ double lds[16];
     const double v = op == 0 ? reduce_partials_sum(d.partial, n, lds) : reduce_partials_min(d.partial, n, lds);
-    if (threadIdx.x == 0) d.scal[slot] = v;
+    if (threadIdx.x == 0) msc(d, m)[slot] = v;
+}
+
+// the time step each mesh's update uses: dt if dt > 0, else its CFL bound
+// times cfl (stored by the last CFL evaluation)
+__global__ void k_set_dt(Dev d, double dt, double cfl) {
+    const int m = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (m < d.nm) d.mesh_dt[m] = dt > 0.0 ? dt : cfl * msc(d, m)[SC_DT_INV];
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -397,21 +411,26 @@ hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, double D, hipStream_t s) {
+hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s) {
     if (fp32)
-        hipLaunchKernelGGL(k_face_flux<float>, dim3(grid_for(d.nf)), dim3(kBlock), 0, s, d, fv32(d), bc, float(D));
+        hipLaunchKernelGGL(k_face_flux<float>, dim3(grid_for(d.nf)), dim3(kBlock), 0, s, d, fv32(d), bc);
     else
-        hipLaunchKernelGGL(k_face_flux<double>, dim3(grid_for(d.nf)), dim3(kBlock), 0, s, d, fv64(d), bc, D);
+        hipLaunchKernelGGL(k_face_flux<double>, dim3(grid_for(d.nf)), dim3(kBlock), 0, s, d, fv64(d), bc);
     return hipGetLastError();
 }
 
-hipError_t launch_update(const Dev& d, bool fp32, double a_dt, bool first_stage, hipStream_t s) {
+hipError_t launch_update(const Dev& d, bool fp32, double alpha, bool first_stage, hipStream_t s) {
     if (fp32)
-        hipLaunchKernelGGL(k_update<float>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv32(d), float(a_dt),
+        hipLaunchKernelGGL(k_update<float>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv32(d), alpha,
                            first_stage ? 1 : 0);
     else
-        hipLaunchKernelGGL(k_update<double>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv64(d), a_dt,
+        hipLaunchKernelGGL(k_update<double>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv64(d), alpha,
                            first_stage ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_dt(const Dev& d, double dt, double cfl, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_dt, dim3((d.nm + 255) / 256), dim3(256), 0, s, d, dt, cfl);
     return hipGetLastError();
 }
 
@@ -460,18 +479,30 @@ hipError_t launch_to_user(const int32_t* perm, int64_t n, int64_t sin, int64_t s
     return hipGetLastError();
 }
 
-hipError_t launch_cfl(const Dev& d, const BcTable& bc, double D, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_cfl, dim3(nblk), dim3(kBlock), 0, s, d, bc, D);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, d, int64_t(nblk), int(SC_DT_INV), 1);
+// per mesh: one grid-stride reduction over the mesh's cells, then a finalize
+static int blocks_for_range(int64_t n) {
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return int(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+}
+
+hipError_t launch_cfl(const Dev& d, const Mesh& mh, const BcTable& bc, hipStream_t s) {
+    for (int m = 0; m < d.nm; ++m) {
+        const int nblk = blocks_for_range(mh.mesh_start[m + 1] - mh.mesh_start[m]);
+        hipLaunchKernelGGL(k_cfl, dim3(nblk), dim3(kBlock), 0, s, d, bc, m);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, d, int64_t(nblk), m, int(SC_DT_INV), 1);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_conservation(const Dev& d, bool fp32, int nblk, hipStream_t s) {
-    if (fp32)
-        hipLaunchKernelGGL(k_conservation<float>, dim3(nblk), dim3(kBlock), 0, s, d, (const float*)d.u32);
-    else
-        hipLaunchKernelGGL(k_conservation<double>, dim3(nblk), dim3(kBlock), 0, s, d, (const double*)d.u);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, d, int64_t(nblk), int(SC_CONS), 0);
+hipError_t launch_conservation(const Dev& d, const Mesh& mh, bool fp32, hipStream_t s) {
+    for (int m = 0; m < d.nm; ++m) {
+        const int nblk = blocks_for_range(mh.mesh_start[m + 1] - mh.mesh_start[m]);
+        if (fp32)
+            hipLaunchKernelGGL(k_conservation<float>, dim3(nblk), dim3(kBlock), 0, s, d, (const float*)d.u32, m);
+        else
+            hipLaunchKernelGGL(k_conservation<double>, dim3(nblk), dim3(kBlock), 0, s, d, (const double*)d.u, m);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, d, int64_t(nblk), m, int(SC_CONS), 0);
+    }
     return hipGetLastError();
 }
 

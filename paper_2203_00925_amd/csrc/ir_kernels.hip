@@ -5,6 +5,7 @@
 // residual also serves as the restart of the inner CG.
 #include "cg_scalars.h"
 #include "reduce.h"
+#include "seg.h"
 #include "state.h"
 
 namespace mifvm {
@@ -12,7 +13,6 @@ namespace mifvm {
 namespace {
 __device__ inline int64_t tid_g() { return int64_t(blockIdx.x) * blockDim.x + threadIdx.x; }
 inline int rows_grid(int64_t n) { return int((n + kBlock - 1) / kBlock); }
-__device__ inline bool ir_done(const Dev& d) { return d.scal[SC_DONE] != 0.0; }
 }  // namespace
 
 __global__ __launch_bounds__(kBlock) void k_cast_matrix(Dev d, int64_t padded) {
@@ -30,7 +30,8 @@ __global__ __launch_bounds__(kBlock) void k_cast_matrix(Dev d, int64_t padded) {
 __global__ __launch_bounds__(kBlock) void k_ir_residual(Dev d) {
     __shared__ double lds[4];
     const int64_t i = tid_g();
-    double rr = 0.0, rz = 0.0, rr32 = 0.0, bb = 0.0;
+    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < d.nc) {
         const int64_t s = i >> 6;
         const int64_t base = d.k_off[s] + (i & 63);
@@ -48,36 +49,28 @@ __global__ __launch_bounds__(kBlock) void k_ir_residual(Dev d) {
         d.z32[i] = z32;
         d.p32[i] = z32;
         d.d32[i] = 0.0f;
-        rr = ri * ri;
-        rz = double(r32) * double(z32);
-        rr32 = double(r32) * double(r32);
-        bb = bi * bi;
+        v[0] = ri * ri;
+        v[1] = double(r32) * double(z32);
+        v[2] = double(r32) * double(r32);
+        v[3] = bi * bi;
     }
-    rr = block_sum256(rr, lds);
-    rz = block_sum256(rz, lds);
-    rr32 = block_sum256(rr32, lds);
-    bb = block_sum256(bb, lds);
-    if (threadIdx.x == 0) {
-        d.partial[blockIdx.x] = rr;
-        d.partial[gridDim.x + blockIdx.x] = rz;
-        d.partial[2 * gridDim.x + blockIdx.x] = rr32;
-        d.partial[3 * gridDim.x + blockIdx.x] = bb;
-    }
+    seg_publish<4>(d, g, v, i >= g.split, lds);
 }
 
-// fresh: a new solve (sets the outer tolerance, limits and count).  The inner
-// solve runs until ||r32|| <= max(tol_in ||r32_0||, tol ||b|| / 2), the
-// iteration limit, or a restart; the outer loop ends when the FP64 true
-// residual meets tol.
+// One block per mesh.  fresh: a new solve (sets the outer tolerance, limits
+// and count).  The inner solve runs until ||r32|| <= max(tol_in ||r32_0||,
+// tol ||b|| / 2), the iteration limit, or a restart; the outer loop ends
+// when the FP64 true residual meets tol.
 __global__ __launch_bounds__(1024) void k_ir_residual_fin(Dev d, int64_t nparts, double tol, double tol_in,
                                                           int maxit, int restart, int fresh) {
     __shared__ double lds[16];
-    const double trr = reduce_partials_sum(d.partial, nparts, lds);
-    const double trz = reduce_partials_sum(d.partial + nparts, nparts, lds);
-    const double trr32 = reduce_partials_sum(d.partial + 2 * nparts, nparts, lds);
-    const double tbb = reduce_partials_sum(d.partial + 3 * nparts, nparts, lds);
+    const int m = blockIdx.x;
+    const double trr = seg_sum(d, 0, m, nparts, kBlock, lds);
+    const double trz = seg_sum(d, 1, m, nparts, kBlock, lds);
+    const double trr32 = seg_sum(d, 2, m, nparts, kBlock, lds);
+    const double tbb = seg_sum(d, 3, m, nparts, kBlock, lds);
     if (threadIdx.x == 0) {
-        double* sc = d.scal;
+        double* sc = msc(d, m);
         sc[SC_TRUE_RR] = trr;
         sc[SC_BB] = tbb;
         sc[SC_RZ] = trz;
@@ -92,7 +85,7 @@ __global__ __launch_bounds__(1024) void k_ir_residual_fin(Dev d, int64_t nparts,
         // further than half the outer tolerance (the last step stops early)
         sc[SC_TOL2BB] = fmax(tol_in * tol_in * trr32, 0.25 * sc[SC_TOL2BB_OUT]);
         sc[SC_SINCE] = 0.0;
-        sc[SC_DONE] = trr <= sc[SC_TOL2BB_OUT] ? 1.0 : (sc[SC_IT] >= sc[SC_MAXIT] ? 2.0 : 0.0);
+        sc[SC_DONE] = (trr <= sc[SC_TOL2BB_OUT] || tbb == 0.0) ? 1.0 : (sc[SC_IT] >= sc[SC_MAXIT] ? 2.0 : 0.0);
     }
 }
 
@@ -100,10 +93,11 @@ __global__ __launch_bounds__(1024) void k_ir_residual_fin(Dev d, int64_t nparts,
 __global__ __launch_bounds__(kBlock) void k_cg32_spmv(Dev d) {
     extern __shared__ float sp32[];
     __shared__ double lds[4];
-    if (ir_done(d)) return;
     const int64_t nc = d.nc;
     const int64_t t = blockIdx.x;
     const int T = blockDim.x;
+    const BlockSeg g = block_seg(d, t * T, T);
+    if (block_done(d, g)) return;
     const int64_t h0 = d.h_off[t];
     const int hn = int(d.h_off[t + 1] - h0);
     for (int h = threadIdx.x; h < hn; h += T) {
@@ -112,8 +106,8 @@ __global__ __launch_bounds__(kBlock) void k_cg32_spmv(Dev d) {
     }
     __syncthreads();
     const int64_t i = t * T + threadIdx.x;
-    double pq = 0.0;
-    if (i < nc) {
+    double v[1] = {0.0};
+    if (i < nc && msc(d, row_mesh(g, i))[SC_DONE] == 0.0) {
         const float pi = sp32[d.h_self[t] + threadIdx.x];
         const int64_t s = i >> 6;
         const int64_t base = d.k_off[s] + (i & 63);
@@ -121,57 +115,55 @@ __global__ __launch_bounds__(kBlock) void k_cg32_spmv(Dev d) {
         float y = d.k_diag32[i] * pi;
         for (int k0 = 0; k0 < w; k0 += 16) {
             uint16_t l[16];
-            float v[16];
+            float a[16];
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const bool in = k0 + j < w;
                 const int64_t at = base + int64_t(k0 + j) * 64;
                 l[j] = in ? d.k_lidx[at] : 0;
-                v[j] = in ? d.k_val32[at] : 0.0f;
+                a[j] = in ? d.k_val32[at] : 0.0f;
             }
 #pragma unroll
-            for (int j = 0; j < 16; ++j) y += v[j] * sp32[l[j]];
+            for (int j = 0; j < 16; ++j) y += a[j] * sp32[l[j]];
         }
         d.q32[i] = y;
-        pq = double(pi) * double(y);
+        v[0] = double(pi) * double(y);
     }
-    pq = block_sum_upto256(pq, lds);
-    if (threadIdx.x == 0) d.partial[blockIdx.x] = pq;
+    seg_publish<1>(d, g, v, i >= g.split, lds);
 }
 
 // d += alpha p; r -= alpha q; z = D^-1 r (FP32); partial rz, rr (FP64)
 __global__ __launch_bounds__(kBlock) void k_cg32_axpy(Dev d) {
     __shared__ double lds[4];
-    if (ir_done(d)) return;
-    const float alpha = float(d.scal[SC_ALPHA]);
+    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    if (block_done(d, g)) return;
     const int64_t i = tid_g();
-    double rz = 0.0, rr = 0.0;
-    if (i < d.nc) {
+    const double* sc = msc(d, row_mesh(g, i));
+    double v[2] = {0.0, 0.0};
+    if (i < d.nc && sc[SC_DONE] == 0.0) {
+        const float alpha = float(sc[SC_ALPHA]);
         d.d32[i] = d.d32[i] + alpha * d.p32[i];
         const float ri = d.r32[i] - alpha * d.q32[i];
         const float zi = d.k_dinv32[i] * ri;
         d.r32[i] = ri;
         d.z32[i] = zi;
-        rz = double(ri) * double(zi);
-        rr = double(ri) * double(ri);
+        v[0] = double(ri) * double(zi);
+        v[1] = double(ri) * double(ri);
     }
-    rz = block_sum256(rz, lds);
-    rr = block_sum256(rr, lds);
-    if (threadIdx.x == 0) {
-        d.partial[blockIdx.x] = rz;
-        d.partial[gridDim.x + blockIdx.x] = rr;
-    }
+    seg_publish<2>(d, g, v, i >= g.split, lds);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg32_dir(Dev d) {
-    if (ir_done(d)) return;
-    const float beta = float(d.scal[SC_BETA]);
+    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    if (block_done(d, g)) return;
     const int64_t i = tid_g();
     if (i >= d.nc) return;
-    d.p32[i] = d.z32[i] + beta * d.p32[i];
+    const double* sc = msc(d, row_mesh(g, i));
+    if (sc[SC_DONE] != 0.0) return;
+    d.p32[i] = d.z32[i] + float(sc[SC_BETA]) * d.p32[i];
 }
 
-// x += d (FP64)
+// x += d (FP64).  d is zero on meshes that ran no inner solve this step.
 __global__ __launch_bounds__(kBlock) void k_ir_update(Dev d) {
     const int64_t i = tid_g();
     if (i >= d.nc) return;
@@ -188,7 +180,7 @@ hipError_t launch_ir_residual(const Dev& d, double tol, double tol_in, int maxit
                               hipStream_t s) {
     const int nb = rows_grid(d.nc);
     hipLaunchKernelGGL(k_ir_residual, dim3(nb), dim3(kBlock), 0, s, d);
-    hipLaunchKernelGGL(k_ir_residual_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb), tol, tol_in, maxit,
+    hipLaunchKernelGGL(k_ir_residual_fin, dim3(d.nm), dim3(1024), 0, s, d, int64_t(nb), tol, tol_in, maxit,
                        restart, fresh ? 1 : 0);
     return hipGetLastError();
 }
@@ -196,14 +188,14 @@ hipError_t launch_ir_residual(const Dev& d, double tol, double tol_in, int maxit
 hipError_t launch_cg32_spmv(const Dev& d, hipStream_t s) {
     hipLaunchKernelGGL(k_cg32_spmv, dim3(unsigned(d.ntiles)), dim3(d.tile_rows),
                        size_t(d.halo_max) * sizeof(float), s, d);
-    hipLaunchKernelGGL(k_cg_alpha<0>, dim3(1), dim3(1024), 0, s, d, d.ntiles);
+    hipLaunchKernelGGL(k_cg_alpha<0>, dim3(d.nm), dim3(1024), 0, s, d, d.ntiles, int64_t(d.tile_rows));
     return hipGetLastError();
 }
 
 hipError_t launch_cg32_axpy(const Dev& d, hipStream_t s) {
     const int nb = rows_grid(d.nc);
     hipLaunchKernelGGL(k_cg32_axpy, dim3(nb), dim3(kBlock), 0, s, d);
-    hipLaunchKernelGGL(k_cg_beta<0>, dim3(1), dim3(1024), 0, s, d, int64_t(nb));
+    hipLaunchKernelGGL(k_cg_beta<0>, dim3(d.nm), dim3(1024), 0, s, d, int64_t(nb), int64_t(kBlock));
     return hipGetLastError();
 }
 

@@ -116,7 +116,7 @@ void pack_sell(const std::vector<int64_t>& ptr, const std::vector<int32_t>& idx,
 
 int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
                const int32_t* btris, const int32_t* btags, int64_t nb_in,
-               int renumber, Mesh& M, std::string& err) {
+               int renumber, const int64_t* mesh_cell_start, int32_t nmeshes, Mesh& M, std::string& err) {
     const int E_ARG = -1, E_MESH = -2;
     if (!xyz || !tets || nv <= 0 || nc <= 0 || nb_in < 0 || (nb_in > 0 && (!btris || !btags))) {
         err = "null pointer or non-positive size";
@@ -132,6 +132,21 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
         if (btris[i] < 0 || btris[i] >= nv) { err = "boundary vertex index out of range"; return E_ARG; }
     for (int64_t i = 0; i < nb_in; ++i)
         if (btags[i] < 0 || btags[i] >= 32) { err = "boundary tag out of [0, 32)"; return E_ARG; }
+    std::vector<int64_t> mstart = {0, nc};
+    if (mesh_cell_start && nmeshes > 1) {
+        if (nmeshes > 4096) { err = "too many meshes in one batch"; return E_ARG; }
+        mstart.assign(mesh_cell_start, mesh_cell_start + nmeshes + 1);
+        if (mstart[0] != 0 || mstart[nmeshes] != nc) { err = "mesh_cell_start must run from 0 to nc"; return E_ARG; }
+        for (int32_t m = 0; m < nmeshes; ++m)
+            if (mstart[m + 1] - mstart[m] < 256) { err = "every mesh of a batch needs at least 256 cells"; return E_ARG; }
+    } else if (nmeshes > 1) {
+        err = "mesh_cell_start is null";
+        return E_ARG;
+    }
+    const int32_t nm = int32_t(mstart.size() - 1);
+    std::vector<int32_t> mesh_of_user(nc);
+    for (int32_t m = 0; m < nm; ++m)
+        for (int64_t c = mstart[m]; c < mstart[m + 1]; ++c) mesh_of_user[c] = m;
 
     auto P = [&](int64_t v) { return V3{xyz[3 * v], xyz[3 * v + 1], xyz[3 * v + 2]}; };
     // MIFVM_PREPROCESS_TIMING=1 prints the time of each stage to stderr
@@ -183,8 +198,11 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
                  cz = uint64_t((cen_u[c].z - lo.z) * q);
             key[c] = spread21(cx) | (spread21(cy) << 1) | (spread21(cz) << 2);
         }
-        std::stable_sort(new2old.begin(), new2old.end(),
-                         [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+        // Morton order within each mesh; meshes stay contiguous and in order
+        std::stable_sort(new2old.begin(), new2old.end(), [&](int32_t a, int32_t b) {
+            if (mesh_of_user[a] != mesh_of_user[b]) return mesh_of_user[a] < mesh_of_user[b];
+            return key[a] < key[b];
+        });
     } else if (renumber != 0) {
         err = "unknown renumbering";
         return E_ARG;
@@ -227,6 +245,10 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
         size_t j = i + 1;
         while (j < rec.size() && rec[j].a == rec[i].a && rec[j].b == rec[i].b && rec[j].c == rec[i].c) ++j;
         if (j - i > 2) { err = "face shared by more than two cells"; return E_MESH; }
+        if (j - i == 2 && mesh_of_user[rec[i].owner] != mesh_of_user[rec[i + 1].owner]) {
+            err = "a face is shared by cells of two different meshes";
+            return E_MESH;
+        }
         uf.push_back({rec[i].a, rec[i].b, rec[i].c, rec[i].owner, j - i == 2 ? rec[i + 1].owner : -1, -1});
         i = j;
     }
@@ -299,6 +321,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     // -- 8. fill internal arrays ------------------------------------------------
     M = Mesh();
     M.nc = nc; M.nv = nv; M.nf = nf; M.nfi = nfi; M.nb = nb;
+    M.mesh_start = mstart;
     M.cell_perm = new2old;
     M.vert_perm = vnew2old;
     M.vol.resize(nc);

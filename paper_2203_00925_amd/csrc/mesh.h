@@ -20,6 +20,8 @@ struct Sell64 {
 
 struct Mesh {
     int64_t nc = 0, nv = 0, nf = 0, nfi = 0, nb = 0;
+    // independent meshes of a batch: internal cells [mesh_start[m], mesh_start[m+1])
+    std::vector<int64_t> mesh_start;
     std::vector<int32_t> cell_perm;   // internal cell -> user cell
     std::vector<int32_t> vert_perm;   // internal vertex -> user vertex
     std::vector<double> vol;          // nc
@@ -67,8 +69,10 @@ struct Mesh {
 };
 
 // Returns 0 or a negative mifvm status; err receives a message.
+// mesh_cell_start (nmeshes+1 entries, or null for one mesh) splits the tets
+// into independent meshes; each must have at least 256 cells when nmeshes > 1.
 int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
                const int32_t* btris, const int32_t* btags, int64_t nb,
-               int renumber, Mesh& out, std::string& err);
+               int renumber, const int64_t* mesh_cell_start, int32_t nmeshes, Mesh& out, std::string& err);
 
 }  // namespace mifvm

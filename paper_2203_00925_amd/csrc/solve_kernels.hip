@@ -6,6 +6,7 @@
 // of an enqueued chunk return at once when the solve has finished).
 #include "cg_scalars.h"
 #include "reduce.h"
+#include "seg.h"
 #include "state.h"
 
 namespace mifvm {
@@ -120,15 +121,18 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Dev d, const double* __restrict_
     d.b[i] = -d.vol[i] * f[i] + d.k_c[i];
 }
 
-// Each CG kernel returns at once when the solve has finished (SC_DONE != 0),
-// so a chunk of enqueued iterations past convergence costs only launches.
-__device__ inline bool cg_done(const Dev& d) { return d.scal[SC_DONE] != 0.0; }
+// Every CG quantity is per mesh (a batch holds independent meshes): a row
+// reads the scalars of its own mesh, rows of a mesh whose solve has finished
+// (SC_DONE != 0) are left untouched, and a block whose meshes have all
+// finished returns at once, so a chunk of enqueued iterations past
+// convergence costs only launches.
 
 // r = b - K x; z = D^-1 r; p = z; partial rz, rr, bb.  (Re)opens the loop.
 __global__ __launch_bounds__(kBlock) void k_cg_setup(Dev d) {
     __shared__ double lds[4];
     const int64_t i = gtid_s();
-    double rz = 0.0, rr = 0.0, bb = 0.0;
+    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    double v[3] = {0.0, 0.0, 0.0};
     if (i < d.nc) {
         const double bi = d.b[i];
         const double ri = bi - spmv_row(d, d.x, i);
@@ -136,30 +140,25 @@ __global__ __launch_bounds__(kBlock) void k_cg_setup(Dev d) {
         d.r[i] = ri;
         d.z[i] = zi;
         d.p[i] = zi;
-        rz = ri * zi;
-        rr = ri * ri;
-        bb = bi * bi;
+        v[0] = ri * zi;
+        v[1] = ri * ri;
+        v[2] = bi * bi;
     }
-    rz = block_sum256(rz, lds);
-    rr = block_sum256(rr, lds);
-    bb = block_sum256(bb, lds);
-    if (threadIdx.x == 0) {
-        d.partial[blockIdx.x] = rz;
-        d.partial[gridDim.x + blockIdx.x] = rr;
-        d.partial[2 * gridDim.x + blockIdx.x] = bb;
-    }
+    seg_publish<3>(d, g, v, i >= g.split, lds);
 }
 
-// fresh != 0: a new solve (sets tolerance, limits, count); otherwise a reopen
-// after a true-residual check or a restart keeps them.
+// One block per mesh.  fresh != 0: a new solve (sets tolerance, limits,
+// count); otherwise a reopen after a true-residual check or a restart keeps
+// them.
 __global__ __launch_bounds__(1024) void k_cg_setup_fin(Dev d, int64_t nparts, double tol, int maxit,
                                                        int restart, int fresh) {
     __shared__ double lds[16];
-    const double trz = reduce_partials_sum(d.partial, nparts, lds);
-    const double trr = reduce_partials_sum(d.partial + nparts, nparts, lds);
-    const double tbb = reduce_partials_sum(d.partial + 2 * nparts, nparts, lds);
+    const int m = blockIdx.x;
+    const double trz = seg_sum(d, 0, m, nparts, kBlock, lds);
+    const double trr = seg_sum(d, 1, m, nparts, kBlock, lds);
+    const double tbb = seg_sum(d, 2, m, nparts, kBlock, lds);
     if (threadIdx.x == 0) {
-        double* sc = d.scal;
+        double* sc = msc(d, m);
         sc[SC_RZ] = trz;
         sc[SC_RR] = trr;
         sc[SC_TRUE_RR] = trr;
@@ -171,7 +170,7 @@ __global__ __launch_bounds__(1024) void k_cg_setup_fin(Dev d, int64_t nparts, do
             sc[SC_IT] = 0.0;
         }
         sc[SC_SINCE] = 0.0;
-        sc[SC_DONE] = trr <= sc[SC_TOL2BB] ? 1.0 : (sc[SC_IT] >= sc[SC_MAXIT] ? 2.0 : 0.0);
+        sc[SC_DONE] = (trr <= sc[SC_TOL2BB] || tbb == 0.0) ? 1.0 : (sc[SC_IT] >= sc[SC_MAXIT] ? 2.0 : 0.0);
     }
 }
 
@@ -182,10 +181,11 @@ __global__ __launch_bounds__(1024) void k_cg_setup_fin(Dev d, int64_t nparts, do
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(Dev d) {
     extern __shared__ double sp[];                   // [halo] p
     __shared__ double lds[4];
-    if (cg_done(d)) return;
     const int64_t nc = d.nc;
     const int64_t t = blockIdx.x;
     const int T = blockDim.x;
+    const BlockSeg g = block_seg(d, t * T, T);
+    if (block_done(d, g)) return;
     const int64_t h0 = d.h_off[t];
     const int hn = int(d.h_off[t + 1] - h0);
     const double* __restrict__ p = d.p;
@@ -195,8 +195,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Dev d) {
     }
     __syncthreads();
     const int64_t i = t * T + threadIdx.x;
-    double pq = 0.0;
-    if (i < nc) {
+    const int m = row_mesh(g, i);
+    double v[1] = {0.0};
+    if (i < nc && msc(d, m)[SC_DONE] == 0.0) {
         const double pi = sp[d.h_self[t] + threadIdx.x];
         const int64_t s = i >> 6;
         const int64_t base = d.k_off[s] + (i & 63);
@@ -208,43 +209,42 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Dev d) {
             y += d.k_val[at] * sp[d.k_lidx[at]];
         }
         d.q[i] = y;
-        pq = pi * y;
+        v[0] = pi * y;
     }
-    pq = block_sum_upto256(pq, lds);
-    if (threadIdx.x == 0) d.partial[blockIdx.x] = pq;
+    seg_publish<1>(d, g, v, i >= g.split, lds);
 }
 
 // x += alpha p; r -= alpha q; z = D^-1 r; partial rz, rr
 __global__ __launch_bounds__(kBlock) void k_cg_axpy(Dev d) {
     __shared__ double lds[4];
-    if (cg_done(d)) return;
-    const double alpha = d.scal[SC_ALPHA];
+    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    if (block_done(d, g)) return;
     const int64_t i = gtid_s();
-    double rz = 0.0, rr = 0.0;
-    if (i < d.nc) {
+    const int m = row_mesh(g, i);
+    const double* sc = msc(d, m);
+    double v[2] = {0.0, 0.0};
+    if (i < d.nc && sc[SC_DONE] == 0.0) {
+        const double alpha = sc[SC_ALPHA];
         d.x[i] = d.x[i] + alpha * d.p[i];
         const double ri = d.r[i] - alpha * d.q[i];
         const double zi = d.k_dinv[i] * ri;
         d.r[i] = ri;
         d.z[i] = zi;
-        rz = ri * zi;
-        rr = ri * ri;
+        v[0] = ri * zi;
+        v[1] = ri * ri;
     }
-    rz = block_sum256(rz, lds);
-    rr = block_sum256(rr, lds);
-    if (threadIdx.x == 0) {
-        d.partial[blockIdx.x] = rz;
-        d.partial[gridDim.x + blockIdx.x] = rr;
-    }
+    seg_publish<2>(d, g, v, i >= g.split, lds);
 }
 
 // p = z + beta p
 __global__ __launch_bounds__(kBlock) void k_cg_dir(Dev d) {
-    if (cg_done(d)) return;
-    const double beta = d.scal[SC_BETA];
+    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    if (block_done(d, g)) return;
     const int64_t i = gtid_s();
     if (i >= d.nc) return;
-    d.p[i] = d.z[i] + beta * d.p[i];
+    const double* sc = msc(d, row_mesh(g, i));
+    if (sc[SC_DONE] != 0.0) return;
+    d.p[i] = d.z[i] + sc[SC_BETA] * d.p[i];
 }
 
 // ---- launchers ---------------------------------------------------------------
@@ -267,7 +267,7 @@ hipError_t launch_rhs(const Dev& d, const double* f, hipStream_t s) {
 hipError_t launch_cg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s) {
     const int nb = grid_rows(d.nc);
     hipLaunchKernelGGL(k_cg_setup, dim3(nb), dim3(kBlock), 0, s, d);
-    hipLaunchKernelGGL(k_cg_setup_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb), tol, maxit, restart,
+    hipLaunchKernelGGL(k_cg_setup_fin, dim3(d.nm), dim3(1024), 0, s, d, int64_t(nb), tol, maxit, restart,
                        fresh ? 1 : 0);
     return hipGetLastError();
 }
@@ -275,14 +275,14 @@ hipError_t launch_cg_setup(const Dev& d, double tol, int maxit, int restart, boo
 hipError_t launch_cg_spmv(const Dev& d, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_spmv, dim3(unsigned(d.ntiles)), dim3(d.tile_rows),
                        size_t(d.halo_max) * sizeof(double), s, d);
-    hipLaunchKernelGGL(k_cg_alpha<0>, dim3(1), dim3(1024), 0, s, d, d.ntiles);
+    hipLaunchKernelGGL(k_cg_alpha<0>, dim3(d.nm), dim3(1024), 0, s, d, d.ntiles, int64_t(d.tile_rows));
     return hipGetLastError();
 }
 
 hipError_t launch_cg_axpy(const Dev& d, hipStream_t s) {
     const int nb = grid_rows(d.nc);
     hipLaunchKernelGGL(k_cg_axpy, dim3(nb), dim3(kBlock), 0, s, d);
-    hipLaunchKernelGGL(k_cg_beta<0>, dim3(1), dim3(1024), 0, s, d, int64_t(nb));
+    hipLaunchKernelGGL(k_cg_beta<0>, dim3(d.nm), dim3(1024), 0, s, d, int64_t(nb), int64_t(kBlock));
     return hipGetLastError();
 }
 

@@ -25,6 +25,10 @@ struct BcTable {                          // per-tag boundary conditions
 // array 256-byte aligned.
 struct Dev {
     int64_t nc, nv, nf, nfi, nb;
+    int32_t nm;                           // independent meshes (batch size)
+    int64_t* mesh_start;                  // nm+1 internal cell offsets
+    double* mesh_D;                       // nm diffusivities
+    double* mesh_dt;                      // nm time steps
     int64_t ns, nvs;                      // 64-row slices of cells / vertices
     // cells
     double *vol, *xc;                     // xc: 3 x (nc+nb)
@@ -63,7 +67,7 @@ struct Dev {
     float *minv32, *kAC32, *kBC32, *kRL32, *area32, *vol32, *n_alpha32, *fx32, *xc32, *gdist32;
     double* tmp;                          // nc+nb scratch (permutation, residual)
     double* partial;                      // reduction partials ([k][block], k < 4)
-    double* scal;                         // solver scalars (see solve_kernels)
+    double* scal;                         // solver scalars, [nm][SC_COUNT_]
 };
 
 // The arrays one precision of the step reads and writes.
@@ -91,6 +95,9 @@ struct State {
     BcTable bc[2]{};                      // SCALAR, POTENTIAL
     double diffusivity = 0.0;
     bool fp32 = false;                    // reduced-precision form of the step
+    double cfl = 0.0;                     // factor of the last CFL evaluation
+    std::vector<int> last_iters;          // per mesh, last solve
+    std::vector<double> last_rel;
     bool assembled = false;
     bool k32_ready = false;               // FP32 copy of K matches K
     bool vel_set = false;
@@ -105,8 +112,9 @@ size_t layout(const Mesh& m, char* base, Dev& d);
 // launchers (fv_kernels.hip)
 hipError_t launch_ghost_fill(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
 hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s);
-hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, double D, hipStream_t s);
-hipError_t launch_update(const Dev& d, bool fp32, double a_dt, bool first_stage, hipStream_t s);
+hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
+hipError_t launch_update(const Dev& d, bool fp32, double alpha, bool first_stage, hipStream_t s);
+hipError_t launch_set_dt(const Dev& d, double dt, double cfl, hipStream_t s);
 hipError_t launch_residual_out(const Dev& d, bool fp32, double* res_internal, hipStream_t s);
 hipError_t launch_face_phi(const Dev& d, hipStream_t s);
 hipError_t launch_make_fp32_geometry(const Dev& d, int64_t node_padded, hipStream_t s);
@@ -116,8 +124,8 @@ hipError_t launch_to_internal(const int32_t* perm, int64_t n, int64_t stride_in,
                               int comps, const double* src, double* dst, hipStream_t s);
 hipError_t launch_to_user(const int32_t* perm, int64_t n, int64_t stride_in, int64_t stride_out,
                           int comps, const double* src, double* dst, hipStream_t s);
-hipError_t launch_cfl(const Dev& d, const BcTable& bc, double D, int nblk, hipStream_t s);
-hipError_t launch_conservation(const Dev& d, bool fp32, int nblk, hipStream_t s);
+hipError_t launch_cfl(const Dev& d, const Mesh& mh, const BcTable& bc, hipStream_t s);
+hipError_t launch_conservation(const Dev& d, const Mesh& mh, bool fp32, hipStream_t s);
 
 // launchers (solve_kernels.hip)
 hipError_t launch_assemble(const Dev& d, const BcTable& bc, int row_max, hipStream_t s);
