@@ -133,7 +133,9 @@ typedef struct {
     double* history;           /* host, optional: recurrence ||r||/||b|| at
                                   every host check                           */
     int32_t method;            /* enum mifvm_solve_method                     */
-    int32_t pad_;
+    int32_t graph;             /* 1: enqueue each chunk by replaying a captured
+                                  hipGraph (not while kernel timing is on);
+                                  -1: the autotuned choice (else 0)          */
     double inner_tol;          /* IR_FP32: relative reduction asked of each
                                   FP32 inner solve (0 = 1e-4)                */
 } mifvm_solve_opts;
@@ -259,6 +261,28 @@ int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* str
  * Synchronises (once per chunk).                                           */
 int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_opts* opts,
                         mifvm_solve_info* info, void* stream);
+
+/* ---- captured replays and the autotuner -----------------------------------
+ * mifvm_step_graph: as mifvm_step, but the n_steps x 3 stages are captured
+ * once into a hipGraph (per (n_steps, dt)) and replayed on `stream`.
+ * mifvm_autotune: times the CG schedule (chunk 8/16/32/64, direct launches
+ * or graph replay) on short solves of the current system (f = U; P is
+ * restored afterwards) and one step direct vs replayed (U restored); keeps
+ * the fastest in the state (used by solves with chunk = 0 / graph = -1 and
+ * by mifvm_step_graph) and records it in the JSON file cache_path (NULL: no
+ * file) under "arch/nmeshes/log2(cells)".  Reads the file first: a recorded
+ * entry is used without timing.  Synchronises.                              */
+typedef struct {
+    int32_t chunk;
+    int32_t graph;
+    int32_t step_graph;
+    int32_t from_cache;
+    double ms_per_iteration;   /* of the chosen CG schedule (0 if cached)     */
+    double ms_per_step_direct;
+    double ms_per_step_graph;
+} mifvm_tune_info;
+int mifvm_step_graph(mifvm_state* st, int32_t n_steps, double dt, void* stream);
+int mifvm_autotune(mifvm_state* st, const char* cache_path, mifvm_tune_info* out, void* stream);
 
 /* ---- per-kernel timing (HIP events on the launch stream) -----------------
  * enable != 0 starts recording an event pair around every kernel launch of

@@ -78,7 +78,13 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("chunk", C.c_int32),
                 ("restart", C.c_int32), ("history_cap", C.c_int32),
                 ("history", C.POINTER(C.c_double)), ("method", C.c_int32),
-                ("pad_", C.c_int32), ("inner_tol", C.c_double)]
+                ("graph", C.c_int32), ("inner_tol", C.c_double)]
+
+
+class TuneInfo(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("graph", C.c_int32), ("step_graph", C.c_int32),
+                ("from_cache", C.c_int32), ("ms_per_iteration", C.c_double),
+                ("ms_per_step_direct", C.c_double), ("ms_per_step_graph", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -117,6 +123,8 @@ def _load():
         "mifvm_poisson_rhs": (C.c_int, [P, P, P, P]),
         "mifvm_poisson_solve": (C.c_int, [P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), P]),
         "mifvm_kernel_timing": (C.c_int, [P, I32]),
+        "mifvm_step_graph": (C.c_int, [P, I32, D, P]),
+        "mifvm_autotune": (C.c_int, [P, C.c_char_p, C.POINTER(TuneInfo), P]),
         "mifvm_kernel_stats": (C.c_int, [P, I32, C.POINTER(D), C.POINTER(I64), P]),
     }
     for name, (res, args) in sig.items():
@@ -272,6 +280,15 @@ class State:
     def step(self, n_steps, dt, stream=None):
         _check(_lib.mifvm_step(self._h, int(n_steps), float(dt), _stream(stream)))
 
+    def step_graph(self, n_steps, dt, stream=None):
+        _check(_lib.mifvm_step_graph(self._h, int(n_steps), float(dt), _stream(stream)))
+
+    def autotune(self, cache_path=None, stream=None):
+        info = TuneInfo()
+        path = cache_path.encode() if cache_path else None
+        _check(_lib.mifvm_autotune(self._h, path, C.byref(info), _stream(stream)))
+        return {f: getattr(info, f) for f, _ in TuneInfo._fields_}
+
     def residual(self, stream=None):
         import torch
         i = self.mesh.info
@@ -309,15 +326,17 @@ class State:
         _check(_lib.mifvm_poisson_rhs(self._h, _ptr(f), _ptr(y), _stream(stream)))
         return y
 
-    def poisson_solve(self, f=None, tol=1e-10, maxit=20000, chunk=32, restart=500,
-                      history=0, method=SOLVE_PLAIN, inner_tol=1e-4, stream=None,
+    def poisson_solve(self, f=None, tol=1e-10, maxit=20000, chunk=0, restart=500,
+                      history=0, method=SOLVE_PLAIN, inner_tol=1e-4, graph=-1, stream=None,
                       allow_not_converged=False):
+        """chunk 0 / graph -1: the autotuned schedule (32 iterations per host
+        check, direct launches when not tuned)."""
         import torch
         if f is not None:
             f = f.to(device=self.device, dtype=torch.float64).contiguous()
         hist = (C.c_double * max(int(history), 1))()
         opts = SolveOpts(float(tol), int(maxit), int(chunk), int(restart), int(history), hist,
-                         int(method), 0, float(inner_tol))
+                         int(method), int(graph), float(inner_tol))
         info = SolveInfo()
         allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
         rc = _check(_lib.mifvm_poisson_solve(self._h, _ptr(f), C.byref(opts), C.byref(info),

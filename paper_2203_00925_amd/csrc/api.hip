@@ -5,8 +5,13 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <sstream>
+#include <array>
 #include <string>
 
 #include "../../include/mifvm.h"
@@ -207,6 +212,46 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
 
 using namespace mifvm;
 
+namespace {
+// Capture the launches `enqueue` makes on the library's capture stream into
+// an executable graph (the kernels take their arguments by value, so the
+// graph can be replayed on any stream).
+template <class F>
+hipError_t capture_graph(State& s, hipGraphExec_t* exec, F enqueue) {
+    hipError_t e = hipSuccess;
+    if (!s.cap_stream) {
+        e = hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    e = hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = enqueue(s.cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s.cap_stream, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return le;
+    }
+    if (e != hipSuccess) return e;
+    if (*exec) (void)hipGraphExecDestroy(*exec);
+    *exec = nullptr;
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+
+// one chunk of n CG iterations (plain FP64 or FP32 inner), no timing events
+hipError_t enqueue_cg_chunk(const Dev& d, int method, int n, hipStream_t q) {
+    for (int c = 0; c < n; ++c) {
+        hipError_t e = method == MIFVM_SOLVE_PLAIN ? launch_cg_spmv(d, q) : launch_cg32_spmv(d, q);
+        if (e == hipSuccess) e = method == MIFVM_SOLVE_PLAIN ? launch_cg_axpy(d, q) : launch_cg32_axpy(d, q);
+        if (e == hipSuccess) e = method == MIFVM_SOLVE_PLAIN ? launch_cg_dir(d, q) : launch_cg32_dir(d, q);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 const char* mifvm_last_error(void) { return g_err.c_str(); }
@@ -392,6 +437,9 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
 
 void mifvm_state_destroy(mifvm_state* st) {
     if (!st) return;
+    if (st->s.cg_exec) (void)hipGraphExecDestroy(st->s.cg_exec);
+    if (st->s.step_exec) (void)hipGraphExecDestroy(st->s.step_exec);
+    if (st->s.cap_stream) (void)hipStreamDestroy(st->s.cap_stream);
     if (st->s.h_scal) (void)hipHostFree(st->s.h_scal);
     for (hipEvent_t e : st->s.timer.pool) (void)hipEventDestroy(e);
     delete st;
@@ -569,6 +617,38 @@ int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream) {
     return MIFVM_OK;
 }
 
+namespace {
+// n RK3 steps without timing events (the body of a captured step graph)
+hipError_t enqueue_steps(const State& s, int n, double dt, hipStream_t q) {
+    static const double alpha[3] = {0.5, 0.5, 1.0};
+    const Dev& d = s.d;
+    hipError_t e = launch_set_dt(d, dt, s.cfl, q);
+    for (int k = 0; e == hipSuccess && k < 3 * n; ++k) {
+        e = launch_ghost_fill(d, s.fp32, s.bc[0], q);
+        if (e == hipSuccess) e = launch_grad_limiter(d, s.fp32, q);
+        if (e == hipSuccess) e = launch_face_flux(d, s.fp32, s.bc[0], q);
+        if (e == hipSuccess) e = launch_update(d, s.fp32, alpha[k % 3], k % 3 == 0, q);
+    }
+    if (e == hipSuccess && n > 0) e = launch_ghost_fill(d, s.fp32, s.bc[0], q);
+    return e;
+}
+}  // namespace
+
+int mifvm_step_graph(mifvm_state* st, int32_t n_steps, double dt, void* stream) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    if (n_steps < 0 || !(dt >= 0) || !std::isfinite(dt)) return fail(MIFVM_E_ARG, "bad n_steps or dt");
+    State& s = st->s;
+    if (dt == 0.0 && !(s.cfl > 0)) return fail(MIFVM_E_STATE, "dt = 0 asks for the CFL steps: call mifvm_cfl_dt first");
+    if (n_steps == 0) return MIFVM_OK;
+    if (s.step_exec == nullptr || s.step_exec_n != n_steps || s.step_exec_dt != dt) {
+        HIPCHK(capture_graph(s, &s.step_exec, [&](hipStream_t q) { return enqueue_steps(s, n_steps, dt, q); }));
+        s.step_exec_n = n_steps;
+        s.step_exec_dt = dt;
+    }
+    HIPCHK(hipGraphLaunch(s.step_exec, S(stream)));
+    return MIFVM_OK;
+}
+
 int mifvm_residual(mifvm_state* st, double* d_res, double* d_grad, double* d_psi, double* d_unode,
                    double* d_flux, void* stream) {
     if (!st) return fail(MIFVM_E_ARG, "null state");
@@ -664,9 +744,11 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
     if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
     const double tol = opts ? opts->tol : 1e-10;
     const int maxit = opts ? opts->maxit : 20000;
-    const int chunk = opts && opts->chunk > 0 ? opts->chunk : 32;
+    const int chunk = opts && opts->chunk > 0 ? opts->chunk : (s.tuned_chunk > 0 ? s.tuned_chunk : 32);
     const int restart = opts ? opts->restart : 500;
     const int method = opts ? opts->method : MIFVM_SOLVE_PLAIN;
+    const int graph_opt = opts ? opts->graph : -1;
+    const bool use_graph = !s.timer.on && (graph_opt == 1 || (graph_opt < 0 && s.tuned_graph == 1));
     const double tol_in = opts && opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
     double* hist = opts ? opts->history : nullptr;
     const int hist_cap = opts && opts->history ? opts->history_cap : 0;
@@ -702,17 +784,37 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
             if (hsc(s, m, SC_DONE) == 0.0) return true;
         return false;
     };
+    if (use_graph && (s.cg_exec == nullptr || s.cg_exec_chunk != chunk || s.cg_exec_method != method)) {
+        HIPCHK(capture_graph(s, &s.cg_exec, [&](hipStream_t q) { return enqueue_cg_chunk(d, method, chunk, q); }));
+        s.cg_exec_chunk = chunk;
+        s.cg_exec_method = method;
+    }
+    // one chunk of iterations: a graph replay, or timed direct launches
+    auto run_chunk = [&]() -> int {
+        if (use_graph) {
+            HIPCHK(hipGraphLaunch(s.cg_exec, hs));
+            return MIFVM_OK;
+        }
+        for (int c = 0; c < chunk; ++c) {
+            if (method == MIFVM_SOLVE_PLAIN) {
+                HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
+                HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
+                HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
+            } else {
+                HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg32_spmv(d, hs); }));
+                HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg32_axpy(d, hs); }));
+                HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg32_dir(d, hs); }));
+            }
+        }
+        return MIFVM_OK;
+    };
     int restarts = 0, outer = 0;
     if (method == MIFVM_SOLVE_PLAIN) {
         HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, true, hs); }));
         if ((rc = pull())) return rc;
         while (any_running()) {
             while (any_running()) {
-                for (int c = 0; c < chunk; ++c) {
-                    HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
-                    HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
-                    HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
-                }
+                if ((rc = run_chunk())) return rc;
                 if ((rc = pull())) return rc;
             }
             // every mesh's recurrence converged, reached its limit or is due a
@@ -734,11 +836,7 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
             if ((rc = pull())) return rc;
             if (!any_running()) break;                   // every mesh converged, or at its limit
             while (any_running()) {
-                for (int c = 0; c < chunk; ++c) {
-                    HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg32_spmv(d, hs); }));
-                    HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg32_axpy(d, hs); }));
-                    HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg32_dir(d, hs); }));
-                }
+                if ((rc = run_chunk())) return rc;
                 if ((rc = pull())) return rc;
             }
             HIPCHK(launch_ir_update(d, hs));
@@ -787,6 +885,141 @@ int mifvm_mesh_values(const mifvm_state* st, int32_t what, double* out, int32_t 
             default: return fail(MIFVM_E_ARG, "unknown value id");
         }
     }
+    return MIFVM_OK;
+}
+
+namespace {
+std::map<std::string, std::array<int, 3>> read_tune_cache(const char* path) {
+    std::map<std::string, std::array<int, 3>> out;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        char key[256];
+        int c = 0, g = 0, sg = 0;
+        if (std::sscanf(line.c_str(), " \"%255[^\"]\": {\"chunk\": %d, \"graph\": %d, \"step_graph\": %d}", key, &c,
+                        &g, &sg) == 4)
+            out[key] = {c, g, sg};
+    }
+    return out;
+}
+
+void write_tune_cache(const char* path, const std::map<std::string, std::array<int, 3>>& m) {
+    std::ofstream o(path);
+    o << "{\n";
+    size_t k = 0;
+    for (auto& kv : m) {
+        o << "  \"" << kv.first << "\": {\"chunk\": " << kv.second[0] << ", \"graph\": " << kv.second[1]
+          << ", \"step_graph\": " << kv.second[2] << "}" << (++k < m.size() ? "," : "") << "\n";
+    }
+    o << "}\n";
+}
+}  // namespace
+
+int mifvm_autotune(mifvm_state* st, const char* cache_path, mifvm_tune_info* out, void* stream) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    State& s = st->s;
+    if (!s.assembled) return fail(MIFVM_E_STATE, "autotune times the solve: assemble first");
+    const Dev& d = s.d;
+    hipStream_t hs = S(stream);
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= d.nc) ++lg;
+    const std::string key = "gfx950/" + std::to_string(d.nm) + "/" + std::to_string(lg);
+    mifvm_tune_info info{};
+    std::map<std::string, std::array<int, 3>> cache;
+    if (cache_path) {
+        cache = read_tune_cache(cache_path);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            s.tuned_chunk = it->second[0];
+            s.tuned_graph = it->second[1];
+            s.tuned_step_graph = it->second[2];
+            info.chunk = s.tuned_chunk;
+            info.graph = s.tuned_graph;
+            info.step_graph = s.tuned_step_graph;
+            info.from_cache = 1;
+            if (out) *out = info;
+            return MIFVM_OK;
+        }
+    }
+    const bool timing_was_on = s.timer.on;
+    if (!s.timer.pending.empty()) return fail(MIFVM_E_STATE, "collect kernel timing first");
+    s.timer.on = false;
+    const int64_t NX = d.nc + d.nb;
+    double* saved_x = d.tmp + NX;                    // P is restored after the trials
+    HIPCHK(hipMemcpyAsync(saved_x, d.x, d.nc * sizeof(double), hipMemcpyDeviceToDevice, hs));
+    auto clock_ms = [&](auto fn) -> double {
+        HIPCHK(hipStreamSynchronize(hs));
+        auto t0 = std::chrono::steady_clock::now();
+        int r = fn();
+        HIPCHK(hipStreamSynchronize(hs));
+        if (r) return -1.0;
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
+    double best = 1e300;
+    int best_chunk = 32, best_graph = 0;
+    for (int chunk : {8, 16, 32, 64}) {
+        for (int graph : {0, 1}) {
+            HIPCHK(hipMemcpyAsync(d.x, saved_x, d.nc * sizeof(double), hipMemcpyDeviceToDevice, hs));
+            mifvm_solve_opts o{};
+            o.tol = 1e-300;                           // never met: exactly maxit iterations
+            o.maxit = 4 * chunk < 128 ? 128 : 4 * chunk;
+            o.chunk = chunk;
+            o.restart = 0;
+            o.graph = graph;
+            o.method = MIFVM_SOLVE_PLAIN;
+            mifvm_solve_info si{};
+            const double ms = clock_ms([&]() {
+                const int r = mifvm_poisson_solve(st, nullptr, &o, &si, stream);
+                return r == MIFVM_NOT_CONVERGED ? 0 : r;
+            });
+            if (ms < 0) return MIFVM_E_HIP;
+            const double per = ms / std::max(si.iterations, 1);
+            if (per < best) {
+                best = per;
+                best_chunk = chunk;
+                best_graph = graph;
+            }
+        }
+    }
+    HIPCHK(hipMemcpyAsync(d.x, saved_x, d.nc * sizeof(double), hipMemcpyDeviceToDevice, hs));
+    // one step, direct launches against a graph replay; the state is restored
+    double* saved_u = d.tmp + 2 * NX;
+    float* saved_u32 = d.d32;                         // inner-CG scratch, free here
+    HIPCHK(hipMemcpyAsync(saved_u, d.u, d.nc * sizeof(double), hipMemcpyDeviceToDevice, hs));
+    HIPCHK(hipMemcpyAsync(saved_u32, d.u32, d.nc * sizeof(float), hipMemcpyDeviceToDevice, hs));
+    const double dt = 1e-12;
+    auto restore_u = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(d.u, saved_u, d.nc * sizeof(double), hipMemcpyDeviceToDevice, hs));
+        HIPCHK(hipMemcpyAsync(d.u32, saved_u32, d.nc * sizeof(float), hipMemcpyDeviceToDevice, hs));
+        HIPCHK(launch_ghost_fill(d, s.fp32, s.bc[0], hs));
+        return MIFVM_OK;
+    };
+    const double t_direct = clock_ms([&]() { return mifvm_step(st, 2, dt, stream); });
+    int rc = restore_u();
+    if (rc) return rc;
+    rc = mifvm_step_graph(st, 2, dt, stream);         // capture outside the timed call
+    if (rc) return rc;
+    rc = restore_u();
+    if (rc) return rc;
+    const double t_graph = clock_ms([&]() { return mifvm_step_graph(st, 2, dt, stream); });
+    rc = restore_u();
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(hs));
+    s.timer.on = timing_was_on;
+    s.tuned_chunk = best_chunk;
+    s.tuned_graph = best_graph;
+    s.tuned_step_graph = t_graph < t_direct ? 1 : 0;
+    info.chunk = best_chunk;
+    info.graph = best_graph;
+    info.step_graph = s.tuned_step_graph;
+    info.ms_per_iteration = best;
+    info.ms_per_step_direct = t_direct / 2;
+    info.ms_per_step_graph = t_graph / 2;
+    if (cache_path) {
+        cache[key] = {best_chunk, best_graph, s.tuned_step_graph};
+        write_tune_cache(cache_path, cache);
+    }
+    if (out) *out = info;
     return MIFVM_OK;
 }
 

@@ -98,6 +98,15 @@ struct State {
     double cfl = 0.0;                     // factor of the last CFL evaluation
     std::vector<int> last_iters;          // per mesh, last solve
     std::vector<double> last_rel;
+    // captured launch sequences (hipGraph), replayed on the caller's stream
+    hipStream_t cap_stream = nullptr;     // library-owned, used only to capture
+    hipGraphExec_t cg_exec = nullptr;     // one chunk of CG iterations
+    int cg_exec_chunk = 0, cg_exec_method = -1;
+    hipGraphExec_t step_exec = nullptr;   // n RK3 steps
+    int step_exec_n = 0;
+    double step_exec_dt = -1.0;
+    // schedule chosen by the autotuner (0 = not tuned)
+    int tuned_chunk = 0, tuned_graph = 0, tuned_step_graph = 0;
     bool assembled = false;
     bool k32_ready = false;               // FP32 copy of K matches K
     bool vel_set = false;

@@ -113,3 +113,35 @@ def test_batch_solves_each_mesh_to_tolerance(method):
         assert abs(si["iterations"] - its[k]) <= 3
     # uneven meshes need different iteration counts, and each stopped on its own
     assert len(set(its.astype(int))) > 1
+
+
+def test_graph_replays_equal_direct_launches(tmp_path):
+    """A captured step graph and captured CG chunks give the same results as
+    direct launches (replayed several times, with other work in between)."""
+    ms, u0, vel = inputs()
+    a = make(B.Mesh.from_batch(ms), u0, vel, DIFF)
+    b = make(B.Mesh.from_batch(ms), u0, vel, DIFF)
+    for st in (a, b):
+        st.cfl_dt(0.4)
+        st.poisson_assemble()
+    for rep in range(3):
+        a.step(2, 0.0)
+        b.step_graph(2, 0.0)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(a.get_field(B.FIELD_U)), host(b.get_field(B.FIELD_U)))
+        ia = a.poisson_solve(None, tol=1e-10, chunk=16, graph=0)
+        ib = b.poisson_solve(None, tol=1e-10, chunk=16, graph=1)
+        assert ia["iterations"] == ib["iterations"]
+        assert np.array_equal(host(a.get_field(B.FIELD_P)), host(b.get_field(B.FIELD_P)))
+    # autotune: picks a schedule, restores the state, and caches the choice
+    cache = str(tmp_path / "tune.json")
+    u_before = host(b.get_field(B.FIELD_U))
+    p_before = host(b.get_field(B.FIELD_P))
+    t = b.autotune(cache)
+    assert t["chunk"] in (8, 16, 32, 64) and t["from_cache"] == 0
+    assert np.array_equal(host(b.get_field(B.FIELD_U)), u_before)
+    assert np.array_equal(host(b.get_field(B.FIELD_P)), p_before)
+    t2 = b.autotune(cache)
+    assert t2["from_cache"] == 1 and t2["chunk"] == t["chunk"]
+    info = b.poisson_solve(None, tol=1e-10)
+    assert info["status"] == B.OK
