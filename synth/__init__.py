@@ -8,8 +8,8 @@ fluxes or solver steps); each side computes those itself.
 """
 from .meshgen import CubeMesh, jittered_cube, BOUNDARY_TAGS
 from .fields import (gaussian_field, rotating_velocity, mms_source,
-                     mms_exact, problem_fields)
+                     mms_exact, problem_fields, batch_recipe, BatchMember)
 
 __all__ = ["CubeMesh", "jittered_cube", "BOUNDARY_TAGS",
            "gaussian_field", "rotating_velocity", "mms_source", "mms_exact",
-           "problem_fields"]
+           "problem_fields", "batch_recipe", "BatchMember"]

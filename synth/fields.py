@@ -57,3 +57,29 @@ def problem_fields(mesh: CubeMesh, center=(0.5, 0.5, 0.5), sigma=0.1,
     return ProblemFields(u0=gaussian_field(mesh, center, sigma),
                          vel=rotating_velocity(mesh),
                          diffusivity=float(diffusivity), cfl=float(cfl))
+
+
+@dataclass(frozen=True)
+class BatchMember:
+    n: int                  # hexes per side (6 n^3 cells)
+    seed: int
+    diffusivity: float
+    center: tuple
+
+
+def batch_recipe(count=64, seed=4242, lo=5e4, hi=2e6):
+    """Batched benchmark: `count` cube meshes with cell counts log-uniform in
+    [lo, hi] (n = round(cbrt(N / 6)) clamped to the range), diffusivity
+    uniform in [1e-4, 1e-2], Gaussian centre uniform in [0.3, 0.7]^3; mesh k
+    uses seed 1000 + k."""
+    rng = np.random.default_rng(seed)
+    nlo = int(np.ceil(np.cbrt(lo / 6.0)))
+    nhi = int(np.floor(np.cbrt(hi / 6.0)))
+    out = []
+    for k in range(count):
+        N = np.exp(rng.uniform(np.log(lo), np.log(hi)))
+        n = int(np.clip(round(np.cbrt(N / 6.0)), nlo, nhi))
+        D = float(rng.uniform(1e-4, 1e-2))
+        c = tuple(float(x) for x in rng.uniform(0.3, 0.7, 3))
+        out.append(BatchMember(n=n, seed=1000 + k, diffusivity=D, center=c))
+    return out
