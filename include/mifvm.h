@@ -42,6 +42,8 @@ extern "C" {
 enum mifvm_status {
     MIFVM_OK = 0,
     MIFVM_NOT_CONVERGED = 1,   /* solve hit maxit; info is filled          */
+    MIFVM_FELL_BACK = 2,       /* learned solve stalled, switched to plain
+                                  Jacobi-CG and converged; info is filled   */
     MIFVM_E_ARG = -1,          /* invalid argument (null, range, size)      */
     MIFVM_E_MESH = -2,         /* degenerate/inverted cell, non-manifold or
                                   untagged boundary face                    */
@@ -138,13 +140,25 @@ typedef struct {
                                   -1: the autotuned choice (else 0)          */
     double inner_tol;          /* IR_FP32: relative reduction asked of each
                                   FP32 inner solve (0 = 1e-4)                */
+    int32_t stall_window;      /* LEARNED: fall back when the best residual
+                                  norm has not dropped by 1% in this many
+                                  iterations (0 = 200)                      */
+    int32_t learned_maxit;     /* LEARNED: fall back after this many flexible
+                                  CG iterations (0 = maxit)                  */
 } mifvm_solve_opts;
 
 /* PLAIN: FP64 Jacobi-CG.  IR_FP32: iterative refinement - the FP64 true
  * residual r = b - K x, an FP32 Jacobi-CG solve of K d = r on an FP32 copy of
  * K (dot products accumulated in FP64), x += d in FP64 - repeated until the
  * FP64 true residual meets tol.                                            */
-enum mifvm_solve_method { MIFVM_SOLVE_PLAIN = 0, MIFVM_SOLVE_IR_FP32 = 1 };
+enum mifvm_solve_method { MIFVM_SOLVE_PLAIN = 0, MIFVM_SOLVE_IR_FP32 = 1, MIFVM_SOLVE_LEARNED = 2 };
+/* LEARNED: flexible CG (Polak-Ribiere beta) preconditioned by the attached
+ * message-passing network (mifvm_nn.h), with restarts from the true residual
+ * as for PLAIN.  A non-finite residual (the iterate is reset to the last
+ * finite one), a stall (stall_window) or learned_maxit switches to PLAIN
+ * Jacobi-CG from the current iterate for the remaining iterations; the
+ * result is then FELL_BACK (or NOT_CONVERGED).  Needs a single-mesh state
+ * with an attached network.                                                 */
 
 typedef struct {
     int32_t iterations;
@@ -154,6 +168,8 @@ typedef struct {
     int32_t outer;             /* IR_FP32: refinement steps                   */
     double rel_residual;       /* final true relative residual (FP64)        */
     double ms;                 /* wall time of the solve call                */
+    int32_t fell_back;         /* LEARNED: 1 if the plain solver finished    */
+    int32_t learned_iterations;/* LEARNED: flexible-CG iterations            */
 } mifvm_solve_info;
 
 /* ---- errors --------------------------------------------------------------- */
@@ -292,7 +308,11 @@ enum mifvm_kernel {
     MIFVM_K_NODE_INTERP = 2 /* reserved: computed inside GRAD_LIMITER, never launched */,
     MIFVM_K_FACE_FLUX = 3, MIFVM_K_UPDATE = 4, MIFVM_K_CG_SETUP = 5, MIFVM_K_CG_SPMV = 6,
     MIFVM_K_CG_AXPY = 7, MIFVM_K_CG_DIR = 8, MIFVM_K_RHS = 9, MIFVM_K_ASSEMBLE = 10,
-    MIFVM_K_COUNT = 11
+    MIFVM_K_NN_LAYER1 = 11, MIFVM_K_NN_LAYER2 = 12, MIFVM_K_NN_LAYER3 = 13 /* network layers
+    (the first includes the encoder, the last the decoder) */,
+    MIFVM_K_FCG_VEC = 14 /* flexible-CG update and its scalar steps */,
+    MIFVM_K_NN_TRAIN = 15 /* one whole training step (all of its launches) */,
+    MIFVM_K_COUNT = 16
 };
 int mifvm_kernel_timing(mifvm_state* st, int32_t enable);
 /* Total milliseconds and number of timed launches of one kernel since the

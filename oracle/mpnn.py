@@ -20,10 +20,12 @@ relative residual of the preconditioned residual,
     L = || r - K z(r) ||^2 / || r ||^2,
 whose gradient needs dL/dz = -2 K^T (r - K z) / ||r||^2.
 
-``forward(..., bf16=True)`` rounds to bfloat16 exactly where the GPU kernels
-store or feed a matrix core (weights, h after every layer, m and u as MFMA
-inputs); ``backward`` differentiates the FP64 forward (rounding treated as
-the identity).  The backward is pinned by finite differences in the tests.
+``forward(..., bf16_like_gpu=True)`` rounds to bfloat16 exactly where the GPU
+kernels store or feed a matrix core (weights, h after every layer, m and u as
+MFMA inputs).  ``backward`` is the chain rule of the forward it is given:
+exact for the FP64 forward (pinned by finite differences in the tests); for
+the rounded forward it treats each rounding as the identity (straight-through)
+and so multiplies by the rounded weights, the ones that forward used.
 """
 from __future__ import annotations
 
@@ -104,7 +106,8 @@ def forward(p, r, dinv, nbr, bf16_like_gpu=False):
     s_r, s_d = scales(r, dinv)
     x = np.stack([r / s_r, dinv * r / s_d], axis=1)
     h = q(x @ q(p["We"]).T + p["be"])
-    cache = {"x": x, "h": [h], "a": [], "v": [], "u": [], "s_d": s_d, "s_r": s_r}
+    cache = {"x": x, "h": [h], "a": [], "v": [], "u": [], "s_d": s_d, "s_r": s_r,
+             "bf16": bool(bf16_like_gpu)}
     for l in range(LAYERS):
         m = q(_neigh_mean(h, nbr))
         a = np.concatenate([h, m], axis=1)
@@ -124,6 +127,7 @@ def backward(p, cache, nbr, dz):
     """Parameter gradients of sum_i dz_i z_i (FP64 chain rule)."""
     g = {}
     n = len(dz)
+    q = bf16 if cache.get("bf16") else (lambda a: np.asarray(a, np.float64))
     dy = cache["s_d"] * dz
     h3 = cache["h"][-1]
     g["wd"] = h3.T @ dy
@@ -133,19 +137,20 @@ def backward(p, cache, nbr, dz):
         a, v, u = cache["a"][l], cache["v"][l], cache["u"][l]
         g[f"W2_{l}"] = dh.T @ u
         g[f"b2_{l}"] = dh.sum(axis=0)
-        du = (dh @ p[f"W2_{l}"]) * (v > 0)
+        du = (dh @ q(p[f"W2_{l}"])) * (v > 0)
         g[f"W1_{l}"] = du.T @ a
         g[f"b1_{l}"] = du.sum(axis=0)
-        da = du @ p[f"W1_{l}"]
+        da = du @ q(p[f"W1_{l}"])
         dh = dh + da[:, :H] + _neigh_scatter(da[:, H:], nbr, n)
     g["We"] = dh.T @ cache["x"]
     g["be"] = dh.sum(axis=0)
     return g
 
 
-def loss_and_grad(p, K, r, dinv, nbr):
-    """L = ||r - K z||^2 / ||r||^2 and its parameter gradient (FP64)."""
-    z, cache = forward(p, r, dinv, nbr)
+def loss_and_grad(p, K, r, dinv, nbr, bf16_like_gpu=False):
+    """L = ||r - K z||^2 / ||r||^2 and its parameter gradient (FP64
+    arithmetic; with bf16_like_gpu the forward rounds as the GPU does)."""
+    z, cache = forward(p, r, dinv, nbr, bf16_like_gpu)
     res = r - K @ z
     rr = np.dot(r, r)
     L = np.dot(res, res) / rr

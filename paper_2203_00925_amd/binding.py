@@ -16,15 +16,17 @@ import numpy as np
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libmifvm.so")
 
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, FELL_BACK = 0, 1, 2
 ZERO_FLUX, NEUMANN, DIRICHLET = 0, 1, 2
 VAR_SCALAR, VAR_POTENTIAL = 0, 1
 FIELD_U, FIELD_VEL, FIELD_SOURCE, FIELD_P = 0, 1, 2, 3
 RENUMBER_NONE, RENUMBER_MORTON = 0, 1
-SOLVE_PLAIN, SOLVE_IR_FP32 = 0, 1
+SOLVE_PLAIN, SOLVE_IR_FP32, SOLVE_LEARNED = 0, 1, 2
 FP64, FP32 = 0, 1
 KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
-           "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble")
+           "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble", "nn_layer1", "nn_layer2", "nn_layer3",
+           "fcg_vec", "nn_train")
+NN_PARAMS = 9537
 
 EXPORTS = {  # id: (name, dtype, shape-fn(info))
     0: ("cell_perm", np.int32, lambda i: (i.nc,)),
@@ -78,7 +80,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("chunk", C.c_int32),
                 ("restart", C.c_int32), ("history_cap", C.c_int32),
                 ("history", C.POINTER(C.c_double)), ("method", C.c_int32),
-                ("graph", C.c_int32), ("inner_tol", C.c_double)]
+                ("graph", C.c_int32), ("inner_tol", C.c_double),
+                ("stall_window", C.c_int32), ("learned_maxit", C.c_int32)]
 
 
 class TuneInfo(C.Structure):
@@ -90,7 +93,23 @@ class TuneInfo(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32),
                 ("history_len", C.c_int32), ("outer", C.c_int32),
-                ("rel_residual", C.c_double), ("ms", C.c_double)]
+                ("rel_residual", C.c_double), ("ms", C.c_double),
+                ("fell_back", C.c_int32), ("learned_iterations", C.c_int32)]
+
+
+class _NnOpts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("init_scale", C.c_double)]
+
+
+class _TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("pad_", C.c_int32), ("seed", C.c_uint64),
+                ("lr", C.c_double), ("lr_min", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double)]
+
+
+class _TrainInfo(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("loss_first", C.c_double), ("loss_last", C.c_double),
+                ("ms", C.c_double)]
 
 
 def _load():
@@ -126,6 +145,20 @@ def _load():
         "mifvm_step_graph": (C.c_int, [P, I32, D, P]),
         "mifvm_autotune": (C.c_int, [P, C.c_char_p, C.POINTER(TuneInfo), P]),
         "mifvm_kernel_stats": (C.c_int, [P, I32, C.POINTER(D), C.POINTER(I64), P]),
+        "mifvm_nn_workspace_bytes": (SZ, []),
+        "mifvm_nn_create": (C.c_int, [C.POINTER(_NnOpts), P, SZ, P, C.POINTER(P)]),
+        "mifvm_nn_destroy": (None, [P]),
+        "mifvm_nn_get_params": (C.c_int, [P, P, I64, P]),
+        "mifvm_nn_set_params": (C.c_int, [P, P, I64, P]),
+        "mifvm_nn_save": (C.c_int, [P, P, C.POINTER(SZ), P]),
+        "mifvm_nn_load": (C.c_int, [P, P, SZ, P]),
+        "mifvm_nn_attach_bytes": (C.c_int, [P, I32, C.POINTER(SZ)]),
+        "mifvm_nn_attach": (C.c_int, [P, P, I32, P, SZ, P]),
+        "mifvm_nn_apply": (C.c_int, [P, P, P, P]),
+        "mifvm_nn_sample": (C.c_int, [P, P, C.POINTER(D), P]),
+        "mifvm_nn_loss_grad": (C.c_int, [P, P, C.POINTER(D), P, P]),
+        "mifvm_nn_train": (C.c_int, [P, P, I32, P, P, I32, C.POINTER(_TrainOpts),
+                                     C.POINTER(_TrainInfo), P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -328,7 +361,8 @@ class State:
 
     def poisson_solve(self, f=None, tol=1e-10, maxit=20000, chunk=0, restart=500,
                       history=0, method=SOLVE_PLAIN, inner_tol=1e-4, graph=-1, stream=None,
-                      allow_not_converged=False):
+                      allow_not_converged=False, stall_window=0, learned_maxit=0,
+                      allow_fell_back=False):
         """chunk 0 / graph -1: the autotuned schedule (32 iterations per host
         check, direct launches when not tuned)."""
         import torch
@@ -336,14 +370,17 @@ class State:
             f = f.to(device=self.device, dtype=torch.float64).contiguous()
         hist = (C.c_double * max(int(history), 1))()
         opts = SolveOpts(float(tol), int(maxit), int(chunk), int(restart), int(history), hist,
-                         int(method), int(graph), float(inner_tol))
+                         int(method), int(graph), float(inner_tol), int(stall_window),
+                         int(learned_maxit))
         info = SolveInfo()
-        allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        allow = (OK,) + ((NOT_CONVERGED,) if allow_not_converged else ()) + \
+            ((FELL_BACK,) if allow_fell_back else ())
         rc = _check(_lib.mifvm_poisson_solve(self._h, _ptr(f), C.byref(opts), C.byref(info),
                                              _stream(stream)), allow)
         return dict(status=rc, iterations=info.iterations, restarts=info.restarts,
                     outer=info.outer, rel_residual=info.rel_residual, ms=info.ms,
-                    history=list(hist[:info.history_len]))
+                    history=list(hist[:info.history_len]), fell_back=info.fell_back,
+                    learned_iterations=info.learned_iterations)
 
     # -- per-kernel timing ----------------------------------------------------------
     def kernel_timing(self, enable=True):
@@ -357,3 +394,112 @@ class State:
             _check(_lib.mifvm_kernel_stats(self._h, k, C.byref(ms), C.byref(n), _stream(stream)))
             out[name] = (ms.value, n.value)
         return out
+
+
+class Network:
+    """Learned preconditioner (mifvm_nn_*): parameters in a torch uint8
+    workspace on the current device."""
+
+    def __init__(self, seed=0, init_scale=1.0, device="cuda", stream=None):
+        import torch
+        nbytes = int(_lib.mifvm_nn_workspace_bytes())
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        h = C.c_void_p()
+        _check(_lib.mifvm_nn_create(C.byref(_NnOpts(int(seed), float(init_scale))),
+                                    C.c_void_p(base + off), nbytes, _stream(stream), C.byref(h)))
+        self._h = h
+        self.device = device
+        self._attached = []
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            for st in getattr(self, "_attached", []):
+                if st._h:
+                    _lib.mifvm_nn_attach(st._h, None, 0, None, 0, None)
+            _lib.mifvm_nn_destroy(h)
+            self._h = None
+
+    def get_params(self, stream=None):
+        out = np.empty(NN_PARAMS, np.float32)
+        _check(_lib.mifvm_nn_get_params(self._h, out.ctypes.data, NN_PARAMS, _stream(stream)))
+        return out
+
+    def set_params(self, p, stream=None):
+        p = np.ascontiguousarray(p, np.float32)
+        _check(_lib.mifvm_nn_set_params(self._h, p.ctypes.data, len(p), _stream(stream)))
+
+    def save(self, stream=None):
+        n = C.c_size_t()
+        _check(_lib.mifvm_nn_save(self._h, None, C.byref(n), _stream(stream)))
+        buf = (C.c_char * n.value)()
+        _check(_lib.mifvm_nn_save(self._h, buf, C.byref(n), _stream(stream)))
+        return bytes(buf[:n.value])
+
+    def load(self, blob, stream=None):
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(_lib.mifvm_nn_load(self._h, buf, len(blob), _stream(stream)))
+
+    def attach(self, state, training=False, stream=None):
+        """Attach to a single-mesh state; the per-state buffers are kept on
+        the state object."""
+        import torch
+        n = C.c_size_t()
+        _check(_lib.mifvm_nn_attach_bytes(state._h, 1 if training else 0, C.byref(n)))
+        ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        _check(_lib.mifvm_nn_attach(state._h, self._h, 1 if training else 0,
+                                    C.c_void_p(ws.data_ptr() + off), n.value, _stream(stream)))
+        state._nn_ws = ws
+        state._nn = self
+        self._attached.append(state)
+
+    def train(self, states, samples, state_of_sample, epochs=1, lr=1e-3, lr_min=1e-4, seed=0,
+              beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        """samples: list of FP32 device tensors from State.nn_sample."""
+        states = list(states)
+        hs = (C.c_void_p * len(states))(*[s._h for s in states])
+        ptrs = (C.c_void_p * len(samples))(*[t.data_ptr() for t in samples])
+        sos = np.ascontiguousarray(state_of_sample, np.int32)
+        opts = _TrainOpts(int(epochs), 0, int(seed), float(lr), float(lr_min), float(beta1),
+                          float(beta2), float(eps))
+        info = _TrainInfo()
+        ep = np.zeros(int(epochs), np.float64)
+        _check(_lib.mifvm_nn_train(self._h, hs, len(states), ptrs, sos.ctypes.data, len(samples),
+                                   C.byref(opts), C.byref(info), ep.ctypes.data, _stream(stream)))
+        return dict(steps=info.steps, loss_first=info.loss_first, loss_last=info.loss_last,
+                    ms=info.ms, epoch_loss=ep)
+
+
+def _state_nn_apply(self, r, stream=None):
+    """z = network(r), FP64 user order."""
+    import torch
+    r = r.to(device=self.device, dtype=torch.float64).contiguous()
+    z = torch.empty_like(r)
+    _check(_lib.mifvm_nn_apply(self._h, _ptr(r), _ptr(z), _stream(stream)))
+    return z
+
+
+def _state_nn_sample(self, out=None, stream=None):
+    """(FP32 internal-order sample of the current true residual, its RMS)."""
+    import torch
+    if out is None:
+        out = torch.empty(self.mesh.info.nc, dtype=torch.float32, device=self.device)
+    rms = C.c_double()
+    _check(_lib.mifvm_nn_sample(self._h, _ptr(out), C.byref(rms), _stream(stream)))
+    return out, rms.value
+
+
+def _state_nn_loss_grad(self, sample, stream=None):
+    loss = C.c_double()
+    grad = np.empty(NN_PARAMS, np.float32)
+    _check(_lib.mifvm_nn_loss_grad(self._h, _ptr(sample), C.byref(loss), grad.ctypes.data,
+                                   _stream(stream)))
+    return loss.value, grad
+
+
+State.nn_apply = _state_nn_apply
+State.nn_sample = _state_nn_sample
+State.nn_loss_grad = _state_nn_loss_grad

@@ -18,9 +18,10 @@ OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libmifvm.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["api.hip", "fv_kernels.hip", "solve_kernels.hip", "ir_kernels.hip"]
+HIP_SOURCES = ["api.hip", "nn_api.hip", "fv_kernels.hip", "solve_kernels.hip", "ir_kernels.hip",
+               "nn_kernels.hip"]
 CXX_SOURCES = ["mesh.cpp"]
-HEADERS = ["mesh.h", "state.h", "reduce.h", "cg_scalars.h"]
+HEADERS = ["mesh.h", "state.h", "reduce.h", "seg.h", "cg_scalars.h", "api_util.h", "nn.h"]
 
 
 def _hipcc() -> str:

@@ -15,89 +15,12 @@
 #include <string>
 
 #include "../../include/mifvm.h"
+#include "api_util.h"
 #include "mesh.h"
 #include "state.h"
 
-struct mifvm_mesh {
-    mifvm::Mesh m;
-};
-struct mifvm_state {
-    mifvm::State s;
-};
+using namespace mifvm_api;
 
-namespace {
-thread_local std::string g_err;
-
-int fail(int code, const std::string& msg) {
-    g_err = msg;
-    return code;
-}
-int hip_fail(hipError_t e, const char* where) {
-    return fail(MIFVM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
-}
-#define HIPCHK(call)                                          \
-    do {                                                      \
-        hipError_t e_ = (call);                               \
-        if (e_ != hipSuccess) return hip_fail(e_, #call);     \
-    } while (0)
-
-inline hipStream_t S(void* p) { return reinterpret_cast<hipStream_t>(p); }
-
-template <class T>
-T* carve(char* base, size_t& off, size_t count) {
-    off = (off + 255) & ~size_t(255);
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += count * sizeof(T);
-    return p;
-}
-
-template <class T>
-hipError_t up(T* dst, const std::vector<T>& src, hipStream_t s) {
-    if (src.empty()) return hipSuccess;
-    return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
-}
-
-int reduce_blocks(int64_t n) {
-    int64_t b = (n + mifvm::kBlock - 1) / mifvm::kBlock;
-    return int(b < 1024 ? (b < 1 ? 1 : b) : 1024);
-}
-
-// Launch `fn` on `s`; with timing on, bracket it with an event pair.
-template <class F>
-hipError_t timed(mifvm::KernelTimer& t, int kid, hipStream_t s, F fn) {
-    if (!t.on) return fn();
-    while (t.pool.size() < t.used + 2) {
-        hipEvent_t e;
-        hipError_t err = hipEventCreate(&e);
-        if (err != hipSuccess) return err;
-        t.pool.push_back(e);
-    }
-    const size_t at = t.used;
-    t.used += 2;
-    hipError_t err = hipEventRecord(t.pool[at], s);
-    if (err != hipSuccess) return err;
-    err = fn();
-    if (err != hipSuccess) return err;
-    err = hipEventRecord(t.pool[at + 1], s);
-    if (err != hipSuccess) return err;
-    t.pending.emplace_back(kid, at);
-    return hipSuccess;
-}
-
-// After the stream has been synchronised: fold pending pairs into totals.
-hipError_t timer_flush(mifvm::KernelTimer& t) {
-    for (auto& pr : t.pending) {
-        float ms = 0.f;
-        hipError_t err = hipEventElapsedTime(&ms, t.pool[pr.second], t.pool[pr.second + 1]);
-        if (err != hipSuccess) return err;
-        t.total_ms[pr.first] += ms;
-        t.count[pr.first] += 1;
-    }
-    t.pending.clear();
-    t.used = 0;
-    return hipSuccess;
-}
-}  // namespace
 
 namespace mifvm {
 
@@ -213,33 +136,6 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
 using namespace mifvm;
 
 namespace {
-// Capture the launches `enqueue` makes on the library's capture stream into
-// an executable graph (the kernels take their arguments by value, so the
-// graph can be replayed on any stream).
-template <class F>
-hipError_t capture_graph(State& s, hipGraphExec_t* exec, F enqueue) {
-    hipError_t e = hipSuccess;
-    if (!s.cap_stream) {
-        e = hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking);
-        if (e != hipSuccess) return e;
-    }
-    e = hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return e;
-    hipError_t le = enqueue(s.cap_stream);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(s.cap_stream, &g);
-    if (le != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return le;
-    }
-    if (e != hipSuccess) return e;
-    if (*exec) (void)hipGraphExecDestroy(*exec);
-    *exec = nullptr;
-    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    return e;
-}
-
 // one chunk of n CG iterations (plain FP64 or FP32 inner), no timing events
 hipError_t enqueue_cg_chunk(const Dev& d, int method, int n, hipStream_t q) {
     for (int c = 0; c < n; ++c) {
@@ -439,6 +335,8 @@ void mifvm_state_destroy(mifvm_state* st) {
     if (!st) return;
     if (st->s.cg_exec) (void)hipGraphExecDestroy(st->s.cg_exec);
     if (st->s.step_exec) (void)hipGraphExecDestroy(st->s.step_exec);
+    if (st->s.fcg_exec) (void)hipGraphExecDestroy(st->s.fcg_exec);
+    delete st->s.nn_state;
     if (st->s.cap_stream) (void)hipStreamDestroy(st->s.cap_stream);
     if (st->s.h_scal) (void)hipHostFree(st->s.h_scal);
     for (hipEvent_t e : st->s.timer.pool) (void)hipEventDestroy(e);
@@ -555,16 +453,6 @@ int mifvm_get_field(const mifvm_state* st, int32_t field, double* d_dst, void* s
     return MIFVM_OK;
 }
 
-namespace {
-// copy every mesh's scalars to the pinned host mirror and wait
-int pull_scalars(State& s, hipStream_t hs) {
-    HIPCHK(hipMemcpyAsync(s.h_scal, s.d.scal, size_t(s.d.nm) * SC_COUNT_ * sizeof(double),
-                          hipMemcpyDeviceToHost, hs));
-    HIPCHK(hipStreamSynchronize(hs));
-    return MIFVM_OK;
-}
-inline double hsc(const State& s, int m, int slot) { return s.h_scal[size_t(m) * SC_COUNT_ + slot]; }
-}  // namespace
 
 int mifvm_cfl_dt(mifvm_state* st, double cfl, double* dt_out, void* stream) {
     if (!st || !dt_out) return fail(MIFVM_E_ARG, "null argument");
@@ -700,6 +588,7 @@ int mifvm_poisson_assemble(mifvm_state* st, void* stream) {
     HIPCHK(timed(s.timer, MIFVM_K_ASSEMBLE, hs, [&] { return launch_assemble(s.d, s.bc[1], s.mesh->row_max, hs); }));
     s.assembled = true;
     s.k32_ready = false;
+    s.kt_ready = false;
     return MIFVM_OK;
 }
 
@@ -722,6 +611,7 @@ int rhs_internal(State& s, const double* d_f, hipStream_t hs) {
     else if (s.fp32) HIPCHK(launch_cast_to_f64(d.nc, d.u32, d.tmp, hs));   // f = the FP32 state, widened
     const double* f = (d_f || s.fp32) ? d.tmp : d.u;
     HIPCHK(timed(s.timer, MIFVM_K_RHS, hs, [&] { return launch_rhs(d, f, hs); }));
+    s.b_ready = true;
     return MIFVM_OK;
 }
 }  // namespace
@@ -754,7 +644,15 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
     const int hist_cap = opts && opts->history ? opts->history_cap : 0;
     if (!(tol > 0) || maxit < 0 || restart < 0 || hist_cap < 0 || !(tol_in < 1))
         return fail(MIFVM_E_ARG, "bad tol, maxit, restart, inner_tol or history");
-    if (method != MIFVM_SOLVE_PLAIN && method != MIFVM_SOLVE_IR_FP32) return fail(MIFVM_E_ARG, "unknown method");
+    if (method != MIFVM_SOLVE_PLAIN && method != MIFVM_SOLVE_IR_FP32 && method != MIFVM_SOLVE_LEARNED)
+        return fail(MIFVM_E_ARG, "unknown method");
+    const int stall_window = opts ? opts->stall_window : 0;
+    const int learned_maxit = opts ? opts->learned_maxit : 0;
+    if (stall_window < 0 || learned_maxit < 0) return fail(MIFVM_E_ARG, "bad stall_window or learned_maxit");
+    if (method == MIFVM_SOLVE_LEARNED) {
+        if (!s.nn || !s.nn_state) return fail(MIFVM_E_STATE, "method LEARNED needs an attached network");
+        if (s.d.nm != 1) return fail(MIFVM_E_ARG, "method LEARNED needs a single-mesh state");
+    }
     const Dev& d = s.d;
     const int nm = d.nm;
     hipStream_t hs = S(stream);
@@ -784,10 +682,20 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
             if (hsc(s, m, SC_DONE) == 0.0) return true;
         return false;
     };
-    if (use_graph && (s.cg_exec == nullptr || s.cg_exec_chunk != chunk || s.cg_exec_method != method)) {
-        HIPCHK(capture_graph(s, &s.cg_exec, [&](hipStream_t q) { return enqueue_cg_chunk(d, method, chunk, q); }));
+    // learned: flexible CG first; the plain solver finishes after a fallback
+    LearnedRun learned;
+    int budget = maxit;
+    if (method == MIFVM_SOLVE_LEARNED) {
+        rc = learned_phase(s, tol, maxit, chunk, restart, stall_window, learned_maxit, use_graph, hs, pull, learned);
+        if (rc) return rc;
+        budget = maxit - learned.iterations;
+    }
+    const int run_method = method == MIFVM_SOLVE_LEARNED ? MIFVM_SOLVE_PLAIN : method;
+    if (use_graph && (method != MIFVM_SOLVE_LEARNED || learned.fell_back) &&
+        (s.cg_exec == nullptr || s.cg_exec_chunk != chunk || s.cg_exec_method != run_method)) {
+        HIPCHK(capture_graph(s, &s.cg_exec, [&](hipStream_t q) { return enqueue_cg_chunk(d, run_method, chunk, q); }));
         s.cg_exec_chunk = chunk;
-        s.cg_exec_method = method;
+        s.cg_exec_method = run_method;
     }
     // one chunk of iterations: a graph replay, or timed direct launches
     auto run_chunk = [&]() -> int {
@@ -796,7 +704,7 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
             return MIFVM_OK;
         }
         for (int c = 0; c < chunk; ++c) {
-            if (method == MIFVM_SOLVE_PLAIN) {
+            if (run_method == MIFVM_SOLVE_PLAIN) {
                 HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
                 HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
                 HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
@@ -808,9 +716,11 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         }
         return MIFVM_OK;
     };
-    int restarts = 0, outer = 0;
-    if (method == MIFVM_SOLVE_PLAIN) {
-        HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, true, hs); }));
+    int restarts = learned.restarts, outer = 0;
+    if (method == MIFVM_SOLVE_LEARNED && !learned.fell_back) {
+        // the flexible CG ended: converged, or at maxit
+    } else if (run_method == MIFVM_SOLVE_PLAIN) {
+        HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, budget, restart, true, hs); }));
         if ((rc = pull())) return rc;
         while (any_running()) {
             while (any_running()) {
@@ -855,7 +765,7 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
             HIPCHK(hipMemsetAsync(d.x + lo, 0, (hi - lo) * sizeof(double), hs));
         }
         s.last_rel[m] = bb > 0 ? std::sqrt(hsc(s, m, SC_TRUE_RR) / bb) : 0.0;
-        s.last_iters[m] = int(hsc(s, m, SC_IT));
+        s.last_iters[m] = int(hsc(s, m, SC_IT)) + (learned.fell_back ? learned.iterations : 0);
         iters = std::max(iters, s.last_iters[m]);
         rel = std::fmax(rel, s.last_rel[m]);
     }
@@ -867,9 +777,11 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         info->outer = outer;
         info->rel_residual = rel;
         info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        info->fell_back = learned.fell_back ? 1 : 0;
+        info->learned_iterations = learned.iterations;
     }
     if (!(rel <= tol)) return MIFVM_NOT_CONVERGED;
-    return MIFVM_OK;
+    return learned.fell_back ? MIFVM_FELL_BACK : MIFVM_OK;
 }
 
 int mifvm_mesh_values(const mifvm_state* st, int32_t what, double* out, int32_t n) {

@@ -1,0 +1,124 @@
+// Message-passing network used as a learned preconditioner for the Poisson
+// solve (not part of the paper's method; an added form of the solver).
+//
+//   x_i  = [r_i / s_r, (D^-1 r)_i / s_d]          s_r, s_d: RMS of r, D^-1 r
+//   h0_i = We x_i + be
+//   3 x: m_i = 1/4 sum_{j face neighbour of i} h_j
+//        u_i = relu(W1 [h_i; m_i] + b1),  h_i <- h_i + W2 u_i + b2
+//   y_i  = wd . h_i + bd,   z_i = (D^-1 r)_i + s_d y_i
+//
+// Hidden width 32.  Weights, h, m and u are bfloat16 (matrix-core operands),
+// accumulation FP32, z FP64.  Parameters are kept in FP32 (master copy) in
+// the order We[32][2], be, then per layer W1[32][64], b1, W2[32][32], b2,
+// then wd, bd.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "state.h"
+
+namespace mifvm {
+
+constexpr int kNnH = 32;
+constexpr int kNnLayers = 3;
+constexpr int kNnLayerSize = 32 * 64 + 32 + 32 * 32 + 32;   // 3136
+constexpr int kNnOffWe = 0, kNnOffBe = 64, kNnOffLayer = 96;
+constexpr int kNnW1 = 0, kNnB1 = 2048, kNnW2 = 2080, kNnB2 = 3104;  // within a layer
+constexpr int kNnOffWd = kNnOffLayer + kNnLayers * kNnLayerSize;    // 9504
+constexpr int kNnOffBd = kNnOffWd + 32;
+constexpr int kNnParams = kNnOffBd + 1;                             // 9537
+constexpr int kNnGridMax = 1024;          // blocks of the weight-gradient kernels
+
+// Storage order of a 32-feature row (h, and the per-cell backward rows):
+// slot q = 8g + j holds feature pi(q) = 4g + j (j < 4) or 16 + 4g + j - 4.
+// Lane group g (lanes 16g..16g+15) of a wave owns slots 8g..8g+7, which are
+// exactly the features a 16x16 matrix-core result tile leaves in its lanes
+// (rows 4g..4g+3 of both 16-row tiles), so every row is loaded and stored as
+// one 16-byte vector per lane.
+__host__ __device__ inline int nn_pi(int q) {
+    const int g = q >> 3, j = q & 7;
+    return j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4);
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Weights rearranged as matrix-core A operands (one 16-byte fragment per
+// lane) and per-slot vectors; rebuilt from the master copy after every update.
+struct NnPackLayer {
+    bf16x8 w1[2][2][64];    // W1 rows 16t.., k = 32s + pi(8g + j)
+    bf16x8 w2[2][64];       // W2 rows 16t.., k = pi(8g + j)
+    bf16x8 w2t[2][64];      // W2^T: row = input feature 16t + lane%16, k = output pi(8g + j)
+    bf16x8 w1t[4][64];      // W1^T: row = input 16t + lane%16 (0..63), k = output pi(8g + j)
+    float b1[32], b2[32];   // slot order
+};
+struct NnPack {
+    float we0[32], we1[32], be[32];   // bf16-rounded encoder columns, slot order
+    float wd[32];                     // slot order (FP32, not rounded)
+    float bd, pad_[63];
+    NnPackLayer layer[kNnLayers];
+};
+
+// Device memory of one network (carved from the caller's workspace).
+struct NnDev {
+    float* params;          // [kNnParams] FP32 master copy
+    float* grad;            // [kNnParams]
+    float* adam_m;          // [kNnParams]
+    float* adam_v;          // [kNnParams]
+    NnPack* pack;
+    float* partial;         // [kNnGridMax][kNnParams] per-block gradient sums
+    double* loss;           // [kNnLossRing] loss of each training step
+};
+constexpr int kNnLossRing = 65536;
+
+// Per-state buffers of an attached network.
+struct NnStateDev {
+    int4* nbr;              // [nc] face neighbours (internal numbering, -1: none)
+    u32x4* h1;              // [nc][4] bf16 rows (16-byte chunks)
+    u32x4* h2;
+    u32x4* h3;              // training only
+    double* r_old;          // [nc] previous residual (flexible CG)
+    double* x_bak;          // [nc] iterate saved at the last good check
+    float* base;            // [nc][32] training: dh + dh through the self half
+    float* dam0;            // [nc][32] training: gradient reaching m (ping)
+    float* dam1;            //                                        (pong)
+    double* kt_val;         // [matrix_padded] values of K^T in K's pattern
+    int32_t* flag;          // [1] pattern check of the transpose (0 = ok)
+    bool training;
+};
+
+size_t nn_layout(char* base, NnDev& n);
+size_t nn_state_layout(const Mesh& m, bool training, char* base, NnStateDev& a);
+
+// launchers (nn_kernels.hip)
+hipError_t launch_nn_pack(const NnDev& n, hipStream_t s);
+hipError_t launch_nn_neighbours(const Dev& d, const NnStateDev& a, hipStream_t s);
+hipError_t launch_nn_transpose(const Dev& d, const NnStateDev& a, hipStream_t s);
+// RMS scales of r (r64 or r32 is the input) into the mesh-0 scalar slots
+hipError_t launch_nn_scale(const Dev& d, const double* r64, const float* r32, hipStream_t s);
+// one forward layer (0, 1, 2); the last writes z (FP64).  fcg: skipped once
+// the solve is done, and the last layer writes partial z.r and z.r_old.
+// keep_h3: the last layer also stores its rows (training).
+hipError_t launch_nn_layer(const Dev& d, const NnDev& n, const NnStateDev& a, int layer, const double* r64,
+                           const float* r32, double* z, bool keep_h3, bool fcg, hipStream_t s);
+int nn_forward_grid(int64_t nc);
+int nn_backward_grid(int64_t nc);
+// training, after the forward on r32 (z in d.z): res = r - K z, the step's
+// loss into *loss_slot, w = K^T res, the backward and per-block gradients
+hipError_t launch_nn_backward(const Dev& d, const NnDev& n, const NnStateDev& a, const float* r32,
+                              double* loss_slot, hipStream_t s);
+// gradient = sum of the per-block sums (nblocks); apply: one Adam update
+// (c1 = 1/(1-beta1^t), c2 = 1/sqrt(1-beta2^t)) and a repack of the operands
+hipError_t launch_nn_adam(const NnDev& n, int nblocks, int apply, float lr, float c1, float c2, float beta1,
+                          float beta2, float eps, hipStream_t s);
+// r = b - K x, its scales, out = r / s_r in FP32 (a training sample)
+hipError_t launch_nn_sample(const Dev& d, float* out, hipStream_t s);
+// flexible CG steps
+hipError_t launch_fcg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s);
+hipError_t launch_fcg_setup_tail(const Dev& d, hipStream_t s);
+hipError_t launch_fcg_axpy(const Dev& d, const NnStateDev& a, hipStream_t s);
+hipError_t launch_fcg_beta(const Dev& d, hipStream_t s);
+hipError_t launch_fcg_backup(const Dev& d, const NnStateDev& a, bool restore, hipStream_t s);
+
+}  // namespace mifvm

@@ -1,0 +1,482 @@
+// C ABI of the learned preconditioner (declared in include/mifvm_nn.h) and
+// the flexible-CG phase of mifvm_poisson_solve with method LEARNED.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <random>
+#include <vector>
+
+#include "../../include/mifvm.h"
+#include "../../include/mifvm_nn.h"
+#include "api_util.h"
+#include "nn.h"
+
+static_assert(MIFVM_NN_PARAMS == mifvm::kNnParams, "parameter count of the ABI and the kernels");
+
+struct mifvm_nn {
+    mifvm::NnDev n;
+    int64_t adam_steps = 0;
+};
+
+using namespace mifvm_api;
+
+namespace mifvm {
+
+size_t nn_layout(char* base, NnDev& n) {
+    size_t off = 0;
+    n.params = carve<float>(base, off, kNnParams);
+    n.grad = carve<float>(base, off, kNnParams);
+    n.adam_m = carve<float>(base, off, kNnParams);
+    n.adam_v = carve<float>(base, off, kNnParams);
+    n.pack = carve<NnPack>(base, off, 1);
+    n.partial = carve<float>(base, off, size_t(kNnGridMax) * kNnParams);
+    n.loss = carve<double>(base, off, kNnLossRing);
+    return (off + 255) & ~size_t(255);
+}
+
+size_t nn_state_layout(const Mesh& m, bool training, char* base, NnStateDev& a) {
+    size_t off = 0;
+    const int64_t nc = m.nc;
+    a = NnStateDev{};
+    a.nbr = carve<int4>(base, off, nc);
+    a.h1 = carve<u32x4>(base, off, 4 * nc);
+    a.h2 = carve<u32x4>(base, off, 4 * nc);
+    a.r_old = carve<double>(base, off, nc);
+    a.x_bak = carve<double>(base, off, nc);
+    a.flag = carve<int32_t>(base, off, 1);
+    if (training) {
+        a.h3 = carve<u32x4>(base, off, 4 * nc);
+        a.base = carve<float>(base, off, 32 * nc);
+        a.dam0 = carve<float>(base, off, 32 * nc);
+        a.dam1 = carve<float>(base, off, 32 * nc);
+        a.kt_val = carve<double>(base, off, m.kmat.idx.size());
+    }
+    a.training = training;
+    return (off + 255) & ~size_t(255);
+}
+
+}  // namespace mifvm
+
+namespace {
+
+std::vector<float> initial_params(uint64_t seed, double scale) {
+    std::vector<float> p(kNnParams, 0.f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> N(0.0, 1.0);
+    auto fill = [&](int at, int count, int fan_in) {
+        const double sd = scale * std::sqrt(2.0 / fan_in);
+        for (int k = 0; k < count; ++k) p[at + k] = float(sd * N(rng));
+    };
+    fill(kNnOffWe, 64, 2);
+    for (int l = 0; l < kNnLayers; ++l) {
+        fill(kNnOffLayer + l * kNnLayerSize + kNnW1, 32 * 64, 64);
+        fill(kNnOffLayer + l * kNnLayerSize + kNnW2, 32 * 32, 32);
+    }
+    return p;
+}
+
+// upload a full parameter set, clear the Adam state, repack the operands
+int put_params(mifvm_nn* nn, const float* p, hipStream_t hs) {
+    for (int k = 0; k < kNnParams; ++k)
+        if (!std::isfinite(p[k])) return fail(MIFVM_E_ARG, "non-finite parameter " + std::to_string(k));
+    const NnDev& n = nn->n;
+    HIPCHK(hipMemcpyAsync(n.params, p, kNnParams * sizeof(float), hipMemcpyHostToDevice, hs));
+    HIPCHK(hipMemsetAsync(n.adam_m, 0, kNnParams * sizeof(float), hs));
+    HIPCHK(hipMemsetAsync(n.adam_v, 0, kNnParams * sizeof(float), hs));
+    HIPCHK(launch_nn_pack(n, hs));
+    HIPCHK(hipStreamSynchronize(hs));                 // p may be freed by the caller
+    nn->adam_steps = 0;
+    return MIFVM_OK;
+}
+
+int need_attached(const State& s, bool training) {
+    if (!s.nn || !s.nn_state) return fail(MIFVM_E_STATE, "no network attached to this state");
+    if (training && !s.nn_state->training) return fail(MIFVM_E_STATE, "the network is attached without training buffers");
+    if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
+    return MIFVM_OK;
+}
+
+// values of K^T, once per assembly
+int ensure_transpose(State& s, hipStream_t hs) {
+    if (s.kt_ready) return MIFVM_OK;
+    const NnStateDev& a = *s.nn_state;
+    HIPCHK(hipMemsetAsync(a.flag, 0, sizeof(int32_t), hs));
+    HIPCHK(launch_nn_transpose(s.d, a, hs));
+    int32_t flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, a.flag, sizeof(int32_t), hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipStreamSynchronize(hs));
+    if (flag) return fail(MIFVM_E_STATE, "the pattern of K is not symmetric: K^T cannot share it");
+    s.kt_ready = true;
+    return MIFVM_OK;
+}
+
+struct AdamCfg {
+    bool apply;
+    float lr, c1, c2, beta1, beta2, eps;
+};
+
+// one forward + backward on a sample; with apply, one Adam step
+hipError_t train_step(State& s, const NnDev& n, const float* r32, double* loss_slot, const AdamCfg& c,
+                      hipStream_t hs) {
+    const Dev& d = s.d;
+    const NnStateDev& a = *s.nn_state;
+    hipError_t e = launch_nn_scale(d, nullptr, r32, hs);
+    for (int l = 0; e == hipSuccess && l < kNnLayers; ++l) e = launch_nn_layer(d, n, a, l, nullptr, r32, d.z, true, false, hs);
+    if (e == hipSuccess) e = launch_nn_backward(d, n, a, r32, loss_slot, hs);
+    if (e == hipSuccess)
+        e = launch_nn_adam(n, nn_backward_grid(d.nc), c.apply ? 1 : 0, c.lr, c.c1, c.c2, c.beta1, c.beta2, c.eps, hs);
+    return e;
+}
+
+// the network layers inside the flexible CG (z from d.r, dots with r, r_old)
+hipError_t fcg_forward(State& s, hipStream_t q, bool timing) {
+    const Dev& d = s.d;
+    const NnStateDev& a = *s.nn_state;
+    KernelTimer& tm = s.timer;
+    for (int l = 0; l < kNnLayers; ++l) {
+        auto fn = [&] { return launch_nn_layer(d, *s.nn, a, l, d.r, nullptr, d.z, false, true, q); };
+        hipError_t e = timing ? timed(tm, MIFVM_K_NN_LAYER1 + l, q, fn) : fn();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t enqueue_fcg_chunk(State& s, int n, hipStream_t q) {
+    const Dev& d = s.d;
+    for (int c = 0; c < n; ++c) {
+        hipError_t e = launch_cg_spmv(d, q);
+        if (e == hipSuccess) e = launch_fcg_axpy(d, *s.nn_state, q);
+        if (e == hipSuccess) e = fcg_forward(s, q, false);
+        if (e == hipSuccess) e = launch_fcg_beta(d, q);
+        if (e == hipSuccess) e = launch_cg_dir(d, q);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+namespace mifvm_api {
+
+int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int stall_window, int learned_maxit,
+                  bool use_graph, hipStream_t hs, const std::function<int()>& pull, LearnedRun& out) {
+    const Dev& d = s.d;
+    const NnStateDev& a = *s.nn_state;
+    KernelTimer& tm = s.timer;
+    const int limit = learned_maxit > 0 ? std::min(learned_maxit, maxit) : maxit;
+    const int window = stall_window > 0 ? stall_window : 200;
+    out = LearnedRun{};
+    auto setup = [&](bool fresh) -> int {
+        HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_fcg_setup(d, tol, limit, restart, fresh, hs); }));
+        HIPCHK(fcg_forward(s, hs, true));
+        HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_setup_tail(d, hs); }));
+        return pull();
+    };
+    if (use_graph && (s.fcg_exec == nullptr || s.fcg_exec_chunk != chunk)) {
+        HIPCHK(capture_graph(s, &s.fcg_exec, [&](hipStream_t q) { return enqueue_fcg_chunk(s, chunk, q); }));
+        s.fcg_exec_chunk = chunk;
+    }
+    auto run_chunk = [&]() -> int {
+        if (use_graph) {
+            HIPCHK(hipGraphLaunch(s.fcg_exec, hs));
+            return MIFVM_OK;
+        }
+        for (int c = 0; c < chunk; ++c) {
+            HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
+            HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_axpy(d, a, hs); }));
+            HIPCHK(fcg_forward(s, hs, true));
+            HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_beta(d, hs); }));
+            HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
+        }
+        return MIFVM_OK;
+    };
+    auto fall_back = [&](bool restore) -> int {
+        if (restore) HIPCHK(launch_fcg_backup(d, a, true, hs));
+        out.fell_back = true;
+        return MIFVM_OK;
+    };
+    HIPCHK(launch_fcg_backup(d, a, false, hs));
+    int rc = setup(true);
+    if (rc) return rc;
+    if (!std::isfinite(hsc(s, 0, SC_TRUE_RR)) || !std::isfinite(hsc(s, 0, SC_RZ))) return fall_back(true);
+    double best = hsc(s, 0, SC_RR);
+    double best_it = 0.0;
+    for (;;) {
+        while (hsc(s, 0, SC_DONE) == 0.0) {
+            if ((rc = run_chunk())) return rc;
+            if ((rc = pull())) return rc;
+            const double rr = hsc(s, 0, SC_RR), it = hsc(s, 0, SC_IT);
+            out.iterations = int(it);
+            if (!std::isfinite(rr) || !std::isfinite(hsc(s, 0, SC_RZ)) || !std::isfinite(hsc(s, 0, SC_BETA)))
+                return fall_back(true);
+            if (rr < 0.98 * best) {                  // the norm dropped by 1%
+                best = rr;
+                best_it = it;
+            } else if (it - best_it >= window) {
+                return fall_back(false);
+            }
+            HIPCHK(launch_fcg_backup(d, a, false, hs));
+        }
+        // converged by the recurrence, at the limit, or a restart is due:
+        // the true residual decides
+        if ((rc = setup(false))) return rc;
+        out.iterations = int(hsc(s, 0, SC_IT));
+        if (!std::isfinite(hsc(s, 0, SC_TRUE_RR)) || !std::isfinite(hsc(s, 0, SC_RZ))) return fall_back(true);
+        const double done = hsc(s, 0, SC_DONE);
+        if (done == 1.0) return MIFVM_OK;
+        if (done == 2.0) return limit < maxit ? fall_back(false) : MIFVM_OK;
+        ++out.restarts;
+    }
+}
+
+}  // namespace mifvm_api
+
+extern "C" {
+
+size_t mifvm_nn_workspace_bytes(void) {
+    NnDev probe{};
+    return nn_layout(nullptr, probe);
+}
+
+int mifvm_nn_create(const mifvm_nn_opts* opts, void* d_ws, size_t ws_bytes, void* stream, mifvm_nn** out) {
+    if (!out || !d_ws) return fail(MIFVM_E_ARG, "null argument");
+    *out = nullptr;
+    if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(MIFVM_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < mifvm_nn_workspace_bytes())
+        return fail(MIFVM_E_WORKSPACE, "workspace too small: need " + std::to_string(mifvm_nn_workspace_bytes()));
+    const double scale = opts && opts->init_scale > 0 ? opts->init_scale : 1.0;
+    if (!std::isfinite(scale)) return fail(MIFVM_E_ARG, "bad init_scale");
+    auto* nn = new (std::nothrow) mifvm_nn();
+    if (!nn) return fail(MIFVM_E_ARG, "out of host memory");
+    nn_layout(static_cast<char*>(d_ws), nn->n);
+    const std::vector<float> p = initial_params(opts ? opts->seed : 0, scale);
+    const int rc = put_params(nn, p.data(), S(stream));
+    if (rc) {
+        delete nn;
+        return rc;
+    }
+    *out = nn;
+    return MIFVM_OK;
+}
+
+void mifvm_nn_destroy(mifvm_nn* nn) { delete nn; }
+
+int mifvm_nn_get_params(const mifvm_nn* nn, float* out, int64_t n, void* stream) {
+    if (!nn || !out) return fail(MIFVM_E_ARG, "null argument");
+    if (n != kNnParams) return fail(MIFVM_E_ARG, "need MIFVM_NN_PARAMS values");
+    hipStream_t hs = S(stream);
+    HIPCHK(hipMemcpyAsync(out, nn->n.params, kNnParams * sizeof(float), hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipStreamSynchronize(hs));
+    return MIFVM_OK;
+}
+
+int mifvm_nn_set_params(mifvm_nn* nn, const float* in, int64_t n, void* stream) {
+    if (!nn || !in) return fail(MIFVM_E_ARG, "null argument");
+    if (n != kNnParams) return fail(MIFVM_E_ARG, "need MIFVM_NN_PARAMS values");
+    return put_params(nn, in, S(stream));
+}
+
+namespace {
+constexpr char kTag[8] = {'M', 'I', 'F', 'V', 'M', 'N', 'N', '1'};
+constexpr size_t kBlobBytes = 16 + sizeof(float) * size_t(kNnParams);
+}  // namespace
+
+int mifvm_nn_save(const mifvm_nn* nn, void* buf, size_t* bytes, void* stream) {
+    if (!nn || !bytes) return fail(MIFVM_E_ARG, "null argument");
+    if (!buf) {
+        *bytes = kBlobBytes;
+        return MIFVM_OK;
+    }
+    if (*bytes < kBlobBytes) return fail(MIFVM_E_ARG, "buffer too small: need " + std::to_string(kBlobBytes));
+    std::vector<float> p(kNnParams);
+    const int rc = mifvm_nn_get_params(nn, p.data(), kNnParams, stream);
+    if (rc) return rc;
+    char* o = static_cast<char*>(buf);
+    const uint32_t version = 1, count = kNnParams;
+    std::memcpy(o, kTag, 8);
+    std::memcpy(o + 8, &version, 4);
+    std::memcpy(o + 12, &count, 4);
+    std::memcpy(o + 16, p.data(), sizeof(float) * p.size());
+    *bytes = kBlobBytes;
+    return MIFVM_OK;
+}
+
+int mifvm_nn_load(mifvm_nn* nn, const void* buf, size_t bytes, void* stream) {
+    if (!nn || !buf) return fail(MIFVM_E_ARG, "null argument");
+    if (bytes != kBlobBytes) return fail(MIFVM_E_ARG, "blob size " + std::to_string(bytes) + " != " + std::to_string(kBlobBytes));
+    const char* b = static_cast<const char*>(buf);
+    uint32_t version = 0, count = 0;
+    std::memcpy(&version, b + 8, 4);
+    std::memcpy(&count, b + 12, 4);
+    if (std::memcmp(b, kTag, 8) != 0) return fail(MIFVM_E_ARG, "not a network blob (tag)");
+    if (version != 1 || count != uint32_t(kNnParams)) return fail(MIFVM_E_ARG, "unsupported version or parameter count");
+    std::vector<float> p(kNnParams);
+    std::memcpy(p.data(), b + 16, sizeof(float) * p.size());
+    return put_params(nn, p.data(), S(stream));
+}
+
+int mifvm_nn_attach_bytes(const mifvm_state* st, int32_t training, size_t* out) {
+    if (!st || !out) return fail(MIFVM_E_ARG, "null argument");
+    NnStateDev probe;
+    *out = nn_state_layout(*st->s.mesh, training != 0, nullptr, probe);
+    return MIFVM_OK;
+}
+
+int mifvm_nn_attach(mifvm_state* st, mifvm_nn* nn, int32_t training, void* d_ws, size_t ws_bytes, void* stream) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    State& s = st->s;
+    if (!nn) {                                        // detach
+        delete s.nn_state;
+        s.nn_state = nullptr;
+        s.nn = nullptr;
+        s.nn_handle = nullptr;
+        s.kt_ready = false;
+        if (s.fcg_exec) (void)hipGraphExecDestroy(s.fcg_exec);
+        s.fcg_exec = nullptr;
+        return MIFVM_OK;
+    }
+    if (!d_ws) return fail(MIFVM_E_ARG, "null workspace");
+    if (s.d.nm != 1) return fail(MIFVM_E_ARG, "the learned preconditioner needs a single-mesh state");
+    if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(MIFVM_E_WORKSPACE, "workspace not 256-byte aligned");
+    NnStateDev probe;
+    const size_t need = nn_state_layout(*s.mesh, training != 0, nullptr, probe);
+    if (ws_bytes < need) return fail(MIFVM_E_WORKSPACE, "workspace too small: need " + std::to_string(need));
+    auto* a = new (std::nothrow) NnStateDev();
+    if (!a) return fail(MIFVM_E_ARG, "out of host memory");
+    nn_state_layout(*s.mesh, training != 0, static_cast<char*>(d_ws), *a);
+    const hipError_t e = launch_nn_neighbours(s.d, *a, S(stream));
+    if (e != hipSuccess) {
+        delete a;
+        return hip_fail(e, "launch_nn_neighbours");
+    }
+    delete s.nn_state;
+    s.nn_state = a;
+    s.nn = &nn->n;
+    s.nn_handle = nn;
+    s.kt_ready = false;
+    if (s.fcg_exec) (void)hipGraphExecDestroy(s.fcg_exec);
+    s.fcg_exec = nullptr;
+    return MIFVM_OK;
+}
+
+int mifvm_nn_apply(mifvm_state* st, const double* d_r, double* d_z, void* stream) {
+    if (!st || !d_r || !d_z) return fail(MIFVM_E_ARG, "null argument");
+    State& s = st->s;
+    int rc = need_attached(s, false);
+    if (rc) return rc;
+    const Dev& d = s.d;
+    hipStream_t hs = S(stream);
+    HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_r, d.r, hs));
+    HIPCHK(launch_nn_scale(d, d.r, nullptr, hs));
+    for (int l = 0; l < kNnLayers; ++l)
+        HIPCHK(timed(s.timer, MIFVM_K_NN_LAYER1 + l, hs,
+                     [&] { return launch_nn_layer(d, *s.nn, *s.nn_state, l, d.r, nullptr, d.z, false, false, hs); }));
+    HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.z, d_z, hs));
+    return MIFVM_OK;
+}
+
+int mifvm_nn_sample(mifvm_state* st, float* d_out, double* rms, void* stream) {
+    if (!st || !d_out || !rms) return fail(MIFVM_E_ARG, "null argument");
+    State& s = st->s;
+    if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
+    if (!s.b_ready) return fail(MIFVM_E_STATE, "no right-hand side yet (solve or mifvm_poisson_rhs first)");
+    if (s.d.nm != 1) return fail(MIFVM_E_ARG, "samples are taken from single-mesh states");
+    hipStream_t hs = S(stream);
+    HIPCHK(launch_nn_sample(s.d, d_out, hs));
+    const int rc = pull_scalars(s, hs);
+    if (rc) return rc;
+    *rms = std::sqrt(hsc(s, 0, SC_NN_RR) / double(s.d.nc));
+    return MIFVM_OK;
+}
+
+int mifvm_nn_loss_grad(mifvm_state* st, const float* d_sample, double* loss, float* grad, void* stream) {
+    if (!st || !d_sample || !loss || !grad) return fail(MIFVM_E_ARG, "null argument");
+    State& s = st->s;
+    int rc = need_attached(s, true);
+    if (rc) return rc;
+    hipStream_t hs = S(stream);
+    if ((rc = ensure_transpose(s, hs))) return rc;
+    const NnDev& n = *s.nn;
+    const AdamCfg none{false, 0.f, 1.f, 1.f, 0.9f, 0.999f, 1e-8f};
+    HIPCHK(train_step(s, n, d_sample, n.loss, none, hs));
+    HIPCHK(hipMemcpyAsync(loss, n.loss, sizeof(double), hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipMemcpyAsync(grad, n.grad, kNnParams * sizeof(float), hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipStreamSynchronize(hs));
+    return MIFVM_OK;
+}
+
+int mifvm_nn_train(mifvm_nn* nn, mifvm_state* const* states, int32_t n_states, const float* const* d_samples,
+                   const int32_t* state_of_sample, int32_t n_samples, const mifvm_train_opts* opts,
+                   mifvm_train_info* info, double* epoch_loss, void* stream) {
+    if (!nn || !states || !d_samples || !state_of_sample || !opts) return fail(MIFVM_E_ARG, "null argument");
+    if (n_states <= 0 || n_samples <= 0 || opts->epochs <= 0) return fail(MIFVM_E_ARG, "nothing to train on");
+    if (!(opts->lr > 0) || !(opts->lr_min >= 0) || opts->lr_min > opts->lr) return fail(MIFVM_E_ARG, "bad lr / lr_min");
+    const float beta1 = opts->beta1 > 0 ? float(opts->beta1) : 0.9f;
+    const float beta2 = opts->beta2 > 0 ? float(opts->beta2) : 0.999f;
+    const float eps = opts->eps > 0 ? float(opts->eps) : 1e-8f;
+    if (!(beta1 < 1.f) || !(beta2 < 1.f)) return fail(MIFVM_E_ARG, "beta1, beta2 must be < 1");
+    hipStream_t hs = S(stream);
+    for (int k = 0; k < n_states; ++k) {
+        if (!states[k]) return fail(MIFVM_E_ARG, "null state");
+        State& s = states[k]->s;
+        int rc = need_attached(s, true);
+        if (rc) return rc;
+        if (s.nn_handle != nn) return fail(MIFVM_E_STATE, "a state is attached to another network");
+        if ((rc = ensure_transpose(s, hs))) return rc;
+    }
+    for (int k = 0; k < n_samples; ++k) {
+        if (state_of_sample[k] < 0 || state_of_sample[k] >= n_states) return fail(MIFVM_E_ARG, "state_of_sample out of range");
+        if (!d_samples[k]) return fail(MIFVM_E_ARG, "null sample");
+    }
+    const NnDev& n = nn->n;
+    auto t0 = std::chrono::steady_clock::now();
+    std::mt19937_64 rng(opts->seed);
+    std::vector<int32_t> order(n_samples);
+    for (int k = 0; k < n_samples; ++k) order[k] = k;
+    const int64_t total = int64_t(opts->epochs) * n_samples;
+    int64_t step = 0;
+    std::vector<double> losses;
+    double first = 0.0, last = 0.0;
+    for (int ep = 0; ep < opts->epochs; ++ep) {
+        std::shuffle(order.begin(), order.end(), rng);
+        double sum = 0.0;
+        for (int k0 = 0; k0 < n_samples; k0 += kNnLossRing) {
+            const int k1 = std::min<int>(n_samples, k0 + kNnLossRing);
+            for (int k = k0; k < k1; ++k) {
+                const int idx = order[k];
+                State& s = states[state_of_sample[idx]]->s;
+                const double frac = double(step) / double(total);
+                const float lr = float(opts->lr_min + 0.5 * (opts->lr - opts->lr_min) * (1.0 + std::cos(3.14159265358979323846 * frac)));
+                ++nn->adam_steps;
+                const double t = double(nn->adam_steps);
+                const AdamCfg c{true, lr, float(1.0 / (1.0 - std::pow(double(beta1), t))),
+                                float(1.0 / std::sqrt(1.0 - std::pow(double(beta2), t))), beta1, beta2, eps};
+                HIPCHK(timed(s.timer, MIFVM_K_NN_TRAIN, hs,
+                             [&] { return train_step(s, n, d_samples[idx], n.loss + (k - k0), c, hs); }));
+                ++step;
+            }
+            losses.resize(k1 - k0);
+            HIPCHK(hipMemcpyAsync(losses.data(), n.loss, losses.size() * sizeof(double), hipMemcpyDeviceToHost, hs));
+            HIPCHK(hipStreamSynchronize(hs));
+            for (double v : losses) sum += v;
+        }
+        for (int k = 0; k < n_states; ++k) HIPCHK(timer_flush(states[k]->s.timer));
+        const double mean = sum / n_samples;
+        if (epoch_loss) epoch_loss[ep] = mean;
+        if (ep == 0) first = mean;
+        last = mean;
+    }
+    if (info) {
+        info->steps = step;
+        info->loss_first = first;
+        info->loss_last = last;
+        info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return MIFVM_OK;
+}
+
+}  // extern "C"

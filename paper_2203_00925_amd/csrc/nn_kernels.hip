@@ -1,0 +1,1027 @@
+// Kernels of the learned preconditioner (network forward, training backward,
+// Adam) and of the flexible conjugate-gradient iteration that applies it.
+//
+// Work split of the network kernels: a wavefront takes 16 consecutive cells
+// (a "group"); lane l works on cell l % 16 and owns row slots 8g..8g+7 of it,
+// g = l / 16 (see nn_pi).  The per-cell products with W1 ([h; m] -> 32) and
+// W2 (32 -> 32) are bf16 16x16x32 matrix-core operations with the weights as
+// the A operand and the 16 cells' rows as the B operand, so each result tile
+// leaves a lane exactly the features of its own slots.  A block (4 waves)
+// walks 64-cell block-groups with a grid stride, the weights staying in
+// registers.  Reductions over cells (loss, dot products, weight gradients)
+// are per-block sums written with plain stores and added in block order by a
+// separate kernel: deterministic for a fixed grid.
+#include "nn.h"
+#include "reduce.h"
+#include "seg.h"
+#include "state.h"
+
+namespace mifvm {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kFwdGridMax = 2048;
+
+inline int nn_fwd_grid(int64_t nc) {
+    const int64_t g = (nc + 63) / 64;
+    return int(g < kFwdGridMax ? (g < 1 ? 1 : g) : kFwdGridMax);
+}
+inline int nn_bwd_grid(int64_t nc) {
+    const int64_t g = (nc + 63) / 64;
+    return int(g < kNnGridMax ? (g < 1 ? 1 : g) : kNnGridMax);
+}
+
+// bfloat16 <-> float (round to nearest even, as the oracle's rounding)
+__device__ inline uint32_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ inline float rbf(float f) { return __uint_as_float(f2bf(f) << 16); }
+
+__device__ inline void unpack8(u32x4 v, float* o) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        o[2 * k] = __uint_as_float(v[k] << 16);
+        o[2 * k + 1] = __uint_as_float(v[k] & 0xFFFF0000u);
+    }
+}
+// f must hold bf16-representable values or values to be rounded here
+__device__ inline u32x4 pack8(const float* f) {
+    u32x4 v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = f2bf(f[2 * k]) | (f2bf(f[2 * k + 1]) << 16);
+    return v;
+}
+__device__ inline bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma16(i16x4 a, i16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// hi + lo split of FP32 values into two bf16 operands (about 16 mantissa bits)
+__device__ inline void split8(const float* f, u32x4& hi, u32x4& lo) {
+    float h[8], l[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        h[j] = rbf(f[j]);
+        l[j] = f[j] - h[j];
+    }
+    hi = pack8(h);
+    lo = pack8(l);
+}
+
+struct NnIn {
+    int64_t nc;
+    const int4* nbr;
+    const double* r64;        // input residual (one of r64 / r32)
+    const float* r32;
+    const double* dinv;
+    const double* scal;       // mesh-0 scalar slots
+    const NnPack* pack;
+};
+
+// h0 of cell e (bf16-rounded), slots 8g..8g+7
+template <bool R32>
+__device__ inline void encode(const NnIn& A, int64_t e, const float* we0, const float* we1, const float* be,
+                              double isr, double isd, float* h) {
+    const double r = R32 ? double(A.r32[e]) : A.r64[e];
+    const float x0 = float(r * isr);
+    const float x1 = float(A.dinv[e] * r * isd);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) h[j] = rbf(fmaf(we0[j], x0, fmaf(we1[j], x1, be[j])));
+}
+
+// [h; m] of cell i for one layer: own row slots and the rounded neighbour mean
+template <bool FIRST, bool R32>
+__device__ inline void layer_input(const NnIn& A, const u32x4* hin, int64_t i, bool valid, int4 nb, int g,
+                                   const float* we0, const float* we1, const float* be, double isr, double isd,
+                                   float* hown, float* m) {
+    float acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = 0.f;
+    const int nbs[4] = {nb.x, nb.y, nb.z, nb.w};
+    if (FIRST) {
+        if (valid) encode<R32>(A, i, we0, we1, be, isr, isd, hown);
+        else
+#pragma unroll
+            for (int j = 0; j < 8; ++j) hown[j] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (nbs[k] < 0) continue;
+            float t[8];
+            encode<R32>(A, nbs[k], we0, we1, be, isr, isd, t);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] += t[j];
+        }
+    } else {
+        u32x4 z4 = {0u, 0u, 0u, 0u};
+        unpack8(valid ? hin[i * 4 + g] : z4, hown);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (nbs[k] < 0) continue;
+            float t[8];
+            unpack8(hin[int64_t(nbs[k]) * 4 + g], t);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] += t[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) m[j] = rbf(acc[j] * 0.25f);
+}
+
+// ---- forward -------------------------------------------------------------------
+// KIND 0: first layer (input encoded from r), 1: middle, 2: last (decoder and
+// z = D^-1 r + s_d y).  FCG: return at once when the solve has finished, and
+// write per-block partial sums of z.r and z.r_old.  KEEP: the last layer also
+// stores its h (training).
+struct NnFwd {
+    NnIn in;
+    const u32x4* hin;
+    u32x4* hout;
+    double* z;
+    const double* r_old;
+    double* partial;          // [2][gridDim.x]
+    int layer;
+};
+
+template <int KIND, bool R32, bool FCG, bool KEEP>
+__global__ __launch_bounds__(256) void k_nn_layer(NnFwd F) {
+    const NnIn& A = F.in;
+    if (FCG && A.scal[SC_DONE] != 0.0) return;
+    __shared__ double lds[4];
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, wv = threadIdx.x >> 6;
+    const NnPack* P = A.pack;
+    const NnPackLayer& L = P->layer[F.layer];
+    bf16x8 w1[2][2], w2[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        w1[t][0] = L.w1[t][0][lane];
+        w1[t][1] = L.w1[t][1][lane];
+        w2[t] = L.w2[t][lane];
+    }
+    float b1[8], b2[8], we0[8], we1[8], be[8], wd[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        b1[j] = L.b1[8 * g + j];
+        b2[j] = L.b2[8 * g + j];
+        we0[j] = P->we0[8 * g + j];
+        we1[j] = P->we1[8 * g + j];
+        be[j] = P->be[8 * g + j];
+        wd[j] = P->wd[8 * g + j];
+    }
+    const float bd = P->bd;
+    const double isr = A.scal[SC_NN_INV_SR], isd = A.scal[SC_NN_INV_SD], sd = A.scal[SC_NN_SD];
+    double zr = 0.0, zro = 0.0;
+    const int64_t nbg = (A.nc + 63) / 64;
+    for (int64_t bg = blockIdx.x; bg < nbg; bg += gridDim.x) {
+        const int64_t i = bg * 64 + wv * 16 + c;
+        const bool valid = i < A.nc;
+        const int4 nb = valid ? A.nbr[i] : make_int4(-1, -1, -1, -1);
+        float hown[8], m[8];
+        layer_input<KIND == 0, R32>(A, F.hin, i, valid, nb, g, we0, we1, be, isr, isd, hown, m);
+        const bf16x8 bh = as_bf(pack8(hown)), bm = as_bf(pack8(m));
+        f32x4 v[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            v[t] = mfma32(w1[t][0], bh, f32x4{0.f, 0.f, 0.f, 0.f});
+            v[t] = mfma32(w1[t][1], bm, v[t]);
+        }
+        float u[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) u[j] = rbf(fmaxf(v[j >> 2][j & 3] + b1[j], 0.f));
+        const bf16x8 bu = as_bf(pack8(u));
+        float hn[8];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const f32x4 o = mfma32(w2[t], bu, f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int k = 0; k < 4; ++k) hn[4 * t + k] = rbf((hown[4 * t + k] + o[k]) + b2[4 * t + k]);
+        }
+        if ((KIND != 2 || KEEP) && valid) F.hout[i * 4 + g] = pack8(hn);
+        if (KIND == 2) {
+            float y = 0.f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) y = fmaf(wd[j], hn[j], y);
+            y += __shfl_xor(y, 16, 64);
+            y += __shfl_xor(y, 32, 64);
+            y += bd;
+            if (g == 0 && valid) {
+                const double r = R32 ? double(A.r32[i]) : A.r64[i];
+                const double zi = A.dinv[i] * r + sd * double(y);
+                F.z[i] = zi;
+                if (FCG) {
+                    zr += zi * r;
+                    zro += zi * F.r_old[i];
+                }
+            }
+        }
+    }
+    if (FCG && KIND == 2) {
+        const double s0 = block_sum256(zr, lds);
+        const double s1 = block_sum256(zro, lds);
+        if (threadIdx.x == 0) {
+            F.partial[blockIdx.x] = s0;
+            F.partial[gridDim.x + blockIdx.x] = s1;
+        }
+    }
+}
+
+// ---- backward ------------------------------------------------------------------
+// Layer `layer` in reverse.  Input of the layer: h (TOP..: saved rows; FIRST:
+// re-encoded from r).  Gradient reaching the layer's output:
+//   TOP:  dh = dy wd with dy = s_d dz, dz = -2 w / ||r||^2, w = K^T (r - K z)
+//   else: dh = base + 1/4 sum_{face neighbours j} dam_j   (from the layer above)
+// The layer recomputes v = W1 [h; m] + b1 and u, then
+//   du = (W2^T dh) * [v > 0],  da = W1^T du = [da_h; da_m],
+//   base_out = dh + da_h,  dam_out = da_m,
+// and adds dW2 = dh u^T, db2 = dh, dW1 = du [h; m]^T, db1 = du (TOP also dwd =
+// dy h_out, dbd = dy) into per-block sums.  The data-path products split dh
+// and du into bf16 hi + lo operands; the weight-gradient products transpose
+// dh, du, u and [h; m] through LDS and run 16x16x16 bf16 tiles with the 16
+// cells as the contraction.
+struct NnBwd {
+    NnIn in;
+    const u32x4* hin;         // layer input rows (unused when FIRST)
+    const u32x4* hout;        // TOP: rows of the last layer's output
+    const double* w;          // TOP: K^T (r - K z)
+    const float* base_in;     // !TOP
+    const float* dam_in;
+    float* base_out;
+    float* dam_out;
+    float* partial;           // [gridDim.x][kNnParams]
+    int layer;
+};
+
+struct WaveT {                // per-wave transposes, [feature][cell] bf16
+    uint16_t dh_hi[32][16], dh_lo[32][16], du_hi[32][16], du_lo[32][16], u[32][16], a[64][16];
+};
+
+__device__ inline i16x4 ld4(const uint16_t* p) { return *reinterpret_cast<const i16x4*>(p); }
+
+template <bool FIRST, bool TOP>
+__global__ __launch_bounds__(256) void k_nn_bwd(NnBwd B) {
+    const NnIn& A = B.in;
+    __shared__ __align__(16) WaveT wt[4];
+    __shared__ float red[kNnLayerSize + 33];
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, wv = threadIdx.x >> 6;
+    const NnPack* P = A.pack;
+    const NnPackLayer& L = P->layer[B.layer];
+    bf16x8 w1[2][2], w2t[2], w1t[4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        w1[t][0] = L.w1[t][0][lane];
+        w1[t][1] = L.w1[t][1][lane];
+        w2t[t] = L.w2t[t][lane];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) w1t[t] = L.w1t[t][lane];
+    float b1[8], we0[8], we1[8], be[8], wd[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        b1[j] = L.b1[8 * g + j];
+        we0[j] = P->we0[8 * g + j];
+        we1[j] = P->we1[8 * g + j];
+        be[j] = P->be[8 * g + j];
+        wd[j] = P->wd[8 * g + j];
+    }
+    const double isr = A.scal[SC_NN_INV_SR], isd = A.scal[SC_NN_INV_SD], sd = A.scal[SC_NN_SD];
+    const double rr = A.scal[SC_NN_RR];
+    const double dscale = rr > 0.0 ? -2.0 * sd / rr : 0.0;      // dy = dscale * w
+    f32x4 gw2[2][2], gw1[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        gw2[a][0] = gw2[a][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gw1[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    float gb1[8], gb2[8], gwd[8], gbd = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) gb1[j] = gb2[j] = gwd[j] = 0.f;
+    WaveT& T = wt[wv];
+    const int64_t nbg = (A.nc + 63) / 64;
+    for (int64_t bg = blockIdx.x; bg < nbg; bg += gridDim.x) {
+        const int64_t i = bg * 64 + wv * 16 + c;
+        const bool valid = i < A.nc;
+        const int4 nb = valid ? A.nbr[i] : make_int4(-1, -1, -1, -1);
+        float hown[8], m[8];
+        layer_input<FIRST, true>(A, B.hin, i, valid, nb, g, we0, we1, be, isr, isd, hown, m);
+        const bf16x8 bh = as_bf(pack8(hown)), bm = as_bf(pack8(m));
+        float u[8];
+        bool on[8];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            f32x4 v = mfma32(w1[t][0], bh, f32x4{0.f, 0.f, 0.f, 0.f});
+            v = mfma32(w1[t][1], bm, v);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float vv = v[k] + b1[4 * t + k];
+                on[4 * t + k] = vv > 0.f;
+                u[4 * t + k] = rbf(fmaxf(vv, 0.f));
+            }
+        }
+        // gradient at the layer output
+        float dh[8];
+        if (TOP) {
+            const float dy = valid ? float(dscale * B.w[i]) : 0.f;
+            float ho[8];
+            u32x4 z4 = {0u, 0u, 0u, 0u};
+            unpack8(valid ? B.hout[i * 4 + g] : z4, ho);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                dh[j] = dy * wd[j];
+                gwd[j] = fmaf(dy, ho[j], gwd[j]);
+            }
+            if (g == 0) gbd += dy;
+        } else {
+            const int nbs[4] = {nb.x, nb.y, nb.z, nb.w};
+            float acc[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (nbs[k] < 0) continue;
+                const float4* q = reinterpret_cast<const float4*>(B.dam_in + int64_t(nbs[k]) * 32 + 8 * g);
+                const float4 q0 = q[0], q1 = q[1];
+                acc[0] += q0.x; acc[1] += q0.y; acc[2] += q0.z; acc[3] += q0.w;
+                acc[4] += q1.x; acc[5] += q1.y; acc[6] += q1.z; acc[7] += q1.w;
+            }
+            if (valid) {
+                const float4* q = reinterpret_cast<const float4*>(B.base_in + i * 32 + 8 * g);
+                const float4 q0 = q[0], q1 = q[1];
+                const float bs[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+                for (int j = 0; j < 8; ++j) dh[j] = bs[j] + 0.25f * acc[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) dh[j] = 0.f;
+            }
+        }
+        // du = (W2^T dh) * [v > 0]
+        u32x4 dh_hi, dh_lo;
+        split8(dh, dh_hi, dh_lo);
+        float du[8];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            f32x4 o = mfma32(w2t[t], as_bf(dh_hi), f32x4{0.f, 0.f, 0.f, 0.f});
+            o = mfma32(w2t[t], as_bf(dh_lo), o);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) du[4 * t + k] = on[4 * t + k] ? o[k] : 0.f;
+        }
+        // da = W1^T du
+        u32x4 du_hi, du_lo;
+        split8(du, du_hi, du_lo);
+        float da_h[8], da_m[8];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f32x4 o = mfma32(w1t[t], as_bf(du_hi), f32x4{0.f, 0.f, 0.f, 0.f});
+            o = mfma32(w1t[t], as_bf(du_lo), o);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (t < 2) da_h[4 * t + k] = o[k];
+                else da_m[4 * (t - 2) + k] = o[k];
+            }
+        }
+        if (valid) {
+            float4* bo = reinterpret_cast<float4*>(B.base_out + i * 32 + 8 * g);
+            float4* mo = reinterpret_cast<float4*>(B.dam_out + i * 32 + 8 * g);
+            bo[0] = make_float4(dh[0] + da_h[0], dh[1] + da_h[1], dh[2] + da_h[2], dh[3] + da_h[3]);
+            bo[1] = make_float4(dh[4] + da_h[4], dh[5] + da_h[5], dh[6] + da_h[6], dh[7] + da_h[7]);
+            mo[0] = make_float4(da_m[0], da_m[1], da_m[2], da_m[3]);
+            mo[1] = make_float4(da_m[4], da_m[5], da_m[6], da_m[7]);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            gb2[j] += dh[j];
+            gb1[j] += du[j];
+        }
+        // transposes for the weight gradients (invalid cells carry zero dh, du)
+        {
+            const u32x4 hh = dh_hi, hl = dh_lo, uh = du_hi, ulo = du_lo;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int f = nn_pi(8 * g + j);
+                const int k = j >> 1, sh = (j & 1) * 16;
+                T.dh_hi[f][c] = uint16_t(hh[k] >> sh);
+                T.dh_lo[f][c] = uint16_t(hl[k] >> sh);
+                T.du_hi[f][c] = uint16_t(uh[k] >> sh);
+                T.du_lo[f][c] = uint16_t(ulo[k] >> sh);
+                T.u[f][c] = uint16_t(f2bf(u[j]));
+                T.a[f][c] = uint16_t(f2bf(hown[j]));
+                T.a[32 + f][c] = uint16_t(f2bf(m[j]));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int to = 0; to < 2; ++to) {
+            const i16x4 ah = ld4(&T.dh_hi[16 * to + c][4 * g]), al = ld4(&T.dh_lo[16 * to + c][4 * g]);
+            const i16x4 ch = ld4(&T.du_hi[16 * to + c][4 * g]), cl = ld4(&T.du_lo[16 * to + c][4 * g]);
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti) {
+                const i16x4 bu = ld4(&T.u[16 * ti + c][4 * g]);
+                gw2[to][ti] = mfma16(ah, bu, gw2[to][ti]);
+                gw2[to][ti] = mfma16(al, bu, gw2[to][ti]);
+            }
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti) {
+                const i16x4 ba = ld4(&T.a[16 * ti + c][4 * g]);
+                gw1[to][ti] = mfma16(ch, ba, gw1[to][ti]);
+                gw1[to][ti] = mfma16(cl, ba, gw1[to][ti]);
+            }
+        }
+        __syncthreads();
+    }
+    // block sums: biases over the 16 cells of a lane group, then the waves in order
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            gb1[j] += __shfl_xor(gb1[j], o, 64);
+            gb2[j] += __shfl_xor(gb2[j], o, 64);
+            if (TOP) gwd[j] += __shfl_xor(gwd[j], o, 64);
+        }
+    if (TOP) {
+        gbd += __shfl_xor(gbd, 1, 64);
+        gbd += __shfl_xor(gbd, 2, 64);
+        gbd += __shfl_xor(gbd, 4, 64);
+        gbd += __shfl_xor(gbd, 8, 64);
+    }
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w) {
+            auto put = [&](int idx, float val) {
+                if (w == 0) red[idx] = val;
+                else red[idx] += val;
+            };
+#pragma unroll
+            for (int to = 0; to < 2; ++to)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int out = 16 * to + 4 * g + k;
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti) put(kNnW2 + out * 32 + 16 * ti + c, gw2[to][ti][k]);
+#pragma unroll
+                    for (int ti = 0; ti < 4; ++ti) put(kNnW1 + out * 64 + 16 * ti + c, gw1[to][ti][k]);
+                }
+            if (c == 0) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int f = nn_pi(8 * g + j);
+                    put(kNnB1 + f, gb1[j]);
+                    put(kNnB2 + f, gb2[j]);
+                    if (TOP) put(kNnLayerSize + f, gwd[j]);
+                }
+                if (TOP && g == 0) put(kNnLayerSize + 32, gbd);
+            }
+        }
+        __syncthreads();
+    }
+    float* out = B.partial + int64_t(blockIdx.x) * kNnParams;
+    const int base = kNnOffLayer + B.layer * kNnLayerSize;
+    for (int k = threadIdx.x; k < kNnLayerSize; k += blockDim.x) out[base + k] = red[k];
+    if (TOP)
+        for (int k = threadIdx.x; k < 33; k += blockDim.x) out[kNnOffWd + k] = red[kNnLayerSize + k];
+}
+
+// Encoder: dh0 = base + 1/4 sum_j dam_j; dWe = dh0 x^T, dbe = dh0.
+__global__ __launch_bounds__(256) void k_nn_enc_bwd(NnIn A, const float* base_in, const float* dam_in,
+                                                     float* partial) {
+    __shared__ float red[96];
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, wv = threadIdx.x >> 6;
+    const double isr = A.scal[SC_NN_INV_SR], isd = A.scal[SC_NN_INV_SD];
+    float g0[8], g1[8], gb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) g0[j] = g1[j] = gb[j] = 0.f;
+    const int64_t nbg = (A.nc + 63) / 64;
+    for (int64_t bg = blockIdx.x; bg < nbg; bg += gridDim.x) {
+        const int64_t i = bg * 64 + wv * 16 + c;
+        if (i >= A.nc) continue;
+        const int4 nb = A.nbr[i];
+        const int nbs[4] = {nb.x, nb.y, nb.z, nb.w};
+        float acc[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (nbs[k] < 0) continue;
+            const float* q = dam_in + int64_t(nbs[k]) * 32 + 8 * g;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] += q[j];
+        }
+        const float* bq = base_in + i * 32 + 8 * g;
+        const double r = double(A.r32[i]);
+        const float x0 = float(r * isr), x1 = float(A.dinv[i] * r * isd);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float d = bq[j] + 0.25f * acc[j];
+            g0[j] = fmaf(d, x0, g0[j]);
+            g1[j] = fmaf(d, x1, g1[j]);
+            gb[j] += d;
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            g0[j] += __shfl_xor(g0[j], o, 64);
+            g1[j] += __shfl_xor(g1[j], o, 64);
+            gb[j] += __shfl_xor(gb[j], o, 64);
+        }
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w && c == 0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int f = nn_pi(8 * g + j);
+                if (w == 0) {
+                    red[2 * f] = g0[j];
+                    red[2 * f + 1] = g1[j];
+                    red[64 + f] = gb[j];
+                } else {
+                    red[2 * f] += g0[j];
+                    red[2 * f + 1] += g1[j];
+                    red[64 + f] += gb[j];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float* out = partial + int64_t(blockIdx.x) * kNnParams;
+    for (int k = threadIdx.x; k < 96; k += blockDim.x) out[kNnOffWe + k] = red[k];
+}
+
+// ---- loss: res = r - K z, w = K^T res --------------------------------------------
+__device__ inline double row_dot(const Dev& d, const double* __restrict__ vals, const double* __restrict__ x,
+                                 int64_t i) {
+    const int64_t s = i >> 6;
+    const int64_t base = d.k_off[s] + (i & 63);
+    const int w = d.k_w[s];
+    double y = d.k_diag[i] * x[i];
+    for (int k = 0; k < w; ++k) {
+        const int64_t at = base + int64_t(k) * 64;
+        y += vals[at] * x[d.k_col[at]];
+    }
+    return y;
+}
+
+__global__ __launch_bounds__(256) void k_nn_resid(Dev d, const float* r32, const double* z, double* res) {
+    __shared__ double lds[4];
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    double v = 0.0;
+    if (i < d.nc) {
+        const double e = double(r32[i]) - row_dot(d, d.k_val, z, i);
+        res[i] = e;
+        v = e * e;
+    }
+    const double s = block_sum256(v, lds);
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_nn_loss_fin(Dev d, int64_t nparts, double* loss_slot) {
+    __shared__ double lds[16];
+    const double s = reduce_partials_sum(d.partial, nparts, lds);
+    if (threadIdx.x == 0) {
+        const double rr = d.scal[SC_NN_RR];
+        *loss_slot = rr > 0.0 ? s / rr : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_nn_spmv_t(Dev d, const double* kt, const double* x, double* y) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < d.nc) y[i] = row_dot(d, kt, x, i);
+}
+
+// ---- scales of the input ------------------------------------------------------
+template <bool R32>
+__global__ __launch_bounds__(256) void k_nn_scale(Dev d, const double* r64, const float* r32) {
+    __shared__ double lds[4];
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (i < d.nc) {
+        const double r = R32 ? double(r32[i]) : r64[i];
+        const double q = d.k_dinv[i] * r;
+        a = r * r;
+        b = q * q;
+    }
+    const double s0 = block_sum256(a, lds);
+    const double s1 = block_sum256(b, lds);
+    if (threadIdx.x == 0) {
+        d.partial[blockIdx.x] = s0;
+        d.partial[gridDim.x + blockIdx.x] = s1;
+    }
+}
+
+__device__ inline void set_scales(double* sc, double rr, double dd, int64_t n) {
+    const double s_r = sqrt(rr / double(n)), s_d = sqrt(dd / double(n));
+    sc[SC_NN_RR] = rr;
+    sc[SC_NN_DD] = dd;
+    sc[SC_NN_INV_SR] = s_r > 0.0 ? 1.0 / s_r : 0.0;
+    sc[SC_NN_INV_SD] = s_d > 0.0 ? 1.0 / s_d : 0.0;
+    sc[SC_NN_SD] = s_d;
+}
+
+__global__ __launch_bounds__(1024) void k_nn_scale_fin(Dev d, int64_t nparts) {
+    __shared__ double lds[16];
+    const double rr = reduce_partials_sum(d.partial, nparts, lds);
+    const double dd = reduce_partials_sum(d.partial + nparts, nparts, lds);
+    if (threadIdx.x == 0) set_scales(d.scal, rr, dd, d.nc);
+}
+
+// ---- gradient sum over blocks and Adam --------------------------------------------
+__global__ __launch_bounds__(256) void k_nn_adam(NnDev n, int nblocks, int apply, float lr, float c1, float c2,
+                                                  float beta1, float beta2, float eps) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= kNnParams) return;
+    float g = 0.f;
+    for (int b = 0; b < nblocks; ++b) g += n.partial[int64_t(b) * kNnParams + p];
+    n.grad[p] = g;
+    if (!apply) return;
+    const float m = beta1 * n.adam_m[p] + (1.f - beta1) * g;
+    const float v = beta2 * n.adam_v[p] + (1.f - beta2) * g * g;
+    n.adam_m[p] = m;
+    n.adam_v[p] = v;
+    n.params[p] -= lr * (m * c1) / (sqrtf(v) * c2 + eps);
+}
+
+// ---- operand packing from the FP32 master copy ------------------------------------
+__device__ inline __bf16 to_bf(float f) { return __builtin_bit_cast(__bf16, uint16_t(f2bf(f))); }
+
+__global__ __launch_bounds__(256) void k_nn_pack(NnDev n) {
+    const float* p = n.params;
+    NnPack* P = n.pack;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < 32; q += 256) {
+        const int f = nn_pi(q);
+        P->we0[q] = rbf(p[kNnOffWe + 2 * f]);
+        P->we1[q] = rbf(p[kNnOffWe + 2 * f + 1]);
+        P->be[q] = p[kNnOffBe + f];
+        P->wd[q] = p[kNnOffWd + f];
+    }
+    if (tid == 0) P->bd = p[kNnOffBd];
+    for (int l = 0; l < kNnLayers; ++l) {
+        const float* W1 = p + kNnOffLayer + l * kNnLayerSize + kNnW1;   // [32][64]
+        const float* W2 = p + kNnOffLayer + l * kNnLayerSize + kNnW2;   // [32][32]
+        const float* b1 = p + kNnOffLayer + l * kNnLayerSize + kNnB1;
+        const float* b2 = p + kNnOffLayer + l * kNnLayerSize + kNnB2;
+        NnPackLayer& L = P->layer[l];
+        for (int q = tid; q < 32; q += 256) {
+            L.b1[q] = b1[nn_pi(q)];
+            L.b2[q] = b2[nn_pi(q)];
+        }
+        // one thread per (fragment, lane): lane = e % 64, g = lane / 16, row = lane % 16
+        for (int e = tid; e < 12 * 64; e += 256) {
+            const int frag = e >> 6, lane = e & 63, g = lane >> 4, row = lane & 15;
+            bf16x8 v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = nn_pi(8 * g + j);
+                float w;
+                if (frag < 4) {              // w1[t][s]
+                    const int t = frag >> 1, s = frag & 1;
+                    w = W1[(16 * t + row) * 64 + 32 * s + k];
+                } else if (frag < 6) {       // w2[t]
+                    w = W2[(16 * (frag - 4) + row) * 32 + k];
+                } else if (frag < 8) {       // w2t[t]
+                    w = W2[k * 32 + 16 * (frag - 6) + row];
+                } else {                     // w1t[t]
+                    w = W1[k * 64 + 16 * (frag - 8) + row];
+                }
+                v[j] = to_bf(w);
+            }
+            if (frag < 4) L.w1[frag >> 1][frag & 1][lane] = v;
+            else if (frag < 6) L.w2[frag - 4][lane] = v;
+            else if (frag < 8) L.w2t[frag - 6][lane] = v;
+            else L.w1t[frag - 8][lane] = v;
+        }
+    }
+}
+
+// ---- per-state set-up ---------------------------------------------------------------
+// face neighbours from the cell->face table (-1 across a boundary face)
+__global__ __launch_bounds__(256) void k_nn_neighbours(Dev d, int4* nbr) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= d.nc) return;
+    int o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int code = d.c2f[k * d.nc + i];
+        const int f = code >= 0 ? code : ~code;
+        const int other = d.fL[f] == i ? d.fR[f] : d.fL[f];
+        o[k] = other < d.nc ? other : -1;
+    }
+    nbr[i] = make_int4(o[0], o[1], o[2], o[3]);
+}
+
+// values of K^T in K's (symmetric) pattern: entry (i, j) takes K's (j, i);
+// a missing mirror entry sets *flag
+__global__ __launch_bounds__(256) void k_nn_transpose(Dev d, double* kt, int32_t* flag) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= d.nc) return;
+    const int64_t s = i >> 6;
+    const int64_t base = d.k_off[s] + (i & 63);
+    const int w = d.k_w[s], len = d.k_len[i];
+    for (int k = 0; k < w; ++k) {
+        const int64_t at = base + int64_t(k) * 64;
+        double v = 0.0;
+        if (k < len) {
+            const int64_t j = d.k_col[at];
+            const int64_t sj = j >> 6;
+            const int64_t bj = d.k_off[sj] + (j & 63);
+            int lo = 0, hi = d.k_len[j] - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (d.k_col[bj + int64_t(mid) * 64] < i) lo = mid + 1;
+                else hi = mid;
+            }
+            const int64_t atj = bj + int64_t(lo) * 64;
+            if (hi >= 0 && d.k_col[atj] == i) v = d.k_val[atj];
+            else *flag = 1;
+        }
+        kt[at] = v;
+    }
+}
+
+// ---- flexible CG ------------------------------------------------------------------
+// r = b - K x; partial rr, bb, dd
+__global__ __launch_bounds__(256) void k_fcg_setup(Dev d) {
+    __shared__ double lds[4];
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    double a = 0.0, b = 0.0, c = 0.0;
+    if (i < d.nc) {
+        const double bi = d.b[i];
+        const double ri = bi - row_dot(d, d.k_val, d.x, i);
+        d.r[i] = ri;
+        const double q = d.k_dinv[i] * ri;
+        a = ri * ri;
+        b = bi * bi;
+        c = q * q;
+    }
+    const double s0 = block_sum256(a, lds), s1 = block_sum256(b, lds), s2 = block_sum256(c, lds);
+    if (threadIdx.x == 0) {
+        d.partial[blockIdx.x] = s0;
+        d.partial[gridDim.x + blockIdx.x] = s1;
+        d.partial[2 * gridDim.x + blockIdx.x] = s2;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_fcg_setup_fin(Dev d, int64_t nparts, double tol, int maxit, int restart,
+                                                        int fresh) {
+    __shared__ double lds[16];
+    const double rr = reduce_partials_sum(d.partial, nparts, lds);
+    const double bb = reduce_partials_sum(d.partial + nparts, nparts, lds);
+    const double dd = reduce_partials_sum(d.partial + 2 * nparts, nparts, lds);
+    if (threadIdx.x == 0) {
+        double* sc = d.scal;
+        sc[SC_RR] = rr;
+        sc[SC_TRUE_RR] = rr;
+        sc[SC_BB] = bb;
+        if (fresh) {
+            sc[SC_TOL2BB] = tol * tol * bb;
+            sc[SC_MAXIT] = double(maxit);
+            sc[SC_RESTART] = double(restart);
+            sc[SC_IT] = 0.0;
+        }
+        sc[SC_SINCE] = 0.0;
+        sc[SC_DONE] = (rr <= sc[SC_TOL2BB] || bb == 0.0) ? 1.0 : (sc[SC_IT] >= sc[SC_MAXIT] ? 2.0 : 0.0);
+        set_scales(sc, rr, dd, d.nc);
+    }
+}
+
+// after the network: rz = z . r, p = z
+__global__ __launch_bounds__(1024) void k_fcg_rz_fin(Dev d, int64_t nparts) {
+    __shared__ double lds[16];
+    if (d.scal[SC_DONE] != 0.0) return;
+    const double zr = reduce_partials_sum(d.partial, nparts, lds);
+    if (threadIdx.x == 0) d.scal[SC_RZ] = zr;
+}
+
+__global__ __launch_bounds__(256) void k_fcg_p0(Dev d) {
+    if (d.scal[SC_DONE] != 0.0) return;
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < d.nc) d.p[i] = d.z[i];
+}
+
+// x += alpha p; r_old = r; r -= alpha q; partial rr, dd
+__global__ __launch_bounds__(256) void k_fcg_axpy(Dev d, double* r_old) {
+    __shared__ double lds[4];
+    if (d.scal[SC_DONE] != 0.0) return;
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    double a = 0.0, c = 0.0;
+    if (i < d.nc) {
+        const double alpha = d.scal[SC_ALPHA];
+        d.x[i] = d.x[i] + alpha * d.p[i];
+        const double ro = d.r[i];
+        const double ri = ro - alpha * d.q[i];
+        r_old[i] = ro;
+        d.r[i] = ri;
+        const double q = d.k_dinv[i] * ri;
+        a = ri * ri;
+        c = q * q;
+    }
+    const double s0 = block_sum256(a, lds), s1 = block_sum256(c, lds);
+    if (threadIdx.x == 0) {
+        d.partial[blockIdx.x] = s0;
+        d.partial[gridDim.x + blockIdx.x] = s1;
+    }
+}
+
+// count; convergence (1), limit (2) or a scheduled restart (3); input scales
+__global__ __launch_bounds__(1024) void k_fcg_rr_fin(Dev d, int64_t nparts) {
+    __shared__ double lds[16];
+    double* sc = d.scal;
+    if (sc[SC_DONE] != 0.0) return;
+    const double rr = reduce_partials_sum(d.partial, nparts, lds);
+    const double dd = reduce_partials_sum(d.partial + nparts, nparts, lds);
+    if (threadIdx.x == 0) {
+        sc[SC_RR] = rr;
+        sc[SC_IT] = sc[SC_IT] + 1.0;
+        sc[SC_SINCE] = sc[SC_SINCE] + 1.0;
+        if (rr <= sc[SC_TOL2BB]) sc[SC_DONE] = 1.0;
+        else if (sc[SC_IT] >= sc[SC_MAXIT]) sc[SC_DONE] = 2.0;
+        else if (sc[SC_RESTART] > 0.0 && sc[SC_SINCE] >= sc[SC_RESTART]) sc[SC_DONE] = 3.0;
+        set_scales(sc, rr, dd, d.nc);
+    }
+}
+
+// flexible (Polak-Ribiere) beta = z_new . (r_new - r_old) / (z_old . r_old)
+__global__ __launch_bounds__(1024) void k_fcg_beta_fin(Dev d, int64_t nparts) {
+    __shared__ double lds[16];
+    double* sc = d.scal;
+    if (sc[SC_DONE] != 0.0) return;
+    const double zr = reduce_partials_sum(d.partial, nparts, lds);
+    const double zro = reduce_partials_sum(d.partial + nparts, nparts, lds);
+    if (threadIdx.x == 0) {
+        sc[SC_ZR] = zr;
+        sc[SC_ZRO] = zro;
+        sc[SC_BETA] = (zr - zro) / sc[SC_RZ];
+        sc[SC_RZ] = zr;
+    }
+}
+
+// training sample: out = r / s_r (FP32) after r = b - K x and its scales
+__global__ __launch_bounds__(256) void k_nn_sample_out(Dev d, float* out) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < d.nc) out[i] = float(d.r[i] * d.scal[SC_NN_INV_SR]);
+}
+
+__global__ __launch_bounds__(256) void k_fcg_copy(int64_t n, const double* src, double* dst) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+inline unsigned rows256(int64_t n) { return unsigned((n + 255) / 256); }
+
+}  // namespace
+
+// ---- launchers ------------------------------------------------------------------------
+hipError_t launch_nn_pack(const NnDev& n, hipStream_t s) {
+    hipLaunchKernelGGL(k_nn_pack, dim3(1), dim3(256), 0, s, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_nn_neighbours(const Dev& d, const NnStateDev& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_nn_neighbours, dim3(rows256(d.nc)), dim3(256), 0, s, d, a.nbr);
+    return hipGetLastError();
+}
+
+hipError_t launch_nn_transpose(const Dev& d, const NnStateDev& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_nn_transpose, dim3(rows256(d.nc)), dim3(256), 0, s, d, a.kt_val, a.flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_nn_scale(const Dev& d, const double* r64, const float* r32, hipStream_t s) {
+    const unsigned nb = rows256(d.nc);
+    if (r32) hipLaunchKernelGGL(k_nn_scale<true>, dim3(nb), dim3(256), 0, s, d, r64, r32);
+    else hipLaunchKernelGGL(k_nn_scale<false>, dim3(nb), dim3(256), 0, s, d, r64, r32);
+    hipLaunchKernelGGL(k_nn_scale_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb));
+    return hipGetLastError();
+}
+
+static NnIn make_in(const Dev& d, const NnDev& n, const NnStateDev& a, const double* r64, const float* r32) {
+    NnIn in;
+    in.nc = d.nc;
+    in.nbr = a.nbr;
+    in.r64 = r64;
+    in.r32 = r32;
+    in.dinv = d.k_dinv;
+    in.scal = d.scal;
+    in.pack = n.pack;
+    return in;
+}
+
+hipError_t launch_nn_layer(const Dev& d, const NnDev& n, const NnStateDev& a, int layer, const double* r64,
+                           const float* r32, double* z, bool keep_h3, bool fcg, hipStream_t s) {
+    NnFwd F;
+    F.in = make_in(d, n, a, r64, r32);
+    F.layer = layer;
+    F.hin = layer == 0 ? nullptr : (layer == 1 ? a.h1 : a.h2);
+    F.hout = layer == 0 ? a.h1 : (layer == 1 ? a.h2 : a.h3);
+    F.z = z;
+    F.r_old = a.r_old;
+    F.partial = d.partial;
+    const dim3 grid(nn_fwd_grid(d.nc)), block(256);
+    const bool r32in = r32 != nullptr;
+#define NN_L(K, R, C, KP) hipLaunchKernelGGL((k_nn_layer<K, R, C, KP>), grid, block, 0, s, F)
+    if (layer == 0) {
+        if (r32in) NN_L(0, true, false, false);
+        else if (fcg) NN_L(0, false, true, false);
+        else NN_L(0, false, false, false);
+    } else if (layer == 1) {
+        if (r32in) NN_L(1, true, false, false);
+        else if (fcg) NN_L(1, false, true, false);
+        else NN_L(1, false, false, false);
+    } else {
+        if (r32in) {
+            if (keep_h3) NN_L(2, true, false, true);
+            else NN_L(2, true, false, false);
+        } else if (fcg) NN_L(2, false, true, false);
+        else NN_L(2, false, false, false);
+    }
+#undef NN_L
+    return hipGetLastError();
+}
+
+int nn_forward_grid(int64_t nc) { return nn_fwd_grid(nc); }
+
+hipError_t launch_nn_backward(const Dev& d, const NnDev& n, const NnStateDev& a, const float* r32,
+                              double* loss_slot, hipStream_t s) {
+    // res = r - K z (z in d.z, res in d.q), loss; w = K^T res (in d.p)
+    const unsigned nb = rows256(d.nc);
+    hipLaunchKernelGGL(k_nn_resid, dim3(nb), dim3(256), 0, s, d, r32, d.z, d.q);
+    hipLaunchKernelGGL(k_nn_loss_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb), loss_slot);
+    hipLaunchKernelGGL(k_nn_spmv_t, dim3(nb), dim3(256), 0, s, d, a.kt_val, d.q, d.p);
+    NnBwd B;
+    B.in = make_in(d, n, a, nullptr, r32);
+    B.partial = n.partial;
+    B.w = d.p;
+    const dim3 grid(nn_bwd_grid(d.nc)), block(256);
+    // last layer: input h2, output h3 -> base, dam0
+    B.layer = 2; B.hin = a.h2; B.hout = a.h3; B.base_in = nullptr; B.dam_in = nullptr;
+    B.base_out = a.base; B.dam_out = a.dam0;
+    hipLaunchKernelGGL((k_nn_bwd<false, true>), grid, block, 0, s, B);
+    // middle layer: input h1; base in place, dam0 -> dam1
+    B.layer = 1; B.hin = a.h1; B.hout = nullptr; B.base_in = a.base; B.dam_in = a.dam0;
+    B.base_out = a.base; B.dam_out = a.dam1;
+    hipLaunchKernelGGL((k_nn_bwd<false, false>), grid, block, 0, s, B);
+    // first layer: input re-encoded from r; dam1 -> dam0
+    B.layer = 0; B.hin = nullptr; B.base_in = a.base; B.dam_in = a.dam1;
+    B.base_out = a.base; B.dam_out = a.dam0;
+    hipLaunchKernelGGL((k_nn_bwd<true, false>), grid, block, 0, s, B);
+    hipLaunchKernelGGL(k_nn_enc_bwd, grid, block, 0, s, B.in, a.base, a.dam0, n.partial);
+    return hipGetLastError();
+}
+
+int nn_backward_grid(int64_t nc) { return nn_bwd_grid(nc); }
+
+hipError_t launch_nn_adam(const NnDev& n, int nblocks, int apply, float lr, float c1, float c2, float beta1,
+                          float beta2, float eps, hipStream_t s) {
+    hipLaunchKernelGGL(k_nn_adam, dim3((kNnParams + 255) / 256), dim3(256), 0, s, n, nblocks, apply, lr, c1, c2,
+                       beta1, beta2, eps);
+    if (apply) hipLaunchKernelGGL(k_nn_pack, dim3(1), dim3(256), 0, s, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_nn_sample(const Dev& d, float* out, hipStream_t s) {
+    const unsigned nb = rows256(d.nc);
+    hipLaunchKernelGGL(k_fcg_setup, dim3(nb), dim3(256), 0, s, d);      // r = b - K x (partials unused)
+    hipLaunchKernelGGL(k_nn_scale<false>, dim3(nb), dim3(256), 0, s, d, d.r, nullptr);
+    hipLaunchKernelGGL(k_nn_scale_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb));
+    hipLaunchKernelGGL(k_nn_sample_out, dim3(nb), dim3(256), 0, s, d, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fcg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s) {
+    const unsigned nb = rows256(d.nc);
+    hipLaunchKernelGGL(k_fcg_setup, dim3(nb), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_fcg_setup_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb), tol, maxit, restart,
+                       fresh ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fcg_setup_tail(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_rz_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nn_fwd_grid(d.nc)));
+    hipLaunchKernelGGL(k_fcg_p0, dim3(rows256(d.nc)), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_fcg_axpy(const Dev& d, const NnStateDev& a, hipStream_t s) {
+    const unsigned nb = rows256(d.nc);
+    hipLaunchKernelGGL(k_fcg_axpy, dim3(nb), dim3(256), 0, s, d, a.r_old);
+    hipLaunchKernelGGL(k_fcg_rr_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb));
+    return hipGetLastError();
+}
+
+hipError_t launch_fcg_beta(const Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_beta_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nn_fwd_grid(d.nc)));
+    return hipGetLastError();
+}
+
+hipError_t launch_fcg_backup(const Dev& d, const NnStateDev& a, bool restore, hipStream_t s) {
+    if (restore) hipLaunchKernelGGL(k_fcg_copy, dim3(rows256(d.nc)), dim3(256), 0, s, d.nc, a.x_bak, d.x);
+    else hipLaunchKernelGGL(k_fcg_copy, dim3(rows256(d.nc)), dim3(256), 0, s, d.nc, d.x, a.x_bak);
+    return hipGetLastError();
+}
+
+}  // namespace mifvm

@@ -77,7 +77,10 @@ struct FvArrays {
     const R *phi, *minv, *kAC, *kBC, *kRL, *area, *vol, *src, *n_alpha, *fx, *xc, *gdist;
 };
 
-constexpr int kNumKernels = 11;
+constexpr int kNumKernels = 16;
+
+struct NnDev;
+struct NnStateDev;
 
 // Event pairs around kernel launches, resolved into totals at sync points.
 struct KernelTimer {
@@ -113,6 +116,15 @@ struct State {
     double* h_scal = nullptr;             // pinned host mirror of scalars
     int nblk_cells = 0;                   // grid for per-cell reductions
     KernelTimer timer;
+    // attached learned preconditioner (the network is not owned; the
+    // per-state buffers live in a caller workspace)
+    const NnDev* nn = nullptr;
+    const void* nn_handle = nullptr;
+    NnStateDev* nn_state = nullptr;       // owned host record
+    bool kt_ready = false;                // K^T values match K
+    bool b_ready = false;                 // d.b holds a right-hand side
+    hipGraphExec_t fcg_exec = nullptr;    // one chunk of flexible-CG iterations
+    int fcg_exec_chunk = 0;
 };
 
 // workspace layout; returns total bytes (and fills d when base != nullptr)
@@ -157,7 +169,9 @@ hipError_t launch_ir_update(const Dev& d, hipStream_t s);
 // scalar slots in Dev::scal
 enum Scal {
     SC_RZ = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_BB, SC_TOL2BB, SC_DONE, SC_IT, SC_MAXIT,
-    SC_TRUE_RR, SC_CONS, SC_DT_INV, SC_RESTART, SC_SINCE, SC_TOL2BB_OUT, SC_COUNT_ = 32
+    SC_TRUE_RR, SC_CONS, SC_DT_INV, SC_RESTART, SC_SINCE, SC_TOL2BB_OUT,
+    // learned preconditioner: input scales and flexible-CG dot products
+    SC_NN_INV_SR, SC_NN_INV_SD, SC_NN_SD, SC_NN_RR, SC_NN_DD, SC_ZR, SC_ZRO, SC_COUNT_ = 32
 };
 
 }  // namespace mifvm

@@ -1,0 +1,192 @@
+"""Learned preconditioner on the GPU: the network's forward and gradient
+against the FP64 oracle of the same network (rounded to bfloat16 where the
+kernels round), training, the flexible-CG solve with its fallback, and the
+parameter blob."""
+import numpy as np
+import pytest
+
+import synth
+from conftest import cube, cube_geometry
+from oracle import mpnn, poisson
+from oracle.geometry import DIRICHLET
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_2203_00925_amd.binding")
+
+# bf16 activations: a value near a rounding boundary can round the other way
+# when the FP32 pre-activation differs from the FP64 one in its last bits;
+# such flips move the result by about one bf16 ulp (2^-8) locally.
+TOL_FWD = 1e-2
+TOL_GRAD = 2e-2
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def poisson_state(n, seed):
+    m = cube(n, seed)
+    mesh = B.Mesh.from_cube(m)
+    st = B.State(mesh)
+    st.set_bcs(B.VAR_POTENTIAL, [DIRICHLET] * 6)
+    st.poisson_assemble()
+    return m, mesh, st
+
+
+def random_params(seed=11, scale=0.3):
+    """Random weights with every bias and the decoder non-zero, rounded to FP32
+    (the GPU's master copy), as the oracle's FP64 dict."""
+    rng = np.random.default_rng(seed)
+    p = mpnn.init_params(seed, scale)
+    for k in p:
+        if k.startswith("b") or k == "wd":
+            p[k] = rng.normal(0, scale, np.shape(p[k]))
+    flat = mpnn.flatten(p).astype(np.float32)
+    return flat, mpnn.unflatten(flat.astype(np.float64), p)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_forward_matches_oracle():
+    n, seed = 5, 1000                        # 750 cells: 12 block-groups, ragged
+    m, mesh, st = poisson_state(n, seed)
+    g = cube_geometry(n, seed)
+    K, _ = poisson.assemble(g, [DIRICHLET] * 6, [0.0] * 6)
+    dinv = 1.0 / K.diagonal()
+    nbr = mpnn.face_neighbours(g)
+    net = B.Network(seed=3)
+    flat, p = random_params()
+    net.set_params(flat)
+    assert np.array_equal(net.get_params(), flat)
+    net.attach(st)
+    r = np.random.default_rng(5).normal(size=m.nc)
+    z = host(st.nn_apply(dev(r)))
+    zo, _ = mpnn.forward(p, r, dinv, nbr, bf16_like_gpu=True)
+    corr, corr_o = z - dinv * r, zo - dinv * r
+    err = rel(corr, corr_o)
+    print(f"[nn] forward: correction rel err {err:.2e}, |corr|/|z| {np.linalg.norm(corr_o) / np.linalg.norm(zo):.2f}")
+    assert err < TOL_FWD
+    # homogeneity: z(2r) = 2 z(r) up to the same roundings (scales are powers of 2)
+    z2 = host(st.nn_apply(dev(2.0 * r)))
+    assert np.array_equal(z2, 2.0 * z)
+    # decoder at zero: exactly Jacobi
+    flat0 = flat.copy()
+    flat0[mpnn.flatten(p).size - 33:] = 0.0
+    net.set_params(flat0)
+    zj = host(st.nn_apply(dev(r)))
+    assert rel(zj, dinv * r) < 1e-12
+
+
+def test_gradient_matches_oracle():
+    n, seed = 5, 1001
+    m, mesh, st = poisson_state(n, seed)
+    g = cube_geometry(n, seed)
+    K, _ = poisson.assemble(g, [DIRICHLET] * 6, [0.0] * 6)
+    dinv = 1.0 / K.diagonal()
+    nbr = mpnn.face_neighbours(g)
+    net = B.Network(seed=4)
+    flat, p = random_params(seed=12)
+    net.set_params(flat)
+    net.attach(st, training=True)
+    r32 = np.random.default_rng(6).normal(size=m.nc).astype(np.float32)
+    perm = mesh.export("cell_perm")               # internal -> user
+    loss, grad = st.nn_loss_grad(dev(r32[perm], torch.float32))
+    Lo, go = mpnn.loss_and_grad(p, K, r32.astype(np.float64), dinv, nbr, bf16_like_gpu=True)
+    go = mpnn.flatten(go)
+    print(f"[nn] loss gpu {loss:.6f} oracle {Lo:.6f}; grad rel err {rel(grad, go):.2e}")
+    assert abs(loss - Lo) <= TOL_FWD * Lo
+    assert rel(grad, go) < TOL_GRAD
+    # every parameter block on its own
+    at = 0
+    for k in mpnn.PARAM_ORDER:
+        size = np.size(p[k])
+        e = rel(grad[at:at + size], go[at:at + size])
+        assert e < 5 * TOL_GRAD, (k, e)
+        at += size
+
+
+def make_samples(st, m, rng, count, segs=(0, 3, 8, 20, 50, 120)):
+    """Residual samples along restarted Jacobi-CG runs of Gaussian right-hand
+    sides."""
+    out = []
+    while len(out) < count:
+        c = rng.uniform(0.25, 0.75, 3)
+        f = synth.gaussian_field(m, c, rng.uniform(0.05, 0.25))
+        st.set_field(B.FIELD_P, dev(np.zeros(m.nc)))
+        for k in segs:
+            if k > 0:
+                st.poisson_solve(dev(f), tol=1e-14, maxit=k, restart=0, allow_not_converged=True)
+            else:
+                st.poisson_rhs(dev(f))
+            s, rms = st.nn_sample()
+            if rms > 0:
+                out.append(s)
+            if len(out) == count:
+                break
+    return out
+
+
+def test_train_learned_solve_fallback_and_blob():
+    rng = np.random.default_rng(21)
+    m_tr, _, st_tr = poisson_state(12, 2000)
+    net = B.Network(seed=7)
+    net.attach(st_tr, training=True)
+    samples = make_samples(st_tr, m_tr, rng, 60)
+    res = net.train([st_tr], samples, [0] * len(samples), epochs=4, lr=3e-3, lr_min=3e-4, seed=1)
+    print(f"[nn] train: {res['steps']} steps, epoch losses {np.round(res['epoch_loss'], 4)}, {res['ms']:.0f} ms")
+    assert res["steps"] == 4 * len(samples)
+    assert res["loss_last"] < res["loss_first"]
+    # an unseen mesh: learned flexible CG against plain Jacobi-CG
+    n, seed = 10, 2001
+    m, mesh, st = poisson_state(n, seed)
+    net.attach(st)
+    f = synth.gaussian_field(m)
+    st.set_field(B.FIELD_P, dev(np.zeros(m.nc)))
+    plain = st.poisson_solve(dev(f), tol=1e-10)
+    st.set_field(B.FIELD_P, dev(np.zeros(m.nc)))
+    lrn = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_LEARNED)
+    print(f"[nn] n={n}: Jacobi-CG {plain['iterations']} it, learned FCG {lrn['iterations']} it "
+          f"({lrn['learned_iterations']} flexible), rel {lrn['rel_residual']:.2e}")
+    assert lrn["status"] == B.OK and lrn["fell_back"] == 0
+    g = cube_geometry(n, seed)
+    K, c = poisson.assemble(g, [DIRICHLET] * 6, [0.0] * 6)
+    b = poisson.rhs(g, f, c)
+    x = host(st.get_field(B.FIELD_P))
+    assert poisson.true_relative_residual(K, b, x) <= 1.01e-10
+    # forced fallback after 5 flexible iterations: the plain solver finishes
+    st.set_field(B.FIELD_P, dev(np.zeros(m.nc)))
+    fb = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_LEARNED, learned_maxit=5,
+                          allow_fell_back=True)
+    assert fb["status"] == B.FELL_BACK and fb["fell_back"] == 1 and fb["learned_iterations"] == 5
+    x = host(st.get_field(B.FIELD_P))
+    assert poisson.true_relative_residual(K, b, x) <= 1.01e-10
+    # parameter blob round trip; a corrupt or non-finite blob is refused
+    blob = net.save()
+    other = B.Network(seed=99)
+    other.load(blob)
+    assert np.array_equal(other.get_params(), net.get_params())
+    with pytest.raises(B.MifvmError) as e:
+        other.load(b"XXXXXXXX" + blob[8:])
+    assert e.value.code == -1
+    bad = np.frombuffer(blob[16:], np.float32).copy()
+    bad[100] = np.nan
+    with pytest.raises(B.MifvmError):
+        other.load(blob[:16] + bad.tobytes())
+    with pytest.raises(B.MifvmError):
+        other.set_params(bad)
+    assert np.array_equal(other.get_params(), net.get_params())

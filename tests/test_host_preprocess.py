@@ -124,9 +124,13 @@ def test_mesh_errors():
 
 
 def test_library_exports_every_declared_symbol():
-    hdr = open(os.path.join(ROOT, "include", "mifvm.h")).read()
-    names = re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(mifvm_\w+)\s*\(", hdr, re.M)
-    assert len(names) >= 20
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            hdr = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(mifvm_\w+)\s*\(", hdr, re.M)
+    assert len(names) >= 35
+    assert "mifvm_nn_train" in names and "mifvm_poisson_solve" in names
     lib = C.CDLL(B._LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
