@@ -274,6 +274,8 @@ def main():
         del st
         torch.cuda.empty_cache()
         result["forms"] = {"fp32_refined": run_fp32_form(args, M, pf, u64, p64)}
+        torch.cuda.empty_cache()
+        result["forms"]["learned"] = run_learned_form(args, M, pf, iters, solve_ms)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
@@ -328,6 +330,135 @@ def run_fp32_form(args, M, pf, u64, p64):
             "u_max_rel_err_vs_fp64": uerr, "P_rel_err_vs_fp64": perr,
             "dtype": "f32 step; f32 inner CG with f64 residual, dots and refinement"}
 
+
+
+# Learned-preconditioner form: training data from config-1-style runs on
+# meshes of 1.05M-1.97M cells (unseen by the test), 2,000 samples.
+LEARNED = dict(train_n=(56, 60, 64, 69), train_seed0=7000, samples=2000, epochs=4, lr=3e-3,
+               lr_min=3e-4, snapshots=(0, 1, 2, 4, 8, 16, 32, 64, 128, 256), data_seed=77)
+
+
+def learned_training_data(B, net, log_prefix="learned"):
+    """Samples of true residuals along the plain solver's runs: per right-hand
+    side, a Gaussian pulse (random centre in [0.3, 0.7]^3, sigma in [0.05,
+    0.2]) advanced 0-10 RK3 steps in the rotating flow, then restarted
+    Jacobi-CG from P = 0 with a sample at each snapshot iteration."""
+    import numpy as np
+    import torch
+    import synth
+    rng = np.random.default_rng(LEARNED["data_seed"])
+    states, samples, owner = [], [], []
+    per = LEARNED["samples"] // len(LEARNED["train_n"])
+    for k, n in enumerate(LEARNED["train_n"]):
+        m = synth.jittered_cube(n, LEARNED["train_seed0"] + k)
+        pf = synth.problem_fields(m)
+        st = B.State(B.Mesh.from_cube(m), diffusivity=pf.diffusivity)
+        st.set_bcs(B.VAR_SCALAR, [B.ZERO_FLUX] * 6)
+        st.set_bcs(B.VAR_POTENTIAL, [B.DIRICHLET] * 6)
+        st.set_field(B.FIELD_VEL, torch.from_numpy(np.ascontiguousarray(pf.vel.T.ravel())))
+        st.poisson_assemble()
+        net.attach(st, training=True)
+        dt = st.cfl_dt(pf.cfl)
+        zero = torch.zeros(m.nc, dtype=torch.float64, device="cuda")
+        got = 0
+        while got < per:
+            c = rng.uniform(0.3, 0.7, 3)
+            st.set_field(B.FIELD_U, torch.from_numpy(synth.gaussian_field(m, c, rng.uniform(0.05, 0.2))))
+            st.step(int(rng.integers(0, 11)), dt)
+            st.set_field(B.FIELD_P, zero)
+            done = 0
+            for it in LEARNED["snapshots"]:
+                if it > done:
+                    st.poisson_solve(None, tol=1e-14, maxit=it - done, restart=0, allow_not_converged=True)
+                    done = it
+                else:
+                    st.poisson_rhs(None)
+                smp, rms = st.nn_sample()
+                if rms > 0:
+                    samples.append(smp)
+                    owner.append(k)
+                    got += 1
+                if got >= per:
+                    break
+        states.append(st)
+        log(f"{log_prefix}: training mesh n={n} ({m.nc} cells): {got} samples")
+    return states, samples, owner
+
+
+def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
+    """The learned preconditioner: generate the training data with the
+    library's own solver on smaller unseen meshes, train the network with the
+    library's kernels, then run the same steps as the FP64 run with the
+    flexible-CG solve; plus one cold solve (P = 0) with each method."""
+    import numpy as np
+    import torch
+    from paper_2203_00925_amd import binding as B
+    net = B.Network(seed=1)
+    t0 = time.perf_counter()
+    tstates, samples, owner = learned_training_data(B, net)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    tr = net.train(tstates, samples, owner, epochs=LEARNED["epochs"], lr=LEARNED["lr"],
+                   lr_min=LEARNED["lr_min"], seed=3, loss=B.LOSS_RESIDUAL)
+    log(f"learned: {len(samples)} samples in {t_data:.1f}s; trained {tr['steps']} steps in "
+        f"{tr['ms'] / 1e3:.1f}s; epoch losses {np.round(tr['epoch_loss'], 4).tolist()}")
+    del samples, tstates
+    torch.cuda.empty_cache()
+    st = B.State(M, diffusivity=pf.diffusivity)
+    st.set_bcs(B.VAR_SCALAR, [B.ZERO_FLUX] * 6)
+    st.set_bcs(B.VAR_POTENTIAL, [B.DIRICHLET] * 6)
+    st.set_field(B.FIELD_VEL, torch.from_numpy(np.ascontiguousarray(pf.vel.T.ravel())))
+    st.set_field(B.FIELD_U, torch.from_numpy(pf.u0))
+    st.poisson_assemble()
+    net.attach(st)
+    dt = st.cfl_dt(pf.cfl)
+    kw = dict(tol=1e-10, restart=500, method=B.SOLVE_LEARNED, allow_fell_back=True)
+    # cold solves of the initial right-hand side, both methods
+    zero = torch.zeros(M.info.nc, dtype=torch.float64, device="cuda")
+    st.set_field(B.FIELD_P, zero)
+    cold_plain = st.poisson_solve(None, tol=1e-10, restart=500)
+    st.set_field(B.FIELD_P, zero)
+    cold = st.poisson_solve(None, **kw)
+    log(f"learned: cold solve {cold['iterations']} it {cold['ms']:.0f} ms vs Jacobi-CG "
+        f"{cold_plain['iterations']} it {cold_plain['ms']:.0f} ms")
+    st.set_field(B.FIELD_P, zero)
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        st.step(1, dt)
+        st.poisson_solve(None, **kw)
+    torch.cuda.synchronize()
+    st.kernel_timing(True)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    solves = []
+    for k in range(args.steps):
+        st.step(1, dt)
+        ev[k][0].record(stream)
+        solves.append(st.poisson_solve(None, **kw))
+        ev[k][1].record(stream)
+        log(f"learned step {k}: {solves[-1]['iterations']} it, rel {solves[-1]['rel_residual']:.2e}, "
+            f"fell back {solves[-1]['fell_back']}")
+    torch.cuda.synchronize()
+    kstats = st.kernel_stats()
+    st.kernel_timing(False)
+    solve_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    plain_ms = sum(plain_solve_ms) / len(plain_solve_ms)
+    layer_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in kstats.items()
+                if k.startswith("nn_") or k in ("cg_spmv", "fcg_vec")}
+    del st
+    return {"poisson_solve_ms": solve_ms,
+            "poisson_iterations": [s["iterations"] for s in solves],
+            "poisson_rel_residual": max(s["rel_residual"] for s in solves),
+            "fell_back": [s["fell_back"] for s in solves],
+            "speedup_vs_jacobi_cg": plain_ms / solve_ms,
+            "jacobi_cg_iterations": plain_iters, "jacobi_cg_solve_ms": plain_ms,
+            "cold": {"learned_iterations": cold["iterations"], "learned_ms": cold["ms"],
+                     "jacobi_cg_iterations": cold_plain["iterations"], "jacobi_cg_ms": cold_plain["ms"]},
+            "kernel_avg_ms": layer_ms,
+            "training": {"meshes_n": list(LEARNED["train_n"]), "samples": LEARNED["samples"],
+                         "epochs": LEARNED["epochs"], "loss": "residual",
+                         "epoch_loss": [round(float(x), 5) for x in tr["epoch_loss"]],
+                         "data_s": t_data, "train_s": tr["ms"] / 1e3},
+            "dtype": "bf16 network (fp32 accumulation), f64 flexible CG"}
 
 
 def run_batch(args):

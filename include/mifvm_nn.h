@@ -18,12 +18,17 @@
  * with FP32 accumulation; z is FP64.  mifvm_poisson_solve with method
  * MIFVM_SOLVE_LEARNED runs flexible CG with z as the preconditioner.
  *
- * Training minimises, per sample r, L = ||r - K z(r)||^2 / ||r||^2 with
- * Adam (one sample per step).  The samples are true residuals b - K x_k of
- * iterates x_k of the library's own solver (mifvm_nn_sample), i.e. r = K e
- * with e = x* - x_k the iterate's error, so L = ||K (e - z)||^2 / ||K e||^2.
- * The gradient is the chain rule of the rounded forward with each rounding
- * taken as the identity.
+ * Training minimises one of two losses per sample r with Adam (one sample
+ * per step):
+ *   RESIDUAL  L = ||r - K z||^2 / ||r||^2
+ *   ENERGY    L = (z^T K z - 2 z^T r) / (r^T D^-1 r)
+ * The energy functional is ||z - e||^2 in the norm of K_s = (K + K^T)/2,
+ * e = K_s^-1 r, minus a constant: the norm conjugate gradients minimise; the
+ * residual loss weights the error by K^2.  Both need K^T, whose values the
+ * library builds in K's (symmetric) pattern.  The samples are true residuals
+ * b - K x_k of iterates of the library's own solver (mifvm_nn_sample), i.e.
+ * r = K e_k with e_k = x* - x_k.  The gradient is the chain rule of the
+ * rounded forward with each rounding taken as the identity.
  *
  * Parameter order (FP32, as get/set/save): We[32][2], be[32], then for each
  * of the 3 layers W1[32][64] (columns: h then m), b1[32], W2[32][32],
@@ -43,6 +48,8 @@ extern "C" {
 #endif
 
 #define MIFVM_NN_PARAMS 9537
+
+enum mifvm_nn_loss { MIFVM_NN_LOSS_RESIDUAL = 0, MIFVM_NN_LOSS_ENERGY = 1 };
 
 typedef struct mifvm_nn mifvm_nn;
 
@@ -93,11 +100,12 @@ int mifvm_nn_sample(mifvm_state* st, float* d_out, double* rms, void* stream);
 /* Loss L of one sample (internal order, as from mifvm_nn_sample) and its
  * gradient (host, MIFVM_NN_PARAMS floats, parameter order), without an
  * update.  Needs a training attachment.  Synchronises.                    */
-int mifvm_nn_loss_grad(mifvm_state* st, const float* d_sample, double* loss, float* grad, void* stream);
+int mifvm_nn_loss_grad(mifvm_state* st, const float* d_sample, int32_t loss_kind, double* loss, float* grad,
+                       void* stream);
 
 typedef struct {
     int32_t epochs;
-    int32_t pad_;
+    int32_t loss;              /* enum mifvm_nn_loss                          */
     uint64_t seed;             /* order of the samples in each epoch          */
     double lr;                 /* Adam step, cosine-decayed to lr_min         */
     double lr_min;

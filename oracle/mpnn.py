@@ -15,14 +15,23 @@ no neighbour):
         h_i <- h_i + W2_l u_i + b2_l
     y_i   = wd . h3_i + bd
 
-z is 1-homogeneous in r (s_r, s_d scale with r).  Training minimises the
-relative residual of the preconditioned residual,
-    L = || r - K z(r) ||^2 / || r ||^2,
-whose gradient needs dL/dz = -2 K^T (r - K z) / ||r||^2.
+z is 1-homogeneous in r (s_r, s_d scale with r).  Two training losses:
+
+  residual:  L = || r - K z(r) ||^2 / || r ||^2,
+             dL/dz = -2 K^T (r - K z) / ||r||^2;
+  energy:    L = (z^T K z - 2 z^T r) / (r^T D^-1 r),
+             dL/dz = 2 (K_s z - r) / (r^T D^-1 r),   K_s = (K + K^T) / 2.
+
+The energy functional is minimised by z = K_s^-1 r and equals
+||z - K_s^-1 r||^2_{K_s} minus a constant, the norm conjugate gradients
+minimise; it needs no solution vector.  The residual loss weights the error
+by K^2, i.e. toward the rough end of the spectrum.
 
 ``forward(..., bf16_like_gpu=True)`` rounds to bfloat16 exactly where the GPU
-kernels store or feed a matrix core (weights, h after every layer, m and u as
-MFMA inputs).  ``backward`` is the chain rule of the forward it is given:
+kernels store or feed a matrix core: the weights, h after the encoder and
+after every layer, and u.  The neighbour mean m is not rounded: the kernels
+form it inside the matrix-core product (each neighbour row times W1's m-half
+scaled by 1/4, FP32 accumulation), so it never exists as a bf16 value.  ``backward`` is the chain rule of the forward it is given:
 exact for the FP64 forward (pinned by finite differences in the tests); for
 the rounded forward it treats each rounding as the identity (straight-through)
 and so multiplies by the rounded weights, the ones that forward used.
@@ -109,7 +118,7 @@ def forward(p, r, dinv, nbr, bf16_like_gpu=False):
     cache = {"x": x, "h": [h], "a": [], "v": [], "u": [], "s_d": s_d, "s_r": s_r,
              "bf16": bool(bf16_like_gpu)}
     for l in range(LAYERS):
-        m = q(_neigh_mean(h, nbr))
+        m = _neigh_mean(h, nbr)
         a = np.concatenate([h, m], axis=1)
         v = a @ q(p[f"W1_{l}"]).T + p[f"b1_{l}"]
         u = q(np.maximum(v, 0.0))
@@ -147,14 +156,22 @@ def backward(p, cache, nbr, dz):
     return g
 
 
-def loss_and_grad(p, K, r, dinv, nbr, bf16_like_gpu=False):
-    """L = ||r - K z||^2 / ||r||^2 and its parameter gradient (FP64
-    arithmetic; with bf16_like_gpu the forward rounds as the GPU does)."""
+def loss_and_grad(p, K, r, dinv, nbr, bf16_like_gpu=False, kind="residual"):
+    """Loss of one sample r and its parameter gradient (FP64 arithmetic; with
+    bf16_like_gpu the forward rounds as the GPU does)."""
     z, cache = forward(p, r, dinv, nbr, bf16_like_gpu)
-    res = r - K @ z
-    rr = np.dot(r, r)
-    L = np.dot(res, res) / rr
-    dz = -2.0 * (K.T @ res) / rr
+    if kind == "residual":
+        res = r - K @ z
+        rr = np.dot(r, r)
+        L = np.dot(res, res) / rr
+        dz = -2.0 * (K.T @ res) / rr
+    elif kind == "energy":
+        rdr = np.dot(r, dinv * r)
+        kz, ktz = K @ z, K.T @ z
+        L = (np.dot(z, kz) - 2.0 * np.dot(z, r)) / rdr
+        dz = (kz + ktz - 2.0 * r) / rdr
+    else:
+        raise ValueError(kind)
     return L, backward(p, cache, nbr, dz)
 
 

@@ -27,6 +27,7 @@ KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "
            "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble", "nn_layer1", "nn_layer2", "nn_layer3",
            "fcg_vec", "nn_train")
 NN_PARAMS = 9537
+LOSS_RESIDUAL, LOSS_ENERGY = 0, 1
 
 EXPORTS = {  # id: (name, dtype, shape-fn(info))
     0: ("cell_perm", np.int32, lambda i: (i.nc,)),
@@ -102,7 +103,7 @@ class _NnOpts(C.Structure):
 
 
 class _TrainOpts(C.Structure):
-    _fields_ = [("epochs", C.c_int32), ("pad_", C.c_int32), ("seed", C.c_uint64),
+    _fields_ = [("epochs", C.c_int32), ("loss", C.c_int32), ("seed", C.c_uint64),
                 ("lr", C.c_double), ("lr_min", C.c_double), ("beta1", C.c_double),
                 ("beta2", C.c_double), ("eps", C.c_double)]
 
@@ -156,7 +157,7 @@ def _load():
         "mifvm_nn_attach": (C.c_int, [P, P, I32, P, SZ, P]),
         "mifvm_nn_apply": (C.c_int, [P, P, P, P]),
         "mifvm_nn_sample": (C.c_int, [P, P, C.POINTER(D), P]),
-        "mifvm_nn_loss_grad": (C.c_int, [P, P, C.POINTER(D), P, P]),
+        "mifvm_nn_loss_grad": (C.c_int, [P, P, I32, C.POINTER(D), P, P]),
         "mifvm_nn_train": (C.c_int, [P, P, I32, P, P, I32, C.POINTER(_TrainOpts),
                                      C.POINTER(_TrainInfo), P, P]),
     }
@@ -417,7 +418,8 @@ class Network:
         h = getattr(self, "_h", None)
         if h and _lib is not None:
             for st in getattr(self, "_attached", []):
-                if st._h:
+                # only states still attached to this network
+                if st._h and getattr(st, "_nn", None) is self:
                     _lib.mifvm_nn_attach(st._h, None, 0, None, 0, None)
             _lib.mifvm_nn_destroy(h)
             self._h = None
@@ -457,13 +459,13 @@ class Network:
         self._attached.append(state)
 
     def train(self, states, samples, state_of_sample, epochs=1, lr=1e-3, lr_min=1e-4, seed=0,
-              beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+              beta1=0.9, beta2=0.999, eps=1e-8, loss=LOSS_RESIDUAL, stream=None):
         """samples: list of FP32 device tensors from State.nn_sample."""
         states = list(states)
         hs = (C.c_void_p * len(states))(*[s._h for s in states])
         ptrs = (C.c_void_p * len(samples))(*[t.data_ptr() for t in samples])
         sos = np.ascontiguousarray(state_of_sample, np.int32)
-        opts = _TrainOpts(int(epochs), 0, int(seed), float(lr), float(lr_min), float(beta1),
+        opts = _TrainOpts(int(epochs), int(loss), int(seed), float(lr), float(lr_min), float(beta1),
                           float(beta2), float(eps))
         info = _TrainInfo()
         ep = np.zeros(int(epochs), np.float64)
@@ -492,11 +494,11 @@ def _state_nn_sample(self, out=None, stream=None):
     return out, rms.value
 
 
-def _state_nn_loss_grad(self, sample, stream=None):
+def _state_nn_loss_grad(self, sample, loss_kind=LOSS_RESIDUAL, stream=None):
     loss = C.c_double()
     grad = np.empty(NN_PARAMS, np.float32)
-    _check(_lib.mifvm_nn_loss_grad(self._h, _ptr(sample), C.byref(loss), grad.ctypes.data,
-                                   _stream(stream)))
+    _check(_lib.mifvm_nn_loss_grad(self._h, _ptr(sample), int(loss_kind), C.byref(loss),
+                                   grad.ctypes.data, _stream(stream)))
     return loss.value, grad
 
 

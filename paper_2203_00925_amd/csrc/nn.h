@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "state.h"
 
@@ -104,9 +105,10 @@ hipError_t launch_nn_layer(const Dev& d, const NnDev& n, const NnStateDev& a, in
                            const float* r32, double* z, bool keep_h3, bool fcg, hipStream_t s);
 int nn_forward_grid(int64_t nc);
 int nn_backward_grid(int64_t nc);
-// training, after the forward on r32 (z in d.z): res = r - K z, the step's
-// loss into *loss_slot, w = K^T res, the backward and per-block gradients
-hipError_t launch_nn_backward(const Dev& d, const NnDev& n, const NnStateDev& a, const float* r32,
+// training, after the forward on r32 (z in d.z): the loss (kind 0 residual,
+// 1 energy) into *loss_slot, its gradient w.r.t. z, the backward and the
+// per-block parameter gradients
+hipError_t launch_nn_backward(const Dev& d, const NnDev& n, const NnStateDev& a, const float* r32, int kind,
                               double* loss_slot, hipStream_t s);
 // gradient = sum of the per-block sums (nblocks); apply: one Adam update
 // (c1 = 1/(1-beta1^t), c2 = 1/sqrt(1-beta2^t)) and a repack of the operands

@@ -115,6 +115,7 @@ int ensure_transpose(State& s, hipStream_t hs) {
 }
 
 struct AdamCfg {
+    int loss;
     bool apply;
     float lr, c1, c2, beta1, beta2, eps;
 };
@@ -126,7 +127,7 @@ hipError_t train_step(State& s, const NnDev& n, const float* r32, double* loss_s
     const NnStateDev& a = *s.nn_state;
     hipError_t e = launch_nn_scale(d, nullptr, r32, hs);
     for (int l = 0; e == hipSuccess && l < kNnLayers; ++l) e = launch_nn_layer(d, n, a, l, nullptr, r32, d.z, true, false, hs);
-    if (e == hipSuccess) e = launch_nn_backward(d, n, a, r32, loss_slot, hs);
+    if (e == hipSuccess) e = launch_nn_backward(d, n, a, r32, c.loss, loss_slot, hs);
     if (e == hipSuccess)
         e = launch_nn_adam(n, nn_backward_grid(d.nc), c.apply ? 1 : 0, c.lr, c.c1, c.c2, c.beta1, c.beta2, c.eps, hs);
     return e;
@@ -351,7 +352,7 @@ int mifvm_nn_attach(mifvm_state* st, mifvm_nn* nn, int32_t training, void* d_ws,
     const hipError_t e = launch_nn_neighbours(s.d, *a, S(stream));
     if (e != hipSuccess) {
         delete a;
-        return hip_fail(e, "launch_nn_neighbours");
+        return hip_fail(e, "attach");
     }
     delete s.nn_state;
     s.nn_state = a;
@@ -393,15 +394,17 @@ int mifvm_nn_sample(mifvm_state* st, float* d_out, double* rms, void* stream) {
     return MIFVM_OK;
 }
 
-int mifvm_nn_loss_grad(mifvm_state* st, const float* d_sample, double* loss, float* grad, void* stream) {
+int mifvm_nn_loss_grad(mifvm_state* st, const float* d_sample, int32_t loss_kind, double* loss, float* grad,
+                       void* stream) {
     if (!st || !d_sample || !loss || !grad) return fail(MIFVM_E_ARG, "null argument");
+    if (loss_kind != MIFVM_NN_LOSS_RESIDUAL && loss_kind != MIFVM_NN_LOSS_ENERGY) return fail(MIFVM_E_ARG, "unknown loss");
     State& s = st->s;
     int rc = need_attached(s, true);
     if (rc) return rc;
     hipStream_t hs = S(stream);
     if ((rc = ensure_transpose(s, hs))) return rc;
     const NnDev& n = *s.nn;
-    const AdamCfg none{false, 0.f, 1.f, 1.f, 0.9f, 0.999f, 1e-8f};
+    const AdamCfg none{loss_kind, false, 0.f, 1.f, 1.f, 0.9f, 0.999f, 1e-8f};
     HIPCHK(train_step(s, n, d_sample, n.loss, none, hs));
     HIPCHK(hipMemcpyAsync(loss, n.loss, sizeof(double), hipMemcpyDeviceToHost, hs));
     HIPCHK(hipMemcpyAsync(grad, n.grad, kNnParams * sizeof(float), hipMemcpyDeviceToHost, hs));
@@ -419,6 +422,7 @@ int mifvm_nn_train(mifvm_nn* nn, mifvm_state* const* states, int32_t n_states, c
     const float beta2 = opts->beta2 > 0 ? float(opts->beta2) : 0.999f;
     const float eps = opts->eps > 0 ? float(opts->eps) : 1e-8f;
     if (!(beta1 < 1.f) || !(beta2 < 1.f)) return fail(MIFVM_E_ARG, "beta1, beta2 must be < 1");
+    if (opts->loss != MIFVM_NN_LOSS_RESIDUAL && opts->loss != MIFVM_NN_LOSS_ENERGY) return fail(MIFVM_E_ARG, "unknown loss");
     hipStream_t hs = S(stream);
     for (int k = 0; k < n_states; ++k) {
         if (!states[k]) return fail(MIFVM_E_ARG, "null state");
@@ -453,7 +457,7 @@ int mifvm_nn_train(mifvm_nn* nn, mifvm_state* const* states, int32_t n_states, c
                 const float lr = float(opts->lr_min + 0.5 * (opts->lr - opts->lr_min) * (1.0 + std::cos(3.14159265358979323846 * frac)));
                 ++nn->adam_steps;
                 const double t = double(nn->adam_steps);
-                const AdamCfg c{true, lr, float(1.0 / (1.0 - std::pow(double(beta1), t))),
+                const AdamCfg c{opts->loss, true, lr, float(1.0 / (1.0 - std::pow(double(beta1), t))),
                                 float(1.0 / std::sqrt(1.0 - std::pow(double(beta2), t))), beta1, beta2, eps};
                 HIPCHK(timed(s.timer, MIFVM_K_NN_TRAIN, hs,
                              [&] { return train_step(s, n, d_samples[idx], n.loss + (k - k0), c, hs); }));

@@ -22,7 +22,7 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kFwdGridMax = 2048;
+constexpr int kFwdGridMax = 768;        // 3 blocks of 4 waves on each of 256 CUs (resident at once)
 
 inline int nn_fwd_grid(int64_t nc) {
     const int64_t g = (nc + 63) / 64;
@@ -63,16 +63,37 @@ __device__ inline f32x4 mfma16(i16x4 a, i16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// float pair -> packed bf16 pair (round to nearest even; one v_cvt_pk_bf16_f32)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ inline uint32_t cvt2(float a, float b) {
+    const f32x2 x = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2));
+}
+__device__ inline u32x4 cvt8(const float* f) {
+    u32x4 v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = cvt2(f[2 * k], f[2 * k + 1]);
+    return v;
+}
+
 // hi + lo split of FP32 values into two bf16 operands (about 16 mantissa bits)
 __device__ inline void split8(const float* f, u32x4& hi, u32x4& lo) {
+    hi = cvt8(f);
     float h[8], l[8];
+    unpack8(hi, h);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        h[j] = rbf(f[j]);
-        l[j] = f[j] - h[j];
-    }
-    hi = pack8(h);
-    lo = pack8(l);
+    for (int j = 0; j < 8; ++j) l[j] = f[j] - h[j];
+    lo = cvt8(l);
+}
+
+// Contiguous range of 64-cell block-groups of this block: consecutive cells
+// stay on one XCD, whose L2 then serves the neighbour rows they share.
+__device__ inline void block_range(int64_t nbg, int64_t& b0, int64_t& b1) {
+    const int64_t per = (nbg + gridDim.x - 1) / gridDim.x;
+    b0 = int64_t(blockIdx.x) * per;
+    if (b0 > nbg) b0 = nbg;
+    b1 = b0 + per < nbg ? b0 + per : nbg;
 }
 
 struct NnIn {
@@ -85,53 +106,28 @@ struct NnIn {
     const NnPack* pack;
 };
 
-// h0 of cell e (bf16-rounded), slots 8g..8g+7
-template <bool R32>
-__device__ inline void encode(const NnIn& A, int64_t e, const float* we0, const float* we1, const float* be,
-                              double isr, double isd, float* h) {
-    const double r = R32 ? double(A.r32[e]) : A.r64[e];
-    const float x0 = float(r * isr);
-    const float x1 = float(A.dinv[e] * r * isd);
+// h0 = We x + be of one cell (slots 8g..8g+7), rounded and packed
+__device__ inline u32x4 encode(double r, double dv, const float* we0, const float* we1, const float* be,
+                               double isr, double isd) {
+    const float x0 = float(r * isr), x1 = float(dv * r * isd);
+    float h[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) h[j] = rbf(fmaf(we0[j], x0, fmaf(we1[j], x1, be[j])));
+    for (int j = 0; j < 8; ++j) h[j] = fmaf(we0[j], x0, fmaf(we1[j], x1, be[j]));
+    return cvt8(h);
 }
 
-// [h; m] of cell i for one layer: own row slots and the rounded neighbour mean
-template <bool FIRST, bool R32>
-__device__ inline void layer_input(const NnIn& A, const u32x4* hin, int64_t i, bool valid, int4 nb, int g,
-                                   const float* we0, const float* we1, const float* be, double isr, double isd,
-                                   float* hown, float* m) {
-    float acc[8];
+// v = W1 [h; m] with m = 1/4 sum of the neighbour rows: the neighbour rows
+// are further K-chunks of the product against W1's m-half scaled by 1/4
+// (w1[t][1]), so m is summed in the FP32 accumulator and never rounded.
+// Absent neighbours are zero rows.  Forward and backward use this one
+// sequence, so the recomputed v is bitwise the forward's.
+__device__ inline void w1_product(const bf16x8 (&w1)[2][2], u32x4 bh, const u32x4 (&bn)[4], f32x4 (&v)[2]) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] = 0.f;
-    const int nbs[4] = {nb.x, nb.y, nb.z, nb.w};
-    if (FIRST) {
-        if (valid) encode<R32>(A, i, we0, we1, be, isr, isd, hown);
-        else
+    for (int t = 0; t < 2; ++t) {
+        v[t] = mfma32(w1[t][0], as_bf(bh), f32x4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-            for (int j = 0; j < 8; ++j) hown[j] = 0.f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (nbs[k] < 0) continue;
-            float t[8];
-            encode<R32>(A, nbs[k], we0, we1, be, isr, isd, t);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) acc[j] += t[j];
-        }
-    } else {
-        u32x4 z4 = {0u, 0u, 0u, 0u};
-        unpack8(valid ? hin[i * 4 + g] : z4, hown);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (nbs[k] < 0) continue;
-            float t[8];
-            unpack8(hin[int64_t(nbs[k]) * 4 + g], t);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) acc[j] += t[j];
-        }
+        for (int k = 0; k < 4; ++k) v[t] = mfma32(w1[t][1], as_bf(bn[k]), v[t]);
     }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) m[j] = rbf(acc[j] * 0.25f);
 }
 
 // ---- forward -------------------------------------------------------------------
@@ -139,6 +135,13 @@ __device__ inline void layer_input(const NnIn& A, const u32x4* hin, int64_t i, b
 // z = D^-1 r + s_d y).  FCG: return at once when the solve has finished, and
 // write per-block partial sums of z.r and z.r_old.  KEEP: the last layer also
 // stores its h (training).
+//
+// A block takes a contiguous range of 64-cell block-groups (so the neighbour
+// rows its cells share are fetched into its XCD's L2 once); each of its waves
+// walks every fourth 16-cell group of the range as a two-stage pipeline:
+// while group k is computed, the rows of group k+1 (whose neighbour indices
+// arrived during step k-1) and the neighbour indices of group k+2 are in
+// flight, so the gather's two dependent loads overlap the matrix-core work.
 struct NnFwd {
     NnIn in;
     const u32x4* hin;
@@ -148,6 +151,47 @@ struct NnFwd {
     double* partial;          // [2][gridDim.x]
     int layer;
 };
+
+// inputs of one group as loaded (rows or residual values of the cell and its
+// face neighbours; absent ones are 0 and flagged by nb < 0)
+template <int KIND>
+struct FwdRaw {
+    u32x4 h[5];               // KIND 1, 2: own row chunk, then the neighbours'
+    double r[5], dv[5];       // KIND 0: r and D^-1 of the cell and neighbours
+    double rs, ds, ro;        // KIND 2: own r, D^-1, r_old
+};
+
+__device__ inline int4 load_nbr(const NnIn& A, int64_t G, int64_t Gend, int c) {
+    const int64_t i = G * 16 + c;
+    return (G < Gend && i < A.nc) ? A.nbr[i] : make_int4(-1, -1, -1, -1);
+}
+
+template <int KIND, bool R32, bool FCG>
+__device__ inline void load_raw(const NnFwd& F, int64_t G, int64_t Gend, int4 nb, int c, int g, FwdRaw<KIND>& w) {
+    const NnIn& A = F.in;
+    const int64_t i = G * 16 + c;
+    const bool valid = G < Gend && i < A.nc;
+    const int nbs[4] = {nb.x, nb.y, nb.z, nb.w};
+    if (KIND == 0) {
+        w.r[0] = valid ? (R32 ? double(A.r32[i]) : A.r64[i]) : 0.0;
+        w.dv[0] = valid ? A.dinv[i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            w.r[k + 1] = nbs[k] >= 0 ? (R32 ? double(A.r32[nbs[k]]) : A.r64[nbs[k]]) : 0.0;
+            w.dv[k + 1] = nbs[k] >= 0 ? A.dinv[nbs[k]] : 0.0;
+        }
+    } else {
+        const u32x4 z4 = {0u, 0u, 0u, 0u};
+        w.h[0] = valid ? F.hin[i * 4 + g] : z4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w.h[k + 1] = nbs[k] >= 0 ? F.hin[int64_t(nbs[k]) * 4 + g] : z4;
+    }
+    if (KIND == 2) {
+        w.rs = valid ? (R32 ? double(A.r32[i]) : A.r64[i]) : 0.0;
+        w.ds = valid ? A.dinv[i] : 0.0;
+        w.ro = (FCG && valid) ? F.r_old[i] : 0.0;
+    }
+}
 
 template <int KIND, bool R32, bool FCG, bool KEEP>
 __global__ __launch_bounds__(256) void k_nn_layer(NnFwd F) {
@@ -177,33 +221,53 @@ __global__ __launch_bounds__(256) void k_nn_layer(NnFwd F) {
     const float bd = P->bd;
     const double isr = A.scal[SC_NN_INV_SR], isd = A.scal[SC_NN_INV_SD], sd = A.scal[SC_NN_SD];
     double zr = 0.0, zro = 0.0;
-    const int64_t nbg = (A.nc + 63) / 64;
-    for (int64_t bg = blockIdx.x; bg < nbg; bg += gridDim.x) {
-        const int64_t i = bg * 64 + wv * 16 + c;
+    int64_t b0, b1r;
+    block_range((A.nc + 63) / 64, b0, b1r);
+    const int64_t Gend = b1r * 4;
+    int64_t G = b0 * 4 + wv;
+    int4 nb_a = load_nbr(A, G, Gend, c);
+    int4 nb_b = load_nbr(A, G + 4, Gend, c);
+    FwdRaw<KIND> ra;
+    load_raw<KIND, R32, FCG>(F, G, Gend, nb_a, c, g, ra);
+    for (; G < Gend; G += 4) {
+        FwdRaw<KIND> rb;
+        load_raw<KIND, R32, FCG>(F, G + 4, Gend, nb_b, c, g, rb);
+        const int4 nb_c = load_nbr(A, G + 8, Gend, c);
+        const int64_t i = G * 16 + c;
         const bool valid = i < A.nc;
-        const int4 nb = valid ? A.nbr[i] : make_int4(-1, -1, -1, -1);
-        float hown[8], m[8];
-        layer_input<KIND == 0, R32>(A, F.hin, i, valid, nb, g, we0, we1, be, isr, isd, hown, m);
-        const bf16x8 bh = as_bf(pack8(hown)), bm = as_bf(pack8(m));
-        f32x4 v[2];
+        const u32x4 z4 = {0u, 0u, 0u, 0u};
+        u32x4 bh, bn[4];
+        if (KIND == 0) {
+            const int nbs[4] = {nb_a.x, nb_a.y, nb_a.z, nb_a.w};
+            bh = valid ? encode(ra.r[0], ra.dv[0], we0, we1, be, isr, isd) : z4;
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            v[t] = mfma32(w1[t][0], bh, f32x4{0.f, 0.f, 0.f, 0.f});
-            v[t] = mfma32(w1[t][1], bm, v[t]);
+            for (int k = 0; k < 4; ++k)
+                bn[k] = nbs[k] >= 0 ? encode(ra.r[k + 1], ra.dv[k + 1], we0, we1, be, isr, isd) : z4;
+        } else {
+            bh = ra.h[0];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bn[k] = ra.h[k + 1];
         }
+        float hown[8];
+        unpack8(bh, hown);
+        f32x4 v[2];
+        w1_product(w1, bh, bn, v);
         float u[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) u[j] = rbf(fmaxf(v[j >> 2][j & 3] + b1[j], 0.f));
-        const bf16x8 bu = as_bf(pack8(u));
-        float hn[8];
+        for (int j = 0; j < 8; ++j) u[j] = fmaxf(v[j >> 2][j & 3] + b1[j], 0.f);
+        const u32x4 bu = cvt8(u);
+        float hf[8];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const f32x4 o = mfma32(w2[t], bu, f32x4{0.f, 0.f, 0.f, 0.f});
+            const f32x4 o = mfma32(w2[t], as_bf(bu), f32x4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-            for (int k = 0; k < 4; ++k) hn[4 * t + k] = rbf((hown[4 * t + k] + o[k]) + b2[4 * t + k]);
+            for (int k = 0; k < 4; ++k) hf[4 * t + k] = (hown[4 * t + k] + o[k]) + b2[4 * t + k];
         }
-        if ((KIND != 2 || KEEP) && valid) F.hout[i * 4 + g] = pack8(hn);
+        const u32x4 hp = cvt8(hf);
+        if ((KIND != 2 || KEEP) && valid) F.hout[i * 4 + g] = hp;
         if (KIND == 2) {
+            float hn[8];
+            unpack8(hp, hn);
             float y = 0.f;
 #pragma unroll
             for (int j = 0; j < 8; ++j) y = fmaf(wd[j], hn[j], y);
@@ -211,15 +275,17 @@ __global__ __launch_bounds__(256) void k_nn_layer(NnFwd F) {
             y += __shfl_xor(y, 32, 64);
             y += bd;
             if (g == 0 && valid) {
-                const double r = R32 ? double(A.r32[i]) : A.r64[i];
-                const double zi = A.dinv[i] * r + sd * double(y);
+                const double zi = ra.ds * ra.rs + sd * double(y);
                 F.z[i] = zi;
                 if (FCG) {
-                    zr += zi * r;
-                    zro += zi * F.r_old[i];
+                    zr += zi * ra.rs;
+                    zro += zi * ra.ro;
                 }
             }
         }
+        nb_a = nb_b;
+        nb_b = nb_c;
+        ra = rb;
     }
     if (FCG && KIND == 2) {
         const double s0 = block_sum256(zr, lds);
@@ -259,6 +325,7 @@ struct NnBwd {
 
 struct WaveT {                // per-wave transposes, [feature][cell] bf16
     uint16_t dh_hi[32][16], dh_lo[32][16], du_hi[32][16], du_lo[32][16], u[32][16], a[64][16];
+    uint16_t m_lo[32][16];    // low part of the (unrounded) neighbour mean
 };
 
 __device__ inline i16x4 ld4(const uint16_t* p) { return *reinterpret_cast<const i16x4*>(p); }
@@ -290,8 +357,7 @@ __global__ __launch_bounds__(256) void k_nn_bwd(NnBwd B) {
         wd[j] = P->wd[8 * g + j];
     }
     const double isr = A.scal[SC_NN_INV_SR], isd = A.scal[SC_NN_INV_SD], sd = A.scal[SC_NN_SD];
-    const double rr = A.scal[SC_NN_RR];
-    const double dscale = rr > 0.0 ? -2.0 * sd / rr : 0.0;      // dy = dscale * w
+    const double dscale = A.scal[SC_NN_DSCALE];                 // dy = dscale * w (set by the loss)
     f32x4 gw2[2][2], gw1[2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -303,27 +369,49 @@ __global__ __launch_bounds__(256) void k_nn_bwd(NnBwd B) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) gb1[j] = gb2[j] = gwd[j] = 0.f;
     WaveT& T = wt[wv];
-    const int64_t nbg = (A.nc + 63) / 64;
-    for (int64_t bg = blockIdx.x; bg < nbg; bg += gridDim.x) {
+    int64_t bg0, bg1;
+    block_range((A.nc + 63) / 64, bg0, bg1);
+    for (int64_t bg = bg0; bg < bg1; ++bg) {         // the same trip count in every wave
         const int64_t i = bg * 64 + wv * 16 + c;
         const bool valid = i < A.nc;
         const int4 nb = valid ? A.nbr[i] : make_int4(-1, -1, -1, -1);
+        const int nbv[4] = {nb.x, nb.y, nb.z, nb.w};
+        const u32x4 z4 = {0u, 0u, 0u, 0u};
+        u32x4 bh, bn[4];
+        if (FIRST) {
+            bh = valid ? encode(double(A.r32[i]), A.dinv[i], we0, we1, be, isr, isd) : z4;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                bn[k] = nbv[k] >= 0 ? encode(double(A.r32[nbv[k]]), A.dinv[nbv[k]], we0, we1, be, isr, isd) : z4;
+        } else {
+            bh = valid ? B.hin[i * 4 + g] : z4;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bn[k] = nbv[k] >= 0 ? B.hin[int64_t(nbv[k]) * 4 + g] : z4;
+        }
         float hown[8], m[8];
-        layer_input<FIRST, true>(A, B.hin, i, valid, nb, g, we0, we1, be, isr, isd, hown, m);
-        const bf16x8 bh = as_bf(pack8(hown)), bm = as_bf(pack8(m));
+        unpack8(bh, hown);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) m[j] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float t[8];
+            unpack8(bn[k], t);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) m[j] += t[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) m[j] *= 0.25f;
+        f32x4 vv4[2];
+        w1_product(w1, bh, bn, vv4);
         float u[8];
         bool on[8];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            f32x4 v = mfma32(w1[t][0], bh, f32x4{0.f, 0.f, 0.f, 0.f});
-            v = mfma32(w1[t][1], bm, v);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float vv = v[k] + b1[4 * t + k];
-                on[4 * t + k] = vv > 0.f;
-                u[4 * t + k] = rbf(fmaxf(vv, 0.f));
-            }
+        for (int j = 0; j < 8; ++j) {
+            const float vv = vv4[j >> 2][j & 3] + b1[j];
+            on[j] = vv > 0.f;
+            u[j] = fmaxf(vv, 0.f);
         }
+        const u32x4 bu = cvt8(u);
         // gradient at the layer output
         float dh[8];
         if (TOP) {
@@ -401,6 +489,8 @@ __global__ __launch_bounds__(256) void k_nn_bwd(NnBwd B) {
         }
         // transposes for the weight gradients (invalid cells carry zero dh, du)
         {
+            u32x4 m_hi, m_lo;
+            split8(m, m_hi, m_lo);
             const u32x4 hh = dh_hi, hl = dh_lo, uh = du_hi, ulo = du_lo;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -410,9 +500,10 @@ __global__ __launch_bounds__(256) void k_nn_bwd(NnBwd B) {
                 T.dh_lo[f][c] = uint16_t(hl[k] >> sh);
                 T.du_hi[f][c] = uint16_t(uh[k] >> sh);
                 T.du_lo[f][c] = uint16_t(ulo[k] >> sh);
-                T.u[f][c] = uint16_t(f2bf(u[j]));
-                T.a[f][c] = uint16_t(f2bf(hown[j]));
-                T.a[32 + f][c] = uint16_t(f2bf(m[j]));
+                T.u[f][c] = uint16_t(bu[k] >> sh);
+                T.a[f][c] = uint16_t(bh[k] >> sh);
+                T.a[32 + f][c] = uint16_t(m_hi[k] >> sh);
+                T.m_lo[f][c] = uint16_t(m_lo[k] >> sh);
             }
         }
         __syncthreads();
@@ -431,6 +522,7 @@ __global__ __launch_bounds__(256) void k_nn_bwd(NnBwd B) {
                 const i16x4 ba = ld4(&T.a[16 * ti + c][4 * g]);
                 gw1[to][ti] = mfma16(ch, ba, gw1[to][ti]);
                 gw1[to][ti] = mfma16(cl, ba, gw1[to][ti]);
+                if (ti >= 2) gw1[to][ti] = mfma16(ch, ld4(&T.m_lo[16 * (ti - 2) + c][4 * g]), gw1[to][ti]);
             }
         }
         __syncthreads();
@@ -495,8 +587,9 @@ __global__ __launch_bounds__(256) void k_nn_enc_bwd(NnIn A, const float* base_in
     float g0[8], g1[8], gb[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) g0[j] = g1[j] = gb[j] = 0.f;
-    const int64_t nbg = (A.nc + 63) / 64;
-    for (int64_t bg = blockIdx.x; bg < nbg; bg += gridDim.x) {
+    int64_t bg0, bg1;
+    block_range((A.nc + 63) / 64, bg0, bg1);
+    for (int64_t bg = bg0; bg < bg1; ++bg) {
         const int64_t i = bg * 64 + wv * 16 + c;
         if (i >= A.nc) continue;
         const int4 nb = A.nbr[i];
@@ -552,7 +645,10 @@ __global__ __launch_bounds__(256) void k_nn_enc_bwd(NnIn A, const float* base_in
     for (int k = threadIdx.x; k < 96; k += blockDim.x) out[kNnOffWe + k] = red[k];
 }
 
-// ---- loss: res = r - K z, w = K^T res --------------------------------------------
+// ---- losses ----------------------------------------------------------------------
+// residual: res = r - K z, L = |res|^2 / |r|^2, w = K^T res, dy = -2 s_d / |r|^2 w
+// energy:   a = K z, L = (z.a - 2 z.r) / r.D^-1 r, w = (a + K^T z) / 2 - r,
+//           dy = 2 s_d / r.D^-1 r w
 __device__ inline double row_dot(const Dev& d, const double* __restrict__ vals, const double* __restrict__ x,
                                  int64_t i) {
     const int64_t s = i >> 6;
@@ -579,12 +675,41 @@ __global__ __launch_bounds__(256) void k_nn_resid(Dev d, const float* r32, const
     if (threadIdx.x == 0) d.partial[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(1024) void k_nn_loss_fin(Dev d, int64_t nparts, double* loss_slot) {
+__global__ __launch_bounds__(256) void k_nn_energy_a(Dev d, const float* r32, const double* z, double* a) {
+    __shared__ double lds[4];
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    double v = 0.0;
+    if (i < d.nc) {
+        const double ai = row_dot(d, d.k_val, z, i);
+        a[i] = ai;
+        v = z[i] * ai - 2.0 * z[i] * double(r32[i]);
+    }
+    const double s = block_sum256(v, lds);
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_nn_energy_w(Dev d, const double* kt, const float* r32, const double* z,
+                                                     const double* a, double* w) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < d.nc) w[i] = 0.5 * (a[i] + row_dot(d, kt, z, i)) - double(r32[i]);
+}
+
+// loss of the step into *loss_slot and the factor of the top layer's dy
+__global__ __launch_bounds__(1024) void k_nn_loss_fin(Dev d, int64_t nparts, int kind, double* loss_slot) {
     __shared__ double lds[16];
     const double s = reduce_partials_sum(d.partial, nparts, lds);
     if (threadIdx.x == 0) {
-        const double rr = d.scal[SC_NN_RR];
-        *loss_slot = rr > 0.0 ? s / rr : 0.0;
+        double* sc = d.scal;
+        const double sd = sc[SC_NN_SD];
+        if (kind == 0) {
+            const double rr = sc[SC_NN_RR];
+            *loss_slot = rr > 0.0 ? s / rr : 0.0;
+            sc[SC_NN_DSCALE] = rr > 0.0 ? -2.0 * sd / rr : 0.0;
+        } else {
+            const double rdr = sc[SC_NN_RDR];
+            *loss_slot = rdr > 0.0 ? s / rdr : 0.0;
+            sc[SC_NN_DSCALE] = rdr > 0.0 ? 2.0 * sd / rdr : 0.0;
+        }
     }
 }
 
@@ -598,18 +723,21 @@ template <bool R32>
 __global__ __launch_bounds__(256) void k_nn_scale(Dev d, const double* r64, const float* r32) {
     __shared__ double lds[4];
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    double a = 0.0, b = 0.0;
+    double a = 0.0, b = 0.0, e = 0.0;
     if (i < d.nc) {
         const double r = R32 ? double(r32[i]) : r64[i];
         const double q = d.k_dinv[i] * r;
         a = r * r;
         b = q * q;
+        e = q * r;
     }
     const double s0 = block_sum256(a, lds);
     const double s1 = block_sum256(b, lds);
+    const double s2 = block_sum256(e, lds);
     if (threadIdx.x == 0) {
         d.partial[blockIdx.x] = s0;
         d.partial[gridDim.x + blockIdx.x] = s1;
+        d.partial[2 * gridDim.x + blockIdx.x] = s2;
     }
 }
 
@@ -626,7 +754,11 @@ __global__ __launch_bounds__(1024) void k_nn_scale_fin(Dev d, int64_t nparts) {
     __shared__ double lds[16];
     const double rr = reduce_partials_sum(d.partial, nparts, lds);
     const double dd = reduce_partials_sum(d.partial + nparts, nparts, lds);
-    if (threadIdx.x == 0) set_scales(d.scal, rr, dd, d.nc);
+    const double rdr = reduce_partials_sum(d.partial + 2 * nparts, nparts, lds);
+    if (threadIdx.x == 0) {
+        set_scales(d.scal, rr, dd, d.nc);
+        d.scal[SC_NN_RDR] = rdr;
+    }
 }
 
 // ---- gradient sum over blocks and Adam --------------------------------------------
@@ -678,9 +810,10 @@ __global__ __launch_bounds__(256) void k_nn_pack(NnDev n) {
             for (int j = 0; j < 8; ++j) {
                 const int k = nn_pi(8 * g + j);
                 float w;
-                if (frag < 4) {              // w1[t][s]
+                if (frag < 4) {              // w1[t][s]; the m-half (s = 1) scaled by 1/4 (exact)
                     const int t = frag >> 1, s = frag & 1;
                     w = W1[(16 * t + row) * 64 + 32 * s + k];
+                    if (s == 1) w = rbf(w) * 0.25f;
                 } else if (frag < 6) {       // w2[t]
                     w = W2[(16 * (frag - 4) + row) * 32 + k];
                 } else if (frag < 8) {       // w2t[t]
@@ -945,13 +1078,19 @@ hipError_t launch_nn_layer(const Dev& d, const NnDev& n, const NnStateDev& a, in
 
 int nn_forward_grid(int64_t nc) { return nn_fwd_grid(nc); }
 
-hipError_t launch_nn_backward(const Dev& d, const NnDev& n, const NnStateDev& a, const float* r32,
+hipError_t launch_nn_backward(const Dev& d, const NnDev& n, const NnStateDev& a, const float* r32, int kind,
                               double* loss_slot, hipStream_t s) {
-    // res = r - K z (z in d.z, res in d.q), loss; w = K^T res (in d.p)
+    // z in d.z; scratch in d.q; w in d.p
     const unsigned nb = rows256(d.nc);
-    hipLaunchKernelGGL(k_nn_resid, dim3(nb), dim3(256), 0, s, d, r32, d.z, d.q);
-    hipLaunchKernelGGL(k_nn_loss_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb), loss_slot);
-    hipLaunchKernelGGL(k_nn_spmv_t, dim3(nb), dim3(256), 0, s, d, a.kt_val, d.q, d.p);
+    if (kind == 0) {
+        hipLaunchKernelGGL(k_nn_resid, dim3(nb), dim3(256), 0, s, d, r32, d.z, d.q);
+        hipLaunchKernelGGL(k_nn_loss_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb), 0, loss_slot);
+        hipLaunchKernelGGL(k_nn_spmv_t, dim3(nb), dim3(256), 0, s, d, a.kt_val, d.q, d.p);
+    } else {
+        hipLaunchKernelGGL(k_nn_energy_a, dim3(nb), dim3(256), 0, s, d, r32, d.z, d.q);
+        hipLaunchKernelGGL(k_nn_loss_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb), 1, loss_slot);
+        hipLaunchKernelGGL(k_nn_energy_w, dim3(nb), dim3(256), 0, s, d, a.kt_val, r32, d.z, d.q, d.p);
+    }
     NnBwd B;
     B.in = make_in(d, n, a, nullptr, r32);
     B.partial = n.partial;

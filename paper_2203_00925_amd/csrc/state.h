@@ -171,7 +171,8 @@ enum Scal {
     SC_RZ = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_BB, SC_TOL2BB, SC_DONE, SC_IT, SC_MAXIT,
     SC_TRUE_RR, SC_CONS, SC_DT_INV, SC_RESTART, SC_SINCE, SC_TOL2BB_OUT,
     // learned preconditioner: input scales and flexible-CG dot products
-    SC_NN_INV_SR, SC_NN_INV_SD, SC_NN_SD, SC_NN_RR, SC_NN_DD, SC_ZR, SC_ZRO, SC_COUNT_ = 32
+    SC_NN_INV_SR, SC_NN_INV_SD, SC_NN_SD, SC_NN_RR, SC_NN_DD, SC_ZR, SC_ZRO, SC_NN_RDR, SC_NN_DSCALE,
+    SC_COUNT_ = 32
 };
 
 }  // namespace mifvm

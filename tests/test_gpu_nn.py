@@ -92,7 +92,8 @@ def test_forward_matches_oracle():
     assert rel(zj, dinv * r) < 1e-12
 
 
-def test_gradient_matches_oracle():
+@pytest.mark.parametrize("kind", [B.LOSS_RESIDUAL, B.LOSS_ENERGY])
+def test_gradient_matches_oracle(kind):
     n, seed = 5, 1001
     m, mesh, st = poisson_state(n, seed)
     g = cube_geometry(n, seed)
@@ -105,11 +106,12 @@ def test_gradient_matches_oracle():
     net.attach(st, training=True)
     r32 = np.random.default_rng(6).normal(size=m.nc).astype(np.float32)
     perm = mesh.export("cell_perm")               # internal -> user
-    loss, grad = st.nn_loss_grad(dev(r32[perm], torch.float32))
-    Lo, go = mpnn.loss_and_grad(p, K, r32.astype(np.float64), dinv, nbr, bf16_like_gpu=True)
+    loss, grad = st.nn_loss_grad(dev(r32[perm], torch.float32), kind)
+    Lo, go = mpnn.loss_and_grad(p, K, r32.astype(np.float64), dinv, nbr, bf16_like_gpu=True,
+                                kind=("residual", "energy")[kind])
     go = mpnn.flatten(go)
-    print(f"[nn] loss gpu {loss:.6f} oracle {Lo:.6f}; grad rel err {rel(grad, go):.2e}")
-    assert abs(loss - Lo) <= TOL_FWD * Lo
+    print(f"[nn] loss {kind}: gpu {loss:.6f} oracle {Lo:.6f}; grad rel err {rel(grad, go):.2e}")
+    assert abs(loss - Lo) <= TOL_FWD * abs(Lo)
     assert rel(grad, go) < TOL_GRAD
     # every parameter block on its own
     at = 0

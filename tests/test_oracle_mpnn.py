@@ -17,7 +17,11 @@ def setup(n=3, seed=2):
     return geo, K, dinv, nbr, r
 
 
-def test_backward_matches_finite_differences():
+import pytest
+
+
+@pytest.mark.parametrize("kind", ["residual", "energy"])
+def test_backward_matches_finite_differences(kind):
     geo, K, dinv, nbr, r = setup()
     p = mpnn.init_params(seed=3, scale=0.3)
     rng = np.random.default_rng(4)
@@ -26,7 +30,7 @@ def test_backward_matches_finite_differences():
     for l in range(mpnn.LAYERS):
         p[f"b1_{l}"] = rng.normal(0, 0.3, mpnn.H)
         p[f"b2_{l}"] = rng.normal(0, 0.3, mpnn.H)
-    L, g = mpnn.loss_and_grad(p, K, r, dinv, nbr)
+    L, g = mpnn.loss_and_grad(p, K, r, dinv, nbr, kind=kind)
     v = mpnn.flatten(p)
     gv = mpnn.flatten(g)
     idx = rng.choice(len(v), 60, replace=False)
@@ -35,8 +39,8 @@ def test_backward_matches_finite_differences():
         vp, vm = v.copy(), v.copy()
         vp[i] += eps
         vm[i] -= eps
-        Lp, _ = mpnn.loss_and_grad(mpnn.unflatten(vp, p), K, r, dinv, nbr)
-        Lm, _ = mpnn.loss_and_grad(mpnn.unflatten(vm, p), K, r, dinv, nbr)
+        Lp, _ = mpnn.loss_and_grad(mpnn.unflatten(vp, p), K, r, dinv, nbr, kind=kind)
+        Lm, _ = mpnn.loss_and_grad(mpnn.unflatten(vm, p), K, r, dinv, nbr, kind=kind)
         fd = (Lp - Lm) / (2 * eps)
         assert abs(fd - gv[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, gv[i])
 
@@ -72,3 +76,21 @@ def test_bf16_rounding():
     assert b[2] == 1.0 + 2 ** -7                # rounds up
     assert b[3] == -2.5
     assert abs(b[4] - 3.0e-3) <= 3.0e-3 * 2 ** -8
+
+
+def test_energy_loss_is_the_energy_norm_of_the_error_up_to_a_constant():
+    """(z^T K z - 2 z^T r) / r^T D^-1 r = (||z - e||^2_Ks - ||e||^2_Ks) / r^T D^-1 r
+    with e = Ks^-1 r, for any z (here: two different networks)."""
+    import scipy.sparse.linalg as spla
+    geo, K, dinv, nbr, r = setup()
+    Ks = ((K + K.T) * 0.5).tocsc()
+    e = spla.spsolve(Ks, r)
+    rdr = np.dot(r, dinv * r)
+    for seed in (1, 2):
+        p = mpnn.init_params(seed=seed, scale=0.3)
+        p["wd"] = np.random.default_rng(seed).normal(0, 0.3, mpnn.H)
+        L, _ = mpnn.loss_and_grad(p, K, r, dinv, nbr, kind="energy")
+        z, _ = mpnn.forward(p, r, dinv, nbr)
+        d = z - e
+        want = (np.dot(d, Ks @ d) - np.dot(e, Ks @ e)) / rdr
+        assert abs(L - want) <= 1e-10 * max(1.0, abs(want))
