@@ -145,13 +145,27 @@ typedef struct {
                                   iterations (0 = 200)                      */
     int32_t learned_maxit;     /* LEARNED: fall back after this many flexible
                                   CG iterations (0 = maxit)                  */
+    int32_t matrix_free;       /* PLAIN, LEARNED: 1 = apply K in the iterations
+                                  from the discretisation (vertex values,
+                                  diamond fluxes, cell gather) instead of the
+                                  stored matrix; the assembled diagonal, c
+                                  and the true-residual checks are unchanged */
+    int32_t pad_;
 } mifvm_solve_opts;
 
 /* PLAIN: FP64 Jacobi-CG.  IR_FP32: iterative refinement - the FP64 true
  * residual r = b - K x, an FP32 Jacobi-CG solve of K d = r on an FP32 copy of
  * K (dot products accumulated in FP64), x += d in FP64 - repeated until the
  * FP64 true residual meets tol.                                            */
-enum mifvm_solve_method { MIFVM_SOLVE_PLAIN = 0, MIFVM_SOLVE_IR_FP32 = 1, MIFVM_SOLVE_LEARNED = 2 };
+enum mifvm_solve_method { MIFVM_SOLVE_PLAIN = 0, MIFVM_SOLVE_IR_FP32 = 1, MIFVM_SOLVE_LEARNED = 2,
+                          MIFVM_SOLVE_FGMRES = 3 };
+/* FGMRES: restarted flexible GMRES(m) with the Jacobi preconditioner, the
+ * Krylov method of the paper's solver runs (Sec. 3.4.2): right
+ * preconditioning z_j = D^-1 v_j, classical Gram-Schmidt, Givens rotations,
+ * and a new cycle from the true residual every m steps (m from
+ * mifvm_fgmres_attach; `restart` is not used).  `iterations` counts steps,
+ * `outer` cycles.  Needs a single-mesh state with an FGMRES workspace;
+ * matrix_free applies.                                                     */
 /* LEARNED: flexible CG (Polak-Ribiere beta) preconditioned by the attached
  * message-passing network (mifvm_nn.h), with restarts from the true residual
  * as for PLAIN.  A non-finite residual (the iterate is reset to the last
@@ -262,6 +276,12 @@ int mifvm_mesh_values(const mifvm_state* st, int32_t what, double* out, int32_t 
 int mifvm_poisson_assemble(mifvm_state* st, void* stream);
 /* d_y = K d_x, both user order.                                            */
 int mifvm_poisson_apply(mifvm_state* st, const double* d_x, double* d_y, void* stream);
+/* d_y = K d_x evaluated from the discretisation, without the stored matrix
+ * (eqs. (7), (laplace): Algorithm 2 vertex values with homogeneous ghosts,
+ * the diamond flux on interior and Dirichlet faces, the sum over each
+ * cell's faces), user order; equal to mifvm_poisson_apply up to rounding.
+ * Needs only the POTENTIAL boundary kinds (no assembly).                  */
+int mifvm_poisson_apply_free(mifvm_state* st, const double* d_x, double* d_y, void* stream);
 /* d_b = -mu * d_f + c (user order; d_f NULL = the current U).              */
 int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* stream);
 /* Jacobi-preconditioned CG on K x = b with b from d_f (NULL = current U);
@@ -277,6 +297,12 @@ int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* str
  * Synchronises (once per chunk).                                           */
 int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_opts* opts,
                         mifvm_solve_info* info, void* stream);
+
+/* FGMRES workspace: (2m + 1) vectors of nc doubles and O(m^2) scalars, in a
+ * caller-owned 256-byte-aligned device buffer that must outlive its use.
+ * 1 <= m <= 64.  attach with d_ws NULL detaches.  E_ARG for a batch.       */
+int mifvm_fgmres_bytes(const mifvm_state* st, int32_t m, size_t* out);
+int mifvm_fgmres_attach(mifvm_state* st, int32_t m, void* d_ws, size_t ws_bytes);
 
 /* ---- captured replays and the autotuner -----------------------------------
  * mifvm_step_graph: as mifvm_step, but the n_steps x 3 stages are captured

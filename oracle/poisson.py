@@ -158,6 +158,72 @@ def jacobi_cg(K, b, x0=None, tol=1e-10, maxit=20000, restart=0, history=None):
             rz = rz_new
 
 
+def jacobi_fgmres(K, b, x0=None, tol=1e-10, m=30, maxit=20000, precond=None, history=None):
+    """Restarted flexible GMRES(m) with right preconditioning, the Krylov
+    method of the paper's solver runs (Sec. 3.4.2), here with the Jacobi
+    preconditioner z = D^{-1} v unless `precond` (a function v -> z, which may
+    vary between calls) is given.
+
+    A cycle opens from the true residual r = b - K x: v_0 = r/|r|,
+    g = |r| e_0.  Step j: z_j = M(v_j), w = K z_j; classical Gram-Schmidt
+    h_ij = v_i . w (i <= j, all against the same w), w -= sum h_ij v_i;
+    h_{j+1,j} = |w|, v_{j+1} = w / h_{j+1,j}; the earlier Givens rotations
+    are applied to column j of H, a new rotation zeroes h_{j+1,j}, and
+    |g_{j+1}| is the residual norm of the least-squares iterate.  The cycle
+    ends when |g_{j+1}| <= tol |b|, after m steps or at maxit; then H y = g
+    (upper triangular, j+1 unknowns) and x += Z y.  The loop reopens from the
+    true residual until it meets the tolerance or maxit.  `history`, if
+    given, receives x after every cycle.  Returns (x, iterations, true
+    relative residual)."""
+    b = np.asarray(b, np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, np.float64)
+    dinv = 1.0 / K.diagonal()
+    M = precond if precond is not None else (lambda v: dinv * v)
+    bnorm = np.linalg.norm(b)
+    it = 0
+    while True:
+        r = b - K @ x
+        beta = np.linalg.norm(r)
+        if beta <= tol * bnorm or it >= maxit:
+            return x, it, float(beta / bnorm)
+        V = [r / beta]
+        Z = []
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        k = 0
+        for j in range(m):
+            z = M(V[j])
+            Z.append(z)
+            w = K @ z
+            h = np.array([vi @ w for vi in V])        # classical: all dots against one w
+            w = w - sum(hi * vi for hi, vi in zip(h, V))
+            H[:j + 1, j] = h
+            H[j + 1, j] = np.linalg.norm(w)
+            V.append(w / H[j + 1, j])
+            for i in range(j):                          # earlier rotations
+                a, c = H[i, j], H[i + 1, j]
+                H[i, j] = cs[i] * a + sn[i] * c
+                H[i + 1, j] = -sn[i] * a + cs[i] * c
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            k = j + 1
+            it += 1
+            if abs(g[j + 1]) <= tol * bnorm or it >= maxit:
+                break
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):                 # back substitution
+            y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
+        x = x + sum(yi * zi for yi, zi in zip(y, Z))
+        if history is not None:
+            history.append(x.copy())
+
+
 def direct_solve(K, b):
     """Sparse LU solve (SuperLU), the pin for x* = K^{-1} b."""
     return spla.spsolve(K.tocsc(), b)

@@ -21,7 +21,7 @@ ZERO_FLUX, NEUMANN, DIRICHLET = 0, 1, 2
 VAR_SCALAR, VAR_POTENTIAL = 0, 1
 FIELD_U, FIELD_VEL, FIELD_SOURCE, FIELD_P = 0, 1, 2, 3
 RENUMBER_NONE, RENUMBER_MORTON = 0, 1
-SOLVE_PLAIN, SOLVE_IR_FP32, SOLVE_LEARNED = 0, 1, 2
+SOLVE_PLAIN, SOLVE_IR_FP32, SOLVE_LEARNED, SOLVE_FGMRES = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
            "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble", "nn_layer1", "nn_layer2", "nn_layer3",
@@ -82,7 +82,8 @@ class SolveOpts(C.Structure):
                 ("restart", C.c_int32), ("history_cap", C.c_int32),
                 ("history", C.POINTER(C.c_double)), ("method", C.c_int32),
                 ("graph", C.c_int32), ("inner_tol", C.c_double),
-                ("stall_window", C.c_int32), ("learned_maxit", C.c_int32)]
+                ("stall_window", C.c_int32), ("learned_maxit", C.c_int32),
+                ("matrix_free", C.c_int32), ("pad_", C.c_int32)]
 
 
 class TuneInfo(C.Structure):
@@ -140,6 +141,9 @@ def _load():
         "mifvm_conservation": (C.c_int, [P, C.POINTER(D), P]),
         "mifvm_poisson_assemble": (C.c_int, [P, P]),
         "mifvm_poisson_apply": (C.c_int, [P, P, P, P]),
+        "mifvm_poisson_apply_free": (C.c_int, [P, P, P, P]),
+        "mifvm_fgmres_bytes": (C.c_int, [P, I32, C.POINTER(SZ)]),
+        "mifvm_fgmres_attach": (C.c_int, [P, I32, P, SZ]),
         "mifvm_poisson_rhs": (C.c_int, [P, P, P, P]),
         "mifvm_poisson_solve": (C.c_int, [P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), P]),
         "mifvm_kernel_timing": (C.c_int, [P, I32]),
@@ -352,6 +356,24 @@ class State:
         _check(_lib.mifvm_poisson_apply(self._h, _ptr(x), _ptr(y), _stream(stream)))
         return y
 
+    def fgmres_attach(self, m=30):
+        """Workspace for method SOLVE_FGMRES with cycles of m steps."""
+        import torch
+        n = C.c_size_t()
+        _check(_lib.mifvm_fgmres_bytes(self._h, int(m), C.byref(n)))
+        ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        _check(_lib.mifvm_fgmres_attach(self._h, int(m), C.c_void_p(ws.data_ptr() + off), n.value))
+        self._gm_ws = ws
+
+    def poisson_apply_free(self, x, stream=None):
+        """K x from the discretisation (no stored matrix)."""
+        import torch
+        x = x.to(device=self.device, dtype=torch.float64).contiguous()
+        y = torch.empty_like(x)
+        _check(_lib.mifvm_poisson_apply_free(self._h, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
     def poisson_rhs(self, f=None, stream=None):
         import torch
         y = torch.empty(self.mesh.info.nc, dtype=torch.float64, device=self.device)
@@ -363,7 +385,7 @@ class State:
     def poisson_solve(self, f=None, tol=1e-10, maxit=20000, chunk=0, restart=500,
                       history=0, method=SOLVE_PLAIN, inner_tol=1e-4, graph=-1, stream=None,
                       allow_not_converged=False, stall_window=0, learned_maxit=0,
-                      allow_fell_back=False):
+                      allow_fell_back=False, matrix_free=False):
         """chunk 0 / graph -1: the autotuned schedule (32 iterations per host
         check, direct launches when not tuned)."""
         import torch
@@ -372,7 +394,7 @@ class State:
         hist = (C.c_double * max(int(history), 1))()
         opts = SolveOpts(float(tol), int(maxit), int(chunk), int(restart), int(history), hist,
                          int(method), int(graph), float(inner_tol), int(stall_window),
-                         int(learned_maxit))
+                         int(learned_maxit), 1 if matrix_free else 0, 0)
         info = SolveInfo()
         allow = (OK,) + ((NOT_CONVERGED,) if allow_not_converged else ()) + \
             ((FELL_BACK,) if allow_fell_back else ())

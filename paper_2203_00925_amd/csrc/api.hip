@@ -16,6 +16,7 @@
 
 #include "../../include/mifvm.h"
 #include "api_util.h"
+#include "gmres.h"
 #include "mesh.h"
 #include "state.h"
 
@@ -120,6 +121,8 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.xc32 = carve<float>(base, off, 3 * NX);
     d.gdist32 = carve<float>(base, off, nb);
     d.tmp = carve<double>(base, off, 3 * NX);
+    d.mf_xv = carve<double>(base, off, nv);
+    d.mf_flux = carve<double>(base, off, nf);
     // per-block partials of up to 4 sums x 2 mesh slots, for blocks of >= 64 rows
     const int64_t nblk = (nc + 63) / 64;
     d.partial = carve<double>(base, off, 8 * (nblk + 1024));
@@ -136,10 +139,13 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
 using namespace mifvm;
 
 namespace {
-// one chunk of n CG iterations (plain FP64 or FP32 inner), no timing events
-hipError_t enqueue_cg_chunk(const Dev& d, int method, int n, hipStream_t q) {
+// one chunk of n CG iterations (plain FP64, matrix-free or stored K, or FP32
+// inner), no timing events
+hipError_t enqueue_cg_chunk(const State& s, int method, int n, hipStream_t q) {
+    const Dev& d = s.d;
     for (int c = 0; c < n; ++c) {
-        hipError_t e = method == MIFVM_SOLVE_PLAIN ? launch_cg_spmv(d, q) : launch_cg32_spmv(d, q);
+        hipError_t e = method == MIFVM_SOLVE_PLAIN ? (s.mf ? launch_mf_cg_spmv(d, s.bc[1], q) : launch_cg_spmv(d, q))
+                                                   : launch_cg32_spmv(d, q);
         if (e == hipSuccess) e = method == MIFVM_SOLVE_PLAIN ? launch_cg_axpy(d, q) : launch_cg32_axpy(d, q);
         if (e == hipSuccess) e = method == MIFVM_SOLVE_PLAIN ? launch_cg_dir(d, q) : launch_cg32_dir(d, q);
         if (e != hipSuccess) return e;
@@ -336,6 +342,8 @@ void mifvm_state_destroy(mifvm_state* st) {
     if (st->s.cg_exec) (void)hipGraphExecDestroy(st->s.cg_exec);
     if (st->s.step_exec) (void)hipGraphExecDestroy(st->s.step_exec);
     if (st->s.fcg_exec) (void)hipGraphExecDestroy(st->s.fcg_exec);
+    if (st->s.gm_exec) (void)hipGraphExecDestroy(st->s.gm_exec);
+    delete st->s.gm;
     delete st->s.nn_state;
     if (st->s.cap_stream) (void)hipStreamDestroy(st->s.cap_stream);
     if (st->s.h_scal) (void)hipHostFree(st->s.h_scal);
@@ -592,6 +600,17 @@ int mifvm_poisson_assemble(mifvm_state* st, void* stream) {
     return MIFVM_OK;
 }
 
+int mifvm_poisson_apply_free(mifvm_state* st, const double* d_x, double* d_y, void* stream) {
+    if (!st || !d_x || !d_y) return fail(MIFVM_E_ARG, "null argument");
+    State& s = st->s;
+    const Dev& d = s.d;
+    hipStream_t hs = S(stream);
+    HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_x, d.tmp, hs));
+    HIPCHK(launch_mf_apply(d, s.bc[1], d.tmp, d.tmp + d.nc, hs));
+    HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.tmp + d.nc, d_y, hs));
+    return MIFVM_OK;
+}
+
 int mifvm_poisson_apply(mifvm_state* st, const double* d_x, double* d_y, void* stream) {
     if (!st || !d_x || !d_y) return fail(MIFVM_E_ARG, "null argument");
     State& s = st->s;
@@ -644,8 +663,16 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
     const int hist_cap = opts && opts->history ? opts->history_cap : 0;
     if (!(tol > 0) || maxit < 0 || restart < 0 || hist_cap < 0 || !(tol_in < 1))
         return fail(MIFVM_E_ARG, "bad tol, maxit, restart, inner_tol or history");
-    if (method != MIFVM_SOLVE_PLAIN && method != MIFVM_SOLVE_IR_FP32 && method != MIFVM_SOLVE_LEARNED)
+    if (method != MIFVM_SOLVE_PLAIN && method != MIFVM_SOLVE_IR_FP32 && method != MIFVM_SOLVE_LEARNED &&
+        method != MIFVM_SOLVE_FGMRES)
         return fail(MIFVM_E_ARG, "unknown method");
+    if (method == MIFVM_SOLVE_FGMRES) {
+        if (!s.gm) return fail(MIFVM_E_STATE, "method FGMRES needs a workspace (mifvm_fgmres_attach)");
+        if (s.d.nm != 1) return fail(MIFVM_E_ARG, "method FGMRES needs a single-mesh state");
+    }
+    const bool matrix_free = opts && opts->matrix_free != 0;
+    if (matrix_free && method == MIFVM_SOLVE_IR_FP32)
+        return fail(MIFVM_E_ARG, "matrix_free is built for the FP64 methods (PLAIN, LEARNED)");
     const int stall_window = opts ? opts->stall_window : 0;
     const int learned_maxit = opts ? opts->learned_maxit : 0;
     if (stall_window < 0 || learned_maxit < 0) return fail(MIFVM_E_ARG, "bad stall_window or learned_maxit");
@@ -656,6 +683,7 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
     const Dev& d = s.d;
     const int nm = d.nm;
     hipStream_t hs = S(stream);
+    s.mf = matrix_free;
     auto t0 = std::chrono::steady_clock::now();
     int rc = rhs_internal(s, d_f, hs);
     if (rc) return rc;
@@ -691,11 +719,12 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         budget = maxit - learned.iterations;
     }
     const int run_method = method == MIFVM_SOLVE_LEARNED ? MIFVM_SOLVE_PLAIN : method;
+    const int graph_key = run_method + (matrix_free ? 16 : 0);
     if (use_graph && (method != MIFVM_SOLVE_LEARNED || learned.fell_back) &&
-        (s.cg_exec == nullptr || s.cg_exec_chunk != chunk || s.cg_exec_method != run_method)) {
-        HIPCHK(capture_graph(s, &s.cg_exec, [&](hipStream_t q) { return enqueue_cg_chunk(d, run_method, chunk, q); }));
+        (s.cg_exec == nullptr || s.cg_exec_chunk != chunk || s.cg_exec_method != graph_key)) {
+        HIPCHK(capture_graph(s, &s.cg_exec, [&](hipStream_t q) { return enqueue_cg_chunk(s, run_method, chunk, q); }));
         s.cg_exec_chunk = chunk;
-        s.cg_exec_method = run_method;
+        s.cg_exec_method = graph_key;
     }
     // one chunk of iterations: a graph replay, or timed direct launches
     auto run_chunk = [&]() -> int {
@@ -705,7 +734,9 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         }
         for (int c = 0; c < chunk; ++c) {
             if (run_method == MIFVM_SOLVE_PLAIN) {
-                HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
+                HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] {
+                    return matrix_free ? launch_mf_cg_spmv(d, s.bc[1], hs) : launch_cg_spmv(d, hs);
+                }));
                 HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
                 HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
             } else {
@@ -717,7 +748,53 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         return MIFVM_OK;
     };
     int restarts = learned.restarts, outer = 0;
-    if (method == MIFVM_SOLVE_LEARNED && !learned.fell_back) {
+    if (method == MIFVM_SOLVE_FGMRES) {
+        const GmDev& g = *s.gm;
+        const BcTable& bcp = s.bc[1];
+        auto open = [&](bool fresh) -> int {
+            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&]() -> hipError_t {
+                if (matrix_free) {
+                    hipError_t e = launch_mf_apply(d, bcp, d.x, d.tmp, hs);
+                    if (e != hipSuccess) return e;
+                }
+                return launch_gm_open(d, g, matrix_free ? d.tmp : nullptr, tol, maxit, fresh, hs);
+            }));
+            return pull();
+        };
+        auto step_spmv = [&](int j, hipStream_t q) {
+            return matrix_free ? launch_mf_apply(d, bcp, g.Z + int64_t(j) * d.nc, g.V + int64_t(j + 1) * d.nc, q,
+                                                 d.scal + SC_DONE)
+                               : launch_gm_spmv(d, g, j, q);
+        };
+        auto enqueue_cycle = [&](hipStream_t q) -> hipError_t {
+            for (int j = 0; j < g.m; ++j) {
+                hipError_t e = step_spmv(j, q);
+                if (e == hipSuccess) e = launch_gm_orth(d, g, j, q);
+                if (e != hipSuccess) return e;
+            }
+            return launch_gm_close(d, g, q);
+        };
+        const int key = g.m + (matrix_free ? 1 << 20 : 0);
+        if (use_graph && (s.gm_exec == nullptr || s.gm_exec_key != key)) {
+            HIPCHK(capture_graph(s, &s.gm_exec, enqueue_cycle));
+            s.gm_exec_key = key;
+        }
+        if ((rc = open(true))) return rc;
+        while (hsc(s, 0, SC_DONE) == 0.0) {
+            if (use_graph) {
+                HIPCHK(hipGraphLaunch(s.gm_exec, hs));
+            } else {
+                for (int j = 0; j < g.m; ++j) {
+                    HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return step_spmv(j, hs); }));
+                    HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_gm_orth(d, g, j, hs); }));
+                }
+                HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_gm_close(d, g, hs); }));
+            }
+            ++outer;
+            if ((rc = open(false))) return rc;       // the true residual decides
+            if (hsc(s, 0, SC_DONE) == 0.0) ++restarts;
+        }
+    } else if (method == MIFVM_SOLVE_LEARNED && !learned.fell_back) {
         // the flexible CG ended: converged, or at maxit
     } else if (run_method == MIFVM_SOLVE_PLAIN) {
         HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, budget, restart, true, hs); }));
@@ -782,6 +859,38 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
     }
     if (!(rel <= tol)) return MIFVM_NOT_CONVERGED;
     return learned.fell_back ? MIFVM_FELL_BACK : MIFVM_OK;
+}
+
+int mifvm_fgmres_bytes(const mifvm_state* st, int32_t m, size_t* out) {
+    if (!st || !out) return fail(MIFVM_E_ARG, "null argument");
+    if (m < 1 || m > kGmMaxM) return fail(MIFVM_E_ARG, "m must be in [1, 64]");
+    GmDev probe{};
+    *out = gm_layout(st->s.d.nc, m, nullptr, probe);
+    return MIFVM_OK;
+}
+
+int mifvm_fgmres_attach(mifvm_state* st, int32_t m, void* d_ws, size_t ws_bytes) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    State& s = st->s;
+    if (s.gm_exec) (void)hipGraphExecDestroy(s.gm_exec);
+    s.gm_exec = nullptr;
+    if (!d_ws) {
+        delete s.gm;
+        s.gm = nullptr;
+        return MIFVM_OK;
+    }
+    if (s.d.nm != 1) return fail(MIFVM_E_ARG, "FGMRES needs a single-mesh state");
+    if (m < 1 || m > kGmMaxM) return fail(MIFVM_E_ARG, "m must be in [1, 64]");
+    if (reinterpret_cast<uintptr_t>(d_ws) & 255) return fail(MIFVM_E_WORKSPACE, "workspace not 256-byte aligned");
+    GmDev probe{};
+    const size_t need = gm_layout(s.d.nc, m, nullptr, probe);
+    if (ws_bytes < need) return fail(MIFVM_E_WORKSPACE, "workspace too small: need " + std::to_string(need));
+    auto* g = new (std::nothrow) GmDev();
+    if (!g) return fail(MIFVM_E_ARG, "out of host memory");
+    gm_layout(s.d.nc, m, static_cast<char*>(d_ws), *g);
+    delete s.gm;
+    s.gm = g;
+    return MIFVM_OK;
 }
 
 int mifvm_mesh_values(const mifvm_state* st, int32_t what, double* out, int32_t n) {

@@ -149,7 +149,7 @@ hipError_t fcg_forward(State& s, hipStream_t q, bool timing) {
 hipError_t enqueue_fcg_chunk(State& s, int n, hipStream_t q) {
     const Dev& d = s.d;
     for (int c = 0; c < n; ++c) {
-        hipError_t e = launch_cg_spmv(d, q);
+        hipError_t e = s.mf ? launch_mf_cg_spmv(d, s.bc[1], q) : launch_cg_spmv(d, q);
         if (e == hipSuccess) e = launch_fcg_axpy(d, *s.nn_state, q);
         if (e == hipSuccess) e = fcg_forward(s, q, false);
         if (e == hipSuccess) e = launch_fcg_beta(d, q);
@@ -177,9 +177,10 @@ int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int s
         HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_setup_tail(d, hs); }));
         return pull();
     };
-    if (use_graph && (s.fcg_exec == nullptr || s.fcg_exec_chunk != chunk)) {
+    const int graph_key = chunk + (s.mf ? 1 << 20 : 0);
+    if (use_graph && (s.fcg_exec == nullptr || s.fcg_exec_chunk != graph_key)) {
         HIPCHK(capture_graph(s, &s.fcg_exec, [&](hipStream_t q) { return enqueue_fcg_chunk(s, chunk, q); }));
-        s.fcg_exec_chunk = chunk;
+        s.fcg_exec_chunk = graph_key;
     }
     auto run_chunk = [&]() -> int {
         if (use_graph) {
@@ -187,7 +188,8 @@ int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int s
             return MIFVM_OK;
         }
         for (int c = 0; c < chunk; ++c) {
-            HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
+            HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs,
+                         [&] { return s.mf ? launch_mf_cg_spmv(d, s.bc[1], hs) : launch_cg_spmv(d, hs); }));
             HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_axpy(d, a, hs); }));
             HIPCHK(fcg_forward(s, hs, true));
             HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_beta(d, hs); }));

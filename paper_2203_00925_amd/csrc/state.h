@@ -66,6 +66,7 @@ struct Dev {
     float *u32, *un32, *src32, *phi32, *grad32, *psi32, *unode32, *flux32;
     float *minv32, *kAC32, *kBC32, *kRL32, *area32, *vol32, *n_alpha32, *fx32, *xc32, *gdist32;
     double* tmp;                          // nc+nb scratch (permutation, residual)
+    double *mf_xv, *mf_flux;              // matrix-free operator: vertex values [nv], face fluxes [nf]
     double* partial;                      // reduction partials ([k][block], k < 4)
     double* scal;                         // solver scalars, [nm][SC_COUNT_]
 };
@@ -81,6 +82,7 @@ constexpr int kNumKernels = 16;
 
 struct NnDev;
 struct NnStateDev;
+struct GmDev;
 
 // Event pairs around kernel launches, resolved into totals at sync points.
 struct KernelTimer {
@@ -122,6 +124,10 @@ struct State {
     const void* nn_handle = nullptr;
     NnStateDev* nn_state = nullptr;       // owned host record
     bool kt_ready = false;                // K^T values match K
+    bool mf = false;                      // the running solve applies K matrix-free
+    GmDev* gm = nullptr;                  // FGMRES workspace (owned host record)
+    hipGraphExec_t gm_exec = nullptr;     // one captured FGMRES cycle
+    int gm_exec_key = 0;
     bool b_ready = false;                 // d.b holds a right-hand side
     hipGraphExec_t fcg_exec = nullptr;    // one chunk of flexible-CG iterations
     int fcg_exec_chunk = 0;
@@ -156,6 +162,12 @@ hipError_t launch_cg_setup(const Dev& d, double tol, int maxit, int restart, boo
 hipError_t launch_cg_spmv(const Dev& d, hipStream_t s);
 hipError_t launch_cg_axpy(const Dev& d, hipStream_t s);
 hipError_t launch_cg_dir(const Dev& d, hipStream_t s);
+
+// launchers (mf_kernels.hip): y = K x from the discretisation (no stored matrix)
+// skip: a device flag; the product is skipped when it is non-zero (nullptr: never)
+hipError_t launch_mf_apply(const Dev& d, const BcTable& bc, const double* x, double* y, hipStream_t s,
+                           const double* skip = nullptr);
+hipError_t launch_mf_cg_spmv(const Dev& d, const BcTable& bc, hipStream_t s);
 
 // launchers (ir_kernels.hip): FP32 inner CG inside FP64 iterative refinement
 hipError_t launch_cast_matrix(const Dev& d, int64_t padded, hipStream_t s);

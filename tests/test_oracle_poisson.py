@@ -138,3 +138,48 @@ def test_cg_iterates_deterministic_prefix():
     z = b / K.diagonal()
     a = (b @ z) / (z @ (K @ z))
     assert np.allclose(h1[0], a * z, rtol=1e-14, atol=0)
+
+
+def test_fgmres_cycle_minimises_the_residual_over_its_search_space():
+    """After one cycle of k steps the iterate is the minimiser of |b - K x| over
+    x0 + span{Z}, with Z = D^-1 V the preconditioned Arnoldi vectors: brute
+    force by least squares on the explicit Krylov basis of (K D^-1, r0)."""
+    geo = cube_geometry(4, 3)
+    K, c = poisson.assemble(geo, [DIRICHLET] * 6, [0.0] * 6)
+    b = poisson.rhs(geo, synth.gaussian_field(cube(4, 3)), c)
+    dinv = 1.0 / K.diagonal()
+    x0 = np.random.default_rng(2).normal(size=geo.nc) * 1e-2
+    for k in (1, 3, 8):
+        hist = []
+        x, it, _ = poisson.jacobi_fgmres(K, b, x0=x0, tol=1e-300, m=k, maxit=k, history=hist)
+        assert it == k and len(hist) == 1
+        r0 = b - K @ x0
+        # Krylov basis of K D^-1 from r0, orthonormalised, mapped by D^-1
+        B_ = [r0]
+        for _ in range(k - 1):
+            B_.append(K @ (dinv * B_[-1]))
+        Q, _ = np.linalg.qr(np.array(B_).T)
+        Zs = dinv[:, None] * Q
+        y, *_ = np.linalg.lstsq(K @ Zs, r0, rcond=None)
+        xb = x0 + Zs @ y
+        assert np.linalg.norm(x - xb) <= 1e-8 * np.linalg.norm(xb)
+        assert np.linalg.norm(b - K @ x) <= np.linalg.norm(b - K @ xb) * (1 + 1e-10)
+
+
+def test_fgmres_converges_to_the_direct_solution():
+    geo = cube_geometry(6, 2)
+    K, c = poisson.assemble(geo, [DIRICHLET] * 6, [0.0] * 6)
+    b = poisson.rhs(geo, synth.gaussian_field(cube(6, 2)), c)
+    x, it, rel = poisson.jacobi_fgmres(K, b, tol=1e-10, m=30)
+    assert rel <= 1e-10 and it > 0
+    xd = poisson.direct_solve(K, b)
+    assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
+    # a flexible (varying) preconditioner still converges to the same point
+    calls = [0]
+
+    def varying(v):
+        calls[0] += 1
+        return (1.0 + 0.5 * np.sin(calls[0])) * (v / K.diagonal())
+    x2, _, rel2 = poisson.jacobi_fgmres(K, b, tol=1e-10, m=30, precond=varying)
+    assert rel2 <= 1e-10
+    assert np.linalg.norm(x2 - xd) <= 1e-7 * np.linalg.norm(xd)
