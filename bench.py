@@ -4,7 +4,8 @@
 One step = one 3-stage Runge-Kutta finite-volume step of the convection-
 diffusion problem followed by one Poisson solve (Jacobi-CG to 1e-10 relative
 true residual, warm-started from the previous solution, right-hand side =
-the transported scalar), on a synthetic jittered-tetrahedron unit cube:
+the transported scalar; the operator applied matrix-free, the stored-matrix
+CG is reported beside it), on a synthetic jittered-tetrahedron unit cube:
 
   cube120 (default): 120^3 hexes x 6 tets = 10,368,000 cells, seed 2
   cube20:             20^3 hexes x 6 tets =     48,000 cells, seed 1
@@ -32,24 +33,24 @@ sys.path.insert(0, ROOT)
 METRIC = "FV cell-updates/s + Poisson solve ms @1e-10 rel; plain vs mixed/learned"
 
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE + WRITE_SIZE on the
-# cube120 workload, scaled by a known-size copy (profiles/all_kernels_cube120_
-# hbm_traffic.md).  Valid only for the kernel sources they were taken on: the
-# bench reports them when the sources still hash to `src`, else null.
-MEASURED_TRAFFIC = {
-    "cube120": {"src": "7c50cf207300467d",
-                "bytes": {"k_grad_limiter": 7057313400, "k_face_flux": 3292082502,
-                          "k_update": 923862782, "k_cg_spmv": 8384813319,
-                          "k_cg_axpy": 666175430, "k_cg_dir": 248850625}},
+# cube120 workload, scaled by a known-size copy (profiles/*_hbm_traffic.md).
+# Each is valid only for the kernel source it was taken on: the bench reports
+# it when that source (the kernel's file and the reduction headers) still
+# hashes to the recorded prefix, else null.
+MEASURED_TRAFFIC = {"cube120": {}}
+KERNEL_FILES = {
+    "grad_limiter": "fv_kernels.hip", "face_flux": "fv_kernels.hip", "update": "fv_kernels.hip",
+    "cg_spmv": "solve_kernels.hip", "cg_axpy": "solve_kernels.hip", "cg_dir": "solve_kernels.hip",
+    "mf_vertex": "mf_kernels.hip", "mf_face": "mf_kernels.hip", "mf_gather": "mf_kernels.hip",
 }
 
 
-def kernel_source_hash():
-    import glob
+def kernel_source_hash(name):
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2203_00925_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for f in (KERNEL_FILES[name], "reduce.h", "seg.h", "cg_scalars.h"):
+        with open(os.path.join(ROOT, "paper_2203_00925_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 HBM_PEAK_GBS = 8000.0
@@ -91,6 +92,14 @@ def algorithmic_bytes(info):
         "cg_axpy": nc * 64,
         # z,p read, p written
         "cg_dir": nc * 24,
+        # matrix-free product: vertex lists (weight 8 + index 4 per entry), x
+        # gathered once, ghost owner + tag, vertex values written
+        "mf_vertex": info.node_entries * 12 + nc * 8 + nb * 8 + nv * 8,
+        # per face: L,R,A,B,C 20 + kAC,kBC,kRL 24 + F written 8; x and vertex
+        # values gathered once; ghost tags
+        "mf_face": nf * 52 + nc * 8 + nv * 8 + nb * 4,
+        # per cell: cell->face 16, p read 8, q written 8; F gathered once
+        "mf_gather": nc * 32 + nf * 8,
     }
 
 
@@ -196,7 +205,7 @@ def main():
         st.step(1, dt)
         if evs is not None:
             evs[1].record(stream)
-        info_s = st.poisson_solve(None, tol=1e-10, restart=500)
+        info_s = st.poisson_solve(None, tol=1e-10, restart=500, matrix_free=True)
         if evs is not None:
             evs[2].record(stream)
         return info_s
@@ -225,14 +234,14 @@ def main():
     value = info.nc * args.steps / fv_total_s
     nbytes = algorithmic_bytes(info)
 
-    measured = MEASURED_TRAFFIC.get(args.workload)
-    traffic_ok = measured is not None and measured["src"] == kernel_source_hash()
+    measured = MEASURED_TRAFFIC.get(args.workload, {})
 
     def roof(name):
         ms, n = kstats[name]
         avg_s = ms / max(n, 1) / 1e3
         gbs = nbytes[name] / avg_s / 1e9
-        traffic = measured["bytes"].get(f"k_{name}") if traffic_ok else None
+        rec = measured.get(f"k_{name}")
+        traffic = rec["bytes"] if rec and rec["src"] == kernel_source_hash(name) else None
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": f"k_{name}",
                 "avg_us": round(avg_s * 1e6, 2), "launches": n,
@@ -263,9 +272,11 @@ def main():
         "poisson_iterations": iters,
         "poisson_rel_residual": max(s["rel_residual"] for s in solves),
         "conservation_rel_drift": abs(total1 - total0) / abs(total0),
-        "roofline": roof("cg_spmv"),
+        # the kernel with the most GPU time in the timed region
+        "roofline": roof(max(("mf_vertex", "mf_face", "mf_gather", "cg_axpy", "cg_dir", "grad_limiter"),
+                             key=lambda k: kstats[k][0])),
         "roofline_fv": {k: roof(k) for k in ("grad_limiter", "face_flux", "update")},
-        "roofline_cg": {k: roof(k) for k in ("cg_axpy", "cg_dir")},
+        "roofline_cg": {k: roof(k) for k in ("mf_vertex", "mf_face", "mf_gather", "cg_axpy", "cg_dir")},
     }
     if not args.no_forms:
         u64 = st.get_field(B.FIELD_U)
@@ -274,6 +285,18 @@ def main():
         del st
         torch.cuda.empty_cache()
         result["forms"] = {"fp32_refined": run_fp32_form(args, M, pf, u64, p64)}
+        torch.cuda.empty_cache()
+        plain_ms = sum(solve_ms) / len(solve_ms)
+        result["forms"]["stored_matrix_cg"] = run_solver_form(
+            args, M, pf, "Jacobi-CG on the stored matrix", dict(matrix_free=False), plain_ms, p64)
+        form_cg = result["forms"]["stored_matrix_cg"]
+        form_cg["roofline_cg_spmv"] = {
+            "bytes_per_launch": nbytes["cg_spmv"], "avg_us": form_cg["kernel_avg_ms"]["cg_spmv"] * 1e3,
+            "achieved_GBps": round(nbytes["cg_spmv"] / (form_cg["kernel_avg_ms"]["cg_spmv"] * 1e-3) / 1e9, 1)}
+        torch.cuda.empty_cache()
+        result["forms"]["fgmres30"] = run_solver_form(
+            args, M, pf, "FGMRES(30) + Jacobi, matrix-free", dict(method=B.SOLVE_FGMRES, matrix_free=True),
+            plain_ms, p64, fgmres_m=30)
         torch.cuda.empty_cache()
         result["forms"]["learned"] = run_learned_form(args, M, pf, iters, solve_ms)
     if not args.no_cpu_baseline:
@@ -330,6 +353,56 @@ def run_fp32_form(args, M, pf, u64, p64):
             "u_max_rel_err_vs_fp64": uerr, "P_rel_err_vs_fp64": perr,
             "dtype": "f32 step; f32 inner CG with f64 residual, dots and refinement"}
 
+
+
+def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0):
+    """The FP64 run's steps with another solver of the same system: solve time
+    and iterations per step, the solution's difference from the plain run's,
+    and one cold solve (P = 0)."""
+    import numpy as np
+    import torch
+    from paper_2203_00925_amd import binding as B
+    st = B.State(M, diffusivity=pf.diffusivity)
+    st.set_bcs(B.VAR_SCALAR, [B.ZERO_FLUX] * 6)
+    st.set_bcs(B.VAR_POTENTIAL, [B.DIRICHLET] * 6)
+    st.set_field(B.FIELD_VEL, torch.from_numpy(np.ascontiguousarray(pf.vel.T.ravel())))
+    st.set_field(B.FIELD_U, torch.from_numpy(pf.u0))
+    st.poisson_assemble()
+    if fgmres_m:
+        st.fgmres_attach(fgmres_m)
+    dt = st.cfl_dt(pf.cfl)
+    kw = dict(tol=1e-10, restart=500, **solve_kw)
+    cold = st.poisson_solve(None, **kw)
+    st.set_field(B.FIELD_P, torch.zeros(M.info.nc, dtype=torch.float64, device="cuda"))
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        st.step(1, dt)
+        st.poisson_solve(None, **kw)
+    torch.cuda.synchronize()
+    st.kernel_timing(True)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    solves = []
+    for k in range(args.steps):
+        st.step(1, dt)
+        ev[k][0].record(stream)
+        solves.append(st.poisson_solve(None, **kw))
+        ev[k][1].record(stream)
+        log(f"{name} step {k}: {solves[-1]['iterations']} it, rel {solves[-1]['rel_residual']:.2e}")
+    torch.cuda.synchronize()
+    kstats = st.kernel_stats()
+    st.kernel_timing(False)
+    p = st.get_field(B.FIELD_P)
+    torch.cuda.synchronize()
+    ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    perr = float((p - p64).norm() / p64.norm())
+    del st
+    return {"solver": name, "poisson_solve_ms": ms, "speedup_vs_main_solve": plain_ms / ms,
+            "poisson_iterations": [s["iterations"] for s in solves],
+            "poisson_rel_residual": max(s["rel_residual"] for s in solves),
+            "P_rel_diff_vs_plain_run": perr,
+            "cold": {"iterations": cold["iterations"], "ms": cold["ms"]},
+            "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kstats.items() if v[1]},
+            "dtype": "f64"}
 
 
 # Learned-preconditioner form: training data from config-1-style runs on
@@ -412,15 +485,22 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
     st.poisson_assemble()
     net.attach(st)
     dt = st.cfl_dt(pf.cfl)
-    kw = dict(tol=1e-10, restart=500, method=B.SOLVE_LEARNED, allow_fell_back=True)
+    kw = dict(tol=1e-10, restart=500, method=B.SOLVE_LEARNED, allow_fell_back=True, matrix_free=True)
+    kw_csr = dict(kw, matrix_free=False)
     # cold solves of the initial right-hand side, both methods
     zero = torch.zeros(M.info.nc, dtype=torch.float64, device="cuda")
     st.set_field(B.FIELD_P, zero)
-    cold_plain = st.poisson_solve(None, tol=1e-10, restart=500)
+    cold_plain = st.poisson_solve(None, tol=1e-10, restart=500, matrix_free=True)
     st.set_field(B.FIELD_P, zero)
     cold = st.poisson_solve(None, **kw)
     log(f"learned: cold solve {cold['iterations']} it {cold['ms']:.0f} ms vs Jacobi-CG "
-        f"{cold_plain['iterations']} it {cold_plain['ms']:.0f} ms")
+        f"{cold_plain['iterations']} it {cold_plain['ms']:.0f} ms (matrix-free product)")
+    st.set_field(B.FIELD_P, zero)
+    cold_csr = st.poisson_solve(None, **kw_csr)
+    st.set_field(B.FIELD_P, zero)
+    cold_plain_csr = st.poisson_solve(None, tol=1e-10, restart=500)
+    log(f"learned, stored matrix: cold solve {cold_csr['iterations']} it {cold_csr['ms']:.0f} ms vs "
+        f"Jacobi-CG {cold_plain_csr['iterations']} it {cold_plain_csr['ms']:.0f} ms")
     st.set_field(B.FIELD_P, zero)
     stream = torch.cuda.current_stream()
     for w in range(args.warmup):
@@ -442,8 +522,7 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
     st.kernel_timing(False)
     solve_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
     plain_ms = sum(plain_solve_ms) / len(plain_solve_ms)
-    layer_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in kstats.items()
-                if k.startswith("nn_") or k in ("cg_spmv", "fcg_vec")}
+    layer_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in kstats.items() if v[1]}
     del st
     return {"poisson_solve_ms": solve_ms,
             "poisson_iterations": [s["iterations"] for s in solves],
@@ -452,7 +531,10 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
             "speedup_vs_jacobi_cg": plain_ms / solve_ms,
             "jacobi_cg_iterations": plain_iters, "jacobi_cg_solve_ms": plain_ms,
             "cold": {"learned_iterations": cold["iterations"], "learned_ms": cold["ms"],
-                     "jacobi_cg_iterations": cold_plain["iterations"], "jacobi_cg_ms": cold_plain["ms"]},
+                     "jacobi_cg_iterations": cold_plain["iterations"], "jacobi_cg_ms": cold_plain["ms"],
+                     "stored_matrix": {"learned_iterations": cold_csr["iterations"], "learned_ms": cold_csr["ms"],
+                                       "jacobi_cg_iterations": cold_plain_csr["iterations"],
+                                       "jacobi_cg_ms": cold_plain_csr["ms"]}},
             "kernel_avg_ms": layer_ms,
             "training": {"meshes_n": list(LEARNED["train_n"]), "samples": LEARNED["samples"],
                          "epochs": LEARNED["epochs"], "loss": "residual",

@@ -338,7 +338,9 @@ enum mifvm_kernel {
     (the first includes the encoder, the last the decoder) */,
     MIFVM_K_FCG_VEC = 14 /* flexible-CG update and its scalar steps */,
     MIFVM_K_NN_TRAIN = 15 /* one whole training step (all of its launches) */,
-    MIFVM_K_COUNT = 16
+    MIFVM_K_MF_VERTEX = 16, MIFVM_K_MF_FACE = 17, MIFVM_K_MF_GATHER = 18 /* the matrix-free
+    product inside the CG (timed one by one; CG_SPMV then counts the stored-matrix product) */,
+    MIFVM_K_COUNT = 19
 };
 int mifvm_kernel_timing(mifvm_state* st, int32_t enable);
 /* Total milliseconds and number of timed launches of one kernel since the

@@ -25,7 +25,7 @@ SOLVE_PLAIN, SOLVE_IR_FP32, SOLVE_LEARNED, SOLVE_FGMRES = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
            "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble", "nn_layer1", "nn_layer2", "nn_layer3",
-           "fcg_vec", "nn_train")
+           "fcg_vec", "nn_train", "mf_vertex", "mf_face", "mf_gather")
 NN_PARAMS = 9537
 LOSS_RESIDUAL, LOSS_ENERGY = 0, 1
 

@@ -20,8 +20,21 @@
 namespace mifvm {
 namespace {
 
-__device__ inline int64_t gtid_m() { return int64_t(blockIdx.x) * blockDim.x + threadIdx.x; }
-inline unsigned rows_m(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+// Blocks are dealt to the 8 XCDs in turn, and each XCD has its own L2.  The
+// grid is padded to a multiple of 8 and block b works on logical block
+// (b % 8) * (grid / 8) + b / 8, so each XCD takes one contiguous eighth of
+// the rows: the neighbour data that consecutive blocks share (vertex lists
+// reading nearby cells, faces reading nearby vertices) then stays in one L2.
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block() {
+    const int64_t per = gridDim.x / kXcds;
+    return int64_t(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+__device__ inline int64_t gtid_m() { return xcd_block() * blockDim.x + threadIdx.x; }
+inline unsigned rows_m(int64_t n) {
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return unsigned((b + kXcds - 1) / kXcds * kXcds);
+}
 
 // x of a cell, or of a ghost entity (homogeneous ghost value)
 __device__ inline double xval(const Dev& d, const BcTable& bc, const double* __restrict__ x, int e) {
@@ -89,18 +102,21 @@ __global__ __launch_bounds__(kBlock) void k_mf_gather(Dev d, const double* __res
 
 // q = K p through F, and the partial p.q (the matrix-free counterpart of
 // k_cg_spmv; rows of finished meshes are left untouched)
-__global__ __launch_bounds__(kBlock) void k_mf_cg_gather(Dev d, const double* __restrict__ F) {
+// (partial slots by logical block; padding blocks past the rows return)
+__global__ __launch_bounds__(kBlock) void k_mf_cg_gather(Dev d, const double* __restrict__ F, int64_t nblk) {
     __shared__ double lds[4];
-    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    const int64_t lb = xcd_block();
+    if (lb >= nblk) return;
+    const BlockSeg g = block_seg(d, lb * kBlock, kBlock);
     if (block_done(d, g)) return;
-    const int64_t i = gtid_m();
+    const int64_t i = lb * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (i < d.nc && msc(d, row_mesh(g, i))[SC_DONE] == 0.0) {
         const double y = gather_row(d, F, i);
         d.q[i] = y;
         v[0] = d.p[i] * y;
     }
-    seg_publish<1>(d, g, v, i >= g.split, lds);
+    seg_publish_at<1>(d, g, v, i >= g.split, lds, lb, nblk);
 }
 
 }  // namespace
@@ -113,14 +129,24 @@ hipError_t launch_mf_apply(const Dev& d, const BcTable& bc, const double* x, dou
     return hipGetLastError();
 }
 
-hipError_t launch_mf_cg_spmv(const Dev& d, const BcTable& bc, hipStream_t s) {
+hipError_t launch_mf_cg_part(const Dev& d, const BcTable& bc, int part, hipStream_t s) {
     const double* none = nullptr;
-    hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv)), dim3(kBlock), 0, s, d, bc, d.p, d.mf_xv, none);
-    hipLaunchKernelGGL(k_mf_face, dim3(rows_m(d.nf)), dim3(kBlock), 0, s, d, bc, d.p, d.mf_xv, d.mf_flux, none);
-    const unsigned nb = rows_m(d.nc);
-    hipLaunchKernelGGL(k_mf_cg_gather, dim3(nb), dim3(kBlock), 0, s, d, d.mf_flux);
-    hipLaunchKernelGGL(k_cg_alpha<1>, dim3(d.nm), dim3(1024), 0, s, d, int64_t(nb), int64_t(kBlock));
+    if (part == 0) {
+        hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv)), dim3(kBlock), 0, s, d, bc, d.p, d.mf_xv, none);
+    } else if (part == 1) {
+        hipLaunchKernelGGL(k_mf_face, dim3(rows_m(d.nf)), dim3(kBlock), 0, s, d, bc, d.p, d.mf_xv, d.mf_flux, none);
+    } else {
+        const int64_t nblk = (d.nc + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_mf_cg_gather, dim3(rows_m(d.nc)), dim3(kBlock), 0, s, d, d.mf_flux, nblk);
+        hipLaunchKernelGGL(k_cg_alpha<1>, dim3(d.nm), dim3(1024), 0, s, d, nblk, int64_t(kBlock));
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_mf_cg_spmv(const Dev& d, const BcTable& bc, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int part = 0; part < 3 && e == hipSuccess; ++part) e = launch_mf_cg_part(d, bc, part, s);
+    return e;
 }
 
 }  // namespace mifvm

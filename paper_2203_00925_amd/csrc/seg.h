@@ -65,6 +65,23 @@ __device__ inline void seg_publish(const Dev& d, const BlockSeg& g, const double
     }
 }
 
+// As seg_publish, for a block that works on logical block `lb` of `nblk`
+// (a kernel whose block order is permuted).
+template <int K>
+__device__ inline void seg_publish_at(const Dev& d, const BlockSeg& g, const double (&v)[K], bool second,
+                                      double* lds, int64_t lb, int64_t nblk) {
+    const bool two = g.m1 != g.m0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double s0 = block_sum_upto256(second ? 0.0 : v[k], lds);
+        const double s1 = two ? block_sum_upto256(second ? v[k] : 0.0, lds) : 0.0;
+        if (threadIdx.x == 0) {
+            d.partial[(2 * k) * nblk + lb] = s0;
+            d.partial[(2 * k + 1) * nblk + lb] = s1;
+        }
+    }
+}
+
 // In the finalize kernel (one 1024-thread block per mesh, blockIdx.x = m):
 // the sum of partial k of mesh m, produced by a kernel of nblk blocks of B
 // rows, added in block order.

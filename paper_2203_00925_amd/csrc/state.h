@@ -78,7 +78,7 @@ struct FvArrays {
     const R *phi, *minv, *kAC, *kBC, *kRL, *area, *vol, *src, *n_alpha, *fx, *xc, *gdist;
 };
 
-constexpr int kNumKernels = 16;
+constexpr int kNumKernels = 19;
 
 struct NnDev;
 struct NnStateDev;
@@ -168,6 +168,9 @@ hipError_t launch_cg_dir(const Dev& d, hipStream_t s);
 hipError_t launch_mf_apply(const Dev& d, const BcTable& bc, const double* x, double* y, hipStream_t s,
                            const double* skip = nullptr);
 hipError_t launch_mf_cg_spmv(const Dev& d, const BcTable& bc, hipStream_t s);
+// the three launches of launch_mf_cg_spmv one by one (part 0 vertex values,
+// 1 face fluxes, 2 gather + p.q + alpha), for per-kernel timing
+hipError_t launch_mf_cg_part(const Dev& d, const BcTable& bc, int part, hipStream_t s);
 
 // launchers (ir_kernels.hip): FP32 inner CG inside FP64 iterative refinement
 hipError_t launch_cast_matrix(const Dev& d, int64_t padded, hipStream_t s);
