@@ -37,7 +37,16 @@ METRIC = "FV cell-updates/s + Poisson solve ms @1e-10 rel; plain vs mixed/learne
 # Each is valid only for the kernel source it was taken on: the bench reports
 # it when that source (the kernel's file and the reduction headers) still
 # hashes to the recorded prefix, else null.
-MEASURED_TRAFFIC = {"cube120": {}}
+MEASURED_TRAFFIC = {"cube120": {
+    "k_mf_vertex": {"src": "b5f76a30cd9b4bad", "bytes": 822086279},
+    "k_mf_face": {"src": "b5f76a30cd9b4bad", "bytes": 1213714645},
+    "k_mf_gather": {"src": "b5f76a30cd9b4bad", "bytes": 499294043},
+    "k_cg_axpy": {"src": "c9fadcf340e762ae", "bytes": 645980149},
+    "k_cg_dir": {"src": "c9fadcf340e762ae", "bytes": 239732901},
+    "k_grad_limiter": {"src": "988d408fd4465bd2", "bytes": 6989907666},
+    "k_face_flux": {"src": "988d408fd4465bd2", "bytes": 3273348809},
+    "k_update": {"src": "988d408fd4465bd2", "bytes": 923241987},
+}}
 KERNEL_FILES = {
     "grad_limiter": "fv_kernels.hip", "face_flux": "fv_kernels.hip", "update": "fv_kernels.hip",
     "cg_spmv": "solve_kernels.hip", "cg_axpy": "solve_kernels.hip", "cg_dir": "solve_kernels.hip",
