@@ -123,6 +123,7 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.tmp = carve<double>(base, off, 3 * NX);
     d.mf_xv = carve<double>(base, off, nv);
     d.mf_flux = carve<double>(base, off, nf);
+    d.mf_xg = carve<double>(base, off, nb > 0 ? nb : 1);
     // per-block partials of up to 4 sums x 2 mesh slots, for blocks of >= 64 rows
     const int64_t nblk = (nc + 63) / 64;
     d.partial = carve<double>(base, off, 8 * (nblk + 1024));

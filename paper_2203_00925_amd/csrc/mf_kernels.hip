@@ -36,27 +36,45 @@ inline unsigned rows_m(int64_t n) {
     return unsigned((b + kXcds - 1) / kXcds * kXcds);
 }
 
-// x of a cell, or of a ghost entity (homogeneous ghost value)
-__device__ inline double xval(const Dev& d, const BcTable& bc, const double* __restrict__ x, int e) {
-    if (e < d.nc) return x[e];
-    const int g = e - int(d.nc);
-    const double s = bc.kind[d.gtag[g]] == kDirichlet ? -1.0 : 1.0;
-    return s * x[d.gowner[g]];
+// ghost values of x (homogeneous part): xg[g] = s_g x_owner
+__global__ __launch_bounds__(kBlock) void k_mf_ghost(Dev d, BcTable bc, const double* __restrict__ x,
+                                                     double* __restrict__ xg, const double* skip) {
+    if (skip && *skip != 0.0) return;
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= d.nb) return;
+    const double sg = bc.kind[d.gtag[g]] == kDirichlet ? -1.0 : 1.0;
+    xg[g] = sg * x[d.gowner[g]];
 }
 
-__global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, BcTable bc, const double* __restrict__ x,
-                                                      double* __restrict__ xv, const double* skip) {
+// x_v = sum alpha x_e over the vertex list; a cell reads x, a ghost xg.  The
+// entries go in batches of 8: the weight and index loads of a batch first,
+// then its gathers, so 8 gathers are in flight per thread.
+__global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const double* __restrict__ x,
+                                                      const double* __restrict__ xg, double* __restrict__ xv,
+                                                      const double* skip) {
     if (skip && *skip != 0.0) return;
     const int64_t v = gtid_m();
     if (v >= d.nv) return;
     const int64_t sl = v >> 6;
     const int64_t base = d.n_off[sl] + (v & 63);
     const int w = d.n_w[sl];
+    const int nc = int(d.nc);
     double s = 0.0;
-    for (int k = 0; k < w; ++k) {
-        const int64_t at = base + int64_t(k) * 64;
-        const double al = d.n_alpha[at];             // padding entries carry 0
-        if (al != 0.0) s += al * xval(d, bc, x, d.n_idx[at]);
+    for (int k0 = 0; k0 < w; k0 += 8) {
+        int e[8];
+        double al[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool in = k0 + j < w;
+            const int64_t at = base + int64_t(k0 + j) * 64;
+            e[j] = in ? d.n_idx[at] : 0;                 // padding entries carry weight 0
+            al[j] = in ? d.n_alpha[at] : 0.0;
+        }
+        double xe[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xe[j] = e[j] < nc ? x[e[j]] : xg[e[j] - nc];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += al[j] * xe[j];
     }
     xv[v] = s;
 }
@@ -123,7 +141,9 @@ __global__ __launch_bounds__(kBlock) void k_mf_cg_gather(Dev d, const double* __
 
 hipError_t launch_mf_apply(const Dev& d, const BcTable& bc, const double* x, double* y, hipStream_t s,
                            const double* skip) {
-    hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv)), dim3(kBlock), 0, s, d, bc, x, d.mf_xv, skip);
+    hipLaunchKernelGGL(k_mf_ghost, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d, bc, x,
+                       d.mf_xg, skip);
+    hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv)), dim3(kBlock), 0, s, d, x, d.mf_xg, d.mf_xv, skip);
     hipLaunchKernelGGL(k_mf_face, dim3(rows_m(d.nf)), dim3(kBlock), 0, s, d, bc, x, d.mf_xv, d.mf_flux, skip);
     hipLaunchKernelGGL(k_mf_gather, dim3(rows_m(d.nc)), dim3(kBlock), 0, s, d, d.mf_flux, y, skip);
     return hipGetLastError();
@@ -132,7 +152,9 @@ hipError_t launch_mf_apply(const Dev& d, const BcTable& bc, const double* x, dou
 hipError_t launch_mf_cg_part(const Dev& d, const BcTable& bc, int part, hipStream_t s) {
     const double* none = nullptr;
     if (part == 0) {
-        hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv)), dim3(kBlock), 0, s, d, bc, d.p, d.mf_xv, none);
+        hipLaunchKernelGGL(k_mf_ghost, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d, bc, d.p,
+                           d.mf_xg, none);
+        hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv)), dim3(kBlock), 0, s, d, d.p, d.mf_xg, d.mf_xv, none);
     } else if (part == 1) {
         hipLaunchKernelGGL(k_mf_face, dim3(rows_m(d.nf)), dim3(kBlock), 0, s, d, bc, d.p, d.mf_xv, d.mf_flux, none);
     } else {

@@ -66,7 +66,8 @@ struct Dev {
     float *u32, *un32, *src32, *phi32, *grad32, *psi32, *unode32, *flux32;
     float *minv32, *kAC32, *kBC32, *kRL32, *area32, *vol32, *n_alpha32, *fx32, *xc32, *gdist32;
     double* tmp;                          // nc+nb scratch (permutation, residual)
-    double *mf_xv, *mf_flux;              // matrix-free operator: vertex values [nv], face fluxes [nf]
+    double *mf_xv, *mf_flux, *mf_xg;      // matrix-free operator: vertex values [nv], face fluxes [nf],
+                                          // ghost values [nb]
     double* partial;                      // reduction partials ([k][block], k < 4)
     double* scal;                         // solver scalars, [nm][SC_COUNT_]
 };
