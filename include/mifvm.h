@@ -107,7 +107,7 @@ typedef struct {
     int32_t row_max;           /* longest off-diagonal matrix row             */
     int32_t tile_rows;         /* cells per LDS tile (256, 128 or 64)         */
     int32_t halo_max;          /* largest tile halo (cells + ghosts)          */
-    int32_t pad_;
+    int32_t tile_vertices_max; /* most vertices the cells of one tile touch   */
     int64_t halo_entries;      /* sum of tile halo sizes                      */
     size_t ws_bytes;           /* device workspace needed by a state          */
 } mifvm_mesh_info;

@@ -69,7 +69,7 @@ class MeshInfo(C.Structure):
                 ("node_entries", C.c_int64), ("matrix_nnz", C.c_int64),
                 ("matrix_padded", C.c_int64), ("stencil_max", C.c_int32),
                 ("node_max", C.c_int32), ("row_max", C.c_int32), ("tile_rows", C.c_int32),
-                ("halo_max", C.c_int32), ("pad_", C.c_int32), ("halo_entries", C.c_int64),
+                ("halo_max", C.c_int32), ("tile_vertices_max", C.c_int32), ("halo_entries", C.c_int64),
                 ("ws_bytes", C.c_size_t)]
 
 

@@ -58,6 +58,17 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.n_w = carve<int32_t>(base, off, m.node.width.size());
     d.n_idx = carve<int32_t>(base, off, m.node.idx.size());
     d.n_alpha = carve<double>(base, off, m.node.val.size());
+    d.n_len = carve<int32_t>(base, off, nv);
+    d.tv_max = m.tv_max;
+    d.e_off = carve<int64_t>(base, off, m.enbr.off.size());
+    d.e_w = carve<int32_t>(base, off, m.enbr.width.size());
+    d.e_lidx = carve<uint16_t>(base, off, m.e_lidx.size() > 0 ? m.e_lidx.size() : 1);
+    d.c2v_l = carve<uint16_t>(base, off, 4 * nc);
+    d.fv_off = carve<int64_t>(base, off, m.fv_off.size());
+    d.fv_len = carve<int32_t>(base, off, m.fv_len.size() > 0 ? m.fv_len.size() : 1);
+    d.f_off = carve<int64_t>(base, off, m.fnode.off.size());
+    d.f_w = carve<int32_t>(base, off, m.fnode.width.size() > 0 ? m.fnode.width.size() : 1);
+    d.f_lidx = carve<uint16_t>(base, off, m.f_lidx.size() > 0 ? m.f_lidx.size() : 1);
     d.k_off = carve<int64_t>(base, off, m.kmat.off.size());
     d.k_w = carve<int32_t>(base, off, m.kmat.width.size());
     d.k_col = carve<int32_t>(base, off, m.kmat.idx.size());
@@ -200,6 +211,7 @@ int mifvm_mesh_get_info(const mifvm_mesh* mesh, mifvm_mesh_info* out) {
     out->row_max = m.row_max;
     out->tile_rows = m.tile_rows;
     out->halo_max = m.halo_max;
+    out->tile_vertices_max = m.tv_max;
     out->halo_entries = (int64_t)m.h_idx.size();
     Dev d{};
     out->ws_bytes = layout(m, nullptr, d);
@@ -293,6 +305,9 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     UP(d.kAC, m.kAC); UP(d.kBC, m.kBC); UP(d.kRL, m.kRL); UP(d.fx, m.fx); UP(d.S, m.S); UP(d.area, m.area);
     UP(d.gowner, m.gowner); UP(d.gtag, m.gtag); UP(d.gdist, m.gdist);
     UP(d.n_off, m.node.off); UP(d.n_w, m.node.width); UP(d.n_idx, m.node.idx); UP(d.n_alpha, m.node.val);
+    UP(d.n_len, m.n_len); UP(d.e_off, m.enbr.off); UP(d.e_w, m.enbr.width); UP(d.e_lidx, m.e_lidx);
+    UP(d.c2v_l, m.c2v_l); UP(d.fv_off, m.fv_off); UP(d.fv_len, m.fv_len);
+    UP(d.f_off, m.fnode.off); UP(d.f_w, m.fnode.width); UP(d.f_lidx, m.f_lidx);
     UP(d.k_off, m.kmat.off); UP(d.k_w, m.kmat.width); UP(d.k_col, m.kmat.idx); UP(d.k_len, m.klen);
     UP(d.cell_perm, m.cell_perm); UP(d.vert_perm, m.vert_perm);
     UP(d.h_off, m.h_off); UP(d.h_idx, m.h_idx); UP(d.h_self, m.h_self);
@@ -331,6 +346,7 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     if (e == hipSuccess) e = hipMemsetAsync(d.u32, 0, NX * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.src32, 0, m.nc * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.phi32, 0, m.nf * sizeof(float), s);
+    if (e == hipSuccess) e = setup_fv_kernels(d);
     if (e == hipSuccess) e = launch_make_fp32_geometry(d, (int64_t)m.node.val.size(), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // host vectors are not pinned
     if (e != hipSuccess) return cleanup(hip_fail(e, "state init"));

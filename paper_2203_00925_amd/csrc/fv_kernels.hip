@@ -29,6 +29,7 @@
 #include "reduce.h"
 #include "seg.h"
 #include "state.h"
+#include "xcd.h"
 
 namespace mifvm {
 
@@ -61,6 +62,31 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(int64_t nc, int64_t nb,
     u[nc + g] = ug;
 }
 
+// Stage tile t's halo in LDS as (x, y, z, u) records (positions relative to
+// `ref`): all index loads of a thread first, then all gathers.
+template <class R, class V4>
+__device__ inline void stage_halo(const Dev& d, const R* __restrict__ u, V4* sm, int64_t t, double4 ref) {
+    const int T = blockDim.x;
+    const int64_t h0 = d.h_off[t];
+    const int hn = int(d.h_off[t + 1] - h0);
+    const double4* __restrict__ P = d.xyz4;
+    for (int hb = 0; hb < hn; hb += 8 * T) {
+        int e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int h = hb + j * T + threadIdx.x;
+            e[j] = h < hn ? d.h_idx[h0 + h] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (e[j] >= 0) {
+                const double4 r = P[e[j]];
+                sm[hb + j * T + threadIdx.x] = mk4(R(r.x - ref.x), R(r.y - ref.y), R(r.z - ref.z), u[e[j]]);
+            }
+        }
+    }
+}
+
 // One block per tile of d.tile_rows cells.  The tile's halo (every cell and
 // ghost its stencils reference) is staged in LDS as (x, y, z, u) records, so
 // the ~70 neighbour reads per cell are LDS reads addressed by 16-bit local
@@ -77,28 +103,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d, FvArrays<R> a) {
     const int64_t nc = d.nc;
     const int64_t t = blockIdx.x;
     const int T = blockDim.x;
-    const int64_t h0 = d.h_off[t];
-    const int hn = int(d.h_off[t + 1] - h0);
-    const R* __restrict__ u = a.u;
     const double4* __restrict__ P = d.xyz4;
     // positions relative to the tile's first cell in the FP32 form
     const double4 ref = rel ? P[t * T] : make_double4(0.0, 0.0, 0.0, 0.0);
-    // stage the halo: all index loads of a thread first, then all gathers
-    for (int hb = 0; hb < hn; hb += 8 * T) {
-        int e[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int h = hb + j * T + threadIdx.x;
-            e[j] = h < hn ? d.h_idx[h0 + h] : -1;
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (e[j] >= 0) {
-                const double4 r = P[e[j]];
-                sm[hb + j * T + threadIdx.x] = mk4(R(r.x - ref.x), R(r.y - ref.y), R(r.z - ref.z), u[e[j]]);
-            }
-        }
-    }
+    stage_halo<R>(d, a.u, sm, t, ref);
     __syncthreads();
 
     // vertex values (Algorithm 2) of the tile's vertices, spread over the waves
@@ -181,6 +189,200 @@ __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d, FvArrays<R> a) {
     for (int k = 0; k < 4; ++k) {
         const double4 xf = d.fx4[fc[k]];
         const R dl = gx * (R(xf.x - ref.x) - xi) + gy * (R(xf.y - ref.y) - yi) + gz * (R(xf.z - ref.z) - zi);
+        R ph = R(1);
+        if (dl > R(0)) ph = fmin(R(1), (umax - ui) / dl);
+        else if (dl < R(0)) ph = fmin(R(1), (umin - ui) / dl);
+        psi = fmin(psi, ph);
+    }
+    a.psi[i] = psi;
+}
+
+// ---- gradient in star-moment form ------------------------------------------
+// The sum of Algorithm 1, J_i = sum_{j in N(i)} (x_j - x_i)(u_j - u_i) over
+// the node-neighbour stencil N(i) (every cell and ghost sharing a vertex
+// with i), rewritten exactly.  An entity sharing m vertices with i lies in m
+// of i's 4 vertex lists, so with T_L(i) = sum_{j in L} (x_j - x_i)(u_j - u_i)
+//   J_i = sum_{v of i} T_{L(v)}(i) - sum_{j sharing only an edge} (.) - 2 sum_{face nbrs} (.)
+// (i itself adds zeros).  For a list L of n entities with mean position xb,
+// mean value ub and centred moment C = sum (x_j - xb)(u_j - ub),
+//   T_L(i) = C + n (xb - x_i)(ub - u_i).
+// Each list is summed once per vertex instead of once per cell of its ~24
+// cells, and a cell reads 4 vertex records, its 4 face neighbours and ~13
+// edge neighbours instead of ~70 stencil entries.  Every term is a product
+// of differences of nearby values, so no large value cancels.
+//
+// One block per tile, as k_grad_limiter: the halo is staged in LDS; every
+// vertex the tile's cells touch (its own, then the foreign ones, whose lists
+// lie in the same halo) gets its record (xb, n), (C, ub) in LDS, from sums
+// shifted by the list's first entry (pad entries repeat it and add zeros):
+//   s = sum (x_j - x_0), q = sum (u_j - u_0), c = sum (x_j - x_0)(u_j - u_0),
+//   xb = x_0 + s/n, ub = u_0 + q/n, C = c - s q/n;
+// own vertices also store u_v = sum alpha u_j (Algorithm 2).
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
+    using V4 = typename Vec4T<R>::T;
+    extern __shared__ __align__(16) unsigned char sm_raw[];
+    V4* sm = reinterpret_cast<V4*>(sm_raw);          // [halo_max] records, then 2 per touched vertex
+    V4* vr = sm + d.halo_max;
+    constexpr bool rel = std::is_same<R, float>::value;
+    const int64_t nc = d.nc;
+    const int64_t t = blockIdx.x;
+    const int T = blockDim.x;
+    const int64_t i = t * T + threadIdx.x;
+    const bool cell = i < nc;
+    const int lself = d.h_self[t] + threadIdx.x;
+
+    // Global loads that do not depend on LDS are issued before the barriers,
+    // so their latency overlaps the halo staging: the cell's tables, the
+    // first batch of its edge neighbours, and the first batch of the vertex
+    // list this thread will sum.
+    uint16_t nl[4] = {0, 0, 0, 0}, lv[4] = {0, 0, 0, 0};
+    int fc[4] = {0, 0, 0, 0};
+    if (cell) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int f = d.c2f[k * nc + i];
+            fc[k] = f < 0 ? ~f : f;
+            nl[k] = d.c2n_l[k * nc + i];
+            lv[k] = d.c2v_l[k * nc + i];
+        }
+    }
+    const uint16_t* __restrict__ eidx = d.e_lidx + (cell ? d.e_off[i >> 6] + (i & 63) : 0);
+    const int ew = cell ? d.e_w[i >> 6] : 0;
+    uint16_t el[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) el[j] = j < ew ? eidx[int64_t(j) * 64] : uint16_t(lself);
+
+    const int64_t v0 = d.v_off[t], f0 = d.fv_off[t];
+    const int own = int(d.v_off[t + 1] - v0), nfor = int(d.fv_off[t + 1] - f0);
+    int r = threadIdx.x;
+    bool mine = r < own;
+    int64_t row = mine ? v0 + r : f0 + (r - own);
+    int64_t vbase = 0;
+    int vw = 0, vn = 1;
+    const uint16_t* __restrict__ li = d.n_lidx;
+    uint16_t vl[8];
+    R val[8];
+    auto vrow = [&]() {                 // row meta and its first batch
+        mine = r < own;
+        row = mine ? v0 + r : f0 + (r - own);
+        const int64_t sl = row >> 6;
+        vbase = (mine ? d.n_off[sl] : d.f_off[sl]) + (row & 63);
+        vw = mine ? d.n_w[sl] : d.f_w[sl];
+        vn = mine ? d.n_len[row] : d.fv_len[row];
+        li = mine ? d.n_lidx : d.f_lidx;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool in = j < vw;
+            vl[j] = in ? li[vbase + int64_t(j) * 64] : uint16_t(0);
+            val[j] = (mine && in) ? a.n_alpha[vbase + int64_t(j) * 64] : R(0);
+        }
+    };
+    if (r < own + nfor) vrow();
+
+    const double4 ref = rel ? d.xyz4[t * T] : make_double4(0.0, 0.0, 0.0, 0.0);
+    stage_halo<R>(d, a.u, sm, t, ref);
+    __syncthreads();
+
+    for (; r < own + nfor; r += T) {
+        if (r != int(threadIdx.x)) vrow();
+        const uint16_t l0 = vl[0];
+        const V4 q0 = sm[l0];
+        R un = R(0), sx = R(0), sy = R(0), sz = R(0), su = R(0), cx = R(0), cy = R(0), cz = R(0);
+        for (int k0 = 0; k0 < vw; k0 += 8) {
+            // next batch in flight while this one is summed (pad = first entry)
+            uint16_t nlx[8];
+            R nal[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bool in = k0 + 8 + j < vw;
+                const int64_t at = vbase + int64_t(k0 + 8 + j) * 64;
+                nlx[j] = in ? li[at] : l0;
+                nal[j] = (mine && in) ? a.n_alpha[at] : R(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const V4 q = sm[k0 + j < vw ? vl[j] : l0];
+                const R dx = q.x - q0.x, dy = q.y - q0.y, dz = q.z - q0.z, du = q.w - q0.w;
+                un += val[j] * q.w;
+                sx += dx; sy += dy; sz += dz; su += du;
+                cx += dx * du; cy += dy * du; cz += dz * du;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                vl[j] = nlx[j];
+                val[j] = nal[j];
+            }
+        }
+        const R inv = R(1) / R(vn);
+        const R mu = su * inv;
+        vr[2 * r] = mk4(q0.x + sx * inv, q0.y + sy * inv, q0.z + sz * inv, R(vn));
+        vr[2 * r + 1] = mk4(cx - sx * mu, cy - sy * mu, cz - sz * mu, q0.w + mu);
+        if (mine) a.unode[row] = un;
+    }
+    __syncthreads();
+    if (!cell) return;
+
+    // loads used at the end (limiter, M^-1) go out before the LDS work
+    double4 xf[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xf[k] = d.fx4[fc[k]];
+    const R* __restrict__ m = a.minv;
+    const R m0 = m[i], m1 = m[nc + i], m2 = m[2 * nc + i];
+    const R m3 = m[3 * nc + i], m4 = m[4 * nc + i], m5 = m[5 * nc + i];
+
+    const V4 me = sm[lself];
+    const R xi = me.x, yi = me.y, zi = me.z, ui = me.w;
+    R jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const V4 vs = vr[2 * lv[k]], vm = vr[2 * lv[k] + 1];
+        const R nd = vs.w * (vm.w - ui);
+        jx += vm.x + (vs.x - xi) * nd;
+        jy += vm.y + (vs.y - yi) * nd;
+        jz += vm.z + (vs.z - zi) * nd;
+    }
+    R umax = ui, umin = ui;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const V4 o = sm[nl[k]];
+        const R du2 = R(2) * (o.w - ui);
+        jx -= (o.x - xi) * du2;
+        jy -= (o.y - yi) * du2;
+        jz -= (o.z - zi) * du2;
+        umax = fmax(umax, o.w);
+        umin = fmin(umin, o.w);
+    }
+    // edge-only neighbours (slice padding = the cell itself, which adds zeros)
+    for (int k0 = 0; k0 < ew; k0 += 8) {
+        uint16_t nx[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            nx[j] = k0 + 8 + j < ew ? eidx[int64_t(k0 + 8 + j) * 64] : uint16_t(lself);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (k0 + j < ew) {          // uniform over the wave (one slice)
+                const V4 o = sm[el[j]];
+                const R du = o.w - ui;
+                jx -= (o.x - xi) * du;
+                jy -= (o.y - yi) * du;
+                jz -= (o.z - zi) * du;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) el[j] = nx[j];
+    }
+    const R gx = m0 * jx + m1 * jy + m2 * jz;
+    const R gy = m1 * jx + m3 * jy + m4 * jz;
+    const R gz = m2 * jx + m4 * jy + m5 * jz;
+    a.grad[i] = gx;
+    a.grad[nc + i] = gy;
+    a.grad[2 * nc + i] = gz;
+    R psi = R(1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const R dl = gx * (R(xf[k].x - ref.x) - xi) + gy * (R(xf[k].y - ref.y) - yi) +
+                     gz * (R(xf[k].z - ref.z) - zi);
         R ph = R(1);
         if (dl > R(0)) ph = fmin(R(1), (umax - ui) / dl);
         else if (dl < R(0)) ph = fmin(R(1), (umin - ui) / dl);
@@ -402,15 +604,26 @@ hipError_t launch_ghost_fill(const Dev& d, bool fp32, const BcTable& bc, hipStre
     return fp32 ? launch_ghost_fill_t(d, fv32(d), bc, s) : launch_ghost_fill_t(d, fv64(d), bc, s);
 }
 
-hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s) {
-    const dim3 g(unsigned(d.ntiles)), b(d.tile_rows);
-    if (fp32)
-        hipLaunchKernelGGL(k_grad_limiter<float>, g, b, size_t(d.halo_max) * sizeof(float4), s, d, fv32(d));
-    else
-        hipLaunchKernelGGL(k_grad_limiter<double>, g, b, size_t(d.halo_max) * sizeof(double4), s, d, fv64(d));
-    return hipGetLastError();
+// FP64: the star-moment tile kernel; FP32: the stencil tile kernel (both
+// also compute the vertex values)
+size_t moments_lds_bytes(const Dev& d) { return size_t(d.halo_max + 2 * d.tv_max) * sizeof(double4); }
+
+hipError_t setup_fv_kernels(const Dev& d) {
+    const size_t lds = moments_lds_bytes(d);
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_moments<double>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
 }
 
+hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s) {
+    const dim3 g(unsigned(d.ntiles)), b(d.tile_rows);
+    if (fp32) {
+        hipLaunchKernelGGL(k_grad_limiter<float>, g, b, size_t(d.halo_max) * sizeof(float4), s, d, fv32(d));
+    } else {
+        hipLaunchKernelGGL(k_grad_moments<double>, g, b, moments_lds_bytes(d), s, d, fv64(d));
+    }
+    return hipGetLastError();
+}
 hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s) {
     if (fp32)
         hipLaunchKernelGGL(k_face_flux<float>, dim3(grid_for(d.nf)), dim3(kBlock), 0, s, d, fv32(d), bc);

@@ -421,7 +421,11 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
         }
     }
     M.node_max = 0;
-    for (int64_t v = 0; v < nv; ++v) M.node_max = std::max<int32_t>(M.node_max, int32_t(M.nptr[v + 1] - M.nptr[v]));
+    M.n_len.assign(nv, 0);
+    for (int64_t v = 0; v < nv; ++v) {
+        M.n_len[v] = int32_t(M.nptr[v + 1] - M.nptr[v]);
+        M.node_max = std::max<int32_t>(M.node_max, M.n_len[v]);
+    }
 
     mark("vertex lists");
     // -- 11. least-squares vertex weights (Algorithm 2) -------------------------
@@ -448,6 +452,10 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     // -- 12. node-neighbour stencil (Algorithm 1): merge of 4 sorted lists ----
     M.sptr.assign(nc + 1, 0);
     M.sidx.clear();
+    M.eptr.assign(nc + 1, 0);
+    M.eidx.clear();
+    M.eidx.reserve(size_t(nc) * 16);
+    M.enbr_max = 0;
     M.sidx.reserve(size_t(nc) * 72);
     M.minv.assign(6 * nc, 0.0);
     M.klen.assign(nc, 0);
@@ -461,6 +469,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             h[k] = M.nptr[v];
             e[k] = M.nptr[v + 1];
         }
+        int faces_seen = 0;
         int64_t last = -1;
         double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
         int32_t klen = 0;
@@ -469,10 +478,19 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             for (int k = 0; k < 4; ++k)
                 if (h[k] < e[k]) best = std::min<int64_t>(best, M.nidx[h[k]]);
             if (best == INT64_MAX) break;
+            int shared = 0;           // vertices of i whose list holds `best`
             for (int k = 0; k < 4; ++k)
-                if (h[k] < e[k] && M.nidx[h[k]] == best) ++h[k];
+                if (h[k] < e[k] && M.nidx[h[k]] == best) { ++h[k]; ++shared; }
             if (best == last || best == i) continue;
             last = best;
+            if (shared == 2) {
+                M.eidx.push_back((int32_t)best);
+            } else if (shared == 3) {
+                bool is_face = false;
+                for (int k = 0; k < 4; ++k) is_face |= M.c2n[k * nc + i] == (int32_t)best;
+                if (!is_face) { err = "entity sharing 3 vertices is not a face neighbour"; return E_MESH; }
+                ++faces_seen;
+            }
             M.sidx.push_back((int32_t)best);
             if (best < nc) ++klen;
             double dx = M.xc[best] - M.xc[i], dy = M.xc[NX + best] - M.xc[NX + i],
@@ -480,7 +498,10 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             m00 += dx * dx; m01 += dx * dy; m02 += dx * dz;
             m11 += dy * dy; m12 += dy * dz; m22 += dz * dz;
         }
+        if (faces_seen != 4) { err = "cell without 4 face-sharing stencil entities"; return E_MESH; }
         M.sptr[i + 1] = (int64_t)M.sidx.size();
+        M.eptr[i + 1] = (int64_t)M.eidx.size();
+        M.enbr_max = std::max<int32_t>(M.enbr_max, int32_t(M.eptr[i + 1] - M.eptr[i]));
         M.klen[i] = klen;
         M.stencil_max = std::max<int32_t>(M.stencil_max, int32_t(M.sptr[i + 1] - M.sptr[i]));
         M.row_max = std::max(M.row_max, klen);
@@ -502,6 +523,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     pack_sell(M.nptr, M.nidx, &M.nalpha, nullptr, nv,
               [&](int64_t r) { return M.nidx[M.nptr[r]]; }, M.node);
     pack_sell(M.sptr, M.sidx, nullptr, &M.klen, nc, [](int64_t r) { return (int32_t)r; }, M.kmat);
+    pack_sell(M.eptr, M.eidx, nullptr, nullptr, nc, [](int64_t r) { return (int32_t)r; }, M.enbr);
 
     mark("slicing");
     // -- 14. tiles and their halos -------------------------------------------------
@@ -553,8 +575,18 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     M.s_lidx.assign(M.stencil.idx.size(), 0);
     M.k_lidx.assign(M.kmat.idx.size(), 0);
     M.c2n_l.assign(4 * nc, 0);
+    M.e_lidx.assign(M.enbr.idx.size(), 0);
+    M.c2v_l.assign(4 * nc, 0);
+    std::vector<int64_t> fptr(1, 0);
+    std::vector<int32_t> fent;                 // foreign lists, local halo indices
+    M.fv_off.assign(M.h_self.size() + 1, 0);
+    M.fv_idx.clear();
+    M.fv_len.clear();
+    M.tv_max = 0;
+    const auto& cell_verts = T;
     {
         std::vector<int32_t> g2l(nc + nb, -1);
+        std::vector<int32_t> v2l(nv, -1);
         const int64_t T = M.tile_rows;
         const int64_t nt = (int64_t)M.h_self.size();
         for (int64_t t = 0; t < nt; ++t) {
@@ -572,7 +604,42 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
                     M.k_lidx[at] = (uint16_t)g2l[M.kmat.idx[at]];
                 }
                 for (int k = 0; k < 4; ++k) M.c2n_l[k * nc + r] = (uint16_t)g2l[M.c2n[k * nc + r]];
+                for (int64_t k = 0; k < M.enbr.width[sl]; ++k) {
+                    const int64_t at = M.enbr.off[sl] + k * 64 + lane;
+                    M.e_lidx[at] = (uint16_t)g2l[M.enbr.idx[at]];
+                }
             }
+            // vertices the tile's cells touch: own first, then foreign (sorted)
+            const int64_t own = M.v_off[t + 1] - M.v_off[t];
+            for (int64_t v = M.v_off[t]; v < M.v_off[t + 1]; ++v) v2l[v] = int32_t(v - M.v_off[t]);
+            const size_t fbeg = M.fv_idx.size();
+            for (int64_t r = t0; r < t1; ++r) {
+                const auto& tt = cell_verts[new2old[r]];
+                for (int k = 0; k < 4; ++k) {
+                    const int32_t v = vold2new[tt[k]];
+                    if (v2l[v] == -1) { v2l[v] = -2; M.fv_idx.push_back(v); }
+                }
+            }
+            std::sort(M.fv_idx.begin() + fbeg, M.fv_idx.end());
+            for (size_t q = fbeg; q < M.fv_idx.size(); ++q) {
+                const int32_t v = M.fv_idx[q];
+                v2l[v] = int32_t(own + int64_t(q - fbeg));
+                M.fv_len.push_back(M.n_len[v]);
+                for (int64_t e = M.nptr[v]; e < M.nptr[v + 1]; ++e) {
+                    const int32_t l = g2l[M.nidx[e]];
+                    if (l < 0) { err = "internal error: vertex list outside the tile halo"; return E_MESH; }
+                    fent.push_back(l);
+                }
+                fptr.push_back((int64_t)fent.size());
+            }
+            M.fv_off[t + 1] = (int64_t)M.fv_idx.size();
+            M.tv_max = std::max<int32_t>(M.tv_max, int32_t(own + int64_t(M.fv_idx.size() - fbeg)));
+            for (int64_t r = t0; r < t1; ++r) {
+                const auto& tt = cell_verts[new2old[r]];
+                for (int k = 0; k < 4; ++k) M.c2v_l[k * nc + r] = (uint16_t)v2l[vold2new[tt[k]]];
+            }
+            for (int64_t v = M.v_off[t]; v < M.v_off[t + 1]; ++v) v2l[v] = -1;
+            for (size_t q = fbeg; q < M.fv_idx.size(); ++q) v2l[M.fv_idx[q]] = -1;
             for (int64_t v = M.v_off[t]; v < M.v_off[t + 1]; ++v) {
                 const int64_t sl = v >> 6;
                 const int lane = int(v & 63);
@@ -585,6 +652,13 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             }
             for (int64_t h = M.h_off[t]; h < M.h_off[t + 1]; ++h) g2l[M.h_idx[h]] = -1;
         }
+    }
+    {   // foreign vertex lists in 64-row slices (pad = the row's first entry)
+        const int64_t nfr = (int64_t)M.fv_idx.size();
+        pack_sell(fptr, fent, nullptr, nullptr, nfr, [&](int64_t r) { return fent[fptr[r]]; }, M.fnode);
+        M.f_lidx.assign(M.fnode.idx.begin(), M.fnode.idx.end());
+        M.fnode.idx.clear();
+        M.fnode.idx.shrink_to_fit();
     }
     mark("local indices");
     // every local index must name the same entity as the global one
@@ -602,7 +676,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             }
         return true;
     };
-    bool ok = verify(M.stencil, M.s_lidx) && verify(M.kmat, M.k_lidx);
+    bool ok = verify(M.stencil, M.s_lidx) && verify(M.kmat, M.k_lidx) && verify(M.enbr, M.e_lidx);
     for (int64_t i = 0; ok && i < nc; ++i) {
         const int64_t t = i / M.tile_rows;
         ok = M.h_idx[M.h_off[t] + M.h_self[t] + (i - t * M.tile_rows)] == i;

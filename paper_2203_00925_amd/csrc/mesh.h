@@ -66,6 +66,27 @@ struct Mesh {
     // cell/ghost lists lie inside the tile's halo
     std::vector<int64_t> v_off;       // ntiles + 1
     std::vector<uint16_t> n_lidx;     // like node.idx, local to the owning tile
+    // Star-moment form of the gradient sum of Algorithm 1.  An entity of the
+    // stencil of cell i shares m in {1, 2, 3} vertices with i, so the sum
+    // over the stencil equals the sum over the 4 vertex lists of i minus
+    // (m - 1) times each entity with m > 1: the entities sharing exactly an
+    // edge (m = 2, listed here) and the 4 face neighbours (m = 3, c2n).
+    std::vector<int64_t> eptr; std::vector<int32_t> eidx;   // edge-only neighbours, CSR
+    Sell64 enbr;                      // the same, pad = the row itself
+    std::vector<uint16_t> e_lidx;     // like enbr.idx, local to the tile
+    int32_t enbr_max = 0;
+    std::vector<int32_t> n_len;       // nv: vertex list lengths
+    // Vertices a tile's cells touch: the tile's own ([v_off[t], v_off[t+1]))
+    // and the foreign ones, listed per tile with their vertex lists in the
+    // tile's local halo indices (pad = first entry).  Tile-local vertex
+    // number: own v -> v - v_off[t], foreign row r -> own count + r - fv_off[t].
+    std::vector<int64_t> fv_off;      // ntiles + 1
+    std::vector<int32_t> fv_idx;      // foreign vertex ids
+    std::vector<int32_t> fv_len;      // their list lengths
+    Sell64 fnode;                     // their lists, idx local (stored in f_lidx)
+    std::vector<uint16_t> f_lidx;
+    std::vector<uint16_t> c2v_l;      // 4 x nc tile-local vertex number
+    int32_t tv_max = 0;               // most vertices touched by one tile
 };
 
 // Returns 0 or a negative mifvm status; err receives a message.

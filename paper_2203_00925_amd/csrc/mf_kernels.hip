@@ -16,25 +16,10 @@
 #include "reduce.h"
 #include "seg.h"
 #include "state.h"
+#include "xcd.h"
 
 namespace mifvm {
 namespace {
-
-// Blocks are dealt to the 8 XCDs in turn, and each XCD has its own L2.  The
-// grid is padded to a multiple of 8 and block b works on logical block
-// (b % 8) * (grid / 8) + b / 8, so each XCD takes one contiguous eighth of
-// the rows: the neighbour data that consecutive blocks share (vertex lists
-// reading nearby cells, faces reading nearby vertices) then stays in one L2.
-constexpr int kXcds = 8;
-__device__ inline int64_t xcd_block() {
-    const int64_t per = gridDim.x / kXcds;
-    return int64_t(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
-}
-__device__ inline int64_t gtid_m() { return xcd_block() * blockDim.x + threadIdx.x; }
-inline unsigned rows_m(int64_t n) {
-    const int64_t b = (n + kBlock - 1) / kBlock;
-    return unsigned((b + kXcds - 1) / kXcds * kXcds);
-}
 
 // ghost values of x (homogeneous part): xg[g] = s_g x_owner
 __global__ __launch_bounds__(kBlock) void k_mf_ghost(Dev d, BcTable bc, const double* __restrict__ x,
@@ -143,9 +128,9 @@ hipError_t launch_mf_apply(const Dev& d, const BcTable& bc, const double* x, dou
                            const double* skip) {
     hipLaunchKernelGGL(k_mf_ghost, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d, bc, x,
                        d.mf_xg, skip);
-    hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv)), dim3(kBlock), 0, s, d, x, d.mf_xg, d.mf_xv, skip);
-    hipLaunchKernelGGL(k_mf_face, dim3(rows_m(d.nf)), dim3(kBlock), 0, s, d, bc, x, d.mf_xv, d.mf_flux, skip);
-    hipLaunchKernelGGL(k_mf_gather, dim3(rows_m(d.nc)), dim3(kBlock), 0, s, d, d.mf_flux, y, skip);
+    hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, x, d.mf_xg, d.mf_xv, skip);
+    hipLaunchKernelGGL(k_mf_face, dim3(rows_m(d.nf, kBlock)), dim3(kBlock), 0, s, d, bc, x, d.mf_xv, d.mf_flux, skip);
+    hipLaunchKernelGGL(k_mf_gather, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, d.mf_flux, y, skip);
     return hipGetLastError();
 }
 
@@ -154,12 +139,12 @@ hipError_t launch_mf_cg_part(const Dev& d, const BcTable& bc, int part, hipStrea
     if (part == 0) {
         hipLaunchKernelGGL(k_mf_ghost, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d, bc, d.p,
                            d.mf_xg, none);
-        hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv)), dim3(kBlock), 0, s, d, d.p, d.mf_xg, d.mf_xv, none);
+        hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, d.p, d.mf_xg, d.mf_xv, none);
     } else if (part == 1) {
-        hipLaunchKernelGGL(k_mf_face, dim3(rows_m(d.nf)), dim3(kBlock), 0, s, d, bc, d.p, d.mf_xv, d.mf_flux, none);
+        hipLaunchKernelGGL(k_mf_face, dim3(rows_m(d.nf, kBlock)), dim3(kBlock), 0, s, d, bc, d.p, d.mf_xv, d.mf_flux, none);
     } else {
         const int64_t nblk = (d.nc + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(k_mf_cg_gather, dim3(rows_m(d.nc)), dim3(kBlock), 0, s, d, d.mf_flux, nblk);
+        hipLaunchKernelGGL(k_mf_cg_gather, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, d.mf_flux, nblk);
         hipLaunchKernelGGL(k_cg_alpha<1>, dim3(d.nm), dim3(1024), 0, s, d, nblk, int64_t(kBlock));
     }
     return hipGetLastError();

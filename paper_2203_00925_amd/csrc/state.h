@@ -44,6 +44,7 @@ struct Dev {
     int32_t *gowner, *gtag; double* gdist;
     // vertices
     int64_t* n_off; int32_t* n_w; int32_t* n_idx; double* n_alpha;
+    int32_t* n_len;                       // nv vertex list lengths
     // Poisson pattern and values
     int64_t* k_off; int32_t* k_w; int32_t* k_col; int32_t* k_len;
     double *k_val, *k_diag, *k_dinv, *k_c;
@@ -55,6 +56,13 @@ struct Dev {
     int64_t* h_off; int32_t* h_idx; int32_t* h_self;
     uint16_t *s_lidx, *k_lidx, *c2n_l, *n_lidx;
     int64_t* v_off;
+    // star-moment gradient: edge-only neighbours (64-row slices, local),
+    // tile-local vertex numbers, the foreign vertices of each tile
+    int32_t tv_max;
+    int64_t* e_off; int32_t* e_w; uint16_t* e_lidx;
+    uint16_t* c2v_l;
+    int64_t* fv_off; int32_t* fv_len;
+    int64_t* f_off; int32_t* f_w; uint16_t* f_lidx;
     // renumbering
     int32_t *cell_perm, *vert_perm;       // internal -> user
     // fields
@@ -140,6 +148,8 @@ size_t layout(const Mesh& m, char* base, Dev& d);
 // launchers (fv_kernels.hip)
 hipError_t launch_ghost_fill(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
 hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s);
+// once per state: kernel attributes (LDS above 64 KB for large tile halos)
+hipError_t setup_fv_kernels(const Dev& d);
 hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
 hipError_t launch_update(const Dev& d, bool fp32, double alpha, bool first_stage, hipStream_t s);
 hipError_t launch_set_dt(const Dev& d, double dt, double cfl, hipStream_t s);
