@@ -40,9 +40,14 @@ inline int grid_for(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 template <class R> struct Vec4T;
 template <> struct Vec4T<double> { using T = double4; };
 template <> struct Vec4T<float> { using T = float4; };
+template <class R> struct Vec2T;
+template <> struct Vec2T<double> { using T = double2; };
+template <> struct Vec2T<float> { using T = float2; };
 
 __device__ inline double4 mk4(double x, double y, double z, double w) { return make_double4(x, y, z, w); }
 __device__ inline float4 mk4(float x, float y, float z, float w) { return make_float4(x, y, z, w); }
+__device__ inline double2 mk2(double x, double y) { return make_double2(x, y); }
+__device__ inline float2 mk2(float x, float y) { return make_float2(x, y); }
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_ghost_fill(int64_t nc, int64_t nb,
@@ -82,6 +87,46 @@ __device__ inline void stage_halo(const Dev& d, const R* __restrict__ u, V4* sm,
             if (e[j] >= 0) {
                 const double4 r = P[e[j]];
                 sm[hb + j * T + threadIdx.x] = mk4(R(r.x - ref.x), R(r.y - ref.y), R(r.z - ref.z), u[e[j]]);
+            }
+        }
+    }
+}
+
+// The same halo as two 16-byte arrays, (x, y) and (z, u): random reads of
+// 16-byte items spread over twice as many LDS bank groups as the first or
+// second half of 32-byte records.
+template <class R>
+struct HaloSoA {
+    using V2 = typename Vec2T<R>::T;
+    using V4 = typename Vec4T<R>::T;
+    V2* xy;
+    V2* zu;
+    __device__ V4 operator[](int l) const {
+        const V2 a = xy[l], b = zu[l];
+        return mk4(a.x, a.y, b.x, b.y);
+    }
+};
+
+template <class R>
+__device__ inline void stage_halo_soa(const Dev& d, const R* __restrict__ u, HaloSoA<R> sm, int64_t t, double4 ref) {
+    const int T = blockDim.x;
+    const int64_t h0 = d.h_off[t];
+    const int hn = int(d.h_off[t + 1] - h0);
+    const double4* __restrict__ P = d.xyz4;
+    for (int hb = 0; hb < hn; hb += 8 * T) {
+        int e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int h = hb + j * T + threadIdx.x;
+            e[j] = h < hn ? d.h_idx[h0 + h] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (e[j] >= 0) {
+                const double4 r = P[e[j]];
+                const int h = hb + j * T + threadIdx.x;
+                sm.xy[h] = mk2(R(r.x - ref.x), R(r.y - ref.y));
+                sm.zu[h] = mk2(R(r.z - ref.z), u[e[j]]);
             }
         }
     }
@@ -220,13 +265,17 @@ __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d, FvArrays<R> a) {
 // own vertices also store u_v = sum alpha u_j (Algorithm 2).
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
+    using V2 = typename Vec2T<R>::T;
     using V4 = typename Vec4T<R>::T;
     extern __shared__ __align__(16) unsigned char sm_raw[];
-    V4* sm = reinterpret_cast<V4*>(sm_raw);          // [halo_max] records, then 2 per touched vertex
-    V4* vr = sm + d.halo_max;
+    // [halo] (x, y), [halo] (z, u), then 2 records per touched vertex
+    const int hcap = (d.halo_max + 1) & ~1;
+    const HaloSoA<R> sm{reinterpret_cast<V2*>(sm_raw), reinterpret_cast<V2*>(sm_raw) + hcap};
+    V4* vr = reinterpret_cast<V4*>(sm.zu + hcap);
     constexpr bool rel = std::is_same<R, float>::value;
     const int64_t nc = d.nc;
-    const int64_t t = blockIdx.x;
+    const int64_t t = xcd_block();
+    if (t >= d.ntiles) return;
     const int T = blockDim.x;
     const int64_t i = t * T + threadIdx.x;
     const bool cell = i < nc;
@@ -281,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
     if (r < own + nfor) vrow();
 
     const double4 ref = rel ? d.xyz4[t * T] : make_double4(0.0, 0.0, 0.0, 0.0);
-    stage_halo<R>(d, a.u, sm, t, ref);
+    stage_halo_soa<R>(d, a.u, sm, t, ref);
     __syncthreads();
 
     for (; r < own + nfor; r += T) {
@@ -606,7 +655,9 @@ hipError_t launch_ghost_fill(const Dev& d, bool fp32, const BcTable& bc, hipStre
 
 // FP64: the star-moment tile kernel; FP32: the stencil tile kernel (both
 // also compute the vertex values)
-size_t moments_lds_bytes(const Dev& d) { return size_t(d.halo_max + 2 * d.tv_max) * sizeof(double4); }
+size_t moments_lds_bytes(const Dev& d) {
+    return size_t(2 * ((d.halo_max + 1) & ~1)) * sizeof(double2) + size_t(2 * d.tv_max) * sizeof(double4);
+}
 
 hipError_t setup_fv_kernels(const Dev& d) {
     const size_t lds = moments_lds_bytes(d);
@@ -620,7 +671,9 @@ hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s) {
     if (fp32) {
         hipLaunchKernelGGL(k_grad_limiter<float>, g, b, size_t(d.halo_max) * sizeof(float4), s, d, fv32(d));
     } else {
-        hipLaunchKernelGGL(k_grad_moments<double>, g, b, moments_lds_bytes(d), s, d, fv64(d));
+        // grid padded to a multiple of 8 for the XCD-contiguous tile order
+        hipLaunchKernelGGL(k_grad_moments<double>, dim3(unsigned((d.ntiles + kXcds - 1) / kXcds * kXcds)), b,
+                           moments_lds_bytes(d), s, d, fv64(d));
     }
     return hipGetLastError();
 }
