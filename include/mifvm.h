@@ -110,6 +110,11 @@ typedef struct {
     int32_t tile_vertices_max; /* most vertices the cells of one tile touch   */
     int64_t halo_entries;      /* sum of tile halo sizes                      */
     size_t ws_bytes;           /* device workspace needed by a state          */
+    int64_t edge_nbr_entries;  /* entities sharing only an edge with a cell,
+                                  summed over cells (unpadded)                */
+    int64_t foreign_rows;      /* vertices touched by a tile's cells but owned
+                                  by another tile, summed over tiles          */
+    int64_t foreign_entries;   /* entries of their vertex lists (unpadded)    */
 } mifvm_mesh_info;
 
 typedef struct {
@@ -145,18 +150,21 @@ typedef struct {
                                   iterations (0 = 200)                      */
     int32_t learned_maxit;     /* LEARNED: fall back after this many flexible
                                   CG iterations (0 = maxit)                  */
-    int32_t matrix_free;       /* PLAIN, LEARNED: 1 = apply K in the iterations
-                                  from the discretisation (vertex values,
-                                  diamond fluxes, cell gather) instead of the
-                                  stored matrix; the assembled diagonal, c
-                                  and the true-residual checks are unchanged */
+    int32_t matrix_free;       /* 1 = apply K in the iterations from the
+                                  discretisation (vertex values, diamond
+                                  fluxes, cell gather) instead of the stored
+                                  matrix; the assembled diagonal and c are
+                                  unchanged.  IR_FP32: the inner CG applies
+                                  it in FP32 (FP32 copies of the vertex
+                                  weights and diamond coefficients) and the
+                                  true residual in FP64                      */
     int32_t pad_;
 } mifvm_solve_opts;
 
 /* PLAIN: FP64 Jacobi-CG.  IR_FP32: iterative refinement - the FP64 true
  * residual r = b - K x, an FP32 Jacobi-CG solve of K d = r on an FP32 copy of
- * K (dot products accumulated in FP64), x += d in FP64 - repeated until the
- * FP64 true residual meets tol.                                            */
+ * K or the FP32 matrix-free product (dot products accumulated in FP64),
+ * x += d in FP64 - repeated until the FP64 true residual meets tol.        */
 enum mifvm_solve_method { MIFVM_SOLVE_PLAIN = 0, MIFVM_SOLVE_IR_FP32 = 1, MIFVM_SOLVE_LEARNED = 2,
                           MIFVM_SOLVE_FGMRES = 3 };
 /* FGMRES: restarted flexible GMRES(m) with the Jacobi preconditioner, the

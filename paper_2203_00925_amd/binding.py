@@ -70,7 +70,8 @@ class MeshInfo(C.Structure):
                 ("matrix_padded", C.c_int64), ("stencil_max", C.c_int32),
                 ("node_max", C.c_int32), ("row_max", C.c_int32), ("tile_rows", C.c_int32),
                 ("halo_max", C.c_int32), ("tile_vertices_max", C.c_int32), ("halo_entries", C.c_int64),
-                ("ws_bytes", C.c_size_t)]
+                ("ws_bytes", C.c_size_t), ("edge_nbr_entries", C.c_int64),
+                ("foreign_rows", C.c_int64), ("foreign_entries", C.c_int64)]
 
 
 class _Params(C.Structure):

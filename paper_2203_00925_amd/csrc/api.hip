@@ -156,8 +156,9 @@ namespace {
 hipError_t enqueue_cg_chunk(const State& s, int method, int n, hipStream_t q) {
     const Dev& d = s.d;
     for (int c = 0; c < n; ++c) {
-        hipError_t e = method == MIFVM_SOLVE_PLAIN ? (s.mf ? launch_mf_cg_spmv(d, s.bc[1], q) : launch_cg_spmv(d, q))
-                                                   : launch_cg32_spmv(d, q);
+        hipError_t e = method == MIFVM_SOLVE_PLAIN
+                           ? (s.mf ? launch_mf_cg_spmv(d, s.bc[1], q) : launch_cg_spmv(d, q))
+                           : (s.mf ? launch_mf_cg32_spmv(d, s.bc[1], q) : launch_cg32_spmv(d, q));
         if (e == hipSuccess) e = method == MIFVM_SOLVE_PLAIN ? launch_cg_axpy(d, q) : launch_cg32_axpy(d, q);
         if (e == hipSuccess) e = method == MIFVM_SOLVE_PLAIN ? launch_cg_dir(d, q) : launch_cg32_dir(d, q);
         if (e != hipSuccess) return e;
@@ -215,6 +216,11 @@ int mifvm_mesh_get_info(const mifvm_mesh* mesh, mifvm_mesh_info* out) {
     out->halo_entries = (int64_t)m.h_idx.size();
     Dev d{};
     out->ws_bytes = layout(m, nullptr, d);
+    out->edge_nbr_entries = (int64_t)m.eidx.size();
+    out->foreign_rows = (int64_t)m.fv_idx.size();
+    int64_t fe = 0;
+    for (int32_t n : m.fv_len) fe += n;
+    out->foreign_entries = fe;
     return MIFVM_OK;
 }
 
@@ -688,8 +694,6 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         if (s.d.nm != 1) return fail(MIFVM_E_ARG, "method FGMRES needs a single-mesh state");
     }
     const bool matrix_free = opts && opts->matrix_free != 0;
-    if (matrix_free && method == MIFVM_SOLVE_IR_FP32)
-        return fail(MIFVM_E_ARG, "matrix_free is built for the FP64 methods (PLAIN, LEARNED)");
     const int stall_window = opts ? opts->stall_window : 0;
     const int learned_maxit = opts ? opts->learned_maxit : 0;
     if (stall_window < 0 || learned_maxit < 0) return fail(MIFVM_E_ARG, "bad stall_window or learned_maxit");
@@ -760,6 +764,12 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
                 }
                 HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
                 HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
+            } else if (matrix_free) {
+                for (int part = 0; part < 3; ++part)
+                    HIPCHK(timed(tm, MIFVM_K_MF_VERTEX + part, hs,
+                                 [&] { return launch_mf_cg32_part(d, s.bc[1], part, hs); }));
+                HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg32_axpy(d, hs); }));
+                HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg32_dir(d, hs); }));
             } else {
                 HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg32_spmv(d, hs); }));
                 HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg32_axpy(d, hs); }));
@@ -838,8 +848,13 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
         }
         bool fresh = true;
         for (;;) {
-            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs,
-                         [&] { return launch_ir_residual(d, tol, tol_in, maxit, restart, fresh, hs); }));
+            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&]() -> hipError_t {
+                if (matrix_free) {      // K x by the FP64 matrix-free product
+                    hipError_t e = launch_mf_apply(d, s.bc[1], d.x, d.tmp, hs);
+                    if (e != hipSuccess) return e;
+                }
+                return launch_ir_residual(d, tol, tol_in, maxit, restart, fresh, matrix_free ? d.tmp : nullptr, hs);
+            }));
             fresh = false;
             if ((rc = pull())) return rc;
             if (!any_running()) break;                   // every mesh converged, or at its limit

@@ -27,19 +27,25 @@ __global__ __launch_bounds__(kBlock) void k_cast_matrix(Dev d, int64_t padded) {
 // Outer step: r = b - K x (FP64, same entries and order as the plain SpMV);
 // inner start d = 0, r32 = r, z32 = D^-1 r32, p32 = z32.  Partials: true
 // rr (FP64), inner rz and rr (FP64 sums of FP32 values), bb.
-__global__ __launch_bounds__(kBlock) void k_ir_residual(Dev d) {
+// kx non-null: K x was formed by the matrix-free product.
+__global__ __launch_bounds__(kBlock) void k_ir_residual(Dev d, const double* __restrict__ kx) {
     __shared__ double lds[4];
     const int64_t i = tid_g();
     const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < d.nc) {
-        const int64_t s = i >> 6;
-        const int64_t base = d.k_off[s] + (i & 63);
-        const int w = d.k_w[s];
-        double y = d.k_diag[i] * d.x[i];
-        for (int k = 0; k < w; ++k) {
-            const int64_t at = base + int64_t(k) * 64;
-            y += d.k_val[at] * d.x[d.k_col[at]];
+        double y;
+        if (kx) {
+            y = kx[i];
+        } else {
+            const int64_t s = i >> 6;
+            const int64_t base = d.k_off[s] + (i & 63);
+            const int w = d.k_w[s];
+            y = d.k_diag[i] * d.x[i];
+            for (int k = 0; k < w; ++k) {
+                const int64_t at = base + int64_t(k) * 64;
+                y += d.k_val[at] * d.x[d.k_col[at]];
+            }
         }
         const double bi = d.b[i];
         const double ri = bi - y;
@@ -177,9 +183,9 @@ hipError_t launch_cast_matrix(const Dev& d, int64_t padded, hipStream_t s) {
 }
 
 hipError_t launch_ir_residual(const Dev& d, double tol, double tol_in, int maxit, int restart, bool fresh,
-                              hipStream_t s) {
+                              const double* kx, hipStream_t s) {
     const int nb = rows_grid(d.nc);
-    hipLaunchKernelGGL(k_ir_residual, dim3(nb), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_ir_residual, dim3(nb), dim3(kBlock), 0, s, d, kx);
     hipLaunchKernelGGL(k_ir_residual_fin, dim3(d.nm), dim3(1024), 0, s, d, int64_t(nb), tol, tol_in, maxit,
                        restart, fresh ? 1 : 0);
     return hipGetLastError();

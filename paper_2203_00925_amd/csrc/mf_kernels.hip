@@ -12,6 +12,8 @@
 // the per-cell gather through the cell->face table, which also writes the
 // partial p.q of the conjugate gradient.  About 210 bytes per row move
 // against about 730 for the stored 64-row-sliced matrix.
+#include <type_traits>
+
 #include "cg_scalars.h"
 #include "reduce.h"
 #include "seg.h"
@@ -21,41 +23,59 @@
 namespace mifvm {
 namespace {
 
+// The coefficient arrays of one precision: FP64, or the FP32 copies the
+// reduced-precision forms read (the inner CG of the refined solve).
+template <class R> struct MfCoef;
+template <> struct MfCoef<double> {
+    __device__ static const double* alpha(const Dev& d) { return d.n_alpha; }
+    __device__ static const double* kac(const Dev& d) { return d.kAC; }
+    __device__ static const double* kbc(const Dev& d) { return d.kBC; }
+    __device__ static const double* krl(const Dev& d) { return d.kRL; }
+};
+template <> struct MfCoef<float> {
+    __device__ static const float* alpha(const Dev& d) { return d.n_alpha32; }
+    __device__ static const float* kac(const Dev& d) { return d.kAC32; }
+    __device__ static const float* kbc(const Dev& d) { return d.kBC32; }
+    __device__ static const float* krl(const Dev& d) { return d.kRL32; }
+};
+
 // ghost values of x (homogeneous part): xg[g] = s_g x_owner
-__global__ __launch_bounds__(kBlock) void k_mf_ghost(Dev d, BcTable bc, const double* __restrict__ x,
-                                                     double* __restrict__ xg, const double* skip) {
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_mf_ghost(Dev d, BcTable bc, const R* __restrict__ x,
+                                                     R* __restrict__ xg, const double* skip) {
     if (skip && *skip != 0.0) return;
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= d.nb) return;
-    const double sg = bc.kind[d.gtag[g]] == kDirichlet ? -1.0 : 1.0;
+    const R sg = bc.kind[d.gtag[g]] == kDirichlet ? R(-1) : R(1);
     xg[g] = sg * x[d.gowner[g]];
 }
 
 // x_v = sum alpha x_e over the vertex list; a cell reads x, a ghost xg.  The
 // entries go in batches of 8: the weight and index loads of a batch first,
 // then its gathers, so 8 gathers are in flight per thread.
-__global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const double* __restrict__ x,
-                                                      const double* __restrict__ xg, double* __restrict__ xv,
-                                                      const double* skip) {
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict__ x, const R* __restrict__ xg,
+                                                      R* __restrict__ xv, const double* skip) {
     if (skip && *skip != 0.0) return;
     const int64_t v = gtid_m();
     if (v >= d.nv) return;
+    const R* __restrict__ alpha = MfCoef<R>::alpha(d);
     const int64_t sl = v >> 6;
     const int64_t base = d.n_off[sl] + (v & 63);
     const int w = d.n_w[sl];
     const int nc = int(d.nc);
-    double s = 0.0;
+    R s = R(0);
     for (int k0 = 0; k0 < w; k0 += 8) {
         int e[8];
-        double al[8];
+        R al[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const bool in = k0 + j < w;
             const int64_t at = base + int64_t(k0 + j) * 64;
             e[j] = in ? d.n_idx[at] : 0;                 // padding entries carry weight 0
-            al[j] = in ? d.n_alpha[at] : 0.0;
+            al[j] = in ? alpha[at] : R(0);
         }
-        double xe[8];
+        R xe[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) xe[j] = e[j] < nc ? x[e[j]] : xg[e[j] - nc];
 #pragma unroll
@@ -64,30 +84,33 @@ __global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const double* __res
     xv[v] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_mf_face(Dev d, BcTable bc, const double* __restrict__ x,
-                                                    const double* __restrict__ xv, double* __restrict__ F,
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_mf_face(Dev d, BcTable bc, const R* __restrict__ x,
+                                                    const R* __restrict__ xv, R* __restrict__ F,
                                                     const double* skip) {
     if (skip && *skip != 0.0) return;
     const int64_t f = gtid_m();
     if (f >= d.nf) return;
     const int L = d.fL[f];
-    double xr;
+    R xr;
     if (f >= d.nfi) {
         if (bc.kind[d.gtag[f - d.nfi]] != kDirichlet) {
-            F[f] = 0.0;
+            F[f] = R(0);
             return;
         }
         xr = -x[L];
     } else {
         xr = x[d.fR[f]];
     }
-    const double xc = xv[d.fC[f]];
-    F[f] = d.kAC[f] * (xv[d.fA[f]] - xc) + d.kBC[f] * (xv[d.fB[f]] - xc) + d.kRL[f] * (xr - x[L]);
+    const R xc = xv[d.fC[f]];
+    F[f] = MfCoef<R>::kac(d)[f] * (xv[d.fA[f]] - xc) + MfCoef<R>::kbc(d)[f] * (xv[d.fB[f]] - xc) +
+           MfCoef<R>::krl(d)[f] * (xr - x[L]);
 }
 
 // y_i = -sum_f s_if F_f
-__device__ inline double gather_row(const Dev& d, const double* __restrict__ F, int64_t i) {
-    double y = 0.0;
+template <class R>
+__device__ inline R gather_row(const Dev& d, const R* __restrict__ F, int64_t i) {
+    R y = R(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int code = d.c2f[k * d.nc + i];
@@ -104,9 +127,11 @@ __global__ __launch_bounds__(kBlock) void k_mf_gather(Dev d, const double* __res
 }
 
 // q = K p through F, and the partial p.q (the matrix-free counterpart of
-// k_cg_spmv; rows of finished meshes are left untouched)
-// (partial slots by logical block; padding blocks past the rows return)
-__global__ __launch_bounds__(kBlock) void k_mf_cg_gather(Dev d, const double* __restrict__ F, int64_t nblk) {
+// k_cg_spmv; rows of finished meshes are left untouched; partial slots by
+// logical block, padding blocks past the rows return).  FP32: q32 = K p32
+// with the FP32 coefficients and the partial in FP64 (as k_cg32_spmv).
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_mf_cg_gather(Dev d, const R* __restrict__ F, int64_t nblk) {
     __shared__ double lds[4];
     const int64_t lb = xcd_block();
     if (lb >= nblk) return;
@@ -115,9 +140,14 @@ __global__ __launch_bounds__(kBlock) void k_mf_cg_gather(Dev d, const double* __
     const int64_t i = lb * kBlock + threadIdx.x;
     double v[1] = {0.0};
     if (i < d.nc && msc(d, row_mesh(g, i))[SC_DONE] == 0.0) {
-        const double y = gather_row(d, F, i);
-        d.q[i] = y;
-        v[0] = d.p[i] * y;
+        const R y = gather_row(d, F, i);
+        if constexpr (std::is_same<R, double>::value) {
+            d.q[i] = y;
+            v[0] = d.p[i] * y;
+        } else {
+            d.q32[i] = y;
+            v[0] = double(d.p32[i]) * double(y);
+        }
     }
     seg_publish_at<1>(d, g, v, i >= g.split, lds, lb, nblk);
 }
@@ -126,33 +156,60 @@ __global__ __launch_bounds__(kBlock) void k_mf_cg_gather(Dev d, const double* __
 
 hipError_t launch_mf_apply(const Dev& d, const BcTable& bc, const double* x, double* y, hipStream_t s,
                            const double* skip) {
-    hipLaunchKernelGGL(k_mf_ghost, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d, bc, x,
-                       d.mf_xg, skip);
-    hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, x, d.mf_xg, d.mf_xv, skip);
-    hipLaunchKernelGGL(k_mf_face, dim3(rows_m(d.nf, kBlock)), dim3(kBlock), 0, s, d, bc, x, d.mf_xv, d.mf_flux, skip);
+    if (d.nb > 0)
+        hipLaunchKernelGGL(k_mf_ghost<double>, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           d, bc, x, d.mf_xg, skip);
+    hipLaunchKernelGGL(k_mf_vertex<double>, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, x, d.mf_xg,
+                       d.mf_xv, skip);
+    hipLaunchKernelGGL(k_mf_face<double>, dim3(rows_m(d.nf, kBlock)), dim3(kBlock), 0, s, d, bc, x, d.mf_xv,
+                       d.mf_flux, skip);
     hipLaunchKernelGGL(k_mf_gather, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, d.mf_flux, y, skip);
     return hipGetLastError();
 }
 
-hipError_t launch_mf_cg_part(const Dev& d, const BcTable& bc, int part, hipStream_t s) {
+namespace {
+// one part of q = K p (FP64 p, or FP32 p32 into the same scratch arrays
+// taken as floats)
+template <class R>
+void mf_cg_part(const Dev& d, const BcTable& bc, int part, const R* p, hipStream_t s) {
     const double* none = nullptr;
+    R* xg = reinterpret_cast<R*>(d.mf_xg);
+    R* xv = reinterpret_cast<R*>(d.mf_xv);
+    R* F = reinterpret_cast<R*>(d.mf_flux);
     if (part == 0) {
-        hipLaunchKernelGGL(k_mf_ghost, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d, bc, d.p,
-                           d.mf_xg, none);
-        hipLaunchKernelGGL(k_mf_vertex, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, d.p, d.mf_xg, d.mf_xv, none);
+        if (d.nb > 0)
+            hipLaunchKernelGGL(k_mf_ghost<R>, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d,
+                               bc, p, xg, none);
+        hipLaunchKernelGGL(k_mf_vertex<R>, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, p, xg, xv, none);
     } else if (part == 1) {
-        hipLaunchKernelGGL(k_mf_face, dim3(rows_m(d.nf, kBlock)), dim3(kBlock), 0, s, d, bc, d.p, d.mf_xv, d.mf_flux, none);
+        hipLaunchKernelGGL(k_mf_face<R>, dim3(rows_m(d.nf, kBlock)), dim3(kBlock), 0, s, d, bc, p, xv, F, none);
     } else {
         const int64_t nblk = (d.nc + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(k_mf_cg_gather, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, d.mf_flux, nblk);
+        hipLaunchKernelGGL(k_mf_cg_gather<R>, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, F, nblk);
         hipLaunchKernelGGL(k_cg_alpha<1>, dim3(d.nm), dim3(1024), 0, s, d, nblk, int64_t(kBlock));
     }
+}
+}  // namespace
+
+hipError_t launch_mf_cg_part(const Dev& d, const BcTable& bc, int part, hipStream_t s) {
+    mf_cg_part<double>(d, bc, part, d.p, s);
     return hipGetLastError();
 }
 
 hipError_t launch_mf_cg_spmv(const Dev& d, const BcTable& bc, hipStream_t s) {
     hipError_t e = hipSuccess;
     for (int part = 0; part < 3 && e == hipSuccess; ++part) e = launch_mf_cg_part(d, bc, part, s);
+    return e;
+}
+
+hipError_t launch_mf_cg32_part(const Dev& d, const BcTable& bc, int part, hipStream_t s) {
+    mf_cg_part<float>(d, bc, part, d.p32, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_mf_cg32_spmv(const Dev& d, const BcTable& bc, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int part = 0; part < 3 && e == hipSuccess; ++part) e = launch_mf_cg32_part(d, bc, part, s);
     return e;
 }
 

@@ -182,11 +182,16 @@ hipError_t launch_mf_cg_spmv(const Dev& d, const BcTable& bc, hipStream_t s);
 // the three launches of launch_mf_cg_spmv one by one (part 0 vertex values,
 // 1 face fluxes, 2 gather + p.q + alpha), for per-kernel timing
 hipError_t launch_mf_cg_part(const Dev& d, const BcTable& bc, int part, hipStream_t s);
+// the same product in FP32 for the inner CG of the refined solve: q32 = K p32
+// with the FP32 coefficient copies, partial p32.q32 in FP64
+hipError_t launch_mf_cg32_spmv(const Dev& d, const BcTable& bc, hipStream_t s);
+hipError_t launch_mf_cg32_part(const Dev& d, const BcTable& bc, int part, hipStream_t s);
 
 // launchers (ir_kernels.hip): FP32 inner CG inside FP64 iterative refinement
 hipError_t launch_cast_matrix(const Dev& d, int64_t padded, hipStream_t s);
+// kx: K x computed by the caller (matrix-free), or null for the stored K
 hipError_t launch_ir_residual(const Dev& d, double tol, double tol_in, int maxit, int restart, bool fresh,
-                              hipStream_t s);
+                              const double* kx, hipStream_t s);
 hipError_t launch_cg32_spmv(const Dev& d, hipStream_t s);
 hipError_t launch_cg32_axpy(const Dev& d, hipStream_t s);
 hipError_t launch_cg32_dir(const Dev& d, hipStream_t s);

@@ -91,21 +91,57 @@ def test_matrix_free_solve_accepted_by_oracle(case):
     assert np.array_equal(x1, host(st.get_field(B.FIELD_P)))
 
 
+@pytest.mark.parametrize("case", list(CASES))
+def test_refined_fp32_matrix_free_solve_accepted_by_oracle(case):
+    """Iterative refinement whose FP32 inner CG applies K matrix-free (FP32
+    vertex weights and diamond coefficients) and whose FP64 true residual
+    uses the FP64 matrix-free product: accepted by the oracle's K, in as
+    many outer steps as with the FP32 stored matrix give or take one, and a
+    captured chunk gives the direct launches' result."""
+    n, seed, kinds, vals = CASES[case]
+    print(f"[gpu] refined FP32 matrix-free solve case={case}", flush=True)
+    mp = Mapped(n, seed)
+    st = B.State(mp.lib)
+    st.set_bcs(B.VAR_POTENTIAL, kinds, vals)
+    st.poisson_assemble()
+    f = synth.gaussian_field(mp.m)
+    ref = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_IR_FP32)
+    st.set_field(B.FIELD_P, dev(np.zeros(mp.geo.nc)))
+    info = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_IR_FP32, matrix_free=True)
+    print(f"[gpu] {case}: stored K32 {ref['iterations']} it / {ref['outer']} outer, "
+          f"matrix-free {info['iterations']} it / {info['outer']} outer", flush=True)
+    assert info["status"] == B.OK and info["rel_residual"] <= 1e-10 and info["outer"] >= 2
+    assert abs(info["outer"] - ref["outer"]) <= 1
+    K, c = poisson.assemble(mp.geo, kinds, vals)
+    b = poisson.rhs(mp.geo, f, c)
+    x = host(st.get_field(B.FIELD_P))
+    assert poisson.true_relative_residual(K, b, x) <= 1.01e-10
+    st.set_field(B.FIELD_P, dev(np.zeros(mp.geo.nc)))
+    g1 = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_IR_FP32, matrix_free=True, chunk=16, graph=1)
+    x1 = host(st.get_field(B.FIELD_P))
+    st.set_field(B.FIELD_P, dev(np.zeros(mp.geo.nc)))
+    g0 = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_IR_FP32, matrix_free=True, chunk=16, graph=0)
+    assert g1["iterations"] == g0["iterations"]
+    assert np.array_equal(x1, host(st.get_field(B.FIELD_P)))
+
+
 def test_matrix_free_batch_and_learned():
     ms = [cube(4, 1000), cube(6, 1002)]
     batch = B.State(B.Mesh.from_batch(ms))
     batch.set_bcs(B.VAR_POTENTIAL, [DIRICHLET] * 6)
     batch.poisson_assemble()
     f = np.concatenate([synth.gaussian_field(m) for m in ms])
-    info = batch.poisson_solve(dev(f), tol=1e-10, matrix_free=True)
-    assert info["status"] == B.OK
-    x = host(batch.get_field(B.FIELD_P))
     off = np.cumsum([0] + [m.nc for m in ms])
-    for k, (n, seed) in enumerate(((4, 1000), (6, 1002))):
-        g = cube_geometry(n, seed)
-        K, c = poisson.assemble(g, [DIRICHLET] * 6, [0.0] * 6)
-        b = poisson.rhs(g, f[off[k]:off[k + 1]], c)
-        assert poisson.true_relative_residual(K, b, x[off[k]:off[k + 1]]) <= 1.01e-10
+    for method in (B.SOLVE_PLAIN, B.SOLVE_IR_FP32):
+        batch.set_field(B.FIELD_P, dev(np.zeros(int(off[-1]))))
+        info = batch.poisson_solve(dev(f), tol=1e-10, matrix_free=True, method=method)
+        assert info["status"] == B.OK
+        x = host(batch.get_field(B.FIELD_P))
+        for k, (n, seed) in enumerate(((4, 1000), (6, 1002))):
+            g = cube_geometry(n, seed)
+            K, c = poisson.assemble(g, [DIRICHLET] * 6, [0.0] * 6)
+            b = poisson.rhs(g, f[off[k]:off[k + 1]], c)
+            assert poisson.true_relative_residual(K, b, x[off[k]:off[k + 1]]) <= 1.01e-10
     # flexible CG with the (untrained: Jacobi) network and the matrix-free operator
     m = cube(8, 1003)
     st = B.State(B.Mesh.from_cube(m))
