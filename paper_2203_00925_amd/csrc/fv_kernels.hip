@@ -3,11 +3,11 @@
 //
 // One residual evaluation is three gather kernels, each owner-computes and
 // free of atomics:
-//   k_grad_limiter  per cell: least-squares gradient over the node-neighbour
-//                   stencil (Algorithm 1), then the Barth-Jespersen limiter
-//                   over the 4 face neighbours; the same kernel computes the
-//                   vertex values of the least-squares interpolation
-//                   (Algorithm 2);
+//   k_grad_moments  per tile of cells (FP64): least-squares gradient
+//   k_grad_limiter  (Algorithm 1; star-moment form, resp. the stencil sum in
+//                   the FP32 form), then the Barth-Jespersen limiter over the
+//                   4 face neighbours; the same kernel computes the vertex
+//                   values of the least-squares interpolation (Algorithm 2);
 //   k_face_flux     per face: MUSCL upwind convective flux (eq. (15)) minus
 //                   the diamond diffusive flux (eq. (diamond)), written once;
 //   k_update        per cell: gathers its 4 face fluxes with their signs.
