@@ -105,6 +105,7 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.phi = carve<double>(base, off, nf);
     d.grad = carve<double>(base, off, 3 * nc);
     d.psi = carve<double>(base, off, nc);
+    d.rec = carve<double4>(base, off, nc);
     d.unode = carve<double>(base, off, nv);
     d.flux = carve<double>(base, off, nf);
     d.x = carve<double>(base, off, nc);
@@ -506,11 +507,11 @@ int mifvm_cfl_dt(mifvm_state* st, double cfl, double* dt_out, void* stream) {
 
 namespace {
 // ghost fill, gradient + limiter + vertex values, face fluxes
-int residual_parts(State& s, hipStream_t hs) {
+int residual_parts(State& s, hipStream_t hs, bool parts = false) {
     const Dev& d = s.d;
     KernelTimer& t = s.timer;
     HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, s.fp32, s.bc[0], hs); }));
-    HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, s.fp32, hs); }));
+    HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, s.fp32, hs, parts); }));
     HIPCHK(timed(t, MIFVM_K_FACE_FLUX, hs, [&] { return launch_face_flux(d, s.fp32, s.bc[0], hs); }));
     return MIFVM_OK;
 }
@@ -574,7 +575,7 @@ int mifvm_residual(mifvm_state* st, double* d_res, double* d_grad, double* d_psi
     State& s = st->s;
     const Dev& d = s.d;
     hipStream_t hs = S(stream);
-    int rc = residual_parts(s, hs);
+    int rc = residual_parts(s, hs, d_grad != nullptr || d_psi != nullptr);
     if (rc) return rc;
     if (d_res) {
         HIPCHK(launch_residual_out(d, s.fp32, d.tmp, hs));

@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d, FvArrays<R> a) {
 //   s = sum (x_j - x_0), q = sum (u_j - u_0), c = sum (x_j - x_0)(u_j - u_0),
 //   xb = x_0 + s/n, ub = u_0 + q/n, C = c - s q/n;
 // own vertices also store u_v = sum alpha u_j (Algorithm 2).
-template <class R>
+template <class R, bool PARTS>
 __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
     using V2 = typename Vec2T<R>::T;
     using V4 = typename Vec4T<R>::T;
@@ -424,9 +424,6 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
     const R gx = m0 * jx + m1 * jy + m2 * jz;
     const R gy = m1 * jx + m3 * jy + m4 * jz;
     const R gz = m2 * jx + m4 * jy + m5 * jz;
-    a.grad[i] = gx;
-    a.grad[nc + i] = gy;
-    a.grad[2 * nc + i] = gz;
     R psi = R(1);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -437,7 +434,15 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
         else if (dl < R(0)) ph = fmin(R(1), (umin - ui) / dl);
         psi = fmin(psi, ph);
     }
-    a.psi[i] = psi;
+    // the face kernel's upwind data in one record; the separate arrays only
+    // when the caller asks for them
+    d.rec[i] = make_double4(psi * gx, psi * gy, psi * gz, ui);
+    if (PARTS) {
+        a.grad[i] = gx;
+        a.grad[nc + i] = gy;
+        a.grad[2 * nc + i] = gz;
+        a.psi[i] = psi;
+    }
 }
 
 template <class R>
@@ -461,20 +466,42 @@ __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTa
     const R D = R(d.mesh_D[mesh_of(d, L)]);
     const R ph = a.phi[f];
     const int up = ph >= R(0) ? L : Rc;
-    R uup = u[up];
-    if (up < nc) {   // MUSCL reconstruction at the face centroid (ghost side: first order)
-        const R rx = a.fx[f] - a.xc[up];
-        const R ry = a.fx[nf + f] - a.xc[NX + up];
-        const R rz = a.fx[2 * nf + f] - a.xc[2 * NX + up];
-        const R gr = a.grad[up] * rx + a.grad[nc + up] * ry + a.grad[2 * nc + up] * rz;
-        uup = uup + a.psi[up] * gr;
+    R uup, uL, uR;
+    if constexpr (std::is_same<R, double>::value) {
+        // FP64: the upwind cell's record (psi g, u) and centre; the other
+        // side's value from u
+        const int dn = up == L ? Rc : L;
+        const R udn = u[dn];
+        R ucell;
+        if (up < nc) {   // MUSCL reconstruction at the face centroid (ghost side: first order)
+            const double4 rc = d.rec[up];
+            const double4 pc = d.xyz4[up];
+            ucell = rc.w;
+            uup = ucell + (rc.x * (a.fx[f] - pc.x) + rc.y * (a.fx[nf + f] - pc.y) + rc.z * (a.fx[2 * nf + f] - pc.z));
+        } else {
+            ucell = u[up];
+            uup = ucell;
+        }
+        uL = up == L ? ucell : udn;
+        uR = up == L ? udn : ucell;
+    } else {
+        uup = u[up];
+        if (up < nc) {   // MUSCL reconstruction at the face centroid (ghost side: first order)
+            const R rx = a.fx[f] - a.xc[up];
+            const R ry = a.fx[nf + f] - a.xc[NX + up];
+            const R rz = a.fx[2 * nf + f] - a.xc[2 * NX + up];
+            const R gr = a.grad[up] * rx + a.grad[nc + up] * ry + a.grad[2 * nc + up] * rz;
+            uup = uup + a.psi[up] * gr;
+        }
+        uL = u[L];
+        uR = u[Rc];
     }
     R diff;
     if (kind == kNeumann) {
         diff = val * a.area[f];
     } else {
         const R uA = a.unode[d.fA[f]], uB = a.unode[d.fB[f]], uC = a.unode[d.fC[f]];
-        diff = a.kAC[f] * (uA - uC) + a.kBC[f] * (uB - uC) + a.kRL[f] * (u[Rc] - u[L]);
+        diff = a.kAC[f] * (uA - uC) + a.kBC[f] * (uB - uC) + a.kRL[f] * (uR - uL);
     }
     a.flux[f] = uup * ph - D * diff;
 }
@@ -662,18 +689,24 @@ size_t moments_lds_bytes(const Dev& d) {
 hipError_t setup_fv_kernels(const Dev& d) {
     const size_t lds = moments_lds_bytes(d);
     if (lds <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_moments<double>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_moments<double, false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_moments<double, true>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
 }
 
-hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s) {
+hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool parts) {
     const dim3 g(unsigned(d.ntiles)), b(d.tile_rows);
     if (fp32) {
         hipLaunchKernelGGL(k_grad_limiter<float>, g, b, size_t(d.halo_max) * sizeof(float4), s, d, fv32(d));
     } else {
         // grid padded to a multiple of 8 for the XCD-contiguous tile order
-        hipLaunchKernelGGL(k_grad_moments<double>, dim3(unsigned((d.ntiles + kXcds - 1) / kXcds * kXcds)), b,
-                           moments_lds_bytes(d), s, d, fv64(d));
+        const dim3 gx(unsigned((d.ntiles + kXcds - 1) / kXcds * kXcds));
+        if (parts)
+            hipLaunchKernelGGL((k_grad_moments<double, true>), gx, b, moments_lds_bytes(d), s, d, fv64(d));
+        else
+            hipLaunchKernelGGL((k_grad_moments<double, false>), gx, b, moments_lds_bytes(d), s, d, fv64(d));
     }
     return hipGetLastError();
 }

@@ -68,6 +68,8 @@ struct Dev {
     // fields
     double *u, *un, *src, *vel, *phi;     // u: nc+nb (ghosts behind), vel 3 x nc
     double *grad, *psi, *unode, *flux;    // grad 3 x nc
+    double4* rec;                         // nc: (psi g, u) per cell, the upwind data the FP64
+                                          // face fluxes read
     // solver vectors (P lives in x)
     double *x, *r, *z, *p, *q, *b;
     // reduced-precision (FP32) form of the step
@@ -147,7 +149,9 @@ size_t layout(const Mesh& m, char* base, Dev& d);
 
 // launchers (fv_kernels.hip)
 hipError_t launch_ghost_fill(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
-hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s);
+// parts: also write the gradient and limiter arrays (FP64 writes the packed
+// upwind records always; FP32 writes the arrays always)
+hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool parts = false);
 // once per state: kernel attributes (LDS above 64 KB for large tile halos)
 hipError_t setup_fv_kernels(const Dev& d);
 hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
