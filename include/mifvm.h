@@ -236,6 +236,9 @@ void mifvm_mesh_destroy(mifvm_mesh* mesh);
  *  13 GHOST_OWNER int32 [nb]
  *  14 GHOST_TAG   int32 [nb]
  *  15 MINV        f64   [6][nc]     xx, xy, xz, yy, yz, zz of M_i^{-1}
+ *  16 EDGE_NBR_PTR int64 [nc+1]     CSR over internal cells of the entities
+ *  17 EDGE_NBR_IDX int32 [edge_nbr_entries]  sharing exactly two vertices
+ *                                    with the cell (cell or nc+ghost, ascending)
  * bytes must equal the array's size exactly (E_ARG otherwise).            */
 int mifvm_mesh_export(const mifvm_mesh* mesh, int32_t what, void* dst, size_t bytes);
 

@@ -46,6 +46,8 @@ EXPORTS = {  # id: (name, dtype, shape-fn(info))
     13: ("ghost_owner", np.int32, lambda i: (i.nb,)),
     14: ("ghost_tag", np.int32, lambda i: (i.nb,)),
     15: ("minv", np.float64, lambda i: (6, i.nc)),
+    16: ("edge_nbr_ptr", np.int64, lambda i: (i.nc + 1,)),
+    17: ("edge_nbr_idx", np.int32, lambda i: (i.edge_nbr_entries,)),
 }
 EXPORT_IDS = {v[0]: k for k, v in EXPORTS.items()}
 

@@ -259,6 +259,8 @@ int mifvm_mesh_export(const mifvm_mesh* mesh, int32_t what, void* dst, size_t by
         case 13: src = m.gowner.data(); n = m.gowner.size() * 4; break;
         case 14: src = m.gtag.data(); n = m.gtag.size() * 4; break;
         case 15: src = m.minv.data(); n = m.minv.size() * 8; break;
+        case 16: src = m.eptr.data(); n = m.eptr.size() * 8; break;
+        case 17: src = m.eidx.data(); n = m.eidx.size() * 4; break;
         default: return fail(MIFVM_E_ARG, "unknown export id");
     }
     if (bytes != n) return fail(MIFVM_E_ARG, "size mismatch: expected " + std::to_string(n) + " bytes");

@@ -73,6 +73,59 @@ def test_stencil_and_gradient_matrix(mapped):
         assert np.allclose(mine, Mi, rtol=1e-11, atol=1e-11 * np.abs(Mi).max())
 
 
+def test_star_moment_tables_and_identity(mapped):
+    """The tables of the star-moment form of Algorithm 1.  Over the 4 vertex
+    lists of a cell (the oracle's, user numbering) every stencil entity
+    appears once per vertex it shares with the cell: the library's
+    edge-only list is exactly the entities counted twice, the face
+    neighbours are counted three times and the cell itself four times.  With
+    those sets the stencil sum J_i = sum (x_j - x_i)(u_j - u_i) equals
+    sum over the vertex lists of [C_L + n_L (xbar_L - x_i)(ubar_L - u_i)]
+    minus the edge-only terms minus twice the face-neighbour terms, for
+    random u (brute force against the oracle's stencil)."""
+    g, L, m = mapped.geo, mapped.lib, mapped.m
+    eptr, eidx = L.export("edge_nbr_ptr"), L.export("edge_nbr_idx")
+    assert eptr[-1] == L.info.edge_nbr_entries
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=g.nc + g.nb) + 3.0      # an offset: the form must not cancel it
+    x = g.xc
+    # per vertex list: n, mean position, mean value, centred moment
+    nl = np.diff(g.nptr)
+    own = np.repeat(np.arange(g.nv), nl)
+    xb = np.zeros((g.nv, 3)); ub = np.zeros(g.nv)
+    np.add.at(xb, own, x[g.nidx]); np.add.at(ub, own, u[g.nidx])
+    xb /= nl[:, None]; ub /= nl
+    C = np.zeros((g.nv, 3))
+    np.add.at(C, own, (x[g.nidx] - xb[own]) * (u[g.nidx] - ub[own])[:, None])
+    worst = 0.0
+    for i in range(0, g.nc, max(1, g.nc // 300)):
+        c = mapped.cp[i]
+        count = {}
+        for v in g.tets[c]:
+            for e in g.nidx[g.nptr[v]:g.nptr[v + 1]]:
+                count[int(e)] = count.get(int(e), 0) + 1
+        assert count.pop(int(c)) == 4
+        sten = g.sidx[g.sptr[c]:g.sptr[c + 1]]
+        assert sorted(count) == sorted(sten.tolist())
+        two = sorted(e for e, k in count.items() if k == 2)
+        three = sorted(e for e, k in count.items() if k == 3)
+        assert max(count.values()) == 3
+        assert sorted(mapped.ent_to_user(eidx[eptr[i]:eptr[i + 1]]).tolist()) == two
+        nbr = sorted(int(np.where(g.fL[f] == c, g.fR[f], g.fL[f])) for f in g.cfaces[c])
+        assert three == nbr
+        d = x[sten] - x[c]
+        direct = (d * (u[sten] - u[c])[:, None]).sum(0)
+        mom = np.zeros(3)
+        for v in g.tets[c]:
+            mom += C[v] + nl[v] * (xb[v] - x[c]) * (ub[v] - u[c])
+        for e in two:
+            mom -= (x[e] - x[c]) * (u[e] - u[c])
+        for e in three:
+            mom -= 2.0 * (x[e] - x[c]) * (u[e] - u[c])
+        worst = max(worst, np.abs(mom - direct).max() / np.abs(direct).max())
+    assert worst < 1e-12, worst
+
+
 def test_vertex_weights(mapped):
     g, L = mapped.geo, mapped.lib
     ptr, idx, al = L.export("node_ptr"), L.export("node_idx"), L.export("node_alpha")
