@@ -70,7 +70,10 @@ enum mifvm_field {
     MIFVM_FIELD_U = 0,        /* transported scalar u                        */
     MIFVM_FIELD_VEL = 1,      /* velocity, 3*Nc values laid out [x..., y..., z...] */
     MIFVM_FIELD_SOURCE = 2,   /* source S_i of eq. (1)                        */
-    MIFVM_FIELD_P = 3         /* Poisson unknown (last solution)              */
+    MIFVM_FIELD_P = 3,        /* Poisson unknown (last solution)              */
+    MIFVM_FIELD_ION = 4,      /* positive-ion density n_p of the coupled loop  */
+    MIFVM_FIELD_EFIELD = 5    /* E = -grad P of the last coupled step, 3*Nc values
+                                 [x..., y..., z...] (get only)                */
 };
 
 enum mifvm_renumber { MIFVM_RENUMBER_NONE = 0, MIFVM_RENUMBER_MORTON = 1 };
@@ -336,6 +339,47 @@ typedef struct {
 } mifvm_tune_info;
 int mifvm_step_graph(mifvm_state* st, int32_t n_steps, double dt, void* stream);
 int mifvm_autotune(mifvm_state* st, const char* cache_path, mifvm_tune_info* out, void* stream);
+
+/* ---- coupled streamer-type loop (Sec. 4, eq. (10)) -------------------------
+ * One species in drift-diffusion coupled to the electrostatic potential:
+ *     d n_e/dt + div(n_e v_e) - div(D grad n_e) = S_e,   d n_p/dt = S_e,
+ *     Delta P = kappa (n_e - n_p),   E = -grad P,
+ *     v_e = -mu E,   S_e = alpha(|E|) |v_e| n_e,   alpha(|E|) = a exp(-b/|E|).
+ * n_e is FIELD_U with the SCALAR boundary conditions and the state's
+ * diffusivity D; P is FIELD_P with the POTENTIAL boundary conditions (the
+ * system must be assembled); n_p is FIELD_ION.  The paper's C1, C2 and its
+ * ionisation fit are not usable as printed, so the mobility is a constant
+ * and alpha a Townsend-type law with caller constants (a = 0: no source).
+ * Each step: P from the Poisson solve (warm-started from the last P; PLAIN
+ * or, with matrix_free, on the matrix-free product), E = -grad P by the
+ * least-squares gradient of Algorithm 1 (ghosts from the POTENTIAL
+ * conditions), v_e and S_e per cell, the face velocities (as FIELD_VEL
+ * does), dt = cfl times each mesh's CFL bound, one RK3 step of n_e with S_e
+ * held over the step, and n_p += dt S_e.  FP64 states only (E_STATE for
+ * FP32).  A solve that does not converge ends the call with its status.  */
+typedef struct {
+    double mobility;           /* mu (>= 0)                                   */
+    double charge_scale;       /* kappa (e / epsilon)                         */
+    double alpha_a, alpha_b;   /* ionisation law constants (>= 0)             */
+    double cfl;                /* > 0                                         */
+    double tol;                /* Poisson tolerance (0 = 1e-10)               */
+    int32_t maxit;             /* per solve (0 = 20000)                       */
+    int32_t restart;           /* as mifvm_solve_opts (0 = 500)               */
+    int32_t matrix_free;
+    int32_t pad_;
+} mifvm_streamer_opts;
+
+typedef struct {
+    int32_t steps;             /* steps taken                                 */
+    int32_t iterations_max;    /* largest CG iteration count of a step        */
+    int64_t iterations_sum;
+    double time;               /* sum of the steps' dt (the smallest over the
+                                  meshes of a batch)                         */
+    double last_dt;
+} mifvm_streamer_info;
+
+int mifvm_streamer_step(mifvm_state* st, int32_t n_steps, const mifvm_streamer_opts* opts,
+                        mifvm_streamer_info* info, void* stream);
 
 /* ---- per-kernel timing (HIP events on the launch stream) -----------------
  * enable != 0 starts recording an event pair around every kernel launch of

@@ -19,7 +19,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "li
 OK, NOT_CONVERGED, FELL_BACK = 0, 1, 2
 ZERO_FLUX, NEUMANN, DIRICHLET = 0, 1, 2
 VAR_SCALAR, VAR_POTENTIAL = 0, 1
-FIELD_U, FIELD_VEL, FIELD_SOURCE, FIELD_P = 0, 1, 2, 3
+FIELD_U, FIELD_VEL, FIELD_SOURCE, FIELD_P, FIELD_ION, FIELD_EFIELD = 0, 1, 2, 3, 4, 5
 RENUMBER_NONE, RENUMBER_MORTON = 0, 1
 SOLVE_PLAIN, SOLVE_IR_FP32, SOLVE_LEARNED, SOLVE_FGMRES = 0, 1, 2, 3
 FP64, FP32 = 0, 1
@@ -100,6 +100,18 @@ class SolveInfo(C.Structure):
                 ("history_len", C.c_int32), ("outer", C.c_int32),
                 ("rel_residual", C.c_double), ("ms", C.c_double),
                 ("fell_back", C.c_int32), ("learned_iterations", C.c_int32)]
+
+
+class StreamerOpts(C.Structure):
+    _fields_ = [("mobility", C.c_double), ("charge_scale", C.c_double), ("alpha_a", C.c_double),
+                ("alpha_b", C.c_double), ("cfl", C.c_double), ("tol", C.c_double),
+                ("maxit", C.c_int32), ("restart", C.c_int32), ("matrix_free", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
+class StreamerInfo(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("iterations_max", C.c_int32), ("iterations_sum", C.c_int64),
+                ("time", C.c_double), ("last_dt", C.c_double)]
 
 
 class _NnOpts(C.Structure):
@@ -307,7 +319,7 @@ class State:
 
     def get_field(self, field, stream=None):
         import torch
-        n = self.mesh.info.nc * (3 if field == FIELD_VEL else 1)
+        n = self.mesh.info.nc * (3 if field in (FIELD_VEL, FIELD_EFIELD) else 1)
         out = torch.empty(n, dtype=torch.float64, device=self.device)
         _check(_lib.mifvm_get_field(self._h, field, _ptr(out), _stream(stream)))
         return out
@@ -323,6 +335,18 @@ class State:
 
     def step_graph(self, n_steps, dt, stream=None):
         _check(_lib.mifvm_step_graph(self._h, int(n_steps), float(dt), _stream(stream)))
+
+    def streamer_step(self, n_steps, mobility, charge_scale, alpha_a=0.0, alpha_b=0.0, cfl=0.4,
+                      tol=1e-10, maxit=0, restart=0, matrix_free=False, stream=None):
+        """Coupled loop (mifvm_streamer_step): n_e = FIELD_U, n_p = FIELD_ION,
+        P = FIELD_P; returns the step count, CG iterations and simulated time."""
+        opts = StreamerOpts(float(mobility), float(charge_scale), float(alpha_a), float(alpha_b),
+                            float(cfl), float(tol), int(maxit), int(restart), 1 if matrix_free else 0, 0)
+        info = StreamerInfo()
+        _check(_lib.mifvm_streamer_step(self._h, int(n_steps), C.byref(opts), C.byref(info),
+                                        _stream(stream)))
+        return {"steps": info.steps, "iterations_max": info.iterations_max,
+                "iterations_sum": info.iterations_sum, "time": info.time, "last_dt": info.last_dt}
 
     def autotune(self, cache_path=None, stream=None):
         info = TuneInfo()

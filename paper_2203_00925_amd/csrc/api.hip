@@ -133,6 +133,8 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.xc32 = carve<float>(base, off, 3 * NX);
     d.gdist32 = carve<float>(base, off, nb);
     d.tmp = carve<double>(base, off, 3 * NX);
+    d.np_ion = carve<double>(base, off, nc);
+    d.efield = carve<double>(base, off, 3 * nc);
     d.mf_xv = carve<double>(base, off, nv);
     d.mf_flux = carve<double>(base, off, nf);
     d.mf_xg = carve<double>(base, off, nb > 0 ? nb : 1);
@@ -351,6 +353,8 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     if (e == hipSuccess) e = hipMemsetAsync(d.vel, 0, 3 * m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.phi, 0, m.nf * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.x, 0, m.nc * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.np_ion, 0, m.nc * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.efield, 0, 3 * m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.scal, 0, size_t(d.nm) * SC_COUNT_ * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.u32, 0, NX * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.src32, 0, m.nc * sizeof(float), s);
@@ -460,6 +464,11 @@ int mifvm_set_field(mifvm_state* st, int32_t field, const double* d_src, void* s
         case MIFVM_FIELD_P:
             HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.x, hs));
             break;
+        case MIFVM_FIELD_ION:
+            HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.np_ion, hs));
+            break;
+        case MIFVM_FIELD_EFIELD:
+            return fail(MIFVM_E_ARG, "FIELD_EFIELD is computed by mifvm_streamer_step (get only)");
         default:
             return fail(MIFVM_E_ARG, "unknown field");
     }
@@ -482,6 +491,10 @@ int mifvm_get_field(const mifvm_state* st, int32_t field, double* d_dst, void* s
         case MIFVM_FIELD_VEL: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 3, d.vel, d_dst, hs)); break;
         case MIFVM_FIELD_SOURCE: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.src, d_dst, hs)); break;
         case MIFVM_FIELD_P: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.x, d_dst, hs)); break;
+        case MIFVM_FIELD_ION: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.np_ion, d_dst, hs)); break;
+        case MIFVM_FIELD_EFIELD:
+            HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 3, d.efield, d_dst, hs));
+            break;
         default: return fail(MIFVM_E_ARG, "unknown field");
     }
     return MIFVM_OK;
@@ -650,8 +663,14 @@ int mifvm_poisson_apply(mifvm_state* st, const double* d_x, double* d_y, void* s
 }
 
 namespace {
-int rhs_internal(State& s, const double* d_f, hipStream_t hs) {
+// f_internal: a right-hand side already in internal order (the coupled loop)
+int rhs_internal(State& s, const double* d_f, hipStream_t hs, const double* f_internal = nullptr) {
     const Dev& d = s.d;
+    if (f_internal) {
+        HIPCHK(timed(s.timer, MIFVM_K_RHS, hs, [&] { return launch_rhs(d, f_internal, hs); }));
+        s.b_ready = true;
+        return MIFVM_OK;
+    }
     if (d_f) HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_f, d.tmp, hs));
     else if (s.fp32) HIPCHK(launch_cast_to_f64(d.nc, d.u32, d.tmp, hs));   // f = the FP32 state, widened
     const double* f = (d_f || s.fp32) ? d.tmp : d.u;
@@ -672,8 +691,19 @@ int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* str
     return MIFVM_OK;
 }
 
+namespace {
+int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, const mifvm_solve_opts* opts,
+               mifvm_solve_info* info, void* stream);
+}
+
 int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_opts* opts,
                         mifvm_solve_info* info, void* stream) {
+    return solve_impl(st, d_f, nullptr, opts, info, stream);
+}
+
+namespace {
+int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, const mifvm_solve_opts* opts,
+               mifvm_solve_info* info, void* stream) {
     if (!st) return fail(MIFVM_E_ARG, "null state");
     State& s = st->s;
     if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
@@ -709,7 +739,7 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
     hipStream_t hs = S(stream);
     s.mf = matrix_free;
     auto t0 = std::chrono::steady_clock::now();
-    int rc = rhs_internal(s, d_f, hs);
+    int rc = rhs_internal(s, d_f, hs, f_internal);
     if (rc) return rc;
     KernelTimer& tm = s.timer;
     int nhist = 0;
@@ -898,6 +928,57 @@ int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_op
     }
     if (!(rel <= tol)) return MIFVM_NOT_CONVERGED;
     return learned.fell_back ? MIFVM_FELL_BACK : MIFVM_OK;
+}
+}  // namespace
+
+int mifvm_streamer_step(mifvm_state* st, int32_t n_steps, const mifvm_streamer_opts* opts,
+                        mifvm_streamer_info* info, void* stream) {
+    if (!st || !opts) return fail(MIFVM_E_ARG, "null argument");
+    State& s = st->s;
+    if (n_steps < 0) return fail(MIFVM_E_ARG, "n_steps must be >= 0");
+    if (!(opts->mobility >= 0) || !std::isfinite(opts->mobility) || !std::isfinite(opts->charge_scale) ||
+        !(opts->alpha_a >= 0) || !std::isfinite(opts->alpha_a) || !(opts->alpha_b >= 0) ||
+        !std::isfinite(opts->alpha_b) || !(opts->cfl > 0) || !std::isfinite(opts->cfl) || opts->tol < 0 ||
+        opts->maxit < 0 || opts->restart < 0)
+        return fail(MIFVM_E_ARG, "bad streamer options");
+    if (s.fp32) return fail(MIFVM_E_STATE, "the coupled loop runs on FP64 states");
+    if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
+    const Dev& d = s.d;
+    hipStream_t hs = S(stream);
+    mifvm_solve_opts so{};
+    so.tol = opts->tol > 0 ? opts->tol : 1e-10;
+    so.maxit = opts->maxit > 0 ? opts->maxit : 20000;
+    so.restart = opts->restart > 0 ? opts->restart : 500;
+    so.method = MIFVM_SOLVE_PLAIN;
+    so.graph = -1;
+    so.matrix_free = opts->matrix_free ? 1 : 0;
+    mifvm_streamer_info out{};
+    for (int n = 0; n < n_steps; ++n) {
+        // Delta P = kappa (n_e - n_p), warm-started from the last P
+        HIPCHK(launch_streamer_rhs(d, opts->charge_scale, d.tmp, hs));
+        mifvm_solve_info si{};
+        int rc = solve_impl(st, nullptr, d.tmp, &so, &si, stream);
+        out.iterations_max = std::max(out.iterations_max, si.iterations);
+        out.iterations_sum += si.iterations;
+        if (rc) {
+            if (info) *info = out;
+            return rc;
+        }
+        // E, v_e and S_e per cell; face velocities; the CFL step; n_p
+        HIPCHK(launch_streamer_fields(d, s.bc[1], opts->mobility, opts->alpha_a, opts->alpha_b, hs));
+        HIPCHK(launch_face_phi(d, hs));
+        s.vel_set = true;
+        double dt = 0.0;
+        if ((rc = mifvm_cfl_dt(st, opts->cfl, &dt, stream))) return rc;
+        if ((rc = mifvm_step(st, 1, 0.0, stream))) return rc;
+        HIPCHK(launch_ion_update(d, hs));
+        out.steps += 1;
+        out.time += dt;
+        out.last_dt = dt;
+    }
+    HIPCHK(hipStreamSynchronize(hs));
+    if (info) *info = out;
+    return MIFVM_OK;
 }
 
 int mifvm_fgmres_bytes(const mifvm_state* st, int32_t m, size_t* out) {

@@ -76,6 +76,7 @@ struct Dev {
     float *u32, *un32, *src32, *phi32, *grad32, *psi32, *unode32, *flux32;
     float *minv32, *kAC32, *kBC32, *kRL32, *area32, *vol32, *n_alpha32, *fx32, *xc32, *gdist32;
     double* tmp;                          // nc+nb scratch (permutation, residual)
+    double *np_ion, *efield;              // coupled loop: ion density [nc], E [3][nc]
     double *mf_xv, *mf_flux, *mf_xg;      // matrix-free operator: vertex values [nv], face fluxes [nf],
                                           // ghost values [nb]
     double* partial;                      // reduction partials ([k][block], k < 4)
@@ -190,6 +191,12 @@ hipError_t launch_mf_cg_part(const Dev& d, const BcTable& bc, int part, hipStrea
 // with the FP32 coefficient copies, partial p32.q32 in FP64
 hipError_t launch_mf_cg32_spmv(const Dev& d, const BcTable& bc, hipStream_t s);
 hipError_t launch_mf_cg32_part(const Dev& d, const BcTable& bc, int part, hipStream_t s);
+
+// launchers (streamer_kernels.hip): the coupled loop's per-step kernels
+hipError_t launch_streamer_rhs(const Dev& d, double kappa, double* f, hipStream_t s);
+hipError_t launch_streamer_fields(const Dev& d, const BcTable& bc_pot, double mu, double a, double b,
+                                  hipStream_t s);
+hipError_t launch_ion_update(const Dev& d, hipStream_t s);
 
 // launchers (ir_kernels.hip): FP32 inner CG inside FP64 iterative refinement
 hipError_t launch_cast_matrix(const Dev& d, int64_t padded, hipStream_t s);
