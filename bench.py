@@ -314,6 +314,8 @@ def main():
             args, M, pf, "FGMRES(30) + Jacobi, matrix-free", dict(method=B.SOLVE_FGMRES, matrix_free=True),
             plain_ms, p64, fgmres_m=30)
         torch.cuda.empty_cache()
+        result["forms"]["streamer"] = run_streamer_form(args, M, pf)
+        torch.cuda.empty_cache()
         result["forms"]["learned"] = run_learned_form(args, M, pf, iters, solve_ms)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
@@ -482,6 +484,48 @@ def learned_training_data(B, net, log_prefix="learned"):
         states.append(st)
         log(f"{log_prefix}: training mesh n={n} ({m.nc} cells): {got} samples")
     return states, samples, owner
+
+
+def run_streamer_form(args, M, pf):
+    """The coupled streamer-type loop (eq. (10)) on the same mesh, set up as
+    the paper's streamer run: potential 1 at x = 0 and 0 at x = 1 with
+    homogeneous Neumann elsewhere, homogeneous Neumann for n_e, n_p = n_e
+    at the start (a Gaussian pulse on a background); constant mobility and
+    Townsend-type ionisation (the paper's fits are not usable).  Each step:
+    the warm-started matrix-free Jacobi-CG solve for the charge, E, v_e and
+    S_e, the CFL step of n_e and the ion update."""
+    import numpy as np
+    import torch
+    from paper_2203_00925_amd import binding as B
+    st = B.State(M, diffusivity=pf.diffusivity)
+    st.set_bcs(B.VAR_SCALAR, [B.NEUMANN] * 6, [0.0] * 6)
+    st.set_bcs(B.VAR_POTENTIAL, [B.DIRICHLET, B.DIRICHLET] + [B.NEUMANN] * 4, [1.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    st.poisson_assemble()
+    ne = torch.from_numpy(pf.u0 + 1e-2)
+    st.set_field(B.FIELD_U, ne)
+    st.set_field(B.FIELD_ION, ne)
+    params = dict(mobility=1.0, charge_scale=40.0, alpha_a=2.0, alpha_b=0.3, cfl=0.4, tol=1e-10,
+                  matrix_free=True)
+    first = st.streamer_step(1, **params)                  # cold solve
+    log(f"streamer: first step {first['iterations_max']} CG iterations")
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    info = st.streamer_step(args.steps, **params)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    ion = st.get_field(B.FIELD_ION)
+    torch.cuda.synchronize()
+    log(f"streamer: {args.steps} steps, {ms:.1f} ms per step, CG {info['iterations_sum']} iterations")
+    out = {"ms_per_coupled_step": ms, "cg_iterations_per_step": info["iterations_sum"] / args.steps,
+           "first_step_cg_iterations": first["iterations_max"], "dt": info["last_dt"],
+           "ion_gain_rel": float(ion.sum().item() / float(ne.sum()) - 1.0),
+           "model": "eq. (10) with v = -mu E (mu 1), alpha = 2 exp(-0.3/|E|), kappa 40, D 1e-3",
+           "dtype": "f64"}
+    del st
+    return out
 
 
 def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
