@@ -169,7 +169,13 @@ typedef struct {
  * K or the FP32 matrix-free product (dot products accumulated in FP64),
  * x += d in FP64 - repeated until the FP64 true residual meets tol.        */
 enum mifvm_solve_method { MIFVM_SOLVE_PLAIN = 0, MIFVM_SOLVE_IR_FP32 = 1, MIFVM_SOLVE_LEARNED = 2,
-                          MIFVM_SOLVE_FGMRES = 3 };
+                          MIFVM_SOLVE_FGMRES = 3, MIFVM_SOLVE_AMG = 4 };
+/* AMG: flexible CG (Polak-Ribiere beta) preconditioned by one V(1,1) cycle
+ * of the attached aggregation multigrid (mifvm_amg_build/attach), reopened
+ * from the true residual when the recurrence converges or `restart`
+ * iterations have passed.  Single-mesh states; matrix_free chooses the
+ * product of the outer iteration (the cycle's finest level always applies K
+ * matrix-free).                                                            */
 /* FGMRES: restarted flexible GMRES(m) with the Jacobi preconditioner, the
  * Krylov method of the paper's solver runs (Sec. 3.4.2): right
  * preconditioning z_j = D^-1 v_j, classical Gram-Schmidt, Givens rotations,
@@ -339,6 +345,58 @@ typedef struct {
 } mifvm_tune_info;
 int mifvm_step_graph(mifvm_state* st, int32_t n_steps, double dt, void* stream);
 int mifvm_autotune(mifvm_state* st, const char* cache_path, mifvm_tune_info* out, void* stream);
+
+/* ---- aggregation multigrid preconditioner ----------------------------------
+ * The analogue of the paper's fastest solver configuration (PETSc GAMG,
+ * Sec. 3.4.2), as plain aggregation: per level, strong neighbours
+ * |a_ij| >= theta max_{k != i} |a_ik|; aggregates in three passes in row
+ * order (a row with all strong neighbours free seeds an aggregate with them;
+ * a free row joins the aggregate of its strongest aggregated strong
+ * neighbour, the smallest index on ties; a row still free seeds one with
+ * its free strong neighbours); A_c = P^T A P with the piecewise-constant P;
+ * until at most coarse_max rows, inverted densely (LU, partial pivoting).
+ * The cycle: x = w D^-1 b; b_c = P^T (b - A x); x += P V(b_c);
+ * x += w D^-1 (b - A x); the dense inverse on the coarsest level.          */
+typedef struct {
+    double theta;              /* 0 = 0.25                                    */
+    double omega;              /* Jacobi damping, 0 = 2/3                     */
+    int32_t max_levels;        /* 0 = 10 (at most 16)                         */
+    int32_t coarse_max;        /* 0 = 1024 (at most 4096)                     */
+} mifvm_amg_opts;
+
+typedef struct {
+    int32_t levels;
+    int32_t pad_;
+    int64_t rows[16];
+    int64_t nnz[16];           /* stored entries, diagonal included           */
+    double setup_ms;           /* mifvm_amg_build: host setup incl. the copy of K */
+    size_t ws_bytes;           /* device workspace for mifvm_amg_attach        */
+} mifvm_amg_info;
+
+/* Build the hierarchy of the state's assembled K on the host (copies K from
+ * the device; synchronises).  E_ARG for a batch or bad options or when the
+ * coarsening stalls; E_STATE without an assembled system.  Replaces an
+ * earlier hierarchy and detaches it.                                       */
+int mifvm_amg_build(mifvm_state* st, const mifvm_amg_opts* opts, mifvm_amg_info* info, void* stream);
+/* Upload the built hierarchy into a caller workspace of info.ws_bytes
+ * (256-byte aligned, outliving the attachment; E_WORKSPACE otherwise);
+ * d_ws NULL detaches.  Synchronises.                                       */
+int mifvm_amg_attach(mifvm_state* st, void* d_ws, size_t ws_bytes, void* stream);
+/* d_z = V(d_r), one cycle, user cell order (for inspection and tests).
+ * Uses the solver's r and z vectors as scratch.                           */
+int mifvm_amg_apply(mifvm_state* st, const double* d_r, double* d_z, void* stream);
+/* The same setup for any square CSR matrix (host arrays, diagonal included,
+ * any column order), without a GPU, for inspection and tests.             */
+typedef struct mifvm_amg_host mifvm_amg_host;
+int mifvm_amg_host_build(int64_t n, const int64_t* ptr, const int32_t* col, const double* val,
+                         const mifvm_amg_opts* opts, mifvm_amg_host** out);
+int mifvm_amg_host_info(const mifvm_amg_host* h, mifvm_amg_info* info);
+/* what: 0 AGG int32 [rows] (not on the coarsest level), 1 PTR int64
+ * [rows+1], 2 COL int32 [nnz], 3 VAL f64 [nnz] of the level's matrix
+ * (columns ascending on coarse levels; level 0 as given), 4 the coarsest
+ * level's dense inverse f64 [rows*rows], row-major.  bytes must match.    */
+int mifvm_amg_host_export(const mifvm_amg_host* h, int32_t level, int32_t what, void* dst, size_t bytes);
+void mifvm_amg_host_destroy(mifvm_amg_host* h);
 
 /* ---- coupled streamer-type loop (Sec. 4, eq. (10)) -------------------------
  * One species in drift-diffusion coupled to the electrostatic potential:

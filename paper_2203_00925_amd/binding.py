@@ -21,7 +21,7 @@ ZERO_FLUX, NEUMANN, DIRICHLET = 0, 1, 2
 VAR_SCALAR, VAR_POTENTIAL = 0, 1
 FIELD_U, FIELD_VEL, FIELD_SOURCE, FIELD_P, FIELD_ION, FIELD_EFIELD = 0, 1, 2, 3, 4, 5
 RENUMBER_NONE, RENUMBER_MORTON = 0, 1
-SOLVE_PLAIN, SOLVE_IR_FP32, SOLVE_LEARNED, SOLVE_FGMRES = 0, 1, 2, 3
+SOLVE_PLAIN, SOLVE_IR_FP32, SOLVE_LEARNED, SOLVE_FGMRES, SOLVE_AMG = 0, 1, 2, 3, 4
 FP64, FP32 = 0, 1
 KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
            "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble", "nn_layer1", "nn_layer2", "nn_layer3",
@@ -100,6 +100,54 @@ class SolveInfo(C.Structure):
                 ("history_len", C.c_int32), ("outer", C.c_int32),
                 ("rel_residual", C.c_double), ("ms", C.c_double),
                 ("fell_back", C.c_int32), ("learned_iterations", C.c_int32)]
+
+
+class AmgOpts(C.Structure):
+    _fields_ = [("theta", C.c_double), ("omega", C.c_double), ("max_levels", C.c_int32),
+                ("coarse_max", C.c_int32)]
+
+
+class AmgInfo(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("pad_", C.c_int32), ("rows", C.c_int64 * 16),
+                ("nnz", C.c_int64 * 16), ("setup_ms", C.c_double), ("ws_bytes", C.c_size_t)]
+
+
+def _amg_info(info):
+    return {"levels": info.levels, "rows": list(info.rows[:info.levels]), "nnz": list(info.nnz[:info.levels]),
+            "setup_ms": info.setup_ms, "ws_bytes": int(info.ws_bytes)}
+
+
+class AmgHost:
+    """Host-only multigrid setup of a CSR matrix (mifvm_amg_host_*), no GPU."""
+
+    def __init__(self, ptr, col, val, theta=0.0, omega=0.0, max_levels=0, coarse_max=0):
+        ptr = np.ascontiguousarray(ptr, np.int64)
+        col = np.ascontiguousarray(col, np.int32)
+        val = np.ascontiguousarray(val, np.float64)
+        h = C.c_void_p()
+        opts = AmgOpts(float(theta), float(omega), int(max_levels), int(coarse_max))
+        _check(_lib.mifvm_amg_host_build(C.c_int64(len(ptr) - 1), ptr.ctypes.data_as(C.c_void_p),
+                                         col.ctypes.data_as(C.c_void_p), val.ctypes.data_as(C.c_void_p),
+                                         C.byref(opts), C.byref(h)))
+        self._h = h
+        info = AmgInfo()
+        _check(_lib.mifvm_amg_host_info(self._h, C.byref(info)))
+        self.info = _amg_info(info)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mifvm_amg_host_destroy(self._h)
+            self._h = None
+
+    def export(self, level, what):
+        """what: 'agg', 'ptr', 'col', 'val', 'cinv'."""
+        n, nnz = self.info["rows"][level], self.info["nnz"][level]
+        dt, count = {"agg": (np.int32, n), "ptr": (np.int64, n + 1), "col": (np.int32, nnz),
+                     "val": (np.float64, nnz), "cinv": (np.float64, n * n)}[what]
+        out = np.empty(count, dt)
+        _check(_lib.mifvm_amg_host_export(self._h, int(level), ["agg", "ptr", "col", "val", "cinv"].index(what),
+                                          out.ctypes.data_as(C.c_void_p), C.c_size_t(out.nbytes)))
+        return out
 
 
 class StreamerOpts(C.Structure):
@@ -392,6 +440,28 @@ class State:
         off = (-ws.data_ptr()) % 256
         _check(_lib.mifvm_fgmres_attach(self._h, int(m), C.c_void_p(ws.data_ptr() + off), n.value))
         self._gm_ws = ws
+
+    def amg_build(self, theta=0.0, omega=0.0, max_levels=0, coarse_max=0, stream=None):
+        """Multigrid hierarchy of the assembled K, uploaded into a workspace
+        this object keeps (mifvm_amg_build + mifvm_amg_attach)."""
+        import torch
+        opts = AmgOpts(float(theta), float(omega), int(max_levels), int(coarse_max))
+        info = AmgInfo()
+        _check(_lib.mifvm_amg_build(self._h, C.byref(opts), C.byref(info), _stream(stream)))
+        ws = torch.empty(int(info.ws_bytes) + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        _check(_lib.mifvm_amg_attach(self._h, C.c_void_p(ws.data_ptr() + off), C.c_size_t(info.ws_bytes),
+                                     _stream(stream)))
+        self._amg_ws = ws
+        return _amg_info(info)
+
+    def amg_apply(self, r, stream=None):
+        """z = V(r), one multigrid cycle (user cell order)."""
+        import torch
+        r = r.to(device=self.device, dtype=torch.float64).contiguous()
+        z = torch.empty_like(r)
+        _check(_lib.mifvm_amg_apply(self._h, _ptr(r), _ptr(z), _stream(stream)))
+        return z
 
     def poisson_apply_free(self, x, stream=None):
         """K x from the discretisation (no stored matrix)."""

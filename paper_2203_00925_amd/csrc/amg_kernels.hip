@@ -1,0 +1,295 @@
+// Aggregation multigrid V(1,1) cycle and the flexible CG around it (the
+// setup and the cycle's definition are in amg.h).  Level 0 is the state's
+// system: its product is the matrix-free one, its diagonal K's; coarser
+// levels store their off-diagonal entries in 64-row slices beside the
+// diagonal.  Every kernel takes the solve's done flag and returns at once
+// when it is set (a captured chunk of iterations then runs to its end
+// without work).
+#include "amg_dev.h"
+#include "reduce.h"
+#include "seg.h"
+#include "state.h"
+
+namespace mifvm {
+namespace {
+
+__device__ inline int64_t tid_a() { return int64_t(blockIdx.x) * blockDim.x + threadIdx.x; }
+inline unsigned grid_a(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+__device__ inline bool done(const double* flag) { return flag && *flag != 0.0; }
+
+// x = w D^-1 b
+__global__ __launch_bounds__(kBlock) void k_amg_smooth0(int64_t n, double w, const double* __restrict__ dinv,
+                                                        const double* __restrict__ b, double* __restrict__ x,
+                                                        const double* flag) {
+    if (done(flag)) return;
+    const int64_t i = tid_a();
+    if (i < n) x[i] = w * dinv[i] * b[i];
+}
+
+// x += w D^-1 (b - t)
+__global__ __launch_bounds__(kBlock) void k_amg_smooth1(int64_t n, double w, const double* __restrict__ dinv,
+                                                        const double* __restrict__ b, const double* __restrict__ t,
+                                                        double* __restrict__ x, const double* flag) {
+    if (done(flag)) return;
+    const int64_t i = tid_a();
+    if (i < n) x[i] = x[i] + w * dinv[i] * (b[i] - t[i]);
+}
+
+// t = A x on a coarse level (diagonal + sliced off-diagonal entries)
+__global__ __launch_bounds__(kBlock) void k_amg_spmv(AmgLevelDev L, const double* __restrict__ x,
+                                                     double* __restrict__ t, const double* flag) {
+    if (done(flag)) return;
+    const int64_t i = tid_a();
+    if (i >= L.n) return;
+    const int64_t base = L.off[i >> 6] + (i & 63);
+    const int w = L.w[i >> 6];
+    double y = L.diag[i] * x[i];
+    for (int k0 = 0; k0 < w; k0 += 8) {
+        int c[8];
+        double a[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool in = k0 + j < w;
+            const int64_t at = base + int64_t(k0 + j) * 64;
+            c[j] = in ? L.idx[at] : int(i);
+            a[j] = in ? L.val[at] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) y += a[j] * x[c[j]];
+    }
+    t[i] = y;
+}
+
+// b_c[I] = sum over the members i of aggregate I of (b[i] - t[i])
+__global__ __launch_bounds__(kBlock) void k_amg_restrict(int64_t nco, const int64_t* __restrict__ mptr,
+                                                         const int32_t* __restrict__ midx,
+                                                         const double* __restrict__ b, const double* __restrict__ t,
+                                                         double* __restrict__ bc, const double* flag) {
+    if (done(flag)) return;
+    const int64_t I = tid_a();
+    if (I >= nco) return;
+    double s = 0.0;
+    for (int64_t m = mptr[I]; m < mptr[I + 1]; ++m) {
+        const int i = midx[m];
+        s += b[i] - t[i];
+    }
+    bc[I] = s;
+}
+
+// x[i] += x_c[agg[i]]
+__global__ __launch_bounds__(kBlock) void k_amg_prolong(int64_t n, const int32_t* __restrict__ agg,
+                                                        const double* __restrict__ xc, double* __restrict__ x,
+                                                        const double* flag) {
+    if (done(flag)) return;
+    const int64_t i = tid_a();
+    if (i < n) x[i] = x[i] + xc[agg[i]];
+}
+
+// x = C^-1 b on the coarsest level: one block per row
+__global__ __launch_bounds__(256) void k_amg_dense(int64_t n, const double* __restrict__ cinv,
+                                                   const double* __restrict__ b, double* __restrict__ x,
+                                                   const double* flag) {
+    __shared__ double lds[4];
+    if (done(flag)) return;
+    const int64_t r = blockIdx.x;
+    double s = 0.0;
+    for (int64_t c = threadIdx.x; c < n; c += 256) s += cinv[r * n + c] * b[c];
+    s = block_sum256(s, lds);
+    if (threadIdx.x == 0) x[r] = s;
+}
+
+// ---- flexible CG (one mesh) -------------------------------------------------------
+// r = b - t (t = K x); partial rr, bb
+__global__ __launch_bounds__(kBlock) void k_amg_open(Dev d, const double* __restrict__ t) {
+    __shared__ double lds[4];
+    const int64_t i = tid_a();
+    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    double v[2] = {0.0, 0.0};
+    if (i < d.nc) {
+        const double bi = d.b[i];
+        const double ri = bi - t[i];
+        d.r[i] = ri;
+        v[0] = ri * ri;
+        v[1] = bi * bi;
+    }
+    seg_publish<2>(d, g, v, i >= g.split, lds);
+}
+
+__global__ __launch_bounds__(1024) void k_amg_open_fin(Dev d, int64_t nparts, double tol, int maxit, int restart,
+                                                       int fresh) {
+    __shared__ double lds[16];
+    const double rr = seg_sum(d, 0, 0, nparts, kBlock, lds);
+    const double bb = seg_sum(d, 1, 0, nparts, kBlock, lds);
+    if (threadIdx.x == 0) {
+        double* sc = d.scal;
+        sc[SC_RR] = rr;
+        sc[SC_TRUE_RR] = rr;
+        sc[SC_BB] = bb;
+        if (fresh) {
+            sc[SC_TOL2BB] = tol * tol * bb;
+            sc[SC_MAXIT] = double(maxit);
+            sc[SC_RESTART] = double(restart);
+            sc[SC_IT] = 0.0;
+        }
+        sc[SC_SINCE] = 0.0;
+        sc[SC_DONE] = (rr <= sc[SC_TOL2BB] || bb == 0.0) ? 1.0 : (sc[SC_IT] >= sc[SC_MAXIT] ? 2.0 : 0.0);
+    }
+}
+
+// after the cycle of the opening: p = z, partial z.r
+__global__ __launch_bounds__(kBlock) void k_amg_p0(Dev d) {
+    __shared__ double lds[4];
+    if (d.scal[SC_DONE] != 0.0) return;
+    const int64_t i = tid_a();
+    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    double v[1] = {0.0};
+    if (i < d.nc) {
+        const double zi = d.z[i];
+        d.p[i] = zi;
+        v[0] = zi * d.r[i];
+    }
+    seg_publish<1>(d, g, v, i >= g.split, lds);
+}
+
+__global__ __launch_bounds__(1024) void k_amg_rz_fin(Dev d, int64_t nparts) {
+    __shared__ double lds[16];
+    if (d.scal[SC_DONE] != 0.0) return;
+    const double zr = seg_sum(d, 0, 0, nparts, kBlock, lds);
+    if (threadIdx.x == 0) d.scal[SC_RZ] = zr;
+}
+
+// x += alpha p; r_old = r; r -= alpha q; partial rr
+__global__ __launch_bounds__(kBlock) void k_amg_axpy(Dev d, double* __restrict__ r_old) {
+    __shared__ double lds[4];
+    if (d.scal[SC_DONE] != 0.0) return;
+    const int64_t i = tid_a();
+    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    double v[1] = {0.0};
+    if (i < d.nc) {
+        const double alpha = d.scal[SC_ALPHA];
+        d.x[i] = d.x[i] + alpha * d.p[i];
+        const double ro = d.r[i];
+        const double ri = ro - alpha * d.q[i];
+        r_old[i] = ro;
+        d.r[i] = ri;
+        v[0] = ri * ri;
+    }
+    seg_publish<1>(d, g, v, i >= g.split, lds);
+}
+
+// count; convergence (1), limit (2) or a scheduled restart (3)
+__global__ __launch_bounds__(1024) void k_amg_rr_fin(Dev d, int64_t nparts) {
+    __shared__ double lds[16];
+    double* sc = d.scal;
+    if (sc[SC_DONE] != 0.0) return;
+    const double rr = seg_sum(d, 0, 0, nparts, kBlock, lds);
+    if (threadIdx.x == 0) {
+        sc[SC_RR] = rr;
+        sc[SC_IT] = sc[SC_IT] + 1.0;
+        sc[SC_SINCE] = sc[SC_SINCE] + 1.0;
+        if (rr <= sc[SC_TOL2BB]) sc[SC_DONE] = 1.0;
+        else if (sc[SC_IT] >= sc[SC_MAXIT]) sc[SC_DONE] = 2.0;
+        else if (sc[SC_RESTART] > 0.0 && sc[SC_SINCE] >= sc[SC_RESTART]) sc[SC_DONE] = 3.0;
+    }
+}
+
+// partial z.r and z.r_old
+__global__ __launch_bounds__(kBlock) void k_amg_zdots(Dev d, const double* __restrict__ r_old) {
+    __shared__ double lds[4];
+    if (d.scal[SC_DONE] != 0.0) return;
+    const int64_t i = tid_a();
+    const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
+    double v[2] = {0.0, 0.0};
+    if (i < d.nc) {
+        const double zi = d.z[i];
+        v[0] = zi * d.r[i];
+        v[1] = zi * r_old[i];
+    }
+    seg_publish<2>(d, g, v, i >= g.split, lds);
+}
+
+// flexible (Polak-Ribiere) beta = z_new . (r_new - r_old) / (z_old . r_old)
+__global__ __launch_bounds__(1024) void k_amg_beta_fin(Dev d, int64_t nparts) {
+    __shared__ double lds[16];
+    double* sc = d.scal;
+    if (sc[SC_DONE] != 0.0) return;
+    const double zr = seg_sum(d, 0, 0, nparts, kBlock, lds);
+    const double zro = seg_sum(d, 1, 0, nparts, kBlock, lds);
+    if (threadIdx.x == 0) {
+        sc[SC_BETA] = (zr - zro) / sc[SC_RZ];
+        sc[SC_RZ] = zr;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_amg_cycle(const Dev& d, const BcTable& bc_pot, const AmgDev& a, const double* b0, double* x0,
+                            const double* flag, hipStream_t s) {
+    const int nl = a.nl;
+    const double w = a.omega;
+    if (nl == 1) {                 // the system is small enough to invert densely
+        hipLaunchKernelGGL(k_amg_dense, dim3(unsigned(d.nc)), dim3(256), 0, s, d.nc, a.cinv, b0, x0, flag);
+        return hipGetLastError();
+    }
+    // down: level 0 (matrix-free product into tmp), then the coarse levels
+    hipLaunchKernelGGL(k_amg_smooth0, dim3(grid_a(d.nc)), dim3(kBlock), 0, s, d.nc, w, d.k_dinv, b0, x0, flag);
+    hipError_t e = launch_mf_apply(d, bc_pot, x0, d.tmp, s, flag);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_amg_restrict, dim3(grid_a(a.lv[1].n)), dim3(kBlock), 0, s, a.lv[1].n, a.lv[0].mptr,
+                       a.lv[0].midx, b0, d.tmp, a.lv[1].b, flag);
+    for (int l = 1; l < nl - 1; ++l) {
+        const AmgLevelDev& L = a.lv[l];
+        hipLaunchKernelGGL(k_amg_smooth0, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L.n, w, L.dinv, L.b, L.x, flag);
+        hipLaunchKernelGGL(k_amg_spmv, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L, L.x, L.t, flag);
+        hipLaunchKernelGGL(k_amg_restrict, dim3(grid_a(a.lv[l + 1].n)), dim3(kBlock), 0, s, a.lv[l + 1].n, L.mptr,
+                           L.midx, L.b, L.t, a.lv[l + 1].b, flag);
+    }
+    const AmgLevelDev& C = a.lv[nl - 1];
+    hipLaunchKernelGGL(k_amg_dense, dim3(unsigned(C.n)), dim3(256), 0, s, C.n, a.cinv, C.b, C.x, flag);
+    // up
+    for (int l = nl - 2; l >= 1; --l) {
+        const AmgLevelDev& L = a.lv[l];
+        hipLaunchKernelGGL(k_amg_prolong, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L.n, L.agg, a.lv[l + 1].x, L.x,
+                           flag);
+        hipLaunchKernelGGL(k_amg_spmv, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L, L.x, L.t, flag);
+        hipLaunchKernelGGL(k_amg_smooth1, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L.n, w, L.dinv, L.b, L.t, L.x,
+                           flag);
+    }
+    hipLaunchKernelGGL(k_amg_prolong, dim3(grid_a(d.nc)), dim3(kBlock), 0, s, d.nc, a.lv[0].agg, a.lv[1].x, x0,
+                       flag);
+    e = launch_mf_apply(d, bc_pot, x0, d.tmp, s, flag);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_amg_smooth1, dim3(grid_a(d.nc)), dim3(kBlock), 0, s, d.nc, w, d.k_dinv, b0, d.tmp, x0,
+                       flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_amg_open(const Dev& d, const BcTable& bc_pot, const AmgDev& a, double tol, int maxit,
+                           int restart, bool fresh, hipStream_t s) {
+    const int64_t nb = grid_a(d.nc);
+    hipError_t e = launch_mf_apply(d, bc_pot, d.x, d.tmp, s);            // t = K x
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_amg_open, dim3(unsigned(nb)), dim3(kBlock), 0, s, d, d.tmp);
+    hipLaunchKernelGGL(k_amg_open_fin, dim3(1), dim3(1024), 0, s, d, nb, tol, maxit, restart, fresh ? 1 : 0);
+    e = launch_amg_cycle(d, bc_pot, a, d.r, d.z, d.scal + SC_DONE, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_amg_p0, dim3(unsigned(nb)), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_amg_rz_fin, dim3(1), dim3(1024), 0, s, d, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_amg_iteration(const Dev& d, const BcTable& bc_pot, const AmgDev& a, bool matrix_free,
+                                hipStream_t s) {
+    const int64_t nb = grid_a(d.nc);
+    hipError_t e = matrix_free ? launch_mf_cg_spmv(d, bc_pot, s) : launch_cg_spmv(d, s);   // q = K p, alpha
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_amg_axpy, dim3(unsigned(nb)), dim3(kBlock), 0, s, d, a.r_old);
+    hipLaunchKernelGGL(k_amg_rr_fin, dim3(1), dim3(1024), 0, s, d, nb);
+    e = launch_amg_cycle(d, bc_pot, a, d.r, d.z, d.scal + SC_DONE, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_amg_zdots, dim3(unsigned(nb)), dim3(kBlock), 0, s, d, a.r_old);
+    hipLaunchKernelGGL(k_amg_beta_fin, dim3(1), dim3(1024), 0, s, d, nb);
+    return launch_cg_dir(d, s);                                           // p = z + beta p
+}
+
+}  // namespace mifvm

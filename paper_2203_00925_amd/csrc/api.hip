@@ -373,6 +373,7 @@ void mifvm_state_destroy(mifvm_state* st) {
     if (st->s.step_exec) (void)hipGraphExecDestroy(st->s.step_exec);
     if (st->s.fcg_exec) (void)hipGraphExecDestroy(st->s.fcg_exec);
     if (st->s.gm_exec) (void)hipGraphExecDestroy(st->s.gm_exec);
+    amg_release(st->s);
     delete st->s.gm;
     delete st->s.nn_state;
     if (st->s.cap_stream) (void)hipStreamDestroy(st->s.cap_stream);
@@ -720,8 +721,12 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
     if (!(tol > 0) || maxit < 0 || restart < 0 || hist_cap < 0 || !(tol_in < 1))
         return fail(MIFVM_E_ARG, "bad tol, maxit, restart, inner_tol or history");
     if (method != MIFVM_SOLVE_PLAIN && method != MIFVM_SOLVE_IR_FP32 && method != MIFVM_SOLVE_LEARNED &&
-        method != MIFVM_SOLVE_FGMRES)
+        method != MIFVM_SOLVE_FGMRES && method != MIFVM_SOLVE_AMG)
         return fail(MIFVM_E_ARG, "unknown method");
+    if (method == MIFVM_SOLVE_AMG) {
+        if (!s.amg) return fail(MIFVM_E_STATE, "method AMG needs an attached hierarchy (mifvm_amg_build/attach)");
+        if (s.d.nm != 1) return fail(MIFVM_E_ARG, "method AMG needs a single-mesh state");
+    }
     if (method == MIFVM_SOLVE_FGMRES) {
         if (!s.gm) return fail(MIFVM_E_STATE, "method FGMRES needs a workspace (mifvm_fgmres_attach)");
         if (s.d.nm != 1) return fail(MIFVM_E_ARG, "method FGMRES needs a single-mesh state");
@@ -774,8 +779,8 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
     }
     const int run_method = method == MIFVM_SOLVE_LEARNED ? MIFVM_SOLVE_PLAIN : method;
     const int graph_key = run_method + (matrix_free ? 16 : 0);
-    if (use_graph && (method != MIFVM_SOLVE_LEARNED || learned.fell_back) &&
-        (s.cg_exec == nullptr || s.cg_exec_chunk != chunk || s.cg_exec_method != graph_key)) {
+    if (use_graph && (method != MIFVM_SOLVE_LEARNED || learned.fell_back) && method != MIFVM_SOLVE_AMG &&
+        method != MIFVM_SOLVE_FGMRES && (s.cg_exec == nullptr || s.cg_exec_chunk != chunk || s.cg_exec_method != graph_key)) {
         HIPCHK(capture_graph(s, &s.cg_exec, [&](hipStream_t q) { return enqueue_cg_chunk(s, run_method, chunk, q); }));
         s.cg_exec_chunk = chunk;
         s.cg_exec_method = graph_key;
@@ -858,6 +863,8 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
             if ((rc = open(false))) return rc;       // the true residual decides
             if (hsc(s, 0, SC_DONE) == 0.0) ++restarts;
         }
+    } else if (method == MIFVM_SOLVE_AMG) {
+        if ((rc = amg_phase(s, tol, maxit, chunk, restart, use_graph, matrix_free, hs, pull, restarts))) return rc;
     } else if (method == MIFVM_SOLVE_LEARNED && !learned.fell_back) {
         // the flexible CG ended: converged, or at maxit
     } else if (run_method == MIFVM_SOLVE_PLAIN) {

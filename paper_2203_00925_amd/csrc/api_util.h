@@ -141,4 +141,11 @@ struct LearnedRun {
 int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int stall_window, int learned_maxit,
                   bool use_graph, hipStream_t hs, const std::function<int()>& pull, LearnedRun& out);
 
+// Multigrid-preconditioned flexible CG (amg_api.hip): runs until the true
+// residual meets tol or the iteration limit; restarts counted.
+int amg_phase(State& s, double tol, int maxit, int chunk, int restart, bool use_graph, bool matrix_free,
+              hipStream_t hs, const std::function<int()>& pull, int& restarts);
+// free the hierarchy, its device record and graph of a state
+void amg_release(State& s);
+
 }  // namespace mifvm_api

@@ -95,6 +95,8 @@ constexpr int kNumKernels = 19;
 struct NnDev;
 struct NnStateDev;
 struct GmDev;
+struct AmgHierarchy;
+struct AmgDev;
 
 // Event pairs around kernel launches, resolved into totals at sync points.
 struct KernelTimer {
@@ -143,6 +145,10 @@ struct State {
     bool b_ready = false;                 // d.b holds a right-hand side
     hipGraphExec_t fcg_exec = nullptr;    // one chunk of flexible-CG iterations
     int fcg_exec_chunk = 0;
+    AmgHierarchy* amg_host = nullptr;     // multigrid hierarchy (host, owned)
+    AmgDev* amg = nullptr;                // its device form (caller workspace; owned record)
+    hipGraphExec_t amg_exec = nullptr;    // one chunk of multigrid-preconditioned iterations
+    int amg_exec_key = 0;
 };
 
 // workspace layout; returns total bytes (and fills d when base != nullptr)
