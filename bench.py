@@ -314,6 +314,10 @@ def main():
             args, M, pf, "FGMRES(30) + Jacobi, matrix-free", dict(method=B.SOLVE_FGMRES, matrix_free=True),
             plain_ms, p64, fgmres_m=30)
         torch.cuda.empty_cache()
+        result["forms"]["multigrid_fcg"] = run_solver_form(
+            args, M, pf, "flexible CG + aggregation multigrid V(1,1), matrix-free",
+            dict(method=B.SOLVE_AMG, matrix_free=True), plain_ms, p64, amg=True)
+        torch.cuda.empty_cache()
         result["forms"]["streamer"] = run_streamer_form(args, M, pf)
         torch.cuda.empty_cache()
         result["forms"]["learned"] = run_learned_form(args, M, pf, iters, solve_ms)
@@ -383,10 +387,11 @@ def run_fp32_form(args, M, pf, u64, p64, plain_ms):
 
 
 
-def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0):
+def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0, amg=False):
     """The FP64 run's steps with another solver of the same system: solve time
     and iterations per step, the solution's difference from the plain run's,
-    and one cold solve (P = 0)."""
+    and one cold solve (P = 0).  amg: build and attach the multigrid
+    hierarchy first (its host setup time is reported, outside the timings)."""
     import numpy as np
     import torch
     from paper_2203_00925_amd import binding as B
@@ -398,6 +403,9 @@ def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0):
     st.poisson_assemble()
     if fgmres_m:
         st.fgmres_attach(fgmres_m)
+    amg_info = st.amg_build() if amg else None
+    if amg:
+        log(f"{name}: {amg_info['levels']} levels {amg_info['rows']}, setup {amg_info['setup_ms'] / 1e3:.1f} s")
     dt = st.cfl_dt(pf.cfl)
     kw = dict(tol=1e-10, restart=500, **solve_kw)
     cold = st.poisson_solve(None, **kw)
@@ -424,7 +432,9 @@ def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0):
     ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
     perr = float((p - p64).norm() / p64.norm())
     del st
-    return {"solver": name, "poisson_solve_ms": ms, "speedup_vs_main_solve": plain_ms / ms,
+    extra = {"multigrid": {"levels": amg_info["levels"], "rows": amg_info["rows"], "nnz": amg_info["nnz"],
+                           "host_setup_s": amg_info["setup_ms"] / 1e3}} if amg else {}
+    return {**extra, "solver": name, "poisson_solve_ms": ms, "speedup_vs_main_solve": plain_ms / ms,
             "poisson_iterations": [s["iterations"] for s in solves],
             "poisson_rel_residual": max(s["rel_residual"] for s in solves),
             "P_rel_diff_vs_plain_run": perr,
