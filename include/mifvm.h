@@ -76,7 +76,10 @@ enum mifvm_field {
                                  [x..., y..., z...] (get only)                */
 };
 
-enum mifvm_renumber { MIFVM_RENUMBER_NONE = 0, MIFVM_RENUMBER_MORTON = 1 };
+/* internal cell order: as given, Morton order of the centres, or reverse
+ * Cuthill-McKee on the face-adjacency graph (per mesh and component, from a
+ * pseudo-peripheral cell); vertices follow their lowest cell              */
+enum mifvm_renumber { MIFVM_RENUMBER_NONE = 0, MIFVM_RENUMBER_MORTON = 1, MIFVM_RENUMBER_RCM = 2 };
 
 #define MIFVM_MAX_TAGS 32
 
@@ -284,6 +287,12 @@ int mifvm_residual(mifvm_state* st, double* d_res, double* d_grad, double* d_psi
 /* sum_i mu_i u_i in FP64 over all meshes (per mesh, deterministic order,
  * then the meshes in order).  Synchronises.                                */
 int mifvm_conservation(mifvm_state* st, double* total_out, void* stream);
+/* Discrete L2 norm of a field's difference from a given one, as the
+ * annex's error report (norml2 with order 1): sqrt(sum_i mu_i (a_i - e_i)^2)
+ * over all cells (cell-centre quadrature); field is FIELD_U, FIELD_P or
+ * FIELD_ION, d_exact (user cell order) may be NULL for e = 0.  FP64.
+ * Synchronises.                                                            */
+int mifvm_norm_l2(mifvm_state* st, int32_t field, const double* d_exact, double* out, void* stream);
 /* Per-mesh results of the last call that produced them (n = nmeshes):
  * what 0 = dt_m of mifvm_cfl_dt, 1 = conservation total, 2 = iterations of
  * the last solve, 3 = its true relative residual.                          */

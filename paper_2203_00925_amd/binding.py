@@ -20,7 +20,7 @@ OK, NOT_CONVERGED, FELL_BACK = 0, 1, 2
 ZERO_FLUX, NEUMANN, DIRICHLET = 0, 1, 2
 VAR_SCALAR, VAR_POTENTIAL = 0, 1
 FIELD_U, FIELD_VEL, FIELD_SOURCE, FIELD_P, FIELD_ION, FIELD_EFIELD = 0, 1, 2, 3, 4, 5
-RENUMBER_NONE, RENUMBER_MORTON = 0, 1
+RENUMBER_NONE, RENUMBER_MORTON, RENUMBER_RCM = 0, 1, 2
 SOLVE_PLAIN, SOLVE_IR_FP32, SOLVE_LEARNED, SOLVE_FGMRES, SOLVE_AMG = 0, 1, 2, 3, 4
 FP64, FP32 = 0, 1
 KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
@@ -383,6 +383,14 @@ class State:
 
     def step_graph(self, n_steps, dt, stream=None):
         _check(_lib.mifvm_step_graph(self._h, int(n_steps), float(dt), _stream(stream)))
+
+    def norm_l2(self, field, exact=None, stream=None):
+        """sqrt(sum mu_i (a_i - e_i)^2) of a field against `exact` (user order)."""
+        import torch
+        e = None if exact is None else exact.to(device=self.device, dtype=torch.float64).contiguous()
+        out = C.c_double()
+        _check(_lib.mifvm_norm_l2(self._h, int(field), _ptr(e), C.byref(out), _stream(stream)))
+        return out.value
 
     def streamer_step(self, n_steps, mobility, charge_scale, alpha_a=0.0, alpha_b=0.0, cfl=0.4,
                       tol=1e-10, maxit=0, restart=0, matrix_free=False, stream=None):

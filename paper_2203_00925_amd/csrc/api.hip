@@ -616,6 +616,38 @@ int mifvm_residual(mifvm_state* st, double* d_res, double* d_grad, double* d_psi
     return MIFVM_OK;
 }
 
+int mifvm_norm_l2(mifvm_state* st, int32_t field, const double* d_exact, double* out, void* stream) {
+    if (!st || !out) return fail(MIFVM_E_ARG, "null argument");
+    State& s = st->s;
+    const Dev& d = s.d;
+    hipStream_t hs = S(stream);
+    const double* a = nullptr;
+    if (field == MIFVM_FIELD_U) {
+        if (s.fp32) {
+            HIPCHK(launch_cast_to_f64(d.nc, d.u32, d.efield, hs));     // widened into scratch
+            a = d.efield;
+        } else {
+            a = d.u;
+        }
+    } else if (field == MIFVM_FIELD_P) {
+        a = d.x;
+    } else if (field == MIFVM_FIELD_ION) {
+        a = d.np_ion;
+    } else {
+        return fail(MIFVM_E_ARG, "norm of FIELD_U, FIELD_P or FIELD_ION");
+    }
+    const double* e = nullptr;
+    if (d_exact) {
+        HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_exact, d.tmp, hs));
+        e = d.tmp;
+    }
+    HIPCHK(launch_norm_l2(d, a, e, hs));
+    int rc = pull_scalars(s, hs);
+    if (rc) return rc;
+    *out = std::sqrt(hsc(s, 0, SC_NORM));
+    return MIFVM_OK;
+}
+
 int mifvm_conservation(mifvm_state* st, double* total_out, void* stream) {
     if (!st || !total_out) return fail(MIFVM_E_ARG, "null argument");
     State& s = st->s;

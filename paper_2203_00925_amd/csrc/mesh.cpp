@@ -203,6 +203,100 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             if (mesh_of_user[a] != mesh_of_user[b]) return mesh_of_user[a] < mesh_of_user[b];
             return key[a] < key[b];
         });
+    } else if (renumber == 2) {
+        // Reverse Cuthill-McKee on the face-adjacency graph of the cells
+        // (Cuthill & McKee 1969; reversed, George 1971), each mesh of a batch
+        // and each connected component on its own: breadth-first from a
+        // pseudo-peripheral cell (the George-Liu search: restart from the
+        // lowest-degree cell of the last level until the depth stops
+        // growing), neighbours visited by increasing degree then index, the
+        // whole order reversed.
+        std::vector<std::array<int32_t, 4>> key(4 * nc);
+        for (int64_t c = 0; c < nc; ++c)
+            for (int k = 0; k < 4; ++k) {
+                std::array<int32_t, 3> v = {T[c][(k + 1) % 4], T[c][(k + 2) % 4], T[c][(k + 3) % 4]};
+                std::sort(v.begin(), v.end());
+                key[4 * c + k] = {v[0], v[1], v[2], int32_t(c)};
+            }
+        std::sort(key.begin(), key.end());
+        std::vector<int64_t> aptr(nc + 1, 0);
+        std::vector<std::pair<int32_t, int32_t>> edges;
+        for (size_t a = 0; a + 1 < key.size(); ++a)
+            if (key[a][0] == key[a + 1][0] && key[a][1] == key[a + 1][1] && key[a][2] == key[a + 1][2])
+                edges.emplace_back(key[a][3], key[a + 1][3]);
+        key.clear();
+        key.shrink_to_fit();
+        for (auto& e : edges) { aptr[e.first + 1]++; aptr[e.second + 1]++; }
+        for (int64_t c = 0; c < nc; ++c) aptr[c + 1] += aptr[c];
+        std::vector<int32_t> adj(aptr[nc]);
+        {
+            std::vector<int64_t> pos(aptr.begin(), aptr.end() - 1);
+            for (auto& e : edges) { adj[pos[e.first]++] = e.second; adj[pos[e.second]++] = e.first; }
+        }
+        edges.clear();
+        edges.shrink_to_fit();
+        auto deg = [&](int32_t c) { return aptr[c + 1] - aptr[c]; };
+        for (int64_t c = 0; c < nc; ++c)
+            std::sort(adj.begin() + aptr[c], adj.begin() + aptr[c + 1], [&](int32_t a, int32_t b) {
+                return deg(a) != deg(b) ? deg(a) < deg(b) : a < b;
+            });
+        std::vector<int32_t> level(nc, -1), order;
+        order.reserve(nc);
+        // breadth-first levels from s over unvisited cells; returns the depth
+        auto levels_from = [&](int32_t s, std::vector<int32_t>& out) -> int32_t {
+            out.clear();
+            out.push_back(s);
+            level[s] = 0;
+            for (size_t h = 0; h < out.size(); ++h) {
+                const int32_t c = out[h];
+                for (int64_t e = aptr[c]; e < aptr[c + 1]; ++e)
+                    if (level[adj[e]] < 0) { level[adj[e]] = level[c] + 1; out.push_back(adj[e]); }
+            }
+            return level[out.back()];
+        };
+        std::vector<int32_t> by_mesh(nc);
+        std::iota(by_mesh.begin(), by_mesh.end(), 0);
+        std::stable_sort(by_mesh.begin(), by_mesh.end(),
+                         [&](int32_t a, int32_t b) { return mesh_of_user[a] < mesh_of_user[b]; });
+        std::vector<char> done(nc, 0);
+        std::vector<int32_t> comp;
+        for (size_t q = 0; q < by_mesh.size(); ++q) {
+            const int32_t c0 = by_mesh[q];
+            if (done[c0]) continue;
+            // lowest-degree cell of this component as the first start
+            int32_t s = c0;
+            levels_from(c0, comp);
+            for (int32_t c : comp) if (deg(c) < deg(s) || (deg(c) == deg(s) && c < s)) s = c;
+            for (int32_t c : comp) level[c] = -1;
+            int32_t depth = levels_from(s, comp);
+            for (int it = 0; it < 8; ++it) {
+                int32_t best = -1;
+                for (int32_t c : comp)
+                    if (level[c] == depth && (best < 0 || deg(c) < deg(best) || (deg(c) == deg(best) && c < best)))
+                        best = c;
+                for (int32_t c : comp) level[c] = -1;
+                std::vector<int32_t> trial;
+                const int32_t d2 = levels_from(best, trial);
+                if (d2 <= depth) {
+                    for (int32_t c : trial) level[c] = -1;
+                    levels_from(s, comp);
+                    break;
+                }
+                s = best;
+                depth = d2;
+                comp.swap(trial);
+            }
+            // comp is the breadth-first order from s (neighbours by degree)
+            const size_t first = order.size();
+            order.insert(order.end(), comp.begin(), comp.end());
+            std::reverse(order.begin() + first, order.end());
+            for (int32_t c : comp) done[c] = 1;
+        }
+        // components of a mesh stay in the order found; meshes in order
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return mesh_of_user[a] < mesh_of_user[b]; });
+        if ((int64_t)order.size() != nc) { err = "internal error: renumbering lost cells"; return E_MESH; }
+        new2old = order;
     } else if (renumber != 0) {
         err = "unknown renumbering";
         return E_ARG;

@@ -203,6 +203,8 @@ hipError_t launch_streamer_rhs(const Dev& d, double kappa, double* f, hipStream_
 hipError_t launch_streamer_fields(const Dev& d, const BcTable& bc_pot, double mu, double a, double b,
                                   hipStream_t s);
 hipError_t launch_ion_update(const Dev& d, hipStream_t s);
+// sum_i mu_i (a_i - e_i)^2 over all cells (e null: 0) into scal[SC_NORM] of mesh 0
+hipError_t launch_norm_l2(const Dev& d, const double* a, const double* e, hipStream_t s);
 
 // launchers (ir_kernels.hip): FP32 inner CG inside FP64 iterative refinement
 hipError_t launch_cast_matrix(const Dev& d, int64_t padded, hipStream_t s);
@@ -220,6 +222,7 @@ enum Scal {
     SC_TRUE_RR, SC_CONS, SC_DT_INV, SC_RESTART, SC_SINCE, SC_TOL2BB_OUT,
     // learned preconditioner: input scales and flexible-CG dot products
     SC_NN_INV_SR, SC_NN_INV_SD, SC_NN_SD, SC_NN_RR, SC_NN_DD, SC_ZR, SC_ZRO, SC_NN_RDR, SC_NN_DSCALE,
+    SC_NORM,                              // mifvm_norm_l2 (mesh 0's slots)
     SC_COUNT_ = 32
 };
 

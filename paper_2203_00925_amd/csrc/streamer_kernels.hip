@@ -9,10 +9,15 @@
 //                      v_e = -mu E, S_e = alpha(|E|) |v_e| n_e with
 //                      alpha(|E|) = a exp(-b / |E|) (0 when E = 0);
 //   k_ion_update       n_p += dt S_e with the cell's mesh's step.
+// Also here: the discrete L2 norm of mifvm_norm_l2 (cell-centre quadrature,
+// the annex's error report), a deterministic two-pass reduction.
 // The stencil is read from the 64-row slices of global indices (padding is
 // the cell itself, which adds exact zeros).  This runs once per coupled
 // step, beside a Poisson solve of some thousand products, so it stays a
 // plain gather kernel.
+#include <algorithm>
+
+#include "reduce.h"
 #include "seg.h"
 #include "state.h"
 
@@ -90,7 +95,34 @@ __global__ __launch_bounds__(kBlock) void k_ion_update(Dev d) {
     if (i < d.nc) d.np_ion[i] = d.np_ion[i] + d.mesh_dt[mesh_of(d, i)] * d.src[i];
 }
 
+// partials of sum mu_i (a_i - e_i)^2: a grid-stride sum per block, then one
+// block adds the partials in block order (deterministic)
+__global__ __launch_bounds__(kBlock) void k_norm_part(Dev d, const double* __restrict__ a,
+                                                      const double* __restrict__ e) {
+    __shared__ double lds[4];
+    double s = 0.0;
+    for (int64_t i = tid_s(); i < d.nc; i += int64_t(gridDim.x) * kBlock) {
+        const double v = a[i] - (e ? e[i] : 0.0);
+        s += d.vol[i] * v * v;
+    }
+    s = block_sum256(s, lds);
+    if (threadIdx.x == 0) d.partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_norm_fin(Dev d, int64_t nparts) {
+    __shared__ double lds[16];
+    const double s = reduce_partials_sum(d.partial, nparts, lds);
+    if (threadIdx.x == 0) d.scal[SC_NORM] = s;
+}
+
 }  // namespace
+
+hipError_t launch_norm_l2(const Dev& d, const double* a, const double* e, hipStream_t s) {
+    const int64_t nb = std::min<int64_t>(1024, std::max<int64_t>(1, (d.nc + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_norm_part, dim3(unsigned(nb)), dim3(kBlock), 0, s, d, a, e);
+    hipLaunchKernelGGL(k_norm_fin, dim3(1), dim3(1024), 0, s, d, nb);
+    return hipGetLastError();
+}
 
 hipError_t launch_streamer_rhs(const Dev& d, double kappa, double* f, hipStream_t s) {
     hipLaunchKernelGGL(k_streamer_rhs, dim3(grid_s(d.nc)), dim3(kBlock), 0, s, d, kappa, f);

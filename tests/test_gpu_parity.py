@@ -104,6 +104,30 @@ def test_cfl_and_steps(case):
         assert abs(tot - t0) <= 1e-13 * abs(t0)
 
 
+def test_rcm_order_steps_and_norm():
+    """The step under the reverse Cuthill-McKee cell order equals the oracle
+    (the order is internal), and mifvm_norm_l2 is the cell-centre L2 norm
+    sqrt(sum mu_i (u_i - e_i)^2) of the annex's error report."""
+    n, seed, kinds, vals, D = CASES["ragged_mixed"]
+    print("[gpu] rcm order steps + L2 norm", flush=True)
+    mp = Mapped(n, seed, B.RENUMBER_RCM)
+    g = mp.geo
+    u0 = synth.gaussian_field(mp.m)
+    st = make_state(mp, kinds, vals, D, u0)
+    phi = fv.face_velocity_flux(g, synth.rotating_velocity(mp.m))
+    dt = fv.cfl_dt(g, phi, D, 0.4, kinds)
+    st.step(4, dt)
+    u = u0.copy()
+    for _ in range(4):
+        u = fv.rk3_step(g, u, dt, phi, D, kinds, vals)
+    assert rel(host(st.get_field(B.FIELD_U)), u) < TOL
+    e = np.sin(g.xc[:g.nc, 0])
+    ref = float(np.sqrt(np.sum(g.vol * (u - e) ** 2)))
+    got = st.norm_l2(B.FIELD_U, dev(e))
+    assert abs(got - ref) <= 1e-12 * ref
+    assert abs(st.norm_l2(B.FIELD_U) - float(np.sqrt(np.sum(g.vol * u ** 2)))) <= 1e-12 * ref
+
+
 def test_zero_steps_and_determinism():
     mp = Mapped(4, 6)
     u0 = synth.gaussian_field(mp.m)
