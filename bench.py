@@ -160,6 +160,9 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="cube120")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--forms", default="all",
+                    help="comma-separated forms to run after the main steps (fp32_refined, stored_matrix_cg, "
+                         "fgmres30, multigrid_fcg, streamer, learned), or all")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the reduced-precision (FP32 + refined solve) run")
     ap.add_argument("--calibrate-copy-gb", type=float, default=0.0,
@@ -300,27 +303,36 @@ def main():
         torch.cuda.synchronize()
         del st
         torch.cuda.empty_cache()
-        result["forms"] = {"fp32_refined": run_fp32_form(args, M, pf, u64, p64, result["poisson_solve_ms"])}
-        torch.cuda.empty_cache()
+        want = None if args.forms == "all" else set(args.forms.split(","))
+        run = lambda name: want is None or name in want
+        result["forms"] = {}
+        if run("fp32_refined"):
+            result["forms"]["fp32_refined"] = run_fp32_form(args, M, pf, u64, p64, result["poisson_solve_ms"])
+            torch.cuda.empty_cache()
         plain_ms = sum(solve_ms) / len(solve_ms)
-        result["forms"]["stored_matrix_cg"] = run_solver_form(
-            args, M, pf, "Jacobi-CG on the stored matrix", dict(matrix_free=False), plain_ms, p64)
-        form_cg = result["forms"]["stored_matrix_cg"]
-        form_cg["roofline_cg_spmv"] = {
-            "bytes_per_launch": nbytes["cg_spmv"], "avg_us": form_cg["kernel_avg_ms"]["cg_spmv"] * 1e3,
-            "achieved_GBps": round(nbytes["cg_spmv"] / (form_cg["kernel_avg_ms"]["cg_spmv"] * 1e-3) / 1e9, 1)}
-        torch.cuda.empty_cache()
-        result["forms"]["fgmres30"] = run_solver_form(
-            args, M, pf, "FGMRES(30) + Jacobi, matrix-free", dict(method=B.SOLVE_FGMRES, matrix_free=True),
-            plain_ms, p64, fgmres_m=30)
-        torch.cuda.empty_cache()
-        result["forms"]["multigrid_fcg"] = run_solver_form(
-            args, M, pf, "flexible CG + aggregation multigrid V(1,1), matrix-free",
-            dict(method=B.SOLVE_AMG, matrix_free=True), plain_ms, p64, amg=True)
-        torch.cuda.empty_cache()
-        result["forms"]["streamer"] = run_streamer_form(args, M, pf)
-        torch.cuda.empty_cache()
-        result["forms"]["learned"] = run_learned_form(args, M, pf, iters, solve_ms)
+        if run("stored_matrix_cg"):
+            result["forms"]["stored_matrix_cg"] = run_solver_form(
+                args, M, pf, "Jacobi-CG on the stored matrix", dict(matrix_free=False), plain_ms, p64)
+            form_cg = result["forms"]["stored_matrix_cg"]
+            form_cg["roofline_cg_spmv"] = {
+                "bytes_per_launch": nbytes["cg_spmv"], "avg_us": form_cg["kernel_avg_ms"]["cg_spmv"] * 1e3,
+                "achieved_GBps": round(nbytes["cg_spmv"] / (form_cg["kernel_avg_ms"]["cg_spmv"] * 1e-3) / 1e9, 1)}
+            torch.cuda.empty_cache()
+        if run("fgmres30"):
+            result["forms"]["fgmres30"] = run_solver_form(
+                args, M, pf, "FGMRES(30) + Jacobi, matrix-free", dict(method=B.SOLVE_FGMRES, matrix_free=True),
+                plain_ms, p64, fgmres_m=30)
+            torch.cuda.empty_cache()
+        if run("multigrid_fcg"):
+            result["forms"]["multigrid_fcg"] = run_solver_form(
+                args, M, pf, "flexible CG + aggregation multigrid V(1,1), matrix-free",
+                dict(method=B.SOLVE_AMG, matrix_free=True), plain_ms, p64, amg=True)
+            torch.cuda.empty_cache()
+        if run("streamer"):
+            result["forms"]["streamer"] = run_streamer_form(args, M, pf)
+            torch.cuda.empty_cache()
+        if run("learned"):
+            result["forms"]["learned"] = run_learned_form(args, M, pf, iters, solve_ms)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
