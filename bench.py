@@ -615,6 +615,30 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
     solve_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
     plain_ms = sum(plain_solve_ms) / len(plain_solve_ms)
     layer_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in kstats.items() if v[1]}
+    # the trained network as the finest-level smoother of the multigrid cycle:
+    # cold solves of one right-hand side with each smoother and plain
+    # Jacobi-CG, then stepped (warm) solves
+    amg_info = st.amg_build()
+    kw_mg = dict(tol=1e-10, restart=500, method=B.SOLVE_AMG, matrix_free=True)
+    cold_mg = {}
+    for name, extra in (("jacobi_smoother", {}), ("learned_smoother", dict(learned_smoother=True, chunk=8))):
+        st.set_field(B.FIELD_P, zero)
+        c = st.poisson_solve(None, **kw_mg, **extra)
+        cold_mg[name] = {"iterations": c["iterations"], "ms": round(c["ms"], 3)}
+    st.set_field(B.FIELD_P, zero)
+    c = st.poisson_solve(None, tol=1e-10, restart=500, matrix_free=True)
+    cold_mg["jacobi_cg"] = {"iterations": c["iterations"], "ms": round(c["ms"], 3)}
+    log(f"learned smoother in the multigrid cycle, cold: {cold_mg}")
+    ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    mg_solves = []
+    for k in range(args.steps):
+        st.step(1, dt)
+        ev2[k][0].record(stream)
+        mg_solves.append(st.poisson_solve(None, **kw_mg, learned_smoother=True, chunk=8))
+        ev2[k][1].record(stream)
+    torch.cuda.synchronize()
+    mg_ms = sum(e[0].elapsed_time(e[1]) for e in ev2) / args.steps
+    log(f"learned smoother in the multigrid cycle, warm: {[s['iterations'] for s in mg_solves]} it, {mg_ms:.1f} ms")
     del st
     return {"poisson_solve_ms": solve_ms,
             "poisson_iterations": [s["iterations"] for s in solves],
@@ -628,6 +652,11 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
                                        "jacobi_cg_iterations": cold_plain_csr["iterations"],
                                        "jacobi_cg_ms": cold_plain_csr["ms"]}},
             "kernel_avg_ms": layer_ms,
+            "as_multigrid_smoother": {"poisson_solve_ms": mg_ms,
+                                      "poisson_iterations": [s["iterations"] for s in mg_solves],
+                                      "poisson_rel_residual": max(s["rel_residual"] for s in mg_solves),
+                                      "speedup_vs_jacobi_cg": plain_ms / mg_ms, "cold": cold_mg,
+                                      "levels": amg_info["rows"]},
             "training": {"meshes_n": list(LEARNED["train_n"]), "samples": LEARNED["samples"],
                          "epochs": LEARNED["epochs"], "loss": "residual",
                          "epoch_loss": [round(float(x), 5) for x in tr["epoch_loss"]],

@@ -164,7 +164,11 @@ typedef struct {
                                   it in FP32 (FP32 copies of the vertex
                                   weights and diamond coefficients) and the
                                   true residual in FP64                      */
-    int32_t pad_;
+    int32_t learned_smoother;  /* AMG: 1 = the attached network (mifvm_nn.h)
+                                  replaces the Jacobi sweeps of the finest
+                                  level: x = z(b), then after the coarse
+                                  correction x += z(b - K x); E_STATE
+                                  without an attached network               */
 } mifvm_solve_opts;
 
 /* PLAIN: FP64 Jacobi-CG.  IR_FP32: iterative refinement - the FP64 true
@@ -391,9 +395,10 @@ int mifvm_amg_build(mifvm_state* st, const mifvm_amg_opts* opts, mifvm_amg_info*
  * (256-byte aligned, outliving the attachment; E_WORKSPACE otherwise);
  * d_ws NULL detaches.  Synchronises.                                       */
 int mifvm_amg_attach(mifvm_state* st, void* d_ws, size_t ws_bytes, void* stream);
-/* d_z = V(d_r), one cycle, user cell order (for inspection and tests).
- * Uses the solver's r and z vectors as scratch.                           */
-int mifvm_amg_apply(mifvm_state* st, const double* d_r, double* d_z, void* stream);
+/* d_z = V(d_r), one cycle, user cell order (for inspection and tests);
+ * learned_smoother as in mifvm_solve_opts.  Uses the solver's r and z
+ * vectors as scratch.                                                     */
+int mifvm_amg_apply(mifvm_state* st, int32_t learned_smoother, const double* d_r, double* d_z, void* stream);
 /* The same setup for any square CSR matrix (host arrays, diagonal included,
  * any column order), without a GPU, for inspection and tests.             */
 typedef struct mifvm_amg_host mifvm_amg_host;

@@ -91,22 +91,26 @@ def build(A: sp.csr_matrix, theta=0.25, coarse_max=1024, max_levels=10):
     return levels, np.linalg.inv(A.toarray())
 
 
-def v_cycle(levels, cinv, b, omega=2.0 / 3.0, level=0):
+def v_cycle(levels, cinv, b, omega=2.0 / 3.0, level=0, fine=None):
+    """One cycle; fine (optional) is a map r -> correction that replaces the
+    Jacobi sweeps on the finest level: x = fine(b), coarse correction,
+    x += fine(b - A x) (a learned smoother)."""
     A, agg = levels[level]
     if agg is None:
         return cinv @ b
     dinv = 1.0 / A.diagonal()
-    x = omega * dinv * b
+    smooth = fine if (fine is not None and level == 0) else (lambda r: omega * dinv * r)
+    x = smooth(b)
     r = b - A @ x
     bc = np.bincount(agg, weights=r, minlength=levels[level + 1][0].shape[0])
     x = x + v_cycle(levels, cinv, bc, omega, level + 1)[agg]
-    return x + omega * dinv * (b - A @ x)
+    return x + smooth(b - A @ x)
 
 
-def fcg(K, b, levels, cinv, x0=None, tol=1e-10, maxit=2000, restart=500, omega=2.0 / 3.0):
+def fcg(K, b, levels, cinv, x0=None, tol=1e-10, maxit=2000, restart=500, omega=2.0 / 3.0, fine=None):
     """Flexible CG (Polak-Ribiere beta) with one cycle as the preconditioner,
     reopened from the true residual when the recurrence meets tol or after
-    `restart` iterations; returns (x, iterations)."""
+    `restart` iterations; returns (x, iterations).  fine: as v_cycle."""
     x = np.zeros_like(b) if x0 is None else np.array(x0, np.float64)
     bb = float(b @ b)
     it = 0
@@ -114,7 +118,7 @@ def fcg(K, b, levels, cinv, x0=None, tol=1e-10, maxit=2000, restart=500, omega=2
         r = b - K @ x
         if r @ r <= tol * tol * bb or it >= maxit:
             return x, it
-        z = v_cycle(levels, cinv, r, omega)
+        z = v_cycle(levels, cinv, r, omega, fine=fine)
         p = z.copy()
         rz = float(z @ r)
         since = 0
@@ -128,7 +132,7 @@ def fcg(K, b, levels, cinv, x0=None, tol=1e-10, maxit=2000, restart=500, omega=2
             since += 1
             if r @ r <= tol * tol * bb or it >= maxit or since >= restart:
                 break
-            z = v_cycle(levels, cinv, r, omega)
+            z = v_cycle(levels, cinv, r, omega, fine=fine)
             zr, zro = float(z @ r), float(z @ r_old)
             beta = (zr - zro) / rz
             rz = zr

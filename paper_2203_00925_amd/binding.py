@@ -86,7 +86,7 @@ class SolveOpts(C.Structure):
                 ("history", C.POINTER(C.c_double)), ("method", C.c_int32),
                 ("graph", C.c_int32), ("inner_tol", C.c_double),
                 ("stall_window", C.c_int32), ("learned_maxit", C.c_int32),
-                ("matrix_free", C.c_int32), ("pad_", C.c_int32)]
+                ("matrix_free", C.c_int32), ("learned_smoother", C.c_int32)]
 
 
 class TuneInfo(C.Structure):
@@ -463,12 +463,12 @@ class State:
         self._amg_ws = ws
         return _amg_info(info)
 
-    def amg_apply(self, r, stream=None):
+    def amg_apply(self, r, learned_smoother=False, stream=None):
         """z = V(r), one multigrid cycle (user cell order)."""
         import torch
         r = r.to(device=self.device, dtype=torch.float64).contiguous()
         z = torch.empty_like(r)
-        _check(_lib.mifvm_amg_apply(self._h, _ptr(r), _ptr(z), _stream(stream)))
+        _check(_lib.mifvm_amg_apply(self._h, 1 if learned_smoother else 0, _ptr(r), _ptr(z), _stream(stream)))
         return z
 
     def poisson_apply_free(self, x, stream=None):
@@ -490,7 +490,7 @@ class State:
     def poisson_solve(self, f=None, tol=1e-10, maxit=20000, chunk=0, restart=500,
                       history=0, method=SOLVE_PLAIN, inner_tol=1e-4, graph=-1, stream=None,
                       allow_not_converged=False, stall_window=0, learned_maxit=0,
-                      allow_fell_back=False, matrix_free=False):
+                      allow_fell_back=False, matrix_free=False, learned_smoother=False):
         """chunk 0 / graph -1: the autotuned schedule (32 iterations per host
         check, direct launches when not tuned)."""
         import torch
@@ -499,7 +499,7 @@ class State:
         hist = (C.c_double * max(int(history), 1))()
         opts = SolveOpts(float(tol), int(maxit), int(chunk), int(restart), int(history), hist,
                          int(method), int(graph), float(inner_tol), int(stall_window),
-                         int(learned_maxit), 1 if matrix_free else 0, 0)
+                         int(learned_maxit), 1 if matrix_free else 0, 1 if learned_smoother else 0)
         info = SolveInfo()
         allow = (OK,) + ((NOT_CONVERGED,) if allow_not_converged else ()) + \
             ((FELL_BACK,) if allow_fell_back else ())

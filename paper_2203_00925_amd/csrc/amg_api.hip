@@ -74,6 +74,8 @@ size_t amg_layout(const AmgHierarchy& h, int64_t nc, char* base, AmgDev* a) {
     }
     A.cinv = carve<double>(base, off, h.cinv.size());
     A.r_old = carve<double>(base, off, nc);
+    A.s0 = carve<double>(base, off, nc);
+    A.s1 = carve<double>(base, off, nc);
     return (off + 255) & ~size_t(255);
 }
 
@@ -124,21 +126,24 @@ void amg_release(State& s) {
 }
 
 int amg_phase(State& s, double tol, int maxit, int chunk, int restart, bool use_graph, bool matrix_free,
-              hipStream_t hs, const std::function<int()>& pull, int& restarts) {
+              bool learned, hipStream_t hs, const std::function<int()>& pull, int& restarts) {
     const Dev& d = s.d;
     const AmgDev& a = *s.amg;
     const BcTable& bc = s.bc[1];
     KernelTimer& tm = s.timer;
+    // the attached network as the finest level's smoother
+    const AmgSmoother nn = [&s](const double* in, double* out, hipStream_t q) { return nn_apply_vec(s, in, out, q); };
+    const AmgSmoother* fine = learned ? &nn : nullptr;
     auto open = [&](bool fresh) -> int {
         HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs,
-                     [&] { return launch_amg_open(d, bc, a, tol, maxit, restart, fresh, hs); }));
+                     [&] { return launch_amg_open(d, bc, a, tol, maxit, restart, fresh, hs, fine); }));
         return pull();
     };
-    const int key = chunk + (matrix_free ? 1 << 20 : 0);
+    const int key = chunk + (matrix_free ? 1 << 20 : 0) + (learned ? 1 << 21 : 0);
     if (use_graph && (s.amg_exec == nullptr || s.amg_exec_key != key)) {
         HIPCHK(capture_graph(s, &s.amg_exec, [&](hipStream_t q) -> hipError_t {
             for (int c = 0; c < chunk; ++c) {
-                hipError_t e = launch_amg_iteration(d, bc, a, matrix_free, q);
+                hipError_t e = launch_amg_iteration(d, bc, a, matrix_free, q, fine);
                 if (e != hipSuccess) return e;
             }
             return hipSuccess;
@@ -155,7 +160,7 @@ int amg_phase(State& s, double tol, int maxit, int chunk, int restart, bool use_
             } else {
                 for (int c = 0; c < chunk; ++c)
                     HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs,
-                                 [&] { return launch_amg_iteration(d, bc, a, matrix_free, hs); }));
+                                 [&] { return launch_amg_iteration(d, bc, a, matrix_free, hs, fine); }));
             }
             if ((rc = pull())) return rc;
         }
@@ -259,14 +264,16 @@ int mifvm_amg_attach(mifvm_state* st, void* d_ws, size_t ws_bytes, void* stream)
     return MIFVM_OK;
 }
 
-int mifvm_amg_apply(mifvm_state* st, const double* d_r, double* d_z, void* stream) {
+int mifvm_amg_apply(mifvm_state* st, int32_t learned_smoother, const double* d_r, double* d_z, void* stream) {
     if (!st || !d_r || !d_z) return fail(MIFVM_E_ARG, "null argument");
     State& s = st->s;
     if (!s.amg) return fail(MIFVM_E_STATE, "no multigrid attached");
+    if (learned_smoother && (!s.nn || !s.nn_state)) return fail(MIFVM_E_STATE, "no network attached");
     const Dev& d = s.d;
     hipStream_t hs = S(stream);
+    const AmgSmoother nn = [&s](const double* in, double* out, hipStream_t q) { return nn_apply_vec(s, in, out, q); };
     HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_r, d.r, hs));
-    HIPCHK(launch_amg_cycle(d, s.bc[1], *s.amg, d.r, d.z, nullptr, hs));
+    HIPCHK(launch_amg_cycle(d, s.bc[1], *s.amg, d.r, d.z, nullptr, hs, learned_smoother ? &nn : nullptr));
     HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.z, d_z, hs));
     return MIFVM_OK;
 }

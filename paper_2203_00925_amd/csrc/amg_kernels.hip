@@ -76,6 +76,23 @@ __global__ __launch_bounds__(kBlock) void k_amg_restrict(int64_t nco, const int6
     bc[I] = s;
 }
 
+// r = b - t
+__global__ __launch_bounds__(kBlock) void k_amg_sub(int64_t n, const double* __restrict__ b,
+                                                    const double* __restrict__ t, double* __restrict__ r,
+                                                    const double* flag) {
+    if (done(flag)) return;
+    const int64_t i = tid_a();
+    if (i < n) r[i] = b[i] - t[i];
+}
+
+// x += y
+__global__ __launch_bounds__(kBlock) void k_amg_add(int64_t n, const double* __restrict__ y, double* __restrict__ x,
+                                                    const double* flag) {
+    if (done(flag)) return;
+    const int64_t i = tid_a();
+    if (i < n) x[i] = x[i] + y[i];
+}
+
 // x[i] += x_c[agg[i]]
 __global__ __launch_bounds__(kBlock) void k_amg_prolong(int64_t n, const int32_t* __restrict__ agg,
                                                         const double* __restrict__ xc, double* __restrict__ x,
@@ -224,7 +241,7 @@ __global__ __launch_bounds__(1024) void k_amg_beta_fin(Dev d, int64_t nparts) {
 }  // namespace
 
 hipError_t launch_amg_cycle(const Dev& d, const BcTable& bc_pot, const AmgDev& a, const double* b0, double* x0,
-                            const double* flag, hipStream_t s) {
+                            const double* flag, hipStream_t s, const AmgSmoother* fine) {
     const int nl = a.nl;
     const double w = a.omega;
     if (nl == 1) {                 // the system is small enough to invert densely
@@ -232,8 +249,15 @@ hipError_t launch_amg_cycle(const Dev& d, const BcTable& bc_pot, const AmgDev& a
         return hipGetLastError();
     }
     // down: level 0 (matrix-free product into tmp), then the coarse levels
-    hipLaunchKernelGGL(k_amg_smooth0, dim3(grid_a(d.nc)), dim3(kBlock), 0, s, d.nc, w, d.k_dinv, b0, x0, flag);
-    hipError_t e = launch_mf_apply(d, bc_pot, x0, d.tmp, s, flag);
+    hipError_t e = hipSuccess;
+    if (fine) {
+        e = (*fine)(b0, x0, s);                    // x = M(b)
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(k_amg_smooth0, dim3(grid_a(d.nc)), dim3(kBlock), 0, s, d.nc, w, d.k_dinv, b0, x0,
+                           flag);
+    }
+    e = launch_mf_apply(d, bc_pot, x0, d.tmp, s, flag);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_amg_restrict, dim3(grid_a(a.lv[1].n)), dim3(kBlock), 0, s, a.lv[1].n, a.lv[0].mptr,
                        a.lv[0].midx, b0, d.tmp, a.lv[1].b, flag);
@@ -259,19 +283,26 @@ hipError_t launch_amg_cycle(const Dev& d, const BcTable& bc_pot, const AmgDev& a
                        flag);
     e = launch_mf_apply(d, bc_pot, x0, d.tmp, s, flag);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_amg_smooth1, dim3(grid_a(d.nc)), dim3(kBlock), 0, s, d.nc, w, d.k_dinv, b0, d.tmp, x0,
-                       flag);
+    if (fine) {                                    // x += M(b - K x)
+        hipLaunchKernelGGL(k_amg_sub, dim3(grid_a(d.nc)), dim3(kBlock), 0, s, d.nc, b0, d.tmp, a.s0, flag);
+        e = (*fine)(a.s0, a.s1, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_amg_add, dim3(grid_a(d.nc)), dim3(kBlock), 0, s, d.nc, a.s1, x0, flag);
+    } else {
+        hipLaunchKernelGGL(k_amg_smooth1, dim3(grid_a(d.nc)), dim3(kBlock), 0, s, d.nc, w, d.k_dinv, b0, d.tmp,
+                           x0, flag);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_amg_open(const Dev& d, const BcTable& bc_pot, const AmgDev& a, double tol, int maxit,
-                           int restart, bool fresh, hipStream_t s) {
+                           int restart, bool fresh, hipStream_t s, const AmgSmoother* fine) {
     const int64_t nb = grid_a(d.nc);
     hipError_t e = launch_mf_apply(d, bc_pot, d.x, d.tmp, s);            // t = K x
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_amg_open, dim3(unsigned(nb)), dim3(kBlock), 0, s, d, d.tmp);
     hipLaunchKernelGGL(k_amg_open_fin, dim3(1), dim3(1024), 0, s, d, nb, tol, maxit, restart, fresh ? 1 : 0);
-    e = launch_amg_cycle(d, bc_pot, a, d.r, d.z, d.scal + SC_DONE, s);
+    e = launch_amg_cycle(d, bc_pot, a, d.r, d.z, d.scal + SC_DONE, s, fine);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_amg_p0, dim3(unsigned(nb)), dim3(kBlock), 0, s, d);
     hipLaunchKernelGGL(k_amg_rz_fin, dim3(1), dim3(1024), 0, s, d, nb);
@@ -279,13 +310,13 @@ hipError_t launch_amg_open(const Dev& d, const BcTable& bc_pot, const AmgDev& a,
 }
 
 hipError_t launch_amg_iteration(const Dev& d, const BcTable& bc_pot, const AmgDev& a, bool matrix_free,
-                                hipStream_t s) {
+                                hipStream_t s, const AmgSmoother* fine) {
     const int64_t nb = grid_a(d.nc);
     hipError_t e = matrix_free ? launch_mf_cg_spmv(d, bc_pot, s) : launch_cg_spmv(d, s);   // q = K p, alpha
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_amg_axpy, dim3(unsigned(nb)), dim3(kBlock), 0, s, d, a.r_old);
     hipLaunchKernelGGL(k_amg_rr_fin, dim3(1), dim3(1024), 0, s, d, nb);
-    e = launch_amg_cycle(d, bc_pot, a, d.r, d.z, d.scal + SC_DONE, s);
+    e = launch_amg_cycle(d, bc_pot, a, d.r, d.z, d.scal + SC_DONE, s, fine);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_amg_zdots, dim3(unsigned(nb)), dim3(kBlock), 0, s, d, a.r_old);
     hipLaunchKernelGGL(k_amg_beta_fin, dim3(1), dim3(1024), 0, s, d, nb);

@@ -755,9 +755,12 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
     if (method != MIFVM_SOLVE_PLAIN && method != MIFVM_SOLVE_IR_FP32 && method != MIFVM_SOLVE_LEARNED &&
         method != MIFVM_SOLVE_FGMRES && method != MIFVM_SOLVE_AMG)
         return fail(MIFVM_E_ARG, "unknown method");
+    const bool learned_smoother = opts && opts->learned_smoother != 0;
     if (method == MIFVM_SOLVE_AMG) {
         if (!s.amg) return fail(MIFVM_E_STATE, "method AMG needs an attached hierarchy (mifvm_amg_build/attach)");
         if (s.d.nm != 1) return fail(MIFVM_E_ARG, "method AMG needs a single-mesh state");
+        if (learned_smoother && (!s.nn || !s.nn_state))
+            return fail(MIFVM_E_STATE, "learned_smoother needs an attached network");
     }
     if (method == MIFVM_SOLVE_FGMRES) {
         if (!s.gm) return fail(MIFVM_E_STATE, "method FGMRES needs a workspace (mifvm_fgmres_attach)");
@@ -896,7 +899,9 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
             if (hsc(s, 0, SC_DONE) == 0.0) ++restarts;
         }
     } else if (method == MIFVM_SOLVE_AMG) {
-        if ((rc = amg_phase(s, tol, maxit, chunk, restart, use_graph, matrix_free, hs, pull, restarts))) return rc;
+        if ((rc = amg_phase(s, tol, maxit, chunk, restart, use_graph, matrix_free, learned_smoother, hs, pull,
+                            restarts)))
+            return rc;
     } else if (method == MIFVM_SOLVE_LEARNED && !learned.fell_back) {
         // the flexible CG ended: converged, or at maxit
     } else if (run_method == MIFVM_SOLVE_PLAIN) {

@@ -143,8 +143,12 @@ int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int s
 
 // Multigrid-preconditioned flexible CG (amg_api.hip): runs until the true
 // residual meets tol or the iteration limit; restarts counted.
+// learned: the attached network replaces the finest level's Jacobi sweeps.
 int amg_phase(State& s, double tol, int maxit, int chunk, int restart, bool use_graph, bool matrix_free,
-              hipStream_t hs, const std::function<int()>& pull, int& restarts);
+              bool learned, hipStream_t hs, const std::function<int()>& pull, int& restarts);
+// out = z(in) of the attached network (input scales, then the 3 layers;
+// nn_api.hip), launches only
+hipError_t nn_apply_vec(State& s, const double* in, double* out, hipStream_t q);
 // free the hierarchy, its device record and graph of a state
 void amg_release(State& s);
 

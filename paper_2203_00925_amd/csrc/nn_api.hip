@@ -236,6 +236,14 @@ int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int s
     }
 }
 
+hipError_t nn_apply_vec(State& s, const double* in, double* out, hipStream_t q) {
+    const Dev& d = s.d;
+    hipError_t e = launch_nn_scale(d, in, nullptr, q);
+    for (int l = 0; e == hipSuccess && l < kNnLayers; ++l)
+        e = launch_nn_layer(d, *s.nn, *s.nn_state, l, in, nullptr, out, false, false, q);
+    return e;
+}
+
 }  // namespace mifvm_api
 
 extern "C" {

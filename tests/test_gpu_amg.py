@@ -13,7 +13,7 @@ import scipy.sparse as sp
 
 import synth
 from conftest import cube
-from oracle import amg, poisson
+from oracle import amg, mpnn, poisson
 from oracle.geometry import DIRICHLET, NEUMANN
 
 pytestmark = pytest.mark.gpu
@@ -115,3 +115,71 @@ def test_single_level_and_errors():
     f = synth.gaussian_field(m)
     s = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_AMG)
     assert s["status"] == B.OK and s["iterations"] <= 2
+
+
+def random_params(seed=11, scale=0.3):
+    """Random network weights with non-zero biases and decoder, rounded to
+    FP32 (the GPU's master copy), as the oracle's FP64 dict."""
+    rng = np.random.default_rng(seed)
+    p = mpnn.init_params(seed, scale)
+    for k in p:
+        if k.startswith("b") or k == "wd":
+            p[k] = rng.normal(0, scale, np.shape(p[k]))
+    flat = mpnn.flatten(p).astype(np.float32)
+    return flat, mpnn.unflatten(flat.astype(np.float64), p)
+
+
+def test_learned_smoother_cycle_and_solve():
+    """The network as the finest level's smoother.  With the decoder at zero
+    the network is exactly z = D^-1 r, so the cycle equals the oracle's cycle
+    with that smoother to rounding (1e-10) and the solve takes the oracle's
+    iterations.  With random weights the cycle equals the oracle's cycle with
+    the oracle network (same bf16 roundings) within the network's own forward
+    tolerance (an activation near a bf16 rounding boundary may round the
+    other way: about one bf16 ulp locally), and it is exactly 1-homogeneous."""
+    print("[gpu] multigrid with the network as smoother", flush=True)
+    mp, K, c, K_int, st = setup()
+    st.amg_build(coarse_max=CMAX)
+    net = B.Network(seed=3)
+    flat, p = random_params()
+    dinv = 1.0 / K.diagonal()
+    dinv_int = 1.0 / K_int.diagonal()
+    nbr = mpnn.face_neighbours(mp.geo)
+    levels, cinv = amg.build(K_int, coarse_max=CMAX)
+    r = np.random.default_rng(8).normal(size=mp.geo.nc)
+    z_ref = np.empty_like(r)
+    # decoder at zero: the Jacobi map exactly
+    flat0 = flat.copy()
+    flat0[mpnn.flatten(p).size - 33:] = 0.0
+    net.set_params(flat0)
+    net.attach(st)
+    z = host(st.amg_apply(dev(r), learned_smoother=True))
+    z_ref[mp.cp] = amg.v_cycle(levels, cinv, r[mp.cp], fine=lambda r_: dinv_int * r_)
+    err = np.abs(z - z_ref).max() / np.abs(z_ref).max()
+    print(f"[gpu] Jacobi-decoder cycle error {err:.2e}", flush=True)
+    assert err < 1e-10
+    f = synth.gaussian_field(mp.m)
+    info = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_AMG, matrix_free=True, learned_smoother=True,
+                            chunk=4)
+    b = poisson.rhs(mp.geo, f, c)
+    assert info["status"] == B.OK
+    assert poisson.true_relative_residual(K, b, host(st.get_field(B.FIELD_P))) <= 1.01e-10
+    _, it_ref = amg.fcg(K_int, b[mp.cp], levels, cinv, tol=1e-10, fine=lambda r_: dinv_int * r_)
+    print(f"[gpu] learned-smoother solve (Jacobi decoder) {info['iterations']} it (oracle {it_ref})", flush=True)
+    assert abs(info["iterations"] - it_ref) <= 2
+    # random weights
+    net.set_params(flat)
+
+    def fine_int(r_int):                     # the network is equivariant: apply it in user order
+        r_user = np.empty_like(r_int)
+        r_user[mp.cp] = r_int
+        z_user, _ = mpnn.forward(p, r_user, dinv, nbr, bf16_like_gpu=True)
+        return z_user[mp.cp]
+
+    z = host(st.amg_apply(dev(r), learned_smoother=True))
+    z_ref[mp.cp] = amg.v_cycle(levels, cinv, r[mp.cp], fine=fine_int)
+    err = np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref)
+    print(f"[gpu] learned-smoother cycle error {err:.2e} (max {np.abs(z - z_ref).max() / np.abs(z_ref).max():.2e})",
+          flush=True)
+    assert err < 1e-2
+    assert np.array_equal(host(st.amg_apply(dev(2.0 * r), learned_smoother=True)), 2.0 * z)

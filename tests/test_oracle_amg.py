@@ -87,6 +87,17 @@ def test_multigrid_flexible_cg_converges_fast():
     assert it < it_j / 4
 
 
+def test_a_jacobi_smoother_passed_in_gives_the_plain_cycle():
+    """fine = the damped Jacobi map reproduces the default cycle exactly."""
+    _, K, _ = poisson_K()
+    levels, cinv = amg.build(K, coarse_max=64)
+    dinv = 1.0 / K.diagonal()
+    b = np.random.default_rng(4).normal(size=K.shape[0])
+    z0 = amg.v_cycle(levels, cinv, b)
+    z1 = amg.v_cycle(levels, cinv, b, fine=lambda r: (2.0 / 3.0) * dinv * r)
+    assert np.array_equal(z0, z1)
+
+
 @pytest.mark.parametrize("coarse_max", [64, 300])
 def test_library_setup_equals_oracle(coarse_max):
     _, K, _ = poisson_K()
