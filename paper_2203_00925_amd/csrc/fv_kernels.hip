@@ -80,14 +80,21 @@ __device__ inline void stage_halo(const Dev& d, const R* __restrict__ u, V4* sm,
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int h = hb + j * T + threadIdx.x;
-            e[j] = h < hn ? d.h_idx[h0 + h] : -1;
+            e[j] = d.h_idx[h0 + (h < hn ? h : 0)];
+        }
+        // every gather is issued before the first LDS write (a slot past the
+        // halo re-reads its first entity and is not stored)
+        double4 r[8];
+        R ue[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            r[j] = P[e[j]];
+            ue[j] = u[e[j]];
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            if (e[j] >= 0) {
-                const double4 r = P[e[j]];
-                sm[hb + j * T + threadIdx.x] = mk4(R(r.x - ref.x), R(r.y - ref.y), R(r.z - ref.z), u[e[j]]);
-            }
+            const int h = hb + j * T + threadIdx.x;
+            if (h < hn) sm[h] = mk4(R(r[j].x - ref.x), R(r[j].y - ref.y), R(r[j].z - ref.z), ue[j]);
         }
     }
 }
@@ -108,25 +115,32 @@ struct HaloSoA {
 };
 
 template <class R>
-__device__ inline void stage_halo_soa(const Dev& d, const R* __restrict__ u, HaloSoA<R> sm, int64_t t, double4 ref) {
+__device__ inline void stage_halo_soa(const Dev& d, const R* __restrict__ u, HaloSoA<R> sm, int64_t t, double4 ref,
+                                      int from = 0) {
     const int T = blockDim.x;
     const int64_t h0 = d.h_off[t];
     const int hn = int(d.h_off[t + 1] - h0);
     const double4* __restrict__ P = d.xyz4;
-    for (int hb = 0; hb < hn; hb += 8 * T) {
+    for (int hb = from; hb < hn; hb += 8 * T) {
         int e[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int h = hb + j * T + threadIdx.x;
-            e[j] = h < hn ? d.h_idx[h0 + h] : -1;
+            e[j] = d.h_idx[h0 + (h < hn ? h : 0)];
+        }
+        double4 r[8];
+        R ue[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            r[j] = P[e[j]];
+            ue[j] = u[e[j]];
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            if (e[j] >= 0) {
-                const double4 r = P[e[j]];
-                const int h = hb + j * T + threadIdx.x;
-                sm.xy[h] = mk2(R(r.x - ref.x), R(r.y - ref.y));
-                sm.zu[h] = mk2(R(r.z - ref.z), u[e[j]]);
+            const int h = hb + j * T + threadIdx.x;
+            if (h < hn) {
+                sm.xy[h] = mk2(R(r[j].x - ref.x), R(r[j].y - ref.y));
+                sm.zu[h] = mk2(R(r[j].z - ref.z), ue[j]);
             }
         }
     }
@@ -281,76 +295,118 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
     const bool cell = i < nc;
     const int lself = d.h_self[t] + threadIdx.x;
 
-    // Global loads that do not depend on LDS are issued before the barriers,
-    // so their latency overlaps the halo staging: the cell's tables, the
-    // first batch of its edge neighbours, and the first batch of the vertex
-    // list this thread will sum.
-    uint16_t nl[4] = {0, 0, 0, 0}, lv[4] = {0, 0, 0, 0};
-    int fc[4] = {0, 0, 0, 0};
-    if (cell) {
+    // Global loads are issued in two waves before the first barrier, so the
+    // tile pays about two memory latencies before its LDS work: first every
+    // load that depends on no other (the first 8T halo indices, the cell's
+    // tables, the slice headers of its edge-neighbour list and of the vertex
+    // list it will sum), then the loads addressed by those (the halo
+    // gathers, the first batches of both lists).  Out-of-range slots read a
+    // valid address and are discarded, so no load sits under a branch.
+    const int64_t h0 = d.h_off[t];
+    const int hn = int(d.h_off[t + 1] - h0);
+    int he[8];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int f = d.c2f[k * nc + i];
-            fc[k] = f < 0 ? ~f : f;
-            nl[k] = d.c2n_l[k * nc + i];
-            lv[k] = d.c2v_l[k * nc + i];
-        }
+    for (int j = 0; j < 8; ++j) {
+        const int h = j * T + threadIdx.x;
+        he[j] = d.h_idx[h0 + (h < hn ? h : 0)];
     }
-    const uint16_t* __restrict__ eidx = d.e_lidx + (cell ? d.e_off[i >> 6] + (i & 63) : 0);
-    const int ew = cell ? d.e_w[i >> 6] : 0;
-    uint16_t el[8];
+    const int64_t ic = cell ? i : nc - 1;
+    uint16_t nl[4], lv[4];
+    int fc[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) el[j] = j < ew ? eidx[int64_t(j) * 64] : uint16_t(lself);
+    for (int k = 0; k < 4; ++k) {
+        fc[k] = d.c2f[k * nc + ic];
+        nl[k] = d.c2n_l[k * nc + ic];
+        lv[k] = d.c2v_l[k * nc + ic];
+    }
+    const int64_t eoff = d.e_off[ic >> 6];
+    const int ew = cell ? d.e_w[ic >> 6] : 0;
 
     const int64_t v0 = d.v_off[t], f0 = d.fv_off[t];
     const int own = int(d.v_off[t + 1] - v0), nfor = int(d.fv_off[t + 1] - f0);
     int r = threadIdx.x;
-    bool mine = r < own;
-    int64_t row = mine ? v0 + r : f0 + (r - own);
-    int64_t vbase = 0;
+    bool mine = true;
+    int64_t row = 0, vbase = 0;
     int vw = 0, vn = 1;
     const uint16_t* __restrict__ li = d.n_lidx;
-    uint16_t vl[8];
-    R val[8];
-    auto vrow = [&]() {                 // row meta and its first batch
-        mine = r < own;
-        row = mine ? v0 + r : f0 + (r - own);
+    constexpr int VB = 8;               // vertex-list entries per batch
+    uint16_t vl[VB];
+    R val[VB];
+    // row meta of vertex row r (threads past the rows read row 0 of the
+    // tile-owned lists and sum nothing)
+    auto vmeta = [&]() {
+        const bool act = r < own + nfor;
+        mine = !act || r < own;
+        row = !act ? 0 : (mine ? v0 + r : f0 + (r - own));
         const int64_t sl = row >> 6;
-        vbase = (mine ? d.n_off[sl] : d.f_off[sl]) + (row & 63);
-        vw = mine ? d.n_w[sl] : d.f_w[sl];
-        vn = mine ? d.n_len[row] : d.fv_len[row];
+        const int64_t* __restrict__ op = mine ? d.n_off : d.f_off;
+        const int32_t* __restrict__ wp = mine ? d.n_w : d.f_w;
+        const int32_t* __restrict__ np = mine ? d.n_len : d.fv_len;
+        vbase = op[sl] + (row & 63);
+        vw = act ? wp[sl] : 0;
+        vn = np[row];
         li = mine ? d.n_lidx : d.f_lidx;
+    };
+    auto vbatch = [&]() {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < VB; ++j) {
             const bool in = j < vw;
             vl[j] = in ? li[vbase + int64_t(j) * 64] : uint16_t(0);
             val[j] = (mine && in) ? a.n_alpha[vbase + int64_t(j) * 64] : R(0);
         }
     };
-    if (r < own + nfor) vrow();
+    vmeta();
+
+    const double4* __restrict__ P = d.xyz4;
+    double4 hp[8];
+    R hu[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        hp[j] = P[he[j]];
+        hu[j] = a.u[he[j]];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fc[k] = fc[k] < 0 ? ~fc[k] : fc[k];
+    const uint16_t* __restrict__ eidx = d.e_lidx + (cell ? eoff + (i & 63) : 0);
+    constexpr int EB = 16;              // edge-only neighbours per batch
+    uint16_t el[EB];
+#pragma unroll
+    for (int j = 0; j < EB; ++j) el[j] = j < ew ? eidx[int64_t(j) * 64] : uint16_t(lself);
+    vbatch();
 
     const double4 ref = rel ? d.xyz4[t * T] : make_double4(0.0, 0.0, 0.0, 0.0);
-    stage_halo_soa<R>(d, a.u, sm, t, ref);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int h = j * T + threadIdx.x;
+        if (h < hn) {
+            sm.xy[h] = mk2(R(hp[j].x - ref.x), R(hp[j].y - ref.y));
+            sm.zu[h] = mk2(R(hp[j].z - ref.z), hu[j]);
+        }
+    }
+    if (hn > 8 * T) stage_halo_soa<R>(d, a.u, sm, t, ref, 8 * T);
     __syncthreads();
 
     for (; r < own + nfor; r += T) {
-        if (r != int(threadIdx.x)) vrow();
+        if (r != int(threadIdx.x)) {
+            vmeta();
+            vbatch();
+        }
         const uint16_t l0 = vl[0];
         const V4 q0 = sm[l0];
         R un = R(0), sx = R(0), sy = R(0), sz = R(0), su = R(0), cx = R(0), cy = R(0), cz = R(0);
-        for (int k0 = 0; k0 < vw; k0 += 8) {
+        for (int k0 = 0; k0 < vw; k0 += VB) {
             // next batch in flight while this one is summed (pad = first entry)
-            uint16_t nlx[8];
-            R nal[8];
+            uint16_t nlx[VB];
+            R nal[VB];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const bool in = k0 + 8 + j < vw;
-                const int64_t at = vbase + int64_t(k0 + 8 + j) * 64;
+            for (int j = 0; j < VB; ++j) {
+                const bool in = k0 + VB + j < vw;
+                const int64_t at = vbase + int64_t(k0 + VB + j) * 64;
                 nlx[j] = in ? li[at] : l0;
                 nal[j] = (mine && in) ? a.n_alpha[at] : R(0);
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < VB; ++j) {
                 const V4 q = sm[k0 + j < vw ? vl[j] : l0];
                 const R dx = q.x - q0.x, dy = q.y - q0.y, dz = q.z - q0.z, du = q.w - q0.w;
                 un += val[j] * q.w;
@@ -358,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
                 cx += dx * du; cy += dy * du; cz += dz * du;
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < VB; ++j) {
                 vl[j] = nlx[j];
                 val[j] = nal[j];
             }
@@ -369,16 +425,15 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
         vr[2 * r + 1] = mk4(cx - sx * mu, cy - sy * mu, cz - sz * mu, q0.w + mu);
         if (mine) a.unode[row] = un;
     }
-    __syncthreads();
-    if (!cell) return;
-
-    // loads used at the end (limiter, M^-1) go out before the LDS work
+    // loads used at the end (limiter, M^-1) go out before the barrier
     double4 xf[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) xf[k] = d.fx4[fc[k]];
     const R* __restrict__ m = a.minv;
-    const R m0 = m[i], m1 = m[nc + i], m2 = m[2 * nc + i];
-    const R m3 = m[3 * nc + i], m4 = m[4 * nc + i], m5 = m[5 * nc + i];
+    const R m0 = m[ic], m1 = m[nc + ic], m2 = m[2 * nc + ic];
+    const R m3 = m[3 * nc + ic], m4 = m[4 * nc + ic], m5 = m[5 * nc + ic];
+    __syncthreads();
+    if (!cell) return;
 
     const V4 me = sm[lself];
     const R xi = me.x, yi = me.y, zi = me.z, ui = me.w;
@@ -403,13 +458,13 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
         umin = fmin(umin, o.w);
     }
     // edge-only neighbours (slice padding = the cell itself, which adds zeros)
-    for (int k0 = 0; k0 < ew; k0 += 8) {
-        uint16_t nx[8];
+    for (int k0 = 0; k0 < ew; k0 += EB) {
+        uint16_t nx[EB];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            nx[j] = k0 + 8 + j < ew ? eidx[int64_t(k0 + 8 + j) * 64] : uint16_t(lself);
+        for (int j = 0; j < EB; ++j)
+            nx[j] = k0 + EB + j < ew ? eidx[int64_t(k0 + EB + j) * 64] : uint16_t(lself);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < EB; ++j) {
             if (k0 + j < ew) {          // uniform over the wave (one slice)
                 const V4 o = sm[el[j]];
                 const R du = o.w - ui;
@@ -419,7 +474,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
             }
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) el[j] = nx[j];
+        for (int j = 0; j < EB; ++j) el[j] = nx[j];
     }
     const R gx = m0 * jx + m1 * jy + m2 * jz;
     const R gy = m1 * jx + m3 * jy + m4 * jz;
@@ -515,12 +570,15 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev d, FvArrays<R> a, double 
     const R a_dt = R(alpha * d.mesh_dt[mesh_of(d, i)]);
     const int64_t nc = d.nc;
     R acc = R(0);
+    // the four flux loads go out together (no load under a branch)
+    int c[4];
+    R fl[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int c = d.c2f[k * nc + i];
-        if (c >= 0) acc += a.flux[c];
-        else acc -= a.flux[~c];
-    }
+    for (int k = 0; k < 4; ++k) c[k] = d.c2f[k * nc + i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fl[k] = a.flux[c[k] >= 0 ? c[k] : ~c[k]];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc += c[k] >= 0 ? fl[k] : -fl[k];
     const R res = -acc / a.vol[i] + a.src[i];
     R base;
     if (first) {
