@@ -4,6 +4,7 @@
 // partial sums of a fixed grid, added in block order by one block
 // (deterministic).
 #include "gmres.h"
+#include "halo_stage.h"
 #include "reduce.h"
 
 namespace mifvm {
@@ -92,12 +93,7 @@ __global__ __launch_bounds__(256) void k_gm_spmv(Dev d, GmDev g, int j) {
     const int T = blockDim.x;
     const double* __restrict__ z = g.Z + int64_t(j) * nc;
     double* w = g.V + int64_t(j + 1) * nc;
-    const int64_t h0 = d.h_off[t];
-    const int hn = int(d.h_off[t + 1] - h0);
-    for (int h = threadIdx.x; h < hn; h += T) {
-        const int e = d.h_idx[h0 + h];
-        sp[h] = e < nc ? z[e] : 0.0;
-    }
+    stage_halo_values(d, t, z, sp);
     __syncthreads();
     const int64_t i = t * T + threadIdx.x;
     if (i >= nc) return;
@@ -105,10 +101,19 @@ __global__ __launch_bounds__(256) void k_gm_spmv(Dev d, GmDev g, int j) {
     const int64_t base = d.k_off[s] + (i & 63);
     const int wd = d.k_w[s];
     double y = d.k_diag[i] * sp[d.h_self[t] + threadIdx.x];
-#pragma unroll 4
-    for (int k = 0; k < wd; ++k) {
-        const int64_t at = base + int64_t(k) * 64;
-        y += d.k_val[at] * sp[d.k_lidx[at]];
+    for (int k0 = 0; k0 < wd; k0 += 16) {
+        uint16_t l[16];
+        double a[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const bool in = k0 + jj < wd;
+            const int64_t at = base + int64_t(k0 + jj) * 64;
+            l[jj] = in ? d.k_lidx[at] : uint16_t(0);
+            a[jj] = in ? d.k_val[at] : 0.0;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj)
+            if (k0 + jj < wd) y += a[jj] * sp[l[jj]];
     }
     w[i] = y;
 }

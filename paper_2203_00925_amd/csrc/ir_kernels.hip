@@ -7,6 +7,7 @@
 #include "reduce.h"
 #include "seg.h"
 #include "state.h"
+#include "halo_stage.h"
 
 namespace mifvm {
 
@@ -104,12 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_cg32_spmv(Dev d) {
     const int T = blockDim.x;
     const BlockSeg g = block_seg(d, t * T, T);
     if (block_done(d, g)) return;
-    const int64_t h0 = d.h_off[t];
-    const int hn = int(d.h_off[t + 1] - h0);
-    for (int h = threadIdx.x; h < hn; h += T) {
-        const int e = d.h_idx[h0 + h];
-        sp32[h] = e < nc ? d.p32[e] : 0.0f;
-    }
+    stage_halo_values(d, t, d.p32, sp32);
     __syncthreads();
     const int64_t i = t * T + threadIdx.x;
     double v[1] = {0.0};

@@ -65,21 +65,35 @@ __global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict
     const int w = d.n_w[sl];
     const int nc = int(d.nc);
     R s = R(0);
-    for (int k0 = 0; k0 < w; k0 += 8) {
-        int e[8];
-        R al[8];
+    // batches of 8: the next batch's indices and weights are in flight while
+    // this batch's values are gathered (one load per entry: a cell's x or a
+    // ghost's xg, by pointer)
+    int e[8];
+    R al[8];
+    auto batch = [&](int k0, int* eo, R* ao) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const bool in = k0 + j < w;
             const int64_t at = base + int64_t(k0 + j) * 64;
-            e[j] = in ? d.n_idx[at] : 0;                 // padding entries carry weight 0
-            al[j] = in ? alpha[at] : R(0);
+            eo[j] = in ? d.n_idx[at] : 0;                // padding entries carry weight 0
+            ao[j] = in ? alpha[at] : R(0);
         }
+    };
+    batch(0, e, al);
+    for (int k0 = 0; k0 < w; k0 += 8) {
         R xe[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) xe[j] = e[j] < nc ? x[e[j]] : xg[e[j] - nc];
+        for (int j = 0; j < 8; ++j) xe[j] = *(e[j] < nc ? x + e[j] : xg + (e[j] - nc));
+        int en[8];
+        R an[8];
+        batch(k0 + 8, en, an);
 #pragma unroll
         for (int j = 0; j < 8; ++j) s += al[j] * xe[j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            e[j] = en[j];
+            al[j] = an[j];
+        }
     }
     xv[v] = s;
 }
@@ -110,12 +124,16 @@ __global__ __launch_bounds__(kBlock) void k_mf_face(Dev d, BcTable bc, const R* 
 // y_i = -sum_f s_if F_f
 template <class R>
 __device__ inline R gather_row(const Dev& d, const R* __restrict__ F, int64_t i) {
+    // the four face codes, then the four fluxes, each set in flight together
+    int code[4];
+    R fl[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) code[k] = d.c2f[k * d.nc + i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fl[k] = F[code[k] >= 0 ? code[k] : ~code[k]];
     R y = R(0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int code = d.c2f[k * d.nc + i];
-        y += code >= 0 ? -F[code] : F[~code];
-    }
+    for (int k = 0; k < 4; ++k) y += code[k] >= 0 ? -fl[k] : fl[k];
     return y;
 }
 
@@ -139,14 +157,15 @@ __global__ __launch_bounds__(kBlock) void k_mf_cg_gather(Dev d, const R* __restr
     if (block_done(d, g)) return;
     const int64_t i = lb * kBlock + threadIdx.x;
     double v[1] = {0.0};
-    if (i < d.nc && msc(d, row_mesh(g, i))[SC_DONE] == 0.0) {
+    if (i < d.nc) {
+        // the row's loads go out before the mesh's done flag is read (a
+        // finished mesh's row is read and dropped)
         const R y = gather_row(d, F, i);
-        if constexpr (std::is_same<R, double>::value) {
-            d.q[i] = y;
-            v[0] = d.p[i] * y;
-        } else {
-            d.q32[i] = y;
-            v[0] = double(d.p32[i]) * double(y);
+        const double pi = std::is_same<R, double>::value ? d.p[i] : double(d.p32[i]);
+        if (msc(d, row_mesh(g, i))[SC_DONE] == 0.0) {
+            if constexpr (std::is_same<R, double>::value) d.q[i] = y;
+            else d.q32[i] = y;
+            v[0] = pi * double(y);
         }
     }
     seg_publish_at<1>(d, g, v, i >= g.split, lds, lb, nblk);

@@ -8,6 +8,7 @@
 #include "reduce.h"
 #include "seg.h"
 #include "state.h"
+#include "halo_stage.h"
 
 namespace mifvm {
 
@@ -186,13 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Dev d) {
     const int T = blockDim.x;
     const BlockSeg g = block_seg(d, t * T, T);
     if (block_done(d, g)) return;
-    const int64_t h0 = d.h_off[t];
-    const int hn = int(d.h_off[t + 1] - h0);
-    const double* __restrict__ p = d.p;
-    for (int h = threadIdx.x; h < hn; h += T) {
-        const int e = d.h_idx[h0 + h];
-        sp[h] = e < nc ? p[e] : 0.0;
-    }
+    stage_halo_values(d, t, d.p, sp);
     __syncthreads();
     const int64_t i = t * T + threadIdx.x;
     const int m = row_mesh(g, i);
@@ -203,10 +198,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(Dev d) {
         const int64_t base = d.k_off[s] + (i & 63);
         const int w = d.k_w[s];
         double y = d.k_diag[i] * pi;
-#pragma unroll 4
-        for (int k = 0; k < w; ++k) {
-            const int64_t at = base + int64_t(k) * 64;
-            y += d.k_val[at] * sp[d.k_lidx[at]];
+        // 16 entries' loads in flight, then their sums in row order
+        for (int k0 = 0; k0 < w; k0 += 16) {
+            uint16_t l[16];
+            double a[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const bool in = k0 + j < w;
+                const int64_t at = base + int64_t(k0 + j) * 64;
+                l[j] = in ? d.k_lidx[at] : uint16_t(0);
+                a[j] = in ? d.k_val[at] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (k0 + j < w) y += a[j] * sp[l[j]];   // w is one slice's: uniform over the wave
         }
         d.q[i] = y;
         v[0] = pi * y;
