@@ -68,10 +68,24 @@ __global__ __launch_bounds__(kBlock) void k_amg_restrict(int64_t nco, const int6
     if (done(flag)) return;
     const int64_t I = tid_a();
     if (I >= nco) return;
+    // members in batches of 8: their indices in flight together, then their
+    // values, then the sums in member order (a slot past the aggregate
+    // re-reads its first member and is not added; aggregates are non-empty)
+    const int64_t m0 = mptr[I], cnt = mptr[I + 1] - m0;
     double s = 0.0;
-    for (int64_t m = mptr[I]; m < mptr[I + 1]; ++m) {
-        const int i = midx[m];
-        s += b[i] - t[i];
+    for (int64_t k0 = 0; k0 < cnt; k0 += 8) {
+        int id[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) id[j] = midx[m0 + (k0 + j < cnt ? k0 + j : 0)];
+        double bv[8], tv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            bv[j] = b[id[j]];
+            tv[j] = t[id[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (k0 + j < cnt) s += bv[j] - tv[j];
     }
     bc[I] = s;
 }
