@@ -56,6 +56,34 @@ KERNEL_FILES = {
 }
 
 
+def measure_copy_peak(gib=1, reps=10):
+    """Achievable HBM bandwidth, the better of two streams over `gib` GiB
+    vectors (torch's kernels): b = a (read + write) and c = a + b (two reads,
+    one write); bytes moved per second, best of `reps` each."""
+    import torch
+    n = (gib << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    c = torch.empty_like(a)
+
+    def best(fn, nbytes):
+        fn()
+        t = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            t = min(t, e0.elapsed_time(e1) / 1e3)
+        return nbytes / t / 1e9
+
+    copy = best(lambda: b.copy_(a), 2 * n * 8)
+    add = best(lambda: torch.add(a, b, out=c), 3 * n * 8)
+    del a, b, c
+    return max(copy, add), {"copy": round(copy, 1), "add": round(add, 1)}
+
+
 def kernel_source_hash(name):
     import hashlib
     h = hashlib.sha256()
@@ -248,6 +276,8 @@ def main():
     solve_ms = [e[1].elapsed_time(e[2]) for e in events]
     total1 = st.conservation()
 
+    copy_gbs, streams = measure_copy_peak()
+    log(f"measured streams: {streams} GB/s")
     fv_total_s = sum(fv_ms) / 1e3
     value = info.nc * args.steps / fv_total_s
     nbytes = algorithmic_bytes(info)
@@ -263,6 +293,7 @@ def main():
         traffic = rec["bytes"] if rec and rec["src"] == kernel_source_hash(name) else None
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+                "copy_peak": round(copy_gbs, 1), "frac_of_copy": round(gbs / copy_gbs, 4),
                 "avg_us": round(avg_s * 1e6, 2), "launches": n,
                 "bytes_per_launch": nbytes[name],
                 "traffic_GBps": round(traffic / avg_s / 1e9, 1) if traffic else None}
@@ -296,6 +327,7 @@ def main():
                              key=lambda k: kstats[k][0])),
         "roofline_fv": {k: roof(k) for k in ("grad_limiter", "face_flux", "update")},
         "roofline_cg": {k: roof(k) for k in ("mf_vertex", "mf_face", "mf_gather", "cg_axpy", "cg_dir")},
+        "measured_streams_GBps": streams,
     }
     if not args.no_forms:
         u64 = st.get_field(B.FIELD_U)
