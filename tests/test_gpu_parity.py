@@ -321,3 +321,63 @@ def test_precision_form_config1_reports_error_per_step():
     perr = np.linalg.norm(x - xo) / np.linalg.norm(xo)
     print(f"[gpu] fp32 form: potential rel. error vs FP64 oracle {perr:.2e}")
     assert perr < 1e-4
+
+
+def shuffled_cube(n=8, seed=3, window=700, rng_seed=17):
+    """The cube with its cells shuffled inside consecutive windows of
+    `window` cells.  Kept in this order (no renumbering), a 256-cell tile's
+    stencil neighbourhood exceeds the 2,048-entity LDS cap, so preprocessing
+    falls back to 64-cell tiles whose halos are larger than 8 entities per
+    thread: the halo staging runs its remainder passes."""
+    import dataclasses
+    from oracle.geometry import build_geometry
+    m = cube(n, seed)
+    rng = np.random.default_rng(rng_seed)
+    perm = np.arange(m.nc)
+    for s in range(0, m.nc, window):
+        perm[s:s + window] = rng.permutation(perm[s:s + window])
+    m2 = dataclasses.replace(m, tets=np.ascontiguousarray(m.tets[perm]))
+    return m2, build_geometry(m2.xyz, m2.tets, m2.btris, m2.btags)
+
+
+def test_small_tiles_with_long_halos():
+    """FP64 and FP32 steps, the stored-matrix and matrix-free solves on a
+    mesh whose tiles hold 64 cells and up to ~1,800 halo entities (halo
+    staging beyond its first 8 entities per thread), against the oracle."""
+    print("[gpu] 64-cell tiles with long halos", flush=True)
+    m, g = shuffled_cube()
+    lib = B.Mesh.from_cube(m, B.RENUMBER_NONE)
+    assert lib.info.tile_rows == 64 and lib.info.halo_max > 8 * 64
+    kinds, vals, D = CASES["ragged_mixed"][2:]
+    vel = synth.rotating_velocity(m)
+    u0 = synth.gaussian_field(m)
+    phi = fv.face_velocity_flux(g, vel)
+    dt = fv.cfl_dt(g, phi, D, 0.4, kinds)
+    u = u0.copy()
+    for _ in range(3):
+        u = fv.rk3_step(g, u, dt, phi, D, kinds, vals)
+    for prec, tol in ((B.FP64, TOL), (B.FP32, 1e-5)):
+        st = B.State(lib, diffusivity=D, precision=prec)
+        st.set_bcs(B.VAR_SCALAR, kinds, vals)
+        st.set_field(B.FIELD_VEL, dev(vel.T.ravel()))
+        st.set_field(B.FIELD_U, dev(u0))
+        st.step(3, dt)
+        err = rel(host(st.get_field(B.FIELD_U)), u)
+        print(f"[gpu] precision {prec}: step error {err:.2e}", flush=True)
+        assert err < tol
+    pk, pv = POISSON["ragged_mixed"][2:]
+    K, c = poisson.assemble(g, pk, pv)
+    b = poisson.rhs(g, u0, c)
+    st = B.State(lib)
+    st.set_bcs(B.VAR_POTENTIAL, pk, pv)
+    st.poisson_assemble()
+    its = []
+    for mf in (False, True):
+        st.set_field(B.FIELD_P, dev(np.zeros(m.nc)))
+        info = st.poisson_solve(dev(u0), tol=1e-10, matrix_free=mf)
+        assert info["status"] == B.OK
+        assert poisson.true_relative_residual(K, b, host(st.get_field(B.FIELD_P))) <= 1.01e-10
+        its.append(info["iterations"])
+    _, it_o, _ = poisson.jacobi_cg(K, b, tol=1e-10)
+    print(f"[gpu] stored / matrix-free CG {its} iterations, oracle {it_o}", flush=True)
+    assert all(abs(i - it_o) <= 3 for i in its)
