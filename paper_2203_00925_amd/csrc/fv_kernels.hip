@@ -282,10 +282,16 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
     using V2 = typename Vec2T<R>::T;
     using V4 = typename Vec4T<R>::T;
     extern __shared__ __align__(16) unsigned char sm_raw[];
-    // [halo] (x, y), [halo] (z, u), then 2 records per touched vertex
+    // [halo] (x, y), [halo] (z, u), then the touched vertices' records as
+    // four 16-byte arrays (xb_x, xb_y), (xb_z, n), (C_x, C_y), (C_z, ub): a
+    // random vertex's first 16 bytes then fall in any of 8 bank groups, not 2
     const int hcap = (d.halo_max + 1) & ~1;
     const HaloSoA<R> sm{reinterpret_cast<V2*>(sm_raw), reinterpret_cast<V2*>(sm_raw) + hcap};
-    V4* vr = reinterpret_cast<V4*>(sm.zu + hcap);
+    const int tvc = d.tv_max;
+    V2* va = sm.zu + hcap;
+    V2* vb = va + tvc;
+    V2* vc = vb + tvc;
+    V2* vd = vc + tvc;
     constexpr bool rel = std::is_same<R, float>::value;
     const int64_t nc = d.nc;
     const int64_t t = xcd_block();
@@ -421,8 +427,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
         }
         const R inv = R(1) / R(vn);
         const R mu = su * inv;
-        vr[2 * r] = mk4(q0.x + sx * inv, q0.y + sy * inv, q0.z + sz * inv, R(vn));
-        vr[2 * r + 1] = mk4(cx - sx * mu, cy - sy * mu, cz - sz * mu, q0.w + mu);
+        va[r] = mk2(q0.x + sx * inv, q0.y + sy * inv);
+        vb[r] = mk2(q0.z + sz * inv, R(vn));
+        vc[r] = mk2(cx - sx * mu, cy - sy * mu);
+        vd[r] = mk2(cz - sz * mu, q0.w + mu);
         if (mine) a.unode[row] = un;
     }
     // loads used at the end (limiter, M^-1) go out before the barrier
@@ -440,7 +448,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
     R jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const V4 vs = vr[2 * lv[k]], vm = vr[2 * lv[k] + 1];
+        const V2 pa = va[lv[k]], pb = vb[lv[k]], pc = vc[lv[k]], pd = vd[lv[k]];
+        const V4 vs = mk4(pa.x, pa.y, pb.x, pb.y), vm = mk4(pc.x, pc.y, pd.x, pd.y);
         const R nd = vs.w * (vm.w - ui);
         jx += vm.x + (vs.x - xi) * nd;
         jy += vm.y + (vs.y - yi) * nd;
