@@ -190,7 +190,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--forms", default="all",
                     help="comma-separated forms to run after the main steps (fp32_refined, stored_matrix_cg, "
-                         "fgmres30, multigrid_fcg, streamer, learned), or all")
+                         "fgmres30, multigrid_fcg, multigrid_w_fcg, streamer, learned), or all")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the reduced-precision (FP32 + refined solve) run")
     ap.add_argument("--calibrate-copy-gb", type=float, default=0.0,
@@ -376,6 +376,11 @@ def main():
                 args, M, pf, "flexible CG + aggregation multigrid V(1,1), matrix-free",
                 dict(method=B.SOLVE_AMG, matrix_free=True), plain_ms, p64, amg=True)
             torch.cuda.empty_cache()
+        if run("multigrid_w_fcg"):
+            result["forms"]["multigrid_w_fcg"] = run_solver_form(
+                args, M, pf, "flexible CG + aggregation multigrid W(1,1), matrix-free",
+                dict(method=B.SOLVE_AMG, matrix_free=True), plain_ms, p64, amg=True, cycle=B.CYCLE_W)
+            torch.cuda.empty_cache()
         if run("streamer"):
             result["forms"]["streamer"] = run_streamer_form(args, M, pf)
             torch.cuda.empty_cache()
@@ -447,11 +452,12 @@ def run_fp32_form(args, M, pf, u64, p64, plain_ms):
 
 
 
-def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0, amg=False):
+def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0, amg=False, cycle=0):
     """The FP64 run's steps with another solver of the same system: solve time
     and iterations per step, the solution's difference from the plain run's,
     and one cold solve (P = 0).  amg: build and attach the multigrid
-    hierarchy first (its host setup time is reported, outside the timings)."""
+    hierarchy first (its host setup time is reported, outside the timings);
+    cycle: its cycle type (0 V, CYCLE_W)."""
     import numpy as np
     import torch
     from paper_2203_00925_amd import binding as B
@@ -463,7 +469,7 @@ def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0, amg=
     st.poisson_assemble()
     if fgmres_m:
         st.fgmres_attach(fgmres_m)
-    amg_info = st.amg_build() if amg else None
+    amg_info = st.amg_build(cycle=cycle) if amg else None
     if amg:
         log(f"{name}: {amg_info['levels']} levels {amg_info['rows']}, setup {amg_info['setup_ms'] / 1e3:.1f} s")
     dt = st.cfl_dt(pf.cfl)
@@ -663,10 +669,10 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
     solve_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
     plain_ms = sum(plain_solve_ms) / len(plain_solve_ms)
     layer_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in kstats.items() if v[1]}
-    # the trained network as the finest-level smoother of the multigrid cycle:
+    # the trained network as the finest-level smoother of the multigrid W-cycle:
     # cold solves of one right-hand side with each smoother and plain
     # Jacobi-CG, then stepped (warm) solves
-    amg_info = st.amg_build()
+    amg_info = st.amg_build(cycle=B.CYCLE_W)
     kw_mg = dict(tol=1e-10, restart=500, method=B.SOLVE_AMG, matrix_free=True)
     cold_mg = {}
     for name, extra in (("jacobi_smoother", {}), ("learned_smoother", dict(learned_smoother=True, chunk=8))):

@@ -369,12 +369,17 @@ int mifvm_autotune(mifvm_state* st, const char* cache_path, mifvm_tune_info* out
  * its free strong neighbours); A_c = P^T A P with the piecewise-constant P;
  * until at most coarse_max rows, inverted densely (LU, partial pivoting).
  * The cycle: x = w D^-1 b; b_c = P^T (b - A x); x += P V(b_c);
- * x += w D^-1 (b - A x); the dense inverse on the coarsest level.          */
+ * x += w D^-1 (b - A x); the dense inverse on the coarsest level.  With
+ * cycle = 2 (W) the coarse correction of every level whose coarser level is
+ * not the dense one is improved once more before it is prolonged:
+ * x_c = V(b_c); x_c += V(b_c - A_c x_c).                                  */
 typedef struct {
     double theta;              /* 0 = 0.25                                    */
     double omega;              /* Jacobi damping, 0 = 2/3                     */
     int32_t max_levels;        /* 0 = 10 (at most 16)                         */
     int32_t coarse_max;        /* 0 = 1024 (at most 4096)                     */
+    int32_t cycle;             /* 0 or 1 = V-cycle, 2 = W-cycle; else E_ARG   */
+    int32_t pad_;
 } mifvm_amg_opts;
 
 typedef struct {

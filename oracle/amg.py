@@ -19,6 +19,11 @@ exact inverse.  One V(1,1) cycle with damped Jacobi (weight w) from zero:
 
     x = w D^-1 b;   x += P V(P^T (b - A x));   x += w D^-1 (b - A x).
 
+With gamma = 2 (a W-cycle) the coarse correction of every level whose
+coarser level is not the exactly solved one is improved once more before
+it is prolonged: with b_c = P^T (b - A x) and x_c = V(b_c),
+x_c += V(b_c - A_c x_c).
+
 Parity unpinned in the paper's sense (the paper gives no multigrid): the
 pins are the algebra's own facts, checked in the tests.
 """
@@ -91,10 +96,10 @@ def build(A: sp.csr_matrix, theta=0.25, coarse_max=1024, max_levels=10):
     return levels, np.linalg.inv(A.toarray())
 
 
-def v_cycle(levels, cinv, b, omega=2.0 / 3.0, level=0, fine=None):
-    """One cycle; fine (optional) is a map r -> correction that replaces the
-    Jacobi sweeps on the finest level: x = fine(b), coarse correction,
-    x += fine(b - A x) (a learned smoother)."""
+def v_cycle(levels, cinv, b, omega=2.0 / 3.0, level=0, fine=None, gamma=1):
+    """One cycle (V for gamma = 1, W for gamma = 2); fine (optional) is a map
+    r -> correction that replaces the Jacobi sweeps on the finest level:
+    x = fine(b), coarse correction, x += fine(b - A x) (a learned smoother)."""
     A, agg = levels[level]
     if agg is None:
         return cinv @ b
@@ -102,15 +107,20 @@ def v_cycle(levels, cinv, b, omega=2.0 / 3.0, level=0, fine=None):
     smooth = fine if (fine is not None and level == 0) else (lambda r: omega * dinv * r)
     x = smooth(b)
     r = b - A @ x
-    bc = np.bincount(agg, weights=r, minlength=levels[level + 1][0].shape[0])
-    x = x + v_cycle(levels, cinv, bc, omega, level + 1)[agg]
+    Ac, agg_c = levels[level + 1]
+    bc = np.bincount(agg, weights=r, minlength=Ac.shape[0])
+    xc = v_cycle(levels, cinv, bc, omega, level + 1, gamma=gamma)
+    if agg_c is not None:                    # the coarse level is not solved exactly
+        for _ in range(gamma - 1):
+            xc = xc + v_cycle(levels, cinv, bc - Ac @ xc, omega, level + 1, gamma=gamma)
+    x = x + xc[agg]
     return x + smooth(b - A @ x)
 
 
-def fcg(K, b, levels, cinv, x0=None, tol=1e-10, maxit=2000, restart=500, omega=2.0 / 3.0, fine=None):
+def fcg(K, b, levels, cinv, x0=None, tol=1e-10, maxit=2000, restart=500, omega=2.0 / 3.0, fine=None, gamma=1):
     """Flexible CG (Polak-Ribiere beta) with one cycle as the preconditioner,
     reopened from the true residual when the recurrence meets tol or after
-    `restart` iterations; returns (x, iterations).  fine: as v_cycle."""
+    `restart` iterations; returns (x, iterations).  fine, gamma: as v_cycle."""
     x = np.zeros_like(b) if x0 is None else np.array(x0, np.float64)
     bb = float(b @ b)
     it = 0
@@ -118,7 +128,7 @@ def fcg(K, b, levels, cinv, x0=None, tol=1e-10, maxit=2000, restart=500, omega=2
         r = b - K @ x
         if r @ r <= tol * tol * bb or it >= maxit:
             return x, it
-        z = v_cycle(levels, cinv, r, omega, fine=fine)
+        z = v_cycle(levels, cinv, r, omega, fine=fine, gamma=gamma)
         p = z.copy()
         rz = float(z @ r)
         since = 0
@@ -132,7 +142,7 @@ def fcg(K, b, levels, cinv, x0=None, tol=1e-10, maxit=2000, restart=500, omega=2
             since += 1
             if r @ r <= tol * tol * bb or it >= maxit or since >= restart:
                 break
-            z = v_cycle(levels, cinv, r, omega, fine=fine)
+            z = v_cycle(levels, cinv, r, omega, fine=fine, gamma=gamma)
             zr, zro = float(z @ r), float(z @ r_old)
             beta = (zr - zro) / rz
             rz = zr

@@ -22,6 +22,7 @@ VAR_SCALAR, VAR_POTENTIAL = 0, 1
 FIELD_U, FIELD_VEL, FIELD_SOURCE, FIELD_P, FIELD_ION, FIELD_EFIELD = 0, 1, 2, 3, 4, 5
 RENUMBER_NONE, RENUMBER_MORTON, RENUMBER_RCM = 0, 1, 2
 SOLVE_PLAIN, SOLVE_IR_FP32, SOLVE_LEARNED, SOLVE_FGMRES, SOLVE_AMG = 0, 1, 2, 3, 4
+CYCLE_V, CYCLE_W = 1, 2
 FP64, FP32 = 0, 1
 KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
            "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble", "nn_layer1", "nn_layer2", "nn_layer3",
@@ -104,7 +105,7 @@ class SolveInfo(C.Structure):
 
 class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("omega", C.c_double), ("max_levels", C.c_int32),
-                ("coarse_max", C.c_int32)]
+                ("coarse_max", C.c_int32), ("cycle", C.c_int32), ("pad_", C.c_int32)]
 
 
 class AmgInfo(C.Structure):
@@ -125,7 +126,7 @@ class AmgHost:
         col = np.ascontiguousarray(col, np.int32)
         val = np.ascontiguousarray(val, np.float64)
         h = C.c_void_p()
-        opts = AmgOpts(float(theta), float(omega), int(max_levels), int(coarse_max))
+        opts = AmgOpts(float(theta), float(omega), int(max_levels), int(coarse_max), 0, 0)
         _check(_lib.mifvm_amg_host_build(C.c_int64(len(ptr) - 1), ptr.ctypes.data_as(C.c_void_p),
                                          col.ctypes.data_as(C.c_void_p), val.ctypes.data_as(C.c_void_p),
                                          C.byref(opts), C.byref(h)))
@@ -449,11 +450,12 @@ class State:
         _check(_lib.mifvm_fgmres_attach(self._h, int(m), C.c_void_p(ws.data_ptr() + off), n.value))
         self._gm_ws = ws
 
-    def amg_build(self, theta=0.0, omega=0.0, max_levels=0, coarse_max=0, stream=None):
+    def amg_build(self, theta=0.0, omega=0.0, max_levels=0, coarse_max=0, cycle=0, stream=None):
         """Multigrid hierarchy of the assembled K, uploaded into a workspace
-        this object keeps (mifvm_amg_build + mifvm_amg_attach)."""
+        this object keeps (mifvm_amg_build + mifvm_amg_attach); cycle: 0 or
+        CYCLE_V, or CYCLE_W."""
         import torch
-        opts = AmgOpts(float(theta), float(omega), int(max_levels), int(coarse_max))
+        opts = AmgOpts(float(theta), float(omega), int(max_levels), int(coarse_max), int(cycle), 0)
         info = AmgInfo()
         _check(_lib.mifvm_amg_build(self._h, C.byref(opts), C.byref(info), _stream(stream)))
         ws = torch.empty(int(info.ws_bytes) + 256, dtype=torch.uint8, device=self.device)

@@ -46,6 +46,7 @@ struct AmgHierarchy {
     std::vector<AmgLevel> lv;             // lv[0] is the input matrix
     std::vector<double> cinv;             // dense inverse of the coarsest matrix, row-major
     double theta = 0.25, omega = 2.0 / 3.0;
+    int gamma = 1;                        // cycle of the device (1 V, 2 W)
     int max_levels = 10;
     int64_t coarse_max = 1024;
 };

@@ -48,6 +48,7 @@ size_t amg_layout(const AmgHierarchy& h, int64_t nc, char* base, AmgDev* a) {
     AmgDev& A = a ? *a : tmp;
     A.nl = int(h.lv.size());
     A.omega = h.omega;
+    A.gamma = h.gamma;
     for (int l = 0; l < A.nl; ++l) {
         const AmgLevel& L = h.lv[l];
         AmgLevelDev& D = A.lv[l];
@@ -65,6 +66,8 @@ size_t amg_layout(const AmgHierarchy& h, int64_t nc, char* base, AmgDev* a) {
             D.b = carve<double>(base, off, D.n);
             D.x = carve<double>(base, off, D.n);
             D.t = carve<double>(base, off, D.n);
+            D.r = carve<double>(base, off, D.n);
+            D.e = carve<double>(base, off, D.n);
         }
         if (l + 1 < A.nl) {
             D.agg = carve<int32_t>(base, off, D.n);
@@ -181,6 +184,7 @@ int mifvm_amg_build(mifvm_state* st, const mifvm_amg_opts* opts, mifvm_amg_info*
     State& s = st->s;
     if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
     if (s.d.nm != 1) return fail(MIFVM_E_ARG, "the multigrid preconditioner needs a single-mesh state");
+    if (opts && (opts->cycle < 0 || opts->cycle > 2)) return fail(MIFVM_E_ARG, "cycle must be 0 or 1 (V) or 2 (W)");
     double theta, omega;
     int levels;
     int64_t cmax;
@@ -193,6 +197,7 @@ int mifvm_amg_build(mifvm_state* st, const mifvm_amg_opts* opts, mifvm_amg_info*
     std::string err;
     rc = amg_build(std::move(A), theta, levels, cmax, omega, *h, err);
     if (rc) return fail(rc, err);
+    h->gamma = opts && opts->cycle == 2 ? 2 : 1;
     amg_release(s);
     s.amg_host = h.release();
     if (info) {

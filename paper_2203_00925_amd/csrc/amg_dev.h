@@ -25,13 +25,15 @@ struct AmgLevelDev {
     int32_t* agg = nullptr;
     int64_t* mptr = nullptr;
     int32_t* midx = nullptr;
-    // level >= 1: right-hand side, iterate, product
-    double *b = nullptr, *x = nullptr, *t = nullptr;
+    // level >= 1: right-hand side, iterate, product; the W-cycle's second
+    // visit: its right-hand side (residual) and correction
+    double *b = nullptr, *x = nullptr, *t = nullptr, *r = nullptr, *e = nullptr;
 };
 
 struct AmgDev {
     int nl = 0;
     double omega = 2.0 / 3.0;
+    int gamma = 1;                    // coarse visits per level: 1 V-cycle, 2 W-cycle
     AmgLevelDev lv[kAmgMaxLevels];
     double* cinv = nullptr;           // dense inverse of the coarsest matrix, row-major
     double* r_old = nullptr;          // flexible CG [nc]

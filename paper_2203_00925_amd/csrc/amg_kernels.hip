@@ -254,6 +254,51 @@ __global__ __launch_bounds__(1024) void k_amg_beta_fin(Dev d, int64_t nparts) {
 
 }  // namespace
 
+namespace {
+
+hipError_t coarse_correction(const AmgDev& a, int l, const double* flag, hipStream_t s);
+
+// x = cycle of coarse level l (>= 1) on the right-hand side b
+hipError_t coarse_cycle(const AmgDev& a, int l, const double* b, double* x, const double* flag, hipStream_t s) {
+    const double w = a.omega;
+    const AmgLevelDev& L = a.lv[l];
+    if (l == a.nl - 1) {               // the coarsest level: its dense inverse
+        hipLaunchKernelGGL(k_amg_dense, dim3(unsigned(L.n)), dim3(256), 0, s, L.n, a.cinv, b, x, flag);
+        return hipGetLastError();
+    }
+    const AmgLevelDev& N = a.lv[l + 1];
+    hipLaunchKernelGGL(k_amg_smooth0, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L.n, w, L.dinv, b, x, flag);
+    hipLaunchKernelGGL(k_amg_spmv, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L, x, L.t, flag);
+    hipLaunchKernelGGL(k_amg_restrict, dim3(grid_a(N.n)), dim3(kBlock), 0, s, N.n, L.mptr, L.midx, b, L.t, N.b,
+                       flag);
+    hipError_t e = coarse_correction(a, l + 1, flag, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_amg_prolong, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L.n, L.agg, N.x, x, flag);
+    hipLaunchKernelGGL(k_amg_spmv, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L, x, L.t, flag);
+    hipLaunchKernelGGL(k_amg_smooth1, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L.n, w, L.dinv, b, L.t, x, flag);
+    return hipGetLastError();
+}
+
+// level l's x from its b (the restricted residual of level l - 1): one
+// cycle, and for a W-cycle a second one on the remaining residual, unless
+// level l is solved exactly
+hipError_t coarse_correction(const AmgDev& a, int l, const double* flag, hipStream_t s) {
+    const AmgLevelDev& N = a.lv[l];
+    hipError_t e = coarse_cycle(a, l, N.b, N.x, flag, s);
+    for (int k = 1; e == hipSuccess && k < a.gamma && l < a.nl - 1; ++k) {
+        hipLaunchKernelGGL(k_amg_spmv, dim3(grid_a(N.n)), dim3(kBlock), 0, s, N, N.x, N.t, flag);
+        hipLaunchKernelGGL(k_amg_sub, dim3(grid_a(N.n)), dim3(kBlock), 0, s, N.n, N.b, N.t, N.r, flag);
+        e = coarse_cycle(a, l, N.r, N.e, flag, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_amg_add, dim3(grid_a(N.n)), dim3(kBlock), 0, s, N.n, N.e, N.x, flag);
+            e = hipGetLastError();
+        }
+    }
+    return e;
+}
+
+}  // namespace
+
 hipError_t launch_amg_cycle(const Dev& d, const BcTable& bc_pot, const AmgDev& a, const double* b0, double* x0,
                             const double* flag, hipStream_t s, const AmgSmoother* fine) {
     const int nl = a.nl;
@@ -262,7 +307,8 @@ hipError_t launch_amg_cycle(const Dev& d, const BcTable& bc_pot, const AmgDev& a
         hipLaunchKernelGGL(k_amg_dense, dim3(unsigned(d.nc)), dim3(256), 0, s, d.nc, a.cinv, b0, x0, flag);
         return hipGetLastError();
     }
-    // down: level 0 (matrix-free product into tmp), then the coarse levels
+    // level 0: smoothing with the matrix-free product (into tmp), then the
+    // coarse levels
     hipError_t e = hipSuccess;
     if (fine) {
         e = (*fine)(b0, x0, s);                    // x = M(b)
@@ -275,24 +321,8 @@ hipError_t launch_amg_cycle(const Dev& d, const BcTable& bc_pot, const AmgDev& a
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_amg_restrict, dim3(grid_a(a.lv[1].n)), dim3(kBlock), 0, s, a.lv[1].n, a.lv[0].mptr,
                        a.lv[0].midx, b0, d.tmp, a.lv[1].b, flag);
-    for (int l = 1; l < nl - 1; ++l) {
-        const AmgLevelDev& L = a.lv[l];
-        hipLaunchKernelGGL(k_amg_smooth0, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L.n, w, L.dinv, L.b, L.x, flag);
-        hipLaunchKernelGGL(k_amg_spmv, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L, L.x, L.t, flag);
-        hipLaunchKernelGGL(k_amg_restrict, dim3(grid_a(a.lv[l + 1].n)), dim3(kBlock), 0, s, a.lv[l + 1].n, L.mptr,
-                           L.midx, L.b, L.t, a.lv[l + 1].b, flag);
-    }
-    const AmgLevelDev& C = a.lv[nl - 1];
-    hipLaunchKernelGGL(k_amg_dense, dim3(unsigned(C.n)), dim3(256), 0, s, C.n, a.cinv, C.b, C.x, flag);
-    // up
-    for (int l = nl - 2; l >= 1; --l) {
-        const AmgLevelDev& L = a.lv[l];
-        hipLaunchKernelGGL(k_amg_prolong, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L.n, L.agg, a.lv[l + 1].x, L.x,
-                           flag);
-        hipLaunchKernelGGL(k_amg_spmv, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L, L.x, L.t, flag);
-        hipLaunchKernelGGL(k_amg_smooth1, dim3(grid_a(L.n)), dim3(kBlock), 0, s, L.n, w, L.dinv, L.b, L.t, L.x,
-                           flag);
-    }
+    e = coarse_correction(a, 1, flag, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_amg_prolong, dim3(grid_a(d.nc)), dim3(kBlock), 0, s, d.nc, a.lv[0].agg, a.lv[1].x, x0,
                        flag);
     e = launch_mf_apply(d, bc_pot, x0, d.tmp, s, flag);

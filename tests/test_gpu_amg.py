@@ -183,3 +183,35 @@ def test_learned_smoother_cycle_and_solve():
           flush=True)
     assert err < 1e-2
     assert np.array_equal(host(st.amg_apply(dev(2.0 * r), learned_smoother=True)), 2.0 * z)
+
+
+def test_w_cycle_matches_oracle_and_solves():
+    """cycle = W: one cycle equals the oracle's W-cycle (gamma = 2) on the
+    same hierarchy to 1e-10; the flexible CG is accepted by the oracle's K in
+    the oracle's iteration count; a bad cycle value is refused."""
+    print("[gpu] multigrid W-cycle", flush=True)
+    mp, K, c, K_int, st = setup()
+    with pytest.raises(B.MifvmError):
+        st.amg_build(coarse_max=16, cycle=3)
+    info = st.amg_build(coarse_max=16, cycle=B.CYCLE_W)
+    levels, cinv = amg.build(K_int, coarse_max=16)
+    assert info["levels"] == len(levels) >= 4
+    r = np.random.default_rng(9).normal(size=mp.geo.nc)
+    z = host(st.amg_apply(dev(r)))
+    z_ref = np.empty_like(r)
+    z_ref[mp.cp] = amg.v_cycle(levels, cinv, r[mp.cp], gamma=2)
+    err = np.abs(z - z_ref).max() / np.abs(z_ref).max()
+    z_v = np.empty_like(r)
+    z_v[mp.cp] = amg.v_cycle(levels, cinv, r[mp.cp])
+    print(f"[gpu] W-cycle error {err:.2e} over {info['levels']} levels "
+          f"(W - V: {np.abs(z_ref - z_v).max() / np.abs(z_ref).max():.2e})", flush=True)
+    assert err < 1e-10
+    f = synth.gaussian_field(mp.m)
+    s = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_AMG, matrix_free=True)
+    b = poisson.rhs(mp.geo, f, c)
+    assert s["status"] == B.OK
+    assert poisson.true_relative_residual(K, b, host(st.get_field(B.FIELD_P))) <= 1.01e-10
+    _, it_w = amg.fcg(K_int, b[mp.cp], levels, cinv, tol=1e-10, gamma=2)
+    _, it_v = amg.fcg(K_int, b[mp.cp], levels, cinv, tol=1e-10)
+    print(f"[gpu] W-cycle FCG {s['iterations']} it (oracle {it_w}; V-cycle oracle {it_v})", flush=True)
+    assert abs(s["iterations"] - it_w) <= 2

@@ -127,3 +127,44 @@ def test_library_setup_rejects_bad_input():
     bad[0] = K.shape[0] + 5
     with pytest.raises(B.MifvmError):
         B.AmgHost(K.indptr, bad, K.data)
+
+
+def test_w_cycle_pins():
+    """gamma = 2: on two levels (coarse level exact) the W-cycle is the
+    V-cycle; on more levels it is still symmetric positive definite on an
+    SPD matrix, equals the V-cycle followed by its defining correction on a
+    three-level hierarchy, and needs fewer flexible-CG iterations."""
+    A = laplacian_2d(30)
+    rng = np.random.default_rng(7)
+    b = rng.normal(size=A.shape[0])
+    lv2, ci2 = amg.build(A, coarse_max=400)
+    assert len(lv2) == 2
+    assert np.array_equal(amg.v_cycle(lv2, ci2, b, gamma=2), amg.v_cycle(lv2, ci2, b))
+    levels, cinv = amg.build(A, coarse_max=40)
+    assert len(levels) >= 3
+    x, y = rng.normal(size=A.shape[0]), rng.normal(size=A.shape[0])
+    wx, wy = amg.v_cycle(levels, cinv, x, gamma=2), amg.v_cycle(levels, cinv, y, gamma=2)
+    assert abs(wx @ y - x @ wy) <= 1e-12 * abs(wx @ y)
+    assert wx @ x > 0 and wy @ y > 0
+    assert np.abs(wx - amg.v_cycle(levels, cinv, x)).max() > 1e-6 * np.abs(wx).max()
+    # three levels written out: level-1 correction = V_1(bc) + V_1(bc - A1 V_1(bc))
+    lv3, ci3 = amg.build(A, coarse_max=120)
+    assert len(lv3) == 3
+    (A0, g0), (A1, g1) = lv3[0], lv3[1]
+    d0 = 1.0 / A0.diagonal()
+    w = 2.0 / 3.0
+    x0 = w * d0 * b
+    bc = np.bincount(g0, weights=b - A0 @ x0, minlength=A1.shape[0])
+    c1 = amg.v_cycle(lv3, ci3, bc, level=1)
+    c1 = c1 + amg.v_cycle(lv3, ci3, bc - A1 @ c1, level=1)
+    x0 = x0 + c1[g0]
+    x0 = x0 + w * d0 * (b - A0 @ x0)
+    assert np.abs(amg.v_cycle(lv3, ci3, b, gamma=2) - x0).max() <= 1e-13 * np.abs(x0).max()
+    _, K, c = poisson_K()
+    lv, ci = amg.build(K, coarse_max=16)
+    bb = rng.normal(size=K.shape[0])
+    _, it_v = amg.fcg(K, bb, lv, ci, tol=1e-10)
+    xw, it_w = amg.fcg(K, bb, lv, ci, tol=1e-10, gamma=2)
+    assert poisson.true_relative_residual(K, bb, xw) <= 1e-10
+    print(f"multigrid FCG: V {it_v}, W {it_w} iterations over {len(lv)} levels")
+    assert it_w < it_v
