@@ -9,6 +9,7 @@ CG is reported beside it), on a synthetic jittered-tetrahedron unit cube:
 
   cube120 (default): 120^3 hexes x 6 tets = 10,368,000 cells, seed 2
   cube20:             20^3 hexes x 6 tets =     48,000 cells, seed 1
+  cube60:             60^3 hexes x 6 tets =  1,296,000 cells, seed 2 (an eighth of cube120)
 
 Fields: Gaussian pulse (sigma 0.1, centre 0.5,0.5,0.5), velocity
 (sin pi y, sin pi z, sin pi x), diffusivity 1e-3, zero-flux walls for the
@@ -96,6 +97,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "cube120": dict(n=120, seed=2),
     "cube20": dict(n=20, seed=1),
+    "cube60": dict(n=60, seed=2),     # one GPU's share of cube120 split 8 ways
     "batch64": None,          # 64 uneven meshes, see run_batch
 }
 

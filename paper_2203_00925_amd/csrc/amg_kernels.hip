@@ -44,18 +44,34 @@ __global__ __launch_bounds__(kBlock) void k_amg_spmv(AmgLevelDev L, const double
     const int64_t base = L.off[i >> 6] + (i & 63);
     const int w = L.w[i >> 6];
     double y = L.diag[i] * x[i];
-    for (int k0 = 0; k0 < w; k0 += 8) {
-        int c[8];
-        double a[8];
+    // batches of 8: the next batch's columns and values are in flight while
+    // this batch's x values are gathered
+    int c[8];
+    double a[8];
+    auto batch = [&](int k0, int* co, double* ao) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const bool in = k0 + j < w;
             const int64_t at = base + int64_t(k0 + j) * 64;
-            c[j] = in ? L.idx[at] : int(i);
-            a[j] = in ? L.val[at] : 0.0;
+            co[j] = in ? L.idx[at] : int(i);
+            ao[j] = in ? L.val[at] : 0.0;
         }
+    };
+    batch(0, c, a);
+    for (int k0 = 0; k0 < w; k0 += 8) {
+        double xe[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) y += a[j] * x[c[j]];
+        for (int j = 0; j < 8; ++j) xe[j] = x[c[j]];
+        int cn[8];
+        double an[8];
+        batch(k0 + 8, cn, an);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) y += a[j] * xe[j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            c[j] = cn[j];
+            a[j] = an[j];
+        }
     }
     t[i] = y;
 }
