@@ -215,3 +215,10 @@ def test_w_cycle_matches_oracle_and_solves():
     _, it_v = amg.fcg(K_int, b[mp.cp], levels, cinv, tol=1e-10)
     print(f"[gpu] W-cycle FCG {s['iterations']} it (oracle {it_w}; V-cycle oracle {it_v})", flush=True)
     assert abs(s["iterations"] - it_w) <= 2
+    # captured chunks equal direct launches
+    out = []
+    for graph in (1, 0):
+        st.set_field(B.FIELD_P, dev(np.zeros(mp.geo.nc)))
+        g = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_AMG, matrix_free=True, chunk=8, graph=graph)
+        out.append((g["iterations"], host(st.get_field(B.FIELD_P))))
+    assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
