@@ -91,7 +91,6 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.h_off = carve<int64_t>(base, off, m.h_off.size());
     d.h_idx = carve<int32_t>(base, off, m.h_idx.size());
     d.h_self = carve<int32_t>(base, off, m.h_self.size());
-    d.s_lidx = carve<uint16_t>(base, off, m.s_lidx.size());
     d.k_lidx = carve<uint16_t>(base, off, m.k_lidx.size());
     d.c2n_l = carve<uint16_t>(base, off, m.c2n_l.size());
     d.n_lidx = carve<uint16_t>(base, off, m.n_lidx.size());
@@ -330,7 +329,7 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
         e = hipStreamSynchronize(s);                       // Dm/zero are freed at scope exit
         if (e != hipSuccess) return cleanup(hip_fail(e, "upload mesh parameters"));
     }
-    UP(d.s_lidx, m.s_lidx); UP(d.k_lidx, m.k_lidx); UP(d.c2n_l, m.c2n_l);
+    UP(d.k_lidx, m.k_lidx); UP(d.c2n_l, m.c2n_l);
     UP(d.n_lidx, m.n_lidx); UP(d.v_off, m.v_off);
     {   // packed records of the centres and face centroids (gathered by tiles)
         std::vector<double> rec(4 * (m.nc + m.nb)), frec(4 * m.nf);

@@ -3,11 +3,11 @@
 //
 // One residual evaluation is three gather kernels, each owner-computes and
 // free of atomics:
-//   k_grad_moments  per tile of cells (FP64): least-squares gradient
-//   k_grad_limiter  (Algorithm 1; star-moment form, resp. the stencil sum in
-//                   the FP32 form), then the Barth-Jespersen limiter over the
-//                   4 face neighbours; the same kernel computes the vertex
-//                   values of the least-squares interpolation (Algorithm 2);
+//   k_grad_moments  per tile of cells: least-squares gradient (Algorithm 1,
+//                   in star-moment form), then the Barth-Jespersen limiter
+//                   over the 4 face neighbours; the same kernel computes the
+//                   vertex values of the least-squares interpolation
+//                   (Algorithm 2);
 //   k_face_flux     per face: MUSCL upwind convective flux (eq. (15)) minus
 //                   the diamond diffusive flux (eq. (diamond)), written once;
 //   k_update        per cell: gathers its 4 face fluxes with their signs.
@@ -67,41 +67,11 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(int64_t nc, int64_t nb,
     u[nc + g] = ug;
 }
 
-// Stage tile t's halo in LDS as (x, y, z, u) records (positions relative to
-// `ref`): all index loads of a thread first, then all gathers.
-template <class R, class V4>
-__device__ inline void stage_halo(const Dev& d, const R* __restrict__ u, V4* sm, int64_t t, double4 ref) {
-    const int T = blockDim.x;
-    const int64_t h0 = d.h_off[t];
-    const int hn = int(d.h_off[t + 1] - h0);
-    const double4* __restrict__ P = d.xyz4;
-    for (int hb = 0; hb < hn; hb += 8 * T) {
-        int e[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int h = hb + j * T + threadIdx.x;
-            e[j] = d.h_idx[h0 + (h < hn ? h : 0)];
-        }
-        // every gather is issued before the first LDS write (a slot past the
-        // halo re-reads its first entity and is not stored)
-        double4 r[8];
-        R ue[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            r[j] = P[e[j]];
-            ue[j] = u[e[j]];
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int h = hb + j * T + threadIdx.x;
-            if (h < hn) sm[h] = mk4(R(r[j].x - ref.x), R(r[j].y - ref.y), R(r[j].z - ref.z), ue[j]);
-        }
-    }
-}
-
-// The same halo as two 16-byte arrays, (x, y) and (z, u): random reads of
-// 16-byte items spread over twice as many LDS bank groups as the first or
-// second half of 32-byte records.
+// Stage tile t's halo in LDS (positions relative to `ref`) as two 16-byte
+// arrays, (x, y) and (z, u): random reads of 16-byte items spread over twice
+// as many LDS bank groups as the halves of 32-byte records would.  Each
+// thread's 8 index loads go out together, then its 8 gathers, then the LDS
+// stores; `from` skips the part already staged.
 template <class R>
 struct HaloSoA {
     using V2 = typename Vec2T<R>::T;
@@ -146,116 +116,6 @@ __device__ inline void stage_halo_soa(const Dev& d, const R* __restrict__ u, Hal
     }
 }
 
-// One block per tile of d.tile_rows cells.  The tile's halo (every cell and
-// ghost its stencils reference) is staged in LDS as (x, y, z, u) records, so
-// the ~70 neighbour reads per cell are LDS reads addressed by 16-bit local
-// indices; global memory sees one gather per halo entity and the streamed
-// local index list.  The same halo holds the cell/ghost list of every vertex
-// owned by the tile, so the vertex values of Algorithm 2 are computed here
-// too (u_v = sum alpha u_c, entries in the same order as the vertex list).
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d, FvArrays<R> a) {
-    using V4 = typename Vec4T<R>::T;
-    extern __shared__ __align__(16) unsigned char sm_raw[];
-    V4* sm = reinterpret_cast<V4*>(sm_raw);          // [halo] x, y, z, u
-    constexpr bool rel = std::is_same<R, float>::value;
-    const int64_t nc = d.nc;
-    const int64_t t = blockIdx.x;
-    const int T = blockDim.x;
-    const double4* __restrict__ P = d.xyz4;
-    // positions relative to the tile's first cell in the FP32 form
-    const double4 ref = rel ? P[t * T] : make_double4(0.0, 0.0, 0.0, 0.0);
-    stage_halo<R>(d, a.u, sm, t, ref);
-    __syncthreads();
-
-    // vertex values (Algorithm 2) of the tile's vertices, spread over the waves
-    {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = T >> 6;
-        for (int64_t v = d.v_off[t] + wave + int64_t(nw) * lane; v < d.v_off[t + 1]; v += int64_t(nw) * 64) {
-            const int64_t vb = d.n_off[v >> 6] + (v & 63);
-            const int vw = d.n_w[v >> 6];
-            R acc = R(0);
-            for (int k0 = 0; k0 < vw; k0 += 8) {
-                uint16_t l[8];
-                R al[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const bool in = k0 + j < vw;
-                    const int64_t at = vb + int64_t(k0 + j) * 64;
-                    l[j] = in ? d.n_lidx[at] : 0;
-                    al[j] = in ? a.n_alpha[at] : R(0);
-                }
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    if (k0 + j < vw) acc += al[j] * sm[l[j]].w;
-            }
-            a.unode[v] = acc;
-        }
-    }
-
-    const int64_t i = t * T + threadIdx.x;
-    if (i >= nc) return;
-    const int lself = d.h_self[t] + threadIdx.x;
-    const V4 me = sm[lself];
-    const R xi = me.x, yi = me.y, zi = me.z, ui = me.w;
-    const int64_t s = i >> 6;
-    const uint16_t* __restrict__ idx = d.s_lidx + d.s_off[s] + (i & 63);
-    const int w = d.s_w[s];
-    R jx = R(0), jy = R(0), jz = R(0);
-    // 16 index loads in flight, then 16 LDS reads; slots past the row length
-    // read the cell itself, which adds exact zeros
-    for (int k0 = 0; k0 < w; k0 += 16) {
-        uint16_t l[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) l[j] = k0 + j < w ? idx[int64_t(k0 + j) * 64] : uint16_t(lself);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const V4 o = sm[l[j]];
-            const R du = o.w - ui;
-            jx += (o.x - xi) * du;
-            jy += (o.y - yi) * du;
-            jz += (o.z - zi) * du;
-        }
-    }
-    const R* __restrict__ m = a.minv;
-    const R m0 = m[i], m1 = m[nc + i], m2 = m[2 * nc + i];
-    const R m3 = m[3 * nc + i], m4 = m[4 * nc + i], m5 = m[5 * nc + i];
-    const R gx = m0 * jx + m1 * jy + m2 * jz;
-    const R gy = m1 * jx + m3 * jy + m4 * jz;
-    const R gz = m2 * jx + m4 * jy + m5 * jz;
-    a.grad[i] = gx;
-    a.grad[nc + i] = gy;
-    a.grad[2 * nc + i] = gz;
-
-    // Barth-Jespersen: bounds over the cell and its face neighbours
-    int fc[4];
-    uint16_t nl[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int f = d.c2f[k * nc + i];
-        fc[k] = f < 0 ? ~f : f;
-        nl[k] = d.c2n_l[k * nc + i];
-    }
-    R umax = ui, umin = ui;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const R v = sm[nl[k]].w;
-        umax = fmax(umax, v);
-        umin = fmin(umin, v);
-    }
-    R psi = R(1);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double4 xf = d.fx4[fc[k]];
-        const R dl = gx * (R(xf.x - ref.x) - xi) + gy * (R(xf.y - ref.y) - yi) + gz * (R(xf.z - ref.z) - zi);
-        R ph = R(1);
-        if (dl > R(0)) ph = fmin(R(1), (umax - ui) / dl);
-        else if (dl < R(0)) ph = fmin(R(1), (umin - ui) / dl);
-        psi = fmin(psi, ph);
-    }
-    a.psi[i] = psi;
-}
-
 // ---- gradient in star-moment form ------------------------------------------
 // The sum of Algorithm 1, J_i = sum_{j in N(i)} (x_j - x_i)(u_j - u_i) over
 // the node-neighbour stencil N(i) (every cell and ghost sharing a vertex
@@ -270,8 +130,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_limiter(Dev d, FvArrays<R> a) {
 // edge neighbours instead of ~70 stencil entries.  Every term is a product
 // of differences of nearby values, so no large value cancels.
 //
-// One block per tile, as k_grad_limiter: the halo is staged in LDS; every
-// vertex the tile's cells touch (its own, then the foreign ones, whose lists
+// One block per tile of d.tile_rows cells.  The tile's halo (every cell and
+// ghost the tile's stencils reference) is staged in LDS and addressed by
+// 16-bit local indices, so global memory sees one gather per halo entity and
+// streamed index lists.  Every vertex the tile's cells touch (its own, then the foreign ones, whose lists
 // lie in the same halo) gets its record (xb, n), (C, ub) in LDS, from sums
 // shifted by the list's first entry (pad entries repeat it and add zeros):
 //   s = sum (x_j - x_0), q = sum (u_j - u_0), c = sum (x_j - x_0)(u_j - u_0),
@@ -498,10 +360,11 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
         else if (dl < R(0)) ph = fmin(R(1), (umin - ui) / dl);
         psi = fmin(psi, ph);
     }
-    // the face kernel's upwind data in one record; the separate arrays only
-    // when the caller asks for them
-    d.rec[i] = make_double4(psi * gx, psi * gy, psi * gz, ui);
-    if (PARTS) {
+    // FP64: the face kernel's upwind data in one record, the separate arrays
+    // only when the caller asks for them; FP32: the arrays (the FP32 face
+    // kernel reads them)
+    if constexpr (!rel) d.rec[i] = make_double4(psi * gx, psi * gy, psi * gz, ui);
+    if (PARTS || rel) {
         a.grad[i] = gx;
         a.grad[nc + i] = gy;
         a.grad[2 * nc + i] = gz;
@@ -747,33 +610,41 @@ hipError_t launch_ghost_fill(const Dev& d, bool fp32, const BcTable& bc, hipStre
     return fp32 ? launch_ghost_fill_t(d, fv32(d), bc, s) : launch_ghost_fill_t(d, fv64(d), bc, s);
 }
 
-// FP64: the star-moment tile kernel; FP32: the stencil tile kernel (both
-// also compute the vertex values)
+// The star-moment tile kernel in either precision (it also computes the
+// vertex values): LDS of the halo's two 2-vectors and the touched vertices'
+// four 2-vectors
+template <class R>
 size_t moments_lds_bytes(const Dev& d) {
-    return size_t(2 * ((d.halo_max + 1) & ~1)) * sizeof(double2) + size_t(2 * d.tv_max) * sizeof(double4);
+    using V2 = typename Vec2T<R>::T;
+    return size_t(2 * ((d.halo_max + 1) & ~1) + 4 * d.tv_max) * sizeof(V2);
 }
 
-hipError_t setup_fv_kernels(const Dev& d) {
-    const size_t lds = moments_lds_bytes(d);
+template <class R, bool PARTS>
+hipError_t allow_lds(const Dev& d) {
+    const size_t lds = moments_lds_bytes<R>(d);
     if (lds <= 65536) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_moments<double, false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_moments<double, true>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_moments<R, PARTS>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
 }
 
+hipError_t setup_fv_kernels(const Dev& d) {
+    hipError_t e = allow_lds<double, false>(d);
+    if (e == hipSuccess) e = allow_lds<double, true>(d);
+    if (e == hipSuccess) e = allow_lds<float, true>(d);
+    return e;
+}
+
 hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool parts) {
-    const dim3 g(unsigned(d.ntiles)), b(d.tile_rows);
+    const dim3 b(d.tile_rows);
+    // grid padded to a multiple of 8 for the XCD-contiguous tile order
+    const dim3 gx(unsigned((d.ntiles + kXcds - 1) / kXcds * kXcds));
     if (fp32) {
-        hipLaunchKernelGGL(k_grad_limiter<float>, g, b, size_t(d.halo_max) * sizeof(float4), s, d, fv32(d));
+        hipLaunchKernelGGL((k_grad_moments<float, true>), gx, b, moments_lds_bytes<float>(d), s, d, fv32(d));
     } else {
-        // grid padded to a multiple of 8 for the XCD-contiguous tile order
-        const dim3 gx(unsigned((d.ntiles + kXcds - 1) / kXcds * kXcds));
         if (parts)
-            hipLaunchKernelGGL((k_grad_moments<double, true>), gx, b, moments_lds_bytes(d), s, d, fv64(d));
+            hipLaunchKernelGGL((k_grad_moments<double, true>), gx, b, moments_lds_bytes<double>(d), s, d, fv64(d));
         else
-            hipLaunchKernelGGL((k_grad_moments<double, false>), gx, b, moments_lds_bytes(d), s, d, fv64(d));
+            hipLaunchKernelGGL((k_grad_moments<double, false>), gx, b, moments_lds_bytes<double>(d), s, d, fv64(d));
     }
     return hipGetLastError();
 }

@@ -666,7 +666,6 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     }
     // global -> local through a dense map filled for one tile at a time
     M.n_lidx.assign(M.node.idx.size(), 0);
-    M.s_lidx.assign(M.stencil.idx.size(), 0);
     M.k_lidx.assign(M.kmat.idx.size(), 0);
     M.c2n_l.assign(4 * nc, 0);
     M.e_lidx.assign(M.enbr.idx.size(), 0);
@@ -689,10 +688,6 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             for (int64_t r = t0; r < t1; ++r) {
                 const int64_t sl = r >> 6;
                 const int lane = int(r & 63);
-                for (int64_t k = 0; k < M.stencil.width[sl]; ++k) {
-                    const int64_t at = M.stencil.off[sl] + k * 64 + lane;
-                    M.s_lidx[at] = (uint16_t)g2l[M.stencil.idx[at]];
-                }
                 for (int64_t k = 0; k < M.kmat.width[sl]; ++k) {
                     const int64_t at = M.kmat.off[sl] + k * 64 + lane;
                     M.k_lidx[at] = (uint16_t)g2l[M.kmat.idx[at]];
@@ -770,7 +765,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             }
         return true;
     };
-    bool ok = verify(M.stencil, M.s_lidx) && verify(M.kmat, M.k_lidx) && verify(M.enbr, M.e_lidx);
+    bool ok = verify(M.kmat, M.k_lidx) && verify(M.enbr, M.e_lidx);
     for (int64_t i = 0; ok && i < nc; ++i) {
         const int64_t t = i / M.tile_rows;
         ok = M.h_idx[M.h_off[t] + M.h_self[t] + (i - t * M.tile_rows)] == i;

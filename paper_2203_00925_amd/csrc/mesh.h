@@ -58,7 +58,6 @@ struct Mesh {
     std::vector<int64_t> h_off;       // ntiles + 1
     std::vector<int32_t> h_idx;       // halo entities
     std::vector<int32_t> h_self;      // ntiles: local index of the tile's first cell
-    std::vector<uint16_t> s_lidx;     // like stencil.idx, local
     std::vector<uint16_t> k_lidx;     // like kmat.idx, local
     std::vector<uint16_t> c2n_l;      // 4 x nc local index of the face neighbour
     // vertices are numbered by their lowest cell, so the vertices of tile t

@@ -54,7 +54,7 @@ struct Dev {
     int32_t tile_rows, halo_max;
     int64_t ntiles;
     int64_t* h_off; int32_t* h_idx; int32_t* h_self;
-    uint16_t *s_lidx, *k_lidx, *c2n_l, *n_lidx;
+    uint16_t *k_lidx, *c2n_l, *n_lidx;
     int64_t* v_off;
     // star-moment gradient: edge-only neighbours (64-row slices, local),
     // tile-local vertex numbers, the foreign vertices of each tile
