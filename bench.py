@@ -201,7 +201,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the method's "
-                          "multi-GPU decomposition is not built (see DESIGN.md)",
+                          "multi-GPU decomposition is not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
