@@ -49,7 +49,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in CXX_SOURCES:
         o = os.path.join(obj_dir, src + ".o")
-        _run(["g++", "-O2", "-g0", "-fPIC", "-std=c++17", "-Wall", "-Wextra", *inc, "-c",
+        _run(["g++", "-O2", "-g0", "-fPIC", "-std=c++17", "-pthread", "-Wall", "-Wextra", *inc, "-c",
               os.path.join(CSRC, src), "-o", o])
         objs.append(o)
     hipflags = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
@@ -62,7 +62,7 @@ def build(verbose: bool = False) -> str:
             print(out)
         objs.append(o)
     tmp = LIB + ".tmp"
-    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
+    _run([hipcc, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", *objs, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -12,24 +12,44 @@ namespace {
 
 constexpr int E_ARG = MIFVM_E_ARG;
 
-// strong neighbours of every row, in column order, with |a_ij|
+// strong neighbours of every row, in column order, with |a_ij|: counted,
+// then written, row-parallel
 void strength(const AmgCsr& A, double theta, std::vector<int64_t>& sptr, std::vector<int32_t>& sidx,
               std::vector<double>& sval) {
     sptr.assign(A.n + 1, 0);
-    sidx.clear();
-    sval.clear();
-    for (int64_t i = 0; i < A.n; ++i) {
+    const int nt = setup_threads(A.n);
+    auto row_max = [&](int64_t i) {
         double mx = 0.0;
         for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
             if (A.col[e] != i) mx = std::max(mx, std::fabs(A.val[e]));
-        if (mx > 0.0)
+        return mx;
+    };
+    auto strong = [&](int64_t i, int64_t e, double mx) {
+        return mx > 0.0 && A.col[e] != i && std::fabs(A.val[e]) >= theta * mx;
+    };
+    for_chunks(A.n, nt, [&](int, int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            const double mx = row_max(i);
+            int64_t c = 0;
+            for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) c += strong(i, e, mx) ? 1 : 0;
+            sptr[i + 1] = c;
+        }
+    });
+    for (int64_t i = 0; i < A.n; ++i) sptr[i + 1] += sptr[i];
+    sidx.assign(sptr[A.n], 0);
+    sval.assign(sptr[A.n], 0.0);
+    for_chunks(A.n, nt, [&](int, int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            const double mx = row_max(i);
+            int64_t at = sptr[i];
             for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e)
-                if (A.col[e] != i && std::fabs(A.val[e]) >= theta * mx) {
-                    sidx.push_back(A.col[e]);
-                    sval.push_back(std::fabs(A.val[e]));
+                if (strong(i, e, mx)) {
+                    sidx[at] = A.col[e];
+                    sval[at] = std::fabs(A.val[e]);
+                    ++at;
                 }
-        sptr[i + 1] = (int64_t)sidx.size();
-    }
+        }
+    });
 }
 
 int64_t aggregate(const AmgCsr& A, const std::vector<int64_t>& sptr, const std::vector<int32_t>& sidx,
@@ -88,36 +108,48 @@ void galerkin(const AmgCsr& A, const std::vector<int32_t>& agg, int64_t na, AmgC
     }
     C.n = na;
     C.ptr.assign(na + 1, 0);
-    C.col.clear();
-    C.val.clear();
-    std::vector<int64_t> slot(na, -1);
-    std::vector<int32_t> cols;
-    std::vector<double> acc;
-    for (int64_t I = 0; I < na; ++I) {
-        cols.clear();
-        acc.clear();
-        for (int64_t m = mptr[I]; m < mptr[I + 1]; ++m) {
-            const int64_t i = mem[m];
-            for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
-                const int32_t J = agg[A.col[e]];
-                if (slot[J] < 0) {
-                    slot[J] = (int64_t)cols.size();
-                    cols.push_back(J);
-                    acc.push_back(0.0);
+    // coarse rows in contiguous chunks, one per thread, each into its own
+    // buffers; then the chunks are concatenated in row order
+    const int nt = setup_threads(A.n);
+    std::vector<std::vector<int32_t>> pcol(nt);
+    std::vector<std::vector<double>> pval(nt);
+    for_chunks(na, nt, [&](int k, int64_t lo, int64_t hi) {
+        std::vector<int32_t> slot(na, -1);
+        std::vector<int32_t> cols, order;
+        std::vector<double> acc;
+        for (int64_t I = lo; I < hi; ++I) {
+            cols.clear();
+            acc.clear();
+            for (int64_t m = mptr[I]; m < mptr[I + 1]; ++m) {
+                const int64_t i = mem[m];
+                for (int64_t e = A.ptr[i]; e < A.ptr[i + 1]; ++e) {
+                    const int32_t J = agg[A.col[e]];
+                    if (slot[J] < 0) {
+                        slot[J] = int32_t(cols.size());
+                        cols.push_back(J);
+                        acc.push_back(0.0);
+                    }
+                    acc[slot[J]] += A.val[e];
                 }
-                acc[slot[J]] += A.val[e];
             }
+            order.resize(cols.size());
+            for (size_t q = 0; q < order.size(); ++q) order[q] = int32_t(q);
+            std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cols[a] < cols[b]; });
+            for (int32_t q : order) {
+                pcol[k].push_back(cols[q]);
+                pval[k].push_back(acc[q]);
+            }
+            for (int32_t J : cols) slot[J] = -1;
+            C.ptr[I + 1] = int64_t(cols.size());
         }
-        std::vector<int32_t> order(cols.size());
-        for (size_t k = 0; k < order.size(); ++k) order[k] = int32_t(k);
-        std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cols[a] < cols[b]; });
-        for (int32_t k : order) {
-            C.col.push_back(cols[k]);
-            C.val.push_back(acc[k]);
-        }
-        for (int32_t J : cols) slot[J] = -1;
-        C.ptr[I + 1] = (int64_t)C.col.size();
-    }
+    });
+    for (int64_t I = 0; I < na; ++I) C.ptr[I + 1] += C.ptr[I];
+    C.col.resize(C.ptr[na]);
+    C.val.resize(C.ptr[na]);
+    for_chunks(na, nt, [&](int k, int64_t lo, int64_t) {
+        std::copy(pcol[k].begin(), pcol[k].end(), C.col.begin() + C.ptr[lo]);
+        std::copy(pval[k].begin(), pval[k].end(), C.val.begin() + C.ptr[lo]);
+    });
 }
 
 // dense inverse by LU with partial pivoting (row-major, n x n)

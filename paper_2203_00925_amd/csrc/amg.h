@@ -19,13 +19,34 @@
 //   x = w D^-1 b;  b_c = P^T (b - A x);  x += P V(b_c);  x += w D^-1 (b - A x),
 // with the dense inverse on the coarsest level.
 #pragma once
+#include <algorithm>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mesh.h"
 
 namespace mifvm {
+
+// Host threads for the setup's row-parallel passes: up to 16 for n rows of
+// at least 65,536, else 1.
+inline int setup_threads(int64_t n) {
+    const unsigned h = std::thread::hardware_concurrency();
+    return n < 65536 ? 1 : int(std::min<unsigned>(16, h ? h : 1));
+}
+
+// f(k, lo, hi) for the nt contiguous chunks [lo, hi) of [0, n), chunk k on
+// its own thread (chunk 0 on the caller's); every row is handled by exactly
+// one call, so results do not depend on nt.
+template <class F>
+void for_chunks(int64_t n, int nt, F&& f) {
+    std::vector<std::thread> th;
+    for (int k = 1; k < nt; ++k)
+        th.emplace_back([&f, n, nt, k] { f(k, n * k / nt, n * (k + 1) / nt); });
+    f(0, 0, n / nt);
+    for (auto& t : th) t.join();
+}
 
 constexpr int kAmgMaxLevels = 16;
 

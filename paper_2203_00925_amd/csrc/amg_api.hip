@@ -92,26 +92,29 @@ int state_matrix(State& s, hipStream_t hs, AmgCsr& A) {
     HIPCHK(hipStreamSynchronize(hs));
     A.n = m.nc;
     A.ptr.assign(m.nc + 1, 0);
-    A.col.clear();
-    A.val.clear();
-    A.col.reserve(size_t(m.matrix_nnz));
-    A.val.reserve(size_t(m.matrix_nnz));
-    std::vector<std::pair<int32_t, double>> row;
-    for (int64_t i = 0; i < m.nc; ++i) {
-        const int64_t sl = i >> 6, lane = i & 63;
-        row.clear();
-        row.emplace_back(int32_t(i), diag[i]);
-        for (int32_t k = 0; k < m.klen[i]; ++k) {
-            const int64_t at = m.kmat.off[sl] + int64_t(k) * 64 + lane;
-            row.emplace_back(m.kmat.idx[at], val[at]);
+    for (int64_t i = 0; i < m.nc; ++i) A.ptr[i + 1] = A.ptr[i] + 1 + m.klen[i];
+    A.col.resize(A.ptr[m.nc]);
+    A.val.resize(A.ptr[m.nc]);
+    // rows are independent: sorted by column in parallel chunks
+    for_chunks(m.nc, setup_threads(m.nc), [&](int, int64_t lo, int64_t hi) {
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t i = lo; i < hi; ++i) {
+            const int64_t sl = i >> 6, lane = i & 63;
+            row.clear();
+            row.emplace_back(int32_t(i), diag[i]);
+            for (int32_t k = 0; k < m.klen[i]; ++k) {
+                const int64_t at = m.kmat.off[sl] + int64_t(k) * 64 + lane;
+                row.emplace_back(m.kmat.idx[at], val[at]);
+            }
+            std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+            int64_t at = A.ptr[i];
+            for (auto& e : row) {
+                A.col[at] = e.first;
+                A.val[at] = e.second;
+                ++at;
+            }
         }
-        std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
-        for (auto& e : row) {
-            A.col.push_back(e.first);
-            A.val.push_back(e.second);
-        }
-        A.ptr[i + 1] = (int64_t)A.col.size();
-    }
+    });
     return MIFVM_OK;
 }
 

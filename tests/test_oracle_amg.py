@@ -168,3 +168,22 @@ def test_w_cycle_pins():
     assert poisson.true_relative_residual(K, bb, xw) <= 1e-10
     print(f"multigrid FCG: V {it_v}, W {it_w} iterations over {len(lv)} levels")
     assert it_w < it_v
+
+
+def test_library_setup_on_threads_equals_oracle():
+    """A matrix of at least 65,536 rows takes the library's threaded setup
+    (strength and Galerkin product in row chunks): its aggregates and coarse
+    matrices still equal the oracle's."""
+    A = laplacian_2d(260)                                   # 67,600 rows
+    A.sort_indices()
+    levels, cinv = amg.build(A, coarse_max=256)
+    h = B.AmgHost(A.indptr, A.indices, A.data, coarse_max=256)
+    assert h.info["levels"] == len(levels) >= 3
+    for l, (Al, agg) in enumerate(levels):
+        assert h.info["rows"][l] == Al.shape[0]
+        if agg is not None:
+            assert np.array_equal(h.export(l, "agg"), agg)
+        if l > 0:
+            assert np.array_equal(h.export(l, "ptr"), Al.indptr)
+            assert np.array_equal(h.export(l, "col"), Al.indices)
+            assert np.abs(h.export(l, "val") - Al.data).max() <= 1e-14 * np.abs(Al.data).max()
