@@ -94,6 +94,9 @@ def kernel_source_hash(name):
             h.update(fh.read())
     return h.hexdigest()[:16]
 HBM_PEAK_GBS = 8000.0
+# strength threshold and Jacobi weight of the W-cycle forms: the best of a
+# sweep theta in {0.1 .. 0.6} x omega in {0.6 .. 1.0} on cube120 (cold solves)
+AMG_W_OPTS = dict(theta=0.4, omega=0.8)
 WORKLOADS = {
     "cube120": dict(n=120, seed=2),
     "cube20": dict(n=20, seed=1),
@@ -385,9 +388,10 @@ def main():
             torch.cuda.empty_cache()
         if run("multigrid_w_fcg"):
             result["forms"]["multigrid_w_fcg"] = run_solver_form(
-                args, M, pf, "flexible CG + aggregation multigrid W(1,1), matrix-free, graph-replayed chunks of 8",
+                args, M, pf, "flexible CG + aggregation multigrid W(1,1), theta 0.4, omega 0.8, matrix-free, "
+                "graph-replayed chunks of 8",
                 dict(method=B.SOLVE_AMG, matrix_free=True, graph=1, chunk=8), plain_ms, p64, amg=True,
-                cycle=B.CYCLE_W, kernel_times=False)
+                cycle=B.CYCLE_W, kernel_times=False, amg_opts=AMG_W_OPTS)
             torch.cuda.empty_cache()
         if run("streamer"):
             result["forms"]["streamer"] = run_streamer_form(args, M, pf)
@@ -461,12 +465,13 @@ def run_fp32_form(args, M, pf, u64, p64, plain_ms):
 
 
 def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0, amg=False, cycle=0,
-                    kernel_times=True):
+                    kernel_times=True, amg_opts=None):
     """The FP64 run's steps with another solver of the same system: solve time
     and iterations per step, the solution's difference from the plain run's,
     and one cold solve (P = 0).  amg: build and attach the multigrid
     hierarchy first (its host setup time is reported, outside the timings);
-    cycle: its cycle type (0 V, CYCLE_W).  kernel_times: time each kernel
+    cycle: its cycle type (0 V, CYCLE_W); amg_opts: its theta / omega.
+    kernel_times: time each kernel
     (per-kernel events, which keep solves from replaying captured graphs);
     off for the forms timed on graph replay."""
     import numpy as np
@@ -480,7 +485,7 @@ def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0, amg=
     st.poisson_assemble()
     if fgmres_m:
         st.fgmres_attach(fgmres_m)
-    amg_info = st.amg_build(cycle=cycle) if amg else None
+    amg_info = st.amg_build(cycle=cycle, **(amg_opts or {})) if amg else None
     if amg:
         log(f"{name}: {amg_info['levels']} levels {amg_info['rows']}, setup {amg_info['setup_ms'] / 1e3:.1f} s")
     dt = st.cfl_dt(pf.cfl)
@@ -686,7 +691,7 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
     # the trained network as the finest-level smoother of the multigrid W-cycle:
     # cold solves of one right-hand side with each smoother and plain
     # Jacobi-CG, then stepped (warm) solves
-    amg_info = st.amg_build(cycle=B.CYCLE_W)
+    amg_info = st.amg_build(cycle=B.CYCLE_W, **AMG_W_OPTS)
     kw_mg = dict(tol=1e-10, restart=500, method=B.SOLVE_AMG, matrix_free=True)
     cold_mg = {}
     for name, extra in (("jacobi_smoother", {}), ("learned_smoother", dict(learned_smoother=True, chunk=8))):

@@ -222,3 +222,12 @@ def test_w_cycle_matches_oracle_and_solves():
         g = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_AMG, matrix_free=True, chunk=8, graph=graph)
         out.append((g["iterations"], host(st.get_field(B.FIELD_P))))
     assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
+    # other strength threshold and Jacobi weight: the oracle's hierarchy and cycle
+    info = st.amg_build(coarse_max=16, cycle=B.CYCLE_W, theta=0.4, omega=0.8)
+    levels, cinv = amg.build(K_int, theta=0.4, coarse_max=16)
+    assert info["rows"] == [A.shape[0] for A, _ in levels]
+    z = host(st.amg_apply(dev(r)))
+    z_ref[mp.cp] = amg.v_cycle(levels, cinv, r[mp.cp], omega=0.8, gamma=2)
+    err = np.abs(z - z_ref).max() / np.abs(z_ref).max()
+    print(f"[gpu] W-cycle (theta 0.4, omega 0.8) error {err:.2e} over {info['levels']} levels", flush=True)
+    assert err < 1e-10
