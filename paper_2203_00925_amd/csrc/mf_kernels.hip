@@ -65,14 +65,15 @@ __global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict
     const int w = d.n_w[sl];
     const int nc = int(d.nc);
     R s = R(0);
-    // batches of 8: the next batch's indices and weights are in flight while
-    // this batch's values are gathered (one load per entry: a cell's x or a
+    // batches of 24 (an interior vertex of the 6-tetrahedra cube has 24
+    // cells): the next batch's indices and weights are in flight while this
+    // batch's values are gathered (one load per entry: a cell's x or a
     // ghost's xg, by pointer)
-    int e[8];
-    R al[8];
+    int e[24];
+    R al[24];
     auto batch = [&](int k0, int* eo, R* ao) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < 24; ++j) {
             const bool in = k0 + j < w;
             const int64_t at = base + int64_t(k0 + j) * 64;
             eo[j] = in ? d.n_idx[at] : 0;                // padding entries carry weight 0
@@ -80,17 +81,17 @@ __global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict
         }
     };
     batch(0, e, al);
-    for (int k0 = 0; k0 < w; k0 += 8) {
-        R xe[8];
+    for (int k0 = 0; k0 < w; k0 += 24) {
+        R xe[24];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) xe[j] = *(e[j] < nc ? x + e[j] : xg + (e[j] - nc));
-        int en[8];
-        R an[8];
-        batch(k0 + 8, en, an);
+        for (int j = 0; j < 24; ++j) xe[j] = *(e[j] < nc ? x + e[j] : xg + (e[j] - nc));
+        int en[24];
+        R an[24];
+        batch(k0 + 24, en, an);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) s += al[j] * xe[j];
+        for (int j = 0; j < 24; ++j) s += al[j] * xe[j];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < 24; ++j) {
             e[j] = en[j];
             al[j] = an[j];
         }
