@@ -122,6 +122,10 @@ def test_library_setup_rejects_bad_input():
     with pytest.raises(B.MifvmError):
         B.AmgHost(K.indptr, K.indices, K.data, theta=2.0)
     with pytest.raises(B.MifvmError):
+        B.AmgHost(K.indptr, K.indices, K.data, omega=2.5)          # Jacobi weight outside (0, 2)
+    with pytest.raises(B.MifvmError):
+        B.AmgHost(K.indptr, K.indices, K.data, coarse_max=5000)    # dense level above 4096 rows
+    with pytest.raises(B.MifvmError):
         B.AmgHost(K.indptr, K.indices, K.data, coarse_max=8, max_levels=2)
     bad = K.indices.copy()
     bad[0] = K.shape[0] + 5
