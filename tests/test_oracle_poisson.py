@@ -183,3 +183,26 @@ def test_fgmres_converges_to_the_direct_solution():
     x2, _, rel2 = poisson.jacobi_fgmres(K, b, tol=1e-10, m=30, precond=varying)
     assert rel2 <= 1e-10
     assert np.linalg.norm(x2 - xd) <= 1e-7 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_annex_variant_with_nonzero_neumann_data(n):
+    """The annex problem with its 'out' wall turned into a Neumann wall:
+    P = 10 on x = 0 and dP/dn = -10 on x = 1 (outward normal +x), zero normal
+    derivative elsewhere.  The exact solution is still 10(1 - x); every ghost
+    value (Dirichlet and Neumann) is then the linear field at the ghost centre
+    and every prescribed flux is exact, so the direct solve reproduces it."""
+    geo = cube_geometry(n, seed=5)
+    kinds = [DIRICHLET, NEUMANN, NEUMANN, NEUMANN, NEUMANN, NEUMANN]
+    vals = [10.0, -10.0, 0.0, 0.0, 0.0, 0.0]
+    K, c = poisson.assemble(geo, kinds, vals)
+    b = poisson.rhs(geo, np.zeros(geo.nc), c)
+    exact = 10.0 * (1.0 - geo.xc[:geo.nc, 0])
+    x = poisson.direct_solve(K, b)
+    assert np.abs(x - exact).max() < 1e-11
+    # the matrix-free operator (a separate code path) agrees: A(exact) = 0
+    assert np.abs(poisson.apply_laplacian(geo, exact, kinds, vals)).max() < 1e-11
+    # and a sign slip in the Neumann data breaks it
+    K2, c2 = poisson.assemble(geo, kinds, [10.0, 10.0, 0.0, 0.0, 0.0, 0.0])
+    x2 = poisson.direct_solve(K2, poisson.rhs(geo, np.zeros(geo.nc), c2))
+    assert np.abs(x2 - exact).max() > 1.0
