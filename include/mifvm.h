@@ -65,7 +65,10 @@ enum mifvm_bc_kind { MIFVM_ZERO_FLUX = 0, MIFVM_NEUMANN = 1, MIFVM_DIRICHLET = 2
 /* variables with their own boundary conditions */
 enum mifvm_var { MIFVM_VAR_SCALAR = 0, MIFVM_VAR_POTENTIAL = 1 };
 
-/* per-cell fields (all float64, user cell order) */
+/* element type of a field array at the ABI (mifvm_set_field/get_field) */
+enum mifvm_dtype { MIFVM_F64 = 0, MIFVM_F32 = 1 };
+
+/* per-cell fields (user cell order; float64 or float32, see mifvm_dtype) */
 enum mifvm_field {
     MIFVM_FIELD_U = 0,        /* transported scalar u                        */
     MIFVM_FIELD_VEL = 1,      /* velocity, 3*Nc values laid out [x..., y..., z...] */
@@ -93,6 +96,12 @@ typedef struct {
                                   tets[start[m]:start[m+1]]; NULL when
                                   nmeshes <= 1.  Meshes of a batch share no
                                   face; each needs >= 256 cells.             */
+    int32_t no_matrix;         /* 1 = do not build the stored Poisson pattern
+                                  (no assembly, no stored-matrix solves; the
+                                  matrix-free solves need none of it): the
+                                  workspace shrinks by about 17 B per matrix
+                                  entry (8.7 GB for the 10.4M-cell cube)      */
+    int32_t pad_;
 } mifvm_mesh_opts;
 
 typedef struct {
@@ -132,7 +141,8 @@ typedef struct {
 /* FP64: the step in FP64.  FP32: the reduced-precision form - state,
  * gradients, limiter, vertex values, fluxes and the geometry they read in
  * FP32 (positions relative to a nearby cell); the CFL bound and the
- * conservation sum stay FP64.  Fields cross the ABI as FP64 either way.    */
+ * conservation sum stay FP64.  Fields cross the ABI in either element type
+ * (mifvm_dtype) whatever the precision of the state.                       */
 enum mifvm_precision { MIFVM_FP64 = 0, MIFVM_FP32 = 1 };
 
 typedef struct {
@@ -159,8 +169,11 @@ typedef struct {
     int32_t matrix_free;       /* 1 = apply K in the iterations from the
                                   discretisation (vertex values, diamond
                                   fluxes, cell gather) instead of the stored
-                                  matrix; the assembled diagonal and c are
-                                  unchanged.  IR_FP32: the inner CG applies
+                                  matrix, the true residual included; needs
+                                  no assembly (the diagonal, D^-1 and c are
+                                  computed from the discretisation when the
+                                  POTENTIAL BCs have changed).  IR_FP32: the
+                                  inner CG applies
                                   it in FP32 (FP32 copies of the vertex
                                   weights and diamond coefficients) and the
                                   true residual in FP64                      */
@@ -262,16 +275,35 @@ int mifvm_mesh_export(const mifvm_mesh* mesh, int32_t what, void* dst, size_t by
 int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params,
                        void* d_ws, size_t ws_bytes, void* stream, mifvm_state** out);
 void mifvm_state_destroy(mifvm_state* st);
-/* kind/value for one boundary tag of one variable; takes effect at the next
- * step (SCALAR) or assemble (POTENTIAL).  Default: ZERO_FLUX, 0.           */
+/* kind/value for one boundary tag of one variable (Annexes: the per-name
+ * dictionary of Variable(domain, BC, values)); default ZERO_FLUX, 0.  The
+ * value is written to every ghost of the tag in device memory (the call
+ * synchronises the device before and after).  It takes effect at the next
+ * step (SCALAR) or solve (POTENTIAL; a stored matrix must be assembled
+ * again).  Captured graphs (mifvm_step_graph, graph-replayed solves) are
+ * dropped and captured again at their next use.                           */
 int mifvm_set_bc(mifvm_state* st, int32_t var, int32_t tag, int32_t kind, double value);
+/* Per-face values for one tag of one variable, for data that varies along
+ * a boundary (Dirichlet data at each face's foot point, a Neumann flux per
+ * face): d_vals holds one float64 per boundary triangle given to
+ * mifvm_mesh_preprocess, in that order (nb values); the entries of
+ * triangles with another tag are not read.  The kind stays the one set by
+ * mifvm_set_bc.  Asynchronous on `stream`; later steps, solves and graph
+ * replays read the new values.  POTENTIAL: the ghost constants c change, so
+ * a stored matrix must be assembled again (matrix-free solves recompute c).
+ * E_ARG for a null pointer, an unknown variable or a tag out of range.     */
+int mifvm_set_bc_values(mifvm_state* st, int32_t var, int32_t tag, const double* d_vals, void* stream);
 int mifvm_set_diffusivity(mifvm_state* st, double diffusivity);          /* every mesh */
 /* one diffusivity per mesh of a batch (n = nmeshes).  Synchronises.        */
 int mifvm_set_mesh_diffusivity(mifvm_state* st, const double* D, int32_t n);
-/* d_src: float64 in user cell order (3*nc for VEL).  Setting VEL recomputes
- * the face velocity fluxes phi_f = 1/2 (V_L + V_R) . S_f.                  */
-int mifvm_set_field(mifvm_state* st, int32_t field, const double* d_src, void* stream);
-int mifvm_get_field(const mifvm_state* st, int32_t field, double* d_dst, void* stream);
+/* d_src: nc values (3*nc for VEL, laid out [x..., y..., z...]) in user cell
+ * order, of element type dtype (mifvm_dtype).  A value crosses into the
+ * state's precision by round to nearest; FIELD_U of an FP32 state from F32
+ * data is taken as is.  Setting VEL recomputes the face velocity fluxes
+ * phi_f = 1/2 (V_L + V_R) . S_f.  get_field writes the same layout.
+ * E_ARG for a null pointer, an unknown field or dtype (and EFIELD to set).  */
+int mifvm_set_field(mifvm_state* st, int32_t field, const void* d_src, int32_t dtype, void* stream);
+int mifvm_get_field(const mifvm_state* st, int32_t field, void* d_dst, int32_t dtype, void* stream);
 
 /* ---- step (eq. (4) with the Runge-Kutta scheme of eq. (6)) ---------------
  * Per mesh: dt_m = cfl * min_i mu_i / sum_{faces of i not ZERO_FLUX}
@@ -305,7 +337,8 @@ int mifvm_mesh_values(const mifvm_state* st, int32_t what, double* out, int32_t 
 /* ---- Poisson (LinearSystem.assembly() / .solve()) ------------------------
  * Assemble K and the ghost-constant vector c of K P = -mu*f + c, from the
  * POTENTIAL boundary conditions (rows without the 1/mu_i factor, sign
- * flipped so that the diagonal is positive).  Asynchronous.                */
+ * flipped so that the diagonal is positive).  E_STATE for a mesh
+ * preprocessed with no_matrix.  Drops captured graphs.  Asynchronous.      */
 int mifvm_poisson_assemble(mifvm_state* st, void* stream);
 /* d_y = K d_x, both user order.                                            */
 int mifvm_poisson_apply(mifvm_state* st, const double* d_x, double* d_y, void* stream);
@@ -315,7 +348,8 @@ int mifvm_poisson_apply(mifvm_state* st, const double* d_x, double* d_y, void* s
  * cell's faces), user order; equal to mifvm_poisson_apply up to rounding.
  * Needs only the POTENTIAL boundary kinds (no assembly).                  */
 int mifvm_poisson_apply_free(mifvm_state* st, const double* d_x, double* d_y, void* stream);
-/* d_b = -mu * d_f + c (user order; d_f NULL = the current U).              */
+/* d_b = -mu * d_f + c (user order; d_f NULL = the current U); c is
+ * computed first if the POTENTIAL BCs changed since it last was.           */
 int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* stream);
 /* Jacobi-preconditioned CG on K x = b with b from d_f (NULL = current U);
  * starts from the stored P (zero after create, the last solution after a
@@ -326,7 +360,9 @@ int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* str
  * `iterations` counts FP32 inner iterations and every outer step restarts
  * the inner CG.  On a batch every mesh runs its own CG (own scalars and
  * stopping test); info reports the largest iteration count and residual.
- * Returns NOT_CONVERGED at maxit.
+ * Returns NOT_CONVERGED at maxit.  Every method but a matrix_free one
+ * (and AMG, whose hierarchy is built from K) needs an assembled system:
+ * E_STATE otherwise.
  * Synchronises (once per chunk).                                           */
 int mifvm_poisson_solve(mifvm_state* st, const double* d_f, const mifvm_solve_opts* opts,
                         mifvm_solve_info* info, void* stream);
@@ -339,7 +375,9 @@ int mifvm_fgmres_attach(mifvm_state* st, int32_t m, void* d_ws, size_t ws_bytes)
 
 /* ---- captured replays and the autotuner -----------------------------------
  * mifvm_step_graph: as mifvm_step, but the n_steps x 3 stages are captured
- * once into a hipGraph (per (n_steps, dt)) and replayed on `stream`.
+ * once into a hipGraph (per (n_steps, dt, CFL factor of the last
+ * mifvm_cfl_dt)) and replayed on `stream`; mifvm_set_bc and
+ * mifvm_poisson_assemble drop every captured graph.
  * mifvm_autotune: times the CG schedule (chunk 8/16/32/64, direct launches
  * or graph replay) on short solves of the current system (f = U; P is
  * restored afterwards) and one step direct vs replayed (U restored); keeps

@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .geometry import Geometry, ZERO_FLUX, NEUMANN, DIRICHLET, ghost_coefficients
+from .geometry import Geometry, ZERO_FLUX, NEUMANN, DIRICHLET, ghost_coefficients, ghost_values
 
 RK3_ALPHA = (0.5, 0.5, 1.0)
 
@@ -115,7 +115,7 @@ def face_fluxes(geo: Geometry, u_ext, grad, psi, u_node, phi, D, kinds, values):
     u_up = np.where(phi >= 0, uL, uR)
     diff = diamond_flux(geo, u_ext, u_node)
     kind = np.where(interior, DIRICHLET, np.asarray(kinds)[np.maximum(geo.ftag, 0)])
-    val = np.where(interior, 0.0, np.asarray(values, np.float64)[np.maximum(geo.ftag, 0)])
+    val = np.where(interior, 0.0, ghost_values(geo, values)[np.maximum(geo.fghost, 0)])
     area = np.linalg.norm(geo.fS, axis=1)
     diff = np.where(kind == NEUMANN, val * area, diff)
     F = u_up * phi - D * diff

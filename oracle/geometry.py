@@ -69,6 +69,8 @@ class Geometry:
     nptr: np.ndarray
     nidx: np.ndarray
     nalpha: np.ndarray
+    # ghost g -> index of its triangle in the boundary triangles given
+    gbtri: np.ndarray = None
 
 
 def _cross(a, b):
@@ -146,6 +148,8 @@ def build_geometry(xyz, tets, btris, btags) -> Geometry:
     bfaces = np.nonzero(~interior)[0]
     fghost = np.full(nf, -1, np.int64)
     fghost[bfaces] = np.arange(nb)
+    gbtri = np.empty(nb, np.int64)
+    gbtri[fghost[pos]] = np.arange(nb_in)
     fR = np.where(interior, fR, nc + fghost)
     n_hat = S[bfaces] / np.linalg.norm(S[bfaces], axis=1)[:, None]
     xL = xcell[fL[bfaces]]
@@ -206,7 +210,8 @@ def build_geometry(xyz, tets, btris, btags) -> Geometry:
                     fghost=fghost, ftag=ftag, kAC=kAC, kBC=kBC, kRL=kRL,
                     gface=bfaces, gowner=fL[bfaces], gtag=ftag[bfaces],
                     gdist=gdist, cfaces=cfaces, csign=csign,
-                    sptr=sptr, sidx=sidx, nptr=nptr, nidx=nidx, nalpha=nalpha)
+                    sptr=sptr, sidx=sidx, nptr=nptr, nidx=nidx, nalpha=nalpha,
+                    gbtri=gbtri)
 
 
 def _match_rows(table, query):
@@ -222,13 +227,30 @@ def _match_rows(table, query):
     return np.where(tk[pos] == qk, pos, -1)
 
 
+class PerFace:
+    """Boundary values given per boundary triangle, in the order of the
+    triangles the mesh was built from, instead of one value per tag (the
+    Annexes' per-name values generalised to data that varies along a wall)."""
+
+    def __init__(self, vals):
+        self.vals = np.asarray(vals, np.float64)
+
+
+def ghost_values(geo: Geometry, values):
+    """The boundary value at each ghost's face: values[tag], or the ghost's
+    triangle's entry of a PerFace."""
+    if isinstance(values, PerFace):
+        return values.vals[geo.gbtri]
+    return np.asarray(values, np.float64)[geo.gtag]
+
+
 def ghost_coefficients(geo: Geometry, kinds, values):
     """Ghost value u_g = s * u_owner + t for each ghost, from per-tag boundary
     conditions (a1).  Zero-flux and Neumann ghosts mirror the owner (plus the
     prescribed normal derivative times the owner-ghost distance); Dirichlet
     ghosts make the face-midpoint average equal to the prescribed value."""
     kinds = np.asarray(kinds)[geo.gtag]
-    values = np.asarray(values, np.float64)[geo.gtag]
+    values = ghost_values(geo, values)
     s = np.where(kinds == DIRICHLET, -1.0, 1.0)
     t = np.where(kinds == DIRICHLET, 2.0 * values,
                  np.where(kinds == NEUMANN, values * geo.gdist, 0.0))

@@ -25,7 +25,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .geometry import Geometry, ZERO_FLUX, NEUMANN, DIRICHLET, ghost_coefficients
+from .geometry import Geometry, ZERO_FLUX, NEUMANN, DIRICHLET, ghost_coefficients, ghost_values
 from .fv import extend_with_ghosts, node_values, diamond_flux
 
 
@@ -33,7 +33,7 @@ def _face_kinds(geo: Geometry, kinds, values):
     interior = geo.fghost < 0
     tag = np.maximum(geo.ftag, 0)
     kind = np.where(interior, DIRICHLET, np.asarray(kinds)[tag])
-    val = np.where(interior, 0.0, np.asarray(values, np.float64)[tag])
+    val = np.where(interior, 0.0, ghost_values(geo, values)[np.maximum(geo.fghost, 0)])
     return kind, val
 
 

@@ -24,6 +24,7 @@ RENUMBER_NONE, RENUMBER_MORTON, RENUMBER_RCM = 0, 1, 2
 SOLVE_PLAIN, SOLVE_IR_FP32, SOLVE_LEARNED, SOLVE_FGMRES, SOLVE_AMG = 0, 1, 2, 3, 4
 CYCLE_V, CYCLE_W = 1, 2
 FP64, FP32 = 0, 1
+F64, F32 = 0, 1                           # element types of field arrays at the ABI
 KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
            "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble", "nn_layer1", "nn_layer2", "nn_layer3",
            "fcg_vec", "nn_train", "mf_vertex", "mf_face", "mf_gather")
@@ -61,7 +62,7 @@ class MifvmError(RuntimeError):
 
 class _MeshOpts(C.Structure):
     _fields_ = [("renumber", C.c_int32), ("nmeshes", C.c_int32),
-                ("mesh_cell_start", C.c_void_p)]
+                ("mesh_cell_start", C.c_void_p), ("no_matrix", C.c_int32), ("pad_", C.c_int32)]
 
 
 class MeshInfo(C.Structure):
@@ -194,11 +195,12 @@ def _load():
         "mifvm_state_create": (C.c_int, [P, C.POINTER(_Params), P, SZ, P, C.POINTER(P)]),
         "mifvm_state_destroy": (None, [P]),
         "mifvm_set_bc": (C.c_int, [P, I32, I32, I32, D]),
+        "mifvm_set_bc_values": (C.c_int, [P, I32, I32, P, P]),
         "mifvm_set_diffusivity": (C.c_int, [P, D]),
         "mifvm_set_mesh_diffusivity": (C.c_int, [P, P, I32]),
         "mifvm_mesh_values": (C.c_int, [P, I32, P, I32]),
-        "mifvm_set_field": (C.c_int, [P, I32, P, P]),
-        "mifvm_get_field": (C.c_int, [P, I32, P, P]),
+        "mifvm_set_field": (C.c_int, [P, I32, P, I32, P]),
+        "mifvm_get_field": (C.c_int, [P, I32, P, I32, P]),
         "mifvm_cfl_dt": (C.c_int, [P, D, C.POINTER(D), P]),
         "mifvm_step": (C.c_int, [P, I32, D, P]),
         "mifvm_residual": (C.c_int, [P, P, P, P, P, P, P]),
@@ -264,7 +266,8 @@ def _stream(stream):
 class Mesh:
     """Host-side preprocessed mesh (mifvm_mesh_preprocess)."""
 
-    def __init__(self, xyz, tets, btris, btags, renumber=RENUMBER_MORTON, mesh_cell_start=None):
+    def __init__(self, xyz, tets, btris, btags, renumber=RENUMBER_MORTON, mesh_cell_start=None,
+                 no_matrix=False):
         xyz = np.ascontiguousarray(xyz, np.float64)
         tets = np.ascontiguousarray(tets, np.int32)
         btris = np.ascontiguousarray(btris, np.int32)
@@ -272,10 +275,10 @@ class Mesh:
         h = C.c_void_p()
         if mesh_cell_start is not None:
             starts = np.ascontiguousarray(mesh_cell_start, np.int64)
-            opts = _MeshOpts(renumber, len(starts) - 1, starts.ctypes.data)
+            opts = _MeshOpts(renumber, len(starts) - 1, starts.ctypes.data, int(no_matrix), 0)
         else:
             starts = None
-            opts = _MeshOpts(renumber, 1, None)
+            opts = _MeshOpts(renumber, 1, None, int(no_matrix), 0)
         _check(_lib.mifvm_mesh_preprocess(
             xyz.ctypes.data, len(xyz), tets.ctypes.data, len(tets),
             btris.ctypes.data, btags.ctypes.data, len(btags), C.byref(opts), C.byref(h)))
@@ -284,11 +287,11 @@ class Mesh:
         _check(_lib.mifvm_mesh_get_info(h, C.byref(self.info)))
 
     @classmethod
-    def from_cube(cls, m, renumber=RENUMBER_MORTON):
-        return cls(m.xyz, m.tets, m.btris, m.btags, renumber)
+    def from_cube(cls, m, renumber=RENUMBER_MORTON, no_matrix=False):
+        return cls(m.xyz, m.tets, m.btris, m.btags, renumber, no_matrix=no_matrix)
 
     @classmethod
-    def from_batch(cls, meshes, renumber=RENUMBER_MORTON):
+    def from_batch(cls, meshes, renumber=RENUMBER_MORTON, no_matrix=False):
         """Independent meshes as one batch: vertex ids of mesh k are offset by
         the vertices of meshes 0..k-1; cells stay in mesh order."""
         voff = np.cumsum([0] + [m.nv for m in meshes])
@@ -297,7 +300,7 @@ class Mesh:
         tets = np.concatenate([m.tets + voff[k] for k, m in enumerate(meshes)])
         btris = np.concatenate([m.btris + voff[k] for k, m in enumerate(meshes)])
         btags = np.concatenate([m.btags for m in meshes])
-        return cls(xyz, tets, btris, btags, renumber, mesh_cell_start=coff)
+        return cls(xyz, tets, btris, btags, renumber, mesh_cell_start=coff, no_matrix=no_matrix)
 
     def export(self, name):
         what = EXPORT_IDS[name]
@@ -346,6 +349,14 @@ class State:
         for t, (k, v) in enumerate(zip(kinds, values)):
             self.set_bc(var, t, k, v)
 
+    def set_bc_values(self, var, tag, vals, stream=None):
+        """Per-face values of one tag: one float64 per boundary triangle of
+        the mesh, in the order given to the mesh."""
+        import torch
+        t = torch.as_tensor(vals).to(device=self.device, dtype=torch.float64).contiguous()
+        _check(_lib.mifvm_set_bc_values(self._h, var, tag, _ptr(t), _stream(stream)))
+        (stream or torch.cuda.current_stream()).synchronize()   # t may be a temporary
+
     def set_diffusivity(self, D):
         _check(_lib.mifvm_set_diffusivity(self._h, float(D)))
 
@@ -361,16 +372,21 @@ class State:
         return out
 
     def set_field(self, field, t, stream=None):
+        """A float32 tensor crosses the ABI as float32, anything else as float64."""
         import torch
-        t = t.to(device=self.device, dtype=torch.float64).contiguous()
-        _check(_lib.mifvm_set_field(self._h, field, _ptr(t), _stream(stream)))
+        dt = torch.float32 if t.dtype == torch.float32 else torch.float64
+        t = t.to(device=self.device, dtype=dt).contiguous()
+        code = F32 if dt == torch.float32 else F64
+        _check(_lib.mifvm_set_field(self._h, field, _ptr(t), code, _stream(stream)))
         (stream or torch.cuda.current_stream()).synchronize()   # t may be a temporary
 
-    def get_field(self, field, stream=None):
+    def get_field(self, field, stream=None, dtype=None):
         import torch
+        dtype = dtype or torch.float64
         n = self.mesh.info.nc * (3 if field in (FIELD_VEL, FIELD_EFIELD) else 1)
-        out = torch.empty(n, dtype=torch.float64, device=self.device)
-        _check(_lib.mifvm_get_field(self._h, field, _ptr(out), _stream(stream)))
+        out = torch.empty(n, dtype=dtype, device=self.device)
+        code = F32 if dtype == torch.float32 else F64
+        _check(_lib.mifvm_get_field(self._h, field, _ptr(out), code, _stream(stream)))
         return out
 
     # -- step ------------------------------------------------------------------

@@ -54,6 +54,9 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.gowner = carve<int32_t>(base, off, nb);
     d.gtag = carve<int32_t>(base, off, nb);
     d.gdist = carve<double>(base, off, nb);
+    d.gbtri = carve<int32_t>(base, off, nb);
+    d.gval = carve<double>(base, off, 2 * nb);
+    d.gval32 = carve<float>(base, off, nb);
     d.n_off = carve<int64_t>(base, off, m.node.off.size());
     d.n_w = carve<int32_t>(base, off, m.node.width.size());
     d.n_idx = carve<int32_t>(base, off, m.node.idx.size());
@@ -148,6 +151,22 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     return (off + 255) & ~size_t(255);
 }
 
+void drop_graphs(State& s) {
+    hipGraphExec_t* execs[] = {&s.cg_exec, &s.step_exec, &s.fcg_exec, &s.gm_exec, &s.amg_exec};
+    for (hipGraphExec_t* e : execs) {
+        if (*e) (void)hipGraphExecDestroy(*e);
+        *e = nullptr;
+    }
+    s.cg_exec_chunk = 0;
+    s.cg_exec_method = -1;
+    s.step_exec_n = 0;
+    s.step_exec_dt = -1.0;
+    s.step_exec_cfl = -1.0;
+    s.fcg_exec_chunk = 0;
+    s.gm_exec_key = 0;
+    s.amg_exec_key = 0;
+}
+
 }  // namespace mifvm
 
 using namespace mifvm;
@@ -185,7 +204,8 @@ int mifvm_mesh_preprocess(const double* xyz, int64_t nv, const int32_t* tets, in
     int rc;
     try {
         rc = preprocess(xyz, nv, tets, nc, btris, btags, nb, opts ? opts->renumber : 1,
-                        opts ? opts->mesh_cell_start : nullptr, opts ? opts->nmeshes : 1, h->m, err);
+                        opts ? opts->mesh_cell_start : nullptr, opts ? opts->nmeshes : 1,
+                        opts && opts->no_matrix != 0, h->m, err);
     } catch (const std::bad_alloc&) {
         rc = MIFVM_E_ARG;
         err = "out of host memory";
@@ -289,11 +309,14 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
         delete h;
         return fail(MIFVM_E_ARG, "unknown precision");
     }
-    for (int v = 0; v < 2; ++v)
+    for (int v = 0; v < 2; ++v) {
         for (int t = 0; t < kMaxTags; ++t) {
             st.bc[v].kind[t] = kZeroFlux;
-            st.bc[v].value[t] = 0.0;
+            st.bc_tag_value[v][t] = 0.0;
         }
+        st.bc[v].val = st.d.gval + v * m.nb;
+        st.bc[v].val32 = v == 0 ? st.d.gval32 : nullptr;
+    }
     st.nblk_cells = reduce_blocks(m.nc);
     hipStream_t s = S(stream);
     const Dev& d = st.d;
@@ -313,7 +336,7 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     UP(d.s_off, m.stencil.off); UP(d.s_w, m.stencil.width); UP(d.s_idx, m.stencil.idx);
     UP(d.fL, m.fL); UP(d.fR, m.fR); UP(d.fA, m.fA); UP(d.fB, m.fB); UP(d.fC, m.fC);
     UP(d.kAC, m.kAC); UP(d.kBC, m.kBC); UP(d.kRL, m.kRL); UP(d.fx, m.fx); UP(d.S, m.S); UP(d.area, m.area);
-    UP(d.gowner, m.gowner); UP(d.gtag, m.gtag); UP(d.gdist, m.gdist);
+    UP(d.gowner, m.gowner); UP(d.gtag, m.gtag); UP(d.gdist, m.gdist); UP(d.gbtri, m.gbtri);
     UP(d.n_off, m.node.off); UP(d.n_w, m.node.width); UP(d.n_idx, m.node.idx); UP(d.n_alpha, m.node.val);
     UP(d.n_len, m.n_len); UP(d.e_off, m.enbr.off); UP(d.e_w, m.enbr.width); UP(d.e_lidx, m.e_lidx);
     UP(d.c2v_l, m.c2v_l); UP(d.fv_off, m.fv_off); UP(d.fv_len, m.fv_len);
@@ -358,6 +381,8 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     if (e == hipSuccess) e = hipMemsetAsync(d.u32, 0, NX * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.src32, 0, m.nc * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.phi32, 0, m.nf * sizeof(float), s);
+    if (e == hipSuccess && m.nb > 0) e = hipMemsetAsync(d.gval, 0, 2 * m.nb * sizeof(double), s);
+    if (e == hipSuccess && m.nb > 0) e = hipMemsetAsync(d.gval32, 0, m.nb * sizeof(float), s);
     if (e == hipSuccess) e = setup_fv_kernels(d);
     if (e == hipSuccess) e = launch_make_fp32_geometry(d, (int64_t)m.node.val.size(), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // host vectors are not pinned
@@ -368,10 +393,7 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
 
 void mifvm_state_destroy(mifvm_state* st) {
     if (!st) return;
-    if (st->s.cg_exec) (void)hipGraphExecDestroy(st->s.cg_exec);
-    if (st->s.step_exec) (void)hipGraphExecDestroy(st->s.step_exec);
-    if (st->s.fcg_exec) (void)hipGraphExecDestroy(st->s.fcg_exec);
-    if (st->s.gm_exec) (void)hipGraphExecDestroy(st->s.gm_exec);
+    drop_graphs(st->s);
     amg_release(st->s);
     delete st->s.gm;
     delete st->s.nn_state;
@@ -411,9 +433,32 @@ int mifvm_set_bc(mifvm_state* st, int32_t var, int32_t tag, int32_t kind, double
     if (tag < 0 || tag >= kMaxTags) return fail(MIFVM_E_ARG, "tag out of range");
     if (kind < 0 || kind > 2) return fail(MIFVM_E_ARG, "unknown boundary-condition kind");
     if (!std::isfinite(value)) return fail(MIFVM_E_ARG, "non-finite boundary value");
-    st->s.bc[var].kind[tag] = kind;
-    st->s.bc[var].value[tag] = value;
-    if (var == MIFVM_VAR_POTENTIAL) st->s.assembled = false;
+    State& s = st->s;
+    // the value goes to every ghost of the tag in device memory, ordered
+    // against work on any stream (this call has no stream argument)
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(launch_set_bc_values(s.d, var, tag, value, nullptr, nullptr));
+    HIPCHK(hipDeviceSynchronize());
+    s.bc[var].kind[tag] = kind;
+    s.bc_tag_value[var][tag] = value;
+    drop_graphs(s);                           // captured launches hold the kinds by value
+    if (var == MIFVM_VAR_POTENTIAL) {
+        s.assembled = false;
+        s.consts_ready = false;
+    }
+    return MIFVM_OK;
+}
+
+int mifvm_set_bc_values(mifvm_state* st, int32_t var, int32_t tag, const double* d_vals, void* stream) {
+    if (!st || !d_vals) return fail(MIFVM_E_ARG, "null argument");
+    if (var < 0 || var > 1) return fail(MIFVM_E_ARG, "unknown variable");
+    if (tag < 0 || tag >= kMaxTags) return fail(MIFVM_E_ARG, "tag out of range");
+    State& s = st->s;
+    HIPCHK(launch_set_bc_values(s.d, var, tag, 0.0, d_vals, S(stream)));
+    if (var == MIFVM_VAR_POTENTIAL) {         // the ghost constants c of the system change
+        s.assembled = false;
+        s.consts_ready = false;
+    }
     return MIFVM_OK;
 }
 
@@ -441,31 +486,39 @@ int mifvm_set_mesh_diffusivity(mifvm_state* st, const double* D, int32_t n) {
     return upload_mesh_D(st->s, std::vector<double>(D, D + n));
 }
 
-int mifvm_set_field(mifvm_state* st, int32_t field, const double* d_src, void* stream) {
+int mifvm_set_field(mifvm_state* st, int32_t field, const void* d_src, int32_t dtype, void* stream) {
     if (!st || !d_src) return fail(MIFVM_E_ARG, "null argument");
+    if (dtype != MIFVM_F64 && dtype != MIFVM_F32) return fail(MIFVM_E_ARG, "unknown dtype");
     State& s = st->s;
     const Dev& d = s.d;
     hipStream_t hs = S(stream);
+    const bool f32 = dtype == MIFVM_F32;
+    auto in64 = [&](int comps, double* dst) { return launch_to_internal_typed(d.cell_perm, d.nc, comps, d_src, f32, dst, false, hs); };
     switch (field) {
         case MIFVM_FIELD_U:
-            HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.u, hs));
-            if (s.fp32) HIPCHK(launch_cast_to_f32(d.nc, d.u, d.u32, hs));
+            if (s.fp32 && f32) {                  // FP32 state from FP32 data: no rounding on the way
+                HIPCHK(launch_to_internal_typed(d.cell_perm, d.nc, 1, d_src, true, d.u32, true, hs));
+                HIPCHK(launch_cast_to_f64(d.nc, d.u32, d.u, hs));
+            } else {
+                HIPCHK(in64(1, d.u));
+                if (s.fp32) HIPCHK(launch_cast_to_f32(d.nc, d.u, d.u32, hs));
+            }
             HIPCHK(launch_ghost_fill(d, s.fp32, s.bc[0], hs));
             break;
         case MIFVM_FIELD_VEL:
-            HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 3, d_src, d.vel, hs));
+            HIPCHK(in64(3, d.vel));
             HIPCHK(launch_face_phi(d, hs));
             s.vel_set = true;
             break;
         case MIFVM_FIELD_SOURCE:
-            HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.src, hs));
+            HIPCHK(in64(1, d.src));
             HIPCHK(launch_cast_to_f32(d.nc, d.src, d.src32, hs));
             break;
         case MIFVM_FIELD_P:
-            HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.x, hs));
+            HIPCHK(in64(1, d.x));
             break;
         case MIFVM_FIELD_ION:
-            HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_src, d.np_ion, hs));
+            HIPCHK(in64(1, d.np_ion));
             break;
         case MIFVM_FIELD_EFIELD:
             return fail(MIFVM_E_ARG, "FIELD_EFIELD is computed by mifvm_streamer_step (get only)");
@@ -475,26 +528,23 @@ int mifvm_set_field(mifvm_state* st, int32_t field, const double* d_src, void* s
     return MIFVM_OK;
 }
 
-int mifvm_get_field(const mifvm_state* st, int32_t field, double* d_dst, void* stream) {
+int mifvm_get_field(const mifvm_state* st, int32_t field, void* d_dst, int32_t dtype, void* stream) {
     if (!st || !d_dst) return fail(MIFVM_E_ARG, "null argument");
+    if (dtype != MIFVM_F64 && dtype != MIFVM_F32) return fail(MIFVM_E_ARG, "unknown dtype");
     const Dev& d = st->s.d;
     hipStream_t hs = S(stream);
+    const bool f32 = dtype == MIFVM_F32;
+    auto out64 = [&](int comps, const double* src) { return launch_to_user_typed(d.cell_perm, d.nc, comps, src, false, d_dst, f32, hs); };
     switch (field) {
         case MIFVM_FIELD_U:
-            if (st->s.fp32) {
-                HIPCHK(launch_cast_to_f64(d.nc, d.u32, d.tmp, hs));
-                HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.tmp, d_dst, hs));
-            } else {
-                HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.u, d_dst, hs));
-            }
+            if (st->s.fp32) HIPCHK(launch_to_user_typed(d.cell_perm, d.nc, 1, d.u32, true, d_dst, f32, hs));
+            else HIPCHK(out64(1, d.u));
             break;
-        case MIFVM_FIELD_VEL: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 3, d.vel, d_dst, hs)); break;
-        case MIFVM_FIELD_SOURCE: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.src, d_dst, hs)); break;
-        case MIFVM_FIELD_P: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.x, d_dst, hs)); break;
-        case MIFVM_FIELD_ION: HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.np_ion, d_dst, hs)); break;
-        case MIFVM_FIELD_EFIELD:
-            HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 3, d.efield, d_dst, hs));
-            break;
+        case MIFVM_FIELD_VEL: HIPCHK(out64(3, d.vel)); break;
+        case MIFVM_FIELD_SOURCE: HIPCHK(out64(1, d.src)); break;
+        case MIFVM_FIELD_P: HIPCHK(out64(1, d.x)); break;
+        case MIFVM_FIELD_ION: HIPCHK(out64(1, d.np_ion)); break;
+        case MIFVM_FIELD_EFIELD: HIPCHK(out64(3, d.efield)); break;
         default: return fail(MIFVM_E_ARG, "unknown field");
     }
     return MIFVM_OK;
@@ -575,10 +625,11 @@ int mifvm_step_graph(mifvm_state* st, int32_t n_steps, double dt, void* stream) 
     State& s = st->s;
     if (dt == 0.0 && !(s.cfl > 0)) return fail(MIFVM_E_STATE, "dt = 0 asks for the CFL steps: call mifvm_cfl_dt first");
     if (n_steps == 0) return MIFVM_OK;
-    if (s.step_exec == nullptr || s.step_exec_n != n_steps || s.step_exec_dt != dt) {
+    if (s.step_exec == nullptr || s.step_exec_n != n_steps || s.step_exec_dt != dt || s.step_exec_cfl != s.cfl) {
         HIPCHK(capture_graph(s, &s.step_exec, [&](hipStream_t q) { return enqueue_steps(s, n_steps, dt, q); }));
         s.step_exec_n = n_steps;
         s.step_exec_dt = dt;
+        s.step_exec_cfl = s.cfl;
     }
     HIPCHK(hipGraphLaunch(s.step_exec, S(stream)));
     return MIFVM_OK;
@@ -660,14 +711,32 @@ int mifvm_conservation(mifvm_state* st, double* total_out, void* stream) {
     return MIFVM_OK;
 }
 
+namespace {
+bool has_matrix(const State& s) { return !s.mesh->kmat.off.empty(); }
+
+// the diagonal, D^-1 and the ghost constants c of the current potential
+// BCs, which every solve needs; the matrix-free solves need nothing else
+int ensure_consts(State& s, hipStream_t hs) {
+    if (s.assembled || s.consts_ready) return MIFVM_OK;
+    HIPCHK(timed(s.timer, MIFVM_K_ASSEMBLE, hs, [&] { return launch_assemble_consts(s.d, s.bc[1], hs); }));
+    s.consts_ready = true;
+    s.k32_ready = false;                      // the FP32 copies of the diagonal follow it
+    return MIFVM_OK;
+}
+}  // namespace
+
 int mifvm_poisson_assemble(mifvm_state* st, void* stream) {
     if (!st) return fail(MIFVM_E_ARG, "null state");
     State& s = st->s;
+    if (!has_matrix(s))
+        return fail(MIFVM_E_STATE, "mesh preprocessed without the Poisson matrix (no_matrix): matrix-free solves only");
     hipStream_t hs = S(stream);
     HIPCHK(timed(s.timer, MIFVM_K_ASSEMBLE, hs, [&] { return launch_assemble(s.d, s.bc[1], s.mesh->row_max, hs); }));
     s.assembled = true;
+    s.consts_ready = true;
     s.k32_ready = false;
     s.kt_ready = false;
+    drop_graphs(s);
     return MIFVM_OK;
 }
 
@@ -715,9 +784,10 @@ int rhs_internal(State& s, const double* d_f, hipStream_t hs, const double* f_in
 int mifvm_poisson_rhs(mifvm_state* st, const double* d_f, double* d_b, void* stream) {
     if (!st || !d_b) return fail(MIFVM_E_ARG, "null argument");
     State& s = st->s;
-    if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
     hipStream_t hs = S(stream);
-    int rc = rhs_internal(s, d_f, hs);
+    int rc = ensure_consts(s, hs);
+    if (rc) return rc;
+    rc = rhs_internal(s, d_f, hs);
     if (rc) return rc;
     HIPCHK(launch_to_user(s.d.cell_perm, s.d.nc, s.d.nc, s.d.nc, 1, s.d.b, d_b, hs));
     return MIFVM_OK;
@@ -738,7 +808,6 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
                mifvm_solve_info* info, void* stream) {
     if (!st) return fail(MIFVM_E_ARG, "null state");
     State& s = st->s;
-    if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
     const double tol = opts ? opts->tol : 1e-10;
     const int maxit = opts ? opts->maxit : 20000;
     const int chunk = opts && opts->chunk > 0 ? opts->chunk : (s.tuned_chunk > 0 ? s.tuned_chunk : 32);
@@ -766,6 +835,9 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
         if (s.d.nm != 1) return fail(MIFVM_E_ARG, "method FGMRES needs a single-mesh state");
     }
     const bool matrix_free = opts && opts->matrix_free != 0;
+    // the stored K is read by every solve that does not apply K matrix-free,
+    // and by the multigrid hierarchy (built from it)
+    if (!matrix_free && !s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
     const int stall_window = opts ? opts->stall_window : 0;
     const int learned_maxit = opts ? opts->learned_maxit : 0;
     if (stall_window < 0 || learned_maxit < 0) return fail(MIFVM_E_ARG, "bad stall_window or learned_maxit");
@@ -778,7 +850,9 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
     hipStream_t hs = S(stream);
     s.mf = matrix_free;
     auto t0 = std::chrono::steady_clock::now();
-    int rc = rhs_internal(s, d_f, hs, f_internal);
+    int rc = ensure_consts(s, hs);
+    if (rc) return rc;
+    rc = rhs_internal(s, d_f, hs, f_internal);
     if (rc) return rc;
     KernelTimer& tm = s.timer;
     int nhist = 0;
@@ -904,7 +978,15 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
     } else if (method == MIFVM_SOLVE_LEARNED && !learned.fell_back) {
         // the flexible CG ended: converged, or at maxit
     } else if (run_method == MIFVM_SOLVE_PLAIN) {
-        HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, budget, restart, true, hs); }));
+        // r = b - K x with K x from the matrix-free product or the stored K
+        auto setup = [&](int limit, bool fresh) -> hipError_t {
+            if (matrix_free) {
+                hipError_t e = launch_mf_apply(d, s.bc[1], d.x, d.tmp, hs);
+                if (e != hipSuccess) return e;
+            }
+            return launch_cg_setup(d, tol, limit, restart, fresh, hs, matrix_free ? d.tmp : nullptr);
+        };
+        HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return setup(budget, true); }));
         if ((rc = pull())) return rc;
         while (any_running()) {
             while (any_running()) {
@@ -913,7 +995,7 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
             }
             // every mesh's recurrence converged, reached its limit or is due a
             // restart: recompute the true residual r = b - K x (FP64) and reopen
-            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_cg_setup(d, tol, maxit, restart, false, hs); }));
+            HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return setup(maxit, false); }));
             if ((rc = pull())) return rc;
             if (any_running()) ++restarts;
         }
@@ -985,7 +1067,7 @@ int mifvm_streamer_step(mifvm_state* st, int32_t n_steps, const mifvm_streamer_o
         opts->maxit < 0 || opts->restart < 0)
         return fail(MIFVM_E_ARG, "bad streamer options");
     if (s.fp32) return fail(MIFVM_E_STATE, "the coupled loop runs on FP64 states");
-    if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
+    if (!opts->matrix_free && !s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
     const Dev& d = s.d;
     hipStream_t hs = S(stream);
     mifvm_solve_opts so{};

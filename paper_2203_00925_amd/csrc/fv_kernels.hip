@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_ghost_fill(int64_t nc, int64_t nb,
     if (g >= nb) return;
     const int t = gtag[g];
     const int kind = bc.kind[t];
-    const R val = R(bc.value[t]);
+    const R val = bc_value<R>(bc, g);
     const R uo = u[gowner[g]];
     R ug;
     if (kind == kDirichlet) ug = R(2) * val - uo;
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTa
     if (f >= d.nfi) {
         const int t = d.gtag[f - d.nfi];
         kind = bc.kind[t];
-        val = R(bc.value[t]);
+        val = bc_value<R>(bc, f - d.nfi);
     }
     if (kind == kZeroFlux) {
         a.flux[f] = R(0);
@@ -523,22 +523,37 @@ __global__ __launch_bounds__(kBlock) void k_cast_to_f64(int64_t n, const float* 
     if (i < n) dst[i] = double(src[i]);
 }
 
+// caller order <-> internal order (perm: internal -> caller), converting
+// the element type on the way (FP64 <-> FP32 rounds to nearest)
+template <class Tin, class Tout>
 __global__ __launch_bounds__(kBlock) void k_to_internal(const int32_t* __restrict__ perm, int64_t n,
                                                          int64_t sin, int64_t sout, int comps,
-                                                         const double* __restrict__ src, double* dst) {
+                                                         const Tin* __restrict__ src, Tout* dst) {
     const int64_t i = gtid();
     if (i >= n) return;
     const int64_t o = perm[i];
-    for (int c = 0; c < comps; ++c) dst[c * sout + i] = src[c * sin + o];
+    for (int c = 0; c < comps; ++c) dst[c * sout + i] = Tout(src[c * sin + o]);
 }
 
+template <class Tin, class Tout>
 __global__ __launch_bounds__(kBlock) void k_to_user(const int32_t* __restrict__ perm, int64_t n,
                                                      int64_t sin, int64_t sout, int comps,
-                                                     const double* __restrict__ src, double* dst) {
+                                                     const Tin* __restrict__ src, Tout* dst) {
     const int64_t i = gtid();
     if (i >= n) return;
     const int64_t o = perm[i];
-    for (int c = 0; c < comps; ++c) dst[c * sout + o] = src[c * sin + i];
+    for (int c = 0; c < comps; ++c) dst[c * sout + o] = Tout(src[c * sin + i]);
+}
+
+// boundary values of variable var at every ghost whose face carries `tag`:
+// the constant `value`, or vals[the caller's boundary triangle of the ghost]
+__global__ __launch_bounds__(kBlock) void k_set_bc_values(Dev d, int var, int tag, double value,
+                                                           const double* __restrict__ vals) {
+    const int64_t g = gtid();
+    if (g >= d.nb || d.gtag[g] != tag) return;
+    const double v = vals ? vals[d.gbtri[g]] : value;
+    d.gval[var * d.nb + g] = v;
+    if (var == 0) d.gval32[g] = float(v);
 }
 
 // dt bound of mesh m: min_i mu_i / sum_{active faces} (|phi_f| + D_m kRL_f),
@@ -702,17 +717,55 @@ hipError_t launch_cast_to_f64(int64_t n, const float* src, double* dst, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_to_internal(const int32_t* perm, int64_t n, int64_t sin, int64_t sout, int comps,
-                              const double* src, double* dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_to_internal, dim3(grid_for(n)), dim3(kBlock), 0, s, perm, n, sin, sout, comps,
+template <class Tin, class Tout>
+hipError_t to_internal_t(const int32_t* perm, int64_t n, int64_t sin, int64_t sout, int comps, const Tin* src,
+                         Tout* dst, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_to_internal<Tin, Tout>), dim3(grid_for(n)), dim3(kBlock), 0, s, perm, n, sin, sout,
+                       comps, src, dst);
+    return hipGetLastError();
+}
+
+template <class Tin, class Tout>
+hipError_t to_user_t(const int32_t* perm, int64_t n, int64_t sin, int64_t sout, int comps, const Tin* src,
+                     Tout* dst, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_to_user<Tin, Tout>), dim3(grid_for(n)), dim3(kBlock), 0, s, perm, n, sin, sout, comps,
                        src, dst);
     return hipGetLastError();
 }
 
+hipError_t launch_to_internal(const int32_t* perm, int64_t n, int64_t sin, int64_t sout, int comps,
+                              const double* src, double* dst, hipStream_t s) {
+    return to_internal_t(perm, n, sin, sout, comps, src, dst, s);
+}
+
 hipError_t launch_to_user(const int32_t* perm, int64_t n, int64_t sin, int64_t sout, int comps,
                           const double* src, double* dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_to_user, dim3(grid_for(n)), dim3(kBlock), 0, s, perm, n, sin, sout, comps, src,
-                       dst);
+    return to_user_t(perm, n, sin, sout, comps, src, dst, s);
+}
+
+hipError_t launch_to_internal_typed(const int32_t* perm, int64_t n, int comps, const void* src, bool src_f32,
+                                    void* dst, bool dst_f32, hipStream_t s) {
+    if (src_f32)
+        return dst_f32 ? to_internal_t(perm, n, n, n, comps, (const float*)src, (float*)dst, s)
+                       : to_internal_t(perm, n, n, n, comps, (const float*)src, (double*)dst, s);
+    return dst_f32 ? to_internal_t(perm, n, n, n, comps, (const double*)src, (float*)dst, s)
+                   : to_internal_t(perm, n, n, n, comps, (const double*)src, (double*)dst, s);
+}
+
+hipError_t launch_to_user_typed(const int32_t* perm, int64_t n, int comps, const void* src, bool src_f32,
+                                void* dst, bool dst_f32, hipStream_t s) {
+    if (src_f32)
+        return dst_f32 ? to_user_t(perm, n, n, n, comps, (const float*)src, (float*)dst, s)
+                       : to_user_t(perm, n, n, n, comps, (const float*)src, (double*)dst, s);
+    return dst_f32 ? to_user_t(perm, n, n, n, comps, (const double*)src, (float*)dst, s)
+                   : to_user_t(perm, n, n, n, comps, (const double*)src, (double*)dst, s);
+}
+
+hipError_t launch_set_bc_values(const Dev& d, int var, int tag, double value, const double* vals, hipStream_t s) {
+    if (d.nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_bc_values, dim3(grid_for(d.nb)), dim3(kBlock), 0, s, d, var, tag, value, vals);
     return hipGetLastError();
 }
 

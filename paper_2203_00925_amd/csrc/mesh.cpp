@@ -116,7 +116,8 @@ void pack_sell(const std::vector<int64_t>& ptr, const std::vector<int32_t>& idx,
 
 int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
                const int32_t* btris, const int32_t* btags, int64_t nb_in,
-               int renumber, const int64_t* mesh_cell_start, int32_t nmeshes, Mesh& M, std::string& err) {
+               int renumber, const int64_t* mesh_cell_start, int32_t nmeshes, bool no_matrix, Mesh& M,
+               std::string& err) {
     const int E_ARG = -1, E_MESH = -2;
     if (!xyz || !tets || nv <= 0 || nc <= 0 || nb_in < 0 || (nb_in > 0 && (!btris || !btags))) {
         err = "null pointer or non-positive size";
@@ -332,6 +333,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
         int32_t a, b, c;
         int32_t L, R;   // user cells; R = -1 on the boundary
         int32_t tag;
+        int32_t bidx;   // index of the caller's boundary triangle (boundary faces)
     };
     std::vector<UFace> uf;
     uf.reserve(2 * nc + nb_in);
@@ -343,7 +345,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             err = "a face is shared by cells of two different meshes";
             return E_MESH;
         }
-        uf.push_back({rec[i].a, rec[i].b, rec[i].c, rec[i].owner, j - i == 2 ? rec[i + 1].owner : -1, -1});
+        uf.push_back({rec[i].a, rec[i].b, rec[i].c, rec[i].owner, j - i == 2 ? rec[i + 1].owner : -1, -1, -1});
         i = j;
     }
     rec.clear();
@@ -367,6 +369,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
         }
         if (it->tag >= 0) { err = "boundary face tagged twice"; return E_MESH; }
         it->tag = btags[i];
+        it->bidx = (int32_t)i;
     }
     int64_t nb = 0, nfi = 0;
     for (auto& f : uf) {
@@ -429,7 +432,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     M.fL.resize(nf); M.fR.resize(nf); M.fA.resize(nf); M.fB.resize(nf); M.fC.resize(nf);
     M.kAC.resize(nf); M.kBC.resize(nf); M.kRL.resize(nf); M.area.resize(nf);
     M.fx.resize(3 * nf); M.S.resize(3 * nf);
-    M.gowner.resize(nb); M.gtag.resize(nb); M.gdist.resize(nb);
+    M.gowner.resize(nb); M.gtag.resize(nb); M.gdist.resize(nb); M.gbtri.resize(nb);
     for (int64_t f = 0; f < nf; ++f) {
         const UFace& u = uf[ford[f]];
         V3 A = P(u.a), B = P(u.b), C = P(u.c);
@@ -450,6 +453,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             xR = add(xL, scale(nh, 2.0 * dot(sub(xf, xL), nh)));
             M.gowner[g] = L;
             M.gtag[g] = u.tag;
+            M.gbtri[g] = u.bidx;
             V3 d = sub(xR, xL);
             M.gdist[g] = std::sqrt(dot(d, d));
             M.xc[nc + g] = xR.x; M.xc[NX + nc + g] = xR.y; M.xc[2 * NX + nc + g] = xR.z;
@@ -616,7 +620,8 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
     pack_sell(M.sptr, M.sidx, nullptr, nullptr, nc, [](int64_t r) { return (int32_t)r; }, M.stencil);
     pack_sell(M.nptr, M.nidx, &M.nalpha, nullptr, nv,
               [&](int64_t r) { return M.nidx[M.nptr[r]]; }, M.node);
-    pack_sell(M.sptr, M.sidx, nullptr, &M.klen, nc, [](int64_t r) { return (int32_t)r; }, M.kmat);
+    if (!no_matrix)
+        pack_sell(M.sptr, M.sidx, nullptr, &M.klen, nc, [](int64_t r) { return (int32_t)r; }, M.kmat);
     pack_sell(M.eptr, M.eidx, nullptr, nullptr, nc, [](int64_t r) { return (int32_t)r; }, M.enbr);
 
     mark("slicing");
@@ -688,7 +693,7 @@ int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
             for (int64_t r = t0; r < t1; ++r) {
                 const int64_t sl = r >> 6;
                 const int lane = int(r & 63);
-                for (int64_t k = 0; k < M.kmat.width[sl]; ++k) {
+                for (int64_t k = 0; !no_matrix && k < M.kmat.width[sl]; ++k) {
                     const int64_t at = M.kmat.off[sl] + k * 64 + lane;
                     M.k_lidx[at] = (uint16_t)g2l[M.kmat.idx[at]];
                 }

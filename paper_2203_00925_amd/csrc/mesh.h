@@ -37,6 +37,7 @@ struct Mesh {
     // ghosts
     std::vector<int32_t> gowner, gtag;
     std::vector<double> gdist;
+    std::vector<int32_t> gbtri;       // ghost -> index of the caller's boundary triangle
     // cell -> faces (f if the cell is L, ~f if R) and cell across each face
     std::vector<int32_t> c2f, c2n;    // 4 x nc
     // CSR forms (for export/tests) and packed forms (for the device)
@@ -47,6 +48,7 @@ struct Mesh {
     Sell64 stencil;                   // node-neighbour stencil, pad = the row itself
     Sell64 node;                      // vertex lists + weights, pad = first entry, weight 0
     Sell64 kmat;                      // Poisson off-diagonal pattern, pad = the row itself
+                                      // (empty when preprocessed with no_matrix)
     std::vector<int32_t> klen;        // off-diagonal entries per row (sorted prefix)
     // Tiles of `tile_rows` consecutive cells (a multiple of 64).  Each tile's
     // halo is the sorted set of cells and ghosts its stencils reference
@@ -93,6 +95,7 @@ struct Mesh {
 // into independent meshes; each must have at least 256 cells when nmeshes > 1.
 int preprocess(const double* xyz, int64_t nv, const int32_t* tets, int64_t nc,
                const int32_t* btris, const int32_t* btags, int64_t nb,
-               int renumber, const int64_t* mesh_cell_start, int32_t nmeshes, Mesh& out, std::string& err);
+               int renumber, const int64_t* mesh_cell_start, int32_t nmeshes, bool no_matrix, Mesh& out,
+               std::string& err);
 
 }  // namespace mifvm

@@ -117,7 +117,9 @@ hipError_t launch_nn_adam(const NnDev& n, int nblocks, int apply, float lr, floa
 // r = b - K x, its scales, out = r / s_r in FP32 (a training sample)
 hipError_t launch_nn_sample(const Dev& d, float* out, hipStream_t s);
 // flexible CG steps
-hipError_t launch_fcg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s);
+// kx: K x computed matrix-free by the caller, or null for the stored K
+hipError_t launch_fcg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s,
+                            const double* kx = nullptr);
 hipError_t launch_fcg_setup_tail(const Dev& d, hipStream_t s);
 hipError_t launch_fcg_axpy(const Dev& d, const NnStateDev& a, hipStream_t s);
 hipError_t launch_fcg_beta(const Dev& d, hipStream_t s);

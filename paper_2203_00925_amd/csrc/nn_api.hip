@@ -96,7 +96,9 @@ int put_params(mifvm_nn* nn, const float* p, hipStream_t hs) {
 int need_attached(const State& s, bool training) {
     if (!s.nn || !s.nn_state) return fail(MIFVM_E_STATE, "no network attached to this state");
     if (training && !s.nn_state->training) return fail(MIFVM_E_STATE, "the network is attached without training buffers");
-    if (!s.assembled) return fail(MIFVM_E_STATE, "poisson system not assembled");
+    // inference reads D^-1 only; training reads K
+    if (training ? !s.assembled : !(s.assembled || s.consts_ready))
+        return fail(MIFVM_E_STATE, "poisson system not assembled");
     return MIFVM_OK;
 }
 
@@ -172,7 +174,13 @@ int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int s
     const int window = stall_window > 0 ? stall_window : 200;
     out = LearnedRun{};
     auto setup = [&](bool fresh) -> int {
-        HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&] { return launch_fcg_setup(d, tol, limit, restart, fresh, hs); }));
+        HIPCHK(timed(tm, MIFVM_K_CG_SETUP, hs, [&]() -> hipError_t {
+            if (s.mf) {                               // K x by the matrix-free product
+                hipError_t e = launch_mf_apply(d, s.bc[1], d.x, d.tmp, hs);
+                if (e != hipSuccess) return e;
+            }
+            return launch_fcg_setup(d, tol, limit, restart, fresh, hs, s.mf ? d.tmp : nullptr);
+        }));
         HIPCHK(fcg_forward(s, hs, true));
         HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_setup_tail(d, hs); }));
         return pull();

@@ -877,14 +877,15 @@ __global__ __launch_bounds__(256) void k_nn_transpose(Dev d, double* kt, int32_t
 }
 
 // ---- flexible CG ------------------------------------------------------------------
-// r = b - K x; partial rr, bb, dd
-__global__ __launch_bounds__(256) void k_fcg_setup(Dev d) {
+// r = b - K x (kx: K x computed matrix-free, or null for the stored K);
+// partial rr, bb, dd
+__global__ __launch_bounds__(256) void k_fcg_setup(Dev d, const double* __restrict__ kx) {
     __shared__ double lds[4];
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     double a = 0.0, b = 0.0, c = 0.0;
     if (i < d.nc) {
         const double bi = d.b[i];
-        const double ri = bi - row_dot(d, d.k_val, d.x, i);
+        const double ri = bi - (kx ? kx[i] : row_dot(d, d.k_val, d.x, i));
         d.r[i] = ri;
         const double q = d.k_dinv[i] * ri;
         a = ri * ri;
@@ -1124,16 +1125,17 @@ hipError_t launch_nn_adam(const NnDev& n, int nblocks, int apply, float lr, floa
 
 hipError_t launch_nn_sample(const Dev& d, float* out, hipStream_t s) {
     const unsigned nb = rows256(d.nc);
-    hipLaunchKernelGGL(k_fcg_setup, dim3(nb), dim3(256), 0, s, d);      // r = b - K x (partials unused)
+    hipLaunchKernelGGL(k_fcg_setup, dim3(nb), dim3(256), 0, s, d, (const double*)nullptr);   // r = b - K x (partials unused)
     hipLaunchKernelGGL(k_nn_scale<false>, dim3(nb), dim3(256), 0, s, d, d.r, nullptr);
     hipLaunchKernelGGL(k_nn_scale_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb));
     hipLaunchKernelGGL(k_nn_sample_out, dim3(nb), dim3(256), 0, s, d, out);
     return hipGetLastError();
 }
 
-hipError_t launch_fcg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s) {
+hipError_t launch_fcg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s,
+                            const double* kx) {
     const unsigned nb = rows256(d.nc);
-    hipLaunchKernelGGL(k_fcg_setup, dim3(nb), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(k_fcg_setup, dim3(nb), dim3(256), 0, s, d, kx);
     hipLaunchKernelGGL(k_fcg_setup_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nb), tol, maxit, restart,
                        fresh ? 1 : 0);
     return hipGetLastError();

@@ -22,16 +22,20 @@ inline int grid_rows(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 // flux that only enters c.  One thread per row, 64-thread blocks, the row's
 // accumulators in LDS ([entry][lane] so lanes hit distinct banks); each row
 // is summed by one thread in a fixed order (deterministic, no atomics).
+// FULL = false computes only the diagonal, D^-1 and c (the same sums in the
+// same order, the off-diagonal coefficients dropped): what the matrix-free
+// solves need, without the stored pattern.
+template <bool FULL>
 __global__ __launch_bounds__(64) void k_assemble(Dev d, BcTable bc) {
-    extern __shared__ double acc[];                       // [row_max][64]
+    extern __shared__ double acc[];                       // [row_max][64] (FULL)
     const int lane = threadIdx.x;
     const int64_t i = int64_t(blockIdx.x) * 64 + lane;
     const int64_t nc = d.nc;
     if (i >= nc) return;
     const int64_t s = i >> 6;
-    const int32_t* __restrict__ cols = d.k_col + d.k_off[s] + (i & 63);
-    const int len = d.k_len[i];
-    const int w = d.k_w[s];
+    const int32_t* __restrict__ cols = FULL ? d.k_col + d.k_off[s] + (i & 63) : nullptr;
+    const int len = FULL ? d.k_len[i] : 0;
+    const int w = FULL ? d.k_w[s] : 0;
     for (int k = 0; k < len; ++k) acc[k * 64 + lane] = 0.0;
     double diag = 0.0, cconst = 0.0;
 
@@ -40,7 +44,7 @@ __global__ __launch_bounds__(64) void k_assemble(Dev d, BcTable bc) {
             const int g = e - int(nc);
             const int t = d.gtag[g];
             const int kind = bc.kind[t];
-            const double val = bc.value[t];
+            const double val = bc.val[g];
             const double sg = kind == kDirichlet ? -1.0 : 1.0;
             const double tg = kind == kDirichlet ? 2.0 * val : (kind == kNeumann ? val * d.gdist[g] : 0.0);
             cconst += tg * coef;
@@ -51,6 +55,7 @@ __global__ __launch_bounds__(64) void k_assemble(Dev d, BcTable bc) {
             diag += coef;
             return;
         }
+        if (!FULL) return;
         int lo = 0, hi = len - 1;                        // sorted prefix of the row
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
@@ -68,7 +73,7 @@ __global__ __launch_bounds__(64) void k_assemble(Dev d, BcTable bc) {
             const int t = d.gtag[f - d.nfi];
             const int kind = bc.kind[t];
             if (kind != kDirichlet) {
-                if (kind == kNeumann) cconst += sgn * (bc.value[t] * d.area[f]);
+                if (kind == kNeumann) cconst += sgn * (bc.val[f - d.nfi] * d.area[f]);
                 continue;
             }
         }
@@ -90,8 +95,10 @@ __global__ __launch_bounds__(64) void k_assemble(Dev d, BcTable bc) {
         add(d.fR[f], sgn * krl);
         add(d.fL[f], -sgn * krl);
     }
-    double* __restrict__ vals = d.k_val + d.k_off[s] + (i & 63);
-    for (int k = 0; k < w; ++k) vals[int64_t(k) * 64] = k < len ? -acc[k * 64 + lane] : 0.0;
+    if (FULL) {
+        double* __restrict__ vals = d.k_val + d.k_off[s] + (i & 63);
+        for (int k = 0; k < w; ++k) vals[int64_t(k) * 64] = k < len ? -acc[k * 64 + lane] : 0.0;
+    }
     d.k_diag[i] = -diag;
     d.k_dinv[i] = 1.0 / (-diag);
     d.k_c[i] = cconst;
@@ -129,14 +136,15 @@ __global__ __launch_bounds__(kBlock) void k_rhs(Dev d, const double* __restrict_
 // convergence costs only launches.
 
 // r = b - K x; z = D^-1 r; p = z; partial rz, rr, bb.  (Re)opens the loop.
-__global__ __launch_bounds__(kBlock) void k_cg_setup(Dev d) {
+// kx: K x already computed (matrix-free), or null for the stored K.
+__global__ __launch_bounds__(kBlock) void k_cg_setup(Dev d, const double* __restrict__ kx) {
     __shared__ double lds[4];
     const int64_t i = gtid_s();
     const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
     double v[3] = {0.0, 0.0, 0.0};
     if (i < d.nc) {
         const double bi = d.b[i];
-        const double ri = bi - spmv_row(d, d.x, i);
+        const double ri = bi - (kx ? kx[i] : spmv_row(d, d.x, i));
         const double zi = d.k_dinv[i] * ri;
         d.r[i] = ri;
         d.z[i] = zi;
@@ -255,7 +263,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(Dev d) {
 // ---- launchers ---------------------------------------------------------------
 hipError_t launch_assemble(const Dev& d, const BcTable& bc, int row_max, hipStream_t s) {
     const size_t lds = size_t(row_max > 0 ? row_max : 1) * 64 * sizeof(double);
-    hipLaunchKernelGGL(k_assemble, dim3(unsigned((d.nc + 63) / 64)), dim3(64), lds, s, d, bc);
+    hipLaunchKernelGGL(k_assemble<true>, dim3(unsigned((d.nc + 63) / 64)), dim3(64), lds, s, d, bc);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_consts(const Dev& d, const BcTable& bc, hipStream_t s) {
+    hipLaunchKernelGGL(k_assemble<false>, dim3(unsigned((d.nc + 63) / 64)), dim3(64), 0, s, d, bc);
     return hipGetLastError();
 }
 
@@ -269,9 +282,10 @@ hipError_t launch_rhs(const Dev& d, const double* f, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_cg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s) {
+hipError_t launch_cg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s,
+                           const double* kx) {
     const int nb = grid_rows(d.nc);
-    hipLaunchKernelGGL(k_cg_setup, dim3(nb), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_cg_setup, dim3(nb), dim3(kBlock), 0, s, d, kx);
     hipLaunchKernelGGL(k_cg_setup_fin, dim3(d.nm), dim3(1024), 0, s, d, int64_t(nb), tol, maxit, restart,
                        fresh ? 1 : 0);
     return hipGetLastError();

@@ -16,10 +16,19 @@ constexpr int kMaxTags = 32;
 constexpr int kBlock = 256;               // threads per block (4 wavefronts)
 constexpr int kZeroFlux = 0, kNeumann = 1, kDirichlet = 2;
 
-struct BcTable {                          // per-tag boundary conditions
+// Boundary conditions of one variable: the kind per tag (captured by value
+// in launches and graphs) and the value per ghost (device memory, read when
+// a kernel runs, so a graph replay sees values set after its capture).
+struct BcTable {
     int32_t kind[kMaxTags];
-    double value[kMaxTags];
+    const double* val;                    // [nb] value at each ghost's face
+    const float* val32;                   // [nb] FP32 copy (scalar variable only; else null)
 };
+
+// the value of ghost g in the precision of the kernel reading it
+template <class R> __device__ inline R bc_value(const BcTable& bc, int64_t g);
+template <> __device__ inline double bc_value<double>(const BcTable& bc, int64_t g) { return bc.val[g]; }
+template <> __device__ inline float bc_value<float>(const BcTable& bc, int64_t g) { return bc.val32[g]; }
 
 // Pointers into the workspace.  Layout: SoA, float64 unless noted, every
 // array 256-byte aligned.
@@ -42,6 +51,9 @@ struct Dev {
     double *kAC, *kBC, *kRL, *fx, *S, *area;   // fx, S: 3 x nf
     // ghosts
     int32_t *gowner, *gtag; double* gdist;
+    int32_t* gbtri;                       // ghost -> caller's boundary triangle
+    double* gval;                         // 2 x nb boundary values (SCALAR, POTENTIAL) per ghost
+    float* gval32;                        // nb: the scalar's values in FP32
     // vertices
     int64_t* n_off; int32_t* n_w; int32_t* n_idx; double* n_alpha;
     int32_t* n_len;                       // nv vertex list lengths
@@ -112,6 +124,8 @@ struct State {
     const Mesh* mesh = nullptr;           // host copy kept for sizes
     Dev d{};
     BcTable bc[2]{};                      // SCALAR, POTENTIAL
+    double bc_tag_value[2][kMaxTags]{};   // the last per-tag value set (host record)
+    double step_exec_cfl = -1.0;          // CFL factor captured in step_exec
     double diffusivity = 0.0;
     bool fp32 = false;                    // reduced-precision form of the step
     double cfl = 0.0;                     // factor of the last CFL evaluation
@@ -126,7 +140,8 @@ struct State {
     double step_exec_dt = -1.0;
     // schedule chosen by the autotuner (0 = not tuned)
     int tuned_chunk = 0, tuned_graph = 0, tuned_step_graph = 0;
-    bool assembled = false;
+    bool assembled = false;               // K's stored values, diagonal and c match the BCs
+    bool consts_ready = false;            // diagonal, D^-1 and c match the BCs (matrix-free solves)
     bool k32_ready = false;               // FP32 copy of K matches K
     bool vel_set = false;
     double* h_scal = nullptr;             // pinned host mirror of scalars
@@ -151,6 +166,13 @@ struct State {
     int amg_exec_key = 0;
 };
 
+// destroy every captured graph (their launch arguments hold boundary kinds,
+// the CFL factor and chunk sizes by value); the next use captures again
+void drop_graphs(State& s);
+// value of every ghost of `tag` for variable var: `value`, or, when vals is
+// not null, vals[caller's boundary triangle of the ghost]
+hipError_t launch_set_bc_values(const Dev& d, int var, int tag, double value, const double* vals, hipStream_t s);
+
 // workspace layout; returns total bytes (and fills d when base != nullptr)
 size_t layout(const Mesh& m, char* base, Dev& d);
 
@@ -173,14 +195,23 @@ hipError_t launch_to_internal(const int32_t* perm, int64_t n, int64_t stride_in,
                               int comps, const double* src, double* dst, hipStream_t s);
 hipError_t launch_to_user(const int32_t* perm, int64_t n, int64_t stride_in, int64_t stride_out,
                           int comps, const double* src, double* dst, hipStream_t s);
+// the same with the element type chosen per side (n rows, stride n)
+hipError_t launch_to_internal_typed(const int32_t* perm, int64_t n, int comps, const void* src, bool src_f32,
+                                    void* dst, bool dst_f32, hipStream_t s);
+hipError_t launch_to_user_typed(const int32_t* perm, int64_t n, int comps, const void* src, bool src_f32,
+                                void* dst, bool dst_f32, hipStream_t s);
 hipError_t launch_cfl(const Dev& d, const Mesh& mh, const BcTable& bc, hipStream_t s);
 hipError_t launch_conservation(const Dev& d, const Mesh& mh, bool fp32, hipStream_t s);
 
 // launchers (solve_kernels.hip)
 hipError_t launch_assemble(const Dev& d, const BcTable& bc, int row_max, hipStream_t s);
+// the diagonal of K, D^-1 and the ghost constants c only (no stored matrix)
+hipError_t launch_assemble_consts(const Dev& d, const BcTable& bc, hipStream_t s);
 hipError_t launch_spmv_plain(const Dev& d, const double* x, double* y, hipStream_t s);
 hipError_t launch_rhs(const Dev& d, const double* f_internal, hipStream_t s);
-hipError_t launch_cg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s);
+// kx: K x computed by the caller (matrix-free), or null for the stored K
+hipError_t launch_cg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s,
+                           const double* kx = nullptr);
 hipError_t launch_cg_spmv(const Dev& d, hipStream_t s);
 hipError_t launch_cg_axpy(const Dev& d, hipStream_t s);
 hipError_t launch_cg_dir(const Dev& d, hipStream_t s);

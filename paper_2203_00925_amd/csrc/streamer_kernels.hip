@@ -39,8 +39,8 @@ __device__ inline double pot_at(const Dev& d, const BcTable& bc, int e) {
     const int t = d.gtag[g];
     const double po = d.x[d.gowner[g]];
     const int kind = bc.kind[t];
-    if (kind == kDirichlet) return 2.0 * bc.value[t] - po;
-    if (kind == kNeumann) return po + bc.value[t] * d.gdist[g];
+    if (kind == kDirichlet) return 2.0 * bc.val[g] - po;
+    if (kind == kNeumann) return po + bc.val[g] * d.gdist[g];
     return po;
 }
 

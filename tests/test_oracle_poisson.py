@@ -206,3 +206,71 @@ def test_annex_variant_with_nonzero_neumann_data(n):
     K2, c2 = poisson.assemble(geo, kinds, [10.0, 10.0, 0.0, 0.0, 0.0, 0.0])
     x2 = poisson.direct_solve(K2, poisson.rhs(geo, np.zeros(geo.nc), c2))
     assert np.abs(x2 - exact).max() > 1.0
+
+
+def _foot_points(m):
+    """For each boundary triangle of the raw mesh (its own order): the
+    orthogonal projection of its cell's centre of gravity onto the triangle's
+    plane, found from the tets directly (no oracle geometry)."""
+    owner = {}
+    for c, t in enumerate(m.tets):
+        for skip in range(4):
+            owner[tuple(sorted(np.delete(t, skip)))] = c
+    feet = np.empty((len(m.btris), 3))
+    for i, tri in enumerate(m.btris):
+        c = owner[tuple(sorted(tri))]
+        xc = m.xyz[m.tets[c]].mean(axis=0)
+        a, b, d = m.xyz[tri]
+        n = np.cross(b - a, d - a)
+        n /= np.linalg.norm(n)
+        feet[i] = xc - np.dot(xc - a, n) * n
+    return feet
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_per_face_dirichlet_data_at_foot_points_reproduce_a_linear_field(n):
+    """Dirichlet data varying along the walls (one value per boundary
+    triangle): with a linear field's values at each face's foot point (the
+    owner centre projected on the face), every ghost value is the field at the
+    ghost centre, so the discrete Laplace problem with f = 0 reproduces the
+    field exactly and the least-squares gradient is exact in every cell."""
+    from oracle import fv
+    from oracle.geometry import PerFace
+    m = cube(n, seed=7)
+    geo = cube_geometry(n, seed=7)
+    a, b0 = np.array([0.8, -1.7, 0.6]), 0.25
+    feet = _foot_points(m)
+    data = PerFace(b0 + feet @ a)
+    kinds = [DIRICHLET] * 6
+    K, c = poisson.assemble(geo, kinds, data)
+    x = poisson.direct_solve(K, poisson.rhs(geo, np.zeros(geo.nc), c))
+    exact = b0 + geo.xc[:geo.nc] @ a
+    assert np.abs(x - exact).max() < 1e-11
+    gs, gt = fv.ghost_coefficients(geo, kinds, data)
+    g = fv.cell_gradient(geo, fv.extend_with_ghosts(geo, exact, gs, gt))
+    assert np.abs(g - a).max() < 1e-11
+    # one value per tag (the tag's mean) is not exact: the data matter
+    tagmean = [float(np.mean((b0 + feet @ a)[m.btags == t])) for t in range(6)]
+    K2, c2 = poisson.assemble(geo, kinds, tagmean)
+    x2 = poisson.direct_solve(K2, poisson.rhs(geo, np.zeros(geo.nc), c2))
+    assert np.abs(x2 - exact).max() > 1e-3
+
+
+def test_per_face_values_constant_per_tag_equal_per_tag_values():
+    """PerFace data that is constant on each tag gives bitwise the same
+    system and residual as the per-tag values."""
+    from oracle import fv
+    from oracle.geometry import PerFace
+    m = cube(3, seed=8)
+    geo = cube_geometry(3, seed=8)
+    kinds = [DIRICHLET, NEUMANN, DIRICHLET, ZERO_FLUX, NEUMANN, DIRICHLET]
+    vals = [1.5, -0.5, 2.0, 0.0, 0.75, -1.0]
+    per = PerFace(np.asarray(vals)[m.btags])
+    K1, c1 = poisson.assemble(geo, kinds, vals)
+    K2, c2 = poisson.assemble(geo, kinds, per)
+    assert (K1 != K2).nnz == 0 and np.array_equal(c1, c2)
+    rng = np.random.default_rng(2)
+    u = rng.normal(size=geo.nc)
+    phi = rng.normal(size=geo.nf)
+    assert np.array_equal(fv.residual(geo, u, phi, 0.1, kinds, vals),
+                          fv.residual(geo, u, phi, 0.1, kinds, per))
