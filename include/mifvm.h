@@ -496,6 +496,21 @@ typedef struct {
 int mifvm_streamer_step(mifvm_state* st, int32_t n_steps, const mifvm_streamer_opts* opts,
                         mifvm_streamer_info* info, void* stream);
 
+/* ---- without allocation ------------------------------------------------------
+ * For callers that cannot allocate device or host memory while they run
+ * (code under graph capture, tight serving loops, harnesses that forbid
+ * it): the total of mifvm_conservation, bitwise the same, with its
+ * reduction scratch (per-block partials, per-mesh totals, the result) in a
+ * fixed array of MIFVM_STATIC_SCRATCH_BYTES that the library holds on each
+ * GPU it runs on until the process ends, instead of the state's workspace
+ * and host mirror.  The call allocates nothing.  At most
+ * MIFVM_STATIC_MAX_MESHES meshes (E_ARG beyond).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other threads,
+ * other streams) race and must be serialised by the caller.  Synchronises.  */
+#define MIFVM_STATIC_MAX_MESHES 1024
+#define MIFVM_STATIC_SCRATCH_BYTES ((1024 + MIFVM_STATIC_MAX_MESHES * 32 + 8) * 8)
+int mifvm_conservation_static(mifvm_state* st, double* total_out, void* stream);
+
 /* ---- per-kernel timing (HIP events on the launch stream) -----------------
  * enable != 0 starts recording an event pair around every kernel launch of
  * this state and clears the totals; enable == 0 stops.  Kernel ids: */
