@@ -44,10 +44,12 @@ class VertexIndex:
         return np.unique(np.concatenate(parts))
 
 
-def submesh(mesh, vidx: VertexIndex, cell):
-    """Two-vertex-ring submesh around `cell`: (xyz, tets, btris, btags,
+def submesh(mesh, vidx: VertexIndex, cell, rings=2):
+    """`rings`-vertex-ring submesh around `cell`: (xyz, tets, btris, btags,
     cells) with cells = the original ids in increasing order."""
-    cells = vidx.ring(vidx.ring([cell]))
+    cells = [cell]
+    for _ in range(rings):
+        cells = vidx.ring(cells)
     tets = vidx.tets[cells]
     verts, inv = np.unique(tets.ravel(), return_inverse=True)
     sub_tets = inv.reshape(-1, 4).astype(np.int32)
@@ -99,3 +101,21 @@ def matrix_rows_times(mesh, vidx, cells, x, kinds, values):
         kx[k] = float((K[j] @ x[ids])[0])
         cc[k] = cvec[j]
     return kx, cc
+
+
+def step_at(mesh, vidx, cells, u, vel, D, kinds, values, dt):
+    """u after one step of eq. (6) at each i in `cells`.  The three stages
+    each read the residual, which reaches two vertex rings; the stage-k value
+    at a cell therefore depends on the data within 2k rings of it, and the
+    step at i on the six-ring submesh, whose cut faces lie outside what is
+    read (as for the residual above)."""
+    kinds = list(kinds) + [0] * (CUT_TAG + 1 - len(kinds))
+    values = list(values) + [0.0] * (CUT_TAG + 1 - len(values))
+    out = np.empty(len(cells))
+    for k, c in enumerate(cells):
+        xyz, tets, btris, btags, ids = submesh(mesh, vidx, c, rings=6)
+        geo = build_geometry(xyz, tets, btris, btags)
+        phi = fv.face_velocity_flux(geo, vel[ids])
+        un = fv.rk3_step(geo, u[ids], dt, phi, D, kinds, values)
+        out[k] = un[np.searchsorted(ids, c)]
+    return out

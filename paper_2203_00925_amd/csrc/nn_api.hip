@@ -13,6 +13,7 @@
 #include "../../include/mifvm.h"
 #include "../../include/mifvm_nn.h"
 #include "api_util.h"
+#include "fcg_monitor.h"
 #include "nn.h"
 
 static_assert(MIFVM_NN_PARAMS == mifvm::kNnParams, "parameter count of the ABI and the kernels");
@@ -211,35 +212,35 @@ int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int s
         return MIFVM_OK;
     };
     HIPCHK(launch_fcg_backup(d, a, false, hs));
+    FcgMonitor mon;
+    mon.window = window;
+    mon.limit_is_learned = limit < maxit;
+    auto act = [&](FcgMonitor::Action x) -> int {
+        switch (x) {
+            case FcgMonitor::FALL_BACK_RESTORE: return fall_back(true);
+            case FcgMonitor::FALL_BACK_KEEP: return fall_back(false);
+            default: return MIFVM_OK;
+        }
+    };
     int rc = setup(true);
     if (rc) return rc;
-    if (!std::isfinite(hsc(s, 0, SC_TRUE_RR)) || !std::isfinite(hsc(s, 0, SC_RZ))) return fall_back(true);
-    double best = hsc(s, 0, SC_RR);
-    double best_it = 0.0;
+    FcgMonitor::Action x = mon.open(hsc(s, 0, SC_TRUE_RR), hsc(s, 0, SC_RZ), hsc(s, 0, SC_RR));
+    if (x != FcgMonitor::CONTINUE) return act(x);
     for (;;) {
         while (hsc(s, 0, SC_DONE) == 0.0) {
             if ((rc = run_chunk())) return rc;
             if ((rc = pull())) return rc;
-            const double rr = hsc(s, 0, SC_RR), it = hsc(s, 0, SC_IT);
-            out.iterations = int(it);
-            if (!std::isfinite(rr) || !std::isfinite(hsc(s, 0, SC_RZ)) || !std::isfinite(hsc(s, 0, SC_BETA)))
-                return fall_back(true);
-            if (rr < 0.98 * best) {                  // the norm dropped by 1%
-                best = rr;
-                best_it = it;
-            } else if (it - best_it >= window) {
-                return fall_back(false);
-            }
+            out.iterations = int(hsc(s, 0, SC_IT));
+            x = mon.after_chunk(hsc(s, 0, SC_RR), hsc(s, 0, SC_RZ), hsc(s, 0, SC_BETA), hsc(s, 0, SC_IT));
+            if (x != FcgMonitor::CONTINUE) return act(x);
             HIPCHK(launch_fcg_backup(d, a, false, hs));
         }
         // converged by the recurrence, at the limit, or a restart is due:
         // the true residual decides
         if ((rc = setup(false))) return rc;
         out.iterations = int(hsc(s, 0, SC_IT));
-        if (!std::isfinite(hsc(s, 0, SC_TRUE_RR)) || !std::isfinite(hsc(s, 0, SC_RZ))) return fall_back(true);
-        const double done = hsc(s, 0, SC_DONE);
-        if (done == 1.0) return MIFVM_OK;
-        if (done == 2.0) return limit < maxit ? fall_back(false) : MIFVM_OK;
+        x = mon.after_reopen(hsc(s, 0, SC_TRUE_RR), hsc(s, 0, SC_RZ), hsc(s, 0, SC_DONE));
+        if (x != FcgMonitor::CONTINUE) return act(x);
         ++out.restarts;
     }
 }

@@ -75,6 +75,35 @@ def test_fullsize_matrix_rows_sampled(big):
     assert err < 1e-12
 
 
+def test_fullsize_step_and_residual_after_it(big):
+    """One step as the bench launches it (the captured step graph at the CFL
+    time step) from the initial field: u at sampled cells against the
+    oracle's step from each cell's six-vertex-ring neighbourhood, then the
+    residual of the stepped field against the oracle's on that field."""
+    m, pf, st, vidx = big
+    st.set_field(B.FIELD_U, torch.from_numpy(pf.u0))
+    dt = st.cfl_dt(pf.cfl)
+    st.step_graph(1, 0.0)
+    u1 = st.get_field(B.FIELD_U).cpu().numpy()
+    cells = sample(m, pf, 16)
+    ref = local.step_at(m, vidx, cells, pf.u0, pf.vel, pf.diffusivity, [ZERO_FLUX] * 6, [0.0] * 6, dt)
+    # the step moves u by about dt |Res| (1e-5 here): compare the increments,
+    # allowing the final FP64 rounding of u on each side (an ulp of max|u|)
+    du, du_ref = u1[cells] - pf.u0[cells], ref - pf.u0[cells]
+    scale = np.abs(u1 - pf.u0).max()
+    err = np.abs(du - du_ref).max()
+    print(f"[gpu] full-size step: {len(cells)} sampled cells, max |du - du_ref| = {err:.2e} "
+          f"(max|du| {scale:.2e})", flush=True)
+    assert err <= 1e-12 * scale + 2.0 ** -51 * np.abs(u1).max()
+    res = st.residual()["res"].cpu().numpy()
+    cells = sample(m, pf, 80)
+    ref = local.residual_at(m, vidx, cells, u1, pf.vel, pf.diffusivity, [ZERO_FLUX] * 6, [0.0] * 6)
+    err = np.abs(res[cells] - ref).max() / np.abs(res).max()
+    print(f"[gpu] full-size residual after the step: {len(cells)} cells, max err / max|Res| = {err:.2e}",
+          flush=True)
+    assert err < 1e-12
+
+
 def test_fullsize_step_conserves_and_solve_converges(big):
     m, pf, st, vidx = big
     t0 = st.conservation()

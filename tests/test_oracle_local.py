@@ -37,3 +37,29 @@ def test_local_matrix_rows_equal_global():
     kx, cc = local.matrix_rows_times(m, vidx, cells, x, kinds, vals)
     assert np.abs(kx - (K @ x)[cells]).max() <= 1e-13 * np.abs(K @ x).max()
     assert np.abs(cc - c[cells]).max() <= 1e-13 * max(np.abs(c).max(), 1.0)
+
+
+def test_local_step_equals_global():
+    """One RK3 step of eq. (6) from six-vertex-ring submeshes equals the
+    global oracle's step at sampled cells (interior, edge and corner cells;
+    on a mesh where the six rings of an interior cell leave cut faces)."""
+    m = cube(12, 23)
+    geo = cube_geometry(12, 23)
+    u = synth.gaussian_field(m, (0.45, 0.5, 0.55), 0.15)
+    vel = synth.rotating_velocity(m)
+    kinds = [DIRICHLET, NEUMANN, ZERO_FLUX, DIRICHLET, ZERO_FLUX, NEUMANN]
+    vals = [0.2, -0.1, 0.0, 0.5, 0.0, 0.3]
+    D = 5e-3
+    phi = fv.face_velocity_flux(geo, vel)
+    dt = fv.cfl_dt(geo, phi, D, 0.4, kinds)
+    ref = fv.rk3_step(geo, u, dt, phi, D, kinds, vals)
+    vidx = local.VertexIndex(m.tets, m.nv)
+    xc = geo.xc[:geo.nc]
+    centre = int(np.argmin(np.linalg.norm(xc - 0.5, axis=1)))
+    corner = int(np.argmin(np.linalg.norm(xc, axis=1)))
+    edge = int(np.argmin(np.linalg.norm(xc - [0.5, 0.0, 1.0], axis=1)))
+    cells = np.array([centre, corner, edge, 17, geo.nc - 5])
+    _, _, _, _, ids = local.submesh(m, vidx, centre, rings=6)
+    assert len(ids) < geo.nc                      # the interior submesh is cut
+    got = local.step_at(m, vidx, cells, u, vel, D, kinds, vals, dt)
+    assert np.abs(got - ref[cells]).max() <= 1e-13 * np.abs(ref).max()
