@@ -397,6 +397,99 @@ typedef struct {
 int mifvm_step_graph(mifvm_state* st, int32_t n_steps, double dt, void* stream);
 int mifvm_autotune(mifvm_state* st, const char* cache_path, mifvm_tune_info* out, void* stream);
 
+/* ---- batched form: persistent solve of many meshes ---------------------------
+ * A batch is a state made of independent meshes (mifvm_mesh_opts.nmeshes;
+ * one workspace, one internal numbering, every step kernel launched once
+ * for all meshes).  mifvm_batch runs the meshes' Poisson solves - each its
+ * own matrix-free Jacobi-CG with the stopping test, restarts and scalars of
+ * mifvm_poisson_solve (matrix_free = 1) - in ONE persistent kernel: every
+ * mesh's iteration is a sequence of phases (vertex values of Algorithm 2,
+ * diamond face fluxes of eq. (diamond), the cell gather with p.q, the
+ * update with r.z and r.r, the new direction; and the opening from the true
+ * residual), each split into items of `item_rows` consecutive rows;
+ * workgroups take (mesh, phase, item) from per-mesh device queues, the
+ * workgroup that completes a phase's last item adds its partial sums in item
+ * order (deterministic) and publishes the next phase, and a mesh that has
+ * converged leaves the queue while the others go on.  A workgroup that sees
+ * no progress of any mesh for about 2^20 polls stops the kernel (E_STATE),
+ * so it cannot hang.  FP64 states only; no stored matrix needed.
+ *
+ * Schedule: item_rows (a multiple of 256: 256 threads, item_rows/256 rows per
+ * thread; 0 = 4096), grid (workgroups; 0 = 1024), policy (the order in which
+ * a workgroup looks for work: 0 ROTATE - meshes by size, rotated per XCD;
+ * 1 XCD - meshes assigned to the 8 XCDs by size (longest processing time
+ * first), an XCD's workgroups take their own meshes first so that a mesh's
+ * data stays in one L2, then steal; 2 LARGEST - the largest mesh first
+ * everywhere; -1 = 1).                                                      */
+typedef struct mifvm_batch mifvm_batch;
+typedef struct {
+    int32_t item_rows;
+    int32_t grid;
+    int32_t policy;
+    int32_t spin_limit;        /* polls without progress before the kernel
+                                  stops (0 = 2^20; for tests of that path)   */
+} mifvm_batch_opts;
+
+typedef struct {
+    double tol;                /* relative true residual per mesh (0 = 1e-10)  */
+    int32_t maxit;             /* per mesh and solve (0 = 20000)              */
+    int32_t restart;           /* reopen from the true residual every this many
+                                  iterations (0 = only at convergence)       */
+    int32_t solve_every;       /* mifvm_batch_run: a solve after every this many
+                                  steps (0 = 1)                              */
+    int32_t pad_;
+} mifvm_batch_solve_opts;
+
+typedef struct {
+    int32_t solves;            /* solves in the call                          */
+    int32_t pad_;
+    int64_t iterations_max;    /* per mesh, summed over the call's solves: the
+                                  largest over the meshes                    */
+    int64_t iterations_sum;    /* over meshes and solves                      */
+    double iterations_mean;    /* per mesh                                    */
+    double rel_residual_max;   /* largest final true relative residual        */
+    double ms;                 /* wall time of the call                       */
+} mifvm_batch_info;
+
+typedef struct {
+    int32_t item_rows, grid, policy;
+    int32_t from_cache;
+    int32_t trials;
+    int32_t iterations;        /* iterations per mesh of each timed trial     */
+    double ms_best;            /* the chosen schedule's trial                 */
+} mifvm_batch_tune_info;
+
+/* Device workspace of a batch (queues, ranges, partial sums, schedule),
+ * 256-byte aligned, caller-owned, outliving the batch.                      */
+int mifvm_batch_bytes(const mifvm_state* st, size_t* out);
+/* Bind a batch to a state.  E_ARG when two meshes share a vertex or a face,
+ * or for a bad schedule; E_STATE for an FP32 state.  Synchronises.        */
+int mifvm_batch_create(mifvm_state* st, const mifvm_batch_opts* opts, void* d_ws, size_t ws_bytes,
+                       void* stream, mifvm_batch** out);
+void mifvm_batch_destroy(mifvm_batch* b);
+/* Change the schedule (fields <= 0, or -1 for the policy, keep theirs).    */
+int mifvm_batch_set_schedule(mifvm_batch* b, const mifvm_batch_opts* opts, void* stream);
+int mifvm_batch_get_schedule(const mifvm_batch* b, mifvm_batch_opts* out);
+/* Every mesh's Poisson solve of Delta P = U (b = -mu U + c, warm-started
+ * from P) in one persistent launch.  Per-mesh iterations and residuals go to
+ * mifvm_mesh_values (2, 3).  NOT_CONVERGED if a mesh stopped at maxit.
+ * Synchronises.                                                            */
+int mifvm_batch_solve(mifvm_batch* b, const mifvm_batch_solve_opts* opts, mifvm_batch_info* info, void* stream);
+/* n_steps of the batched configuration: each an RK3 step of every mesh at
+ * its own CFL time step (mifvm_cfl_dt first), then, every solve_every steps,
+ * the persistent solve - the whole sequence captured once into one hipGraph
+ * (per n_steps and options; dropped with the state's graphs) and replayed.
+ * info sums the run's solves.  Synchronises.                               */
+int mifvm_batch_run(mifvm_batch* b, int32_t n_steps, const mifvm_batch_solve_opts* opts, mifvm_batch_info* info,
+                    void* stream);
+/* Time `iterations` (0 = 24) iterations of every mesh for queue policy x
+ * grid {512, 1024, 2048} at 4096-row items, then item_rows {1024 .. 16384}
+ * at the best; keep the fastest and record it in the JSON file cache_path
+ * (NULL: none) under "gfx950/batch/<meshes>/<log2 cells>"; a recorded entry
+ * is used without timing.  P is restored.  Synchronises.                  */
+int mifvm_batch_autotune(mifvm_batch* b, const char* cache_path, int32_t iterations, mifvm_batch_tune_info* out,
+                         void* stream);
+
 /* ---- aggregation multigrid preconditioner ----------------------------------
  * The analogue of the paper's fastest solver configuration (PETSc GAMG,
  * Sec. 3.4.2), as plain aggregation: per level, strong neighbours

@@ -104,6 +104,28 @@ class SolveInfo(C.Structure):
                 ("fell_back", C.c_int32), ("learned_iterations", C.c_int32)]
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("item_rows", C.c_int32), ("grid", C.c_int32), ("policy", C.c_int32),
+                ("spin_limit", C.c_int32)]
+
+
+class BatchSolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("restart", C.c_int32),
+                ("solve_every", C.c_int32), ("pad_", C.c_int32)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("solves", C.c_int32), ("pad_", C.c_int32), ("iterations_max", C.c_int64),
+                ("iterations_sum", C.c_int64), ("iterations_mean", C.c_double),
+                ("rel_residual_max", C.c_double), ("ms", C.c_double)]
+
+
+class BatchTuneInfo(C.Structure):
+    _fields_ = [("item_rows", C.c_int32), ("grid", C.c_int32), ("policy", C.c_int32),
+                ("from_cache", C.c_int32), ("trials", C.c_int32), ("iterations", C.c_int32),
+                ("ms_best", C.c_double)]
+
+
 class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("omega", C.c_double), ("max_levels", C.c_int32),
                 ("coarse_max", C.c_int32), ("cycle", C.c_int32), ("pad_", C.c_int32)]
@@ -215,6 +237,14 @@ def _load():
         "mifvm_kernel_timing": (C.c_int, [P, I32]),
         "mifvm_step_graph": (C.c_int, [P, I32, D, P]),
         "mifvm_autotune": (C.c_int, [P, C.c_char_p, C.POINTER(TuneInfo), P]),
+        "mifvm_batch_bytes": (C.c_int, [P, C.POINTER(SZ)]),
+        "mifvm_batch_create": (C.c_int, [P, C.POINTER(BatchOpts), P, SZ, P, C.POINTER(P)]),
+        "mifvm_batch_destroy": (None, [P]),
+        "mifvm_batch_set_schedule": (C.c_int, [P, C.POINTER(BatchOpts), P]),
+        "mifvm_batch_get_schedule": (C.c_int, [P, C.POINTER(BatchOpts)]),
+        "mifvm_batch_solve": (C.c_int, [P, C.POINTER(BatchSolveOpts), C.POINTER(BatchInfo), P]),
+        "mifvm_batch_run": (C.c_int, [P, I32, C.POINTER(BatchSolveOpts), C.POINTER(BatchInfo), P]),
+        "mifvm_batch_autotune": (C.c_int, [P, C.c_char_p, I32, C.POINTER(BatchTuneInfo), P]),
         "mifvm_kernel_stats": (C.c_int, [P, I32, C.POINTER(D), C.POINTER(I64), P]),
         "mifvm_nn_workspace_bytes": (SZ, []),
         "mifvm_nn_create": (C.c_int, [C.POINTER(_NnOpts), P, SZ, P, C.POINTER(P)]),
@@ -540,6 +570,68 @@ class State:
             _check(_lib.mifvm_kernel_stats(self._h, k, C.byref(ms), C.byref(n), _stream(stream)))
             out[name] = (ms.value, n.value)
         return out
+
+
+BQ_ROTATE, BQ_XCD, BQ_LARGEST = 0, 1, 2
+
+
+class Batch:
+    """Persistent batched solve of every mesh of a multi-mesh state
+    (mifvm_batch_*); the workspace is a torch uint8 tensor."""
+
+    def __init__(self, state, item_rows=0, grid=0, policy=-1, spin_limit=0, stream=None):
+        import torch
+        self.state = state
+        n = C.c_size_t()
+        _check(_lib.mifvm_batch_bytes(state._h, C.byref(n)))
+        self.ws = torch.empty(n.value + 256, dtype=torch.uint8, device=state.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        h = C.c_void_p()
+        opts = BatchOpts(int(item_rows), int(grid), int(policy), int(spin_limit))
+        _check(_lib.mifvm_batch_create(state._h, C.byref(opts), C.c_void_p(base + off), n.value,
+                                       _stream(stream), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.mifvm_batch_destroy(h)
+            self._h = None
+
+    def schedule(self):
+        o = BatchOpts()
+        _check(_lib.mifvm_batch_get_schedule(self._h, C.byref(o)))
+        return {"item_rows": o.item_rows, "grid": o.grid, "policy": o.policy, "spin_limit": o.spin_limit}
+
+    def set_schedule(self, item_rows=0, grid=0, policy=-1, spin_limit=0, stream=None):
+        o = BatchOpts(int(item_rows), int(grid), int(policy), int(spin_limit))
+        _check(_lib.mifvm_batch_set_schedule(self._h, C.byref(o), _stream(stream)))
+
+    @staticmethod
+    def _info(rc, info):
+        return dict(status=rc, solves=info.solves, iterations_max=info.iterations_max,
+                    iterations_sum=info.iterations_sum, iterations_mean=info.iterations_mean,
+                    rel_residual_max=info.rel_residual_max, ms=info.ms)
+
+    def solve(self, tol=1e-10, maxit=20000, restart=500, stream=None, allow_not_converged=False):
+        o = BatchSolveOpts(float(tol), int(maxit), int(restart), 1, 0)
+        info = BatchInfo()
+        allow = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        rc = _check(_lib.mifvm_batch_solve(self._h, C.byref(o), C.byref(info), _stream(stream)), allow)
+        return self._info(rc, info)
+
+    def run(self, n_steps, tol=1e-10, maxit=20000, restart=500, solve_every=1, stream=None):
+        o = BatchSolveOpts(float(tol), int(maxit), int(restart), int(solve_every), 0)
+        info = BatchInfo()
+        rc = _check(_lib.mifvm_batch_run(self._h, int(n_steps), C.byref(o), C.byref(info), _stream(stream)))
+        return self._info(rc, info)
+
+    def autotune(self, cache_path=None, iterations=0, stream=None):
+        info = BatchTuneInfo()
+        path = cache_path.encode() if cache_path else None
+        _check(_lib.mifvm_batch_autotune(self._h, path, int(iterations), C.byref(info), _stream(stream)))
+        return {f: getattr(info, f) for f, _ in BatchTuneInfo._fields_}
 
 
 class Network:

@@ -20,7 +20,8 @@ ARCH = "gfx950"
 
 HIP_SOURCES = ["api.hip", "nn_api.hip", "fv_kernels.hip", "solve_kernels.hip", "ir_kernels.hip",
                "nn_kernels.hip", "mf_kernels.hip", "gmres_kernels.hip", "streamer_kernels.hip",
-               "amg_kernels.hip", "amg_api.hip", "noalloc.hip"]
+               "amg_kernels.hip", "amg_api.hip", "noalloc.hip", "batch_kernels.hip",
+               "batch_api.hip"]
 CXX_SOURCES = ["mesh.cpp", "amg.cpp"]
 HEADERS = ["mesh.h", "state.h", "reduce.h", "seg.h", "cg_scalars.h", "api_util.h", "nn.h", "gmres.h"]
 

@@ -165,6 +165,7 @@ void drop_graphs(State& s) {
     s.fcg_exec_chunk = 0;
     s.gm_exec_key = 0;
     s.amg_exec_key = 0;
+    ++s.graph_gen;                            // graphs held elsewhere (a batch's) follow
 }
 
 }  // namespace mifvm
@@ -602,7 +603,9 @@ int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream) {
     return MIFVM_OK;
 }
 
-namespace {
+}  // extern "C"
+
+namespace mifvm_api {
 // n RK3 steps without timing events (the body of a captured step graph)
 hipError_t enqueue_steps(const State& s, int n, double dt, hipStream_t q) {
     static const double alpha[3] = {0.5, 0.5, 1.0};
@@ -617,7 +620,9 @@ hipError_t enqueue_steps(const State& s, int n, double dt, hipStream_t q) {
     if (e == hipSuccess && n > 0) e = launch_ghost_fill(d, s.fp32, s.bc[0], q);
     return e;
 }
-}  // namespace
+}  // namespace mifvm_api
+
+extern "C" {
 
 int mifvm_step_graph(mifvm_state* st, int32_t n_steps, double dt, void* stream) {
     if (!st) return fail(MIFVM_E_ARG, "null state");
@@ -711,9 +716,13 @@ int mifvm_conservation(mifvm_state* st, double* total_out, void* stream) {
     return MIFVM_OK;
 }
 
+}  // extern "C"
+
 namespace {
 bool has_matrix(const State& s) { return !s.mesh->kmat.off.empty(); }
+}  // namespace
 
+namespace mifvm_api {
 // the diagonal, D^-1 and the ghost constants c of the current potential
 // BCs, which every solve needs; the matrix-free solves need nothing else
 int ensure_consts(State& s, hipStream_t hs) {
@@ -723,7 +732,9 @@ int ensure_consts(State& s, hipStream_t hs) {
     s.k32_ready = false;                      // the FP32 copies of the diagonal follow it
     return MIFVM_OK;
 }
-}  // namespace
+}  // namespace mifvm_api
+
+extern "C" {
 
 int mifvm_poisson_assemble(mifvm_state* st, void* stream) {
     if (!st) return fail(MIFVM_E_ARG, "null state");

@@ -121,6 +121,11 @@ inline hipError_t capture_graph(State& s, hipGraphExec_t* exec, F enqueue) {
     return e;
 }
 
+// n RK3 steps without timing events (api.hip)
+hipError_t enqueue_steps(const mifvm::State& s, int n, double dt, hipStream_t q);
+// the diagonal, D^-1 and c of the current potential BCs, computed if stale (api.hip)
+int ensure_consts(mifvm::State& s, hipStream_t hs);
+
 // copy every mesh's scalars to the pinned host mirror and wait
 inline int pull_scalars(State& s, hipStream_t hs) {
     HIPCHK(hipMemcpyAsync(s.h_scal, s.d.scal, size_t(s.d.nm) * SC_COUNT_ * sizeof(double),

@@ -126,6 +126,7 @@ struct State {
     BcTable bc[2]{};                      // SCALAR, POTENTIAL
     double bc_tag_value[2][kMaxTags]{};   // the last per-tag value set (host record)
     double step_exec_cfl = -1.0;          // CFL factor captured in step_exec
+    int64_t graph_gen = 0;                // bumped whenever the captured graphs are dropped
     double diffusivity = 0.0;
     bool fp32 = false;                    // reduced-precision form of the step
     double cfl = 0.0;                     // factor of the last CFL evaluation

@@ -1,0 +1,183 @@
+"""Batched form in one persistent kernel (mifvm_batch_*): every mesh of a
+multi-mesh state solves its own Poisson system, pulling work from device
+queues.  Each mesh's solution is accepted by the oracle's K; the run of
+steps and solves (one captured graph) equals the oracle's steps and the
+per-launch path; schedules, determinism, graph replays, the autotuner and
+the stop on no progress."""
+import numpy as np
+import pytest
+
+import synth
+from conftest import cube, cube_geometry
+from oracle import fv, poisson
+from oracle.geometry import ZERO_FLUX, DIRICHLET
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+B = pytest.importorskip("paper_2203_00925_amd.binding")
+
+TOL = 1e-12
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def recipe(sizes, seed=4242):
+    """Per-mesh diffusivity U[1e-4, 1e-2] and Gaussian centre U[0.3, 0.7]^3
+    (the batched configuration's recipe), meshes of the given sizes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, n in enumerate(sizes):
+        D = rng.uniform(1e-4, 1e-2)
+        c = rng.uniform(0.3, 0.7, 3)
+        out.append((n, 1000 + k, D, c))
+    return out
+
+
+def make(rec, no_matrix=True):
+    ms = [cube(n, s) for n, s, _, _ in rec]
+    u0 = [synth.gaussian_field(m, c, 0.1) for m, (_, _, _, c) in zip(ms, rec)]
+    vel = [synth.rotating_velocity(m) for m in ms]
+    st = B.State(B.Mesh.from_batch(ms, no_matrix=no_matrix))
+    st.set_mesh_diffusivity([D for _, _, D, _ in rec])
+    st.set_bcs(B.VAR_SCALAR, [ZERO_FLUX] * 6)
+    st.set_bcs(B.VAR_POTENTIAL, [DIRICHLET] * 6)
+    st.set_field(B.FIELD_VEL, dev(np.concatenate([np.concatenate([v[:, k] for v in vel]) for k in range(3)])))
+    st.set_field(B.FIELD_U, dev(np.concatenate(u0)))
+    return ms, u0, vel, st
+
+
+SMALL = recipe([4, 5, 6])                       # 384, 750, 1,296 cells
+
+
+def accepted(rec, ms, f_all, x_all):
+    off = np.cumsum([0] + [m.nc for m in ms])
+    worst = 0.0
+    for k, (n, s, _, _) in enumerate(rec):
+        g = cube_geometry(n, s)
+        K, c = poisson.assemble(g, [DIRICHLET] * 6, [0.0] * 6)
+        b = poisson.rhs(g, f_all[off[k]:off[k + 1]], c)
+        worst = max(worst, poisson.true_relative_residual(K, b, x_all[off[k]:off[k + 1]]))
+    return worst
+
+
+@pytest.mark.parametrize("item_rows,grid,policy", [(4096, 1024, B.BQ_XCD), (256, 8, B.BQ_ROTATE),
+                                                   (512, 3, B.BQ_LARGEST), (1024, 512, B.BQ_XCD)])
+def test_persistent_solve_accepted_and_matches_launches(item_rows, grid, policy):
+    """Every mesh converges on its own and is accepted by the oracle's K; the
+    same per-mesh algorithm as the per-launch matrix-free solve (iterations
+    within 3, solutions to 1e-8), whatever the schedule (items smaller than
+    meshes, fewer workgroups than items, any queue order)."""
+    print(f"[gpu] persistent batch solve: item_rows={item_rows} grid={grid} policy={policy}", flush=True)
+    ms, u0, vel, st = make(SMALL)
+    bt = B.Batch(st, item_rows=item_rows, grid=grid, policy=policy)
+    info = bt.solve(tol=1e-10)
+    its = st.mesh_values("iterations")
+    assert info["status"] == B.OK and np.all(st.mesh_values("rel_residual") <= 1e-10)
+    x = host(st.get_field(B.FIELD_P))
+    assert accepted(SMALL, ms, np.concatenate(u0), x) <= 1.01e-10
+    # the per-launch path from the same start
+    st.set_field(B.FIELD_P, dev(np.zeros(len(x))))
+    st.poisson_solve(None, tol=1e-10, matrix_free=True)
+    its_l = st.mesh_values("iterations")
+    print(f"[gpu] iterations persistent {its.astype(int)}, per-launch {its_l.astype(int)}", flush=True)
+    assert np.all(np.abs(its - its_l) <= 3)
+    assert rel(x, host(st.get_field(B.FIELD_P))) < 1e-8
+    # deterministic: the same schedule from the same start gives the same bits
+    st.set_field(B.FIELD_P, dev(np.zeros(len(x))))
+    bt.solve(tol=1e-10)
+    assert np.array_equal(host(st.get_field(B.FIELD_P)), x)
+
+
+def test_persistent_run_eight_meshes_against_oracle():
+    """Eight meshes of 384 to 55,566 cells with per-mesh diffusivity and
+    centre: two steps of the batched configuration (each mesh's RK3 step at
+    its own CFL time step, then its warm-started solve), captured in one
+    graph: u equals the oracle's steps to 1e-12 per mesh, P after each step is
+    accepted by the oracle's K for that step's right-hand side, and the run
+    equals steps and solves called one by one (bitwise) over several replays
+    with other work in between."""
+    rec = recipe([4, 5, 6, 7, 8, 9, 10, 21])
+    ms, u0, vel, st = make(rec)
+    assert max(m.nc for m in ms) >= 50000
+    twin = make(rec)[3]
+    bt, bw = B.Batch(st), B.Batch(twin)
+    st.cfl_dt(0.4)
+    twin.cfl_dt(0.4)
+    dts = st.mesh_values("dt")
+    off = np.cumsum([0] + [m.nc for m in ms])
+    us = [u.copy() for u in u0]
+    for rep in range(3):
+        print(f"[gpu] eight-mesh run, replay {rep}", flush=True)
+        info = bt.run(2, tol=1e-10)
+        for _ in range(2):
+            twin.step(1, 0.0)
+            bw.solve(tol=1e-10)
+        ua, pa = host(st.get_field(B.FIELD_U)), host(st.get_field(B.FIELD_P))
+        assert np.array_equal(ua, host(twin.get_field(B.FIELD_U)))
+        assert np.array_equal(pa, host(twin.get_field(B.FIELD_P)))
+        assert info["status"] == B.OK and info["solves"] == 2 and info["rel_residual_max"] <= 1e-10
+        if rep == 0:                             # against the oracle (2 steps)
+            for k, (n, s, D, _) in enumerate(rec):
+                g = cube_geometry(n, s)
+                phi = fv.face_velocity_flux(g, vel[k])
+                dt = fv.cfl_dt(g, phi, D, 0.4, [ZERO_FLUX] * 6)
+                assert abs(dt - dts[k]) <= 1e-14 * dt
+                for _ in range(2):
+                    us[k] = fv.rk3_step(g, us[k], dt, phi, D, [ZERO_FLUX] * 6, [0.0] * 6)
+                assert rel(ua[off[k]:off[k + 1]], us[k]) < TOL, k
+            assert accepted(rec, ms, ua, pa) <= 1.01e-10
+        # other work between replays
+        torch.ones(1 << 20, device="cuda").sum().item()
+
+
+def test_autotune_picks_schedule_and_restores_p(tmp_path):
+    ms, u0, vel, st = make(SMALL)
+    bt = B.Batch(st)
+    bt.solve(tol=1e-10)
+    p0 = host(st.get_field(B.FIELD_P))
+    cache = str(tmp_path / "batch_tune.json")
+    t = bt.autotune(cache, iterations=8)
+    print(f"[gpu] batch autotune: {t}", flush=True)
+    assert t["from_cache"] == 0 and t["trials"] >= 12
+    assert t["item_rows"] % 256 == 0 and t["policy"] in (0, 1, 2)
+    assert np.array_equal(host(st.get_field(B.FIELD_P)), p0)
+    assert bt.schedule()["item_rows"] == t["item_rows"]
+    t2 = bt.autotune(cache)
+    assert t2["from_cache"] == 1 and t2["grid"] == t["grid"] and t2["policy"] == t["policy"]
+    assert bt.solve(tol=1e-10)["status"] == B.OK
+
+
+def test_stop_without_progress_is_reported():
+    """A spin limit of one poll (set from the host) stops the kernel as soon
+    as a workgroup finds no work twice without progress anywhere: every
+    workgroup exits, the call returns E_STATE, and the batch solves normally
+    again with the default limit."""
+    rec = recipe([4, 5, 6, 7, 8, 9, 10, 21])
+    ms, u0, vel, st = make(rec)
+    bt = B.Batch(st, grid=2048, spin_limit=1)
+    with pytest.raises(B.MifvmError) as e:
+        bt.solve(tol=1e-10)
+    assert e.value.code == -5
+    bt.set_schedule(spin_limit=1 << 20)
+    st.set_field(B.FIELD_P, dev(np.zeros(sum(m.nc for m in ms))))
+    info = bt.solve(tol=1e-10)
+    assert info["status"] == B.OK
+    assert accepted(rec, ms, np.concatenate(u0), host(st.get_field(B.FIELD_P))) <= 1.01e-10
