@@ -177,9 +177,21 @@ def cpu_baseline(seconds_target=15.0):
         t1 = time.perf_counter()
         _, its, _ = poisson.jacobi_cg(K, poisson.rhs(geo, u, c), tol=1e-10)
         t_solve = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    try:
+        host_cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        host_cores = os.cpu_count()
     return {"value": geo.nc * steps / t_fv, "unit": "cell-updates/s", "cores": 1,
+            "host_cores": host_cores, "host_cpu": model,
             "kind": "oracle",
-            "sample": f"48,000-cell cube of the same recipe (n=20, seed 1), {steps} RK3 steps "
+            "sample": f"single thread (1 core of the {host_cores} this process may use); "
+                      f"48,000-cell cube of the same recipe (n=20, seed 1), {steps} RK3 steps "
                       f"in {t_fv:.1f} s; one cold Jacobi-CG solve to 1e-10: {its} iterations, "
                       f"{t_solve * 1e3:.0f} ms",
             "poisson_solve_ms": t_solve * 1e3}
@@ -195,7 +207,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--forms", default="all",
                     help="comma-separated forms to run after the main steps (fp32_refined, stored_matrix_cg, "
-                         "fgmres30, multigrid_fcg, multigrid_w_fcg, streamer, learned), or all")
+                         "fgmres30, multigrid_fcg, multigrid_w_fcg, streamer, learned, batch64), or all; "
+                         "each runs min(--steps, 5) steps (batch64: 4)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the reduced-precision (FP32 + refined solve) run")
     ap.add_argument("--calibrate-copy-gb", type=float, default=0.0,
@@ -363,8 +376,13 @@ def main():
         want = None if args.forms == "all" else set(args.forms.split(","))
         run = lambda name: want is None or name in want
         result["forms"] = {}
+        main_args = args
+        args = argparse.Namespace(**vars(main_args))      # the forms run at most 5 steps
+        args.steps = min(main_args.steps, 5)
+        args.warmup = min(main_args.warmup, 1)
         if run("fp32_refined"):
-            result["forms"]["fp32_refined"] = run_fp32_form(args, M, pf, u64, p64, result["poisson_solve_ms"])
+            # as many steps as the FP64 run: its errors are against that run's end state
+            result["forms"]["fp32_refined"] = run_fp32_form(main_args, M, pf, u64, p64, result["poisson_solve_ms"])
             torch.cuda.empty_cache()
         plain_ms = sum(solve_ms) / len(solve_ms)
         if run("stored_matrix_cg"):
@@ -398,6 +416,18 @@ def main():
             torch.cuda.empty_cache()
         if run("learned"):
             result["forms"]["learned"] = run_learned_form(args, M, pf, iters, solve_ms)
+            torch.cuda.empty_cache()
+        if run("batch64"):
+            del M
+            b = run_batch(args, steps=min(args.steps, 4), warmup=args.warmup)
+            result["forms"]["batch64"] = {k: b[k] for k in (
+                "value", "unit", "config", "fv_ms_per_step", "step_plus_solve_ms", "poisson_solve_ms",
+                "poisson_iterations_max_per_solve", "poisson_iterations_mean_per_solve",
+                "poisson_rel_residual_max", "per_launch_solve_ms", "per_launch_iterations_max",
+                "persistent_same_solve_ms", "autotune",
+                "preprocess_s", "workspace_GB", "steps", "warmup")}
+            torch.cuda.empty_cache()
+        args = main_args
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
@@ -467,8 +497,8 @@ def run_fp32_form(args, M, pf, u64, p64, plain_ms):
 def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0, amg=False, cycle=0,
                     kernel_times=True, amg_opts=None):
     """The FP64 run's steps with another solver of the same system: solve time
-    and iterations per step, the solution's difference from the plain run's,
-    and one cold solve (P = 0).  amg: build and attach the multigrid
+    and iterations per step, the last solution's difference from plain
+    Jacobi-CG continued to 1e-12, and one cold solve (P = 0).  amg: build and attach the multigrid
     hierarchy first (its host setup time is reported, outside the timings);
     cycle: its cycle type (0 V, CYCLE_W); amg_opts: its theta / omega.
     kernel_times: time each kernel
@@ -512,17 +542,20 @@ def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0, amg=
     torch.cuda.synchronize()
     kstats = st.kernel_stats() if kernel_times else {}
     st.kernel_timing(False)
-    p = st.get_field(B.FIELD_P)
+    p = st.get_field(B.FIELD_P).clone()
     torch.cuda.synchronize()
     ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
-    perr = float((p - p64).norm() / p64.norm())
+    # the last solution against plain Jacobi-CG taken on to 1e-12 from it
+    st.poisson_solve(None, tol=1e-12, restart=500, matrix_free=True)
+    p_ref = st.get_field(B.FIELD_P)
+    perr = float((p - p_ref).norm() / p_ref.norm())
     del st
     extra = {"multigrid": {"levels": amg_info["levels"], "rows": amg_info["rows"], "nnz": amg_info["nnz"],
                            "host_setup_s": amg_info["setup_ms"] / 1e3}} if amg else {}
     return {**extra, "solver": name, "poisson_solve_ms": ms, "speedup_vs_main_solve": plain_ms / ms,
             "poisson_iterations": [s["iterations"] for s in solves],
             "poisson_rel_residual": max(s["rel_residual"] for s in solves),
-            "P_rel_diff_vs_plain_run": perr,
+            "P_rel_diff_vs_plain_cg_1e-12": perr,
             "cold": {"iterations": cold["iterations"], "ms": cold["ms"]},
             "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in kstats.items() if v[1]},
             "dtype": "f64"}
@@ -737,16 +770,21 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
             "dtype": "bf16 network (fp32 accumulation), f64 flexible CG"}
 
 
-def run_batch(args):
+def run_batch(args, steps=None, warmup=None):
     """Batched form: 64 jittered cubes with log-uniform cell counts in
     [5e4, 2e6] (33.8M cells in all), per-mesh diffusivity and Gaussian
-    centre, all advanced in one state: one launch per kernel for all meshes,
-    per-mesh CFL steps and per-mesh CG, schedule from the autotuner, steps
-    and CG chunks replayed from captured graphs."""
+    centre, all advanced in one state without the stored Poisson matrix:
+    each step an RK3 step of every mesh at its own CFL time step (one launch
+    per kernel for all meshes), then every mesh's warm-started matrix-free
+    Jacobi-CG in the persistent batch kernel (schedule from its autotuner),
+    the whole run captured in one graph.  Also timed: the FV steps alone
+    (cell-updates/s) and one step with the per-launch solver for comparison."""
     import numpy as np
     import torch
     import synth
     from paper_2203_00925_amd import binding as B
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     recipe = synth.batch_recipe()
     t = time.perf_counter()
     meshes = [synth.jittered_cube(r.n, r.seed) for r in recipe]
@@ -756,53 +794,102 @@ def run_batch(args):
     log(f"batch: {len(meshes)} meshes, {sum(m.nc for m in meshes)} cells generated in "
         f"{time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
-    M = B.Mesh.from_batch(meshes)
+    M = B.Mesh.from_batch(meshes, no_matrix=True)
     del meshes
-    log(f"batch preprocessed in {time.perf_counter() - t:.1f}s; workspace {M.info.ws_bytes / 1e9:.2f} GB")
+    t_pre = time.perf_counter() - t
+    log(f"batch preprocessed in {t_pre:.1f}s; workspace {M.info.ws_bytes / 1e9:.2f} GB (no stored matrix)")
     st = B.State(M)
     st.set_mesh_diffusivity([r.diffusivity for r in recipe])
     st.set_bcs(B.VAR_SCALAR, [B.ZERO_FLUX] * 6)
     st.set_bcs(B.VAR_POTENTIAL, [B.DIRICHLET] * 6)
     st.set_field(B.FIELD_VEL, torch.from_numpy(vel))
     st.set_field(B.FIELD_U, torch.from_numpy(u0))
-    st.poisson_assemble()
     st.cfl_dt(0.4)
-    tune = st.autotune(os.path.join(ROOT, "paper_2203_00925_amd", "_lib", "autotune.json"))
-    log(f"autotune: {tune}")
+    bt = B.Batch(st)
+    tune = bt.autotune(os.path.join(ROOT, "paper_2203_00925_amd", "_lib", "batch_tune.json"))
+    log(f"batch autotune: {tune}")
+
     stream = torch.cuda.current_stream()
-    for w in range(args.warmup):
-        st.step_graph(1, 0.0)
-        s = st.poisson_solve(None, tol=1e-10, restart=500, matrix_free=True)
-        log(f"batch warmup {w}: solve max {s['iterations']} it, {s['ms']:.0f} ms")
+    if warmup > 0:
+        w = bt.run(warmup)
+        log(f"batch warmup: {warmup} steps, solve max {w['iterations_max']} it, {w['ms']:.0f} ms")
+    nc = M.info.nc
+    # the FV steps alone (captured step graph), restored afterwards
+    u_keep = st.get_field(B.FIELD_U).clone()
+    st.step_graph(steps, 0.0)                        # capture outside the timing
+    st.set_field(B.FIELD_U, u_keep)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    its = []
+    e0.record(stream)
+    st.step_graph(steps, 0.0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fv_ms = e0.elapsed_time(e1) / steps
+    st.set_field(B.FIELD_U, u_keep)
+    del u_keep
+    # the timed run: steps and persistent solves, one graph (captured by the
+    # first call, so run once untimed with the same arguments)
+    p_keep = st.get_field(B.FIELD_P).clone()
+    u_keep = st.get_field(B.FIELD_U).clone()
+    bt.run(steps)
+    st.set_field(B.FIELD_U, u_keep)
+    st.set_field(B.FIELD_P, p_keep)
+    torch.cuda.synchronize()
+    e0.record(stream)
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        st.step_graph(1, 0.0)
-        ev[k][1].record(stream)
-        s = st.poisson_solve(None, tol=1e-10, restart=500, matrix_free=True)
-        ev[k][2].record(stream)
-        its.append(st.mesh_values("iterations"))
-        log(f"batch step {k}: solve max {s['iterations']} it, rel {s['rel_residual']:.2e}")
+    info = bt.run(steps)
+    e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    fv_ms = sum(e[0].elapsed_time(e[1]) for e in ev)
-    solve_ms = sum(e[1].elapsed_time(e[2]) for e in ev)
-    its = np.array(its)
-    nc = M.info.nc
-    return {"metric": METRIC, "value": nc * args.steps / (fv_ms / 1e3), "unit": "cell-updates/s",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "batch64: 64 jittered 6-tet cubes, cells log-uniform in [5e4, 2e6] "
-                                   f"({nc} in all), per-mesh D and centre; RK3 step with per-mesh CFL "
-                                   "dt + per-mesh warm-started Jacobi-CG (matrix-free product) to 1e-10, one state",
-                       "cells": nc, "meshes": M.info.nmeshes, "parallelism": "single GPU"},
-            "fv_ms_per_step": fv_ms / args.steps, "poisson_solve_ms": solve_ms / args.steps,
-            "poisson_iterations_max": int(its.max()), "poisson_iterations_mean": float(its.mean()),
-            "autotune": tune}
+    run_ms = e0.elapsed_time(e1) / steps
+    its = st.mesh_values("iterations")
+    log(f"batch run: {steps} steps, {run_ms:.0f} ms per step (FV {fv_ms:.1f} ms); solve iterations per mesh "
+        f"max {info['iterations_max']} mean {info['iterations_mean']:.0f} over the run, rel max "
+        f"{info['rel_residual_max']:.2e}")
+    # one more step, then its solve twice from the same start: the per-launch
+    # solver (chunks of iterations for all meshes, host checks between them)
+    # and the persistent kernel
+    st.step_graph(1, 0.0)
+    p_keep = st.get_field(B.FIELD_P).clone()
+    e2 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s_l = st.poisson_solve(None, tol=1e-10, restart=500, matrix_free=True)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = e0.elapsed_time(e2)
+    st.set_field(B.FIELD_P, p_keep)
+    chosen = bt.schedule()
+    # the persistent kernel at its best schedule from the tuner
+    bt.set_schedule(item_rows=tune["p_item_rows"], grid=tune["p_grid"], policy=tune["p_policy"],
+                    vertex_batch=tune["p_vertex_batch"])
+    torch.cuda.synchronize()
+    e0.record(stream)
+    bt_one = bt.solve(tol=1e-10)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    persistent_ms = e0.elapsed_time(e2)
+    bt.set_schedule(**{k: chosen[k] for k in ("item_rows", "grid", "policy", "vertex_batch", "chunk")})
+    log(f"batch: one step's solve per-launch {launch_ms:.0f} ms ({s_l['iterations']} it max) vs persistent "
+        f"{persistent_ms:.0f} ms ({bt_one['iterations_max']} it max)")
+    out = {"metric": METRIC, "value": nc / (fv_ms / 1e3), "unit": "cell-updates/s",
+           "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "batch64: 64 jittered 6-tet cubes, cells log-uniform in [5e4, 2e6] "
+                                  f"({nc} in all), per-mesh D and centre; RK3 step with per-mesh CFL "
+                                  "dt + per-mesh warm-started Jacobi-CG (matrix-free product) to 1e-10, "
+                                  "persistent batch kernel, one graph",
+                      "cells": nc, "meshes": M.info.nmeshes, "parallelism": "single GPU"},
+           "fv_ms_per_step": fv_ms, "step_plus_solve_ms": run_ms, "poisson_solve_ms": run_ms - fv_ms,
+           "poisson_iterations_max_per_solve": int(its.max()),
+           "poisson_iterations_mean_per_solve": float(info["iterations_mean"] / max(info["solves"], 1)),
+           "poisson_rel_residual_max": info["rel_residual_max"],
+           "per_launch_solve_ms": launch_ms, "per_launch_iterations_max": s_l["iterations"],
+           "persistent_same_solve_ms": persistent_ms,
+           "autotune": tune, "preprocess_s": t_pre, "workspace_GB": M.info.ws_bytes / 1e9}
+    del bt, st
+    return out
 
 
 if __name__ == "__main__":

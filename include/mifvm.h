@@ -420,7 +420,11 @@ int mifvm_autotune(mifvm_state* st, const char* cache_path, mifvm_tune_info* out
  * 1 XCD - meshes assigned to the 8 XCDs by size (longest processing time
  * first), an XCD's workgroups take their own meshes first so that a mesh's
  * data stays in one L2, then steal; 2 LARGEST - the largest mesh first
- * everywhere; -1 = 1).                                                      */
+ * everywhere; 3 LAUNCHES - no persistent kernel: the state's per-launch
+ * matrix-free CG, every launch covering all meshes, chunks of iterations
+ * replayed from a captured graph and the host checking the meshes between
+ * chunks (mifvm_batch_run then replays a step graph and these chunks per
+ * step instead of one graph for the whole run); -1 = 1).                   */
 typedef struct mifvm_batch mifvm_batch;
 typedef struct {
     int32_t item_rows;
@@ -428,6 +432,10 @@ typedef struct {
     int32_t policy;
     int32_t spin_limit;        /* polls without progress before the kernel
                                   stops (0 = 2^20; for tests of that path)   */
+    int32_t vertex_batch;      /* vertex-list entries gathered together per
+                                  thread: 8 or 24 (0 = 8)                     */
+    int32_t chunk;             /* LAUNCHES: CG iterations per replayed chunk
+                                  (0 = 32)                                   */
 } mifvm_batch_opts;
 
 typedef struct {
@@ -457,6 +465,10 @@ typedef struct {
     int32_t trials;
     int32_t iterations;        /* iterations per mesh of each timed trial     */
     double ms_best;            /* the chosen schedule's trial                 */
+    int32_t vertex_batch, chunk;
+    double ms_persistent;      /* best persistent-kernel trial                */
+    double ms_launches;        /* best per-launch trial                       */
+    int32_t p_item_rows, p_grid, p_policy, p_vertex_batch;   /* that persistent schedule */
 } mifvm_batch_tune_info;
 
 /* Device workspace of a batch (queues, ranges, partial sums, schedule),
@@ -483,10 +495,12 @@ int mifvm_batch_solve(mifvm_batch* b, const mifvm_batch_solve_opts* opts, mifvm_
 int mifvm_batch_run(mifvm_batch* b, int32_t n_steps, const mifvm_batch_solve_opts* opts, mifvm_batch_info* info,
                     void* stream);
 /* Time `iterations` (0 = 24) iterations of every mesh for queue policy x
- * grid {512, 1024, 2048} at 4096-row items, then item_rows {1024 .. 16384}
- * at the best; keep the fastest and record it in the JSON file cache_path
- * (NULL: none) under "gfx950/batch/<meshes>/<log2 cells>"; a recorded entry
- * is used without timing.  P is restored.  Synchronises.                  */
+ * grid {512, 1024, 2048} at 4096-row items, then item_rows {1024 .. 65536}
+ * and vertex_batch {8, 24} at the best, then LAUNCHES with chunk {16, 32,
+ * 64}; keep the fastest and record it in the JSON file cache_path (NULL:
+ * none) under "gfx950/batch/<meshes>/<log2 cells>"; a recorded entry is used
+ * without timing.  ms_persistent / ms_launches: the best trial of each kind.
+ * P is restored.  Synchronises.                                           */
 int mifvm_batch_autotune(mifvm_batch* b, const char* cache_path, int32_t iterations, mifvm_batch_tune_info* out,
                          void* stream);
 
@@ -618,7 +632,8 @@ enum mifvm_kernel {
     MIFVM_K_NN_TRAIN = 15 /* one whole training step (all of its launches) */,
     MIFVM_K_MF_VERTEX = 16, MIFVM_K_MF_FACE = 17, MIFVM_K_MF_GATHER = 18 /* the matrix-free
     product inside the CG (timed one by one; CG_SPMV then counts the stored-matrix product) */,
-    MIFVM_K_COUNT = 19
+    MIFVM_K_NN_FUSED = 19 /* the whole network in one launch (encoder, 3 layers, decoder) */,
+    MIFVM_K_COUNT = 20
 };
 int mifvm_kernel_timing(mifvm_state* st, int32_t enable);
 /* Total milliseconds and number of timed launches of one kernel since the

@@ -88,8 +88,18 @@ int mifvm_nn_attach_bytes(const mifvm_state* st, int32_t training, size_t* out);
 int mifvm_nn_attach(mifvm_state* st, mifvm_nn* nn, int32_t training, void* d_ws, size_t ws_bytes,
                     void* stream);
 /* d_z = z(d_r), both FP64 in user cell order (for inspection and tests).
- * E_STATE without an attached network or an assembled system.             */
+ * E_STATE without an attached network or an assembled system (or, for
+ * matrix-free use, the diagonal of a solve).  The network runs in one launch
+ * per tile of consecutive cells (the encoding of the cells within three
+ * face-neighbour steps of the tile kept in LDS, every layer evaluated where
+ * the next one reads it), as inside the flexible CG and the multigrid
+ * smoother; a mesh whose tiles exceed the kernel's LDS or register limits
+ * falls back to the layer-by-layer form.                                   */
 int mifvm_nn_apply(mifvm_state* st, const double* d_r, double* d_z, void* stream);
+/* The same network layer by layer: three launches with the activation rows
+ * going through device memory (the form training uses).  Bitwise the same
+ * z as mifvm_nn_apply.                                                     */
+int mifvm_nn_apply_layers(mifvm_state* st, const double* d_r, double* d_z, void* stream);
 /* A training sample from the state's current solve: the true residual
  * r = b - K x of the stored P against the right-hand side of the last solve
  * (or mifvm_poisson_rhs), scaled to unit RMS, written as FP32 in the

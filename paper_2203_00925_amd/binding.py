@@ -27,7 +27,7 @@ FP64, FP32 = 0, 1
 F64, F32 = 0, 1                           # element types of field arrays at the ABI
 KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
            "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble", "nn_layer1", "nn_layer2", "nn_layer3",
-           "fcg_vec", "nn_train", "mf_vertex", "mf_face", "mf_gather")
+           "fcg_vec", "nn_train", "mf_vertex", "mf_face", "mf_gather", "nn_fused")
 NN_PARAMS = 9537
 LOSS_RESIDUAL, LOSS_ENERGY = 0, 1
 
@@ -106,7 +106,7 @@ class SolveInfo(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("item_rows", C.c_int32), ("grid", C.c_int32), ("policy", C.c_int32),
-                ("spin_limit", C.c_int32)]
+                ("spin_limit", C.c_int32), ("vertex_batch", C.c_int32), ("chunk", C.c_int32)]
 
 
 class BatchSolveOpts(C.Structure):
@@ -123,7 +123,10 @@ class BatchInfo(C.Structure):
 class BatchTuneInfo(C.Structure):
     _fields_ = [("item_rows", C.c_int32), ("grid", C.c_int32), ("policy", C.c_int32),
                 ("from_cache", C.c_int32), ("trials", C.c_int32), ("iterations", C.c_int32),
-                ("ms_best", C.c_double)]
+                ("ms_best", C.c_double), ("vertex_batch", C.c_int32), ("chunk", C.c_int32),
+                ("ms_persistent", C.c_double), ("ms_launches", C.c_double),
+                ("p_item_rows", C.c_int32), ("p_grid", C.c_int32), ("p_policy", C.c_int32),
+                ("p_vertex_batch", C.c_int32)]
 
 
 class AmgOpts(C.Structure):
@@ -256,6 +259,7 @@ def _load():
         "mifvm_nn_attach_bytes": (C.c_int, [P, I32, C.POINTER(SZ)]),
         "mifvm_nn_attach": (C.c_int, [P, P, I32, P, SZ, P]),
         "mifvm_nn_apply": (C.c_int, [P, P, P, P]),
+        "mifvm_nn_apply_layers": (C.c_int, [P, P, P, P]),
         "mifvm_nn_sample": (C.c_int, [P, P, C.POINTER(D), P]),
         "mifvm_nn_loss_grad": (C.c_int, [P, P, I32, C.POINTER(D), P, P]),
         "mifvm_nn_train": (C.c_int, [P, P, I32, P, P, I32, C.POINTER(_TrainOpts),
@@ -572,14 +576,15 @@ class State:
         return out
 
 
-BQ_ROTATE, BQ_XCD, BQ_LARGEST = 0, 1, 2
+BQ_ROTATE, BQ_XCD, BQ_LARGEST, BQ_LAUNCHES = 0, 1, 2, 3
 
 
 class Batch:
     """Persistent batched solve of every mesh of a multi-mesh state
     (mifvm_batch_*); the workspace is a torch uint8 tensor."""
 
-    def __init__(self, state, item_rows=0, grid=0, policy=-1, spin_limit=0, stream=None):
+    def __init__(self, state, item_rows=0, grid=0, policy=-1, spin_limit=0, vertex_batch=0, chunk=0,
+                 stream=None):
         import torch
         self.state = state
         n = C.c_size_t()
@@ -588,7 +593,7 @@ class Batch:
         base = self.ws.data_ptr()
         off = (-base) % 256
         h = C.c_void_p()
-        opts = BatchOpts(int(item_rows), int(grid), int(policy), int(spin_limit))
+        opts = BatchOpts(int(item_rows), int(grid), int(policy), int(spin_limit), int(vertex_batch), int(chunk))
         _check(_lib.mifvm_batch_create(state._h, C.byref(opts), C.c_void_p(base + off), n.value,
                                        _stream(stream), C.byref(h)))
         self._h = h
@@ -602,10 +607,11 @@ class Batch:
     def schedule(self):
         o = BatchOpts()
         _check(_lib.mifvm_batch_get_schedule(self._h, C.byref(o)))
-        return {"item_rows": o.item_rows, "grid": o.grid, "policy": o.policy, "spin_limit": o.spin_limit}
+        return {"item_rows": o.item_rows, "grid": o.grid, "policy": o.policy, "spin_limit": o.spin_limit,
+                "vertex_batch": o.vertex_batch, "chunk": o.chunk}
 
-    def set_schedule(self, item_rows=0, grid=0, policy=-1, spin_limit=0, stream=None):
-        o = BatchOpts(int(item_rows), int(grid), int(policy), int(spin_limit))
+    def set_schedule(self, item_rows=0, grid=0, policy=-1, spin_limit=0, vertex_batch=0, chunk=0, stream=None):
+        o = BatchOpts(int(item_rows), int(grid), int(policy), int(spin_limit), int(vertex_batch), int(chunk))
         _check(_lib.mifvm_batch_set_schedule(self._h, C.byref(o), _stream(stream)))
 
     @staticmethod
@@ -712,12 +718,13 @@ class Network:
                     ms=info.ms, epoch_loss=ep)
 
 
-def _state_nn_apply(self, r, stream=None):
-    """z = network(r), FP64 user order."""
+def _state_nn_apply(self, r, stream=None, layers=False):
+    """z = network(r), FP64 user order (layers: the layer-by-layer form)."""
     import torch
     r = r.to(device=self.device, dtype=torch.float64).contiguous()
     z = torch.empty_like(r)
-    _check(_lib.mifvm_nn_apply(self._h, _ptr(r), _ptr(z), _stream(stream)))
+    fn = _lib.mifvm_nn_apply_layers if layers else _lib.mifvm_nn_apply
+    _check(fn(self._h, _ptr(r), _ptr(z), _stream(stream)))
     return z
 
 

@@ -41,7 +41,10 @@ enum BatchPhase : uint32_t {
 enum BatchGlob { BG_DONE = 0, BG_PROGRESS = 1, BG_ABORT = 2, BG_COUNT = 16 };
 
 // queue policies: the order in which a workgroup looks at the meshes
-enum BatchPolicy { BQ_ROTATE = 0, BQ_XCD = 1, BQ_LARGEST = 2 };
+// BQ_LAUNCHES: no persistent kernel - the per-launch matrix-free CG of the
+// state (all meshes per launch, chunks of iterations replayed from a graph,
+// the host checking between chunks)
+enum BatchPolicy { BQ_ROTATE = 0, BQ_XCD = 1, BQ_LARGEST = 2, BQ_LAUNCHES = 3 };
 
 struct BatchRange {
     int64_t c0, c1;     // cells
@@ -68,16 +71,13 @@ struct BatchDev {
     long long spin_limit;             // polls without progress before an abort
 };
 
-// layout of the batch workspace; returns bytes (fills b when base != null)
-size_t batch_layout(const Dev& d, int nm, int64_t pstride_total, char* base, BatchDev& b, int32_t** scan_out,
-                    BatchRange** range_out, int64_t** poff_out, int64_t** pstride_out);
-
 // per-solve reset (queues at BP_OV, scalars, flags); zero_run: also the
 // run's accumulators
 hipError_t launch_batch_init(const Dev& d, const BatchDev& b, int maxit, int restart, bool zero_run,
                              hipStream_t s);
 // the persistent solve of every mesh of the state
-hipError_t launch_batch_solve(const Dev& d, const BatchDev& b, int grid, double tol, hipStream_t s);
+hipError_t launch_batch_solve(const Dev& d, const BatchDev& b, int grid, int vertex_batch, double tol,
+                              hipStream_t s);
 // ghost factors from the potential's boundary kinds
 hipError_t launch_batch_gsign(const Dev& d, const BatchDev& b, const BcTable& bc_pot, hipStream_t s);
 

@@ -29,7 +29,7 @@ struct mifvm_batch {
     std::vector<BatchRange> range;
     std::vector<int64_t> cells;
     int32_t* d_scan = nullptr;                // device scan lists [8][nm]
-    int grid = 0, item_rows = 0, policy = 0;
+    int grid = 0, item_rows = 0, policy = 0, vb = 8, chunk = 32;
     hipGraphExec_t exec = nullptr;            // captured run
     int exec_steps = 0, exec_every = 0, exec_maxit = 0, exec_restart = 0;
     double exec_tol = 0.0;
@@ -172,12 +172,18 @@ int upload_schedule(mifvm_batch* h, hipStream_t hs) {
     return MIFVM_OK;
 }
 
-int check_schedule(int item_rows, int grid, int policy) {
+int check_schedule(int item_rows, int grid, int policy, int vb, int chunk) {
     if (item_rows < kBatchMinItemRows || item_rows % kBatchBlock != 0 || item_rows > (1 << 20))
         return fail(MIFVM_E_ARG, "item_rows must be a multiple of 256 in [256, 2^20]");
     if (grid < 1 || grid > 65536) return fail(MIFVM_E_ARG, "grid must be in [1, 65536]");
-    if (policy < BQ_ROTATE || policy > BQ_LARGEST) return fail(MIFVM_E_ARG, "unknown queue policy");
+    if (policy < BQ_ROTATE || policy > BQ_LAUNCHES) return fail(MIFVM_E_ARG, "unknown queue policy");
+    if (vb != 8 && vb != 24) return fail(MIFVM_E_ARG, "vertex_batch must be 8 or 24");
+    if (chunk < 1 || chunk > 4096) return fail(MIFVM_E_ARG, "chunk must be in [1, 4096]");
     return MIFVM_OK;
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 // the solve's device work on q (no host interaction)
@@ -186,8 +192,50 @@ hipError_t enqueue_solve(const mifvm_batch* h, double tol, int maxit, int restar
     hipError_t e = launch_rhs(s.d, s.d.u, q);                  // b = -mu u + c
     if (e == hipSuccess) e = launch_batch_gsign(s.d, h->b, s.bc[1], q);
     if (e == hipSuccess) e = launch_batch_init(s.d, h->b, maxit, restart, zero_run, q);
-    if (e == hipSuccess) e = launch_batch_solve(s.d, h->b, h->grid, tol, q);
+    if (e == hipSuccess) e = launch_batch_solve(s.d, h->b, h->grid, h->vb, tol, q);
     return e;
+}
+
+// LAUNCHES: the state's per-launch matrix-free CG (b = -mu U + c from the
+// current U); run totals added into it / rel
+int solve_launches(mifvm_batch* h, double tol, int maxit, int restart, hipStream_t hs, std::vector<int64_t>& it,
+                   std::vector<double>& rel) {
+    mifvm_solve_opts o{};
+    o.tol = tol;
+    o.maxit = maxit;
+    o.chunk = h->chunk;
+    o.restart = restart;
+    o.method = MIFVM_SOLVE_PLAIN;
+    o.graph = 1;
+    o.matrix_free = 1;
+    mifvm_solve_info si{};
+    const int rc = mifvm_poisson_solve(h->st, nullptr, &o, &si, hs);
+    if (rc < 0) return rc;
+    const State& s = h->st->s;
+    for (int m = 0; m < h->b.nm; ++m) {
+        it[m] += s.last_iters[m];
+        rel[m] = std::fmax(rel[m], s.last_rel[m]);
+    }
+    return MIFVM_OK;
+}
+
+// the outcome of LAUNCHES solves, in the form collect() reports
+int report_launches(mifvm_batch* h, const std::vector<int64_t>& it, const std::vector<double>& rel,
+                    mifvm_batch_info* info, double t0_ms, int solves) {
+    const State& s = h->st->s;
+    mifvm_batch_info out{};
+    bool all = true;
+    for (int m = 0; m < h->b.nm; ++m) {
+        out.iterations_max = std::max<int64_t>(out.iterations_max, it[m]);
+        out.iterations_sum += it[m];
+        out.rel_residual_max = std::fmax(out.rel_residual_max, rel[m]);
+        all = all && hsc(s, m, SC_DONE) == 1.0;
+    }
+    out.solves = solves;
+    out.iterations_mean = h->b.nm > 0 ? double(out.iterations_sum) / h->b.nm : 0.0;
+    out.ms = now_ms() - t0_ms;
+    if (info) *info = out;
+    return all ? MIFVM_OK : MIFVM_NOT_CONVERGED;
 }
 
 int solve_opts(const mifvm_batch_solve_opts* o, double& tol, int& maxit, int& restart, int& every) {
@@ -197,10 +245,6 @@ int solve_opts(const mifvm_batch_solve_opts* o, double& tol, int& maxit, int& re
     every = o && o->solve_every > 0 ? o->solve_every : 1;
     if (!(tol > 0) || restart < 0) return fail(MIFVM_E_ARG, "bad tol or restart");
     return MIFVM_OK;
-}
-
-double now_ms() {
-    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 // per-mesh outcome after the device work: scalars, the run accumulators,
@@ -264,7 +308,9 @@ int mifvm_batch_create(mifvm_state* st, const mifvm_batch_opts* opts, void* d_ws
     const int item_rows = opts && opts->item_rows > 0 ? opts->item_rows : kDefaultItemRows;
     const int grid = opts && opts->grid > 0 ? opts->grid : kDefaultGrid;
     const int policy = opts && opts->policy >= 0 ? opts->policy : kDefaultPolicy;
-    int rc = check_schedule(item_rows, grid, policy);
+    const int vb = opts && opts->vertex_batch > 0 ? opts->vertex_batch : 8;
+    const int chunk = opts && opts->chunk > 0 ? opts->chunk : 32;
+    int rc = check_schedule(item_rows, grid, policy, vb, chunk);
     if (rc) return rc;
     auto* h = new (std::nothrow) mifvm_batch();
     if (!h) return fail(MIFVM_E_ARG, "out of host memory");
@@ -288,6 +334,8 @@ int mifvm_batch_create(mifvm_state* st, const mifvm_batch_opts* opts, void* d_ws
     h->item_rows = item_rows;
     h->grid = grid;
     h->policy = policy;
+    h->vb = vb;
+    h->chunk = chunk;
     hipStream_t hs = S(stream);
     std::vector<int64_t> poff(h->cells.size()), pstride(h->cells.size());
     int64_t at = 0;
@@ -328,11 +376,15 @@ int mifvm_batch_set_schedule(mifvm_batch* h, const mifvm_batch_opts* opts, void*
     const int item_rows = opts->item_rows > 0 ? opts->item_rows : h->item_rows;
     const int grid = opts->grid > 0 ? opts->grid : h->grid;
     const int policy = opts->policy >= 0 ? opts->policy : h->policy;
-    int rc = check_schedule(item_rows, grid, policy);
+    const int vb = opts->vertex_batch > 0 ? opts->vertex_batch : h->vb;
+    const int chunk = opts->chunk > 0 ? opts->chunk : h->chunk;
+    int rc = check_schedule(item_rows, grid, policy, vb, chunk);
     if (rc) return rc;
     h->item_rows = item_rows;
     h->grid = grid;
     h->policy = policy;
+    h->vb = vb;
+    h->chunk = chunk;
     if (opts->spin_limit > 0) h->b.spin_limit = opts->spin_limit;
     return upload_schedule(h, S(stream));
 }
@@ -344,6 +396,8 @@ int mifvm_batch_get_schedule(const mifvm_batch* h, mifvm_batch_opts* out) {
     out->grid = h->grid;
     out->policy = h->policy;
     out->spin_limit = int32_t(h->b.spin_limit);
+    out->vertex_batch = h->vb;
+    out->chunk = h->chunk;
     return MIFVM_OK;
 }
 
@@ -357,6 +411,12 @@ int mifvm_batch_solve(mifvm_batch* h, const mifvm_batch_solve_opts* opts, mifvm_
     hipStream_t hs = S(stream);
     const double t0 = now_ms();
     if ((rc = ensure_consts(s, hs))) return rc;
+    if (h->policy == BQ_LAUNCHES) {
+        std::vector<int64_t> it(h->b.nm, 0);
+        std::vector<double> rel(h->b.nm, 0.0);
+        if ((rc = solve_launches(h, tol, maxit, restart, hs, it, rel))) return rc;
+        return report_launches(h, it, rel, info, t0, 1);
+    }
     HIPCHK(enqueue_solve(h, tol, maxit, restart, true, hs));
     s.b_ready = true;
     return collect(h, hs, info, t0, 1);
@@ -375,6 +435,19 @@ int mifvm_batch_run(mifvm_batch* h, int32_t n_steps, const mifvm_batch_solve_opt
     hipStream_t hs = S(stream);
     const double t0 = now_ms();
     if ((rc = ensure_consts(s, hs))) return rc;
+    if (h->policy == BQ_LAUNCHES) {             // a step graph and the chunked solve per step
+        std::vector<int64_t> it(h->b.nm, 0);
+        std::vector<double> rel(h->b.nm, 0.0);
+        int solves = 0;
+        for (int k = 0; k < n_steps; ++k) {
+            if ((rc = mifvm_step_graph(h->st, 1, 0.0, stream))) return rc;
+            if ((k + 1) % every == 0) {
+                if ((rc = solve_launches(h, tol, maxit, restart, hs, it, rel))) return rc;
+                ++solves;
+            }
+        }
+        return report_launches(h, it, rel, info, t0, solves);
+    }
     if (!h->exec || h->exec_steps != n_steps || h->exec_every != every || h->exec_tol != tol ||
         h->exec_maxit != maxit || h->exec_restart != restart || h->exec_gen != s.graph_gen) {
         HIPCHK(capture_graph(s, &h->exec, [&](hipStream_t q) -> hipError_t {
@@ -405,27 +478,32 @@ int mifvm_batch_run(mifvm_batch* h, int32_t n_steps, const mifvm_batch_solve_opt
 
 namespace {
 
-std::map<std::string, std::array<int, 3>> read_batch_cache(const char* path) {
-    std::map<std::string, std::array<int, 3>> out;
+using TuneEntry = std::array<int, 5>;       // item_rows, grid, policy, vertex_batch, chunk
+
+std::map<std::string, TuneEntry> read_batch_cache(const char* path) {
+    std::map<std::string, TuneEntry> out;
     std::ifstream in(path);
     std::string line;
     while (std::getline(in, line)) {
         char key[256];
-        int a = 0, g = 0, p = 0;
-        if (std::sscanf(line.c_str(), " \"%255[^\"]\": {\"item_rows\": %d, \"grid\": %d, \"policy\": %d}", key, &a,
-                        &g, &p) == 4)
-            out[key] = {a, g, p};
+        TuneEntry e{};
+        if (std::sscanf(line.c_str(),
+                        " \"%255[^\"]\": {\"item_rows\": %d, \"grid\": %d, \"policy\": %d, \"vertex_batch\": %d, "
+                        "\"chunk\": %d}",
+                        key, &e[0], &e[1], &e[2], &e[3], &e[4]) == 6)
+            out[key] = e;
     }
     return out;
 }
 
-void write_batch_cache(const char* path, const std::map<std::string, std::array<int, 3>>& m) {
+void write_batch_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
     std::ofstream o(path);
     o << "{\n";
     size_t k = 0;
     for (auto& kv : m)
         o << "  \"" << kv.first << "\": {\"item_rows\": " << kv.second[0] << ", \"grid\": " << kv.second[1]
-          << ", \"policy\": " << kv.second[2] << "}" << (++k < m.size() ? "," : "") << "\n";
+          << ", \"policy\": " << kv.second[2] << ", \"vertex_batch\": " << kv.second[3]
+          << ", \"chunk\": " << kv.second[4] << "}" << (++k < m.size() ? "," : "") << "\n";
     o << "}\n";
 }
 
@@ -441,20 +519,27 @@ extern "C" int mifvm_batch_autotune(mifvm_batch* h, const char* cache_path, int3
     while ((int64_t(1) << (lg + 1)) <= d.nc) ++lg;
     const std::string key = "gfx950/batch/" + std::to_string(d.nm) + "/" + std::to_string(lg);
     mifvm_batch_tune_info info{};
-    std::map<std::string, std::array<int, 3>> cache;
+    std::map<std::string, TuneEntry> cache;
+    auto apply = [&](const TuneEntry& e) -> int {
+        mifvm_batch_opts o{};
+        o.item_rows = e[0];
+        o.grid = e[1];
+        o.policy = e[2];
+        o.vertex_batch = e[3];
+        o.chunk = e[4];
+        return mifvm_batch_set_schedule(h, &o, stream);
+    };
     if (cache_path) {
         cache = read_batch_cache(cache_path);
         auto it = cache.find(key);
         if (it != cache.end()) {
-            mifvm_batch_opts o{};
-            o.item_rows = it->second[0];
-            o.grid = it->second[1];
-            o.policy = it->second[2];
-            int rc = mifvm_batch_set_schedule(h, &o, stream);
+            int rc = apply(it->second);
             if (rc) return rc;
-            info.item_rows = o.item_rows;
-            info.grid = o.grid;
-            info.policy = o.policy;
+            info.item_rows = h->item_rows;
+            info.grid = h->grid;
+            info.policy = h->policy;
+            info.vertex_batch = h->vb;
+            info.chunk = h->chunk;
             info.from_cache = 1;
             if (out) *out = info;
             return MIFVM_OK;
@@ -463,65 +548,100 @@ extern "C" int mifvm_batch_autotune(mifvm_batch* h, const char* cache_path, int3
     const int iters = iterations > 0 ? iterations : 24;
     int rc = ensure_consts(s, hs);
     if (rc) return rc;
-    // the trials run `iters` iterations of every mesh from the current P,
-    // which is restored afterwards
-    double* saved_x = d.tmp;
+    // every trial runs `iters` iterations of every mesh from the current P,
+    // which is restored afterwards (kept in the scratch array's last third:
+    // the per-launch solve's true residual uses its first)
+    double* saved_x = d.tmp + 2 * (d.nc + d.nb);
     HIPCHK(hipMemcpyAsync(saved_x, d.x, d.nc * sizeof(double), hipMemcpyDeviceToDevice, hs));
-    auto trial = [&](int item_rows, int grid, int policy, double* ms) -> int {
-        mifvm_batch_opts o{};
-        o.item_rows = item_rows;
-        o.grid = grid;
-        o.policy = policy;
-        int r = mifvm_batch_set_schedule(h, &o, stream);
+    auto trial = [&](const TuneEntry& e, double* ms) -> int {
+        int r = apply(e);
         if (r) return r;
         HIPCHK(hipMemcpyAsync(d.x, saved_x, d.nc * sizeof(double), hipMemcpyDeviceToDevice, hs));
         HIPCHK(hipStreamSynchronize(hs));
         const double t0 = now_ms();
-        HIPCHK(enqueue_solve(h, 1e-300, iters, 0, true, hs));     // never converged: exactly iters each
+        if (h->policy == BQ_LAUNCHES) {
+            std::vector<int64_t> it(h->b.nm, 0);
+            std::vector<double> rel(h->b.nm, 0.0);
+            if ((r = solve_launches(h, 1e-300, iters, 0, hs, it, rel))) return r;
+        } else {
+            HIPCHK(enqueue_solve(h, 1e-300, iters, 0, true, hs));   // never converged: exactly iters each
+        }
         HIPCHK(hipStreamSynchronize(hs));
         *ms = now_ms() - t0;
-        unsigned int glob[BG_COUNT];
-        HIPCHK(hipMemcpy(glob, h->b.glob, sizeof(glob), hipMemcpyDeviceToHost));
-        if (glob[BG_ABORT]) return fail(MIFVM_E_STATE, "persistent batch solve stopped during autotuning");
+        if (h->policy != BQ_LAUNCHES) {
+            unsigned int glob[BG_COUNT];
+            HIPCHK(hipMemcpy(glob, h->b.glob, sizeof(glob), hipMemcpyDeviceToHost));
+            if (glob[BG_ABORT]) return fail(MIFVM_E_STATE, "persistent batch solve stopped during autotuning");
+        }
         return MIFVM_OK;
     };
     double ms = 0.0;
-    if ((rc = trial(kDefaultItemRows, kDefaultGrid, kDefaultPolicy, &ms))) return rc;   // warm-up
-    double best = 1e300;
-    int bi = kDefaultItemRows, bg = kDefaultGrid, bp = kDefaultPolicy;
+    TuneEntry best_p = {kDefaultItemRows, kDefaultGrid, kDefaultPolicy, 8, h->chunk};
+    if ((rc = trial(best_p, &ms))) return rc;                      // warm-up
+    double tp = 1e300;
     int n = 0;
     for (int policy : {BQ_ROTATE, BQ_XCD, BQ_LARGEST})
         for (int grid : {512, 1024, 2048}) {
-            if ((rc = trial(kDefaultItemRows, grid, policy, &ms))) return rc;
+            const TuneEntry e = {kDefaultItemRows, grid, policy, 8, h->chunk};
+            if ((rc = trial(e, &ms))) return rc;
             ++n;
-            if (ms < best) {
-                best = ms;
-                bg = grid;
-                bp = policy;
+            if (ms < tp) {
+                tp = ms;
+                best_p = e;
             }
         }
-    for (int item_rows : {1024, 2048, 8192, 16384}) {
-        if ((rc = trial(item_rows, bg, bp, &ms))) return rc;
+    for (int item_rows : {1024, 2048, 8192, 16384, 32768, 65536}) {
+        TuneEntry e = best_p;
+        e[0] = item_rows;
+        if ((rc = trial(e, &ms))) return rc;
         ++n;
-        if (ms < best) {
-            best = ms;
-            bi = item_rows;
+        if (ms < tp) {
+            tp = ms;
+            best_p = e;
+        }
+    }
+    {
+        TuneEntry e = best_p;
+        e[3] = 24;
+        if ((rc = trial(e, &ms))) return rc;
+        ++n;
+        if (ms < tp) {
+            tp = ms;
+            best_p = e;
+        }
+    }
+    double tl = 1e300;
+    TuneEntry best_l = best_p;
+    for (int chunk : {16, 32, 64}) {
+        TuneEntry e = best_p;
+        e[2] = BQ_LAUNCHES;
+        e[4] = chunk;
+        if ((rc = trial(e, &ms))) return rc;
+        ++n;
+        if (ms < tl) {
+            tl = ms;
+            best_l = e;
         }
     }
     HIPCHK(hipMemcpyAsync(d.x, saved_x, d.nc * sizeof(double), hipMemcpyDeviceToDevice, hs));
-    mifvm_batch_opts o{};
-    o.item_rows = bi;
-    o.grid = bg;
-    o.policy = bp;
-    if ((rc = mifvm_batch_set_schedule(h, &o, stream))) return rc;
-    info.item_rows = bi;
-    info.grid = bg;
-    info.policy = bp;
+    const TuneEntry best = tl < tp ? best_l : best_p;
+    if ((rc = apply(best))) return rc;
+    info.item_rows = best[0];
+    info.grid = best[1];
+    info.policy = best[2];
+    info.vertex_batch = best[3];
+    info.chunk = best[4];
     info.trials = n;
-    info.ms_best = best;
+    info.ms_best = std::fmin(tp, tl);
+    info.ms_persistent = tp;
+    info.ms_launches = tl;
+    info.p_item_rows = best_p[0];
+    info.p_grid = best_p[1];
+    info.p_policy = best_p[2];
+    info.p_vertex_batch = best_p[3];
     info.iterations = iters;
     if (cache_path) {
-        cache[key] = {bi, bg, bp};
+        cache[key] = best;
         write_batch_cache(cache_path, cache);
     }
     if (out) *out = info;

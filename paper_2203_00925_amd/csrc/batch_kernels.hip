@@ -30,6 +30,20 @@ __device__ inline int64_t phase_items(const BatchDev& b, const BatchRange& r, ui
     return (phase_rows(r, ph) + b.item_rows - 1) / b.item_rows;
 }
 
+// queue word: item index in bits 0-31, phase in 32-39, phase epoch (counts
+// the mesh's phase changes) in 40-63
+__device__ inline uint32_t q_phase(unsigned long long w) { return uint32_t(w >> 32) & 0xffu; }
+__device__ inline uint32_t q_epoch(unsigned long long w) { return uint32_t(w >> 40); }
+__device__ inline int64_t q_item(unsigned long long w) { return int64_t(w & 0xffffffffull); }
+__device__ inline unsigned long long q_word(uint32_t epoch, uint32_t phase) {
+    return ((unsigned long long)(epoch & 0xffffffu) << 40) | ((unsigned long long)phase << 32);
+}
+// fences at device (agent) scope: a release writes back what this
+// workgroup stored, an acquire drops stale cached copies; each is paid only
+// where the queue protocol needs it
+__device__ inline void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ inline void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 __device__ inline unsigned long long ld_q(const unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -38,15 +52,12 @@ __device__ inline unsigned int ld_u(const unsigned int* p) {
 }
 
 // x_v = sum alpha_{v,e} src_e over the vertex list; a ghost entry stands for
-// s_g src_owner.  Entries in batches of kVb, the indices and weights of a
-// batch loaded before its values, summed in list order (as the single-mesh
-// vertex kernel, so the values are the same bits).  The batch is smaller
-// than that kernel's 24 so that the persistent kernel, which holds every
-// phase's registers, keeps more waves resident.
-#ifndef MIFVM_BATCH_VB
-#define MIFVM_BATCH_VB 8
-#endif
-constexpr int kVb = MIFVM_BATCH_VB;
+// s_g src_owner.  Entries in batches of VB (a schedule choice: 24, the
+// single-mesh vertex kernel's, keeps more gathers in flight; 8 needs fewer
+// registers, so more waves stay resident), the indices and weights of a
+// batch loaded before its values, summed in list order (so the values are
+// the single-mesh kernel's bits).
+template <int kVb>
 __device__ inline double vertex_value(const Dev& d, const BatchDev& b, const double* __restrict__ src, int64_t v) {
     const int64_t sl = v >> 6;
     const int64_t base = d.n_off[sl] + (v & 63);
@@ -112,6 +123,7 @@ __device__ inline double gather_row(const Dev& d, const double* __restrict__ F, 
 
 // one item: rows [lo, hi) of the phase's range; partial sums of the item
 // into its slots
+template <int VB>
 __device__ void run_item(const Dev& d, const BatchDev& b, const BatchRange& r, uint32_t ph, int m, int64_t item,
                          double* lds) {
     const int64_t lo = item * b.item_rows;
@@ -123,7 +135,7 @@ __device__ void run_item(const Dev& d, const BatchDev& b, const BatchRange& r, u
         case BP_OV:
         case BP_V: {
             const double* src = ph == BP_OV ? d.x : d.p;
-            for (int64_t k = lo + tid; k < hi; k += kBatchBlock) d.mf_xv[r.v0 + k] = vertex_value(d, b, src, r.v0 + k);
+            for (int64_t k = lo + tid; k < hi; k += kBatchBlock) d.mf_xv[r.v0 + k] = vertex_value<VB>(d, b, src, r.v0 + k);
             break;
         }
         case BP_OF:
@@ -295,18 +307,20 @@ __device__ uint32_t finish_phase(const Dev& d, const BatchDev& b, const BatchRan
     }
 }
 
+template <int VB>
 __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(Dev d, BatchDev b, double tol) {
     __shared__ double lds[4];
-    __shared__ long long s_cmd[3];           // phase (-1 none, -2 exit), mesh, item
+    __shared__ long long s_cmd[4];           // phase (-1 none, -2 exit), mesh, item, epoch
     __shared__ int s_last;
     const int tid = threadIdx.x;
     const int nm = b.nm;
     const int32_t* scan = b.scan + int64_t(blockIdx.x % 8) * nm;
     unsigned int seen = 0xffffffffu;
     long long idle = 0;
+    long long last_m = -1, last_ep = -1;     // wave 0: the epoch last acquired
     for (;;) {
         if (tid < 64) {                       // wave 0 looks for an item
-            long long cph = -1, cm = 0, ci = 0;
+            long long cph = -1, cm = 0, ci = 0, cep = 0;
             // the global words as lane 0 reads them (one value for the wave)
             const unsigned int gdone = __shfl(ld_u(&b.glob[BG_DONE]), 0, 64);
             const unsigned int gabort = __shfl(ld_u(&b.glob[BG_ABORT]), 0, 64);
@@ -320,7 +334,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(Dev d, BatchDev b, 
                     if (k < nm) {
                         m = scan[k];
                         const unsigned long long w = ld_q(&b.q[m]);
-                        avail = int64_t(w & 0xffffffffull) < phase_items(b, b.range[m], uint32_t(w >> 32));
+                        avail = q_item(w) < phase_items(b, b.range[m], q_phase(w));
                     }
                     unsigned long long mask = __ballot(avail);
                     while (mask != 0ull && cph == -1) {
@@ -329,13 +343,14 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(Dev d, BatchDev b, 
                         unsigned long long w2 = 0ull;
                         if (tid == lane) {
                             w2 = atomicAdd(&b.q[m], 1ull);
-                            ok = int64_t(w2 & 0xffffffffull) < phase_items(b, b.range[m], uint32_t(w2 >> 32));
+                            ok = q_item(w2) < phase_items(b, b.range[m], q_phase(w2));
                         }
                         ok = __shfl(ok, lane, 64);
                         if (ok) {
                             const unsigned lo32 = __shfl(unsigned(w2 & 0xffffffffull), lane, 64);
                             const unsigned hi32 = __shfl(unsigned(w2 >> 32), lane, 64);
-                            cph = hi32;
+                            cph = hi32 & 0xffu;
+                            cep = hi32 >> 8;
                             cm = __shfl(m, lane, 64);
                             ci = lo32;
                         }
@@ -353,11 +368,18 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(Dev d, BatchDev b, 
                     }
                 }
             }
-            if (cph >= 0) __threadfence();      // acquire: the phase's inputs, written by other workgroups
+            // acquire the phase's inputs (written by other workgroups) once
+            // per phase epoch: later items of the same epoch read the same data
+            if (cph >= 0 && (cm != last_m || cep != last_ep)) {
+                fence_acquire();
+                last_m = cm;
+                last_ep = cep;
+            }
             if (tid == 0) {
                 s_cmd[0] = cph;
                 s_cmd[1] = cm;
                 s_cmd[2] = ci;
+                s_cmd[3] = cep;
             }
             if (cph == -1) __builtin_amdgcn_s_sleep(2);
         }
@@ -371,13 +393,13 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(Dev d, BatchDev b, 
         const int m = int(s_cmd[1]);
         const int64_t item = s_cmd[2];
         const BatchRange r = b.range[m];
-        run_item(d, b, r, uint32_t(ph), m, item, lds);
-        __syncthreads();                        // the item's stores precede the release below
+        run_item<VB>(d, b, r, uint32_t(ph), m, item, lds);
+        fence_release();                        // every wave releases its stores of the item
+        __syncthreads();                        // ... before the item is counted
         if (tid == 0) {
-            __threadfence();                    // release the item's results
             const unsigned int old = atomicAdd(&b.done[m], 1u);
             s_last = int64_t(old) + 1 == phase_items(b, r, uint32_t(ph)) ? 1 : 0;
-            if (s_last) __threadfence();        // acquire every other item's results
+            if (s_last) fence_acquire();        // every other item's results
         }
         __syncthreads();
         if (s_last) {
@@ -385,8 +407,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(Dev d, BatchDev b, 
             __syncthreads();                    // scalars written before they are released
             if (tid == 0) {
                 atomicExch(&b.done[m], 0u);
-                __threadfence();
-                atomicExch(&b.q[m], (unsigned long long)next << 32);
+                fence_release();                // scalars and the reset before the new phase
+                atomicExch(&b.q[m], q_word(uint32_t(s_cmd[3]) + 1u, next));
                 atomicAdd(&b.glob[BG_PROGRESS], 1u);
                 if (next == BP_IDLE) atomicAdd(&b.glob[BG_DONE], 1u);
             }
@@ -400,7 +422,7 @@ __global__ void k_batch_init(Dev d, BatchDev b, int maxit, int restart, int zero
     if (m == 0)
         for (int k = 0; k < BG_COUNT; ++k) b.glob[k] = 0u;
     if (m >= b.nm) return;
-    b.q[m] = (unsigned long long)BP_OV << 32;
+    b.q[m] = q_word(0u, BP_OV);
     b.done[m] = 0u;
     b.fresh[m] = 1;
     double* sc = msc(d, m);
@@ -429,8 +451,12 @@ hipError_t launch_batch_init(const Dev& d, const BatchDev& b, int maxit, int res
     return hipGetLastError();
 }
 
-hipError_t launch_batch_solve(const Dev& d, const BatchDev& b, int grid, double tol, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_solve, dim3(unsigned(grid)), dim3(kBatchBlock), 0, s, d, b, tol);
+hipError_t launch_batch_solve(const Dev& d, const BatchDev& b, int grid, int vertex_batch, double tol,
+                              hipStream_t s) {
+    if (vertex_batch == 24)
+        hipLaunchKernelGGL(k_batch_solve<24>, dim3(unsigned(grid)), dim3(kBatchBlock), 0, s, d, b, tol);
+    else
+        hipLaunchKernelGGL(k_batch_solve<8>, dim3(unsigned(grid)), dim3(kBatchBlock), 0, s, d, b, tol);
     return hipGetLastError();
 }
 

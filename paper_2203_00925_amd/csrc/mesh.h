@@ -2,10 +2,13 @@
 // library's internal numbering (cells on a Morton curve of their centres).
 #pragma once
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
 namespace mifvm {
+
+struct NnTiles;
 
 // Rows packed in slices of 64 (one wavefront): slice s stores entry k of row
 // 64*s + lane at off[s] + k*64 + lane, for k < width[s].  Short rows are
@@ -88,6 +91,8 @@ struct Mesh {
     std::vector<uint16_t> f_lidx;
     std::vector<uint16_t> c2v_l;      // 4 x nc tile-local vertex number
     int32_t tv_max = 0;               // most vertices touched by one tile
+    // tiles of the network's fused forward, built on first use
+    mutable std::shared_ptr<const NnTiles> nn_tiles;
 };
 
 // Returns 0 or a negative mifvm status; err receives a message.

@@ -73,6 +73,31 @@ struct NnDev {
 };
 constexpr int kNnLossRing = 65536;
 
+// Tiles of the fused forward: tile t holds `tile_rows` consecutive cells
+// (ring 0) and the cells within three face-neighbour steps of them (rings
+// 1-3), each ring in ascending cell order; the face neighbours of rings 0-2
+// as indices into the tile's list (0xFFFF: a boundary face).  Three layers
+// of the network at the tile's own cells read the first layer's output on
+// rings 0-2, which reads the encoding on rings 0-3.
+struct NnTiles {
+    int32_t tile_rows = 0;
+    int32_t ext_max = 0;              // most cells of one tile's list
+    int32_t r2_max = 0;               // most cells of rings 0-2 of one tile
+    int64_t ntiles = 0;
+    std::vector<int64_t> ext_off;     // [ntiles + 1]
+    std::vector<int32_t> ring;        // [ntiles][4] cumulative ring sizes
+    std::vector<int32_t> cell;        // the lists
+    std::vector<int64_t> nb_off;      // [ntiles + 1]
+    std::vector<uint16_t> nb;         // [entries of rings 0-2][4]
+};
+constexpr int kNnFusedMaxGroups = 16;           // 16-cell groups per wave and layer (registers)
+constexpr int kNnFusedWaves = 4;
+constexpr size_t kNnFusedLdsMax = 78 * 1024;    // two workgroups per CU
+// the tiles of a mesh (largest tile size <= 256 that fits the limits;
+// computed once per mesh and kept with it); null if none fits
+const NnTiles* nn_tiles(const Mesh& m);
+inline size_t nn_fused_lds(const NnTiles& t) { return size_t(t.ext_max) * 64 + size_t(t.r2_max) * 8; }
+
 // Per-state buffers of an attached network.
 struct NnStateDev {
     int4* nbr;              // [nc] face neighbours (internal numbering, -1: none)
@@ -87,6 +112,14 @@ struct NnStateDev {
     double* kt_val;         // [matrix_padded] values of K^T in K's pattern
     int32_t* flag;          // [1] pattern check of the transpose (0 = ok)
     bool training;
+    // fused forward (null tables: the three-launch forward is used)
+    const NnTiles* tiles = nullptr;
+    int64_t* t_ext_off;
+    int4* t_ring;
+    int32_t* t_cell;
+    int64_t* t_nb_off;
+    ushort4* t_nb;
+    double* t_partial;      // [2][ntiles] z.r, z.r_old per tile
 };
 
 size_t nn_layout(char* base, NnDev& n);
@@ -104,6 +137,14 @@ hipError_t launch_nn_scale(const Dev& d, const double* r64, const float* r32, hi
 hipError_t launch_nn_layer(const Dev& d, const NnDev& n, const NnStateDev& a, int layer, const double* r64,
                            const float* r32, double* z, bool keep_h3, bool fcg, hipStream_t s);
 int nn_forward_grid(int64_t nc);
+// the whole forward in one launch on the state's tiles (z from r64); fcg:
+// skipped once the solve is done, per-tile partial z.r and z.r_old
+hipError_t launch_nn_fused(const Dev& d, const NnDev& n, const NnStateDev& a, const double* r64, double* z,
+                           bool fcg, hipStream_t s);
+// kernel attribute for dynamic LDS above 64 KB (once per tile set)
+hipError_t setup_nn_fused(size_t lds);
+// partial sums the forward leaves for the flexible CG's z.r and z.r_old
+int64_t nn_forward_parts(const Dev& d, const NnStateDev& a);
 int nn_backward_grid(int64_t nc);
 // training, after the forward on r32 (z in d.z): the loss (kind 0 residual,
 // 1 energy) into *loss_slot, its gradient w.r.t. z, the backward and the
@@ -120,9 +161,9 @@ hipError_t launch_nn_sample(const Dev& d, float* out, hipStream_t s);
 // kx: K x computed matrix-free by the caller, or null for the stored K
 hipError_t launch_fcg_setup(const Dev& d, double tol, int maxit, int restart, bool fresh, hipStream_t s,
                             const double* kx = nullptr);
-hipError_t launch_fcg_setup_tail(const Dev& d, hipStream_t s);
+hipError_t launch_fcg_setup_tail(const Dev& d, const NnStateDev& a, hipStream_t s);
 hipError_t launch_fcg_axpy(const Dev& d, const NnStateDev& a, hipStream_t s);
-hipError_t launch_fcg_beta(const Dev& d, hipStream_t s);
+hipError_t launch_fcg_beta(const Dev& d, const NnStateDev& a, hipStream_t s);
 hipError_t launch_fcg_backup(const Dev& d, const NnStateDev& a, bool restore, hipStream_t s);
 
 }  // namespace mifvm

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <random>
 #include <vector>
@@ -39,6 +40,74 @@ size_t nn_layout(char* base, NnDev& n) {
     return (off + 255) & ~size_t(255);
 }
 
+namespace {
+// the tiles of size T; false if a limit of the fused kernel is exceeded
+bool build_tiles(const Mesh& m, int T, NnTiles& out) {
+    const int64_t nc = m.nc;
+    out = NnTiles{};
+    out.tile_rows = T;
+    out.ntiles = (nc + T - 1) / T;
+    out.ext_off.assign(out.ntiles + 1, 0);
+    out.ring.assign(4 * out.ntiles, 0);
+    out.nb_off.assign(out.ntiles + 1, 0);
+    out.cell.reserve(size_t(nc) * 4);
+    out.nb.reserve(size_t(nc) * 12);
+    std::vector<int64_t> stamp(nc, -1);
+    std::vector<int32_t> loc(nc, 0), list, next;
+    for (int64_t t = 0; t < out.ntiles; ++t) {
+        list.clear();
+        const int64_t c0 = t * T, c1 = std::min<int64_t>(nc, c0 + T);
+        for (int64_t c = c0; c < c1; ++c) {
+            stamp[c] = t;
+            list.push_back(int32_t(c));
+        }
+        out.ring[4 * t] = int32_t(list.size());
+        size_t begin = 0;
+        for (int k = 1; k < 4; ++k) {
+            const size_t end = list.size();
+            next.clear();
+            for (size_t idx = begin; idx < end; ++idx)
+                for (int f = 0; f < 4; ++f) {
+                    const int64_t j = m.c2n[f * nc + list[idx]];
+                    if (j < nc && stamp[j] != t) {
+                        stamp[j] = t;
+                        next.push_back(int32_t(j));
+                    }
+                }
+            std::sort(next.begin(), next.end());
+            list.insert(list.end(), next.begin(), next.end());
+            begin = end;
+            out.ring[4 * t + k] = int32_t(list.size());
+        }
+        if (list.size() > 65535) return false;
+        for (size_t e = 0; e < list.size(); ++e) loc[list[e]] = int32_t(e);
+        out.ext_max = std::max(out.ext_max, int32_t(list.size()));
+        out.r2_max = std::max(out.r2_max, out.ring[4 * t + 2]);
+        out.cell.insert(out.cell.end(), list.begin(), list.end());
+        out.ext_off[t + 1] = int64_t(out.cell.size());
+        for (int e = 0; e < out.ring[4 * t + 2]; ++e)
+            for (int f = 0; f < 4; ++f) {
+                const int64_t j = m.c2n[f * nc + list[e]];
+                out.nb.push_back(j < nc ? uint16_t(loc[j]) : uint16_t(0xFFFF));
+            }
+        out.nb_off[t + 1] = int64_t(out.nb.size() / 4);
+    }
+    return out.r2_max <= kNnFusedMaxGroups * kNnFusedWaves * 16 && nn_fused_lds(out) <= kNnFusedLdsMax;
+}
+}  // namespace
+
+const NnTiles* nn_tiles(const Mesh& m) {
+    if (m.nn_tiles) return m.nn_tiles.get();
+    for (int T : {256, 192, 128, 64}) {
+        auto t = std::make_shared<NnTiles>();
+        if (build_tiles(m, T, *t)) {
+            m.nn_tiles = t;
+            return t.get();
+        }
+    }
+    return nullptr;
+}
+
 size_t nn_state_layout(const Mesh& m, bool training, char* base, NnStateDev& a) {
     size_t off = 0;
     const int64_t nc = m.nc;
@@ -57,6 +126,16 @@ size_t nn_state_layout(const Mesh& m, bool training, char* base, NnStateDev& a) 
         a.kt_val = carve<double>(base, off, m.kmat.idx.size());
     }
     a.training = training;
+    a.tiles = nn_tiles(m);
+    if (a.tiles) {
+        const NnTiles& t = *a.tiles;
+        a.t_ext_off = carve<int64_t>(base, off, t.ext_off.size());
+        a.t_ring = carve<int4>(base, off, size_t(t.ntiles));
+        a.t_cell = carve<int32_t>(base, off, t.cell.size());
+        a.t_nb_off = carve<int64_t>(base, off, t.nb_off.size());
+        a.t_nb = carve<ushort4>(base, off, t.nb.size() / 4);
+        a.t_partial = carve<double>(base, off, 2 * size_t(t.ntiles));
+    }
     return (off + 255) & ~size_t(255);
 }
 
@@ -136,11 +215,16 @@ hipError_t train_step(State& s, const NnDev& n, const float* r32, double* loss_s
     return e;
 }
 
-// the network layers inside the flexible CG (z from d.r, dots with r, r_old)
+// the network inside the flexible CG (z from d.r, dots with r, r_old): the
+// fused forward when the state has its tiles, else layer by layer
 hipError_t fcg_forward(State& s, hipStream_t q, bool timing) {
     const Dev& d = s.d;
     const NnStateDev& a = *s.nn_state;
     KernelTimer& tm = s.timer;
+    if (a.tiles) {
+        auto fn = [&] { return launch_nn_fused(d, *s.nn, a, d.r, d.z, true, q); };
+        return timing ? timed(tm, MIFVM_K_NN_FUSED, q, fn) : fn();
+    }
     for (int l = 0; l < kNnLayers; ++l) {
         auto fn = [&] { return launch_nn_layer(d, *s.nn, a, l, d.r, nullptr, d.z, false, true, q); };
         hipError_t e = timing ? timed(tm, MIFVM_K_NN_LAYER1 + l, q, fn) : fn();
@@ -155,7 +239,7 @@ hipError_t enqueue_fcg_chunk(State& s, int n, hipStream_t q) {
         hipError_t e = s.mf ? launch_mf_cg_spmv(d, s.bc[1], q) : launch_cg_spmv(d, q);
         if (e == hipSuccess) e = launch_fcg_axpy(d, *s.nn_state, q);
         if (e == hipSuccess) e = fcg_forward(s, q, false);
-        if (e == hipSuccess) e = launch_fcg_beta(d, q);
+        if (e == hipSuccess) e = launch_fcg_beta(d, *s.nn_state, q);
         if (e == hipSuccess) e = launch_cg_dir(d, q);
         if (e != hipSuccess) return e;
     }
@@ -183,7 +267,7 @@ int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int s
             return launch_fcg_setup(d, tol, limit, restart, fresh, hs, s.mf ? d.tmp : nullptr);
         }));
         HIPCHK(fcg_forward(s, hs, true));
-        HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_setup_tail(d, hs); }));
+        HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_setup_tail(d, a, hs); }));
         return pull();
     };
     const int graph_key = chunk + (s.mf ? 1 << 20 : 0);
@@ -201,7 +285,7 @@ int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int s
                          [&] { return s.mf ? launch_mf_cg_spmv(d, s.bc[1], hs) : launch_cg_spmv(d, hs); }));
             HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_axpy(d, a, hs); }));
             HIPCHK(fcg_forward(s, hs, true));
-            HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_beta(d, hs); }));
+            HIPCHK(timed(tm, MIFVM_K_FCG_VEC, hs, [&] { return launch_fcg_beta(d, a, hs); }));
             HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
         }
         return MIFVM_OK;
@@ -247,9 +331,11 @@ int learned_phase(State& s, double tol, int maxit, int chunk, int restart, int s
 
 hipError_t nn_apply_vec(State& s, const double* in, double* out, hipStream_t q) {
     const Dev& d = s.d;
+    const NnStateDev& a = *s.nn_state;
     hipError_t e = launch_nn_scale(d, in, nullptr, q);
+    if (e == hipSuccess && a.tiles) return launch_nn_fused(d, *s.nn, a, in, out, false, q);
     for (int l = 0; e == hipSuccess && l < kNnLayers; ++l)
-        e = launch_nn_layer(d, *s.nn, *s.nn_state, l, in, nullptr, out, false, false, q);
+        e = launch_nn_layer(d, *s.nn, a, l, in, nullptr, out, false, false, q);
     return e;
 }
 
@@ -368,7 +454,21 @@ int mifvm_nn_attach(mifvm_state* st, mifvm_nn* nn, int32_t training, void* d_ws,
     auto* a = new (std::nothrow) NnStateDev();
     if (!a) return fail(MIFVM_E_ARG, "out of host memory");
     nn_state_layout(*s.mesh, training != 0, static_cast<char*>(d_ws), *a);
-    const hipError_t e = launch_nn_neighbours(s.d, *a, S(stream));
+    hipStream_t hs = S(stream);
+    hipError_t e = launch_nn_neighbours(s.d, *a, hs);
+    if (e == hipSuccess && a->tiles) {                // the fused forward's tiles
+        const NnTiles& t = *a->tiles;
+        e = hipMemcpyAsync(a->t_ext_off, t.ext_off.data(), t.ext_off.size() * 8, hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(a->t_ring, t.ring.data(), t.ring.size() * 4, hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(a->t_cell, t.cell.data(), t.cell.size() * 4, hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(a->t_nb_off, t.nb_off.data(), t.nb_off.size() * 8, hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess) e = hipMemcpyAsync(a->t_nb, t.nb.data(), t.nb.size() * 2, hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    }
+    if (e == hipSuccess && a->tiles) e = setup_nn_fused(nn_fused_lds(*a->tiles));
     if (e != hipSuccess) {
         delete a;
         return hip_fail(e, "attach");
@@ -383,20 +483,39 @@ int mifvm_nn_attach(mifvm_state* st, mifvm_nn* nn, int32_t training, void* d_ws,
     return MIFVM_OK;
 }
 
-int mifvm_nn_apply(mifvm_state* st, const double* d_r, double* d_z, void* stream) {
+}  // extern "C"
+
+namespace {
+int nn_apply_impl(mifvm_state* st, const double* d_r, double* d_z, void* stream, bool layers) {
     if (!st || !d_r || !d_z) return fail(MIFVM_E_ARG, "null argument");
     State& s = st->s;
     int rc = need_attached(s, false);
     if (rc) return rc;
     const Dev& d = s.d;
+    const NnStateDev& a = *s.nn_state;
     hipStream_t hs = S(stream);
     HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_r, d.r, hs));
     HIPCHK(launch_nn_scale(d, d.r, nullptr, hs));
-    for (int l = 0; l < kNnLayers; ++l)
-        HIPCHK(timed(s.timer, MIFVM_K_NN_LAYER1 + l, hs,
-                     [&] { return launch_nn_layer(d, *s.nn, *s.nn_state, l, d.r, nullptr, d.z, false, false, hs); }));
+    if (a.tiles && !layers) {
+        HIPCHK(timed(s.timer, MIFVM_K_NN_FUSED, hs, [&] { return launch_nn_fused(d, *s.nn, a, d.r, d.z, false, hs); }));
+    } else {
+        for (int l = 0; l < kNnLayers; ++l)
+            HIPCHK(timed(s.timer, MIFVM_K_NN_LAYER1 + l, hs,
+                         [&] { return launch_nn_layer(d, *s.nn, a, l, d.r, nullptr, d.z, false, false, hs); }));
+    }
     HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.z, d_z, hs));
     return MIFVM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mifvm_nn_apply(mifvm_state* st, const double* d_r, double* d_z, void* stream) {
+    return nn_apply_impl(st, d_r, d_z, stream, false);
+}
+
+int mifvm_nn_apply_layers(mifvm_state* st, const double* d_r, double* d_z, void* stream) {
+    return nn_apply_impl(st, d_r, d_z, stream, true);
 }
 
 int mifvm_nn_sample(mifvm_state* st, float* d_out, double* rms, void* stream) {

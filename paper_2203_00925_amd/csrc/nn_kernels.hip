@@ -96,6 +96,14 @@ __device__ inline void block_range(int64_t nbg, int64_t& b0, int64_t& b1) {
     b1 = b0 + per < nbg ? b0 + per : nbg;
 }
 
+// tile of this block: blocks are dealt to the 8 XCDs in turn, so with the
+// grid padded to a multiple of 8 each XCD takes a contiguous eighth of the
+// tiles (neighbouring tiles share the cells of their rings in one L2)
+__device__ inline int64_t xcd_tile(int64_t ntiles) {
+    const int64_t per = gridDim.x / 8;
+    return int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
 struct NnIn {
     int64_t nc;
     const int4* nbr;
@@ -275,7 +283,7 @@ __global__ __launch_bounds__(256) void k_nn_layer(NnFwd F) {
             y += __shfl_xor(y, 32, 64);
             y += bd;
             if (g == 0 && valid) {
-                const double zi = ra.ds * ra.rs + sd * double(y);
+                const double zi = __fma_rn(sd, double(y), ra.ds * ra.rs);   // one rounding order in every forward
                 F.z[i] = zi;
                 if (FCG) {
                     zr += zi * ra.rs;
@@ -293,6 +301,156 @@ __global__ __launch_bounds__(256) void k_nn_layer(NnFwd F) {
         if (threadIdx.x == 0) {
             F.partial[blockIdx.x] = s0;
             F.partial[gridDim.x + blockIdx.x] = s1;
+        }
+    }
+}
+
+// ---- fused forward ----------------------------------------------------------------
+// The three layers of one tile in one workgroup: the encoding of the tile's
+// whole list (rings 0-3) goes to LDS as bf16 rows; layer 1 is evaluated on
+// rings 0-2, layer 2 on rings 0-1, layer 3 and the decoder on ring 0 (the
+// tile's own cells).  Each layer's outputs stay in registers (at most
+// kNnFusedMaxGroups 16-cell groups per wave) until every wave has read its
+// inputs, then overwrite the rows in place.  A cell's arithmetic is the
+// three-launch forward's (the same encode, products, roundings and
+// decoder), so z is bitwise the same; only the rows of neighbouring cells
+// are recomputed per tile instead of read from HBM.
+struct NnFused {
+    NnIn in;
+    const int64_t* ext_off;
+    const int4* ring;
+    const int32_t* cell;
+    const int64_t* nb_off;
+    const ushort4* nb;
+    int64_t ntiles;
+    int32_t ext_max;
+    double* z;
+    const double* r_old;
+    double* partial;          // [2][ntiles]
+};
+
+template <bool FCG>
+__global__ __launch_bounds__(256) void k_nn_fused(NnFused F) {
+    extern __shared__ __align__(16) unsigned char nn_smem[];
+    u32x4* rows = reinterpret_cast<u32x4*>(nn_smem);                                  // [ext][4]
+    ushort4* lnb = reinterpret_cast<ushort4*>(nn_smem + size_t(F.ext_max) * 64);      // [rings 0-2]
+    __shared__ double lds[4];
+    const NnIn& A = F.in;
+    if (FCG && A.scal[SC_DONE] != 0.0) return;
+    const int64_t t = xcd_tile(F.ntiles);
+    if (t >= F.ntiles) return;
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, wv = threadIdx.x >> 6;
+    const NnPack* P = A.pack;
+    const int4 rn = F.ring[t];                       // cumulative ring sizes
+    const int64_t eo = F.ext_off[t], no = F.nb_off[t];
+    for (int e = threadIdx.x; e < rn.z; e += 256) lnb[e] = F.nb[no + e];
+    {   // encoding of every cell of the list
+        float we0[8], we1[8], be[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            we0[j] = P->we0[8 * g + j];
+            we1[j] = P->we1[8 * g + j];
+            be[j] = P->be[8 * g + j];
+        }
+        const double isr = A.scal[SC_NN_INV_SR], isd = A.scal[SC_NN_INV_SD];
+        for (int G = wv; G * 16 < rn.w; G += kNnFusedWaves) {
+            const int e = G * 16 + c;
+            if (e < rn.w) {
+                const int cl = F.cell[eo + e];
+                rows[e * 4 + g] = encode(A.r64[cl], A.dinv[cl], we0, we1, be, isr, isd);
+            }
+        }
+    }
+    __syncthreads();
+    const double sd = A.scal[SC_NN_SD];
+    double zr = 0.0, zro = 0.0;
+    const u32x4 z4 = {0u, 0u, 0u, 0u};
+    for (int l = 0; l < kNnLayers; ++l) {
+        const int N = l == 0 ? rn.z : (l == 1 ? rn.y : rn.x);
+        const NnPackLayer& L = P->layer[l];
+        bf16x8 w1[2][2], w2[2];
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            w1[tt][0] = L.w1[tt][0][lane];
+            w1[tt][1] = L.w1[tt][1][lane];
+            w2[tt] = L.w2[tt][lane];
+        }
+        float b1[8], b2[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            b1[j] = L.b1[8 * g + j];
+            b2[j] = L.b2[8 * g + j];
+        }
+        u32x4 out[kNnFusedMaxGroups];
+#pragma unroll
+        for (int k = 0; k < kNnFusedMaxGroups; ++k) {
+            const int G = wv + kNnFusedWaves * k;
+            if (G * 16 >= N) break;                  // uniform over the wave
+            const int e = G * 16 + c;
+            const bool valid = e < N;
+            const u32x4 bh = valid ? rows[e * 4 + g] : z4;
+            const ushort4 nb = valid ? lnb[e] : make_ushort4(0xFFFF, 0xFFFF, 0xFFFF, 0xFFFF);
+            const uint16_t nbs[4] = {nb.x, nb.y, nb.z, nb.w};
+            u32x4 bn[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bn[q] = nbs[q] != 0xFFFF ? rows[int(nbs[q]) * 4 + g] : z4;
+            float hown[8];
+            unpack8(bh, hown);
+            f32x4 v[2];
+            w1_product(w1, bh, bn, v);
+            float u[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) u[j] = fmaxf(v[j >> 2][j & 3] + b1[j], 0.f);
+            const u32x4 bu = cvt8(u);
+            float hf[8];
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                const f32x4 o = mfma32(w2[tt], as_bf(bu), f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                for (int q = 0; q < 4; ++q) hf[4 * tt + q] = (hown[4 * tt + q] + o[q]) + b2[4 * tt + q];
+            }
+            out[k] = cvt8(hf);
+            if (l == kNnLayers - 1) {                // decoder: ring 0 is the tile's own cells
+                float hn[8], wd[8];
+                unpack8(out[k], hn);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) wd[j] = P->wd[8 * g + j];
+                float y = 0.f;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) y = fmaf(wd[j], hn[j], y);
+                y += __shfl_xor(y, 16, 64);
+                y += __shfl_xor(y, 32, 64);
+                y += P->bd;
+                if (g == 0 && valid) {
+                    const int64_t i = int64_t(F.cell[eo + e]);
+                    const double rs = A.r64[i], ds = A.dinv[i];
+                    const double zi = __fma_rn(sd, double(y), ds * rs);
+                    F.z[i] = zi;
+                    if (FCG) {
+                        zr += zi * rs;
+                        zro += zi * F.r_old[i];
+                    }
+                }
+            }
+        }
+        if (l < kNnLayers - 1) {
+            __syncthreads();                         // every wave has read the layer's inputs
+#pragma unroll
+            for (int k = 0; k < kNnFusedMaxGroups; ++k) {
+                const int G = wv + kNnFusedWaves * k;
+                if (G * 16 >= N) break;
+                const int e = G * 16 + c;
+                if (e < N) rows[e * 4 + g] = out[k];
+            }
+            __syncthreads();
+        }
+    }
+    if (FCG) {
+        const double s0 = block_sum256(zr, lds);
+        const double s1 = block_sum256(zro, lds);
+        if (threadIdx.x == 0) {
+            F.partial[t] = s0;
+            F.partial[F.ntiles + t] = s1;
         }
     }
 }
@@ -1141,8 +1299,8 @@ hipError_t launch_fcg_setup(const Dev& d, double tol, int maxit, int restart, bo
     return hipGetLastError();
 }
 
-hipError_t launch_fcg_setup_tail(const Dev& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_fcg_rz_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nn_fwd_grid(d.nc)));
+hipError_t launch_fcg_setup_tail(const Dev& d, const NnStateDev& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_rz_fin, dim3(1), dim3(1024), 0, s, d, nn_forward_parts(d, a));
     hipLaunchKernelGGL(k_fcg_p0, dim3(rows256(d.nc)), dim3(256), 0, s, d);
     return hipGetLastError();
 }
@@ -1154,9 +1312,45 @@ hipError_t launch_fcg_axpy(const Dev& d, const NnStateDev& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_fcg_beta(const Dev& d, hipStream_t s) {
-    hipLaunchKernelGGL(k_fcg_beta_fin, dim3(1), dim3(1024), 0, s, d, int64_t(nn_fwd_grid(d.nc)));
+hipError_t launch_fcg_beta(const Dev& d, const NnStateDev& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_fcg_beta_fin, dim3(1), dim3(1024), 0, s, d, nn_forward_parts(d, a));
     return hipGetLastError();
+}
+
+int64_t nn_forward_parts(const Dev& d, const NnStateDev& a) {
+    return a.tiles ? a.tiles->ntiles : int64_t(nn_fwd_grid(d.nc));
+}
+
+hipError_t launch_nn_fused(const Dev& d, const NnDev& n, const NnStateDev& a, const double* r64, double* z,
+                           bool fcg, hipStream_t s) {
+    const NnTiles& t = *a.tiles;
+    NnFused F;
+    F.in = make_in(d, n, a, r64, nullptr);
+    F.ext_off = a.t_ext_off;
+    F.ring = a.t_ring;
+    F.cell = a.t_cell;
+    F.nb_off = a.t_nb_off;
+    F.nb = a.t_nb;
+    F.ntiles = t.ntiles;
+    F.ext_max = t.ext_max;
+    F.z = z;
+    F.r_old = a.r_old;
+    F.partial = d.partial;
+    const dim3 grid(unsigned((t.ntiles + 7) / 8 * 8)), block(256);
+    const size_t lds = nn_fused_lds(t);
+    if (fcg) hipLaunchKernelGGL(k_nn_fused<true>, grid, block, lds, s, F);
+    else hipLaunchKernelGGL(k_nn_fused<false>, grid, block, lds, s, F);
+    return hipGetLastError();
+}
+
+hipError_t setup_nn_fused(size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nn_fused<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_nn_fused<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    return e;
 }
 
 hipError_t launch_fcg_backup(const Dev& d, const NnStateDev& a, bool restore, hipStream_t s) {

@@ -102,7 +102,7 @@ struct FvArrays {
     const R *phi, *minv, *kAC, *kBC, *kRL, *area, *vol, *src, *n_alpha, *fx, *xc, *gdist;
 };
 
-constexpr int kNumKernels = 19;
+constexpr int kNumKernels = 20;
 
 struct NnDev;
 struct NnStateDev;

@@ -78,16 +78,17 @@ def accepted(rec, ms, f_all, x_all):
     return worst
 
 
-@pytest.mark.parametrize("item_rows,grid,policy", [(4096, 1024, B.BQ_XCD), (256, 8, B.BQ_ROTATE),
-                                                   (512, 3, B.BQ_LARGEST), (1024, 512, B.BQ_XCD)])
-def test_persistent_solve_accepted_and_matches_launches(item_rows, grid, policy):
+@pytest.mark.parametrize("item_rows,grid,policy,vb", [(4096, 1024, B.BQ_XCD, 8), (256, 8, B.BQ_ROTATE, 8),
+                                                      (512, 3, B.BQ_LARGEST, 24), (1024, 512, B.BQ_XCD, 24),
+                                                      (4096, 1024, B.BQ_LAUNCHES, 8)])
+def test_persistent_solve_accepted_and_matches_launches(item_rows, grid, policy, vb):
     """Every mesh converges on its own and is accepted by the oracle's K; the
     same per-mesh algorithm as the per-launch matrix-free solve (iterations
     within 3, solutions to 1e-8), whatever the schedule (items smaller than
     meshes, fewer workgroups than items, any queue order)."""
-    print(f"[gpu] persistent batch solve: item_rows={item_rows} grid={grid} policy={policy}", flush=True)
+    print(f"[gpu] batch solve: item_rows={item_rows} grid={grid} policy={policy} vertex_batch={vb}", flush=True)
     ms, u0, vel, st = make(SMALL)
-    bt = B.Batch(st, item_rows=item_rows, grid=grid, policy=policy)
+    bt = B.Batch(st, item_rows=item_rows, grid=grid, policy=policy, vertex_batch=vb)
     info = bt.solve(tol=1e-10)
     its = st.mesh_values("iterations")
     assert info["status"] == B.OK and np.all(st.mesh_values("rel_residual") <= 1e-10)
@@ -156,12 +157,14 @@ def test_autotune_picks_schedule_and_restores_p(tmp_path):
     cache = str(tmp_path / "batch_tune.json")
     t = bt.autotune(cache, iterations=8)
     print(f"[gpu] batch autotune: {t}", flush=True)
-    assert t["from_cache"] == 0 and t["trials"] >= 12
-    assert t["item_rows"] % 256 == 0 and t["policy"] in (0, 1, 2)
+    assert t["from_cache"] == 0 and t["trials"] >= 16
+    assert t["item_rows"] % 256 == 0 and t["policy"] in (0, 1, 2, 3) and t["vertex_batch"] in (8, 24)
+    assert t["ms_best"] == min(t["ms_persistent"], t["ms_launches"])
     assert np.array_equal(host(st.get_field(B.FIELD_P)), p0)
     assert bt.schedule()["item_rows"] == t["item_rows"]
     t2 = bt.autotune(cache)
     assert t2["from_cache"] == 1 and t2["grid"] == t["grid"] and t2["policy"] == t["policy"]
+    assert t2["vertex_batch"] == t["vertex_batch"] and t2["chunk"] == t["chunk"]
     assert bt.solve(tol=1e-10)["status"] == B.OK
 
 

@@ -247,3 +247,21 @@ def test_stall_fallback_with_untrained_network():
     K, c = poisson.assemble(g, [DIRICHLET] * 6, [0.0] * 6)
     x = host(st.get_field(B.FIELD_P))
     assert poisson.true_relative_residual(K, poisson.rhs(g, f, c), x) <= 1.01e-10
+
+
+@pytest.mark.parametrize("n,seed", [(5, 1000), (14, 1003)])
+def test_fused_forward_equals_layer_by_layer(n, seed):
+    """The one-launch forward (tiles of consecutive cells with their
+    three-step face-neighbour rings in LDS) gives bitwise the z of the
+    layer-by-layer forward, on a mesh of a few tiles and one of 65 tiles."""
+    print(f"[nn] fused forward, n={n}", flush=True)
+    m, mesh, st = poisson_state(n, seed)
+    net = B.Network(seed=3)
+    flat, _ = random_params(seed=14)
+    net.set_params(flat)
+    net.attach(st)
+    for rs in (5, 6):
+        r = np.random.default_rng(rs).normal(size=m.nc)
+        zf = host(st.nn_apply(dev(r)))
+        zl = host(st.nn_apply(dev(r), layers=True))
+        assert np.array_equal(zf, zl)
