@@ -211,6 +211,9 @@ def main():
                          "each runs min(--steps, 5) steps (batch64: 4)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the reduced-precision (FP32 + refined solve) run")
+    ap.add_argument("--log", default=None,
+                    help="append per-step and per-solve JSON-lines records of the main run to this file "
+                         "(adds one conservation sum and a host synchronisation per timed step)")
     ap.add_argument("--calibrate-copy-gb", type=float, default=0.0,
                     help="first run one device-to-device copy of this many GB (a kernel of "
                          "known traffic, to scale hardware byte counters)")
@@ -288,10 +291,13 @@ def main():
     st.kernel_timing(True)
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     solves = []
+    totals = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         solves.append(one_step(events[k]))
+        if args.log:
+            totals.append(st.conservation())
         log(f"step {k}: solve {solves[-1]['iterations']} it, rel {solves[-1]['rel_residual']:.2e}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -337,6 +343,17 @@ def main():
                 "traffic_GBps": round(traffic / avg_s / 1e9, 1) if traffic else None}
 
     iters = [s["iterations"] for s in solves]
+    if args.log:
+        from paper_2203_00925_amd.runlog import RunLog
+        mf_bytes = nbytes["mf_vertex"] + nbytes["mf_face"] + nbytes["mf_gather"] + nbytes["cg_axpy"] + \
+            nbytes["cg_dir"]
+        with RunLog(args.log, cells=info.nc, conservation0=total0) as rl:
+            rl.run(workload=args.workload, cells=info.nc, faces=info.nf, steps=args.steps,
+                   warmup=args.warmup, dt=dt, conservation_initial=total0)
+            for k in range(args.steps):
+                rl.step(args.warmup + k + 1, dt, conservation=totals[k], ms=fv_ms[k])
+                rl.solve(args.warmup + k + 1, solves[k], method=0, ms=solve_ms[k],
+                         bytes_per_iteration=mf_bytes, matrix_free=True)
     result = {
         "metric": METRIC,
         "value": value,
@@ -682,6 +699,10 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
     st.set_field(B.FIELD_U, torch.from_numpy(pf.u0))
     st.poisson_assemble()
     net.attach(st)
+    form, ms_layers, ms_fused = st.nn_form()
+    form_info = {"form": {B.NN_FORM_LAYERS: "layers", B.NN_FORM_FUSED: "fused"}.get(form, str(form)),
+                 "attach_ms_layers": round(ms_layers, 4), "attach_ms_fused": round(ms_fused, 4)}
+    log(f"learned: network forward {form_info}")
     dt = st.cfl_dt(pf.cfl)
     kw = dict(tol=1e-10, restart=500, method=B.SOLVE_LEARNED, allow_fell_back=True, matrix_free=True)
     kw_csr = dict(kw, matrix_free=False)
@@ -758,6 +779,7 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
                                        "jacobi_cg_iterations": cold_plain_csr["iterations"],
                                        "jacobi_cg_ms": cold_plain_csr["ms"]}},
             "kernel_avg_ms": layer_ms,
+            "network_forward": form_info,
             "as_multigrid_smoother": {"poisson_solve_ms": mg_ms,
                                       "poisson_iterations": [s["iterations"] for s in mg_solves],
                                       "poisson_rel_residual": max(s["rel_residual"] for s in mg_solves),

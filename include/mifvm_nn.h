@@ -84,22 +84,36 @@ int mifvm_nn_load(mifvm_nn* nn, const void* buf, size_t bytes, void* stream);
  * also FP32 backward rows and the values of K^T.                           */
 int mifvm_nn_attach_bytes(const mifvm_state* st, int32_t training, size_t* out);
 /* Attach nn to a single-mesh state (E_ARG for a batch); nn NULL detaches.
- * The workspace must outlive the attachment.  Asynchronous.                 */
+ * The workspace must outlive the attachment.  When the mesh has tiles for the
+ * one-launch forward (below), attaching times one application of each form on
+ * the given stream (the cell volumes as input) and keeps the faster; the
+ * state's scratch vectors are overwritten.  Synchronises in that case.      */
 int mifvm_nn_attach(mifvm_state* st, mifvm_nn* nn, int32_t training, void* d_ws, size_t ws_bytes,
                     void* stream);
-/* d_z = z(d_r), both FP64 in user cell order (for inspection and tests).
- * E_STATE without an attached network or an assembled system (or, for
- * matrix-free use, the diagonal of a solve).  The network runs in one launch
- * per tile of consecutive cells (the encoding of the cells within three
- * face-neighbour steps of the tile kept in LDS, every layer evaluated where
- * the next one reads it), as inside the flexible CG and the multigrid
- * smoother; a mesh whose tiles exceed the kernel's LDS or register limits
- * falls back to the layer-by-layer form.                                   */
+/* d_z = z(d_r), both FP64 in user cell order (for inspection and tests), in
+ * the form the state uses (mifvm_nn_form), as inside the flexible CG and the
+ * multigrid smoother.  E_STATE without an attached network or an assembled
+ * system (or, for matrix-free use, the diagonal of a solve).               */
 int mifvm_nn_apply(mifvm_state* st, const double* d_r, double* d_z, void* stream);
 /* The same network layer by layer: three launches with the activation rows
  * going through device memory (the form training uses).  Bitwise the same
- * z as mifvm_nn_apply.                                                     */
+ * z as the one-launch form.                                                */
 int mifvm_nn_apply_layers(mifvm_state* st, const double* d_r, double* d_z, void* stream);
+/* Forms of the forward.  LAYERS: three launches, rows through device memory.
+ * FUSED: one launch per tile of consecutive cells; the encoding of the cells
+ * within three face-neighbour steps of the tile kept in LDS and each layer
+ * evaluated where the next reads it (so the rings are evaluated more than
+ * once).  A mesh whose tiles exceed the fused kernel's LDS or register limits
+ * has LAYERS only.  Both give bitwise the same z.                          */
+#define MIFVM_NN_FORM_AUTO 0
+#define MIFVM_NN_FORM_LAYERS 1
+#define MIFVM_NN_FORM_FUSED 2
+/* Select the form (AUTO: the faster of the attach-time timings; -1: leave
+ * it) and report the one in use (*chosen, LAYERS or FUSED) and the timings
+ * of one application of each (ms, 0 if not timed); outputs may be NULL.
+ * E_STATE without an attached network or for FUSED without tiles; E_ARG for
+ * an unknown form.  Drops captured chunks that launch the network.         */
+int mifvm_nn_form(mifvm_state* st, int32_t form, int32_t* chosen, float* ms_layers, float* ms_fused);
 /* A training sample from the state's current solve: the true residual
  * r = b - K x of the stored P against the right-hand side of the last solve
  * (or mifvm_poisson_rhs), scaled to unit RMS, written as FP32 in the

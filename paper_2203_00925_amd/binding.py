@@ -30,6 +30,7 @@ KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "
            "fcg_vec", "nn_train", "mf_vertex", "mf_face", "mf_gather", "nn_fused")
 NN_PARAMS = 9537
 LOSS_RESIDUAL, LOSS_ENERGY = 0, 1
+NN_FORM_AUTO, NN_FORM_LAYERS, NN_FORM_FUSED = 0, 1, 2
 
 EXPORTS = {  # id: (name, dtype, shape-fn(info))
     0: ("cell_perm", np.int32, lambda i: (i.nc,)),
@@ -260,6 +261,7 @@ def _load():
         "mifvm_nn_attach": (C.c_int, [P, P, I32, P, SZ, P]),
         "mifvm_nn_apply": (C.c_int, [P, P, P, P]),
         "mifvm_nn_apply_layers": (C.c_int, [P, P, P, P]),
+        "mifvm_nn_form": (C.c_int, [P, I32, C.POINTER(I32), C.POINTER(C.c_float), C.POINTER(C.c_float)]),
         "mifvm_nn_sample": (C.c_int, [P, P, C.POINTER(D), P]),
         "mifvm_nn_loss_grad": (C.c_int, [P, P, I32, C.POINTER(D), P, P]),
         "mifvm_nn_train": (C.c_int, [P, P, I32, P, P, I32, C.POINTER(_TrainOpts),
@@ -746,6 +748,15 @@ def _state_nn_loss_grad(self, sample, loss_kind=LOSS_RESIDUAL, stream=None):
     return loss.value, grad
 
 
+def _state_nn_form(self, form=-1):
+    """Select the network's forward form (NN_FORM_AUTO / _LAYERS / _FUSED;
+    -1 leaves it) and return (form in use, ms layers, ms fused)."""
+    chosen, ml, mf = C.c_int32(), C.c_float(), C.c_float()
+    _check(_lib.mifvm_nn_form(self._h, int(form), C.byref(chosen), C.byref(ml), C.byref(mf)))
+    return chosen.value, ml.value, mf.value
+
+
 State.nn_apply = _state_nn_apply
+State.nn_form = _state_nn_form
 State.nn_sample = _state_nn_sample
 State.nn_loss_grad = _state_nn_loss_grad

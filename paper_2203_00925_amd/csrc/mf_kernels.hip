@@ -51,8 +51,8 @@ __global__ __launch_bounds__(kBlock) void k_mf_ghost(Dev d, BcTable bc, const R*
 }
 
 // x_v = sum alpha x_e over the vertex list; a cell reads x, a ghost xg.  The
-// entries go in batches of 8: the weight and index loads of a batch first,
-// then its gathers, so 8 gathers are in flight per thread.
+// entries go in batches of 24: the weight and index loads of a batch first,
+// then its gathers, so 24 gathers are in flight per thread.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict__ x, const R* __restrict__ xg,
                                                       R* __restrict__ xv, const double* skip) {

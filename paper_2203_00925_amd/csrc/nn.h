@@ -92,6 +92,7 @@ struct NnTiles {
 };
 constexpr int kNnFusedMaxGroups = 16;           // 16-cell groups per wave and layer (registers)
 constexpr int kNnFusedWaves = 4;
+constexpr int kNnFusedEntriesPerThread = 5;    // list entries per thread (256 threads) in the prologue
 constexpr size_t kNnFusedLdsMax = 78 * 1024;    // two workgroups per CU
 // the tiles of a mesh (largest tile size <= 256 that fits the limits;
 // computed once per mesh and kept with it); null if none fits
@@ -120,6 +121,10 @@ struct NnStateDev {
     int64_t* t_nb_off;
     ushort4* t_nb;
     double* t_partial;      // [2][ntiles] z.r, z.r_old per tile
+    // the form in use (both give bitwise the same z): fused when the tiles
+    // exist and it was chosen; the attach-time timings of one application
+    bool fused = false;
+    float ms_layers = 0.f, ms_fused = 0.f;
 };
 
 size_t nn_layout(char* base, NnDev& n);

@@ -92,7 +92,8 @@ bool build_tiles(const Mesh& m, int T, NnTiles& out) {
             }
         out.nb_off[t + 1] = int64_t(out.nb.size() / 4);
     }
-    return out.r2_max <= kNnFusedMaxGroups * kNnFusedWaves * 16 && nn_fused_lds(out) <= kNnFusedLdsMax;
+    return out.r2_max <= kNnFusedMaxGroups * kNnFusedWaves * 16 &&
+           out.ext_max <= kNnFusedEntriesPerThread * 256 && nn_fused_lds(out) <= kNnFusedLdsMax;
 }
 }  // namespace
 
@@ -216,12 +217,12 @@ hipError_t train_step(State& s, const NnDev& n, const float* r32, double* loss_s
 }
 
 // the network inside the flexible CG (z from d.r, dots with r, r_old): the
-// fused forward when the state has its tiles, else layer by layer
+// fused forward when it is the state's chosen form, else layer by layer
 hipError_t fcg_forward(State& s, hipStream_t q, bool timing) {
     const Dev& d = s.d;
     const NnStateDev& a = *s.nn_state;
     KernelTimer& tm = s.timer;
-    if (a.tiles) {
+    if (a.tiles && a.fused) {
         auto fn = [&] { return launch_nn_fused(d, *s.nn, a, d.r, d.z, true, q); };
         return timing ? timed(tm, MIFVM_K_NN_FUSED, q, fn) : fn();
     }
@@ -333,10 +334,53 @@ hipError_t nn_apply_vec(State& s, const double* in, double* out, hipStream_t q) 
     const Dev& d = s.d;
     const NnStateDev& a = *s.nn_state;
     hipError_t e = launch_nn_scale(d, in, nullptr, q);
-    if (e == hipSuccess && a.tiles) return launch_nn_fused(d, *s.nn, a, in, out, false, q);
+    if (e == hipSuccess && a.tiles && a.fused) return launch_nn_fused(d, *s.nn, a, in, out, false, q);
     for (int l = 0; e == hipSuccess && l < kNnLayers; ++l)
         e = launch_nn_layer(d, *s.nn, a, l, in, nullptr, out, false, false, q);
     return e;
+}
+
+// captured chunks that launch the network (flexible CG; the multigrid cycle
+// with the learned smoother) hold its buffers and form: dropped whenever
+// those change
+void drop_nn_graphs(State& s) {
+    if (s.fcg_exec) (void)hipGraphExecDestroy(s.fcg_exec);
+    s.fcg_exec = nullptr;
+    if (s.amg_exec) (void)hipGraphExecDestroy(s.amg_exec);
+    s.amg_exec = nullptr;
+}
+
+// Times one application of each form (the second of two, on the cell
+// volumes as input; d.z is scratch here) and keeps the faster.  The forms
+// give bitwise the same z, so the choice changes only the speed.
+hipError_t choose_form(State& s, const NnDev& n, NnStateDev& a, hipStream_t q) {
+    const Dev& d = s.d;
+    hipEvent_t ev[3];
+    for (auto& x : ev)
+        if (hipError_t e = hipEventCreate(&x); e != hipSuccess) return e;
+    auto run = [&](bool fused) {
+        hipError_t e = launch_nn_scale(d, d.vol, nullptr, q);
+        if (e == hipSuccess && fused) return launch_nn_fused(d, n, a, d.vol, d.z, false, q);
+        for (int l = 0; e == hipSuccess && l < kNnLayers; ++l)
+            e = launch_nn_layer(d, n, a, l, d.vol, nullptr, d.z, false, false, q);
+        return e;
+    };
+    float ms[2] = {0.f, 0.f};
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < 2 && e == hipSuccess; ++f) {
+        e = run(f == 1);
+        if (e == hipSuccess) e = hipEventRecord(ev[0], q);
+        if (e == hipSuccess) e = run(f == 1);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], q);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms[f], ev[0], ev[1]);
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return e;
+    a.ms_layers = ms[0];
+    a.ms_fused = ms[1];
+    a.fused = ms[1] < ms[0];
+    return hipSuccess;
 }
 
 }  // namespace mifvm_api
@@ -441,8 +485,7 @@ int mifvm_nn_attach(mifvm_state* st, mifvm_nn* nn, int32_t training, void* d_ws,
         s.nn = nullptr;
         s.nn_handle = nullptr;
         s.kt_ready = false;
-        if (s.fcg_exec) (void)hipGraphExecDestroy(s.fcg_exec);
-        s.fcg_exec = nullptr;
+        drop_nn_graphs(s);
         return MIFVM_OK;
     }
     if (!d_ws) return fail(MIFVM_E_ARG, "null workspace");
@@ -469,6 +512,7 @@ int mifvm_nn_attach(mifvm_state* st, mifvm_nn* nn, int32_t training, void* d_ws,
         if (e == hipSuccess) e = hipStreamSynchronize(hs);
     }
     if (e == hipSuccess && a->tiles) e = setup_nn_fused(nn_fused_lds(*a->tiles));
+    if (e == hipSuccess && a->tiles) e = choose_form(s, nn->n, *a, hs);
     if (e != hipSuccess) {
         delete a;
         return hip_fail(e, "attach");
@@ -478,8 +522,7 @@ int mifvm_nn_attach(mifvm_state* st, mifvm_nn* nn, int32_t training, void* d_ws,
     s.nn = &nn->n;
     s.nn_handle = nn;
     s.kt_ready = false;
-    if (s.fcg_exec) (void)hipGraphExecDestroy(s.fcg_exec);
-    s.fcg_exec = nullptr;
+    drop_nn_graphs(s);
     return MIFVM_OK;
 }
 
@@ -496,7 +539,7 @@ int nn_apply_impl(mifvm_state* st, const double* d_r, double* d_z, void* stream,
     hipStream_t hs = S(stream);
     HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_r, d.r, hs));
     HIPCHK(launch_nn_scale(d, d.r, nullptr, hs));
-    if (a.tiles && !layers) {
+    if (a.tiles && a.fused && !layers) {
         HIPCHK(timed(s.timer, MIFVM_K_NN_FUSED, hs, [&] { return launch_nn_fused(d, *s.nn, a, d.r, d.z, false, hs); }));
     } else {
         for (int l = 0; l < kNnLayers; ++l)
@@ -516,6 +559,25 @@ int mifvm_nn_apply(mifvm_state* st, const double* d_r, double* d_z, void* stream
 
 int mifvm_nn_apply_layers(mifvm_state* st, const double* d_r, double* d_z, void* stream) {
     return nn_apply_impl(st, d_r, d_z, stream, true);
+}
+
+int mifvm_nn_form(mifvm_state* st, int32_t form, int32_t* chosen, float* ms_layers, float* ms_fused) {
+    if (!st) return fail(MIFVM_E_ARG, "null state");
+    State& s = st->s;
+    int rc = need_attached(s, false);
+    if (rc) return rc;
+    NnStateDev& a = *s.nn_state;
+    if (form == MIFVM_NN_FORM_FUSED && !a.tiles)
+        return fail(MIFVM_E_STATE, "the mesh's tiles exceed the fused forward's limits");
+    if (form == MIFVM_NN_FORM_AUTO) a.fused = a.tiles && a.ms_fused < a.ms_layers;
+    else if (form == MIFVM_NN_FORM_LAYERS) a.fused = false;
+    else if (form == MIFVM_NN_FORM_FUSED) a.fused = true;
+    else if (form != -1) return fail(MIFVM_E_ARG, "unknown network form");
+    drop_nn_graphs(s);                                          // captured chunks hold the old form
+    if (chosen) *chosen = a.fused ? MIFVM_NN_FORM_FUSED : MIFVM_NN_FORM_LAYERS;
+    if (ms_layers) *ms_layers = a.ms_layers;
+    if (ms_fused) *ms_fused = a.ms_fused;
+    return MIFVM_OK;
 }
 
 int mifvm_nn_sample(mifvm_state* st, float* d_out, double* rms, void* stream) {

@@ -309,12 +309,17 @@ __global__ __launch_bounds__(256) void k_nn_layer(NnFwd F) {
 // The three layers of one tile in one workgroup: the encoding of the tile's
 // whole list (rings 0-3) goes to LDS as bf16 rows; layer 1 is evaluated on
 // rings 0-2, layer 2 on rings 0-1, layer 3 and the decoder on ring 0 (the
-// tile's own cells).  Each layer's outputs stay in registers (at most
-// kNnFusedMaxGroups 16-cell groups per wave) until every wave has read its
-// inputs, then overwrite the rows in place.  A cell's arithmetic is the
-// three-launch forward's (the same encode, products, roundings and
-// decoder), so z is bitwise the same; only the rows of neighbouring cells
-// are recomputed per tile instead of read from HBM.
+// tile's own cells).  The first two layers keep their outputs in registers
+// (at most kNnFusedMaxGroups 16-cell groups per wave, statically indexed)
+// until every wave has read its inputs, then overwrite the rows in place; the
+// last layer feeds the decoder directly.  A cell's arithmetic is the
+// three-launch forward's (the same encode, products, roundings and decoder),
+// so z is bitwise the same; only the rows of neighbouring cells are
+// recomputed per tile instead of read from HBM.
+//
+// LDS rows are planar, [slot group g][list entry]: the 16 lanes of one slot
+// group read 16 consecutive 16-byte rows of their own cells, which fall in
+// distinct banks (the neighbour rows are random reads either way).
 struct NnFused {
     NnIn in;
     const int64_t* ext_off;
@@ -329,11 +334,122 @@ struct NnFused {
     double* partial;          // [2][ntiles]
 };
 
+// one network layer on the first N entries of the tile's list; LAST: the
+// decoder and z of the tile's own cells (and the FCG dot partials).  Groups
+// go in pairs of straight-line code, so the LDS reads and matrix-core chain
+// of one group overlap the other's (a pair past N reads zero rows).
+template <bool FCG, int L>
+__device__ inline void fused_layer(const NnFused& F, u32x4* rows, int cap, const ushort4* lnb, int N, int lane,
+                                   int wv, int64_t eo, double sd, double& zr, double& zro) {
+    constexpr bool LAST = L == kNnLayers - 1;
+    const int c = lane & 15, g = lane >> 4;
+    const NnPack* P = F.in.pack;
+    const NnPackLayer& Ly = P->layer[L];
+    const u32x4* plane = rows + size_t(g) * cap;
+    bf16x8 w1[2][2], w2[2];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        w1[tt][0] = Ly.w1[tt][0][lane];
+        w1[tt][1] = Ly.w1[tt][1][lane];
+        w2[tt] = Ly.w2[tt][lane];
+    }
+    float b1[8], b2[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        b1[j] = Ly.b1[8 * g + j];
+        b2[j] = Ly.b2[8 * g + j];
+    }
+    const u32x4 z4 = {0u, 0u, 0u, 0u};
+    // one 16-cell group: the layer's output slots of this lane
+    auto group = [&](int G) -> u32x4 {
+        const int e = G * 16 + c;
+        const bool valid = e < N;
+        const u32x4 bh = valid ? plane[e] : z4;
+        const ushort4 nb = valid ? lnb[e] : make_ushort4(0xFFFF, 0xFFFF, 0xFFFF, 0xFFFF);
+        const uint16_t nbs[4] = {nb.x, nb.y, nb.z, nb.w};
+        u32x4 bn[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bn[q] = nbs[q] != 0xFFFF ? plane[nbs[q]] : z4;
+        float hown[8];
+        unpack8(bh, hown);
+        f32x4 v[2];
+        w1_product(w1, bh, bn, v);
+        float u[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) u[j] = fmaxf(v[j >> 2][j & 3] + b1[j], 0.f);
+        const u32x4 bu = cvt8(u);
+        float hf[8];
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const f32x4 o = mfma32(w2[tt], as_bf(bu), f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int q = 0; q < 4; ++q) hf[4 * tt + q] = (hown[4 * tt + q] + o[q]) + b2[4 * tt + q];
+        }
+        return cvt8(hf);
+    };
+    constexpr int W = kNnFusedWaves;
+    if constexpr (LAST) {
+        float wd[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) wd[j] = P->wd[8 * g + j];
+        const float bd = P->bd;
+        auto decode = [&](int G, u32x4 out) {
+            float hn[8];
+            unpack8(out, hn);
+            float y = 0.f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) y = fmaf(wd[j], hn[j], y);
+            y += __shfl_xor(y, 16, 64);
+            y += __shfl_xor(y, 32, 64);
+            y += bd;
+            const int e = G * 16 + c;
+            if (g == 0 && e < N) {
+                const int64_t i = int64_t(F.cell[eo + e]);
+                const double rs = F.in.r64[i], ds = F.in.dinv[i];
+                const double zi = __fma_rn(sd, double(y), ds * rs);
+                F.z[i] = zi;
+                if (FCG) {
+                    zr += zi * rs;
+                    zro += zi * F.r_old[i];
+                }
+            }
+        };
+        for (int G = wv; G * 16 < N; G += 2 * W) {
+            const u32x4 o0 = group(G);
+            const u32x4 o1 = group(G + W);
+            decode(G, o0);
+            decode(G + W, o1);
+        }
+    } else {
+        u32x4 out[kNnFusedMaxGroups];
+#pragma unroll
+        for (int k = 0; k < kNnFusedMaxGroups; k += 2) {
+            const int G = wv + W * k;
+            if (G * 16 < N) {                         // uniform over the wave
+                out[k] = group(G);
+                out[k + 1] = group(G + W);
+            } else {
+                out[k] = z4;
+                out[k + 1] = z4;
+            }
+        }
+        __syncthreads();                              // every wave has read the layer's inputs
+        u32x4* wplane = rows + size_t(g) * cap;
+#pragma unroll
+        for (int k = 0; k < kNnFusedMaxGroups; ++k) {
+            const int e = (wv + W * k) * 16 + c;
+            if (e < N) wplane[e] = out[k];
+        }
+        __syncthreads();
+    }
+}
+
 template <bool FCG>
 __global__ __launch_bounds__(256) void k_nn_fused(NnFused F) {
     extern __shared__ __align__(16) unsigned char nn_smem[];
-    u32x4* rows = reinterpret_cast<u32x4*>(nn_smem);                                  // [ext][4]
-    ushort4* lnb = reinterpret_cast<ushort4*>(nn_smem + size_t(F.ext_max) * 64);      // [rings 0-2]
+    const int cap = F.ext_max;
+    u32x4* rows = reinterpret_cast<u32x4*>(nn_smem);                                  // [4][cap]
+    ushort4* lnb = reinterpret_cast<ushort4*>(nn_smem + size_t(cap) * 64);            // [rings 0-2]
     __shared__ double lds[4];
     const NnIn& A = F.in;
     if (FCG && A.scal[SC_DONE] != 0.0) return;
@@ -343,8 +459,40 @@ __global__ __launch_bounds__(256) void k_nn_fused(NnFused F) {
     const NnPack* P = A.pack;
     const int4 rn = F.ring[t];                       // cumulative ring sizes
     const int64_t eo = F.ext_off[t], no = F.nb_off[t];
-    for (int e = threadIdx.x; e < rn.z; e += 256) lnb[e] = F.nb[no + e];
-    {   // encoding of every cell of the list
+    {   // one thread per list entry: every index and residual load goes out
+        // at once; (r, D^-1 r) wait in plane 0 of the entry's row
+        int cl[kNnFusedEntriesPerThread];
+        ushort4 nbv[kNnFusedEntriesPerThread];
+#pragma unroll
+        for (int j = 0; j < kNnFusedEntriesPerThread; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            cl[j] = F.cell[eo + (e < rn.w ? e : 0)];
+            nbv[j] = F.nb[no + (e < rn.z ? e : 0)];
+        }
+        double rv[kNnFusedEntriesPerThread], dv[kNnFusedEntriesPerThread];
+#pragma unroll
+        for (int j = 0; j < kNnFusedEntriesPerThread; ++j) {
+            rv[j] = A.r64[cl[j]];
+            dv[j] = A.dinv[cl[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < kNnFusedEntriesPerThread; ++j) {
+            const int e = threadIdx.x + 256 * j;
+            if (e < rn.z) lnb[e] = nbv[j];
+            if (e < rn.w) {
+                u32x4 pk;
+                const uint64_t rb = __double_as_longlong(rv[j]), db = __double_as_longlong(dv[j]);
+                pk[0] = uint32_t(rb);
+                pk[1] = uint32_t(rb >> 32);
+                pk[2] = uint32_t(db);
+                pk[3] = uint32_t(db >> 32);
+                rows[e] = pk;
+            }
+        }
+    }
+    __syncthreads();
+    {   // encoding of every cell of the list: the four lanes of a cell read
+        // (r, D^-1) from plane 0 before the wave overwrites it
         float we0[8], we1[8], be[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -353,98 +501,26 @@ __global__ __launch_bounds__(256) void k_nn_fused(NnFused F) {
             be[j] = P->be[8 * g + j];
         }
         const double isr = A.scal[SC_NN_INV_SR], isd = A.scal[SC_NN_INV_SD];
+        u32x4* plane = rows + size_t(g) * cap;
         for (int G = wv; G * 16 < rn.w; G += kNnFusedWaves) {
             const int e = G * 16 + c;
             if (e < rn.w) {
-                const int cl = F.cell[eo + e];
-                rows[e * 4 + g] = encode(A.r64[cl], A.dinv[cl], we0, we1, be, isr, isd);
+                const u32x4 pk = rows[e];
+                const double r = __longlong_as_double(int64_t(uint64_t(pk[0]) | (uint64_t(pk[1]) << 32)));
+                const double d = __longlong_as_double(int64_t(uint64_t(pk[2]) | (uint64_t(pk[3]) << 32)));
+                const u32x4 h = encode(r, d, we0, we1, be, isr, isd);
+                __builtin_amdgcn_wave_barrier();
+                plane[e] = h;
             }
         }
     }
     __syncthreads();
     const double sd = A.scal[SC_NN_SD];
     double zr = 0.0, zro = 0.0;
-    const u32x4 z4 = {0u, 0u, 0u, 0u};
-    for (int l = 0; l < kNnLayers; ++l) {
-        const int N = l == 0 ? rn.z : (l == 1 ? rn.y : rn.x);
-        const NnPackLayer& L = P->layer[l];
-        bf16x8 w1[2][2], w2[2];
-#pragma unroll
-        for (int tt = 0; tt < 2; ++tt) {
-            w1[tt][0] = L.w1[tt][0][lane];
-            w1[tt][1] = L.w1[tt][1][lane];
-            w2[tt] = L.w2[tt][lane];
-        }
-        float b1[8], b2[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            b1[j] = L.b1[8 * g + j];
-            b2[j] = L.b2[8 * g + j];
-        }
-        u32x4 out[kNnFusedMaxGroups];
-#pragma unroll
-        for (int k = 0; k < kNnFusedMaxGroups; ++k) {
-            const int G = wv + kNnFusedWaves * k;
-            if (G * 16 >= N) break;                  // uniform over the wave
-            const int e = G * 16 + c;
-            const bool valid = e < N;
-            const u32x4 bh = valid ? rows[e * 4 + g] : z4;
-            const ushort4 nb = valid ? lnb[e] : make_ushort4(0xFFFF, 0xFFFF, 0xFFFF, 0xFFFF);
-            const uint16_t nbs[4] = {nb.x, nb.y, nb.z, nb.w};
-            u32x4 bn[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) bn[q] = nbs[q] != 0xFFFF ? rows[int(nbs[q]) * 4 + g] : z4;
-            float hown[8];
-            unpack8(bh, hown);
-            f32x4 v[2];
-            w1_product(w1, bh, bn, v);
-            float u[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) u[j] = fmaxf(v[j >> 2][j & 3] + b1[j], 0.f);
-            const u32x4 bu = cvt8(u);
-            float hf[8];
-#pragma unroll
-            for (int tt = 0; tt < 2; ++tt) {
-                const f32x4 o = mfma32(w2[tt], as_bf(bu), f32x4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-                for (int q = 0; q < 4; ++q) hf[4 * tt + q] = (hown[4 * tt + q] + o[q]) + b2[4 * tt + q];
-            }
-            out[k] = cvt8(hf);
-            if (l == kNnLayers - 1) {                // decoder: ring 0 is the tile's own cells
-                float hn[8], wd[8];
-                unpack8(out[k], hn);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) wd[j] = P->wd[8 * g + j];
-                float y = 0.f;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) y = fmaf(wd[j], hn[j], y);
-                y += __shfl_xor(y, 16, 64);
-                y += __shfl_xor(y, 32, 64);
-                y += P->bd;
-                if (g == 0 && valid) {
-                    const int64_t i = int64_t(F.cell[eo + e]);
-                    const double rs = A.r64[i], ds = A.dinv[i];
-                    const double zi = __fma_rn(sd, double(y), ds * rs);
-                    F.z[i] = zi;
-                    if (FCG) {
-                        zr += zi * rs;
-                        zro += zi * F.r_old[i];
-                    }
-                }
-            }
-        }
-        if (l < kNnLayers - 1) {
-            __syncthreads();                         // every wave has read the layer's inputs
-#pragma unroll
-            for (int k = 0; k < kNnFusedMaxGroups; ++k) {
-                const int G = wv + kNnFusedWaves * k;
-                if (G * 16 >= N) break;
-                const int e = G * 16 + c;
-                if (e < N) rows[e * 4 + g] = out[k];
-            }
-            __syncthreads();
-        }
-    }
+    static_assert(kNnLayers == 3, "the fused forward is written for three layers");
+    fused_layer<FCG, 0>(F, rows, cap, lnb, rn.z, lane, wv, eo, sd, zr, zro);
+    fused_layer<FCG, 1>(F, rows, cap, lnb, rn.y, lane, wv, eo, sd, zr, zro);
+    fused_layer<FCG, 2>(F, rows, cap, lnb, rn.x, lane, wv, eo, sd, zr, zro);
     if (FCG) {
         const double s0 = block_sum256(zr, lds);
         const double s1 = block_sum256(zro, lds);
@@ -1318,7 +1394,7 @@ hipError_t launch_fcg_beta(const Dev& d, const NnStateDev& a, hipStream_t s) {
 }
 
 int64_t nn_forward_parts(const Dev& d, const NnStateDev& a) {
-    return a.tiles ? a.tiles->ntiles : int64_t(nn_fwd_grid(d.nc));
+    return (a.tiles && a.fused) ? a.tiles->ntiles : int64_t(nn_fwd_grid(d.nc));
 }
 
 hipError_t launch_nn_fused(const Dev& d, const NnDev& n, const NnStateDev& a, const double* r64, double* z,

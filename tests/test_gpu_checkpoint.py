@@ -72,3 +72,36 @@ def test_ten_steps_equal_five_checkpoint_five(precision, tmp_path):
     assert dt_b == dt
     assert its_a == its_b + its_c
     assert np.array_equal(ua, uc) and np.array_equal(pa, pc)
+
+
+def test_run_log_records_the_library_totals(tmp_path):
+    """Per-step and per-solve JSON lines: the logged conservation totals are
+    the library's, the drift stays at round-off (zero-flux walls conserve),
+    and every solve record carries its residual history."""
+    from paper_2203_00925_amd.runlog import RunLog, read
+    print("[gpu] run log, 4 steps", flush=True)
+    m = cube(6, 2)
+    pf = synth.problem_fields(m)
+    st = new_state(m, pf, B.FP64)
+    st.set_field(B.FIELD_U, torch.as_tensor(pf.u0, device="cuda"))
+    dt = st.cfl_dt(pf.cfl)
+    total0 = st.conservation()
+    path = tmp_path / "run.jsonl"
+    totals = []
+    with RunLog(str(path), cells=m.nc, conservation0=total0) as rl:
+        rl.run(cells=m.nc, dt=dt)
+        for k in range(4):
+            st.step(1, dt)
+            info = st.poisson_solve(None, tol=1e-10, matrix_free=True, history=64)
+            totals.append(st.conservation())
+            rl.step(k + 1, dt, conservation=totals[-1], ms=1.0)
+            rl.solve(k + 1, info, method=B.SOLVE_PLAIN)
+    recs = read(str(path))
+    steps = [r for r in recs if r["kind"] == "step"]
+    solves = [r for r in recs if r["kind"] == "solve"]
+    assert [r["conservation"] for r in steps] == totals
+    assert max(r["conservation_rel_drift"] for r in steps) < 1e-13
+    assert abs(steps[-1]["t"] - 4 * dt) <= 4e-16 * 4 * dt
+    for r in solves:
+        assert r["rel_residual"] <= 1e-10 and r["iterations"] > 0
+        assert 0 < len(r["residual_history"]) <= 64

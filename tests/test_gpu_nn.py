@@ -260,8 +260,33 @@ def test_fused_forward_equals_layer_by_layer(n, seed):
     flat, _ = random_params(seed=14)
     net.set_params(flat)
     net.attach(st)
+    form, ms_layers, ms_fused = st.nn_form()
+    print(f"[nn] attach-time timings: layers {ms_layers:.3f} ms, fused {ms_fused:.3f} ms, form {form}", flush=True)
+    assert form in (B.NN_FORM_LAYERS, B.NN_FORM_FUSED) and ms_layers > 0 and ms_fused > 0
+    assert form == (B.NN_FORM_FUSED if ms_fused < ms_layers else B.NN_FORM_LAYERS)
+    assert st.nn_form(B.NN_FORM_FUSED)[0] == B.NN_FORM_FUSED
     for rs in (5, 6):
         r = np.random.default_rng(rs).normal(size=m.nc)
         zf = host(st.nn_apply(dev(r)))
         zl = host(st.nn_apply(dev(r), layers=True))
         assert np.array_equal(zf, zl)
+    # the flexible CG converges alike in either form (z is bitwise the same;
+    # the dot products z.r and z.r_old are summed over different partial
+    # blocks, per tile or per block of cells, so the iterates differ by
+    # rounding only)
+    f = np.random.default_rng(7).normal(size=m.nc)
+    runs = {}
+    for form in (B.NN_FORM_FUSED, B.NN_FORM_LAYERS):
+        assert st.nn_form(form)[0] == form
+        st.set_field(B.FIELD_P, dev(np.zeros(m.nc)))
+        out = st.poisson_solve(dev(f), tol=1e-10, method=B.SOLVE_LEARNED, allow_fell_back=True)
+        runs[form] = (out["iterations"], host(st.get_field(B.FIELD_P)))
+    assert abs(runs[B.NN_FORM_FUSED][0] - runs[B.NN_FORM_LAYERS][0]) <= 2
+    assert rel(runs[B.NN_FORM_FUSED][1], runs[B.NN_FORM_LAYERS][1]) < 1e-8
+    assert st.nn_form(B.NN_FORM_AUTO)[0] == form0_of(ms_layers, ms_fused)
+    with pytest.raises(B.MifvmError):
+        st.nn_form(7)
+
+
+def form0_of(ms_layers, ms_fused):
+    return B.NN_FORM_FUSED if ms_fused < ms_layers else B.NN_FORM_LAYERS
