@@ -128,8 +128,9 @@ def algorithmic_bytes(info):
         + info.foreign_entries * 2 + info.foreign_rows * 4 + nc * (16 + 8 + 8 + 48 + 32)
         + info.edge_nbr_entries * 2 + nf * 24,
         # per face: L,R,A,B,C 20 + kAC,kBC,kRL,phi 32 + centroid 24 + F 8;
-        # per cell (gathered): u, grad, psi, centre 64; vertex values 8
-        "face_flux": nf * 84 + nc * 64 + nv * 8,
+        # per cell (gathered): u 8 and the upwind record (psi g, u - psi g.x)
+        # 32; vertex values 8
+        "face_flux": nf * 84 + nc * 40 + nv * 8,
         # per cell: c2f 16, F 16 (each face read by its 2 cells), vol 8,
         # src 8, u^n 8, u written 8
         "update": nc * (16 + 16 + 8 + 8 + 8 + 8),
@@ -211,6 +212,9 @@ def main():
                          "each runs min(--steps, 5) steps (batch64: 4)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the reduced-precision (FP32 + refined solve) run")
+    ap.add_argument("--learned-samples", type=int, default=0,
+                    help="training samples of the learned form (default 2000; fewer only to shorten "
+                         "profiled runs, whose network is then trained less)")
     ap.add_argument("--log", default=None,
                     help="append per-step and per-solve JSON-lines records of the main run to this file "
                          "(adds one conservation sum and a host synchronisation per timed step)")
@@ -218,6 +222,8 @@ def main():
                     help="first run one device-to-device copy of this many GB (a kernel of "
                          "known traffic, to scale hardware byte counters)")
     args = ap.parse_args()
+    if args.learned_samples > 0:
+        LEARNED["samples"] = args.learned_samples
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the method's "
                           "multi-GPU decomposition is not built",

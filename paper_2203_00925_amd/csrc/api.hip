@@ -572,11 +572,13 @@ int mifvm_cfl_dt(mifvm_state* st, double cfl, double* dt_out, void* stream) {
 }
 
 namespace {
-// ghost fill, gradient + limiter + vertex values, face fluxes
-int residual_parts(State& s, hipStream_t hs, bool parts = false) {
+// ghost fill (unless the ghosts are known current), gradient + limiter +
+// vertex values, face fluxes
+int residual_parts(State& s, hipStream_t hs, bool parts = false, bool ghosts = true) {
     const Dev& d = s.d;
     KernelTimer& t = s.timer;
-    HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, s.fp32, s.bc[0], hs); }));
+    if (ghosts)
+        HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, s.fp32, s.bc[0], hs); }));
     HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, s.fp32, hs, parts); }));
     HIPCHK(timed(t, MIFVM_K_FACE_FLUX, hs, [&] { return launch_face_flux(d, s.fp32, s.bc[0], hs); }));
     return MIFVM_OK;
@@ -591,15 +593,14 @@ int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream) {
     if (dt == 0.0 && !(s.cfl > 0)) return fail(MIFVM_E_STATE, "dt = 0 asks for the CFL steps: call mifvm_cfl_dt first");
     if (n_steps > 0) HIPCHK(launch_set_dt(s.d, dt, s.cfl, hs));
     static const double alpha[3] = {0.5, 0.5, 1.0};
+    // the ghosts are filled once; every update then sets those of its cells
     for (int n = 0; n < n_steps; ++n)
         for (int k = 0; k < 3; ++k) {
-            int rc = residual_parts(s, hs);
+            int rc = residual_parts(s, hs, false, n == 0 && k == 0);
             if (rc) return rc;
             HIPCHK(timed(s.timer, MIFVM_K_UPDATE, hs,
-                         [&] { return launch_update(s.d, s.fp32, alpha[k], k == 0, hs); }));
+                         [&] { return launch_update(s.d, s.fp32, s.bc[0], alpha[k], k == 0, hs); }));
         }
-    if (n_steps > 0)
-        HIPCHK(timed(s.timer, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(s.d, s.fp32, s.bc[0], hs); }));
     return MIFVM_OK;
 }
 
@@ -611,13 +612,13 @@ hipError_t enqueue_steps(const State& s, int n, double dt, hipStream_t q) {
     static const double alpha[3] = {0.5, 0.5, 1.0};
     const Dev& d = s.d;
     hipError_t e = launch_set_dt(d, dt, s.cfl, q);
-    for (int k = 0; e == hipSuccess && k < 3 * n; ++k) {
-        e = launch_ghost_fill(d, s.fp32, s.bc[0], q);
-        if (e == hipSuccess) e = launch_grad_limiter(d, s.fp32, q);
-        if (e == hipSuccess) e = launch_face_flux(d, s.fp32, s.bc[0], q);
-        if (e == hipSuccess) e = launch_update(d, s.fp32, alpha[k % 3], k % 3 == 0, q);
-    }
+    // the ghosts are filled once; every update then sets those of its cells
     if (e == hipSuccess && n > 0) e = launch_ghost_fill(d, s.fp32, s.bc[0], q);
+    for (int k = 0; e == hipSuccess && k < 3 * n; ++k) {
+        e = launch_grad_limiter(d, s.fp32, q);
+        if (e == hipSuccess) e = launch_face_flux(d, s.fp32, s.bc[0], q);
+        if (e == hipSuccess) e = launch_update(d, s.fp32, s.bc[0], alpha[k % 3], k % 3 == 0, q);
+    }
     return e;
 }
 }  // namespace mifvm_api

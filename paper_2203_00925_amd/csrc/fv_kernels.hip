@@ -11,8 +11,9 @@
 //   k_face_flux     per face: MUSCL upwind convective flux (eq. (15)) minus
 //                   the diamond diffusive flux (eq. (diamond)), written once;
 //   k_update        per cell: gathers its 4 face fluxes with their signs.
-// Ghost values (behind boundary faces) are materialised after every update
-// by k_ghost_fill, so every gather is a plain indexed load.
+// Ghost values (behind boundary faces) are materialised by k_ghost_fill
+// before a run of steps and by k_update after every stage, so every gather
+// is a plain indexed load.
 //
 // Every kernel is instantiated for FP64 (the method as stated) and FP32 (the
 // reduced-precision form: state, gradients, fluxes and geometry copies in
@@ -360,10 +361,14 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
         else if (dl < R(0)) ph = fmin(R(1), (umin - ui) / dl);
         psi = fmin(psi, ph);
     }
-    // FP64: the face kernel's upwind data in one record, the separate arrays
-    // only when the caller asks for them; FP32: the arrays (the FP32 face
-    // kernel reads them)
-    if constexpr (!rel) d.rec[i] = make_double4(psi * gx, psi * gy, psi * gz, ui);
+    // FP64: the face kernel's upwind data in one record, (psi g, u - psi g.x_i),
+    // so that u + psi g.(x_f - x_i) is rec.w + rec.xyz . x_f without the
+    // cell's centre; the separate arrays only when the caller asks for them.
+    // FP32: the arrays (the FP32 face kernel reads them)
+    if constexpr (!rel) {
+        const double px = psi * gx, py = psi * gy, pz = psi * gz;
+        d.rec[i] = make_double4(px, py, pz, ui - (px * xi + py * yi + pz * zi));
+    }
     if (PARTS || rel) {
         a.grad[i] = gx;
         a.grad[nc + i] = gy;
@@ -395,22 +400,17 @@ __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTa
     const int up = ph >= R(0) ? L : Rc;
     R uup, uL, uR;
     if constexpr (std::is_same<R, double>::value) {
-        // FP64: the upwind cell's record (psi g, u) and centre; the other
-        // side's value from u
-        const int dn = up == L ? Rc : L;
-        const R udn = u[dn];
-        R ucell;
-        if (up < nc) {   // MUSCL reconstruction at the face centroid (ghost side: first order)
+        // FP64: both sides' values from u; the upwind cell's record
+        // (psi g, u - psi g.x_c) gives the MUSCL value at the face centroid
+        // (ghost side: first order)
+        uL = u[L];
+        uR = u[Rc];
+        if (up < nc) {
             const double4 rc = d.rec[up];
-            const double4 pc = d.xyz4[up];
-            ucell = rc.w;
-            uup = ucell + (rc.x * (a.fx[f] - pc.x) + rc.y * (a.fx[nf + f] - pc.y) + rc.z * (a.fx[2 * nf + f] - pc.z));
+            uup = rc.w + (rc.x * a.fx[f] + rc.y * a.fx[nf + f] + rc.z * a.fx[2 * nf + f]);
         } else {
-            ucell = u[up];
-            uup = ucell;
+            uup = up == L ? uL : uR;
         }
-        uL = up == L ? ucell : udn;
-        uR = up == L ? udn : ucell;
     } else {
         uup = u[up];
         if (up < nc) {   // MUSCL reconstruction at the face centroid (ghost side: first order)
@@ -434,9 +434,11 @@ __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTa
 }
 
 // u^(k) = u^n + a dt Res(u^(k-1)) with the cell's mesh's dt; the first stage
-// also saves u^n.
+// also saves u^n.  The cell then sets the ghosts behind its boundary faces
+// from its new value (as k_ghost_fill does; a ghost has one owner), so the
+// next stage reads current ghosts without a launch of its own.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_update(Dev d, FvArrays<R> a, double alpha, int first) {
+__global__ __launch_bounds__(kBlock) void k_update(Dev d, FvArrays<R> a, BcTable bc, double alpha, int first) {
     const int64_t i = gtid();
     if (i >= d.nc) return;
     const R a_dt = R(alpha * d.mesh_dt[mesh_of(d, i)]);
@@ -459,7 +461,22 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev d, FvArrays<R> a, double 
     } else {
         base = a.un[i];
     }
-    a.u[i] = base + a_dt * res;
+    const R unew = base + a_dt * res;
+    a.u[i] = unew;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int f = c[k] >= 0 ? c[k] : ~c[k];
+        if (f >= d.nfi) {                     // boundary face: ghost g behind it
+            const int64_t g = f - d.nfi;
+            const int kind = bc.kind[d.gtag[g]];
+            const R val = bc_value<R>(bc, g);
+            R ug;
+            if (kind == kDirichlet) ug = R(2) * val - unew;
+            else if (kind == kNeumann) ug = unew + val * a.gdist[g];
+            else ug = unew;
+            a.u[d.nc + g] = ug;
+        }
+    }
 }
 
 template <class R>
@@ -671,12 +688,12 @@ hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_update(const Dev& d, bool fp32, double alpha, bool first_stage, hipStream_t s) {
+hipError_t launch_update(const Dev& d, bool fp32, const BcTable& bc, double alpha, bool first_stage, hipStream_t s) {
     if (fp32)
-        hipLaunchKernelGGL(k_update<float>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv32(d), alpha,
+        hipLaunchKernelGGL(k_update<float>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv32(d), bc, alpha,
                            first_stage ? 1 : 0);
     else
-        hipLaunchKernelGGL(k_update<double>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv64(d), alpha,
+        hipLaunchKernelGGL(k_update<double>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv64(d), bc, alpha,
                            first_stage ? 1 : 0);
     return hipGetLastError();
 }

@@ -9,6 +9,7 @@
 #include "seg.h"
 #include "state.h"
 #include "halo_stage.h"
+#include "xcd.h"
 
 namespace mifvm {
 
@@ -19,89 +20,184 @@ inline int grid_rows(int64_t n) { return int((n + kBlock - 1) / kBlock); }
 // where F_f = kAC (P_A - P_C) + kBC (P_B - P_C) + kRL (P_R - P_L) on interior
 // and Dirichlet faces, P_v = sum alpha_{v,e} P_e over the vertex list, and a
 // ghost value is s_g P_owner + t_g.  Neumann / zero-flux faces carry a fixed
-// flux that only enters c.  One thread per row, 64-thread blocks, the row's
-// accumulators in LDS ([entry][lane] so lanes hit distinct banks); each row
-// is summed by one thread in a fixed order (deterministic, no atomics).
+// flux that only enters c.  No atomics: each row is summed by one wavefront.
 // FULL = false computes only the diagonal, D^-1 and c (the same sums in the
 // same order, the off-diagonal coefficients dropped): what the matrix-free
 // solves need, without the stored pattern.
+//
+// One wavefront per row (four rows per 256-thread block).  All
+// of a row's loads go out together: its four faces' data, then the entries of
+// its twelve vertex lists, one entry per lane and list.  The row's entries
+// are summed in LDS ([row_cap] per wave, columns staged beside them for the
+// binary search of a column's slot).  The faces go in order; a vertex list's
+// cells are distinct, so their contributions are added by all lanes at once,
+// then its ghost entries (mapped to their owners, which may repeat a column)
+// one lane after the other in list order, then R and L.  Every sum is in a
+// fixed order (deterministic).
+__device__ inline double lane_read(double x, int c) {
+    const int64_t b = __double_as_longlong(x);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b)), c));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(uint64_t(b) >> 32)), c));
+    return __longlong_as_double(int64_t((uint64_t(hi) << 32) | lo));
+}
+
 template <bool FULL>
-__global__ __launch_bounds__(64) void k_assemble(Dev d, BcTable bc) {
-    extern __shared__ double acc[];                       // [row_max][64] (FULL)
-    const int lane = threadIdx.x;
-    const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+__global__ __launch_bounds__(256) void k_assemble_rows(Dev d, BcTable bc, int row_cap) {
+    extern __shared__ __align__(8) unsigned char asm_raw[];
+    constexpr int NONE = -1, DIAG = -2, OFF = -3;         // OFF: off-diagonal, constant part only
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    // XCD-contiguous block order: the 16 blocks of a 64-row slice share one
+    // L2, which merges their 8-byte stores into whole lines of the slice
+    const int64_t i = xcd_block() * 4 + wv;
     const int64_t nc = d.nc;
     if (i >= nc) return;
     const int64_t s = i >> 6;
-    const int32_t* __restrict__ cols = FULL ? d.k_col + d.k_off[s] + (i & 63) : nullptr;
+    double* acc = reinterpret_cast<double*>(asm_raw) + size_t(wv) * row_cap;
+    int32_t* cols = reinterpret_cast<int32_t*>(reinterpret_cast<double*>(asm_raw) + size_t(4) * row_cap) +
+                    size_t(wv) * row_cap;
     const int len = FULL ? d.k_len[i] : 0;
     const int w = FULL ? d.k_w[s] : 0;
-    for (int k = 0; k < len; ++k) acc[k * 64 + lane] = 0.0;
-    double diag = 0.0, cconst = 0.0;
-
-    auto add = [&](int e, double coef) {
-        if (e >= nc) {                                   // ghost -> owner
-            const int g = e - int(nc);
-            const int t = d.gtag[g];
-            const int kind = bc.kind[t];
-            const double val = bc.val[g];
-            const double sg = kind == kDirichlet ? -1.0 : 1.0;
-            const double tg = kind == kDirichlet ? 2.0 * val : (kind == kNeumann ? val * d.gdist[g] : 0.0);
-            cconst += tg * coef;
-            coef = sg * coef;
-            e = d.gowner[g];
+    if (FULL) {
+        const int32_t* __restrict__ kc = d.k_col + d.k_off[s] + (i & 63);
+        for (int j = lane; j < len; j += 64) {
+            cols[j] = kc[int64_t(j) * 64];
+            acc[j] = 0.0;
         }
-        if (e == i) {
-            diag += coef;
-            return;
-        }
-        if (!FULL) return;
-        int lo = 0, hi = len - 1;                        // sorted prefix of the row
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // the row's faces: sign, kind, and for diamond faces the three vertices,
+    // their weights and R, L (the same on every lane)
+    int fcode[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fcode[k] = d.c2f[k * nc + i];
+    int fkind[4], vtx[12], fr[4], fl[4];
+    double fsg[4], wts[12], krl[4], nconst[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int f = fcode[k] >= 0 ? fcode[k] : ~fcode[k];
+        fsg[k] = fcode[k] >= 0 ? 1.0 : -1.0;
+        fkind[k] = f >= d.nfi ? bc.kind[d.gtag[f - d.nfi]] : kDirichlet;
+        nconst[k] = fkind[k] == kNeumann ? fsg[k] * (bc.val[f - d.nfi] * d.area[f]) : 0.0;
+        const double kac = d.kAC[f], kbc = d.kBC[f];
+        krl[k] = d.kRL[f];
+        vtx[3 * k] = d.fA[f];
+        vtx[3 * k + 1] = d.fB[f];
+        vtx[3 * k + 2] = d.fC[f];
+        wts[3 * k] = fsg[k] * kac;
+        wts[3 * k + 1] = fsg[k] * kbc;
+        wts[3 * k + 2] = fsg[k] * (-(kac + kbc));
+        fr[k] = d.fR[f];
+        fl[k] = d.fL[f];
+    }
+    // first 64 entries of every list, one per lane, all loads in flight
+    int64_t lbase[12];
+    int lw[12], le[12];
+    double la[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const int v = vtx[q];
+        lbase[q] = d.n_off[v >> 6] + (v & 63);
+        lw[q] = d.n_w[v >> 6];
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const bool in = lane < lw[q] && fkind[q / 3] == kDirichlet;
+        const int64_t at = lbase[q] + int64_t(in ? lane : 0) * 64;
+        le[q] = d.n_idx[at];
+        la[q] = in ? d.n_alpha[at] : 0.0;
+    }
+    auto slot_of = [&](int e) -> int {                     // sorted prefix of the row
+        int lo = 0, hi = len - 1;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (cols[int64_t(mid) * 64] < e) lo = mid + 1;
+            if (cols[mid] < e) lo = mid + 1;
             else hi = mid;
         }
-        acc[lo * 64 + lane] += coef;
+        return lo;
     };
-
+    double diag = 0.0, cconst = 0.0;                       // the same on every lane
+    auto ghost_map = [&](int& e, double& coef, double& cp) {
+        const int g = e - int(nc);
+        const int kind = bc.kind[d.gtag[g]];
+        const double val = bc.val[g];
+        const double sg = kind == kDirichlet ? -1.0 : 1.0;
+        const double tg = kind == kDirichlet ? 2.0 * val : (kind == kNeumann ? val * d.gdist[g] : 0.0);
+        cp = tg * coef;
+        coef = sg * coef;
+        e = d.gowner[g];
+    };
+    // one batch of list entries (entry e, weight al on each lane; al = 0: none)
+    auto batch = [&](int e, double al, double wq) {
+        double coef = wq * al, cp = 0.0;
+        bool gh = false;
+        int sl = NONE;
+        if (al != 0.0) {
+            if (e >= nc) {
+                ghost_map(e, coef, cp);
+                gh = true;
+            }
+            sl = e == i ? DIAG : (FULL ? slot_of(e) : OFF);
+        }
+        if (FULL && !gh && sl >= 0) acc[sl] += coef;       // distinct cells: distinct entries
+        const uint64_t dm = __ballot(!gh && sl == DIAG);   // the row's own cell
+        if (dm) diag += lane_read(coef, __builtin_ctzll(dm));
+        uint64_t gm = __ballot(gh);
+        while (gm) {
+            const int c = __builtin_ctzll(gm);
+            gm &= gm - 1;
+            const int sc = __builtin_amdgcn_readlane(sl, c);
+            const double vc = lane_read(coef, c);
+            cconst += lane_read(cp, c);
+            if (sc == DIAG) diag += vc;
+            else if (FULL && sc >= 0 && lane == 0) acc[sc] += vc;
+        }
+    };
+    auto single = [&](int e, double coef) {                // R or L of a face
+        double cp = 0.0;
+        if (e >= nc) {
+            ghost_map(e, coef, cp);
+            cconst += cp;
+        }
+        if (e == i) diag += coef;
+        else if (FULL) {
+            const int sl = slot_of(e);
+            if (lane == 0) acc[sl] += coef;
+        }
+    };
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int code = d.c2f[k * nc + i];
-        const double sgn = code >= 0 ? 1.0 : -1.0;
-        const int f = code >= 0 ? code : ~code;
-        if (f >= d.nfi) {
-            const int t = d.gtag[f - d.nfi];
-            const int kind = bc.kind[t];
-            if (kind != kDirichlet) {
-                if (kind == kNeumann) cconst += sgn * (bc.val[f - d.nfi] * d.area[f]);
-                continue;
-            }
+        if (fkind[k] != kDirichlet) {                      // Neumann / zero flux: a fixed flux
+            cconst += nconst[k];
+            continue;
         }
-        const double kac = d.kAC[f], kbc = d.kBC[f], krl = d.kRL[f];
-        const int verts[3] = {d.fA[f], d.fB[f], d.fC[f]};
-        const double wts[3] = {kac, kbc, -(kac + kbc)};
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const int v = verts[a];
-            const int64_t vs = v >> 6;
-            const int64_t base = d.n_off[vs] + (v & 63);
-            const int vw = d.n_w[vs];
-            const double wv = sgn * wts[a];
-            for (int kk = 0; kk < vw; ++kk) {
-                const int64_t at = base + int64_t(kk) * 64;
-                const double al = d.n_alpha[at];
-                if (al != 0.0) add(d.n_idx[at], wv * al);
+            const int q = 3 * k + a;
+            batch(le[q], la[q], wts[q]);
+            for (int k0 = 64; k0 < lw[q]; k0 += 64) {      // lists longer than a wavefront
+                const bool in = k0 + lane < lw[q];
+                const int64_t at = lbase[q] + int64_t(in ? k0 + lane : 0) * 64;
+                batch(d.n_idx[at], in ? d.n_alpha[at] : 0.0, wts[q]);
             }
         }
-        add(d.fR[f], sgn * krl);
-        add(d.fL[f], -sgn * krl);
+        single(fr[k], fsg[k] * krl[k]);
+        single(fl[k], -fsg[k] * krl[k]);
     }
     if (FULL) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         double* __restrict__ vals = d.k_val + d.k_off[s] + (i & 63);
-        for (int k = 0; k < w; ++k) vals[int64_t(k) * 64] = k < len ? -acc[k * 64 + lane] : 0.0;
+        for (int k = lane; k < w; k += 64) vals[int64_t(k) * 64] = k < len ? -acc[k] : 0.0;
     }
-    d.k_diag[i] = -diag;
-    d.k_dinv[i] = 1.0 / (-diag);
-    d.k_c[i] = cconst;
+    if (lane == 0) {
+        d.k_diag[i] = -diag;
+        d.k_dinv[i] = 1.0 / (-diag);
+        d.k_c[i] = cconst;
+    }
 }
 
 __device__ inline double spmv_row(const Dev& d, const double* __restrict__ x, int64_t i) {
@@ -262,13 +358,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir(Dev d) {
 
 // ---- launchers ---------------------------------------------------------------
 hipError_t launch_assemble(const Dev& d, const BcTable& bc, int row_max, hipStream_t s) {
-    const size_t lds = size_t(row_max > 0 ? row_max : 1) * 64 * sizeof(double);
-    hipLaunchKernelGGL(k_assemble<true>, dim3(unsigned((d.nc + 63) / 64)), dim3(64), lds, s, d, bc);
+    const int cap = row_max > 0 ? row_max : 1;
+    if (size_t(4) * cap * (sizeof(double) + sizeof(int32_t)) > 65536) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_assemble_rows<true>, dim3(rows_m(d.nc, 4)), dim3(256),
+                       size_t(4) * cap * (sizeof(double) + sizeof(int32_t)), s, d, bc, cap);
     return hipGetLastError();
 }
 
 hipError_t launch_assemble_consts(const Dev& d, const BcTable& bc, hipStream_t s) {
-    hipLaunchKernelGGL(k_assemble<false>, dim3(unsigned((d.nc + 63) / 64)), dim3(64), 0, s, d, bc);
+    hipLaunchKernelGGL(k_assemble_rows<false>, dim3(rows_m(d.nc, 4)), dim3(256), 0, s, d, bc, 1);
     return hipGetLastError();
 }
 

@@ -185,7 +185,8 @@ hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool part
 // once per state: kernel attributes (LDS above 64 KB for large tile halos)
 hipError_t setup_fv_kernels(const Dev& d);
 hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
-hipError_t launch_update(const Dev& d, bool fp32, double alpha, bool first_stage, hipStream_t s);
+// the RK stage update; it also sets the ghosts behind the updated cells
+hipError_t launch_update(const Dev& d, bool fp32, const BcTable& bc, double alpha, bool first_stage, hipStream_t s);
 hipError_t launch_set_dt(const Dev& d, double dt, double cfl, hipStream_t s);
 hipError_t launch_residual_out(const Dev& d, bool fp32, double* res_internal, hipStream_t s);
 hipError_t launch_face_phi(const Dev& d, hipStream_t s);
