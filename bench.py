@@ -39,14 +39,14 @@ METRIC = "FV cell-updates/s + Poisson solve ms @1e-10 rel; plain vs mixed/learne
 # it when that source (the kernel's file and the reduction headers) still
 # hashes to the recorded prefix, else null.
 MEASURED_TRAFFIC = {"cube120": {
-    "k_mf_vertex": {"src": "4672ba8d021973df", "bytes": 624943433},
-    "k_mf_face": {"src": "4672ba8d021973df", "bytes": 1214059116},
-    "k_mf_cg_gather": {"src": "4672ba8d021973df", "bytes": 517359431},
-    "k_cg_axpy": {"src": "b5d2496a8c8e2357", "bytes": 668802017},
-    "k_cg_dir": {"src": "b5d2496a8c8e2357", "bytes": 248853718},
-    "k_grad_moments": {"src": "7d7950c3fcb4fe52", "bytes": 3720892011},
-    "k_face_flux": {"src": "7d7950c3fcb4fe52", "bytes": 3024624442},
-    "k_update": {"src": "7d7950c3fcb4fe52", "bytes": 921521579},
+    "k_mf_vertex": {"src": "9aa783096e15adb7", "bytes": 624972083},
+    "k_mf_face": {"src": "9aa783096e15adb7", "bytes": 1214098432},
+    "k_mf_cg_gather": {"src": "9aa783096e15adb7", "bytes": 517369036},
+    "k_cg_axpy": {"src": "2632548940b858f0", "bytes": 668815360},
+    "k_cg_dir": {"src": "2632548940b858f0", "bytes": 248862720},
+    "k_grad_moments": {"src": "5c7dbc8b429ce3a1", "bytes": 3721005056},
+    "k_face_flux": {"src": "5c7dbc8b429ce3a1", "bytes": 2575641600},
+    "k_update": {"src": "5c7dbc8b429ce3a1", "bytes": 927618048},
 }}
 # timing id -> the FP64 kernel it times
 KERNEL_NAMES = {"grad_limiter": "k_grad_moments", "mf_gather": "k_mf_cg_gather"}
