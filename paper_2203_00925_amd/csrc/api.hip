@@ -18,6 +18,7 @@
 #include "api_util.h"
 #include "gmres.h"
 #include "mesh.h"
+#include "nn.h"
 #include "state.h"
 
 using namespace mifvm_api;
@@ -1166,6 +1167,8 @@ int mifvm_mesh_values(const mifvm_state* st, int32_t what, double* out, int32_t 
     return MIFVM_OK;
 }
 
+}  // extern "C"
+
 namespace {
 std::map<std::string, std::array<int, 3>> read_tune_cache(const char* path) {
     std::map<std::string, std::array<int, 3>> out;
@@ -1192,6 +1195,8 @@ void write_tune_cache(const char* path, const std::map<std::string, std::array<i
     o << "}\n";
 }
 }  // namespace
+
+extern "C" {
 
 int mifvm_autotune(mifvm_state* st, const char* cache_path, mifvm_tune_info* out, void* stream) {
     if (!st) return fail(MIFVM_E_ARG, "null state");

@@ -33,7 +33,6 @@ __device__ inline int64_t phase_items(const BatchDev& b, const BatchRange& r, ui
 // queue word: item index in bits 0-31, phase in 32-39, phase epoch (counts
 // the mesh's phase changes) in 40-63
 __device__ inline uint32_t q_phase(unsigned long long w) { return uint32_t(w >> 32) & 0xffu; }
-__device__ inline uint32_t q_epoch(unsigned long long w) { return uint32_t(w >> 40); }
 __device__ inline int64_t q_item(unsigned long long w) { return int64_t(w & 0xffffffffull); }
 __device__ inline unsigned long long q_word(uint32_t epoch, uint32_t phase) {
     return ((unsigned long long)(epoch & 0xffffffu) << 40) | ((unsigned long long)phase << 32);

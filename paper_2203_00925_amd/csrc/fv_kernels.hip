@@ -377,60 +377,47 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
     }
 }
 
+// One thread per face.  Every load of the face goes out before its first
+// branch (boundary faces read a valid dummy where they need no data); the
+// arithmetic of each kind of face is unchanged by that.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTable bc) {
     const int64_t f = gtid();
     if (f >= d.nf) return;
     const int64_t nc = d.nc, NX = d.nc + d.nb, nf = d.nf;
     const R* __restrict__ u = a.u;
-    int kind = kDirichlet;
-    R val = R(0);
-    if (f >= d.nfi) {
-        const int t = d.gtag[f - d.nfi];
-        kind = bc.kind[t];
-        val = bc_value<R>(bc, f - d.nfi);
-    }
-    if (kind == kZeroFlux) {
-        a.flux[f] = R(0);
-        return;
-    }
+    const bool bnd = f >= d.nfi;
+    const int64_t g = bnd ? f - d.nfi : 0;
+    const int kind = bnd ? bc.kind[d.gtag[g]] : kDirichlet;
+    const R val = bnd ? bc_value<R>(bc, g) : R(0);
+    const R area = bnd ? a.area[f] : R(0);            // used on Neumann faces only
     const int L = d.fL[f], Rc = d.fR[f];
     const R D = R(d.mesh_D[mesh_of(d, L)]);
     const R ph = a.phi[f];
+    const R fxx = a.fx[f], fxy = a.fx[nf + f], fxz = a.fx[2 * nf + f];
+    const R cAC = a.kAC[f], cBC = a.kBC[f], cRL = a.kRL[f];
+    const int iA = d.fA[f], iB = d.fB[f], iC = d.fC[f];
+    const R uL = u[L], uR = u[Rc];
+    const R uA = a.unode[iA], uB = a.unode[iB], uC = a.unode[iC];
     const int up = ph >= R(0) ? L : Rc;
-    R uup, uL, uR;
+    const bool cellside = up < nc;          // MUSCL on a cell side; a ghost side is first order
+    const int uc = cellside ? up : L;
+    R uup;
     if constexpr (std::is_same<R, double>::value) {
-        // FP64: both sides' values from u; the upwind cell's record
-        // (psi g, u - psi g.x_c) gives the MUSCL value at the face centroid
-        // (ghost side: first order)
-        uL = u[L];
-        uR = u[Rc];
-        if (up < nc) {
-            const double4 rc = d.rec[up];
-            uup = rc.w + (rc.x * a.fx[f] + rc.y * a.fx[nf + f] + rc.z * a.fx[2 * nf + f]);
-        } else {
-            uup = up == L ? uL : uR;
-        }
+        // FP64: the upwind cell's record (psi g, u - psi g.x_c) gives the
+        // MUSCL value at the face centroid
+        const double4 rc = d.rec[uc];
+        uup = cellside ? rc.w + (rc.x * fxx + rc.y * fxy + rc.z * fxz) : (up == L ? uL : uR);
     } else {
-        uup = u[up];
-        if (up < nc) {   // MUSCL reconstruction at the face centroid (ghost side: first order)
-            const R rx = a.fx[f] - a.xc[up];
-            const R ry = a.fx[nf + f] - a.xc[NX + up];
-            const R rz = a.fx[2 * nf + f] - a.xc[2 * NX + up];
-            const R gr = a.grad[up] * rx + a.grad[nc + up] * ry + a.grad[2 * nc + up] * rz;
-            uup = uup + a.psi[up] * gr;
-        }
-        uL = u[L];
-        uR = u[Rc];
+        const R rx = fxx - a.xc[uc];
+        const R ry = fxy - a.xc[NX + uc];
+        const R rz = fxz - a.xc[2 * NX + uc];
+        const R gr = a.grad[uc] * rx + a.grad[nc + uc] * ry + a.grad[2 * nc + uc] * rz;
+        const R uupc = up == L ? uL : uR;
+        uup = cellside ? uupc + a.psi[uc] * gr : uupc;
     }
-    R diff;
-    if (kind == kNeumann) {
-        diff = val * a.area[f];
-    } else {
-        const R uA = a.unode[d.fA[f]], uB = a.unode[d.fB[f]], uC = a.unode[d.fC[f]];
-        diff = a.kAC[f] * (uA - uC) + a.kBC[f] * (uB - uC) + a.kRL[f] * (uR - uL);
-    }
-    a.flux[f] = uup * ph - D * diff;
+    const R diff = kind == kNeumann ? val * area : cAC * (uA - uC) + cBC * (uB - uC) + cRL * (uR - uL);
+    a.flux[f] = kind == kZeroFlux ? R(0) : uup * ph - D * diff;
 }
 
 // u^(k) = u^n + a dt Res(u^(k-1)) with the cell's mesh's dt; the first stage

@@ -10,7 +10,6 @@
 namespace mifvm {
 namespace {
 
-inline unsigned rows_g(int64_t n) { return unsigned((n + 255) / 256); }
 inline unsigned grid_red(int64_t n) {
     const int64_t b = (n + 255) / 256;
     return unsigned(b < kGmGrid ? (b < 1 ? 1 : b) : kGmGrid);

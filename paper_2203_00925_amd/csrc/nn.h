@@ -30,6 +30,7 @@ constexpr int kNnOffWd = kNnOffLayer + kNnLayers * kNnLayerSize;    // 9504
 constexpr int kNnOffBd = kNnOffWd + 32;
 constexpr int kNnParams = kNnOffBd + 1;                             // 9537
 constexpr int kNnGridMax = 1024;          // blocks of the weight-gradient kernels
+constexpr int kNnGradChunks = 32;         // first stage of the block-gradient sum
 
 // Storage order of a 32-feature row (h, and the per-cell backward rows):
 // slot q = 8g + j holds feature pi(q) = 4g + j (j < 4) or 16 + 4g + j - 4.
@@ -69,6 +70,7 @@ struct NnDev {
     float* adam_v;          // [kNnParams]
     NnPack* pack;
     float* partial;         // [kNnGridMax][kNnParams] per-block gradient sums
+    float* partial2;        // [kNnGradChunks][kNnParams] their sums by chunk
     double* loss;           // [kNnLossRing] loss of each training step
 };
 constexpr int kNnLossRing = 65536;

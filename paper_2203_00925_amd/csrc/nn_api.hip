@@ -36,6 +36,7 @@ size_t nn_layout(char* base, NnDev& n) {
     n.adam_v = carve<float>(base, off, kNnParams);
     n.pack = carve<NnPack>(base, off, 1);
     n.partial = carve<float>(base, off, size_t(kNnGridMax) * kNnParams);
+    n.partial2 = carve<float>(base, off, size_t(kNnGradChunks) * kNnParams);
     n.loss = carve<double>(base, off, kNnLossRing);
     return (off + 255) & ~size_t(255);
 }

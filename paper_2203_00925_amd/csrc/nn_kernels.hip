@@ -47,13 +47,6 @@ __device__ inline void unpack8(u32x4 v, float* o) {
         o[2 * k + 1] = __uint_as_float(v[k] & 0xFFFF0000u);
     }
 }
-// f must hold bf16-representable values or values to be rounded here
-__device__ inline u32x4 pack8(const float* f) {
-    u32x4 v;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = f2bf(f[2 * k]) | (f2bf(f[2 * k + 1]) << 16);
-    return v;
-}
 __device__ inline bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 __device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -590,7 +583,7 @@ __global__ __launch_bounds__(256) void k_nn_bwd(NnBwd B) {
         be[j] = P->be[8 * g + j];
         wd[j] = P->wd[8 * g + j];
     }
-    const double isr = A.scal[SC_NN_INV_SR], isd = A.scal[SC_NN_INV_SD], sd = A.scal[SC_NN_SD];
+    const double isr = A.scal[SC_NN_INV_SR], isd = A.scal[SC_NN_INV_SD];
     const double dscale = A.scal[SC_NN_DSCALE];                 // dy = dscale * w (set by the loss)
     f32x4 gw2[2][2], gw1[2][4];
 #pragma unroll
@@ -996,12 +989,26 @@ __global__ __launch_bounds__(1024) void k_nn_scale_fin(Dev d, int64_t nparts) {
 }
 
 // ---- gradient sum over blocks and Adam --------------------------------------------
-__global__ __launch_bounds__(256) void k_nn_adam(NnDev n, int nblocks, int apply, float lr, float c1, float c2,
+// The gradient is the sum of the per-block sums, in two fixed-order stages:
+// chunk c of kNnGradChunks adds blocks c, c + chunks, c + 2 chunks, ... (one
+// thread per parameter and chunk, so many loads are in flight), then the
+// Adam kernel adds the chunks in order.  Deterministic for a fixed grid.
+__global__ __launch_bounds__(256) void k_nn_grad_chunks(NnDev n, int nblocks) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (p >= kNnParams) return;
+    float g = 0.f;
+    for (int b = c; b < nblocks; b += kNnGradChunks) g += n.partial[int64_t(b) * kNnParams + p];
+    n.partial2[int64_t(c) * kNnParams + p] = g;
+}
+
+__global__ __launch_bounds__(256) void k_nn_adam(NnDev n, int apply, float lr, float c1, float c2,
                                                   float beta1, float beta2, float eps) {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= kNnParams) return;
     float g = 0.f;
-    for (int b = 0; b < nblocks; ++b) g += n.partial[int64_t(b) * kNnParams + p];
+#pragma unroll
+    for (int c = 0; c < kNnGradChunks; ++c) g += n.partial2[int64_t(c) * kNnParams + p];
     n.grad[p] = g;
     if (!apply) return;
     const float m = beta1 * n.adam_m[p] + (1.f - beta1) * g;
@@ -1351,7 +1358,8 @@ int nn_backward_grid(int64_t nc) { return nn_bwd_grid(nc); }
 
 hipError_t launch_nn_adam(const NnDev& n, int nblocks, int apply, float lr, float c1, float c2, float beta1,
                           float beta2, float eps, hipStream_t s) {
-    hipLaunchKernelGGL(k_nn_adam, dim3((kNnParams + 255) / 256), dim3(256), 0, s, n, nblocks, apply, lr, c1, c2,
+    hipLaunchKernelGGL(k_nn_grad_chunks, dim3((kNnParams + 255) / 256, kNnGradChunks), dim3(256), 0, s, n, nblocks);
+    hipLaunchKernelGGL(k_nn_adam, dim3((kNnParams + 255) / 256), dim3(256), 0, s, n, apply, lr, c1, c2,
                        beta1, beta2, eps);
     if (apply) hipLaunchKernelGGL(k_nn_pack, dim3(1), dim3(256), 0, s, n);
     return hipGetLastError();
