@@ -40,8 +40,6 @@ METRIC = "FV cell-updates/s + Poisson solve ms @1e-10 rel; plain vs mixed/learne
 # hashes to the recorded prefix, else null.
 MEASURED_TRAFFIC = {"cube120": {
     "k_mf_vertex": {"src": "9aa783096e15adb7", "bytes": 624972083},
-    "k_mf_face": {"src": "9aa783096e15adb7", "bytes": 1214098432},
-    "k_mf_cg_gather": {"src": "9aa783096e15adb7", "bytes": 517369036},
     "k_cg_axpy": {"src": "2632548940b858f0", "bytes": 668815360},
     "k_cg_dir": {"src": "2632548940b858f0", "bytes": 248862720},
     "k_grad_moments": {"src": "5c7dbc8b429ce3a1", "bytes": 3721005056},
@@ -49,11 +47,11 @@ MEASURED_TRAFFIC = {"cube120": {
     "k_update": {"src": "5c7dbc8b429ce3a1", "bytes": 927618048},
 }}
 # timing id -> the FP64 kernel it times
-KERNEL_NAMES = {"grad_limiter": "k_grad_moments", "mf_gather": "k_mf_cg_gather"}
+KERNEL_NAMES = {"grad_limiter": "k_grad_moments", "mf_gather": "k_mf_cg_cell"}
 KERNEL_FILES = {
     "grad_limiter": "fv_kernels.hip", "face_flux": "fv_kernels.hip", "update": "fv_kernels.hip",
     "cg_spmv": "solve_kernels.hip", "cg_axpy": "solve_kernels.hip", "cg_dir": "solve_kernels.hip",
-    "mf_vertex": "mf_kernels.hip", "mf_face": "mf_kernels.hip", "mf_gather": "mf_kernels.hip",
+    "mf_vertex": "mf_kernels.hip", "mf_gather": "mf_kernels.hip",
 }
 
 
@@ -144,11 +142,10 @@ def algorithmic_bytes(info):
         # matrix-free product: vertex lists (weight 8 + index 4 per entry), x
         # gathered once, ghost owner + tag, vertex values written
         "mf_vertex": info.node_entries * 12 + nc * 8 + nb * 8 + nv * 8,
-        # per face: L,R,A,B,C 20 + kAC,kBC,kRL 24 + F written 8; x and vertex
-        # values gathered once; ghost tags
-        "mf_face": nf * 52 + nc * 8 + nv * 8 + nb * 4,
-        # per cell: cell->face 16, p read 8, q written 8; F gathered once
-        "mf_gather": nc * 32 + nf * 8,
+        # the per-cell product: per cell 4 vertex ids 16, 4 vertex weights 32,
+        # 4 face neighbours 16, 4 neighbour weights 32, diagonal term 8, p 8
+        # (neighbours' p counted once), q written 8; vertex values gathered once
+        "mf_gather": nc * 120 + nv * 8,
     }
 
 
@@ -351,7 +348,7 @@ def main():
     iters = [s["iterations"] for s in solves]
     if args.log:
         from paper_2203_00925_amd.runlog import RunLog
-        mf_bytes = nbytes["mf_vertex"] + nbytes["mf_face"] + nbytes["mf_gather"] + nbytes["cg_axpy"] + \
+        mf_bytes = nbytes["mf_vertex"] + nbytes["mf_gather"] + nbytes["cg_axpy"] + \
             nbytes["cg_dir"]
         with RunLog(args.log, cells=info.nc, conservation0=total0) as rl:
             rl.run(workload=args.workload, cells=info.nc, faces=info.nf, steps=args.steps,
@@ -384,10 +381,10 @@ def main():
         "poisson_rel_residual": max(s["rel_residual"] for s in solves),
         "conservation_rel_drift": abs(total1 - total0) / abs(total0),
         # the kernel with the most GPU time in the timed region
-        "roofline": roof(max(("mf_vertex", "mf_face", "mf_gather", "cg_axpy", "cg_dir", "grad_limiter"),
+        "roofline": roof(max(("mf_vertex", "mf_gather", "cg_axpy", "cg_dir", "grad_limiter"),
                              key=lambda k: kstats[k][0])),
         "roofline_fv": {k: roof(k) for k in ("grad_limiter", "face_flux", "update")},
-        "roofline_cg": {k: roof(k) for k in ("mf_vertex", "mf_face", "mf_gather", "cg_axpy", "cg_dir")},
+        "roofline_cg": {k: roof(k) for k in ("mf_vertex", "mf_gather", "cg_axpy", "cg_dir")},
         "measured_streams_GBps": streams,
     }
     if not args.no_forms:

@@ -630,10 +630,14 @@ enum mifvm_kernel {
     (the first includes the encoder, the last the decoder) */,
     MIFVM_K_FCG_VEC = 14 /* flexible-CG update and its scalar steps */,
     MIFVM_K_NN_TRAIN = 15 /* one whole training step (all of its launches) */,
-    MIFVM_K_MF_VERTEX = 16, MIFVM_K_MF_FACE = 17, MIFVM_K_MF_GATHER = 18 /* the matrix-free
-    product inside the CG (timed one by one; CG_SPMV then counts the stored-matrix product) */,
+    MIFVM_K_MF_VERTEX = 16 /* matrix-free product inside the CG: ghost and vertex values */,
+    MIFVM_K_MF_FACE = 17 /* reserved: the face terms are summed per cell inside MF_GATHER,
+    never launched */,
+    MIFVM_K_MF_GATHER = 18 /* matrix-free product inside the CG: the per-cell product over
+    the cell's vertices and faces, with p.q (CG_SPMV counts the stored-matrix product) */,
     MIFVM_K_NN_FUSED = 19 /* the whole network in one launch (encoder, 3 layers, decoder) */,
-    MIFVM_K_COUNT = 20
+    MIFVM_K_CG_ALPHA = 20 /* the matrix-free CG's alpha step (its p.q partials summed per mesh) */,
+    MIFVM_K_COUNT = 21
 };
 int mifvm_kernel_timing(mifvm_state* st, int32_t enable);
 /* Total milliseconds and number of timed launches of one kernel since the

@@ -280,6 +280,7 @@ int mifvm_amg_apply(mifvm_state* st, int32_t learned_smoother, const double* d_r
     const Dev& d = s.d;
     hipStream_t hs = S(stream);
     const AmgSmoother nn = [&s](const double* in, double* out, hipStream_t q) { return nn_apply_vec(s, in, out, q); };
+    if (int rc = ensure_mf_tables(s, hs)) return rc;      // the finest level's matrix-free product
     HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_r, d.r, hs));
     HIPCHK(launch_amg_cycle(d, s.bc[1], *s.amg, d.r, d.z, nullptr, hs, learned_smoother ? &nn : nullptr));
     HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.z, d_z, hs));

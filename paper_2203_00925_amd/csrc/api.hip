@@ -23,6 +23,8 @@
 
 using namespace mifvm_api;
 
+static_assert(mifvm::kNumKernels == MIFVM_K_COUNT, "kernel timing slots and the ABI's kernel ids disagree");
+
 
 namespace mifvm {
 
@@ -141,6 +143,13 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.mf_xv = carve<double>(base, off, nv);
     d.mf_flux = carve<double>(base, off, nf);
     d.mf_xg = carve<double>(base, off, nb > 0 ? nb : 1);
+    d.mfc_vid = carve<int32_t>(base, off, 4 * nc);
+    d.mfc_w = carve<double>(base, off, 4 * nc);
+    d.mfc_r = carve<double>(base, off, 4 * nc);
+    d.mfc_d = carve<double>(base, off, nc);
+    d.mfc_w32 = carve<float>(base, off, 4 * nc);
+    d.mfc_r32 = carve<float>(base, off, 4 * nc);
+    d.mfc_d32 = carve<float>(base, off, nc);
     // per-block partials of up to 4 sums x 2 mesh slots, for blocks of >= 64 rows
     const int64_t nblk = (nc + 63) / 64;
     d.partial = carve<double>(base, off, 8 * (nblk + 1024));
@@ -447,6 +456,7 @@ int mifvm_set_bc(mifvm_state* st, int32_t var, int32_t tag, int32_t kind, double
     if (var == MIFVM_VAR_POTENTIAL) {
         s.assembled = false;
         s.consts_ready = false;
+        s.mfc_ready = false;
     }
     return MIFVM_OK;
 }
@@ -727,7 +737,16 @@ bool has_matrix(const State& s) { return !s.mesh->kmat.off.empty(); }
 namespace mifvm_api {
 // the diagonal, D^-1 and the ghost constants c of the current potential
 // BCs, which every solve needs; the matrix-free solves need nothing else
+int ensure_mf_tables(State& s, hipStream_t hs) {
+    if (!s.mfc_ready) {                       // the matrix-free product's per-cell tables
+        HIPCHK(launch_mf_cell_setup(s.d, s.bc[1], hs));
+        s.mfc_ready = true;
+    }
+    return MIFVM_OK;
+}
+
 int ensure_consts(State& s, hipStream_t hs) {
+    if (int rc = ensure_mf_tables(s, hs)) return rc;
     if (s.assembled || s.consts_ready) return MIFVM_OK;
     HIPCHK(timed(s.timer, MIFVM_K_ASSEMBLE, hs, [&] { return launch_assemble_consts(s.d, s.bc[1], hs); }));
     s.consts_ready = true;
@@ -758,6 +777,7 @@ int mifvm_poisson_apply_free(mifvm_state* st, const double* d_x, double* d_y, vo
     State& s = st->s;
     const Dev& d = s.d;
     hipStream_t hs = S(stream);
+    if (int rc = ensure_mf_tables(s, hs)) return rc;
     HIPCHK(launch_to_internal(d.cell_perm, d.nc, d.nc, d.nc, 1, d_x, d.tmp, hs));
     HIPCHK(launch_mf_apply(d, s.bc[1], d.tmp, d.tmp + d.nc, hs));
     HIPCHK(launch_to_user(d.cell_perm, d.nc, d.nc, d.nc, 1, d.tmp + d.nc, d_y, hs));
@@ -915,8 +935,8 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
         for (int c = 0; c < chunk; ++c) {
             if (run_method == MIFVM_SOLVE_PLAIN) {
                 if (matrix_free) {
-                    for (int part = 0; part < 3; ++part)
-                        HIPCHK(timed(tm, MIFVM_K_MF_VERTEX + part, hs,
+                    for (int part = 0; part < kMfParts; ++part)
+                        HIPCHK(timed(tm, (part == 0 ? MIFVM_K_MF_VERTEX : part == 1 ? MIFVM_K_MF_GATHER : MIFVM_K_CG_ALPHA), hs,
                                      [&] { return launch_mf_cg_part(d, s.bc[1], part, hs); }));
                 } else {
                     HIPCHK(timed(tm, MIFVM_K_CG_SPMV, hs, [&] { return launch_cg_spmv(d, hs); }));
@@ -924,8 +944,8 @@ int solve_impl(mifvm_state* st, const double* d_f, const double* f_internal, con
                 HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg_axpy(d, hs); }));
                 HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg_dir(d, hs); }));
             } else if (matrix_free) {
-                for (int part = 0; part < 3; ++part)
-                    HIPCHK(timed(tm, MIFVM_K_MF_VERTEX + part, hs,
+                for (int part = 0; part < kMfParts; ++part)
+                    HIPCHK(timed(tm, (part == 0 ? MIFVM_K_MF_VERTEX : part == 1 ? MIFVM_K_MF_GATHER : MIFVM_K_CG_ALPHA), hs,
                                  [&] { return launch_mf_cg32_part(d, s.bc[1], part, hs); }));
                 HIPCHK(timed(tm, MIFVM_K_CG_AXPY, hs, [&] { return launch_cg32_axpy(d, hs); }));
                 HIPCHK(timed(tm, MIFVM_K_CG_DIR, hs, [&] { return launch_cg32_dir(d, hs); }));

@@ -123,7 +123,11 @@ inline hipError_t capture_graph(State& s, hipGraphExec_t* exec, F enqueue) {
 
 // n RK3 steps without timing events (api.hip)
 hipError_t enqueue_steps(const mifvm::State& s, int n, double dt, hipStream_t q);
-// the diagonal, D^-1 and c of the current potential BCs, computed if stale (api.hip)
+// the matrix-free product's per-cell tables of the current potential BC
+// kinds, built if stale (api.hip)
+int ensure_mf_tables(mifvm::State& s, hipStream_t hs);
+// the diagonal, D^-1 and c of the current potential BCs, computed if stale,
+// and the per-cell tables (api.hip)
 int ensure_consts(mifvm::State& s, hipStream_t hs);
 
 // copy every mesh's scalars to the pinned host mirror and wait

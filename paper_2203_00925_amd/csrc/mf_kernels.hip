@@ -23,20 +23,14 @@
 namespace mifvm {
 namespace {
 
-// The coefficient arrays of one precision: FP64, or the FP32 copies the
+// The vertex weights of one precision: FP64, or the FP32 copies the
 // reduced-precision forms read (the inner CG of the refined solve).
 template <class R> struct MfCoef;
 template <> struct MfCoef<double> {
     __device__ static const double* alpha(const Dev& d) { return d.n_alpha; }
-    __device__ static const double* kac(const Dev& d) { return d.kAC; }
-    __device__ static const double* kbc(const Dev& d) { return d.kBC; }
-    __device__ static const double* krl(const Dev& d) { return d.kRL; }
 };
 template <> struct MfCoef<float> {
     __device__ static const float* alpha(const Dev& d) { return d.n_alpha32; }
-    __device__ static const float* kac(const Dev& d) { return d.kAC32; }
-    __device__ static const float* kbc(const Dev& d) { return d.kBC32; }
-    __device__ static const float* krl(const Dev& d) { return d.kRL32; }
 };
 
 // ghost values of x (homogeneous part): xg[g] = s_g x_owner
@@ -99,96 +93,144 @@ __global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict
     xv[v] = s;
 }
 
-// FPT faces per thread (blocks of kBlock threads take kBlock * FPT
-// consecutive faces, thread t faces t, t + kBlock, ...): every face's index
-// and coefficient loads go out before any of its gathers, with no branch
-// between them.  A face's arithmetic does not depend on FPT.  At 10.4M cells
-// one face per thread measured fastest (0.230 ms; 2 and 4: 0.234, 0.238; the
-// form that returned early on non-Dirichlet boundary faces: 0.245).
-constexpr int kMfFacesPerThread = 1;
-template <class R, int FPT>
-__global__ __launch_bounds__(kBlock) void k_mf_face(Dev d, BcTable bc, const R* __restrict__ x,
-                                                    const R* __restrict__ xv, R* __restrict__ F,
-                                                    const double* skip) {
-    if (skip && *skip != 0.0) return;
-    const int64_t f0 = xcd_block() * (int64_t(kBlock) * FPT) + threadIdx.x;
-    const R* __restrict__ kac = MfCoef<R>::kac(d);
-    const R* __restrict__ kbc = MfCoef<R>::kbc(d);
-    const R* __restrict__ krl = MfCoef<R>::krl(d);
-    int L[FPT], Rr[FPT], A[FPT], Bv[FPT], C[FPT];
-    bool act[FPT], bnd[FPT];
-    R ca[FPT], cb[FPT], cr[FPT];
+// ---- the product per cell ----------------------------------------------------
+// gather_row's y_i = -sum_f s_if F_f regrouped per cell: each face of a
+// tetrahedron holds three of its four vertices, so the vertex terms of its
+// faces add up to one weight per vertex, w_k = sum over the cell's faces f
+// holding vertex k of s_if times that vertex's coefficient in F_f (kAC, kBC
+// or -(kAC + kBC)); the kRL term s_if kRL (x_R - x_L) is kRL (x_n - x_i)
+// on an interior face (n the cell across it) and -2 kRL x_i on a Dirichlet
+// face (its ghost is -x_i in the homogeneous part).  Faces of other kinds are
+// not part of K.  So
+//     (K x)_i = -(sum_k w_k x_v[vid_k] + sum_k r_k x[n_k] - dg x_i)
+// with r_k = kRL on interior faces (0 else) and dg = sum of kRL over the
+// interior faces + 2 kRL over the Dirichlet ones.  Built once per potential
+// boundary-kind set; in the product a cell streams 4 vertex ids and 12
+// coefficients instead of its faces' indices and coefficients, and no face
+// flux goes through memory.
+__global__ __launch_bounds__(kBlock) void k_mf_cell_setup(Dev d, BcTable bc) {
+    const int64_t i = gtid_m();
+    if (i >= d.nc) return;
+    const int64_t nc = d.nc;
+    int vid[4] = {-1, -1, -1, -1};
+    double w[4] = {0.0, 0.0, 0.0, 0.0}, r[4] = {0.0, 0.0, 0.0, 0.0}, dg = 0.0;
+    auto add = [&](int v, double c) {                 // the vertex's slot (first seen, first slot)
+        bool done = false;
 #pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-        const int64_t f = f0 + int64_t(j) * kBlock;
-        const int64_t fi = f < d.nf ? f : d.nf - 1;      // past the faces: a valid face, not stored
-        bnd[j] = fi >= d.nfi;
-        act[j] = f < d.nf && (!bnd[j] || bc.kind[d.gtag[fi - d.nfi]] == kDirichlet);
-        L[j] = d.fL[fi];
-        Rr[j] = d.fR[fi];
-        A[j] = d.fA[fi];
-        Bv[j] = d.fB[fi];
-        C[j] = d.fC[fi];
-        ca[j] = kac[fi];
-        cb[j] = kbc[fi];
-        cr[j] = krl[fi];
-    }
-#pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-        const int64_t f = f0 + int64_t(j) * kBlock;
-        if (f >= d.nf) continue;
-        if (!act[j]) {                                    // Neumann / zero flux: no part in K
-            F[f] = R(0);
-            continue;
+        for (int q = 0; q < 4; ++q) {
+            const bool hit = !done && (vid[q] == v || vid[q] < 0);
+            if (hit) {
+                vid[q] = v;
+                w[q] += c;
+            }
+            done = done || hit;
         }
-        const R xl = x[L[j]];
-        const R xr = bnd[j] ? -xl : x[Rr[j]];
-        const R xc = xv[C[j]];
-        F[f] = ca[j] * (xv[A[j]] - xc) + cb[j] * (xv[Bv[j]] - xc) + cr[j] * (xr - xl);
+    };
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int code = d.c2f[k * nc + i];
+        const int f = code >= 0 ? code : ~code;
+        const double sg = code >= 0 ? 1.0 : -1.0;
+        const bool bnd = f >= d.nfi;
+        if (bnd && bc.kind[d.gtag[f - d.nfi]] != kDirichlet) continue;
+        const double kac = d.kAC[f], kbc = d.kBC[f], krl = d.kRL[f];
+        add(d.fA[f], sg * kac);
+        add(d.fB[f], sg * kbc);
+        add(d.fC[f], sg * (-(kac + kbc)));
+        if (bnd) {
+            dg += 2.0 * krl;
+        } else {
+            r[k] = krl;
+            dg += krl;
+        }
     }
+    // unused slots (a cell none of whose faces is in K) point at a used
+    // vertex, or vertex 0, with weight 0
+    const int v0 = vid[0] >= 0 ? vid[0] : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        d.mfc_vid[q * nc + i] = vid[q] >= 0 ? vid[q] : v0;
+        d.mfc_w[q * nc + i] = w[q];
+        d.mfc_r[q * nc + i] = r[q];
+        d.mfc_w32[q * nc + i] = float(w[q]);
+        d.mfc_r32[q * nc + i] = float(r[q]);
+    }
+    d.mfc_d[i] = dg;
+    d.mfc_d32[i] = float(dg);
 }
 
-// y_i = -sum_f s_if F_f
+template <class R> struct MfCell;
+template <> struct MfCell<double> {
+    __device__ static const double* w(const Dev& d) { return d.mfc_w; }
+    __device__ static const double* r(const Dev& d) { return d.mfc_r; }
+    __device__ static const double* dg(const Dev& d) { return d.mfc_d; }
+};
+template <> struct MfCell<float> {
+    __device__ static const float* w(const Dev& d) { return d.mfc_w32; }
+    __device__ static const float* r(const Dev& d) { return d.mfc_r32; }
+    __device__ static const float* dg(const Dev& d) { return d.mfc_d32; }
+};
+
+// (K x)_i from the tables: the row's table loads go out together, then its
+// 4 vertex values and 4 neighbour values (a boundary face reads x_i, with
+// r = 0)
 template <class R>
-__device__ inline R gather_row(const Dev& d, const R* __restrict__ F, int64_t i) {
-    // the four face codes, then the four fluxes, each set in flight together
-    int code[4];
-    R fl[4];
+__device__ inline R cell_row(const Dev& d, const R* __restrict__ x, const R* __restrict__ xv, int64_t i) {
+    const int64_t nc = d.nc;
+    const R* __restrict__ W = MfCell<R>::w(d);
+    const R* __restrict__ Rk = MfCell<R>::r(d);
+    int vid[4], nb[4];
+    R w[4], r[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) code[k] = d.c2f[k * d.nc + i];
+    for (int k = 0; k < 4; ++k) {
+        vid[k] = d.mfc_vid[k * nc + i];
+        nb[k] = d.c2n[k * nc + i];
+        w[k] = W[k * nc + i];
+        r[k] = Rk[k * nc + i];
+    }
+    const R dg = MfCell<R>::dg(d)[i], xi = x[i];
+    R xvv[4], xn[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) fl[k] = F[code[k] >= 0 ? code[k] : ~code[k]];
-    R y = R(0);
+    for (int k = 0; k < 4; ++k) {
+        xvv[k] = xv[vid[k]];
+        xn[k] = x[nb[k] < nc ? nb[k] : i];
+    }
+    R acc = -dg * xi;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) y += code[k] >= 0 ? -fl[k] : fl[k];
-    return y;
+    for (int k = 0; k < 4; ++k) acc += w[k] * xvv[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc += r[k] * xn[k];
+    return -acc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_mf_gather(Dev d, const double* __restrict__ F, double* y,
-                                                      const double* skip) {
+__global__ __launch_bounds__(kBlock) void k_mf_cell(Dev d, const double* __restrict__ x,
+                                                    const double* __restrict__ xv, double* y, const double* skip) {
     if (skip && *skip != 0.0) return;
     const int64_t i = gtid_m();
-    if (i < d.nc) y[i] = gather_row(d, F, i);
+    if (i < d.nc) y[i] = cell_row(d, x, xv, i);
 }
 
-// q = K p through F, and the partial p.q (the matrix-free counterpart of
-// k_cg_spmv; rows of finished meshes are left untouched; partial slots by
+// q = K p from the tables, and the partial p.q (the matrix-free counterpart
+// of k_cg_spmv; rows of finished meshes are left untouched; partial slots by
 // logical block, padding blocks past the rows return).  FP32: q32 = K p32
-// with the FP32 coefficients and the partial in FP64 (as k_cg32_spmv).
+// with the FP32 tables and the partial in FP64 (as k_cg32_spmv).
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_mf_cg_gather(Dev d, const R* __restrict__ F, int64_t nblk) {
+__global__ __launch_bounds__(kBlock) void k_mf_cg_cell(Dev d, int64_t nblk) {
     __shared__ double lds[4];
     const int64_t lb = xcd_block();
     if (lb >= nblk) return;
     const BlockSeg g = block_seg(d, lb * kBlock, kBlock);
     if (block_done(d, g)) return;
     const int64_t i = lb * kBlock + threadIdx.x;
+    const R* __restrict__ p = std::is_same<R, double>::value ? reinterpret_cast<const R*>(d.p)
+                                                              : reinterpret_cast<const R*>(d.p32);
+    const R* __restrict__ xv = reinterpret_cast<const R*>(d.mf_xv);
     double v[1] = {0.0};
     if (i < d.nc) {
         // the row's loads go out before the mesh's done flag is read (a
         // finished mesh's row is read and dropped)
-        const R y = gather_row(d, F, i);
-        const double pi = std::is_same<R, double>::value ? d.p[i] : double(d.p32[i]);
+        const R y = cell_row(d, p, xv, i);
+        const double pi = double(p[i]);
         if (msc(d, row_mesh(g, i))[SC_DONE] == 0.0) {
             if constexpr (std::is_same<R, double>::value) d.q[i] = y;
             else d.q32[i] = y;
@@ -207,33 +249,34 @@ hipError_t launch_mf_apply(const Dev& d, const BcTable& bc, const double* x, dou
                            d, bc, x, d.mf_xg, skip);
     hipLaunchKernelGGL(k_mf_vertex<double>, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, x, d.mf_xg,
                        d.mf_xv, skip);
-    hipLaunchKernelGGL((k_mf_face<double, kMfFacesPerThread>), dim3(rows_m(d.nf, kBlock * kMfFacesPerThread)),
-                       dim3(kBlock), 0, s, d, bc, x, d.mf_xv,
-                       d.mf_flux, skip);
-    hipLaunchKernelGGL(k_mf_gather, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, d.mf_flux, y, skip);
+    hipLaunchKernelGGL(k_mf_cell, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, x, d.mf_xv, y, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_mf_cell_setup(const Dev& d, const BcTable& bc_pot, hipStream_t s) {
+    hipLaunchKernelGGL(k_mf_cell_setup, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, bc_pot);
     return hipGetLastError();
 }
 
 namespace {
 // one part of q = K p (FP64 p, or FP32 p32 into the same scratch arrays
-// taken as floats)
+// taken as floats): 0 the ghost and vertex values, 1 the per-cell product
+// with the p.q partials, 2 alpha
 template <class R>
 void mf_cg_part(const Dev& d, const BcTable& bc, int part, const R* p, hipStream_t s) {
     const double* none = nullptr;
     R* xg = reinterpret_cast<R*>(d.mf_xg);
     R* xv = reinterpret_cast<R*>(d.mf_xv);
-    R* F = reinterpret_cast<R*>(d.mf_flux);
     if (part == 0) {
         if (d.nb > 0)
             hipLaunchKernelGGL(k_mf_ghost<R>, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d,
                                bc, p, xg, none);
         hipLaunchKernelGGL(k_mf_vertex<R>, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, p, xg, xv, none);
     } else if (part == 1) {
-        hipLaunchKernelGGL((k_mf_face<R, kMfFacesPerThread>), dim3(rows_m(d.nf, kBlock * kMfFacesPerThread)),
-                           dim3(kBlock), 0, s, d, bc, p, xv, F, none);
+        const int64_t nblk = (d.nc + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_mf_cg_cell<R>, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, nblk);
     } else {
         const int64_t nblk = (d.nc + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(k_mf_cg_gather<R>, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, F, nblk);
         hipLaunchKernelGGL(k_cg_alpha<1>, dim3(d.nm), dim3(1024), 0, s, d, nblk, int64_t(kBlock));
     }
 }
@@ -246,7 +289,7 @@ hipError_t launch_mf_cg_part(const Dev& d, const BcTable& bc, int part, hipStrea
 
 hipError_t launch_mf_cg_spmv(const Dev& d, const BcTable& bc, hipStream_t s) {
     hipError_t e = hipSuccess;
-    for (int part = 0; part < 3 && e == hipSuccess; ++part) e = launch_mf_cg_part(d, bc, part, s);
+    for (int part = 0; part < kMfParts && e == hipSuccess; ++part) e = launch_mf_cg_part(d, bc, part, s);
     return e;
 }
 
@@ -257,7 +300,7 @@ hipError_t launch_mf_cg32_part(const Dev& d, const BcTable& bc, int part, hipStr
 
 hipError_t launch_mf_cg32_spmv(const Dev& d, const BcTable& bc, hipStream_t s) {
     hipError_t e = hipSuccess;
-    for (int part = 0; part < 3 && e == hipSuccess; ++part) e = launch_mf_cg32_part(d, bc, part, s);
+    for (int part = 0; part < kMfParts && e == hipSuccess; ++part) e = launch_mf_cg32_part(d, bc, part, s);
     return e;
 }
 

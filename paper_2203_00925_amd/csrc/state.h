@@ -91,6 +91,12 @@ struct Dev {
     double *np_ion, *efield;              // coupled loop: ion density [nc], E [3][nc]
     double *mf_xv, *mf_flux, *mf_xg;      // matrix-free operator: vertex values [nv], face fluxes [nf],
                                           // ghost values [nb]
+    // matrix-free operator per cell i (from the faces and the potential's
+    // boundary kinds): (K x)_i = -(sum_k w[k] x_v[vid[k]] + sum_k r[k] x[c2n[k]] - dg x_i)
+    // over the cell's 4 vertices and 4 faces ([4][nc] each; FP32 copies)
+    int32_t* mfc_vid;
+    double *mfc_w, *mfc_r, *mfc_d;
+    float *mfc_w32, *mfc_r32, *mfc_d32;
     double* partial;                      // reduction partials ([k][block], k < 4)
     double* scal;                         // solver scalars, [nm][SC_COUNT_]
 };
@@ -102,7 +108,7 @@ struct FvArrays {
     const R *phi, *minv, *kAC, *kBC, *kRL, *area, *vol, *src, *n_alpha, *fx, *xc, *gdist;
 };
 
-constexpr int kNumKernels = 20;
+constexpr int kNumKernels = 21;
 
 struct NnDev;
 struct NnStateDev;
@@ -143,6 +149,7 @@ struct State {
     int tuned_chunk = 0, tuned_graph = 0, tuned_step_graph = 0;
     bool assembled = false;               // K's stored values, diagonal and c match the BCs
     bool consts_ready = false;            // diagonal, D^-1 and c match the BCs (matrix-free solves)
+    bool mfc_ready = false;               // the matrix-free per-cell tables match the potential's BC kinds
     bool k32_ready = false;               // FP32 copy of K matches K
     bool vel_set = false;
     double* h_scal = nullptr;             // pinned host mirror of scalars
@@ -187,6 +194,8 @@ hipError_t setup_fv_kernels(const Dev& d);
 hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
 // the RK stage update; it also sets the ghosts behind the updated cells
 hipError_t launch_update(const Dev& d, bool fp32, const BcTable& bc, double alpha, bool first_stage, hipStream_t s);
+// the matrix-free per-cell tables (mf_kernels.hip)
+hipError_t launch_mf_cell_setup(const Dev& d, const BcTable& bc_pot, hipStream_t s);
 hipError_t launch_set_dt(const Dev& d, double dt, double cfl, hipStream_t s);
 hipError_t launch_residual_out(const Dev& d, bool fp32, double* res_internal, hipStream_t s);
 hipError_t launch_face_phi(const Dev& d, hipStream_t s);
@@ -223,11 +232,12 @@ hipError_t launch_cg_dir(const Dev& d, hipStream_t s);
 hipError_t launch_mf_apply(const Dev& d, const BcTable& bc, const double* x, double* y, hipStream_t s,
                            const double* skip = nullptr);
 hipError_t launch_mf_cg_spmv(const Dev& d, const BcTable& bc, hipStream_t s);
-// the three launches of launch_mf_cg_spmv one by one (part 0 vertex values,
-// 1 face fluxes, 2 gather + p.q + alpha), for per-kernel timing
+// the parts of launch_mf_cg_spmv one by one (part 0 ghost and vertex values,
+// 1 the per-cell product + p.q partials, 2 alpha), for per-kernel timing
+constexpr int kMfParts = 3;
 hipError_t launch_mf_cg_part(const Dev& d, const BcTable& bc, int part, hipStream_t s);
 // the same product in FP32 for the inner CG of the refined solve: q32 = K p32
-// with the FP32 coefficient copies, partial p32.q32 in FP64
+// with the FP32 vertex weights and per-cell tables, partial p32.q32 in FP64
 hipError_t launch_mf_cg32_spmv(const Dev& d, const BcTable& bc, hipStream_t s);
 hipError_t launch_mf_cg32_part(const Dev& d, const BcTable& bc, int part, hipStream_t s);
 
