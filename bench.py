@@ -51,7 +51,7 @@ KERNEL_NAMES = {"grad_limiter": "k_grad_moments", "mf_gather": "k_mf_cg_cell"}
 KERNEL_FILES = {
     "grad_limiter": "fv_kernels.hip", "face_flux": "fv_kernels.hip", "update": "fv_kernels.hip",
     "cg_spmv": "solve_kernels.hip", "cg_axpy": "solve_kernels.hip", "cg_dir": "solve_kernels.hip",
-    "mf_vertex": "mf_kernels.hip", "mf_gather": "mf_kernels.hip",
+    "mf_vertex": ("mf_kernels.hip", "mf_cell.h"), "mf_gather": ("mf_kernels.hip", "mf_cell.h"),
 }
 
 
@@ -86,7 +86,8 @@ def measure_copy_peak(gib=1, reps=10):
 def kernel_source_hash(name):
     import hashlib
     h = hashlib.sha256()
-    for f in (KERNEL_FILES[name], "reduce.h", "seg.h", "cg_scalars.h", "halo_stage.h"):
+    files = KERNEL_FILES[name] if isinstance(KERNEL_FILES[name], tuple) else (KERNEL_FILES[name],)
+    for f in files + ("reduce.h", "seg.h", "cg_scalars.h", "halo_stage.h"):
         with open(os.path.join(ROOT, "paper_2203_00925_amd", "csrc", f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())

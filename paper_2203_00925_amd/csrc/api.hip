@@ -141,7 +141,6 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.np_ion = carve<double>(base, off, nc);
     d.efield = carve<double>(base, off, 3 * nc);
     d.mf_xv = carve<double>(base, off, nv);
-    d.mf_flux = carve<double>(base, off, nf);
     d.mf_xg = carve<double>(base, off, nb > 0 ? nb : 1);
     d.mfc_vid = carve<int32_t>(base, off, 4 * nc);
     d.mfc_w = carve<double>(base, off, 4 * nc);

@@ -1,6 +1,6 @@
 // Batched form: the Poisson solves of many independent meshes of one state
 // run in one persistent kernel.  Each mesh's matrix-free Jacobi-CG is a
-// sequence of phases (vertex values, face fluxes, cell gather, update,
+// sequence of phases (vertex values, the per-cell product, update,
 // direction; and the opening from the true residual); a phase is split into
 // items of consecutive rows.  Workgroups pull (mesh, phase, item) from
 // per-mesh device queues; the workgroup that completes a phase's last item
@@ -26,11 +26,9 @@ constexpr int kBatchMaxMeshes = 4096;
 // 32 bits and the next unclaimed item in its low 32 bits)
 enum BatchPhase : uint32_t {
     BP_OV = 0,   // open: vertex values of x
-    BP_OF,       // open: face fluxes of x
-    BP_OG,       // open: r = b - K x, z = D^-1 r, p = z; partial rz, rr, bb
+    BP_OG,       // open: r = b - K x (per-cell product), z = D^-1 r, p = z; partial rz, rr, bb
     BP_V,        // vertex values of p
-    BP_F,        // face fluxes of p
-    BP_G,        // q = K p; partial p.q  -> alpha
+    BP_G,        // q = K p (per-cell product); partial p.q  -> alpha
     BP_AX,       // x += alpha p, r -= alpha q, z = D^-1 r; partial rz, rr -> beta, tests
     BP_DIR,      // p = z + beta p
     BP_ZX,       // b = 0: x = 0

@@ -8,6 +8,7 @@
 // faces (the matrix-free product of eqs. (7), (laplace)), and the CG vector
 // updates.
 #include "batch.h"
+#include "mf_cell.h"
 #include "reduce.h"
 #include "seg.h"
 #include "state.h"
@@ -19,8 +20,6 @@ __device__ inline int64_t phase_rows(const BatchRange& r, uint32_t ph) {
     switch (ph) {
         case BP_OV:
         case BP_V: return r.v1 - r.v0;
-        case BP_OF:
-        case BP_F: return (r.fi1 - r.fi0) + (r.fb1 - r.fb0);
         case BP_IDLE: return 0;
         default: return r.c1 - r.c0;
     }
@@ -90,36 +89,6 @@ __device__ inline double vertex_value(const Dev& d, const BatchDev& b, const dou
     return s;
 }
 
-// F_f = kAC (x_A - x_C) + kBC (x_B - x_C) + kRL (x_R - x_L); a Dirichlet
-// face's R is the ghost (-x_L); other boundary faces carry no term of K
-__device__ inline double face_flux(const Dev& d, const BatchDev& b, const double* __restrict__ src,
-                                   const double* __restrict__ xv, int64_t f) {
-    const int L = d.fL[f];
-    double xr;
-    if (f >= d.nfi) {
-        if (b.gsign[f - d.nfi] > 0.0) return 0.0;
-        xr = -src[L];
-    } else {
-        xr = src[d.fR[f]];
-    }
-    const double xc = xv[d.fC[f]];
-    return d.kAC[f] * (xv[d.fA[f]] - xc) + d.kBC[f] * (xv[d.fB[f]] - xc) + d.kRL[f] * (xr - src[L]);
-}
-
-// (K x)_i = -sum_f s_if F_f
-__device__ inline double gather_row(const Dev& d, const double* __restrict__ F, int64_t i) {
-    int code[4];
-    double fl[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) code[k] = d.c2f[k * d.nc + i];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) fl[k] = F[code[k] >= 0 ? code[k] : ~code[k]];
-    double y = 0.0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) y += code[k] >= 0 ? -fl[k] : fl[k];
-    return y;
-}
-
 // one item: rows [lo, hi) of the phase's range; partial sums of the item
 // into its slots
 template <int VB>
@@ -137,21 +106,11 @@ __device__ void run_item(const Dev& d, const BatchDev& b, const BatchRange& r, u
             for (int64_t k = lo + tid; k < hi; k += kBatchBlock) d.mf_xv[r.v0 + k] = vertex_value<VB>(d, b, src, r.v0 + k);
             break;
         }
-        case BP_OF:
-        case BP_F: {
-            const double* src = ph == BP_OF ? d.x : d.p;
-            const int64_t ni = r.fi1 - r.fi0;
-            for (int64_t k = lo + tid; k < hi; k += kBatchBlock) {
-                const int64_t f = k < ni ? r.fi0 + k : r.fb0 + (k - ni);
-                d.mf_flux[f] = face_flux(d, b, src, d.mf_xv, f);
-            }
-            break;
-        }
         case BP_OG:
             for (int64_t k = lo + tid; k < hi; k += kBatchBlock) {
                 const int64_t i = r.c0 + k;
                 const double bi = d.b[i];
-                const double ri = bi - gather_row(d, d.mf_flux, i);
+                const double ri = bi - cell_row(d, d.x, d.mf_xv, i);
                 const double zi = d.k_dinv[i] * ri;
                 d.r[i] = ri;
                 d.z[i] = zi;
@@ -164,7 +123,7 @@ __device__ void run_item(const Dev& d, const BatchDev& b, const BatchRange& r, u
         case BP_G:
             for (int64_t k = lo + tid; k < hi; k += kBatchBlock) {
                 const int64_t i = r.c0 + k;
-                const double y = gather_row(d, d.mf_flux, i);
+                const double y = cell_row(d, d.p, d.mf_xv, i);
                 d.q[i] = y;
                 v0 += d.p[i] * y;
             }
@@ -173,7 +132,7 @@ __device__ void run_item(const Dev& d, const BatchDev& b, const BatchRange& r, u
             const double alpha = sc[SC_ALPHA];
             for (int64_t k = lo + tid; k < hi; k += kBatchBlock) {
                 const int64_t i = r.c0 + k;
-                d.x[i] = d.x[i] + alpha * d.p[i];
+                d.x[i] += alpha * d.p[i];
                 const double ri = d.r[i] - alpha * d.q[i];
                 const double zi = d.k_dinv[i] * ri;
                 d.r[i] = ri;
@@ -230,10 +189,8 @@ __device__ uint32_t finish_phase(const Dev& d, const BatchDev& b, const BatchRan
     const int64_t n = phase_items(b, r, ph);
     const bool t0 = threadIdx.x == 0;
     switch (ph) {
-        case BP_OV: return BP_OF;
-        case BP_OF: return BP_OG;
-        case BP_V: return BP_F;
-        case BP_F: return BP_G;
+        case BP_OV: return BP_OG;
+        case BP_V: return BP_G;
         case BP_DIR: return BP_V;
         case BP_ZX: return BP_IDLE;
         case BP_G: {

@@ -15,6 +15,7 @@
 #include <type_traits>
 
 #include "cg_scalars.h"
+#include "mf_cell.h"
 #include "reduce.h"
 #include "seg.h"
 #include "state.h"
@@ -157,50 +158,6 @@ __global__ __launch_bounds__(kBlock) void k_mf_cell_setup(Dev d, BcTable bc) {
     }
     d.mfc_d[i] = dg;
     d.mfc_d32[i] = float(dg);
-}
-
-template <class R> struct MfCell;
-template <> struct MfCell<double> {
-    __device__ static const double* w(const Dev& d) { return d.mfc_w; }
-    __device__ static const double* r(const Dev& d) { return d.mfc_r; }
-    __device__ static const double* dg(const Dev& d) { return d.mfc_d; }
-};
-template <> struct MfCell<float> {
-    __device__ static const float* w(const Dev& d) { return d.mfc_w32; }
-    __device__ static const float* r(const Dev& d) { return d.mfc_r32; }
-    __device__ static const float* dg(const Dev& d) { return d.mfc_d32; }
-};
-
-// (K x)_i from the tables: the row's table loads go out together, then its
-// 4 vertex values and 4 neighbour values (a boundary face reads x_i, with
-// r = 0)
-template <class R>
-__device__ inline R cell_row(const Dev& d, const R* __restrict__ x, const R* __restrict__ xv, int64_t i) {
-    const int64_t nc = d.nc;
-    const R* __restrict__ W = MfCell<R>::w(d);
-    const R* __restrict__ Rk = MfCell<R>::r(d);
-    int vid[4], nb[4];
-    R w[4], r[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        vid[k] = d.mfc_vid[k * nc + i];
-        nb[k] = d.c2n[k * nc + i];
-        w[k] = W[k * nc + i];
-        r[k] = Rk[k * nc + i];
-    }
-    const R dg = MfCell<R>::dg(d)[i], xi = x[i];
-    R xvv[4], xn[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        xvv[k] = xv[vid[k]];
-        xn[k] = x[nb[k] < nc ? nb[k] : i];
-    }
-    R acc = -dg * xi;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc += w[k] * xvv[k];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc += r[k] * xn[k];
-    return -acc;
 }
 
 __global__ __launch_bounds__(kBlock) void k_mf_cell(Dev d, const double* __restrict__ x,

@@ -89,8 +89,7 @@ struct Dev {
     float *minv32, *kAC32, *kBC32, *kRL32, *area32, *vol32, *n_alpha32, *fx32, *xc32, *gdist32;
     double* tmp;                          // nc+nb scratch (permutation, residual)
     double *np_ion, *efield;              // coupled loop: ion density [nc], E [3][nc]
-    double *mf_xv, *mf_flux, *mf_xg;      // matrix-free operator: vertex values [nv], face fluxes [nf],
-                                          // ghost values [nb]
+    double *mf_xv, *mf_xg;                // matrix-free operator: vertex values [nv], ghost values [nb]
     // matrix-free operator per cell i (from the faces and the potential's
     // boundary kinds): (K x)_i = -(sum_k w[k] x_v[vid[k]] + sum_k r[k] x[c2n[k]] - dg x_i)
     // over the cell's 4 vertices and 4 faces ([4][nc] each; FP32 copies)
