@@ -43,13 +43,11 @@ MEASURED_TRAFFIC = {"cube120": {
     "k_cg_axpy": {"src": "2632548940b858f0", "bytes": 668815360},
     "k_cg_dir": {"src": "2632548940b858f0", "bytes": 248862720},
     "k_grad_moments": {"src": "5c7dbc8b429ce3a1", "bytes": 3721005056},
-    "k_face_flux": {"src": "5c7dbc8b429ce3a1", "bytes": 2575641600},
-    "k_update": {"src": "5c7dbc8b429ce3a1", "bytes": 927618048},
 }}
 # timing id -> the FP64 kernel it times
-KERNEL_NAMES = {"grad_limiter": "k_grad_moments", "mf_gather": "k_mf_cg_cell"}
+KERNEL_NAMES = {"grad_limiter": "k_grad_moments", "mf_gather": "k_mf_cg_cell", "fv_cell": "k_cell_step"}
 KERNEL_FILES = {
-    "grad_limiter": "fv_kernels.hip", "face_flux": "fv_kernels.hip", "update": "fv_kernels.hip",
+    "grad_limiter": "fv_kernels.hip", "fv_cell": "fv_kernels.hip",
     "cg_spmv": "solve_kernels.hip", "cg_axpy": "solve_kernels.hip", "cg_dir": "solve_kernels.hip",
     "mf_vertex": ("mf_kernels.hip", "mf_cell.h"), "mf_gather": ("mf_kernels.hip", "mf_cell.h"),
 }
@@ -120,19 +118,19 @@ def algorithmic_bytes(info):
         # z, u of cells and ghosts 32; own vertex lists: 16-bit local index 2
         # + weight 8 per entry, list length 4 and value written 8 per vertex;
         # foreign vertex lists: index 2 per entry, length 4 per row; per cell
-        # c2f 16, local face neighbours 8, local vertices 8, M^-1 48, grad +
-        # psi written 32; edge-only neighbours: index 2 per entry; face
-        # centroids 24/face
+        # c2f 16, local face neighbours 8, local vertices 8, M^-1 48, the
+        # four face values written 32; edge-only neighbours: index 2 per
+        # entry; face centroids 24/face
         "grad_limiter": halo * 4 + (nc + nb) * 32 + info.node_entries * 10 + nv * 12
         + info.foreign_entries * 2 + info.foreign_rows * 4 + nc * (16 + 8 + 8 + 48 + 32)
         + info.edge_nbr_entries * 2 + nf * 24,
-        # per face: L,R,A,B,C 20 + kAC,kBC,kRL,phi 32 + centroid 24 + F 8;
-        # per cell (gathered): u 8 and the upwind record (psi g, u - psi g.x)
-        # 32; vertex values 8
-        "face_flux": nf * 84 + nc * 40 + nv * 8,
-        # per cell: c2f 16, F 16 (each face read by its 2 cells), vol 8,
-        # src 8, u^n 8, u written 8
-        "update": nc * (16 + 16 + 8 + 8 + 8 + 8),
+        # the FP64 stage in one pass per cell: per cell outward phi 32, c2n
+        # 16, face slots 1, vertex ids 16, vertex weights 32, kRL weights 32,
+        # its four face values 32 (the neighbours' gathered, counted once),
+        # u_in 8, u^n 8, vol 8, src 8, u written 8; the vertex values 8 per
+        # vertex, gathered once; per ghost: its value read and written 16,
+        # its face's kAC, kBC, kRL, A, B, C, area, tag, value and distance 64
+        "fv_cell": nc * 201 + nv * 8 + nb * 80,
         # value 8 + 16-bit local index 2 per off-diagonal entry; tile halo
         # list 4/entity; p 8, diagonal 8, q written 8 per row
         "cg_spmv": offdiag * 10 + halo * 4 + nc * 24,
@@ -319,7 +317,7 @@ def main():
     st.kernel_timing(False)
     st.set_field(B.FIELD_U, u_keep)
     del u_keep
-    for k in ("ghost_fill", "grad_limiter", "face_flux", "update"):
+    for k in ("ghost_fill", "grad_limiter", "fv_cell"):
         kstats[k] = fv_stats[k]
     solve_ms = [e[1].elapsed_time(e[2]) for e in events]
     total1 = st.conservation()
@@ -384,7 +382,7 @@ def main():
         # the kernel with the most GPU time in the timed region
         "roofline": roof(max(("mf_vertex", "mf_gather", "cg_axpy", "cg_dir", "grad_limiter"),
                              key=lambda k: kstats[k][0])),
-        "roofline_fv": {k: roof(k) for k in ("grad_limiter", "face_flux", "update")},
+        "roofline_fv": {k: roof(k) for k in ("grad_limiter", "fv_cell")},
         "roofline_cg": {k: roof(k) for k in ("mf_vertex", "mf_gather", "cg_axpy", "cg_dir")},
         "measured_streams_GBps": streams,
     }

@@ -637,7 +637,9 @@ enum mifvm_kernel {
     the cell's vertices and faces, with p.q (CG_SPMV counts the stored-matrix product) */,
     MIFVM_K_NN_FUSED = 19 /* the whole network in one launch (encoder, 3 layers, decoder) */,
     MIFVM_K_CG_ALPHA = 20 /* the matrix-free CG's alpha step (its p.q partials summed per mesh) */,
-    MIFVM_K_COUNT = 21
+    MIFVM_K_FV_CELL = 21 /* FP64 step: face fluxes and the RK stage update in one pass per cell
+    (FACE_FLUX and UPDATE then count the FP32 step and the residual evaluation) */,
+    MIFVM_K_COUNT = 22
 };
 int mifvm_kernel_timing(mifvm_state* st, int32_t enable);
 /* Total milliseconds and number of timed launches of one kernel since the

@@ -27,7 +27,7 @@ FP64, FP32 = 0, 1
 F64, F32 = 0, 1                           # element types of field arrays at the ABI
 KERNELS = ("ghost_fill", "grad_limiter", "node_interp", "face_flux", "update", "cg_setup",
            "cg_spmv", "cg_axpy", "cg_dir", "rhs", "assemble", "nn_layer1", "nn_layer2", "nn_layer3",
-           "fcg_vec", "nn_train", "mf_vertex", "mf_face", "mf_gather", "nn_fused", "cg_alpha")
+           "fcg_vec", "nn_train", "mf_vertex", "mf_face", "mf_gather", "nn_fused", "cg_alpha", "fv_cell")
 NN_PARAMS = 9537
 LOSS_RESIDUAL, LOSS_ENERGY = 0, 1
 NN_FORM_AUTO, NN_FORM_LAYERS, NN_FORM_FUSED = 0, 1, 2

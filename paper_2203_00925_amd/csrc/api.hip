@@ -110,7 +110,14 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.phi = carve<double>(base, off, nf);
     d.grad = carve<double>(base, off, 3 * nc);
     d.psi = carve<double>(base, off, nc);
-    d.rec = carve<double4>(base, off, nc);
+    d.uf = carve<double>(base, off, 4 * nc);
+    d.u_b = carve<double>(base, off, NX);
+    d.u_c = carve<double>(base, off, NX);
+    d.fvc_vid = carve<int32_t>(base, off, 4 * nc);
+    d.fvc_w = carve<double>(base, off, 4 * nc);
+    d.fvc_r = carve<double>(base, off, 4 * nc);
+    d.fvc_slot = carve<uint8_t>(base, off, nc);
+    d.fvc_phi = carve<double>(base, off, 4 * nc);
     d.unode = carve<double>(base, off, nv);
     d.flux = carve<double>(base, off, nf);
     d.x = carve<double>(base, off, nc);
@@ -384,6 +391,7 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     if (e == hipSuccess) e = hipMemsetAsync(d.src, 0, m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.vel, 0, 3 * m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.phi, 0, m.nf * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.fvc_phi, 0, 4 * m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.x, 0, m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.np_ion, 0, m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.efield, 0, 3 * m.nc * sizeof(double), s);
@@ -395,6 +403,7 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     if (e == hipSuccess && m.nb > 0) e = hipMemsetAsync(d.gval32, 0, m.nb * sizeof(float), s);
     if (e == hipSuccess) e = setup_fv_kernels(d);
     if (e == hipSuccess) e = launch_make_fp32_geometry(d, (int64_t)m.node.val.size(), s);
+    if (e == hipSuccess) e = launch_fv_cell_setup(d, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);   // host vectors are not pinned
     if (e != hipSuccess) return cleanup(hip_fail(e, "state init"));
     *out = h;
@@ -583,15 +592,23 @@ int mifvm_cfl_dt(mifvm_state* st, double cfl, double* dt_out, void* stream) {
 
 namespace {
 // ghost fill (unless the ghosts are known current), gradient + limiter +
-// vertex values, face fluxes
-int residual_parts(State& s, hipStream_t hs, bool parts = false, bool ghosts = true) {
+// vertex values, face fluxes: the residual evaluation and the FP32 step
+int residual_parts(State& s, hipStream_t hs, bool ghosts = true) {
     const Dev& d = s.d;
     KernelTimer& t = s.timer;
     if (ghosts)
         HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, s.fp32, s.bc[0], hs); }));
-    HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, s.fp32, hs, parts); }));
+    HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, s.fp32, hs, true); }));
     HIPCHK(timed(t, MIFVM_K_FACE_FLUX, hs, [&] { return launch_face_flux(d, s.fp32, s.bc[0], hs); }));
     return MIFVM_OK;
+}
+
+// the FP64 step's buffers of RK stage k: every stage adds to u^n (kept in
+// u), so stage 0 reads u and writes u_b, stage 1 reads u_b and writes u_c,
+// stage 2 reads u_c and writes u (cell i alone reads u[i] there)
+void stage_buffers(const Dev& d, int k, const double** uin, double** uout) {
+    *uin = k == 0 ? d.u : (k == 1 ? d.u_b : d.u_c);
+    *uout = k == 0 ? d.u_b : (k == 1 ? d.u_c : d.u);
 }
 }  // namespace
 
@@ -603,13 +620,26 @@ int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream) {
     if (dt == 0.0 && !(s.cfl > 0)) return fail(MIFVM_E_STATE, "dt = 0 asks for the CFL steps: call mifvm_cfl_dt first");
     if (n_steps > 0) HIPCHK(launch_set_dt(s.d, dt, s.cfl, hs));
     static const double alpha[3] = {0.5, 0.5, 1.0};
+    const Dev& d = s.d;
+    KernelTimer& t = s.timer;
     // the ghosts are filled once; every update then sets those of its cells
     for (int n = 0; n < n_steps; ++n)
         for (int k = 0; k < 3; ++k) {
-            int rc = residual_parts(s, hs, false, n == 0 && k == 0);
-            if (rc) return rc;
-            HIPCHK(timed(s.timer, MIFVM_K_UPDATE, hs,
-                         [&] { return launch_update(s.d, s.fp32, s.bc[0], alpha[k], k == 0, hs); }));
+            const bool fill = n == 0 && k == 0;
+            if (s.fp32) {
+                int rc = residual_parts(s, hs, fill);
+                if (rc) return rc;
+                HIPCHK(timed(t, MIFVM_K_UPDATE, hs,
+                             [&] { return launch_update(d, true, s.bc[0], alpha[k], k == 0, hs); }));
+                continue;
+            }
+            const double* uin;
+            double* uout;
+            stage_buffers(d, k, &uin, &uout);
+            if (fill)
+                HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, false, s.bc[0], hs); }));
+            HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, false, hs, false, uin); }));
+            HIPCHK(timed(t, MIFVM_K_FV_CELL, hs, [&] { return launch_cell_step(d, s.bc[0], uin, uout, alpha[k], hs); }));
         }
     return MIFVM_OK;
 }
@@ -625,9 +655,17 @@ hipError_t enqueue_steps(const State& s, int n, double dt, hipStream_t q) {
     // the ghosts are filled once; every update then sets those of its cells
     if (e == hipSuccess && n > 0) e = launch_ghost_fill(d, s.fp32, s.bc[0], q);
     for (int k = 0; e == hipSuccess && k < 3 * n; ++k) {
-        e = launch_grad_limiter(d, s.fp32, q);
-        if (e == hipSuccess) e = launch_face_flux(d, s.fp32, s.bc[0], q);
-        if (e == hipSuccess) e = launch_update(d, s.fp32, s.bc[0], alpha[k % 3], k % 3 == 0, q);
+        if (s.fp32) {
+            e = launch_grad_limiter(d, true, q);
+            if (e == hipSuccess) e = launch_face_flux(d, true, s.bc[0], q);
+            if (e == hipSuccess) e = launch_update(d, true, s.bc[0], alpha[k % 3], k % 3 == 0, q);
+            continue;
+        }
+        const double* uin;
+        double* uout;
+        stage_buffers(d, k % 3, &uin, &uout);
+        e = launch_grad_limiter(d, false, q, false, uin);
+        if (e == hipSuccess) e = launch_cell_step(d, s.bc[0], uin, uout, alpha[k % 3], q);
     }
     return e;
 }
@@ -657,7 +695,7 @@ int mifvm_residual(mifvm_state* st, double* d_res, double* d_grad, double* d_psi
     State& s = st->s;
     const Dev& d = s.d;
     hipStream_t hs = S(stream);
-    int rc = residual_parts(s, hs, d_grad != nullptr || d_psi != nullptr);
+    int rc = residual_parts(s, hs);
     if (rc) return rc;
     if (d_res) {
         HIPCHK(launch_residual_out(d, s.fp32, d.tmp, hs));

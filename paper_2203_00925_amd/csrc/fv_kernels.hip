@@ -351,23 +351,22 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
     const R gx = m0 * jx + m1 * jy + m2 * jz;
     const R gy = m1 * jx + m3 * jy + m4 * jz;
     const R gz = m2 * jx + m4 * jy + m5 * jz;
-    R psi = R(1);
+    R psi = R(1), dl[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const R dl = gx * (R(xf[k].x - ref.x) - xi) + gy * (R(xf[k].y - ref.y) - yi) +
-                     gz * (R(xf[k].z - ref.z) - zi);
+        dl[k] = gx * (R(xf[k].x - ref.x) - xi) + gy * (R(xf[k].y - ref.y) - yi) + gz * (R(xf[k].z - ref.z) - zi);
         R ph = R(1);
-        if (dl > R(0)) ph = fmin(R(1), (umax - ui) / dl);
-        else if (dl < R(0)) ph = fmin(R(1), (umin - ui) / dl);
+        if (dl[k] > R(0)) ph = fmin(R(1), (umax - ui) / dl[k]);
+        else if (dl[k] < R(0)) ph = fmin(R(1), (umin - ui) / dl[k]);
         psi = fmin(psi, ph);
     }
-    // FP64: the face kernel's upwind data in one record, (psi g, u - psi g.x_i),
-    // so that u + psi g.(x_f - x_i) is rec.w + rec.xyz . x_f without the
-    // cell's centre; the separate arrays only when the caller asks for them.
-    // FP32: the arrays (the FP32 face kernel reads them)
-    if constexpr (!rel) {
-        const double px = psi * gx, py = psi * gy, pz = psi * gz;
-        d.rec[i] = make_double4(px, py, pz, ui - (px * xi + py * yi + pz * zi));
+    // FP64 step: the MUSCL value u + psi g.(x_f - x_i) at each of the cell's
+    // face centroids (in c2f order), which the cell step reads for both sides
+    // of a face.  With parts (and always in FP32): the gradient and limiter
+    // arrays, which the face kernel reads.
+    if constexpr (!rel && !PARTS) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d.uf[k * nc + i] = ui + psi * dl[k];
     }
     if (PARTS || rel) {
         a.grad[i] = gx;
@@ -377,9 +376,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
     }
 }
 
-// One thread per face.  Every load of the face goes out before its first
-// branch (boundary faces read a valid dummy where they need no data); the
-// arithmetic of each kind of face is unchanged by that.
+// One thread per face (the FP32 step and the residual evaluation; it reads
+// the gradient and limiter arrays).  Every load of the face goes out before
+// its first branch (boundary faces read a valid dummy where they need no
+// data); the arithmetic of each kind of face is unchanged by that.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTable bc) {
     const int64_t f = gtid();
@@ -402,20 +402,12 @@ __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTa
     const int up = ph >= R(0) ? L : Rc;
     const bool cellside = up < nc;          // MUSCL on a cell side; a ghost side is first order
     const int uc = cellside ? up : L;
-    R uup;
-    if constexpr (std::is_same<R, double>::value) {
-        // FP64: the upwind cell's record (psi g, u - psi g.x_c) gives the
-        // MUSCL value at the face centroid
-        const double4 rc = d.rec[uc];
-        uup = cellside ? rc.w + (rc.x * fxx + rc.y * fxy + rc.z * fxz) : (up == L ? uL : uR);
-    } else {
-        const R rx = fxx - a.xc[uc];
-        const R ry = fxy - a.xc[NX + uc];
-        const R rz = fxz - a.xc[2 * NX + uc];
-        const R gr = a.grad[uc] * rx + a.grad[nc + uc] * ry + a.grad[2 * nc + uc] * rz;
-        const R uupc = up == L ? uL : uR;
-        uup = cellside ? uupc + a.psi[uc] * gr : uupc;
-    }
+    const R rx = fxx - a.xc[uc];
+    const R ry = fxy - a.xc[NX + uc];
+    const R rz = fxz - a.xc[2 * NX + uc];
+    const R gr = a.grad[uc] * rx + a.grad[nc + uc] * ry + a.grad[2 * nc + uc] * rz;
+    const R uupc = up == L ? uL : uR;
+    const R uup = cellside ? uupc + a.psi[uc] * gr : uupc;
     const R diff = kind == kNeumann ? val * area : cAC * (uA - uC) + cBC * (uB - uC) + cRL * (uR - uL);
     a.flux[f] = kind == kZeroFlux ? R(0) : uup * ph - D * diff;
 }
@@ -466,6 +458,158 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev d, FvArrays<R> a, BcTable
     }
 }
 
+// ---- the FP64 step: face fluxes and update in one pass per cell -------------
+// The residual of cell i is -(1/vol_i) sum_k s_k F_k + src_i over its four
+// faces, s_k = +1 where the cell is the face's L side.  On the interior
+// faces the diffusive parts are regrouped per cell as in the matrix-free
+// product: a face of a tetrahedron holds three of the cell's four vertices,
+// so sum_k s_k (kAC (u_A - u_C) + kBC (u_B - u_C)) = sum_v w_v u_node[v], and
+// s_k kRL (u_R - u_L) = kRL (u_n - u_i) with n the cell across face k.  The
+// convective part is (s_k phi_f) times the upwind side's MUSCL value at the
+// face centroid, which the gradient kernel stores per cell and face: uf[k][i]
+// on the cell's side, uf[j][n] across (j = the face's slot among n's
+// faces).  Both cells of a face take the same upwind value, so its
+// convective parts cancel exactly in the sum over cells.  Boundary faces
+// (the cell is always their L side) are evaluated as in k_face_flux.
+
+// the tables: geometry only, built once per state
+__global__ __launch_bounds__(kBlock) void k_fv_cell_setup(Dev d) {
+    const int64_t i = gtid();
+    if (i >= d.nc) return;
+    const int64_t nc = d.nc;
+    int vid[4] = {-1, -1, -1, -1};
+    double w[4] = {0.0, 0.0, 0.0, 0.0}, r[4] = {0.0, 0.0, 0.0, 0.0};
+    auto add = [&](int v, double c) {                 // the vertex's slot (first seen, first slot)
+        bool done = false;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool hit = !done && (vid[q] == v || vid[q] < 0);
+            if (hit) {
+                vid[q] = v;
+                w[q] += c;
+            }
+            done = done || hit;
+        }
+    };
+    uint32_t slots = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int code = d.c2f[k * nc + i];
+        const int f = code >= 0 ? code : ~code;
+        const double sg = code >= 0 ? 1.0 : -1.0;
+        const bool in = f < d.nfi;
+        // a boundary face only places its vertices (weight 0): every vertex
+        // of the cell gets a slot
+        const double on = in ? sg : 0.0;
+        const double kac = d.kAC[f], kbc = d.kBC[f];
+        add(d.fA[f], on * kac);
+        add(d.fB[f], on * kbc);
+        add(d.fC[f], on * (-(kac + kbc)));
+        r[k] = in ? d.kRL[f] : 0.0;
+        const int n = in ? d.c2n[k * nc + i] : int(i);
+        uint32_t j = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cn = d.c2f[q * nc + n];
+            if ((cn >= 0 ? cn : ~cn) == f) j = uint32_t(q);
+        }
+        slots |= (in ? j : 0u) << (2 * k);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        d.fvc_vid[q * nc + i] = vid[q] >= 0 ? vid[q] : vid[0];
+        d.fvc_w[q * nc + i] = w[q];
+        d.fvc_r[q * nc + i] = r[q];
+    }
+    d.fvc_slot[i] = uint8_t(slots);
+}
+
+// u_out[i] = u[i] + alpha dt Res(u_in)_i (u holds u^n; u_in and u_out are
+// other buffers, or u_out = u on the last stage, whose cell i alone reads
+// u[i]); then the ghosts behind the cell's boundary faces, from the new value
+__global__ __launch_bounds__(kBlock) void k_cell_step(Dev d, BcTable bc, const double* __restrict__ uin,
+                                                      double* uout, double alpha) {
+    const int64_t i = gtid_m();                        // XCD-contiguous: neighbours' data in one L2
+    if (i >= d.nc) return;
+    const int64_t nc = d.nc;
+    const int m = mesh_of(d, i);
+    // the cell's tables go out first (coalesced), then the gathers they
+    // address; the neighbour's face value only on lanes where it is the
+    // upwind side (the gathers' address work is what bounds this kernel)
+    int nb[4], vid[4];
+    double w[4], r[4], uo[4], po[4];
+    const uint32_t sl = d.fvc_slot[i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        nb[k] = d.c2n[k * nc + i];
+        vid[k] = d.fvc_vid[k * nc + i];
+        w[k] = d.fvc_w[k * nc + i];
+        r[k] = d.fvc_r[k * nc + i];
+        uo[k] = d.uf[k * nc + i];
+        po[k] = d.fvc_phi[k * nc + i];                 // outward
+    }
+    const double ui = uin[i], base = d.u[i], vol = d.vol[i], src = d.src[i];
+    const double D = d.mesh_D[m], a_dt = alpha * d.mesh_dt[m];
+    double un[4], ux[4], uv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        un[k] = uin[nb[k]];                            // a ghost's value behind a boundary face
+        uv[k] = d.unode[vid[k]];
+        ux[k] = 0.0;
+        if (nb[k] < nc && po[k] < 0.0) ux[k] = d.uf[int64_t((sl >> (2 * k)) & 3u) * nc + nb[k]];
+    }
+    double dif = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dif += w[k] * uv[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dif += r[k] * (un[k] - ui);
+    double conv = 0.0;
+    bool bnd = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool in = nb[k] < nc;
+        bnd = bnd || !in;
+        conv += in ? po[k] * (po[k] >= 0.0 ? uo[k] : ux[k]) : 0.0;
+    }
+    double acc = conv - D * dif;
+    if (bnd) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (nb[k] < nc) continue;
+            const int64_t g = nb[k] - nc;              // the cell is the L side of its boundary faces
+            const int64_t f = d.nfi + g;
+            const int kind = bc.kind[d.gtag[g]];
+            if (kind == kZeroFlux) continue;
+            // upwind: the cell's MUSCL value, or the ghost's value (first order)
+            const double uup = po[k] >= 0.0 ? uo[k] : un[k];
+            double diff;
+            if (kind == kNeumann) {
+                diff = bc.val[g] * d.area[f];
+            } else {
+                const double uA = d.unode[d.fA[f]], uB = d.unode[d.fB[f]], uC = d.unode[d.fC[f]];
+                diff = d.kAC[f] * (uA - uC) + d.kBC[f] * (uB - uC) + d.kRL[f] * (un[k] - ui);
+            }
+            acc += uup * po[k] - D * diff;
+        }
+    }
+    const double unew = base + a_dt * (-acc / vol + src);
+    uout[i] = unew;
+    if (bnd) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (nb[k] < nc) continue;
+            const int64_t g = nb[k] - nc;
+            const int kind = bc.kind[d.gtag[g]];
+            const double val = bc.val[g];
+            double ug;
+            if (kind == kDirichlet) ug = 2.0 * val - unew;
+            else if (kind == kNeumann) ug = unew + val * d.gdist[g];
+            else ug = unew;
+            uout[nc + g] = ug;
+        }
+    }
+}
+
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_residual_out(Dev d, FvArrays<R> a, double* res) {
     const int64_t i = gtid();
@@ -494,6 +638,18 @@ __global__ __launch_bounds__(kBlock) void k_face_phi(Dev d) {
     const double ph = vx * d.S[f] + vy * d.S[nf + f] + vz * d.S[2 * nf + f];
     d.phi[f] = ph;
     d.phi32[f] = float(ph);
+}
+
+// the FP64 cell step's copy of phi: per cell and face, outward from the cell
+__global__ __launch_bounds__(kBlock) void k_cell_phi(Dev d) {
+    const int64_t i = gtid();
+    if (i >= d.nc) return;
+    const int64_t nc = d.nc;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int code = d.c2f[k * nc + i];
+        d.fvc_phi[k * nc + i] = code >= 0 ? d.phi[code] : -d.phi[~code];
+    }
 }
 
 // FP32 copies of the static geometry the FP32 kernels read
@@ -653,17 +809,19 @@ hipError_t setup_fv_kernels(const Dev& d) {
     return e;
 }
 
-hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool parts) {
+hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool parts, const double* u_in) {
     const dim3 b(d.tile_rows);
     // grid padded to a multiple of 8 for the XCD-contiguous tile order
     const dim3 gx(unsigned((d.ntiles + kXcds - 1) / kXcds * kXcds));
     if (fp32) {
         hipLaunchKernelGGL((k_grad_moments<float, true>), gx, b, moments_lds_bytes<float>(d), s, d, fv32(d));
     } else {
+        FvArrays<double> a = fv64(d);
+        if (u_in) a.u = const_cast<double*>(u_in);       // read only
         if (parts)
-            hipLaunchKernelGGL((k_grad_moments<double, true>), gx, b, moments_lds_bytes<double>(d), s, d, fv64(d));
+            hipLaunchKernelGGL((k_grad_moments<double, true>), gx, b, moments_lds_bytes<double>(d), s, d, a);
         else
-            hipLaunchKernelGGL((k_grad_moments<double, false>), gx, b, moments_lds_bytes<double>(d), s, d, fv64(d));
+            hipLaunchKernelGGL((k_grad_moments<double, false>), gx, b, moments_lds_bytes<double>(d), s, d, a);
     }
     return hipGetLastError();
 }
@@ -685,6 +843,18 @@ hipError_t launch_update(const Dev& d, bool fp32, const BcTable& bc, double alph
     return hipGetLastError();
 }
 
+hipError_t launch_cell_step(const Dev& d, const BcTable& bc, const double* u_in, double* u_out, double alpha,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_step, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, bc, u_in, u_out, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_fv_cell_setup(const Dev& d, hipStream_t s) {
+    if (d.nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fv_cell_setup, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_dt(const Dev& d, double dt, double cfl, hipStream_t s) {
     hipLaunchKernelGGL(k_set_dt, dim3((d.nm + 255) / 256), dim3(256), 0, s, d, dt, cfl);
     return hipGetLastError();
@@ -700,6 +870,9 @@ hipError_t launch_residual_out(const Dev& d, bool fp32, double* res, hipStream_t
 
 hipError_t launch_face_phi(const Dev& d, hipStream_t s) {
     hipLaunchKernelGGL(k_face_phi, dim3(grid_for(d.nf)), dim3(kBlock), 0, s, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || d.nc == 0) return e;
+    hipLaunchKernelGGL(k_cell_phi, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d);
     return hipGetLastError();
 }
 

@@ -80,8 +80,18 @@ struct Dev {
     // fields
     double *u, *un, *src, *vel, *phi;     // u: nc+nb (ghosts behind), vel 3 x nc
     double *grad, *psi, *unode, *flux;    // grad 3 x nc
-    double4* rec;                         // nc: (psi g, u) per cell, the upwind data the FP64
-                                          // face fluxes read
+    // FP64 step (per cell): the MUSCL value at each of the cell's four face
+    // centroids [4][nc] (gradient kernel -> cell step); the two stage buffers
+    // of u (nc+nb each: a stage reads one and writes the other, u^n stays in u)
+    double *uf, *u_b, *u_c;
+    // per-cell tables of the FP64 step (geometry only): the cell's 4 vertex
+    // ids, their diffusion weights and the kRL weights over its interior
+    // faces ([4][nc] each), and per face k the slot of the same face among
+    // the neighbour's faces (2 bits per face)
+    int32_t* fvc_vid;
+    double *fvc_w, *fvc_r;
+    uint8_t* fvc_slot;
+    double* fvc_phi;                      // [4][nc] outward phi of the cell's faces (with phi)
     // solver vectors (P lives in x)
     double *x, *r, *z, *p, *q, *b;
     // reduced-precision (FP32) form of the step
@@ -107,7 +117,7 @@ struct FvArrays {
     const R *phi, *minv, *kAC, *kBC, *kRL, *area, *vol, *src, *n_alpha, *fx, *xc, *gdist;
 };
 
-constexpr int kNumKernels = 21;
+constexpr int kNumKernels = 22;
 
 struct NnDev;
 struct NnStateDev;
@@ -185,14 +195,22 @@ size_t layout(const Mesh& m, char* base, Dev& d);
 
 // launchers (fv_kernels.hip)
 hipError_t launch_ghost_fill(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
-// parts: also write the gradient and limiter arrays (FP64 writes the packed
-// upwind records always; FP32 writes the arrays always)
-hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool parts = false);
+// parts: write the gradient and limiter arrays (the face kernel reads
+// them); FP64 without parts writes the per-face MUSCL values of the cell step
+// instead, from u_in (d.u if null).  FP32 always writes the arrays.
+hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool parts = false,
+                               const double* u_in = nullptr);
 // once per state: kernel attributes (LDS above 64 KB for large tile halos)
 hipError_t setup_fv_kernels(const Dev& d);
 hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
 // the RK stage update; it also sets the ghosts behind the updated cells
 hipError_t launch_update(const Dev& d, bool fp32, const BcTable& bc, double alpha, bool first_stage, hipStream_t s);
+// FP64 RK stage in one pass per cell (face fluxes and update):
+// u_out = u + alpha dt Res(u_in), with the ghosts behind the cells
+hipError_t launch_cell_step(const Dev& d, const BcTable& bc, const double* u_in, double* u_out, double alpha,
+                            hipStream_t s);
+// once per state: the cell step's tables
+hipError_t launch_fv_cell_setup(const Dev& d, hipStream_t s);
 // the matrix-free per-cell tables (mf_kernels.hip)
 hipError_t launch_mf_cell_setup(const Dev& d, const BcTable& bc_pot, hipStream_t s);
 hipError_t launch_set_dt(const Dev& d, double dt, double cfl, hipStream_t s);
