@@ -142,9 +142,9 @@ def algorithmic_bytes(info):
         # gathered once, ghost owner + tag, vertex values written
         "mf_vertex": info.node_entries * 12 + nc * 8 + nb * 8 + nv * 8,
         # the per-cell product: per cell 4 vertex ids 16, 4 vertex weights 32,
-        # 4 face neighbours 16, 4 neighbour weights 32, diagonal term 8, p 8
-        # (neighbours' p counted once), q written 8; vertex values gathered once
-        "mf_gather": nc * 120 + nv * 8,
+        # 4 face neighbours 16, 4 face weights 32, p 8 (neighbours' p counted
+        # once), q written 8; vertex values gathered once
+        "mf_gather": nc * 112 + nv * 8,
     }
 
 

@@ -152,10 +152,8 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.mfc_vid = carve<int32_t>(base, off, 4 * nc);
     d.mfc_w = carve<double>(base, off, 4 * nc);
     d.mfc_r = carve<double>(base, off, 4 * nc);
-    d.mfc_d = carve<double>(base, off, nc);
     d.mfc_w32 = carve<float>(base, off, 4 * nc);
     d.mfc_r32 = carve<float>(base, off, 4 * nc);
-    d.mfc_d32 = carve<float>(base, off, nc);
     // per-block partials of up to 4 sums x 2 mesh slots, for blocks of >= 64 rows
     const int64_t nblk = (nc + 63) / 64;
     d.partial = carve<double>(base, off, 8 * (nblk + 1024));

@@ -1,9 +1,10 @@
 // Row i of the matrix-free Poisson operator from the per-cell tables that
 // k_mf_cell_setup (mf_kernels.hip) builds:
-//     (K x)_i = -(sum_k w_k x_v[vid_k] + sum_k r_k x[n_k] - dg_i x_i)
+//     (K x)_i = -(sum_k w_k x_v[vid_k] + sum_k r_k t_k)
 // over the cell's 4 vertices (vertex values x_v of the current x) and its 4
-// face neighbours n_k (c2n; a boundary face has r_k = 0).  Shared by the
-// per-launch product and the persistent batch solver.
+// faces: t_k = x[n_k] - x_i across an interior face (n_k from c2n), t_k = x_i
+// on a boundary face (r_k = -2 kRL on a Dirichlet face, 0 on the others).
+// Shared by the per-launch product and the persistent batch solver.
 #pragma once
 #include "state.h"
 
@@ -13,17 +14,14 @@ template <class R> struct MfCell;
 template <> struct MfCell<double> {
     __device__ static const double* w(const Dev& d) { return d.mfc_w; }
     __device__ static const double* r(const Dev& d) { return d.mfc_r; }
-    __device__ static const double* dg(const Dev& d) { return d.mfc_d; }
 };
 template <> struct MfCell<float> {
     __device__ static const float* w(const Dev& d) { return d.mfc_w32; }
     __device__ static const float* r(const Dev& d) { return d.mfc_r32; }
-    __device__ static const float* dg(const Dev& d) { return d.mfc_d32; }
 };
 
 // (K x)_i from the tables: the row's table loads go out together, then its
-// 4 vertex values and 4 neighbour values (a boundary face reads x_i, with
-// r = 0)
+// 4 vertex values and 4 neighbour values (a boundary face reads x_i)
 template <class R>
 __device__ inline R cell_row(const Dev& d, const R* __restrict__ x, const R* __restrict__ xv, int64_t i) {
     const int64_t nc = d.nc;
@@ -38,18 +36,18 @@ __device__ inline R cell_row(const Dev& d, const R* __restrict__ x, const R* __r
         w[k] = W[k * nc + i];
         r[k] = Rk[k * nc + i];
     }
-    const R dg = MfCell<R>::dg(d)[i], xi = x[i];
+    const R xi = x[i];
     R xvv[4], xn[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         xvv[k] = xv[vid[k]];
         xn[k] = x[nb[k] < nc ? nb[k] : i];
     }
-    R acc = -dg * xi;
+    R acc = R(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc += w[k] * xvv[k];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc += r[k] * xn[k];
+    for (int k = 0; k < 4; ++k) acc += r[k] * (nb[k] < nc ? xn[k] - xi : xn[k]);
     return -acc;
 }
 

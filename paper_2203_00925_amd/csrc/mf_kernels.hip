@@ -103,18 +103,18 @@ __global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict
 // on an interior face (n the cell across it) and -2 kRL x_i on a Dirichlet
 // face (its ghost is -x_i in the homogeneous part).  Faces of other kinds are
 // not part of K.  So
-//     (K x)_i = -(sum_k w_k x_v[vid_k] + sum_k r_k x[n_k] - dg x_i)
-// with r_k = kRL on interior faces (0 else) and dg = sum of kRL over the
-// interior faces + 2 kRL over the Dirichlet ones.  Built once per potential
-// boundary-kind set; in the product a cell streams 4 vertex ids and 12
-// coefficients instead of its faces' indices and coefficients, and no face
-// flux goes through memory.
+//     (K x)_i = -(sum_k w_k x_v[vid_k] + sum_k r_k t_k)
+// with r_k = kRL and t_k = x[n_k] - x_i on interior faces, r_k = -2 kRL and
+// t_k = x_i on Dirichlet faces (r_k = 0 on the others).  Built once per
+// potential boundary-kind set; in the product a cell streams 4 vertex ids,
+// 4 face neighbours and 8 coefficients instead of its faces' indices and
+// coefficients, and no face flux goes through memory.
 __global__ __launch_bounds__(kBlock) void k_mf_cell_setup(Dev d, BcTable bc) {
     const int64_t i = gtid_m();
     if (i >= d.nc) return;
     const int64_t nc = d.nc;
     int vid[4] = {-1, -1, -1, -1};
-    double w[4] = {0.0, 0.0, 0.0, 0.0}, r[4] = {0.0, 0.0, 0.0, 0.0}, dg = 0.0;
+    double w[4] = {0.0, 0.0, 0.0, 0.0}, r[4] = {0.0, 0.0, 0.0, 0.0};
     auto add = [&](int v, double c) {                 // the vertex's slot (first seen, first slot)
         bool done = false;
 #pragma unroll
@@ -138,12 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_cell_setup(Dev d, BcTable bc) {
         add(d.fA[f], sg * kac);
         add(d.fB[f], sg * kbc);
         add(d.fC[f], sg * (-(kac + kbc)));
-        if (bnd) {
-            dg += 2.0 * krl;
-        } else {
-            r[k] = krl;
-            dg += krl;
-        }
+        r[k] = bnd ? -2.0 * krl : krl;
     }
     // unused slots (a cell none of whose faces is in K) point at a used
     // vertex, or vertex 0, with weight 0
@@ -156,8 +151,6 @@ __global__ __launch_bounds__(kBlock) void k_mf_cell_setup(Dev d, BcTable bc) {
         d.mfc_w32[q * nc + i] = float(w[q]);
         d.mfc_r32[q * nc + i] = float(r[q]);
     }
-    d.mfc_d[i] = dg;
-    d.mfc_d32[i] = float(dg);
 }
 
 __global__ __launch_bounds__(kBlock) void k_mf_cell(Dev d, const double* __restrict__ x,

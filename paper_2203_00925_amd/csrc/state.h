@@ -101,11 +101,12 @@ struct Dev {
     double *np_ion, *efield;              // coupled loop: ion density [nc], E [3][nc]
     double *mf_xv, *mf_xg;                // matrix-free operator: vertex values [nv], ghost values [nb]
     // matrix-free operator per cell i (from the faces and the potential's
-    // boundary kinds): (K x)_i = -(sum_k w[k] x_v[vid[k]] + sum_k r[k] x[c2n[k]] - dg x_i)
-    // over the cell's 4 vertices and 4 faces ([4][nc] each; FP32 copies)
+    // boundary kinds): (K x)_i = -(sum_k w[k] x_v[vid[k]] + sum_k r[k] t_k) over
+    // the cell's 4 vertices and 4 faces, t_k = x[c2n[k]] - x_i across an
+    // interior face and x_i on a boundary face ([4][nc] each; FP32 copies)
     int32_t* mfc_vid;
-    double *mfc_w, *mfc_r, *mfc_d;
-    float *mfc_w32, *mfc_r32, *mfc_d32;
+    double *mfc_w, *mfc_r;
+    float *mfc_w32, *mfc_r32;
     double* partial;                      // reduction partials ([k][block], k < 4)
     double* scal;                         // solver scalars, [nm][SC_COUNT_]
 };
