@@ -165,8 +165,9 @@ __global__ __launch_bounds__(kBlock) void k_amg_open(Dev d, const double* __rest
 __global__ __launch_bounds__(1024) void k_amg_open_fin(Dev d, int64_t nparts, double tol, int maxit, int restart,
                                                        int fresh) {
     __shared__ double lds[16];
-    const double rr = seg_sum(d, 0, 0, nparts, kBlock, lds);
-    const double bb = seg_sum(d, 1, 0, nparts, kBlock, lds);
+    double t[2];
+    seg_sums<2>(d, 0, 0, nparts, kBlock, lds, t);
+    const double rr = t[0], bb = t[1];
     if (threadIdx.x == 0) {
         double* sc = d.scal;
         sc[SC_RR] = rr;
@@ -260,8 +261,9 @@ __global__ __launch_bounds__(1024) void k_amg_beta_fin(Dev d, int64_t nparts) {
     __shared__ double lds[16];
     double* sc = d.scal;
     if (sc[SC_DONE] != 0.0) return;
-    const double zr = seg_sum(d, 0, 0, nparts, kBlock, lds);
-    const double zro = seg_sum(d, 1, 0, nparts, kBlock, lds);
+    double t[2];
+    seg_sums<2>(d, 0, 0, nparts, kBlock, lds, t);
+    const double zr = t[0], zro = t[1];
     if (threadIdx.x == 0) {
         sc[SC_BETA] = (zr - zro) / sc[SC_RZ];
         sc[SC_RZ] = zr;

@@ -30,8 +30,9 @@ __global__ __launch_bounds__(1024) void k_cg_beta(Dev d, int64_t nparts, int64_t
     const int m = blockIdx.x;
     double* sc = msc(d, m);
     if (sc[SC_DONE] != 0.0) return;
-    const double trz = seg_sum(d, 0, m, nparts, rows_per_block, lds);
-    const double trr = seg_sum(d, 1, m, nparts, rows_per_block, lds);
+    double t[2];
+    seg_sums<2>(d, 0, m, nparts, rows_per_block, lds, t);
+    const double trz = t[0], trr = t[1];
     if (threadIdx.x == 0) {
         sc[SC_BETA] = trz / sc[SC_RZ];
         sc[SC_RZ] = trz;

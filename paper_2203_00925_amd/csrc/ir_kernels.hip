@@ -72,10 +72,9 @@ __global__ __launch_bounds__(1024) void k_ir_residual_fin(Dev d, int64_t nparts,
                                                           int maxit, int restart, int fresh) {
     __shared__ double lds[16];
     const int m = blockIdx.x;
-    const double trr = seg_sum(d, 0, m, nparts, kBlock, lds);
-    const double trz = seg_sum(d, 1, m, nparts, kBlock, lds);
-    const double trr32 = seg_sum(d, 2, m, nparts, kBlock, lds);
-    const double tbb = seg_sum(d, 3, m, nparts, kBlock, lds);
+    double t[4];
+    seg_sums<4>(d, 0, m, nparts, kBlock, lds, t);
+    const double trr = t[0], trz = t[1], trr32 = t[2], tbb = t[3];
     if (threadIdx.x == 0) {
         double* sc = msc(d, m);
         sc[SC_TRUE_RR] = trr;

@@ -83,24 +83,45 @@ __device__ inline void seg_publish_at(const Dev& d, const BlockSeg& g, const dou
 }
 
 // In the finalize kernel (one 1024-thread block per mesh, blockIdx.x = m):
-// the sum of partial k of mesh m, produced by a kernel of nblk blocks of B
-// rows, added in block order.
-__device__ inline double seg_sum(const Dev& d, int k, int m, int64_t nblk, int64_t B, double* lds) {
+// the sums of partials k0 .. k0+K-1 of mesh m, produced by a kernel of nblk
+// blocks of B rows, each added in block order, in one pass over the
+// partials (a thread keeps 16 loads in flight: the finalize is a chain of
+// load latencies).  Thread t adds the blocks t, t + 1024, ... in increasing
+// order, whatever the batch width, so the sums do not depend on it.
+template <int K>
+__device__ inline void seg_sums(const Dev& d, int k0, int m, int64_t nblk, int64_t B, double* lds,
+                                double (&out)[K]) {
+    constexpr int J = K == 1 ? 16 : 8;
     const int64_t lo = d.mesh_start[m], hi = d.mesh_start[m + 1];
     const int64_t first = lo / B, last = (hi - 1) / B;
-    double s = 0.0;
-    for (int64_t b0 = first + threadIdx.x; b0 <= last; b0 += 8 * 1024) {
-        double v[8];
+    double s[K];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+    for (int q = 0; q < K; ++q) s[q] = 0.0;
+    for (int64_t b0 = first + threadIdx.x; b0 <= last; b0 += J * 1024) {
+        double v[K][J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
             const int64_t b = b0 + int64_t(j) * 1024;
+            const bool in = b <= last;
+            const int64_t bb = in ? b : first;
             // a block that starts before the mesh holds it in its second slot
-            v[j] = b <= last ? d.partial[(2 * k + (b * B >= lo ? 0 : 1)) * nblk + b] : 0.0;
+            const int side = bb * B >= lo ? 0 : 1;
+#pragma unroll
+            for (int q = 0; q < K; ++q) v[q][j] = in ? d.partial[(2 * (k0 + q) + side) * nblk + bb] : 0.0;
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) s += v[j];
+        for (int q = 0; q < K; ++q)
+#pragma unroll
+            for (int j = 0; j < J; ++j) s[q] += v[q][j];
     }
-    return block_sum1024(s, lds);
+#pragma unroll
+    for (int q = 0; q < K; ++q) out[q] = block_sum1024(s[q], lds);
+}
+
+__device__ inline double seg_sum(const Dev& d, int k, int m, int64_t nblk, int64_t B, double* lds) {
+    double s[1];
+    seg_sums<1>(d, k, m, nblk, B, lds, s);
+    return s[0];
 }
 
 }  // namespace mifvm
