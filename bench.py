@@ -39,10 +39,12 @@ METRIC = "FV cell-updates/s + Poisson solve ms @1e-10 rel; plain vs mixed/learne
 # it when that source (the kernel's file and the reduction headers) still
 # hashes to the recorded prefix, else null.
 MEASURED_TRAFFIC = {"cube120": {
-    "k_mf_vertex": {"src": "9aa783096e15adb7", "bytes": 624972083},
-    "k_cg_axpy": {"src": "2632548940b858f0", "bytes": 668815360},
-    "k_cg_dir": {"src": "2632548940b858f0", "bytes": 248862720},
-    "k_grad_moments": {"src": "5c7dbc8b429ce3a1", "bytes": 3721005056},
+    "k_mf_cg_cell": {"src": "d411d59405441bd8", "bytes": 1215546999},
+    "k_mf_vertex": {"src": "d411d59405441bd8", "bytes": 624963909},
+    "k_cg_axpy": {"src": "50d641f414878f07", "bytes": 668798361},
+    "k_cg_dir": {"src": "50d641f414878f07", "bytes": 248844609},
+    "k_grad_moments": {"src": "0c3663800744f32c", "bytes": 3720615232},
+    "k_cell_step": {"src": "0c3663800744f32c", "bytes": 2158338440},
 }}
 # timing id -> the FP64 kernel it times
 KERNEL_NAMES = {"grad_limiter": "k_grad_moments", "mf_gather": "k_mf_cg_cell", "fv_cell": "k_cell_step"}
