@@ -103,10 +103,12 @@ __device__ void run_item(const Dev& d, const BatchDev& b, const BatchRange& r, u
         case BP_OV:
         case BP_V: {
             const double* src = ph == BP_OV ? d.x : d.p;
+#pragma unroll 1
             for (int64_t k = lo + tid; k < hi; k += kBatchBlock) d.mf_xv[r.v0 + k] = vertex_value<VB>(d, b, src, r.v0 + k);
             break;
         }
         case BP_OG:
+#pragma unroll 1
             for (int64_t k = lo + tid; k < hi; k += kBatchBlock) {
                 const int64_t i = r.c0 + k;
                 const double bi = d.b[i];
@@ -121,6 +123,7 @@ __device__ void run_item(const Dev& d, const BatchDev& b, const BatchRange& r, u
             }
             break;
         case BP_G:
+#pragma unroll 1
             for (int64_t k = lo + tid; k < hi; k += kBatchBlock) {
                 const int64_t i = r.c0 + k;
                 const double y = cell_row(d, d.p, d.mf_xv, i);
@@ -130,6 +133,7 @@ __device__ void run_item(const Dev& d, const BatchDev& b, const BatchRange& r, u
             break;
         case BP_AX: {
             const double alpha = sc[SC_ALPHA];
+#pragma unroll 1
             for (int64_t k = lo + tid; k < hi; k += kBatchBlock) {
                 const int64_t i = r.c0 + k;
                 d.x[i] += alpha * d.p[i];
@@ -144,6 +148,7 @@ __device__ void run_item(const Dev& d, const BatchDev& b, const BatchRange& r, u
         }
         case BP_DIR: {
             const double beta = sc[SC_BETA];
+#pragma unroll 1
             for (int64_t k = lo + tid; k < hi; k += kBatchBlock) {
                 const int64_t i = r.c0 + k;
                 d.p[i] = d.z[i] + beta * d.p[i];
@@ -151,6 +156,7 @@ __device__ void run_item(const Dev& d, const BatchDev& b, const BatchRange& r, u
             break;
         }
         case BP_ZX:
+#pragma unroll 1
             for (int64_t k = lo + tid; k < hi; k += kBatchBlock) d.x[r.c0 + k] = 0.0;
             break;
         default: break;
