@@ -624,7 +624,9 @@ int mifvm_conservation_static(mifvm_state* st, double* total_out, void* stream);
 enum mifvm_kernel {
     MIFVM_K_GHOST_FILL = 0, MIFVM_K_GRAD_LIMITER = 1 /* incl. vertex values */,
     MIFVM_K_NODE_INTERP = 2 /* reserved: computed inside GRAD_LIMITER, never launched */,
-    MIFVM_K_FACE_FLUX = 3, MIFVM_K_UPDATE = 4, MIFVM_K_CG_SETUP = 5, MIFVM_K_CG_SPMV = 6,
+    MIFVM_K_FACE_FLUX = 3 /* face fluxes of the residual evaluation */,
+    MIFVM_K_UPDATE = 4 /* reserved: the update is part of FV_CELL, never launched */,
+    MIFVM_K_CG_SETUP = 5, MIFVM_K_CG_SPMV = 6,
     MIFVM_K_CG_AXPY = 7, MIFVM_K_CG_DIR = 8, MIFVM_K_RHS = 9, MIFVM_K_ASSEMBLE = 10,
     MIFVM_K_NN_LAYER1 = 11, MIFVM_K_NN_LAYER2 = 12, MIFVM_K_NN_LAYER3 = 13 /* network layers
     (the first includes the encoder, the last the decoder) */,
@@ -637,8 +639,7 @@ enum mifvm_kernel {
     the cell's vertices and faces, with p.q (CG_SPMV counts the stored-matrix product) */,
     MIFVM_K_NN_FUSED = 19 /* the whole network in one launch (encoder, 3 layers, decoder) */,
     MIFVM_K_CG_ALPHA = 20 /* the matrix-free CG's alpha step (its p.q partials summed per mesh) */,
-    MIFVM_K_FV_CELL = 21 /* FP64 step: face fluxes and the RK stage update in one pass per cell
-    (FACE_FLUX and UPDATE then count the FP32 step and the residual evaluation) */,
+    MIFVM_K_FV_CELL = 21 /* the step: face fluxes and the RK stage update in one pass per cell */,
     MIFVM_K_COUNT = 22
 };
 int mifvm_kernel_timing(mifvm_state* st, int32_t enable);

@@ -104,7 +104,6 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.cell_perm = carve<int32_t>(base, off, nc);
     d.vert_perm = carve<int32_t>(base, off, nv);
     d.u = carve<double>(base, off, NX);
-    d.un = carve<double>(base, off, nc);
     d.src = carve<double>(base, off, nc);
     d.vel = carve<double>(base, off, 3 * nc);
     d.phi = carve<double>(base, off, nf);
@@ -118,6 +117,12 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.fvc_r = carve<double>(base, off, 4 * nc);
     d.fvc_slot = carve<uint8_t>(base, off, nc);
     d.fvc_phi = carve<double>(base, off, 4 * nc);
+    d.uf32 = carve<float>(base, off, 4 * nc);
+    d.u_b32 = carve<float>(base, off, NX);
+    d.u_c32 = carve<float>(base, off, NX);
+    d.fvc_w32 = carve<float>(base, off, 4 * nc);
+    d.fvc_r32 = carve<float>(base, off, 4 * nc);
+    d.fvc_phi32 = carve<float>(base, off, 4 * nc);
     d.unode = carve<double>(base, off, nv);
     d.flux = carve<double>(base, off, nf);
     d.x = carve<double>(base, off, nc);
@@ -127,7 +132,6 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.q = carve<double>(base, off, nc);
     d.b = carve<double>(base, off, nc);
     d.u32 = carve<float>(base, off, NX);
-    d.un32 = carve<float>(base, off, nc);
     d.src32 = carve<float>(base, off, nc);
     d.phi32 = carve<float>(base, off, nf);
     d.grad32 = carve<float>(base, off, 3 * nc);
@@ -390,6 +394,7 @@ int mifvm_state_create(const mifvm_mesh* mesh, const mifvm_params* params, void*
     if (e == hipSuccess) e = hipMemsetAsync(d.vel, 0, 3 * m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.phi, 0, m.nf * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.fvc_phi, 0, 4 * m.nc * sizeof(double), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.fvc_phi32, 0, 4 * m.nc * sizeof(float), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.x, 0, m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.np_ion, 0, m.nc * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(d.efield, 0, 3 * m.nc * sizeof(double), s);
@@ -601,12 +606,17 @@ int residual_parts(State& s, hipStream_t hs, bool ghosts = true) {
     return MIFVM_OK;
 }
 
-// the FP64 step's buffers of RK stage k: every stage adds to u^n (kept in
-// u), so stage 0 reads u and writes u_b, stage 1 reads u_b and writes u_c,
-// stage 2 reads u_c and writes u (cell i alone reads u[i] there)
-void stage_buffers(const Dev& d, int k, const double** uin, double** uout) {
-    *uin = k == 0 ? d.u : (k == 1 ? d.u_b : d.u_c);
-    *uout = k == 0 ? d.u_b : (k == 1 ? d.u_c : d.u);
+// the step's buffers of RK stage k: every stage adds to u^n (kept in u), so
+// stage 0 reads u and writes u_b, stage 1 reads u_b and writes u_c, stage 2
+// reads u_c and writes u (cell i alone reads u[i] there)
+void stage_buffers(const Dev& d, bool fp32, int k, const void** uin, void** uout) {
+    if (fp32) {
+        *uin = k == 0 ? d.u32 : (k == 1 ? d.u_b32 : d.u_c32);
+        *uout = k == 0 ? d.u_b32 : (k == 1 ? d.u_c32 : d.u32);
+    } else {
+        *uin = k == 0 ? d.u : (k == 1 ? d.u_b : d.u_c);
+        *uout = k == 0 ? d.u_b : (k == 1 ? d.u_c : d.u);
+    }
 }
 }  // namespace
 
@@ -624,20 +634,15 @@ int mifvm_step(mifvm_state* st, int32_t n_steps, double dt, void* stream) {
     for (int n = 0; n < n_steps; ++n)
         for (int k = 0; k < 3; ++k) {
             const bool fill = n == 0 && k == 0;
-            if (s.fp32) {
-                int rc = residual_parts(s, hs, fill);
-                if (rc) return rc;
-                HIPCHK(timed(t, MIFVM_K_UPDATE, hs,
-                             [&] { return launch_update(d, true, s.bc[0], alpha[k], k == 0, hs); }));
-                continue;
-            }
-            const double* uin;
-            double* uout;
-            stage_buffers(d, k, &uin, &uout);
+            const void* uin;
+            void* uout;
+            stage_buffers(d, s.fp32, k, &uin, &uout);
             if (fill)
-                HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, false, s.bc[0], hs); }));
-            HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs, [&] { return launch_grad_limiter(d, false, hs, false, uin); }));
-            HIPCHK(timed(t, MIFVM_K_FV_CELL, hs, [&] { return launch_cell_step(d, s.bc[0], uin, uout, alpha[k], hs); }));
+                HIPCHK(timed(t, MIFVM_K_GHOST_FILL, hs, [&] { return launch_ghost_fill(d, s.fp32, s.bc[0], hs); }));
+            HIPCHK(timed(t, MIFVM_K_GRAD_LIMITER, hs,
+                         [&] { return launch_grad_limiter(d, s.fp32, hs, false, uin); }));
+            HIPCHK(timed(t, MIFVM_K_FV_CELL, hs,
+                         [&] { return launch_cell_step(d, s.fp32, s.bc[0], uin, uout, alpha[k], hs); }));
         }
     return MIFVM_OK;
 }
@@ -653,17 +658,11 @@ hipError_t enqueue_steps(const State& s, int n, double dt, hipStream_t q) {
     // the ghosts are filled once; every update then sets those of its cells
     if (e == hipSuccess && n > 0) e = launch_ghost_fill(d, s.fp32, s.bc[0], q);
     for (int k = 0; e == hipSuccess && k < 3 * n; ++k) {
-        if (s.fp32) {
-            e = launch_grad_limiter(d, true, q);
-            if (e == hipSuccess) e = launch_face_flux(d, true, s.bc[0], q);
-            if (e == hipSuccess) e = launch_update(d, true, s.bc[0], alpha[k % 3], k % 3 == 0, q);
-            continue;
-        }
-        const double* uin;
-        double* uout;
-        stage_buffers(d, k % 3, &uin, &uout);
-        e = launch_grad_limiter(d, false, q, false, uin);
-        if (e == hipSuccess) e = launch_cell_step(d, s.bc[0], uin, uout, alpha[k % 3], q);
+        const void* uin;
+        void* uout;
+        stage_buffers(d, s.fp32, k % 3, &uin, &uout);
+        e = launch_grad_limiter(d, s.fp32, q, false, uin);
+        if (e == hipSuccess) e = launch_cell_step(d, s.fp32, s.bc[0], uin, uout, alpha[k % 3], q);
     }
     return e;
 }

@@ -1,19 +1,22 @@
 // Kernels of the explicit finite-volume residual (eq. (4) of the paper) and
 // its Runge-Kutta update (eq. (6)), for CDNA4 wave64.
 //
-// One residual evaluation is three gather kernels, each owner-computes and
-// free of atomics:
+// A Runge-Kutta stage is two gather kernels, each owner-computes and free
+// of atomics:
 //   k_grad_moments  per tile of cells: least-squares gradient (Algorithm 1,
 //                   in star-moment form), then the Barth-Jespersen limiter
-//                   over the 4 face neighbours; the same kernel computes the
+//                   over the 4 face neighbours and the MUSCL values at the
+//                   cell's face centroids; the same kernel computes the
 //                   vertex values of the least-squares interpolation
 //                   (Algorithm 2);
-//   k_face_flux     per face: MUSCL upwind convective flux (eq. (15)) minus
-//                   the diamond diffusive flux (eq. (diamond)), written once;
-//   k_update        per cell: gathers its 4 face fluxes with their signs.
+//   k_cell_step     per cell: the upwind convective fluxes (eq. (15)) minus
+//                   the diamond diffusive fluxes (eq. (diamond)) of its four
+//                   faces, summed, and the stage update.
+// The residual evaluation that returns the face fluxes runs the face kernel
+// k_face_flux (one thread per face) after the gradient kernel instead.
 // Ghost values (behind boundary faces) are materialised by k_ghost_fill
-// before a run of steps and by k_update after every stage, so every gather
-// is a plain indexed load.
+// before a run of steps and by k_cell_step after every stage, so every
+// gather is a plain indexed load.
 //
 // Every kernel is instantiated for FP64 (the method as stated) and FP32 (the
 // reduced-precision form: state, gradients, fluxes and geometry copies in
@@ -360,15 +363,14 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
         else if (dl[k] < R(0)) ph = fmin(R(1), (umin - ui) / dl[k]);
         psi = fmin(psi, ph);
     }
-    // FP64 step: the MUSCL value u + psi g.(x_f - x_i) at each of the cell's
+    // The step: the MUSCL value u + psi g.(x_f - x_i) at each of the cell's
     // face centroids (in c2f order), which the cell step reads for both sides
-    // of a face.  With parts (and always in FP32): the gradient and limiter
-    // arrays, which the face kernel reads.
-    if constexpr (!rel && !PARTS) {
+    // of a face.  With parts: the gradient and limiter arrays, which the face
+    // kernel reads.
+    if constexpr (!PARTS) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) d.uf[k * nc + i] = ui + psi * dl[k];
-    }
-    if (PARTS || rel) {
+        for (int k = 0; k < 4; ++k) a.uf[k * nc + i] = ui + psi * dl[k];
+    } else {
         a.grad[i] = gx;
         a.grad[nc + i] = gy;
         a.grad[2 * nc + i] = gz;
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_moments(Dev d, FvArrays<R> a) {
     }
 }
 
-// One thread per face (the FP32 step and the residual evaluation; it reads
+// One thread per face (the residual evaluation; it reads
 // the gradient and limiter arrays).  Every load of the face goes out before
 // its first branch (boundary faces read a valid dummy where they need no
 // data); the arithmetic of each kind of face is unchanged by that.
@@ -412,53 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_face_flux(Dev d, FvArrays<R> a, BcTa
     a.flux[f] = kind == kZeroFlux ? R(0) : uup * ph - D * diff;
 }
 
-// u^(k) = u^n + a dt Res(u^(k-1)) with the cell's mesh's dt; the first stage
-// also saves u^n.  The cell then sets the ghosts behind its boundary faces
-// from its new value (as k_ghost_fill does; a ghost has one owner), so the
-// next stage reads current ghosts without a launch of its own.
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_update(Dev d, FvArrays<R> a, BcTable bc, double alpha, int first) {
-    const int64_t i = gtid();
-    if (i >= d.nc) return;
-    const R a_dt = R(alpha * d.mesh_dt[mesh_of(d, i)]);
-    const int64_t nc = d.nc;
-    R acc = R(0);
-    // the four flux loads go out together (no load under a branch)
-    int c[4];
-    R fl[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) c[k] = d.c2f[k * nc + i];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) fl[k] = a.flux[c[k] >= 0 ? c[k] : ~c[k]];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) acc += c[k] >= 0 ? fl[k] : -fl[k];
-    const R res = -acc / a.vol[i] + a.src[i];
-    R base;
-    if (first) {
-        base = a.u[i];
-        a.un[i] = base;
-    } else {
-        base = a.un[i];
-    }
-    const R unew = base + a_dt * res;
-    a.u[i] = unew;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int f = c[k] >= 0 ? c[k] : ~c[k];
-        if (f >= d.nfi) {                     // boundary face: ghost g behind it
-            const int64_t g = f - d.nfi;
-            const int kind = bc.kind[d.gtag[g]];
-            const R val = bc_value<R>(bc, g);
-            R ug;
-            if (kind == kDirichlet) ug = R(2) * val - unew;
-            else if (kind == kNeumann) ug = unew + val * a.gdist[g];
-            else ug = unew;
-            a.u[d.nc + g] = ug;
-        }
-    }
-}
-
-// ---- the FP64 step: face fluxes and update in one pass per cell -------------
+// ---- the step: face fluxes and update in one pass per cell ------------------
 // The residual of cell i is -(1/vol_i) sum_k s_k F_k + src_i over its four
 // faces, s_k = +1 where the cell is the face's L side.  On the interior
 // faces the diffusive parts are regrouped per cell as in the matrix-free
@@ -520,6 +476,8 @@ __global__ __launch_bounds__(kBlock) void k_fv_cell_setup(Dev d) {
         d.fvc_vid[q * nc + i] = vid[q] >= 0 ? vid[q] : vid[0];
         d.fvc_w[q * nc + i] = w[q];
         d.fvc_r[q * nc + i] = r[q];
+        d.fvc_w32[q * nc + i] = float(w[q]);
+        d.fvc_r32[q * nc + i] = float(r[q]);
     }
     d.fvc_slot[i] = uint8_t(slots);
 }
@@ -527,9 +485,10 @@ __global__ __launch_bounds__(kBlock) void k_fv_cell_setup(Dev d) {
 // u_out[i] = u[i] + alpha dt Res(u_in)_i (u holds u^n; u_in and u_out are
 // other buffers, or u_out = u on the last stage, whose cell i alone reads
 // u[i]); then the ghosts behind the cell's boundary faces, from the new value
-__global__ __launch_bounds__(kBlock) void k_cell_step(Dev d, BcTable bc, const double* __restrict__ uin,
-                                                      double* uout, double alpha) {
-    const int64_t i = gtid_m();                        // XCD-contiguous: neighbours' data in one L2
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_cell_step(Dev d, FvArrays<R> a, BcTable bc, const R* __restrict__ uin,
+                                                      R* uout, double alpha) {
+    const int64_t i = gtid_m();                        // XCD-contiguous block order
     if (i >= d.nc) return;
     const int64_t nc = d.nc;
     const int m = mesh_of(d, i);
@@ -537,41 +496,41 @@ __global__ __launch_bounds__(kBlock) void k_cell_step(Dev d, BcTable bc, const d
     // address; the neighbour's face value only on lanes where it is the
     // upwind side (the gathers' address work is what bounds this kernel)
     int nb[4], vid[4];
-    double w[4], r[4], uo[4], po[4];
+    R w[4], r[4], uo[4], po[4];
     const uint32_t sl = d.fvc_slot[i];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         nb[k] = d.c2n[k * nc + i];
         vid[k] = d.fvc_vid[k * nc + i];
-        w[k] = d.fvc_w[k * nc + i];
-        r[k] = d.fvc_r[k * nc + i];
-        uo[k] = d.uf[k * nc + i];
-        po[k] = d.fvc_phi[k * nc + i];                 // outward
+        w[k] = a.cw[k * nc + i];
+        r[k] = a.cr[k * nc + i];
+        uo[k] = a.uf[k * nc + i];
+        po[k] = a.cphi[k * nc + i];                    // outward
     }
-    const double ui = uin[i], base = d.u[i], vol = d.vol[i], src = d.src[i];
-    const double D = d.mesh_D[m], a_dt = alpha * d.mesh_dt[m];
-    double un[4], ux[4], uv[4];
+    const R ui = uin[i], base = a.u[i], vol = a.vol[i], src = a.src[i];
+    const R D = R(d.mesh_D[m]), a_dt = R(alpha * d.mesh_dt[m]);
+    R un[4], ux[4], uv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         un[k] = uin[nb[k]];                            // a ghost's value behind a boundary face
-        uv[k] = d.unode[vid[k]];
-        ux[k] = 0.0;
-        if (nb[k] < nc && po[k] < 0.0) ux[k] = d.uf[int64_t((sl >> (2 * k)) & 3u) * nc + nb[k]];
+        uv[k] = a.unode[vid[k]];
+        ux[k] = R(0);
+        if (nb[k] < nc && po[k] < R(0)) ux[k] = a.uf[int64_t((sl >> (2 * k)) & 3u) * nc + nb[k]];
     }
-    double dif = 0.0;
+    R dif = R(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) dif += w[k] * uv[k];
 #pragma unroll
     for (int k = 0; k < 4; ++k) dif += r[k] * (un[k] - ui);
-    double conv = 0.0;
+    R conv = R(0);
     bool bnd = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const bool in = nb[k] < nc;
         bnd = bnd || !in;
-        conv += in ? po[k] * (po[k] >= 0.0 ? uo[k] : ux[k]) : 0.0;
+        conv += in ? po[k] * (po[k] >= R(0) ? uo[k] : ux[k]) : R(0);
     }
-    double acc = conv - D * dif;
+    R acc = conv - D * dif;
     if (bnd) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -581,18 +540,18 @@ __global__ __launch_bounds__(kBlock) void k_cell_step(Dev d, BcTable bc, const d
             const int kind = bc.kind[d.gtag[g]];
             if (kind == kZeroFlux) continue;
             // upwind: the cell's MUSCL value, or the ghost's value (first order)
-            const double uup = po[k] >= 0.0 ? uo[k] : un[k];
-            double diff;
+            const R uup = po[k] >= R(0) ? uo[k] : un[k];
+            R diff;
             if (kind == kNeumann) {
-                diff = bc.val[g] * d.area[f];
+                diff = bc_value<R>(bc, g) * a.area[f];
             } else {
-                const double uA = d.unode[d.fA[f]], uB = d.unode[d.fB[f]], uC = d.unode[d.fC[f]];
-                diff = d.kAC[f] * (uA - uC) + d.kBC[f] * (uB - uC) + d.kRL[f] * (un[k] - ui);
+                const R uA = a.unode[d.fA[f]], uB = a.unode[d.fB[f]], uC = a.unode[d.fC[f]];
+                diff = a.kAC[f] * (uA - uC) + a.kBC[f] * (uB - uC) + a.kRL[f] * (un[k] - ui);
             }
             acc += uup * po[k] - D * diff;
         }
     }
-    const double unew = base + a_dt * (-acc / vol + src);
+    const R unew = base + a_dt * (-acc / vol + src);
     uout[i] = unew;
     if (bnd) {
 #pragma unroll
@@ -600,10 +559,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_step(Dev d, BcTable bc, const d
             if (nb[k] < nc) continue;
             const int64_t g = nb[k] - nc;
             const int kind = bc.kind[d.gtag[g]];
-            const double val = bc.val[g];
-            double ug;
-            if (kind == kDirichlet) ug = 2.0 * val - unew;
-            else if (kind == kNeumann) ug = unew + val * d.gdist[g];
+            const R val = bc_value<R>(bc, g);
+            R ug;
+            if (kind == kDirichlet) ug = R(2) * val - unew;
+            else if (kind == kNeumann) ug = unew + val * a.gdist[g];
             else ug = unew;
             uout[nc + g] = ug;
         }
@@ -648,7 +607,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_phi(Dev d) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int code = d.c2f[k * nc + i];
-        d.fvc_phi[k * nc + i] = code >= 0 ? d.phi[code] : -d.phi[~code];
+        const double po = code >= 0 ? d.phi[code] : -d.phi[~code];
+        d.fvc_phi[k * nc + i] = po;
+        d.fvc_phi32[k * nc + i] = float(po);
     }
 }
 
@@ -764,13 +725,14 @@ __global__ void k_set_dt(Dev d, double dt, double cfl) {
 
 // ---- launchers ---------------------------------------------------------------
 FvArrays<double> fv64(const Dev& d) {
-    return {d.u, d.un, d.grad, d.psi, d.unode, d.flux, d.phi, d.minv, d.kAC, d.kBC, d.kRL, d.area,
-            d.vol, d.src, d.n_alpha, d.fx, d.xc, d.gdist};
+    return {d.u, d.grad, d.psi, d.unode, d.flux, d.phi, d.minv, d.kAC, d.kBC, d.kRL, d.area,
+            d.vol, d.src, d.n_alpha, d.fx, d.xc, d.gdist, d.uf, d.fvc_w, d.fvc_r, d.fvc_phi};
 }
 
 FvArrays<float> fv32(const Dev& d) {
-    return {d.u32, d.un32, d.grad32, d.psi32, d.unode32, d.flux32, d.phi32, d.minv32, d.kAC32, d.kBC32,
-            d.kRL32, d.area32, d.vol32, d.src32, d.n_alpha32, d.fx32, d.xc32, d.gdist32};
+    return {d.u32, d.grad32, d.psi32, d.unode32, d.flux32, d.phi32, d.minv32, d.kAC32, d.kBC32,
+            d.kRL32, d.area32, d.vol32, d.src32, d.n_alpha32, d.fx32, d.xc32, d.gdist32,
+            d.uf32, d.fvc_w32, d.fvc_r32, d.fvc_phi32};
 }
 
 template <class R>
@@ -806,23 +768,25 @@ hipError_t setup_fv_kernels(const Dev& d) {
     hipError_t e = allow_lds<double, false>(d);
     if (e == hipSuccess) e = allow_lds<double, true>(d);
     if (e == hipSuccess) e = allow_lds<float, true>(d);
+    if (e == hipSuccess) e = allow_lds<float, false>(d);
     return e;
 }
 
-hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool parts, const double* u_in) {
+template <class R>
+void launch_grad_t(const Dev& d, FvArrays<R> a, bool parts, const void* u_in, hipStream_t s) {
     const dim3 b(d.tile_rows);
     // grid padded to a multiple of 8 for the XCD-contiguous tile order
     const dim3 gx(unsigned((d.ntiles + kXcds - 1) / kXcds * kXcds));
-    if (fp32) {
-        hipLaunchKernelGGL((k_grad_moments<float, true>), gx, b, moments_lds_bytes<float>(d), s, d, fv32(d));
-    } else {
-        FvArrays<double> a = fv64(d);
-        if (u_in) a.u = const_cast<double*>(u_in);       // read only
-        if (parts)
-            hipLaunchKernelGGL((k_grad_moments<double, true>), gx, b, moments_lds_bytes<double>(d), s, d, a);
-        else
-            hipLaunchKernelGGL((k_grad_moments<double, false>), gx, b, moments_lds_bytes<double>(d), s, d, a);
-    }
+    if (u_in) a.u = const_cast<R*>(static_cast<const R*>(u_in));   // read only
+    if (parts)
+        hipLaunchKernelGGL((k_grad_moments<R, true>), gx, b, moments_lds_bytes<R>(d), s, d, a);
+    else
+        hipLaunchKernelGGL((k_grad_moments<R, false>), gx, b, moments_lds_bytes<R>(d), s, d, a);
+}
+
+hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool parts, const void* u_in) {
+    if (fp32) launch_grad_t(d, fv32(d), parts, u_in, s);
+    else launch_grad_t(d, fv64(d), parts, u_in, s);
     return hipGetLastError();
 }
 hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s) {
@@ -833,19 +797,14 @@ hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_update(const Dev& d, bool fp32, const BcTable& bc, double alpha, bool first_stage, hipStream_t s) {
+hipError_t launch_cell_step(const Dev& d, bool fp32, const BcTable& bc, const void* u_in, void* u_out,
+                            double alpha, hipStream_t s) {
     if (fp32)
-        hipLaunchKernelGGL(k_update<float>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv32(d), bc, alpha,
-                           first_stage ? 1 : 0);
+        hipLaunchKernelGGL(k_cell_step<float>, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, fv32(d), bc,
+                           static_cast<const float*>(u_in), static_cast<float*>(u_out), alpha);
     else
-        hipLaunchKernelGGL(k_update<double>, dim3(grid_for(d.nc)), dim3(kBlock), 0, s, d, fv64(d), bc, alpha,
-                           first_stage ? 1 : 0);
-    return hipGetLastError();
-}
-
-hipError_t launch_cell_step(const Dev& d, const BcTable& bc, const double* u_in, double* u_out, double alpha,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_cell_step, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, bc, u_in, u_out, alpha);
+        hipLaunchKernelGGL(k_cell_step<double>, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, fv64(d), bc,
+                           static_cast<const double*>(u_in), static_cast<double*>(u_out), alpha);
     return hipGetLastError();
 }
 

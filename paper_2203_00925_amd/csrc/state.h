@@ -78,7 +78,7 @@ struct Dev {
     // renumbering
     int32_t *cell_perm, *vert_perm;       // internal -> user
     // fields
-    double *u, *un, *src, *vel, *phi;     // u: nc+nb (ghosts behind), vel 3 x nc
+    double *u, *src, *vel, *phi;     // u: nc+nb (ghosts behind), vel 3 x nc
     double *grad, *psi, *unode, *flux;    // grad 3 x nc
     // FP64 step (per cell): the MUSCL value at each of the cell's four face
     // centroids [4][nc] (gradient kernel -> cell step); the two stage buffers
@@ -92,10 +92,12 @@ struct Dev {
     double *fvc_w, *fvc_r;
     uint8_t* fvc_slot;
     double* fvc_phi;                      // [4][nc] outward phi of the cell's faces (with phi)
+    // the same for the FP32 step: face values, stage buffers, weights, phi
+    float *uf32, *u_b32, *u_c32, *fvc_w32, *fvc_r32, *fvc_phi32;
     // solver vectors (P lives in x)
     double *x, *r, *z, *p, *q, *b;
     // reduced-precision (FP32) form of the step
-    float *u32, *un32, *src32, *phi32, *grad32, *psi32, *unode32, *flux32;
+    float *u32, *src32, *phi32, *grad32, *psi32, *unode32, *flux32;
     float *minv32, *kAC32, *kBC32, *kRL32, *area32, *vol32, *n_alpha32, *fx32, *xc32, *gdist32;
     double* tmp;                          // nc+nb scratch (permutation, residual)
     double *np_ion, *efield;              // coupled loop: ion density [nc], E [3][nc]
@@ -114,8 +116,11 @@ struct Dev {
 // The arrays one precision of the step reads and writes.
 template <class R>
 struct FvArrays {
-    R *u, *un, *grad, *psi, *unode, *flux;
+    R *u, *grad, *psi, *unode, *flux;
     const R *phi, *minv, *kAC, *kBC, *kRL, *area, *vol, *src, *n_alpha, *fx, *xc, *gdist;
+    // the per-cell stage: face values [4][nc], vertex and kRL weights, outward phi
+    R* uf;
+    const R *cw, *cr, *cphi;
 };
 
 constexpr int kNumKernels = 22;
@@ -197,19 +202,18 @@ size_t layout(const Mesh& m, char* base, Dev& d);
 // launchers (fv_kernels.hip)
 hipError_t launch_ghost_fill(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
 // parts: write the gradient and limiter arrays (the face kernel reads
-// them); FP64 without parts writes the per-face MUSCL values of the cell step
-// instead, from u_in (d.u if null).  FP32 always writes the arrays.
+// them); without parts, the per-face MUSCL values of the cell step instead,
+// from u_in (the state's u in the step's precision if null)
 hipError_t launch_grad_limiter(const Dev& d, bool fp32, hipStream_t s, bool parts = false,
-                               const double* u_in = nullptr);
+                               const void* u_in = nullptr);
 // once per state: kernel attributes (LDS above 64 KB for large tile halos)
 hipError_t setup_fv_kernels(const Dev& d);
 hipError_t launch_face_flux(const Dev& d, bool fp32, const BcTable& bc, hipStream_t s);
-// the RK stage update; it also sets the ghosts behind the updated cells
-hipError_t launch_update(const Dev& d, bool fp32, const BcTable& bc, double alpha, bool first_stage, hipStream_t s);
-// FP64 RK stage in one pass per cell (face fluxes and update):
-// u_out = u + alpha dt Res(u_in), with the ghosts behind the cells
-hipError_t launch_cell_step(const Dev& d, const BcTable& bc, const double* u_in, double* u_out, double alpha,
-                            hipStream_t s);
+// RK stage in one pass per cell (face fluxes and update):
+// u_out = u + alpha dt Res(u_in), with the ghosts behind the cells (u, u_in
+// and u_out in the step's precision: double, or float with fp32)
+hipError_t launch_cell_step(const Dev& d, bool fp32, const BcTable& bc, const void* u_in, void* u_out,
+                            double alpha, hipStream_t s);
 // once per state: the cell step's tables
 hipError_t launch_fv_cell_setup(const Dev& d, hipStream_t s);
 // the matrix-free per-cell tables (mf_kernels.hip)
