@@ -643,6 +643,13 @@ enum mifvm_kernel {
     MIFVM_K_COUNT = 22
 };
 int mifvm_kernel_timing(mifvm_state* st, int32_t enable);
+/* As mifvm_kernel_timing(st, 1), but only the launches of the kernels whose
+ * bit (1 << id) is set in `kernels` get an event pair (and totals); the
+ * others launch without events, so a timed run carries fewer event records.
+ * With any bit set, solves launch their kernels directly instead of
+ * replaying captured chunks (as with all kernels timed).  0 stops timing;
+ * E_ARG for a bit at or above MIFVM_K_COUNT; E_STATE as mifvm_kernel_timing. */
+int mifvm_kernel_timing_select(mifvm_state* st, uint64_t kernels);
 /* Total milliseconds and number of timed launches of one kernel since the
  * last enable.  Synchronises the stream.                                    */
 int mifvm_kernel_stats(mifvm_state* st, int32_t kernel, double* total_ms, int64_t* launches,

@@ -239,6 +239,7 @@ def _load():
         "mifvm_poisson_rhs": (C.c_int, [P, P, P, P]),
         "mifvm_poisson_solve": (C.c_int, [P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), P]),
         "mifvm_kernel_timing": (C.c_int, [P, I32]),
+        "mifvm_kernel_timing_select": (C.c_int, [P, C.c_uint64]),
         "mifvm_step_graph": (C.c_int, [P, I32, D, P]),
         "mifvm_autotune": (C.c_int, [P, C.c_char_p, C.POINTER(TuneInfo), P]),
         "mifvm_batch_bytes": (C.c_int, [P, C.POINTER(SZ)]),
@@ -565,8 +566,16 @@ class State:
                     learned_iterations=info.learned_iterations)
 
     # -- per-kernel timing ----------------------------------------------------------
-    def kernel_timing(self, enable=True):
-        _check(_lib.mifvm_kernel_timing(self._h, 1 if enable else 0))
+    def kernel_timing(self, enable=True, only=None):
+        """Per-kernel event timing on or off; `only`: the kernel names (from
+        KERNELS) that get events, the others launch untimed."""
+        if only is None:
+            _check(_lib.mifvm_kernel_timing(self._h, 1 if enable else 0))
+            return
+        mask = 0
+        for name in only:
+            mask |= 1 << KERNELS.index(name)
+        _check(_lib.mifvm_kernel_timing_select(self._h, C.c_uint64(mask if enable else 0)))
 
     def kernel_stats(self, stream=None):
         """{kernel: (total_ms, launches)} since timing was enabled (synchronises)."""

@@ -425,17 +425,23 @@ void mifvm_state_destroy(mifvm_state* st) {
     delete st;
 }
 
-int mifvm_kernel_timing(mifvm_state* st, int32_t enable) {
+int mifvm_kernel_timing_select(mifvm_state* st, uint64_t kernels) {
     if (!st) return fail(MIFVM_E_ARG, "null state");
+    if (kernels >> kNumKernels) return fail(MIFVM_E_ARG, "kernel bit at or above MIFVM_K_COUNT");
     KernelTimer& t = st->s.timer;
     if (!t.pending.empty()) return fail(MIFVM_E_STATE, "timed launches not yet collected (call mifvm_kernel_stats)");
-    t.on = enable != 0;
+    t.on = kernels != 0;
+    t.mask = kernels;
     if (t.on)
         for (int k = 0; k < kNumKernels; ++k) {
             t.total_ms[k] = 0.0;
             t.count[k] = 0;
         }
     return MIFVM_OK;
+}
+
+int mifvm_kernel_timing(mifvm_state* st, int32_t enable) {
+    return mifvm_kernel_timing_select(st, enable != 0 ? (uint64_t(1) << kNumKernels) - 1 : 0);
 }
 
 int mifvm_kernel_stats(mifvm_state* st, int32_t kernel, double* total_ms, int64_t* launches, void* stream) {

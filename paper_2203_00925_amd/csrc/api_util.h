@@ -59,7 +59,7 @@ inline int reduce_blocks(int64_t n) {
 // Launch `fn` on `s`; with timing on, bracket it with an event pair.
 template <class F>
 hipError_t timed(mifvm::KernelTimer& t, int kid, hipStream_t s, F fn) {
-    if (!t.on) return fn();
+    if (!t.on || !((t.mask >> kid) & 1u)) return fn();
     while (t.pool.size() < t.used + 2) {
         hipEvent_t e;
         hipError_t err = hipEventCreate(&e);

@@ -134,6 +134,7 @@ struct AmgDev;
 // Event pairs around kernel launches, resolved into totals at sync points.
 struct KernelTimer {
     bool on = false;
+    uint64_t mask = ~uint64_t(0);           // kernel ids that get an event pair while on
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<std::pair<int, size_t>> pending;   // kernel id, index of start event

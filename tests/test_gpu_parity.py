@@ -141,6 +141,27 @@ def test_zero_steps_and_determinism():
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_selected_kernel_timing():
+    """Timing a subset of kernels: only the selected ids get launches and
+    time, the step's result is unchanged, and an id past the last is
+    refused."""
+    mp = Mapped(4, 6)
+    u0 = synth.gaussian_field(mp.m)
+    outs = []
+    for only in (None, ["fv_cell"]):
+        st = make_state(mp, [NEUMANN] * 6, [0.0] * 6, 1e-2, u0)
+        st.kernel_timing(True, only=only)
+        st.step(2, 1e-3)
+        ks = st.kernel_stats()
+        st.kernel_timing(False)
+        assert ks["fv_cell"][1] == 6 and ks["fv_cell"][0] > 0.0
+        assert ks["grad_limiter"][1] == (6 if only is None else 0)
+        outs.append(host(st.get_field(B.FIELD_U)))
+    assert np.array_equal(outs[0], outs[1])
+    with pytest.raises(B.MifvmError):
+        B._check(B._lib.mifvm_kernel_timing_select(st._h, 1 << len(B.KERNELS)))
+
+
 POISSON = {
     "ragged_mixed": (5, 3, [DIRICHLET, NEUMANN, ZERO_FLUX, DIRICHLET, NEUMANN, DIRICHLET],
                      [1.0, 0.5, 0.0, -2.0, 0.0, 0.25]),
