@@ -473,6 +473,22 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def timed_kernels(st, dt, solve_kw, p):
+    """Per-kernel durations of a form, outside its timed solves (whose
+    durations carry no event records): one more step and solve with every
+    kernel timed, then u and P restored (P to `p`)."""
+    from paper_2203_00925_amd import binding as B
+    u_keep = st.get_field(B.FIELD_U).clone()
+    st.kernel_timing(True)
+    st.step(1, dt)
+    st.poisson_solve(None, **solve_kw)
+    kstats = st.kernel_stats()
+    st.kernel_timing(False)
+    st.set_field(B.FIELD_U, u_keep)
+    st.set_field(B.FIELD_P, p)
+    return kstats
+
+
 def run_fp32_form(args, M, pf, u64, p64, plain_ms):
     """The same steps in the reduced-precision form: FP32 step kernels and the
     FP32-inner, FP64-refined Poisson solve (inner CG on the FP32 matrix-free
@@ -569,7 +585,6 @@ def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0, amg=
         st.step(1, dt)
         st.poisson_solve(None, **kw)
     torch.cuda.synchronize()
-    st.kernel_timing(kernel_times)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     solves = []
     for k in range(args.steps):
@@ -579,11 +594,10 @@ def run_solver_form(args, M, pf, name, solve_kw, plain_ms, p64, fgmres_m=0, amg=
         ev[k][1].record(stream)
         log(f"{name} step {k}: {solves[-1]['iterations']} it, rel {solves[-1]['rel_residual']:.2e}")
     torch.cuda.synchronize()
-    kstats = st.kernel_stats() if kernel_times else {}
-    st.kernel_timing(False)
     p = st.get_field(B.FIELD_P).clone()
     torch.cuda.synchronize()
     ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    kstats = timed_kernels(st, dt, kw, p) if kernel_times else {}
     # the last solution against plain Jacobi-CG taken on to 1e-12 from it
     st.poisson_solve(None, tol=1e-12, restart=500, matrix_free=True)
     p_ref = st.get_field(B.FIELD_P)
@@ -748,7 +762,6 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
         st.step(1, dt)
         st.poisson_solve(None, **kw)
     torch.cuda.synchronize()
-    st.kernel_timing(True)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     solves = []
     for k in range(args.steps):
@@ -759,9 +772,8 @@ def run_learned_form(args, M, pf, plain_iters, plain_solve_ms):
         log(f"learned step {k}: {solves[-1]['iterations']} it, rel {solves[-1]['rel_residual']:.2e}, "
             f"fell back {solves[-1]['fell_back']}")
     torch.cuda.synchronize()
-    kstats = st.kernel_stats()
-    st.kernel_timing(False)
     solve_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    kstats = timed_kernels(st, dt, kw, st.get_field(B.FIELD_P).clone())
     plain_ms = sum(plain_solve_ms) / len(plain_solve_ms)
     layer_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in kstats.items() if v[1]}
     # the trained network as the finest-level smoother of the multigrid W-cycle:
