@@ -269,8 +269,9 @@ def main():
     log(f"state ready; dt={dt:.6g}")
 
     stream = torch.cuda.current_stream()
-    # the FV step replays the library's captured step graph (3 stages, 13
-    # launches); capture it here, outside warm-up and timing, and undo the
+    # the FV step replays the library's captured step graph (the time step,
+    # one ghost fill, 3 stages of 2 launches); capture it here, outside
+    # warm-up and timing, and undo the
     # step it runs so that the state stays in step with the forms' runs
     u_keep = st.get_field(B.FIELD_U).clone()
     st.step_graph(1, dt)
