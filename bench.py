@@ -140,9 +140,10 @@ def algorithmic_bytes(info):
         "cg_axpy": nc * 64,
         # z,p read, p written
         "cg_dir": nc * 24,
-        # matrix-free product: vertex lists (weight 8 + index 4 per entry), x
-        # gathered once, ghost owner + tag, vertex values written
-        "mf_vertex": info.node_entries * 12 + nc * 8 + nb * 8 + nv * 8,
+        # matrix-free product: vertex lists (weight 8 + index 4 per entry, a
+        # ghost entry folded onto its owner), x gathered once, vertex values
+        # written
+        "mf_vertex": info.node_entries * 12 + nc * 8 + nv * 8,
         # the per-cell product: per cell 4 vertex ids 16, 4 vertex weights 32,
         # 4 face neighbours 16, 4 face weights 32, p 8 (neighbours' p counted
         # once), q written 8; vertex values gathered once

@@ -632,7 +632,7 @@ enum mifvm_kernel {
     (the first includes the encoder, the last the decoder) */,
     MIFVM_K_FCG_VEC = 14 /* flexible-CG update and its scalar steps */,
     MIFVM_K_NN_TRAIN = 15 /* one whole training step (all of its launches) */,
-    MIFVM_K_MF_VERTEX = 16 /* matrix-free product inside the CG: ghost and vertex values */,
+    MIFVM_K_MF_VERTEX = 16 /* matrix-free product inside the CG: the vertex values */,
     MIFVM_K_MF_FACE = 17 /* reserved: the face terms are summed per cell inside MF_GATHER,
     never launched */,
     MIFVM_K_MF_GATHER = 18 /* matrix-free product inside the CG: the per-cell product over

@@ -152,7 +152,8 @@ size_t layout(const Mesh& m, char* base, Dev& d) {
     d.np_ion = carve<double>(base, off, nc);
     d.efield = carve<double>(base, off, 3 * nc);
     d.mf_xv = carve<double>(base, off, nv);
-    d.mf_xg = carve<double>(base, off, nb > 0 ? nb : 1);
+    d.mf_nidx = carve<int32_t>(base, off, m.node.idx.size() > 0 ? m.node.idx.size() : 1);
+    d.n_entries = int64_t(m.node.idx.size());
     d.mfc_vid = carve<int32_t>(base, off, 4 * nc);
     d.mfc_w = carve<double>(base, off, 4 * nc);
     d.mfc_r = carve<double>(base, off, 4 * nc);

@@ -34,23 +34,31 @@ template <> struct MfCoef<float> {
     __device__ static const float* alpha(const Dev& d) { return d.n_alpha32; }
 };
 
-// ghost values of x (homogeneous part): xg[g] = s_g x_owner
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_mf_ghost(Dev d, BcTable bc, const R* __restrict__ x,
-                                                     R* __restrict__ xg, const double* skip) {
-    if (skip && *skip != 0.0) return;
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= d.nb) return;
-    const R sg = bc.kind[d.gtag[g]] == kDirichlet ? R(-1) : R(1);
-    xg[g] = sg * x[d.gowner[g]];
+// The vertex lists for the operator: each ghost entry folded onto its owner
+// (the homogeneous ghost value is s_g x_owner, s_g = -1 behind a Dirichlet
+// face, +1 otherwise; stored as ~owner for -1), so the vertex pass gathers
+// cells only.  Built with the per-cell tables, once per potential
+// boundary-kind set.
+__global__ __launch_bounds__(kBlock) void k_mf_nidx_setup(Dev d, BcTable bc) {
+    const int64_t p = gtid_m();
+    if (p >= d.n_entries) return;
+    const int e = d.n_idx[p];
+    int out = e;
+    if (e >= d.nc) {
+        const int64_t g = e - d.nc;
+        const int o = d.gowner[g];
+        out = bc.kind[d.gtag[g]] == kDirichlet ? ~o : o;
+    }
+    d.mf_nidx[p] = out;
 }
 
-// x_v = sum alpha x_e over the vertex list; a cell reads x, a ghost xg.  The
-// entries go in batches of 24: the weight and index loads of a batch first,
-// then its gathers, so 24 gathers are in flight per thread.
+// x_v = sum alpha x_e over the vertex list, a ghost entry as +-x of its
+// owner (mf_nidx).  The entries go in batches of 24: the weight and index
+// loads of a batch first, then its gathers, so 24 gathers are in flight per
+// thread.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict__ x, const R* __restrict__ xg,
-                                                      R* __restrict__ xv, const double* skip) {
+__global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict__ x, R* __restrict__ xv,
+                                                      const double* skip) {
     if (skip && *skip != 0.0) return;
     const int64_t v = gtid_m();
     if (v >= d.nv) return;
@@ -58,12 +66,11 @@ __global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict
     const int64_t sl = v >> 6;
     const int64_t base = d.n_off[sl] + (v & 63);
     const int w = d.n_w[sl];
-    const int nc = int(d.nc);
     R s = R(0);
     // batches of 24 (an interior vertex of the 6-tetrahedra cube has 24
     // cells): the next batch's indices and weights are in flight while this
-    // batch's values are gathered (one load per entry: a cell's x or a
-    // ghost's xg, by pointer)
+    // batch's values are gathered (one load per entry: a cell's x, negated
+    // for a ghost stored as ~owner)
     int e[24];
     R al[24];
     auto batch = [&](int k0, int* eo, R* ao) {
@@ -71,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict
         for (int j = 0; j < 24; ++j) {
             const bool in = k0 + j < w;
             const int64_t at = base + int64_t(k0 + j) * 64;
-            eo[j] = in ? d.n_idx[at] : 0;                // padding entries carry weight 0
+            eo[j] = in ? d.mf_nidx[at] : 0;              // padding entries carry weight 0
             ao[j] = in ? alpha[at] : R(0);
         }
     };
@@ -79,7 +86,10 @@ __global__ __launch_bounds__(kBlock) void k_mf_vertex(Dev d, const R* __restrict
     for (int k0 = 0; k0 < w; k0 += 24) {
         R xe[24];
 #pragma unroll
-        for (int j = 0; j < 24; ++j) xe[j] = *(e[j] < nc ? x + e[j] : xg + (e[j] - nc));
+        for (int j = 0; j < 24; ++j) {
+            const R xo = x[e[j] >= 0 ? e[j] : ~e[j]];
+            xe[j] = e[j] >= 0 ? xo : -xo;
+        }
         int en[24];
         R an[24];
         batch(k0 + 24, en, an);
@@ -194,34 +204,30 @@ __global__ __launch_bounds__(kBlock) void k_mf_cg_cell(Dev d, int64_t nblk) {
 
 hipError_t launch_mf_apply(const Dev& d, const BcTable& bc, const double* x, double* y, hipStream_t s,
                            const double* skip) {
-    if (d.nb > 0)
-        hipLaunchKernelGGL(k_mf_ghost<double>, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           d, bc, x, d.mf_xg, skip);
-    hipLaunchKernelGGL(k_mf_vertex<double>, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, x, d.mf_xg,
-                       d.mf_xv, skip);
+    (void)bc;                                  // its kinds are in the tables
+    hipLaunchKernelGGL(k_mf_vertex<double>, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, x, d.mf_xv, skip);
     hipLaunchKernelGGL(k_mf_cell, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, x, d.mf_xv, y, skip);
     return hipGetLastError();
 }
 
 hipError_t launch_mf_cell_setup(const Dev& d, const BcTable& bc_pot, hipStream_t s) {
     hipLaunchKernelGGL(k_mf_cell_setup, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, bc_pot);
+    if (d.n_entries > 0)
+        hipLaunchKernelGGL(k_mf_nidx_setup, dim3(rows_m(d.n_entries, kBlock)), dim3(kBlock), 0, s, d, bc_pot);
     return hipGetLastError();
 }
 
 namespace {
 // one part of q = K p (FP64 p, or FP32 p32 into the same scratch arrays
-// taken as floats): 0 the ghost and vertex values, 1 the per-cell product
-// with the p.q partials, 2 alpha
+// taken as floats): 0 the vertex values, 1 the per-cell product with the
+// p.q partials, 2 alpha
 template <class R>
 void mf_cg_part(const Dev& d, const BcTable& bc, int part, const R* p, hipStream_t s) {
+    (void)bc;                                  // its kinds are in the tables
     const double* none = nullptr;
-    R* xg = reinterpret_cast<R*>(d.mf_xg);
     R* xv = reinterpret_cast<R*>(d.mf_xv);
     if (part == 0) {
-        if (d.nb > 0)
-            hipLaunchKernelGGL(k_mf_ghost<R>, dim3(unsigned((d.nb + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, d,
-                               bc, p, xg, none);
-        hipLaunchKernelGGL(k_mf_vertex<R>, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, p, xg, xv, none);
+        hipLaunchKernelGGL(k_mf_vertex<R>, dim3(rows_m(d.nv, kBlock)), dim3(kBlock), 0, s, d, p, xv, none);
     } else if (part == 1) {
         const int64_t nblk = (d.nc + kBlock - 1) / kBlock;
         hipLaunchKernelGGL(k_mf_cg_cell<R>, dim3(rows_m(d.nc, kBlock)), dim3(kBlock), 0, s, d, nblk);

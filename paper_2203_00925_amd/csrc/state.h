@@ -101,7 +101,12 @@ struct Dev {
     float *minv32, *kAC32, *kBC32, *kRL32, *area32, *vol32, *n_alpha32, *fx32, *xc32, *gdist32;
     double* tmp;                          // nc+nb scratch (permutation, residual)
     double *np_ion, *efield;              // coupled loop: ion density [nc], E [3][nc]
-    double *mf_xv, *mf_xg;                // matrix-free operator: vertex values [nv], ghost values [nb]
+    double* mf_xv;                        // matrix-free operator: vertex values [nv]
+    // the vertex lists' entries for the matrix-free operator (same slots as
+    // n_idx, n_entries of them): a cell reads itself, a ghost is folded onto
+    // its owner, as ~owner where its homogeneous value is -x_owner (Dirichlet)
+    int32_t* mf_nidx;
+    int64_t n_entries;
     // matrix-free operator per cell i (from the faces and the potential's
     // boundary kinds): (K x)_i = -(sum_k w[k] x_v[vid[k]] + sum_k r[k] t_k) over
     // the cell's 4 vertices and 4 faces, t_k = x[c2n[k]] - x_i across an
