@@ -39,12 +39,12 @@ METRIC = "FV cell-updates/s + Poisson solve ms @1e-10 rel; plain vs mixed/learne
 # it when that source (the kernel's file and the reduction headers) still
 # hashes to the recorded prefix, else null.
 MEASURED_TRAFFIC = {"cube120": {
-    "k_mf_cg_cell": {"src": "d411d59405441bd8", "bytes": 1215484128},
-    "k_mf_vertex": {"src": "d411d59405441bd8", "bytes": 624980292},
-    "k_cg_axpy": {"src": "50d641f414878f07", "bytes": 668803480},
+    "k_mf_cg_cell": {"src": "8fdb010b17804213", "bytes": 1215810467},
+    "k_mf_vertex": {"src": "8fdb010b17804213", "bytes": 623188346},
+    "k_cg_axpy": {"src": "50d641f414878f07", "bytes": 668804504},
     "k_cg_dir": {"src": "50d641f414878f07", "bytes": 248844609},
-    "k_grad_moments": {"src": "7212ca82332031bf", "bytes": 3720717629},
-    "k_cell_step": {"src": "7212ca82332031bf", "bytes": 2159457124},
+    "k_grad_moments": {"src": "7212ca82332031bf", "bytes": 3720635711},
+    "k_cell_step": {"src": "7212ca82332031bf", "bytes": 2159479857},
 }}
 # timing id -> the FP64 kernel it times
 KERNEL_NAMES = {"grad_limiter": "k_grad_moments", "mf_gather": "k_mf_cg_cell", "fv_cell": "k_cell_step"}
