@@ -63,7 +63,6 @@ struct BatchDev {
     double* partial;
     const int32_t* scan;              // [8][nm] mesh order per XCD
     unsigned int* glob;               // [BG_COUNT]
-    const double* gsign;              // [nb] homogeneous ghost factor s_g (-1 Dirichlet, +1 else)
     double* rel_max;                  // [nm] largest final relative residual of a run
     int64_t* it_total;                // [nm] iterations summed over a run's solves
     long long spin_limit;             // polls without progress before an abort
@@ -77,6 +76,5 @@ hipError_t launch_batch_init(const Dev& d, const BatchDev& b, int maxit, int res
 hipError_t launch_batch_solve(const Dev& d, const BatchDev& b, int grid, int vertex_batch, double tol,
                               hipStream_t s);
 // ghost factors from the potential's boundary kinds
-hipError_t launch_batch_gsign(const Dev& d, const BatchDev& b, const BcTable& bc_pot, hipStream_t s);
 
 }  // namespace mifvm

@@ -99,7 +99,6 @@ size_t layout_b(const Dev& d, const std::vector<int64_t>& cells, char* base, Bat
     b.partial = carve_b<double>(base, off, size_t(ptot));
     b.scan = carve_b<int32_t>(base, off, size_t(8) * nm);
     b.glob = carve_b<unsigned int>(base, off, BG_COUNT);
-    b.gsign = carve_b<double>(base, off, size_t(d.nb > 0 ? d.nb : 1));
     b.rel_max = carve_b<double>(base, off, nm);
     b.it_total = carve_b<int64_t>(base, off, nm);
     return (off + 255) & ~size_t(255);
@@ -190,7 +189,6 @@ double now_ms() {
 hipError_t enqueue_solve(const mifvm_batch* h, double tol, int maxit, int restart, bool zero_run, hipStream_t q) {
     const State& s = h->st->s;
     hipError_t e = launch_rhs(s.d, s.d.u, q);                  // b = -mu u + c
-    if (e == hipSuccess) e = launch_batch_gsign(s.d, h->b, s.bc[1], q);
     if (e == hipSuccess) e = launch_batch_init(s.d, h->b, maxit, restart, zero_run, q);
     if (e == hipSuccess) e = launch_batch_solve(s.d, h->b, h->grid, h->vb, tol, q);
     return e;

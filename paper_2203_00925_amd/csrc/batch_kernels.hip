@@ -49,8 +49,8 @@ __device__ inline unsigned int ld_u(const unsigned int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// x_v = sum alpha_{v,e} src_e over the vertex list; a ghost entry stands for
-// s_g src_owner.  Entries in batches of VB (a schedule choice: 24, the
+// x_v = sum alpha_{v,e} src_e over the vertex list, each ghost entry folded
+// onto its owner (the operator's list, mf_nidx).  Entries in batches of VB (a schedule choice: 24, the
 // single-mesh vertex kernel's, keeps more gathers in flight; 8 needs fewer
 // registers, so more waves stay resident), the indices and weights of a
 // batch loaded before its values, summed in list order (so the values are
@@ -60,7 +60,6 @@ __device__ inline double vertex_value(const Dev& d, const BatchDev& b, const dou
     const int64_t sl = v >> 6;
     const int64_t base = d.n_off[sl] + (v & 63);
     const int w = d.n_w[sl];
-    const int nc = int(d.nc);
     double s = 0.0;
     for (int k0 = 0; k0 < w; k0 += kVb) {
         int e[kVb];
@@ -69,19 +68,14 @@ __device__ inline double vertex_value(const Dev& d, const BatchDev& b, const dou
         for (int j = 0; j < kVb; ++j) {
             const bool in = k0 + j < w;
             const int64_t at = base + int64_t(k0 + j) * 64;
-            e[j] = in ? d.n_idx[at] : 0;              // padding entries carry weight 0
+            e[j] = in ? d.mf_nidx[at] : 0;            // padding entries carry weight 0
             al[j] = in ? d.n_alpha[at] : 0.0;
         }
         double xe[kVb];
 #pragma unroll
-        for (int j = 0; j < kVb; ++j) {
-            int src_i = e[j];
-            double sg = 1.0;
-            if (e[j] >= nc) {                        // ghost: s_g times its owner's value
-                src_i = d.gowner[e[j] - nc];
-                sg = b.gsign[e[j] - nc];
-            }
-            xe[j] = sg * src[src_i];
+        for (int j = 0; j < kVb; ++j) {              // a ghost folded onto its owner, as ~owner for -x
+            const double xo = src[e[j] >= 0 ? e[j] : ~e[j]];
+            xe[j] = e[j] >= 0 ? xo : -xo;
         }
 #pragma unroll
         for (int j = 0; j < kVb; ++j) s += al[j] * xe[j];
@@ -399,10 +393,6 @@ __global__ void k_batch_init(Dev d, BatchDev b, int maxit, int restart, int zero
     }
 }
 
-__global__ void k_batch_gsign(Dev d, BatchDev b, BcTable bc) {
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g < d.nb) const_cast<double*>(b.gsign)[g] = bc.kind[d.gtag[g]] == kDirichlet ? -1.0 : 1.0;
-}
 
 }  // namespace
 
@@ -422,10 +412,5 @@ hipError_t launch_batch_solve(const Dev& d, const BatchDev& b, int grid, int ver
     return hipGetLastError();
 }
 
-hipError_t launch_batch_gsign(const Dev& d, const BatchDev& b, const BcTable& bc_pot, hipStream_t s) {
-    if (d.nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_gsign, dim3(unsigned((d.nb + 255) / 256)), dim3(256), 0, s, d, b, bc_pot);
-    return hipGetLastError();
-}
 
 }  // namespace mifvm
