@@ -133,19 +133,24 @@ __global__ __launch_bounds__(kBlock) void k_cg32_spmv(Dev d) {
     seg_publish<1>(d, g, v, i >= g.split, lds);
 }
 
-// d += alpha p; r -= alpha q; z = D^-1 r (FP32); partial rz, rr (FP64)
+// d += alpha p; r -= alpha q; z = D^-1 r (FP32); partial rz, rr (FP64).
+// The row's loads go out before the meshes' scalars are read (they do not
+// depend on them; a row past the mesh reads a valid row and is dropped), so
+// a block pays one memory latency, not three, before its stores.
 __global__ __launch_bounds__(kBlock) void k_cg32_axpy(Dev d) {
     __shared__ double lds[4];
+    const int64_t i = tid_g();
+    const int64_t j = i < d.nc ? i : d.nc - 1;
+    const float di = d.d32[j], pi = d.p32[j], r0 = d.r32[j], qi = d.q32[j], dv = d.k_dinv32[j];
     const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
     if (block_done(d, g)) return;
-    const int64_t i = tid_g();
     const double* sc = msc(d, row_mesh(g, i));
     double v[2] = {0.0, 0.0};
     if (i < d.nc && sc[SC_DONE] == 0.0) {
         const float alpha = float(sc[SC_ALPHA]);
-        d.d32[i] = d.d32[i] + alpha * d.p32[i];
-        const float ri = d.r32[i] - alpha * d.q32[i];
-        const float zi = d.k_dinv32[i] * ri;
+        d.d32[i] = di + alpha * pi;
+        const float ri = r0 - alpha * qi;
+        const float zi = dv * ri;
         d.r32[i] = ri;
         d.z32[i] = zi;
         v[0] = double(ri) * double(zi);
@@ -154,14 +159,17 @@ __global__ __launch_bounds__(kBlock) void k_cg32_axpy(Dev d) {
     seg_publish<2>(d, g, v, i >= g.split, lds);
 }
 
+// p = z + beta p (FP32), the row's loads first as above
 __global__ __launch_bounds__(kBlock) void k_cg32_dir(Dev d) {
+    const int64_t i = tid_g();
+    const int64_t j = i < d.nc ? i : d.nc - 1;
+    const float zi = d.z32[j], pi = d.p32[j];
     const BlockSeg g = block_seg(d, int64_t(blockIdx.x) * kBlock, kBlock);
     if (block_done(d, g)) return;
-    const int64_t i = tid_g();
     if (i >= d.nc) return;
     const double* sc = msc(d, row_mesh(g, i));
     if (sc[SC_DONE] != 0.0) return;
-    d.p32[i] = d.z32[i] + float(sc[SC_BETA]) * d.p32[i];
+    d.p32[i] = zi + float(sc[SC_BETA]) * pi;
 }
 
 // x += d (FP64).  d is zero on meshes that ran no inner solve this step.
