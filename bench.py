@@ -18,7 +18,10 @@ scalar, Dirichlet 0 for the potential, dt from CFL 0.4.
 Prints one JSON line.  `value` is FV cell-updates per second (cells x RK3
 steps / FV time); the Poisson solve time per step is reported beside it.
 Per-kernel durations come from HIP events the library records around its
-own launches on the launch stream during the timed region.
+own launches on the launch stream: in the timed region around the solve's
+dominant kernel only (named by the last warm-up step's fully timed solve,
+which gives the other solve kernels' durations); the FV kernels' from the
+same steps launched directly after the timed region.
 """
 from __future__ import annotations
 
@@ -207,8 +210,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--forms", default="all",
                     help="comma-separated forms to run after the main steps (fp32_refined, stored_matrix_cg, "
-                         "fgmres30, multigrid_fcg, multigrid_w_fcg, streamer, learned, batch64), or all; "
-                         "each runs min(--steps, 5) steps (batch64: 4)")
+                         "fgmres30, multigrid_fcg, multigrid_w_fcg, streamer, learned, cube20, batch64), or all; "
+                         "each runs min(--steps, 5) steps (batch64: 4; cube20: its own 10)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the reduced-precision (FP32 + refined solve) run")
     ap.add_argument("--learned-samples", type=int, default=0,
@@ -458,6 +461,9 @@ def main():
         if run("learned"):
             result["forms"]["learned"] = run_learned_form(args, M, pf, iters, solve_ms)
             torch.cuda.empty_cache()
+        if run("cube20"):
+            result["forms"]["cube20"] = run_small_form()
+            torch.cuda.empty_cache()
         if run("batch64"):
             del M
             b = run_batch(args, steps=min(args.steps, 4), warmup=args.warmup)
@@ -667,6 +673,53 @@ def learned_training_data(B, net, log_prefix="learned"):
         states.append(st)
         log(f"{log_prefix}: training mesh n={n} ({m.nc} cells): {got} samples")
     return states, samples, owner
+
+
+def run_small_form():
+    """The small configuration on the GPU: the 48,000-cell cube (n = 20, seed
+    1) with the same fields, 10 RK3 steps at CFL 0.4 (one captured graph),
+    then one cold Jacobi-CG solve to 1e-10 (Dirichlet 0, right-hand side =
+    the stepped scalar), matrix-free and on the stored matrix.  At this size
+    the step is bound by its launches, not by HBM."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2203_00925_amd import binding as B
+    wl = WORKLOADS["cube20"]
+    m = synth.jittered_cube(wl["n"], wl["seed"])
+    pf = synth.problem_fields(m)
+    st = B.State(B.Mesh.from_cube(m), diffusivity=pf.diffusivity)
+    st.set_bcs(B.VAR_SCALAR, [B.ZERO_FLUX] * 6)
+    st.set_bcs(B.VAR_POTENTIAL, [B.DIRICHLET] * 6)
+    st.set_field(B.FIELD_VEL, torch.from_numpy(np.ascontiguousarray(pf.vel.T.ravel())))
+    st.set_field(B.FIELD_U, torch.from_numpy(pf.u0))
+    st.poisson_assemble()
+    dt = st.cfl_dt(pf.cfl)
+    u0 = st.get_field(B.FIELD_U).clone()
+    st.step_graph(10, dt)                               # capture (and one untimed run)
+    st.set_field(B.FIELD_U, u0)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    st.step_graph(10, dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fv_ms = e0.elapsed_time(e1)
+    solves = {}
+    for name, mf in (("matrix_free", True), ("stored_matrix", False)):
+        st.set_field(B.FIELD_P, torch.zeros(m.nc, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        e0.record(stream)
+        s = st.poisson_solve(None, tol=1e-10, restart=500, matrix_free=mf)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        solves[name] = {"iterations": s["iterations"], "ms": round(e0.elapsed_time(e1), 3),
+                        "rel_residual": s["rel_residual"]}
+    log(f"cube20: 10 steps {fv_ms:.2f} ms, solves {solves}")
+    del st
+    return {"cells": m.nc, "fv_cell_updates_per_s": m.nc * 10 / (fv_ms / 1e3), "fv_ms_per_step": fv_ms / 10,
+            "poisson_solve": solves, "dtype": "f64"}
 
 
 def run_streamer_form(args, M, pf):
