@@ -117,37 +117,38 @@ __global__ __launch_bounds__(256) void k_gm_spmv(Dev d, GmDev g, int j) {
     w[i] = y;
 }
 
-// partial h_i = v_i . w for i in [i0, i0 + cnt), cnt <= 8, w = V[j + 1]
+// partial h_i = v_i . w for i in [i0, i0 + cnt), cnt <= kGmDots, w = V[j + 1]:
+// one pass over w for up to kGmDots basis vectors
+constexpr int kGmDots = 32;
 __global__ __launch_bounds__(256) void k_gm_dots(Dev d, GmDev g, int j, int i0, int cnt) {
     __shared__ double lds[4];
     if (finished(d)) return;
     const double* __restrict__ w = g.V + int64_t(j + 1) * d.nc;
-    double acc[8];
+    double acc[kGmDots];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int q = 0; q < kGmDots; ++q) acc[q] = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < d.nc; i += int64_t(gridDim.x) * 256) {
         const double wi = w[i];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < kGmDots; ++q)
             if (q < cnt) acc[q] += g.V[int64_t(i0 + q) * d.nc + i] * wi;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        if (q >= cnt) break;
-        const double s = block_sum256(acc[q], lds);
-        if (threadIdx.x == 0) g.partial[int64_t(i0 + q) * kGmGrid + blockIdx.x] = s;
+    for (int q = 0; q < kGmDots; ++q) {
+        if (q < cnt) {                         // cnt is the same for the whole block
+            const double s = block_sum256(acc[q], lds);
+            if (threadIdx.x == 0) g.partial[int64_t(i0 + q) * kGmGrid + blockIdx.x] = s;
+        }
     }
 }
 
-// column j of H from the partials
+// column j of H from the partials: block i sums those of h_ij
 __global__ __launch_bounds__(1024) void k_gm_hcol(Dev d, GmDev g, int j, int nparts) {
     __shared__ double lds[16];
     if (finished(d)) return;
-    for (int i = 0; i <= j; ++i) {
-        const double h = reduce_partials_sum(g.partial + int64_t(i) * kGmGrid, nparts, lds);
-        if (threadIdx.x == 0) g.H[int64_t(j) * (g.m + 1) + i] = h;
-        __syncthreads();
-    }
+    const int i = blockIdx.x;
+    const double h = reduce_partials_sum(g.partial + int64_t(i) * kGmGrid, nparts, lds);
+    if (threadIdx.x == 0) g.H[int64_t(j) * (g.m + 1) + i] = h;
 }
 
 // w -= sum_{i <= j} h_ij v_i; partial |w|^2
@@ -261,11 +262,11 @@ hipError_t launch_gm_spmv(const Dev& d, const GmDev& g, int j, hipStream_t s) {
 
 hipError_t launch_gm_orth(const Dev& d, const GmDev& g, int j, hipStream_t s) {
     const unsigned nb = grid_red(d.nc);
-    for (int i0 = 0; i0 <= j; i0 += 8) {
-        const int cnt = j + 1 - i0 < 8 ? j + 1 - i0 : 8;
+    for (int i0 = 0; i0 <= j; i0 += kGmDots) {
+        const int cnt = j + 1 - i0 < kGmDots ? j + 1 - i0 : kGmDots;
         hipLaunchKernelGGL(k_gm_dots, dim3(nb), dim3(256), 0, s, d, g, j, i0, cnt);
     }
-    hipLaunchKernelGGL(k_gm_hcol, dim3(1), dim3(1024), 0, s, d, g, j, int(nb));
+    hipLaunchKernelGGL(k_gm_hcol, dim3(unsigned(j + 1)), dim3(1024), 0, s, d, g, j, int(nb));
     hipLaunchKernelGGL(k_gm_orth, dim3(nb), dim3(256), 0, s, d, g, j);
     hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(1024), 0, s, d, g, j, int(nb));
     if (j + 1 < g.m) hipLaunchKernelGGL(k_gm_next, dim3(nb), dim3(256), 0, s, d, g, j + 1);
